@@ -1,0 +1,222 @@
+/*
+ * ctof.h - C ABI of libctof, the MI355X (gfx950) implementation of the
+ * confocal time-of-flight diffuse optical tomography hot path of
+ * "High Resolution, Deep Imaging Using Confocal Time-of-flight Diffuse
+ * Optical Tomography" (arXiv 2101.11680).
+ *
+ * What is computed
+ *   The forward model of Eq. 11: a confocal histogram
+ *       m[k][i][j] = sum_z sum_{i',j'} K_z[i-i'][j-j'][k] * mu_z[i'][j']
+ *   (lateral linear convolution of each depth layer mu_z with a
+ *   depth-dependent, time-resolved kernel, summed over layers), its adjoint
+ *   (transpose), and the FISTA reconstruction of section "Reconstruction
+ *   Algorithm" for the non-negative Tikhonov-regularised problem
+ *       min_{mu >= 0} 1/2 ||A mu - d||^2 + lambda/2 ||mu||^2.
+ *   The kernel K_z is the time-binned Jacobian of Eq. 5 (time convolution
+ *   of the diffusion fluence and reflectance) for collocated source and
+ *   detector on a semi-infinite homogeneous medium with an extrapolated
+ *   boundary, integrated exactly over each time bin and scaled by the voxel
+ *   volume.
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns ctof_status; none aborts, throws or prints.
+ *     On failure ctof_last_error() returns a message (thread-local, valid
+ *     until the next call on the same thread).
+ *   - Arguments are validated before any GPU work is enqueued; on
+ *     CTOF_EINVAL / CTOF_EUNSUPPORTED / CTOF_ENOMEM no output byte is
+ *     written.
+ *   - All device memory (kernel spectrum, workspace, inputs, outputs) is
+ *     owned by the caller.  Pointers named *_dev are device pointers on the
+ *     current HIP device; the library never allocates device memory.
+ *   - Work is enqueued on the given stream (NULL = the default stream) and
+ *     is asynchronous unless stated otherwise.
+ *   - Element type: double for CTOF_FP64, float for CTOF_FP32, CTOF_BF16X3
+ *     and CTOF_BF16.  Arrays are C-contiguous:
+ *       volume mu, g          [nz][n][n]
+ *       histogram m, d, r     [nt][n][n]
+ *   - A ctof_kernel handle is immutable after tabulation and may be used
+ *     concurrently from several streams as long as each call has its own
+ *     workspace.
+ */
+#ifndef CTOF_H
+#define CTOF_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CTOF_OK = 0,
+  CTOF_EINVAL = -1,        /* an argument breaks a documented rule              */
+  CTOF_ENOMEM = -2,        /* a caller buffer is smaller than required           */
+  CTOF_EHIP = -3,          /* a HIP runtime call failed                          */
+  CTOF_ENONFINITE = -4,    /* a NaN/Inf appeared in an FP64 norm                 */
+  CTOF_EUNSUPPORTED = -5   /* valid but outside what this build implements       */
+} ctof_status;
+
+typedef enum {
+  CTOF_FP64 = 0,   /* FP64 FFTs and contraction (small grids, parity runs)           */
+  CTOF_FP32 = 1,   /* FP32 FFTs, FP32 matrix-core contraction                        */
+  CTOF_BF16X3 = 2, /* FP32 FFTs; contraction as BF16 hi*hi + hi*lo + lo*hi, FP32 acc. */
+  CTOF_BF16 = 3    /* FP32 FFTs; kernel spectrum stored as BF16 (half the bytes),
+                      data split hi+lo: K_hi*v_hi + K_hi*v_lo                        */
+} ctof_precision;
+
+/*
+ * Scan geometry and background optics (section "Confocal ToF-DOT": a
+ * collocated source/detector pair scanned over an n x n grid; the voxel
+ * grid is the scan grid, aligned, one voxel layer per entry of z_mm).
+ *   nx, ny            scan points per side; this build requires nx == ny,
+ *                     1 <= n <= 128 (CTOF_EUNSUPPORTED otherwise)
+ *   pitch_mm          lateral pitch (> 0), equal in x and y
+ *   nz, z_mm          number of layers (>= 1) and a HOST array of layer
+ *                     centre depths, strictly increasing, > 0
+ *   dz_mm             voxel thickness; 0 means the uniform spacing of z_mm
+ *                     (then z_mm must be uniform, and nz == 1 needs dz_mm > 0)
+ *   nt, dt_ps, t0_ps  time bins: bin k = [t0 + k dt, t0 + (k+1) dt), nt >= 1,
+ *                     dt > 0, t0 >= 0 (t = 0 is the pulse entering the medium)
+ *   mus_prime_per_mm  reduced scattering coefficient (> 0)
+ *   mua_per_mm        background absorption (> 0; the closed form needs it)
+ *   n_medium          refractive index inside (>= 1; 1 outside)
+ */
+typedef struct {
+  int32_t nx, ny;
+  double pitch_mm;
+  int32_t nz;
+  const double *z_mm;
+  double dz_mm;
+  int32_t nt;
+  double dt_ps, t0_ps;
+  double mus_prime_per_mm, mua_per_mm, n_medium;
+} ctof_geometry;
+
+typedef struct ctof_kernel_s *ctof_kernel; /* opaque host handle */
+
+/*
+ * Sizes needed to tabulate a kernel: the spectrum buffer that the handle
+ * keeps referring to, and a scratch workspace used only during
+ * ctof_kernel_tabulate.  Pure host computation; no GPU needed.
+ */
+ctof_status ctof_kernel_bytes(const ctof_geometry *geom, ctof_precision prec,
+                              size_t *khat_bytes, size_t *tab_ws_bytes);
+
+/*
+ * Tabulate the kernel of Eq. 5 for every layer, lateral offset and time bin
+ * in FP64 on the GPU, transform it to its (real, even) 2D spectrum in FP64,
+ * and pack that spectrum in the precision `prec` into khat_dev.  The caller
+ * keeps khat_dev alive until ctof_kernel_free.  Enqueues on `stream` and
+ * synchronises it before returning (tab_ws_dev may be reused afterwards).
+ * On success *out receives a new handle.
+ */
+ctof_status ctof_kernel_tabulate(const ctof_geometry *geom, ctof_precision prec,
+                                 void *khat_dev, size_t khat_bytes,
+                                 void *tab_ws_dev, size_t tab_ws_bytes,
+                                 hipStream_t stream, ctof_kernel *out);
+
+/*
+ * Test hook: the same FP64 kernel values as ctof_kernel_tabulate, before the
+ * transform, for lateral offsets 0 <= dy, dx < n:
+ *   quad_dev[z][k][dy][dx] = K_z[dy][dx][k]   (double, nz*nt*n*n entries).
+ * Enqueues on `stream`; asynchronous.
+ */
+ctof_status ctof_kernel_tabulate_quadrant(const ctof_geometry *geom, double *quad_dev,
+                                          size_t quad_bytes, hipStream_t stream);
+
+/* Frees the host handle only; the spectrum buffer stays the caller's. */
+void ctof_kernel_free(ctof_kernel k);
+
+/*
+ * Shape facts of a handle (any pointer may be NULL):
+ *   n, nz, nt   grid, layers, bins;   p   FFT size (power of two >= 2n-1)
+ *   nmat        distinct spectrum matrices, (p/2+1)(p/2+2)/2
+ *   prec        precision the handle was tabulated for
+ */
+ctof_status ctof_kernel_info(ctof_kernel k, int32_t *n, int32_t *nz, int32_t *nt,
+                             int32_t *p, int32_t *nmat, int32_t *prec);
+
+/*
+ * Workspace bytes for ctof_forward / ctof_adjoint (op_ws) and for
+ * ctof_reconstruct with at most max_iter iterations (solve_ws).
+ */
+ctof_status ctof_workspace_bytes(ctof_kernel k, int32_t max_iter, size_t *op_ws,
+                                 size_t *solve_ws);
+
+/*
+ * Forward model (Eq. 11): m = A mu.  mu_dev [nz][n][n], m_dev [nt][n][n],
+ * element type of the handle's precision.  Asynchronous.
+ */
+ctof_status ctof_forward(ctof_kernel k, const void *mu_dev, void *m_dev, void *ws_dev,
+                         size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Adjoint (the transpose of A; the kernel is real): g = A^T r.
+ * r_dev [nt][n][n], g_dev [nz][n][n].  Asynchronous.
+ */
+ctof_status ctof_adjoint(ctof_kernel k, const void *r_dev, void *g_dev, void *ws_dev,
+                         size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Solver options (section "Reconstruction Algorithm"; FISTA with constant
+ * step, no restart):
+ *   max_iter         iterations to run (>= 1)
+ *   lambda_tikhonov  Tikhonov weight; < 0 means 1e-3 * L_A
+ *   lipschitz        step constant L (tau = 1/L); 0 means
+ *                    L = 1.01 L_A + lambda with L_A = ||A||^2 from
+ *                    power_iters power iterations (FP64 Rayleigh quotients);
+ *                    if > 0, lambda_tikhonov must be >= 0
+ *   power_iters      power iterations when lipschitz == 0 (0 means 50)
+ *   rel_tol          stop when the gradient-mapping ratio
+ *                    ||y_k - mu_k|| / (tau ||max(0, A^T d)||) <= rel_tol,
+ *                    checked every check_every iterations (0 = run max_iter)
+ *   check_every      >= 1 when rel_tol > 0
+ *   warm_start       0: mu_inout is zeroed first; 1: mu_inout is mu_0
+ *   history_dev      optional device array double[max_iter][2] receiving
+ *                    (1/2 ||A y_k - d||^2, gradient-mapping ratio) per
+ *                    iteration; NULL for none
+ */
+typedef struct {
+  int32_t max_iter;
+  double lambda_tikhonov;
+  double lipschitz;
+  int32_t power_iters;
+  double rel_tol;
+  int32_t check_every;
+  int32_t warm_start;
+  double *history_dev;
+} ctof_solver_opts;
+
+/*
+ * Report (host memory):
+ *   iters       iterations run;  status  final ctof_status of the solve
+ *   datafit0    1/2 ||A mu_0 - d||^2;  datafit  1/2 ||A mu_final - d||^2
+ *   gmap_ratio  gradient-mapping ratio of the last iteration
+ *   lipschitz, lambda   the L and lambda used;  lipschitz_a  L_A (0 if L given)
+ *   gmap0       ||max(0, A^T d)||, the ratio's denominator
+ */
+typedef struct {
+  int32_t iters, status;
+  double datafit0, datafit, gmap_ratio, lipschitz, lambda, lipschitz_a, gmap0;
+} ctof_solver_report;
+
+/*
+ * FISTA reconstruction.  d_dev [nt][n][n] (the measured histogram),
+ * mu_inout_dev [nz][n][n] (start point if warm_start, result on return).
+ * Enqueues on `stream` and synchronises it before returning (the report is
+ * filled from device scalars); also synchronises every check_every
+ * iterations when rel_tol > 0.  Reaching max_iter is not an error.
+ */
+ctof_status ctof_reconstruct(ctof_kernel k, const void *d_dev, void *mu_inout_dev,
+                             const ctof_solver_opts *opts, ctof_solver_report *report,
+                             void *ws_dev, size_t ws_bytes, hipStream_t stream);
+
+const char *ctof_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CTOF_H */

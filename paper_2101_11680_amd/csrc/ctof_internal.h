@@ -1,0 +1,132 @@
+// Internal declarations shared by the libctof translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/ctof.h"
+
+namespace ctof {
+
+constexpr int kMaxN = 128;      // largest scan side (FFT size <= 256)
+constexpr int kMaxLayers = 256; // layer depths travel as a kernel argument
+constexpr int kMinP = 16;       // smallest FFT size used
+
+inline size_t round_up(size_t v, size_t m) { return (v + m - 1) / m * m; }
+
+// Sizes derived from a geometry.  p: FFT size (power of two >= 2n-1);
+// h = p/2; nmat = distinct real spectrum matrices (a <= b <= h);
+// nzp / ntp: layer / bin counts padded for the matrix-core tiles.
+struct Dims {
+  int n, nz, nt, p, h, nmat, nzp, ntp;
+};
+
+Dims make_dims(int n, int nz, int nt, ctof_precision prec);
+
+// Background optics and the per-voxel constants of the kernel closed form.
+struct Optics {
+  double c, D, z0, zb, mua, mueff;
+};
+
+struct LayerDepths {
+  double z[kMaxLayers];
+};
+
+struct GaussLegendre16 {
+  double x[16], w[16];
+};
+
+// Geometry of one tabulation, all on the host side of a launch.
+struct TabGeom {
+  int n, nz, nt;
+  double pitch, dt, t0, dv, rmin;
+  Optics o;
+};
+
+// Byte layout of a packed spectrum (offsets into khat_dev).
+struct KhatLayout {
+  size_t fwd, fwd_lo, adj, adj_lo, total;  // fwd_lo/adj_lo == SIZE_MAX when unused
+};
+
+KhatLayout khat_layout(const Dims &d, ctof_precision prec);
+
+}  // namespace ctof
+
+struct ctof_kernel_s {
+  ctof::Dims dims;
+  ctof_precision prec;
+  ctof::TabGeom geom;
+  void *khat;                 // caller-owned device buffer
+  ctof::KhatLayout layout;
+};
+
+namespace ctof {
+
+// ---- tabulation (tabulate.hip) --------------------------------------------
+hipError_t launch_tab_values(const TabGeom &g, const LayerDepths &z, const GaussLegendre16 &gl,
+                             double *out, size_t s_dy, size_t s_dx, size_t s_z, size_t s_t,
+                             hipStream_t st);
+hipError_t launch_cosine_matrix(int n, int p, double *C, hipStream_t st);
+// C[M][N] = A[M][K] * B[K][N] (row-major, FP64), batched with strides.
+hipError_t launch_gemm_f64(int M, long long N, int K, const double *A, int lda, long long sA,
+                           const double *B, long long ldb, long long sB, double *C, long long ldc,
+                           long long sC, int batch, hipStream_t st);
+hipError_t launch_pack(const Dims &d, ctof_precision prec, const double *k64, void *khat,
+                       const KhatLayout &lay, double scale, hipStream_t st);
+
+// ---- FFT passes (fft.hip) ---------------------------------------------------
+// Column pass along kx for every ky of a spectrum block.
+//   inverse: in [h+1][p][2][B] -> out [h+1][n][2][B] (rows >= n dropped)
+//   forward: in [h+1][n][2][B] (rows >= n are zero) -> out [h+1][p][2][B]
+template <typename T>
+hipError_t launch_col_pass(const Dims &d, int B, bool inverse, const T *in, T *out,
+                           hipStream_t st);
+
+enum RowOp : int {
+  ROW_SPEC_TO_SPATIAL = 0,   // c2r -> crop -> store spatial (forward/adjoint output)
+  ROW_SPATIAL_TO_SPEC = 1,   // spatial (optionally scaled) -> pad -> r2c
+  ROW_RESIDUAL = 2,          // c2r -> r = x - d, partial 1/2 r^2 -> r2c
+  ROW_PASS = 3,              // c2r -> partial 1/2 x^2 -> r2c (power iteration)
+  ROW_FISTA = 4,             // c2r -> prox/FISTA update -> r2c of y_{k+1}
+  ROW_POWER_W = 5,           // c2r -> store w, partials |w|^2 and <v, w>
+  ROW_GMAP0 = 6,             // c2r -> partial |max(0, x)|^2
+  ROW_SCALE_TO_SPEC = 7      // spatial w * (1/sqrt(scalar)) -> store v -> r2c
+};
+
+struct RowArgs {
+  int op;
+  int B;            // batch stride of spectra (ntp or nzp)
+  int nplanes;      // real planes (nt or nz); planes beyond read as zero
+  const void *spec_in;   // [h+1][n][2][B]
+  void *spec_out;        // [h+1][n][2][B] (may alias spec_in)
+  const void *sp_in;     // spatial input [planes][n][n] (d, y, v, ...)
+  void *sp_out;          // spatial output [planes][n][n]
+  void *sp_aux;          // second spatial buffer (mu for FISTA)
+  double *partials;      // per-block FP64 partials (2 per block)
+  const double *scalar;  // device scalar (ROW_SCALE_TO_SPEC: |w|^2)
+  double tau, lambda, beta;
+};
+
+template <typename T>
+hipError_t launch_row_pass(const Dims &d, const RowArgs &a, hipStream_t st);
+int row_pass_blocks(const Dims &d, int B, bool fp64);
+
+// ---- contraction (contract.hip) ---------------------------------------------
+// forward:  out[f][re/im][t] = sum_z K_s(f)[t][z] in[f][re/im][z]
+// adjoint:  out[f][re/im][z] = sum_t K_s(f)[t][z] in[f][re/im][t]
+hipError_t launch_contract(const ctof_kernel_s *k, bool adjoint, const void *in, void *out,
+                           hipStream_t st);
+
+// ---- reductions and small kernels (solver.hip) --------------------------------
+// sums[j] = sum_i partials[i*stride + j] for j < count, over nrows rows (FP64,
+// fixed order).
+hipError_t launch_reduce_rows(const double *partials, int nrows, int stride, int count,
+                              double *sums, hipStream_t st);
+hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st);
+hipError_t launch_history_k(const double *partials, int iters, int nblk_t, int nblk_z, double tau,
+                            const double *g0sq, double *hist, double *last, hipStream_t st);
+hipError_t launch_fill_value(float *p, size_t n, float v, hipStream_t st);
+hipError_t launch_fill_value_f64(double *p, size_t n, double v, hipStream_t st);
+
+}  // namespace ctof

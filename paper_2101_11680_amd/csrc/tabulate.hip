@@ -1,0 +1,309 @@
+// FP64 tabulation of the confocal kernel and its real 2D spectrum (gfx950).
+//
+// Kernel values follow Eq. 5 of the paper (the time-resolved Jacobian as
+// the time convolution of the diffusion fluence Phi0 from the source and
+// the reflectance R back to the detector), for a collocated source and
+// detector on a semi-infinite homogeneous medium with an extrapolated
+// boundary.  The convolution has a closed form: with a = r1 + r2 (source or
+// its image to the voxel, plus voxel or its image to the detector) each of
+// the four image terms is
+//   amp * t^(-3/2) exp(-alpha/t - beta t) (2 alpha/t + g - 1),
+//   alpha = a^2/(4 D c), beta = mu_a c, g = a / r2,
+// whose integral from 0 to T is
+//   F(T) = 2 e(T)/sqrt(T) + g I_{3/2}(T) + 2 beta I_{1/2}(T),
+// where I_nu(T) = int_0^T s^(-nu) exp(-alpha/s - beta s) ds are written
+// with erfcx/erfc (device math library).  A bin is F(hi) - F(lo) while that
+// difference does not cancel (F(lo) <= 100 |F(hi) - F(lo)|), else 16-point
+// Gauss-Legendre on the integrand.  Each value is scaled by the voxel
+// volume.
+//
+// The kernel is even in both lateral offsets, so its spectrum on a P x P
+// torus is real and equals a cosine transform:
+//   Khat(a, b) = sum_{dy, dx} w_dy w_dx K[dy][dx] cos(2 pi a dy / P) cos(2 pi b dx / P)
+// with w_0 = 1, w_{>0} = 2 over the quadrant dy, dx in [0, n).  It is
+// evaluated as two FP64 GEMMs with the cosine matrix C[a][d] = w_d cos(2 pi a d / P).
+#include "ctof_internal.h"
+
+#include <cmath>
+
+namespace ctof {
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kSqrtPi = 1.77245385090551602730;
+
+__device__ inline double antiderivative(double alpha, double sqrt_alpha, double beta,
+                                        double sqrt_beta, double g, double T) {
+  if (!(T > 0.0)) return 0.0;
+  const double x = sqrt(alpha / T);
+  const double y = sqrt(beta * T);
+  const double E = exp(-x * x - y * y);
+  const double ep = E * erfcx(x + y);
+  const double em = (x >= y) ? E * erfcx(x - y) : exp(-2.0 * x * y) * erfc(x - y);
+  const double i32 = kSqrtPi / (2.0 * sqrt_alpha) * (em + ep);
+  const double i12 = kSqrtPi / (2.0 * sqrt_beta) * (em - ep);
+  return 2.0 * E / sqrt(T) + g * i32 + 2.0 * beta * i12;
+}
+
+__device__ inline double integrand(double alpha, double beta, double g, double s) {
+  const double inv = 1.0 / s;
+  return inv * sqrt(inv) * exp(-alpha * inv - beta * s) * (2.0 * alpha * inv + g - 1.0);
+}
+
+// One thread per (layer, dy, dx); loops over the time bins so that F at the
+// upper edge of bin k is reused as the lower edge of bin k+1.
+__global__ void __launch_bounds__(128)
+tab_values_kernel(TabGeom g, LayerDepths zs, GaussLegendre16 gl, double *__restrict__ out,
+                  size_t s_dy, size_t s_dx, size_t s_z, size_t s_t, int z_fastest) {
+  const size_t tid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t total = (size_t)g.nz * g.n * g.n;
+  if (tid >= total) return;
+  int z, dy, dx;
+  if (z_fastest) {
+    z = (int)(tid % g.nz);
+    const size_t r = tid / g.nz;
+    dx = (int)(r % g.n);
+    dy = (int)(r / g.n);
+  } else {
+    dx = (int)(tid % g.n);
+    const size_t r = tid / g.n;
+    dy = (int)(r % g.n);
+    z = (int)(r / g.n);
+  }
+  const Optics o = g.o;
+  const double zz = zs.z[z];
+  const double rho2 = g.pitch * g.pitch * (double)(dy * dy + dx * dx);
+  const double Dc = o.D * o.c;
+  const double beta = o.mua * o.c;
+  const double sqrt_beta = sqrt(beta);
+  const double norm = 1.0 / (2.0 * sqrt(kPi * Dc));
+
+  const double r11 = fmax(sqrt(rho2 + (zz - o.z0) * (zz - o.z0)), g.rmin);
+  const double zs1 = zz + o.z0 + 2.0 * o.zb;
+  const double r12 = sqrt(rho2 + zs1 * zs1);
+  const double zi = zz + 2.0 * o.zb;
+  const double r21 = sqrt(rho2 + zz * zz);
+  const double r22 = sqrt(rho2 + zi * zi);
+
+  double amp[4], alpha[4], sa[4], gg[4], flo[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double sigma = (q < 2) ? 1.0 : -1.0;
+    const double r1 = (q < 2) ? r11 : r12;
+    const double w = (q & 1) ? zi : zz;
+    const double r2 = (q & 1) ? r22 : r21;
+    const double a = r1 + r2;
+    amp[q] = sigma * w / (16.0 * kPi * kPi * o.D * r1 * r2 * r2) * norm;
+    alpha[q] = a * a / (4.0 * Dc);
+    sa[q] = sqrt(alpha[q]);
+    gg[q] = a / r2;
+    flo[q] = antiderivative(alpha[q], sa[q], beta, sqrt_beta, gg[q], g.t0);
+  }
+  double *dst = out + (size_t)dy * s_dy + (size_t)dx * s_dx + (size_t)z * s_z;
+  for (int k = 0; k < g.nt; ++k) {
+    const double tlo = g.t0 + (double)k * g.dt;
+    const double thi = g.t0 + (double)(k + 1) * g.dt;
+    const double mid = 0.5 * (thi + tlo);
+    const double half = 0.5 * (thi - tlo);
+    double sum = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double fhi = antiderivative(alpha[q], sa[q], beta, sqrt_beta, gg[q], thi);
+      const double df = fhi - flo[q];
+      double bin;
+      if (flo[q] <= 100.0 * fabs(df)) {
+        bin = df;
+      } else {
+        double acc = 0.0;
+#pragma unroll 4
+        for (int e = 0; e < 16; ++e) acc += gl.w[e] * integrand(alpha[q], beta, gg[q], mid + half * gl.x[e]);
+        bin = acc * half;
+      }
+      sum += amp[q] * bin;
+      flo[q] = fhi;
+    }
+    dst[(size_t)k * s_t] = g.dv * sum;
+  }
+}
+
+// C[a][d] = w_d cos(2 pi a d / p), a in [0, h], d in [0, n).
+__global__ void cosine_kernel(int n, int p, double *__restrict__ C) {
+  const int h = p / 2;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (h + 1) * n) return;
+  const int a = idx / n;
+  const int d = idx % n;
+  const long long m = (2LL * a * d) % (2LL * p);
+  const double w = (d == 0) ? 1.0 : 2.0;
+  C[idx] = w * cospi((double)m / (double)p);
+}
+
+// Tiled FP64 GEMM, C = A * B, 32 x 64 output tile per block of 256 threads.
+constexpr int GBM = 32, GBN = 64, GBK = 16;
+
+__global__ void __launch_bounds__(256)
+gemm_f64_kernel(int M, long long N, int K, const double *__restrict__ A, int lda, long long sA,
+                const double *__restrict__ B, long long ldb, long long sB, double *__restrict__ C,
+                long long ldc, long long sC) {
+  __shared__ double As[GBK][GBM + 1];
+  __shared__ double Bs[GBK][GBN];
+  const int tid = threadIdx.x;
+  const int tx = tid % 16, ty = tid / 16;
+  const long long n0 = (long long)blockIdx.x * GBN;
+  const int m0 = blockIdx.y * GBM;
+  A += sA * blockIdx.z;
+  B += sB * blockIdx.z;
+  C += sC * blockIdx.z;
+  double acc[2][4] = {};
+  for (int k0 = 0; k0 < K; k0 += GBK) {
+    for (int e = tid; e < GBM * GBK; e += 256) {
+      const int mm = e / GBK, kk = e % GBK;
+      const int gm = m0 + mm, gk = k0 + kk;
+      As[kk][mm] = (gm < M && gk < K) ? A[(long long)gm * lda + gk] : 0.0;
+    }
+    for (int e = tid; e < GBK * GBN; e += 256) {
+      const int kk = e / GBN, nn = e % GBN;
+      const int gk = k0 + kk;
+      const long long gn = n0 + nn;
+      Bs[kk][nn] = (gk < K && gn < N) ? B[(long long)gk * ldb + gn] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GBK; ++kk) {
+      const double a0 = As[kk][ty * 2], a1 = As[kk][ty * 2 + 1];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const double b = Bs[kk][tx + 16 * j];
+        acc[0][j] = fma(a0, b, acc[0][j]);
+        acc[1][j] = fma(a1, b, acc[1][j]);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int gm = m0 + ty * 2 + i;
+    if (gm >= M) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const long long gn = n0 + tx + 16 * j;
+      if (gn < N) C[(long long)gm * ldc + gn] = acc[i][j];
+    }
+  }
+}
+
+__device__ inline void matrix_ab(int s, int &a, int &b) {
+  int bb = (int)((sqrt(8.0 * (double)s + 1.0) - 1.0) * 0.5);
+  while ((bb + 1) * (bb + 2) / 2 <= s) ++bb;
+  while (bb * (bb + 1) / 2 > s) --bb;
+  b = bb;
+  a = s - bb * (bb + 1) / 2;
+}
+
+template <typename T>
+__device__ inline void store_val(T *p, size_t i, double v) { p[i] = (T)v; }
+
+// Pack the FP64 spectrum k64[a][b][k][z] (a, b in [0, h]) into the contraction
+// layouts fwd[s][ntp][nzp] and adj[s][nzp][ntp], s = b(b+1)/2 + a for a <= b,
+// scaled by `scale` (the 1/p^2 of the unnormalised inverse FFTs).
+constexpr int PK = 16;
+
+template <int KIND>  // 0 double, 1 float, 2 bf16 hi+lo, 3 bf16 hi
+__global__ void __launch_bounds__(256)
+pack_kernel(Dims d, const double *__restrict__ k64, char *__restrict__ khat, KhatLayout lay,
+            double scale) {
+  extern __shared__ double tile[];  // [PK][nzp + 1]
+  const int s = blockIdx.x;
+  const int k0 = blockIdx.y * PK;
+  int a, b;
+  matrix_ab(s, a, b);
+  const int ld = d.nzp + 1;
+  const double *src = k64 + (((size_t)a * (d.h + 1) + b) * d.nt) * d.nz;
+  for (int e = threadIdx.x; e < PK * d.nzp; e += blockDim.x) {
+    const int kk = e / d.nzp, z = e % d.nzp;
+    const int k = k0 + kk;
+    tile[kk * ld + z] = (k < d.nt && z < d.nz) ? src[(size_t)k * d.nz + z] * scale : 0.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < PK * d.nzp; e += blockDim.x) {
+    const int kk = e / d.nzp, z = e % d.nzp;
+    const double v = tile[kk * ld + z];
+    const size_t i = ((size_t)s * d.ntp + k0 + kk) * d.nzp + z;
+    if (KIND == 0) {
+      reinterpret_cast<double *>(khat + lay.fwd)[i] = v;
+    } else if (KIND == 1) {
+      reinterpret_cast<float *>(khat + lay.fwd)[i] = (float)v;
+    } else {
+      const __bf16 hi = (__bf16)(float)v;
+      reinterpret_cast<__bf16 *>(khat + lay.fwd)[i] = hi;
+      if (KIND == 2) reinterpret_cast<__bf16 *>(khat + lay.fwd_lo)[i] = (__bf16)(float)(v - (double)(float)hi);
+    }
+  }
+  for (int e = threadIdx.x; e < PK * d.nzp; e += blockDim.x) {
+    const int z = e / PK, kk = e % PK;
+    const double v = tile[kk * ld + z];
+    const size_t i = ((size_t)s * d.nzp + z) * d.ntp + k0 + kk;
+    if (KIND == 0) {
+      reinterpret_cast<double *>(khat + lay.adj)[i] = v;
+    } else if (KIND == 1) {
+      reinterpret_cast<float *>(khat + lay.adj)[i] = (float)v;
+    } else {
+      const __bf16 hi = (__bf16)(float)v;
+      reinterpret_cast<__bf16 *>(khat + lay.adj)[i] = hi;
+      if (KIND == 2) reinterpret_cast<__bf16 *>(khat + lay.adj_lo)[i] = (__bf16)(float)(v - (double)(float)hi);
+    }
+  }
+}
+
+}  // namespace
+
+hipError_t launch_tab_values(const TabGeom &g, const LayerDepths &z, const GaussLegendre16 &gl,
+                             double *out, size_t s_dy, size_t s_dx, size_t s_z, size_t s_t,
+                             hipStream_t st) {
+  const size_t total = (size_t)g.nz * g.n * g.n;
+  const int z_fastest = (s_z == 1) ? 1 : 0;
+  const unsigned blocks = (unsigned)((total + 127) / 128);
+  hipLaunchKernelGGL(tab_values_kernel, dim3(blocks), dim3(128), 0, st, g, z, gl, out, s_dy, s_dx,
+                     s_z, s_t, z_fastest);
+  return hipGetLastError();
+}
+
+hipError_t launch_cosine_matrix(int n, int p, double *C, hipStream_t st) {
+  const int total = (p / 2 + 1) * n;
+  hipLaunchKernelGGL(cosine_kernel, dim3((total + 255) / 256), dim3(256), 0, st, n, p, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm_f64(int M, long long N, int K, const double *A, int lda, long long sA,
+                           const double *B, long long ldb, long long sB, double *C, long long ldc,
+                           long long sC, int batch, hipStream_t st) {
+  dim3 grid((unsigned)((N + GBN - 1) / GBN), (unsigned)((M + GBM - 1) / GBM), (unsigned)batch);
+  hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(256), 0, st, M, N, K, A, lda, sA, B, ldb, sB, C,
+                     ldc, sC);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(const Dims &d, ctof_precision prec, const double *k64, void *khat,
+                       const KhatLayout &lay, double scale, hipStream_t st) {
+  dim3 grid((unsigned)d.nmat, (unsigned)(d.ntp / PK));
+  const size_t shm = (size_t)PK * (d.nzp + 1) * sizeof(double);
+  char *kh = reinterpret_cast<char *>(khat);
+  switch (prec) {
+    case CTOF_FP64:
+      hipLaunchKernelGGL(pack_kernel<0>, grid, dim3(256), shm, st, d, k64, kh, lay, scale);
+      break;
+    case CTOF_FP32:
+      hipLaunchKernelGGL(pack_kernel<1>, grid, dim3(256), shm, st, d, k64, kh, lay, scale);
+      break;
+    case CTOF_BF16X3:
+      hipLaunchKernelGGL(pack_kernel<2>, grid, dim3(256), shm, st, d, k64, kh, lay, scale);
+      break;
+    default:
+      hipLaunchKernelGGL(pack_kernel<3>, grid, dim3(256), shm, st, d, k64, kh, lay, scale);
+      break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace ctof

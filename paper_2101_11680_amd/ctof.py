@@ -1,0 +1,283 @@
+"""Python binding of libctof (ctypes; argument marshalling only).
+
+Every step of the forward model, its adjoint, the kernel tabulation and the
+FISTA reconstruction runs in the HIP library; this module allocates device
+buffers with torch, passes raw pointers and the current stream, and turns
+status codes into exceptions.  It never computes any part of the method and
+has no CPU fallback: if the library is missing it raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libctof.so")
+
+FP64, FP32, BF16X3, BF16 = 0, 1, 2, 3
+PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "bf16": BF16}
+STATUS = {0: "CTOF_OK", -1: "CTOF_EINVAL", -2: "CTOF_ENOMEM", -3: "CTOF_EHIP",
+          -4: "CTOF_ENONFINITE", -5: "CTOF_EUNSUPPORTED"}
+
+EXPORTS = ("ctof_kernel_bytes", "ctof_kernel_tabulate", "ctof_kernel_tabulate_quadrant",
+           "ctof_kernel_free", "ctof_kernel_info", "ctof_workspace_bytes", "ctof_forward",
+           "ctof_adjoint", "ctof_reconstruct", "ctof_last_error")
+
+
+class CtofError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class _Geometry(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("pitch_mm", ctypes.c_double),
+                ("nz", ctypes.c_int32), ("z_mm", ctypes.POINTER(ctypes.c_double)),
+                ("dz_mm", ctypes.c_double), ("nt", ctypes.c_int32), ("dt_ps", ctypes.c_double),
+                ("t0_ps", ctypes.c_double), ("mus_prime_per_mm", ctypes.c_double),
+                ("mua_per_mm", ctypes.c_double), ("n_medium", ctypes.c_double)]
+
+
+class _SolverOpts(ctypes.Structure):
+    _fields_ = [("max_iter", ctypes.c_int32), ("lambda_tikhonov", ctypes.c_double),
+                ("lipschitz", ctypes.c_double), ("power_iters", ctypes.c_int32),
+                ("rel_tol", ctypes.c_double), ("check_every", ctypes.c_int32),
+                ("warm_start", ctypes.c_int32), ("history_dev", ctypes.c_void_p)]
+
+
+class _SolverReport(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("datafit0", ctypes.c_double), ("datafit", ctypes.c_double),
+                ("gmap_ratio", ctypes.c_double), ("lipschitz", ctypes.c_double),
+                ("lambda_", ctypes.c_double), ("lipschitz_a", ctypes.c_double),
+                ("gmap0", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libctof.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python paper_2101_11680_amd/build.py`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, sz, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32
+        gp = ctypes.POINTER(_Geometry)
+        L.ctof_kernel_bytes.argtypes = [gp, ctypes.c_int, ctypes.POINTER(sz), ctypes.POINTER(sz)]
+        L.ctof_kernel_tabulate.argtypes = [gp, ctypes.c_int, vp, sz, vp, sz, vp, ctypes.POINTER(vp)]
+        L.ctof_kernel_tabulate_quadrant.argtypes = [gp, vp, sz, vp]
+        L.ctof_kernel_free.argtypes = [vp]
+        L.ctof_kernel_free.restype = None
+        L.ctof_kernel_info.argtypes = [vp] + [ctypes.POINTER(i32)] * 6
+        L.ctof_workspace_bytes.argtypes = [vp, i32, ctypes.POINTER(sz), ctypes.POINTER(sz)]
+        L.ctof_forward.argtypes = [vp, vp, vp, vp, sz, vp]
+        L.ctof_adjoint.argtypes = [vp, vp, vp, vp, sz, vp]
+        L.ctof_reconstruct.argtypes = [vp, vp, vp, ctypes.POINTER(_SolverOpts),
+                                       ctypes.POINTER(_SolverReport), vp, sz, vp]
+        L.ctof_last_error.argtypes = []
+        L.ctof_last_error.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name != "ctof_kernel_free" and name != "ctof_last_error":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int) -> None:
+    if status != 0:
+        msg = lib().ctof_last_error().decode(errors="replace")
+        raise CtofError(status, msg)
+
+
+def _geometry(g) -> tuple:
+    z = (ctypes.c_double * len(g.z_mm))(*[float(v) for v in g.z_mm])
+    s = _Geometry(int(g.nx), int(g.ny), float(g.pitch_mm), len(g.z_mm),
+                  ctypes.cast(z, ctypes.POINTER(ctypes.c_double)), float(g.dz_mm), int(g.nt),
+                  float(g.dt_ps), float(getattr(g, "t0_ps", 0.0)), float(g.mus_prime_per_mm),
+                  float(g.mua_per_mm), float(g.n_medium))
+    return s, z  # keep z alive with the struct
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dtype(prec: int):
+    torch = _torch()
+    return torch.float64 if prec == FP64 else torch.float32
+
+
+def kernel_bytes(geometry, precision: int) -> tuple:
+    gs, _z = _geometry(geometry)
+    kb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(lib().ctof_kernel_bytes(ctypes.byref(gs), int(precision), ctypes.byref(kb), ctypes.byref(wb)))
+    return kb.value, wb.value
+
+
+@dataclass
+class KernelInfo:
+    n: int
+    nz: int
+    nt: int
+    p: int
+    nmat: int
+    precision: int
+
+
+class Kernel:
+    """A tabulated kernel: the host handle plus the device spectrum it refers to."""
+
+    def __init__(self, handle: int, khat, precision: int):
+        self._h = ctypes.c_void_p(handle)
+        self.khat = khat
+        self.precision = precision
+        vals = [ctypes.c_int32() for _ in range(6)]
+        _check(lib().ctof_kernel_info(self._h, *[ctypes.byref(v) for v in vals]))
+        self.info = KernelInfo(*[v.value for v in vals])
+        self._ws = {}
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        return self._h
+
+    def close(self) -> None:
+        if self._h is not None and self._h.value:
+            lib().ctof_kernel_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self, max_iter: int = 1) -> tuple:
+        a, b = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib().ctof_workspace_bytes(self._h, int(max_iter), ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def workspace(self, nbytes: int, device):
+        torch = _torch()
+        key = str(device)
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < nbytes:
+            ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+            self._ws[key] = ws
+        return ws
+
+
+def tabulate(geometry, precision: int = FP32, device="cuda", stream=None) -> Kernel:
+    torch = _torch()
+    gs, _z = _geometry(geometry)
+    kb, wb = kernel_bytes(geometry, precision)
+    khat = torch.empty(kb, dtype=torch.uint8, device=device)
+    ws = torch.empty(max(wb, 256), dtype=torch.uint8, device=device)
+    out = ctypes.c_void_p()
+    _check(lib().ctof_kernel_tabulate(ctypes.byref(gs), int(precision), khat.data_ptr(), kb,
+                                      ws.data_ptr(), ws.numel(), _stream_ptr(stream),
+                                      ctypes.byref(out)))
+    del ws
+    return Kernel(out.value, khat, precision)
+
+
+def tabulate_quadrant(geometry, device="cuda", stream=None):
+    """FP64 kernel values [nz][nt][n][n] for offsets dy, dx >= 0 (test hook)."""
+    torch = _torch()
+    gs, _z = _geometry(geometry)
+    n = int(geometry.nx)
+    out = torch.empty((len(geometry.z_mm), int(geometry.nt), n, n), dtype=torch.float64, device=device)
+    _check(lib().ctof_kernel_tabulate_quadrant(ctypes.byref(gs), out.data_ptr(),
+                                               out.numel() * 8, _stream_ptr(stream)))
+    return out
+
+
+def _contig(x, dtype, shape):
+    if x.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {x.dtype}")
+    if tuple(x.shape) != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {tuple(x.shape)}")
+    if not x.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return x
+
+
+def forward(k: Kernel, mu, out=None, stream=None):
+    torch = _torch()
+    i = k.info
+    mu = _contig(mu, _dtype(k.precision), (i.nz, i.n, i.n))
+    if out is None:
+        out = torch.empty((i.nt, i.n, i.n), dtype=mu.dtype, device=mu.device)
+    out = _contig(out, mu.dtype, (i.nt, i.n, i.n))
+    nb, _ = k.workspace_bytes(1)
+    ws = k.workspace(nb, mu.device)
+    _check(lib().ctof_forward(k.handle, mu.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(),
+                              _stream_ptr(stream)))
+    return out
+
+
+def adjoint(k: Kernel, r, out=None, stream=None):
+    torch = _torch()
+    i = k.info
+    r = _contig(r, _dtype(k.precision), (i.nt, i.n, i.n))
+    if out is None:
+        out = torch.empty((i.nz, i.n, i.n), dtype=r.dtype, device=r.device)
+    out = _contig(out, r.dtype, (i.nz, i.n, i.n))
+    nb, _ = k.workspace_bytes(1)
+    ws = k.workspace(nb, r.device)
+    _check(lib().ctof_adjoint(k.handle, r.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(),
+                              _stream_ptr(stream)))
+    return out
+
+
+@dataclass
+class Report:
+    iters: int
+    status: int
+    datafit0: float
+    datafit: float
+    gmap_ratio: float
+    lipschitz: float
+    lam: float
+    lipschitz_a: float
+    gmap0: float
+
+
+def reconstruct(k: Kernel, d, mu=None, max_iter: int = 200, lam: float = -1.0,
+                lipschitz: float = 0.0, power_iters: int = 50, rel_tol: float = 0.0,
+                check_every: int = 10, warm_start: bool = False, history: bool = False,
+                stream=None):
+    """FISTA reconstruction; returns (mu, Report, history or None)."""
+    torch = _torch()
+    i = k.info
+    d = _contig(d, _dtype(k.precision), (i.nt, i.n, i.n))
+    if mu is None:
+        mu = torch.empty((i.nz, i.n, i.n), dtype=d.dtype, device=d.device)
+        warm_start = False
+    mu = _contig(mu, d.dtype, (i.nz, i.n, i.n))
+    hist = torch.zeros((max_iter, 2), dtype=torch.float64, device=d.device) if history else None
+    opts = _SolverOpts(int(max_iter), float(lam), float(lipschitz), int(power_iters),
+                       float(rel_tol), int(check_every), int(bool(warm_start)),
+                       hist.data_ptr() if hist is not None else None)
+    rep = _SolverReport()
+    _, nb = k.workspace_bytes(max_iter)
+    ws = k.workspace(nb, d.device)
+    _check(lib().ctof_reconstruct(k.handle, d.data_ptr(), mu.data_ptr(), ctypes.byref(opts),
+                                  ctypes.byref(rep), ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
+    report = Report(rep.iters, rep.status, rep.datafit0, rep.datafit, rep.gmap_ratio,
+                    rep.lipschitz, rep.lambda_, rep.lipschitz_a, rep.gmap0)
+    if hist is not None:
+        hist = hist[: rep.iters]
+    return mu, report, hist
