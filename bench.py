@@ -1,0 +1,239 @@
+#!/usr/bin/env python3
+"""Throughput of the confocal ToF-DOT reconstruction on one MI355X.
+
+A step is one FISTA iteration of the whole hot path on one volume: forward
+contraction, measurement-side FFT passes with the residual, adjoint
+contraction, volume-side FFT passes with the prox/momentum update.  The
+workload is the 128 x 128 scan, 64 layers over 1-30 mm, 512 bins of 20 ps,
+mu_s' drawn from U[0.8, 1.2] per scan, synthetic absorbers and Poisson
+noise at 1e5 peak counts (no public data exist for this path).
+
+Prints one JSON line.  The timed region is one ctof_reconstruct call of
+exactly --steps iterations with L and lambda fixed beforehand (the power
+iteration and the kernel tabulation are set-up and are reported apart).
+Per-kernel durations come from HIP events that the library records on its
+stream inside the same timed call.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "recon iters/s at 128^2x64 vox, 512 bins; % HBM/MFMA peak; rel err vs FP64"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "contract_traffic.json")
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_digest(path: str) -> str:
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(n_launch_units: float):
+    """HBM bytes per contraction launch from the committed rocprofv3 counters,
+    or None when absent or taken on a different contraction source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as f:
+        t = json.load(f)
+    src = os.path.join(ROOT, "paper_2101_11680_amd", "csrc", "contract.hip")
+    if t.get("source_sha256") != source_digest(src):
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(g, n_iter: int = 2):
+    """Oracle FFT tier FISTA iterations on the host cores, bounded sample.
+
+    The oracle's per-iteration cost does not depend on the kernel values and
+    is affine in the number of time bins, so it is timed on the full lateral
+    grid and all layers with 32 and with 64 of the bins (seeded random
+    kernel values) and extrapolated linearly to the workload's bin count.
+    """
+    import numpy as np
+    from oracle import operator as oop
+    from oracle import solver as osolver
+
+    workers = os.cpu_count() or 1
+    times = {}
+    for nt_s in (32, 64):
+        rng = np.random.default_rng(nt_s)
+        Kq = rng.random((g.nz, g.ny, g.nx, nt_s))
+        F = oop.FFTOperator(Kq, workers=workers)
+        d = rng.random((nt_s, g.ny, g.nx))
+        osolver.fista(F, d, 1.0, 1e-3, 1)  # warm-up
+        t0 = time.perf_counter()
+        osolver.fista(F, d, 1.0, 1e-3, n_iter)
+        times[nt_s] = (time.perf_counter() - t0) / n_iter
+        del F, Kq
+    slope = (times[64] - times[32]) / 32.0
+    t_full = times[64] + slope * (g.nt - 64)
+    return {
+        "value": 1.0 / t_full,
+        "unit": "iters/s",
+        "cores": workers,
+        "kind": "oracle",
+        "sample": (f"FP64 oracle FFT-tier FISTA on the full {g.ny}x{g.nx} grid and {g.nz} layers "
+                   f"with 32 and 64 time bins ({n_iter} timed iterations each, seeded random kernel "
+                   f"values), extrapolated linearly to {g.nt} bins; scipy.fft with {workers} "
+                   f"workers, einsum single-threaded; measured s/iter "
+                   f"{times[32]:.3f} (32 bins), {times[64]:.3f} (64 bins)"),
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "bf16", "fp64"])
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              f"(asked for --gpus {args.gpus}, WORLD_SIZE={world})", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_2101_11680_amd import ctof
+    from synth import noise, phantoms, workloads
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    prec = ctof.PRECISIONS[args.precision]
+    dtype = torch.float64 if prec == ctof.FP64 else torch.float32
+
+    w = workloads.workload("precision")
+    g = workloads.geometry_for("precision", seed=args.seed)
+    log(f"geometry n={g.nx} nz={g.nz} nt={g.nt} dt={g.dt_ps}ps mus'={g.mus_prime_per_mm:.4f}")
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    k = ctof.tabulate(g, prec)
+    torch.cuda.synchronize()
+    t_tab = time.perf_counter() - t0
+    torch.cuda.empty_cache()
+    i = k.info
+    log(f"tabulated P={i.p} matrices={i.nmat} in {t_tab:.3f}s")
+
+    mu_true = phantoms.workload_phantom(w, g, args.seed)
+    m_true = ctof.forward(k, torch.tensor(mu_true, dtype=dtype, device=dev))
+    d_np = noise.poisson_histogram(m_true.double().cpu().numpy(), w["peak"][0], 1000 + args.seed)
+    d = torch.tensor(d_np, dtype=dtype, device=dev)
+    del m_true
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, rep0, _ = ctof.reconstruct(k, d, max_iter=1)
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    L, lam = rep0.lipschitz, rep0.lam
+    log(f"power iteration L={L:.6e} lambda={lam:.3e} ({t_setup:.3f}s incl. one iteration)")
+
+    if args.warmup > 0:
+        ctof.reconstruct(k, d, max_iter=args.warmup, lam=lam, lipschitz=L)
+    torch.cuda.synchronize()
+    log(f"warm-up {args.warmup} iterations done")
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mu, rep, _ = ctof.reconstruct(k, d, max_iter=args.steps, lam=lam, lipschitz=L, timing=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    assert rep.iters == args.steps
+    value = args.steps / wall
+    log(f"timed {args.steps} iterations in {wall:.4f}s -> {value:.1f} iters/s "
+        f"(loop events {rep.ms_loop:.3f} ms)")
+
+    # algorithmic bytes (unpadded sizes) of one contraction launch
+    es = {ctof.FP64: 8, ctof.FP32: 4, ctof.BF16X3: 4, ctof.BF16: 2}[prec]
+    vs = 8 if prec == ctof.FP64 else 4
+    nfreq = i.p * (i.p // 2 + 1)
+    khat_bytes = i.nmat * g.nt * g.nz * es
+    fwd_bytes = khat_bytes + nfreq * g.nz * 2 * vs + nfreq * g.nt * 2 * vs
+    adj_bytes = khat_bytes + nfreq * g.nt * 2 * vs + nfreq * g.nz * 2 * vs
+    fwd_ms = rep.ms_contract_fwd / rep.iters
+    adj_ms = rep.ms_contract_adj / rep.iters
+    ach_fwd = fwd_bytes / (fwd_ms * 1e-3) / 1e9
+    ach_adj = adj_bytes / (adj_ms * 1e-3) / 1e9
+    # whole-iteration floor: kernel spectrum twice, data once, volume state
+    vol = g.nz * g.ny * g.nx * vs
+    floor_bytes = 2 * khat_bytes + g.nt * g.ny * g.nx * vs + 5 * vol
+    traffic = measured_traffic(1.0)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp64": "f64", "bf16x3": "bf16x3+f32", "bf16": "bf16+f32"}[args.precision],
+        "data": "synthetic",
+        "config": {
+            "workload": ("precision config: 128x128 confocal scan at 0.5 mm, 64 layers 1-30 mm, "
+                         "512 bins of 20 ps, one volume, FISTA non-negative Tikhonov"),
+            "n": g.nx, "nz": g.nz, "nt": g.nt, "fft_size": i.p, "matrices": i.nmat,
+            "precision": args.precision, "mus_prime_per_mm": g.mus_prime_per_mm,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "contract_fwd_kernel (forward per-frequency contraction)",
+            "achieved": ach_fwd,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": ach_fwd / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "bytes_per_launch": fwd_bytes,
+            "ms_per_launch": fwd_ms,
+            "adjoint": {"achieved": ach_adj, "frac": ach_adj / HBM_PEAK_GBS,
+                        "bytes_per_launch": adj_bytes, "ms_per_launch": adj_ms},
+        },
+        "stages_ms_per_iter": {
+            "contract_fwd": fwd_ms, "fft_t": rep.ms_fft_t / rep.iters,
+            "contract_adj": adj_ms, "fft_z": rep.ms_fft_z / rep.iters,
+            "loop": rep.ms_loop / rep.iters,
+        },
+        "iteration_floor": {"bytes": floor_bytes,
+                            "achieved_GBs": floor_bytes * value / 1e9,
+                            "frac": floor_bytes * value / 1e9 / HBM_PEAK_GBS},
+        "setup_s": {"tabulate": t_tab, "power_iteration_and_one_iter": t_setup},
+        "report": {"datafit0": rep.datafit0, "datafit": rep.datafit,
+                   "gmap_ratio": rep.gmap_ratio},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on the host (bounded sample)")
+        out["cpu_baseline"] = cpu_baseline(g)
+        log(f"cpu baseline {out['cpu_baseline']['value']:.4f} iters/s")
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -177,6 +177,9 @@ ctof_status ctof_adjoint(ctof_kernel k, const void *r_dev, void *g_dev, void *ws
  *   history_dev      optional device array double[max_iter][2] receiving
  *                    (1/2 ||A y_k - d||^2, gradient-mapping ratio) per
  *                    iteration; NULL for none
+ *   timing           1: record HIP events on `stream` around the stages of
+ *                    every iteration and fill the ms_* fields of the report
+ *                    (adds event records between launches); 0: no events
  */
 typedef struct {
   int32_t max_iter;
@@ -187,6 +190,7 @@ typedef struct {
   int32_t check_every;
   int32_t warm_start;
   double *history_dev;
+  int32_t timing;
 } ctof_solver_opts;
 
 /*
@@ -196,10 +200,16 @@ typedef struct {
  *   gmap_ratio  gradient-mapping ratio of the last iteration
  *   lipschitz, lambda   the L and lambda used;  lipschitz_a  L_A (0 if L given)
  *   gmap0       ||max(0, A^T d)||, the ratio's denominator
+ *   ms_*        with opts.timing: GPU milliseconds summed over the iterations
+ *               for the forward contraction, the measurement-side FFT passes
+ *               (inverse column, residual row, column), the adjoint
+ *               contraction, the volume-side FFT passes (inverse column,
+ *               prox row, column), and the whole iteration loop
  */
 typedef struct {
   int32_t iters, status;
   double datafit0, datafit, gmap_ratio, lipschitz, lambda, lipschitz_a, gmap0;
+  double ms_contract_fwd, ms_fft_t, ms_contract_adj, ms_fft_z, ms_loop;
 } ctof_solver_report;
 
 /*

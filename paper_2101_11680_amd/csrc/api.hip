@@ -373,15 +373,37 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
     HIP_TRY(ops.mu_to_spec(a));
   }
   const std::vector<double> beta = fista_betas(K);
+  // optional stage timing: five events per iteration on the caller's stream
+  std::vector<hipEvent_t> ev;
+  struct EventGuard {
+    std::vector<hipEvent_t> *v;
+    ~EventGuard() {
+      for (hipEvent_t e : *v) (void)hipEventDestroy(e);
+    }
+  } guard{&ev};
+  if (opt->timing) {
+    ev.resize((size_t)K * 5, nullptr);
+    for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+  }
+  auto mark = [&](int it, int j) -> hipError_t {
+    return opt->timing ? hipEventRecord(ev[(size_t)it * 5 + j], st) : hipSuccess;
+  };
   int done = 0;
   for (int it = 0; it < K; ++it) {
     double *pk = part + (size_t)it * L.part_stride;
-    HIP_TRY(ops.fwd_to_xt());
+    HIP_TRY(mark(it, 0));
+    HIP_TRY(ctof::launch_contract(k, false, ops.yhat(), ops.mhat(), st));
+    HIP_TRY(mark(it, 1));
+    HIP_TRY(ctof::launch_col_pass<T>(dm, dm.ntp, true, ops.mhat(), ops.xt(), st));
     ctof::RowArgs a = ops.row(ctof::ROW_RESIDUAL, true);
     a.sp_in = d;
     a.partials = pk;
     HIP_TRY(ctof::launch_row_pass<T>(dm, a, st));
-    HIP_TRY(ops.adj_to_xz());
+    HIP_TRY(ctof::launch_col_pass<T>(dm, dm.ntp, false, ops.xt(), ops.mhat(), st));
+    HIP_TRY(mark(it, 2));
+    HIP_TRY(ctof::launch_contract(k, true, ops.mhat(), ops.yhat(), st));
+    HIP_TRY(mark(it, 3));
+    HIP_TRY(ctof::launch_col_pass<T>(dm, dm.nzp, true, ops.yhat(), ops.xz(), st));
     ctof::RowArgs b = ops.row(ctof::ROW_FISTA, false);
     b.sp_in = y;
     b.sp_out = y;
@@ -392,6 +414,7 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
     b.beta = beta[it];
     HIP_TRY(ctof::launch_row_pass<T>(dm, b, st));
     HIP_TRY(ctof::launch_col_pass<T>(dm, dm.nzp, false, ops.xz(), ops.yhat(), st));
+    HIP_TRY(mark(it, 4));
     done = it + 1;
     if (opt->rel_tol > 0 && (done % opt->check_every == 0) && done < K) {
       HIP_TRY(ctof::launch_history_k(part + (size_t)it * L.part_stride, 1, L.nblk_t, L.nblk_z, tau,
@@ -425,6 +448,23 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
   HIP_TRY(hipMemcpyAsync(hs, scal, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(h0, hist, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
+  if (opt->timing && done > 0) {
+    double acc[4] = {0, 0, 0, 0};
+    for (int it = 0; it < done; ++it) {
+      for (int j = 0; j < 4; ++j) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, ev[(size_t)it * 5 + j], ev[(size_t)it * 5 + j + 1]));
+        acc[j] += ms;
+      }
+    }
+    float loop = 0.f;
+    HIP_TRY(hipEventElapsedTime(&loop, ev[0], ev[(size_t)(done - 1) * 5 + 4]));
+    rep->ms_contract_fwd = acc[0];
+    rep->ms_fft_t = acc[1];
+    rep->ms_contract_adj = acc[2];
+    rep->ms_fft_z = acc[3];
+    rep->ms_loop = loop;
+  }
   rep->iters = done;
   rep->datafit0 = h0[0];
   rep->datafit = hs[3];

@@ -162,7 +162,7 @@ contract_adj_kernel(const T *__restrict__ khat, const T *__restrict__ vin, T *__
                     int h, int p, int nzp, int ntp) {
   using M = Mfma<T>;
   extern __shared__ unsigned char smem_raw[];
-  T *red = reinterpret_cast<T *>(smem_raw);  // [4 waves][ZT][32 lanes][4]
+  T *red = reinterpret_cast<T *>(smem_raw);  // [4 waves][ZT][64 lanes][4]
   const int s = blockIdx.x;
   const int w = threadIdx.x >> 6;
   const int l = threadIdx.x & 63;
@@ -192,13 +192,12 @@ contract_adj_kernel(const T *__restrict__ khat, const T *__restrict__ vin, T *__
       for (int kk = 0; kk < 4; ++kk) acc[zt] = M::step(av[kk], bv[kk], acc[zt]);
     }
   }
-  // sum the four waves' partial products (fixed order)
-  if (l < 32) {
+  // sum the four waves' partial products (fixed order); output rows 4g..4g+3
+  // of every tile sit in lane group g, so all 64 lanes take part
 #pragma unroll
-    for (int zt = 0; zt < ZT; ++zt)
+  for (int zt = 0; zt < ZT; ++zt)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) red[((w * ZT + zt) * 32 + l) * 4 + r] = acc[zt][r];
-  }
+    for (int r = 0; r < 4; ++r) red[((w * ZT + zt) * 64 + l) * 4 + r] = acc[zt][r];
   __syncthreads();
   if (w == 0 && col) {
     T *ocol = vout + ((size_t)sl.f[q & 3] * 2 + (c & 1)) * nzp;
@@ -207,10 +206,10 @@ contract_adj_kernel(const T *__restrict__ khat, const T *__restrict__ vin, T *__
       typename M::acc_t o;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        T v = red[((0 * ZT + zt) * 32 + l) * 4 + r];
-        v += red[((1 * ZT + zt) * 32 + l) * 4 + r];
-        v += red[((2 * ZT + zt) * 32 + l) * 4 + r];
-        v += red[((3 * ZT + zt) * 32 + l) * 4 + r];
+        T v = red[((0 * ZT + zt) * 64 + l) * 4 + r];
+        v += red[((1 * ZT + zt) * 64 + l) * 4 + r];
+        v += red[((2 * ZT + zt) * 64 + l) * 4 + r];
+        v += red[((3 * ZT + zt) * 64 + l) * 4 + r];
         o[r] = v;
       }
       store4<T>(ocol + zt * 16 + 4 * g, o);
@@ -328,12 +327,10 @@ contract_adj_bf16_kernel(const __bf16 *__restrict__ khi, const __bf16 *__restric
       }
     }
   }
-  if (l < 32) {
 #pragma unroll
-    for (int zt = 0; zt < ZT; ++zt)
+  for (int zt = 0; zt < ZT; ++zt)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) red[((w * ZT + zt) * 32 + l) * 4 + r] = acc[zt][r];
-  }
+    for (int r = 0; r < 4; ++r) red[((w * ZT + zt) * 64 + l) * 4 + r] = acc[zt][r];
   __syncthreads();
   if (w == 0 && col) {
     float *ocol = vout + ((size_t)sl.f[q & 3] * 2 + (c & 1)) * nzp;
@@ -342,10 +339,10 @@ contract_adj_bf16_kernel(const __bf16 *__restrict__ khi, const __bf16 *__restric
       float o[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        float v = red[((0 * ZT + zt) * 32 + l) * 4 + r];
-        v += red[((1 * ZT + zt) * 32 + l) * 4 + r];
-        v += red[((2 * ZT + zt) * 32 + l) * 4 + r];
-        v += red[((3 * ZT + zt) * 32 + l) * 4 + r];
+        float v = red[((0 * ZT + zt) * 64 + l) * 4 + r];
+        v += red[((1 * ZT + zt) * 64 + l) * 4 + r];
+        v += red[((2 * ZT + zt) * 64 + l) * 4 + r];
+        v += red[((3 * ZT + zt) * 64 + l) * 4 + r];
         o[r] = v;
       }
       *reinterpret_cast<float4 *>(ocol + zt * 16 + 4 * g) = make_float4(o[0], o[1], o[2], o[3]);
@@ -374,7 +371,7 @@ hipError_t launch_plain(const ctof_kernel_s *k, bool adjoint, const void *in, vo
   } else {
     const T *K = reinterpret_cast<const T *>(kh + k->layout.adj);
     const int zt = d.nzp / 16;
-    const size_t shm = (size_t)4 * zt * 32 * 4 * sizeof(T);
+    const size_t shm = (size_t)4 * zt * 64 * 4 * sizeof(T);
     switch (zt) {
       case 1: hipLaunchKernelGGL((contract_adj_kernel<T, 1>), grid, block, shm, st, K, vin, vout, d.h, d.p, d.nzp, d.ntp); break;
       case 2: hipLaunchKernelGGL((contract_adj_kernel<T, 2>), grid, block, shm, st, K, vin, vout, d.h, d.p, d.nzp, d.ntp); break;
@@ -410,7 +407,7 @@ hipError_t launch_bf16(const ctof_kernel_s *k, bool adjoint, const void *in, voi
     const __bf16 *hi = reinterpret_cast<const __bf16 *>(kh + k->layout.adj);
     const __bf16 *lo = KIND == 2 ? reinterpret_cast<const __bf16 *>(kh + k->layout.adj_lo) : hi;
     const int zt = d.nzp / 16;
-    const size_t shm = (size_t)4 * zt * 32 * 4 * sizeof(float);
+    const size_t shm = (size_t)4 * zt * 64 * 4 * sizeof(float);
     switch (zt) {
       case 2: hipLaunchKernelGGL((contract_adj_bf16_kernel<KIND, 2>), grid, block, shm, st, hi, lo, vin, vout, d.h, d.p, d.nzp, d.ntp); break;
       case 4: hipLaunchKernelGGL((contract_adj_bf16_kernel<KIND, 4>), grid, block, shm, st, hi, lo, vin, vout, d.h, d.p, d.nzp, d.ntp); break;

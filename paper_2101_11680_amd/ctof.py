@@ -45,7 +45,8 @@ class _SolverOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("lambda_tikhonov", ctypes.c_double),
                 ("lipschitz", ctypes.c_double), ("power_iters", ctypes.c_int32),
                 ("rel_tol", ctypes.c_double), ("check_every", ctypes.c_int32),
-                ("warm_start", ctypes.c_int32), ("history_dev", ctypes.c_void_p)]
+                ("warm_start", ctypes.c_int32), ("history_dev", ctypes.c_void_p),
+                ("timing", ctypes.c_int32)]
 
 
 class _SolverReport(ctypes.Structure):
@@ -53,7 +54,9 @@ class _SolverReport(ctypes.Structure):
                 ("datafit0", ctypes.c_double), ("datafit", ctypes.c_double),
                 ("gmap_ratio", ctypes.c_double), ("lipschitz", ctypes.c_double),
                 ("lambda_", ctypes.c_double), ("lipschitz_a", ctypes.c_double),
-                ("gmap0", ctypes.c_double)]
+                ("gmap0", ctypes.c_double), ("ms_contract_fwd", ctypes.c_double),
+                ("ms_fft_t", ctypes.c_double), ("ms_contract_adj", ctypes.c_double),
+                ("ms_fft_z", ctypes.c_double), ("ms_loop", ctypes.c_double)]
 
 
 _lib = None
@@ -253,12 +256,17 @@ class Report:
     lam: float
     lipschitz_a: float
     gmap0: float
+    ms_contract_fwd: float = 0.0
+    ms_fft_t: float = 0.0
+    ms_contract_adj: float = 0.0
+    ms_fft_z: float = 0.0
+    ms_loop: float = 0.0
 
 
 def reconstruct(k: Kernel, d, mu=None, max_iter: int = 200, lam: float = -1.0,
                 lipschitz: float = 0.0, power_iters: int = 50, rel_tol: float = 0.0,
                 check_every: int = 10, warm_start: bool = False, history: bool = False,
-                stream=None):
+                timing: bool = False, stream=None):
     """FISTA reconstruction; returns (mu, Report, history or None)."""
     torch = _torch()
     i = k.info
@@ -270,14 +278,15 @@ def reconstruct(k: Kernel, d, mu=None, max_iter: int = 200, lam: float = -1.0,
     hist = torch.zeros((max_iter, 2), dtype=torch.float64, device=d.device) if history else None
     opts = _SolverOpts(int(max_iter), float(lam), float(lipschitz), int(power_iters),
                        float(rel_tol), int(check_every), int(bool(warm_start)),
-                       hist.data_ptr() if hist is not None else None)
+                       hist.data_ptr() if hist is not None else None, int(bool(timing)))
     rep = _SolverReport()
     _, nb = k.workspace_bytes(max_iter)
     ws = k.workspace(nb, d.device)
     _check(lib().ctof_reconstruct(k.handle, d.data_ptr(), mu.data_ptr(), ctypes.byref(opts),
                                   ctypes.byref(rep), ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
     report = Report(rep.iters, rep.status, rep.datafit0, rep.datafit, rep.gmap_ratio,
-                    rep.lipschitz, rep.lambda_, rep.lipschitz_a, rep.gmap0)
+                    rep.lipschitz, rep.lambda_, rep.lipschitz_a, rep.gmap0, rep.ms_contract_fwd,
+                    rep.ms_fft_t, rep.ms_contract_adj, rep.ms_fft_z, rep.ms_loop)
     if hist is not None:
         hist = hist[: rep.iters]
     return mu, report, hist
