@@ -20,7 +20,9 @@
 // in k-step kk, lane group g = lane/16 carries index g * KC + kk.
 //
 // Layouts (element type by precision):
-//   khat fwd   [s][ntp][nzp]       khat adj [s][nzp][ntp]
+//   khat fwd / adj   per matrix, fragment order (see Frag): each 16-byte
+//                    vector load reads one contiguous 1 KB run per wave,
+//                    streamed with non-temporal loads (read once per pass)
 //   mu side    [ky][kx][re/im][nzp]  t side [ky][kx][re/im][ntp]
 #include "ctof_internal.h"
 
@@ -82,6 +84,11 @@ struct Mfma<double> {
   }
 };
 
+typedef float nt_f4 __attribute__((ext_vector_type(4)));
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+typedef unsigned int nt_u4 __attribute__((ext_vector_type(4)));
+
+// N contiguous elements (16-byte words) through the regular cache path
 template <typename T, int N>
 __device__ __forceinline__ void load_run(const T *__restrict__ p, T (&v)[N]) {
   constexpr int PER = 16 / sizeof(T);
@@ -98,6 +105,28 @@ __device__ __forceinline__ void load_run(const T *__restrict__ p, T (&v)[N]) {
       const double2 w = *reinterpret_cast<const double2 *>(p + q * PER);
       v[q * 2 + 0] = w.x;
       v[q * 2 + 1] = w.y;
+    }
+  }
+}
+
+// N elements of one lane from a fragment block: word q sits at (q*64 + lane)
+template <typename T, int N>
+__device__ __forceinline__ void load_frag(const T *__restrict__ blk, int lane, T (&v)[N]) {
+  constexpr int PER = 16 / sizeof(T);
+  static_assert(N % PER == 0, "fragments are whole 16-byte words");
+#pragma unroll
+  for (int q = 0; q < N / PER; ++q) {
+    const T *p = blk + ((size_t)q * 64 + lane) * PER;
+    if constexpr (sizeof(T) == 4) {
+      const nt_f4 w = __builtin_nontemporal_load(reinterpret_cast<const nt_f4 *>(p));
+      v[q * 4 + 0] = w[0];
+      v[q * 4 + 1] = w[1];
+      v[q * 4 + 2] = w[2];
+      v[q * 4 + 3] = w[3];
+    } else {
+      const nt_d2 w = __builtin_nontemporal_load(reinterpret_cast<const nt_d2 *>(p));
+      v[q * 2 + 0] = w[0];
+      v[q * 2 + 1] = w[1];
     }
   }
 }
@@ -128,8 +157,7 @@ contract_fwd_kernel(const T *__restrict__ khat, const T *__restrict__ vin, T *__
   const int nchunk = nzp / (4 * KZ);
   const T *vcol = vin + ((size_t)sl.f[q & 3] * 2 + (c & 1)) * nzp;
   T *ocol = vout + ((size_t)sl.f[q & 3] * 2 + (c & 1)) * ntp;
-  const int arow = M::row_of(l & 15);
-  const T *kbase = khat + (size_t)s * ntp * nzp;
+  const int ntt = ntp / 16;
   for (int ch = 0; ch < nchunk; ++ch) {
     T bv[KZ];
     if (col) {
@@ -141,7 +169,7 @@ contract_fwd_kernel(const T *__restrict__ khat, const T *__restrict__ vin, T *__
     for (int tt = w; tt < ntp / 16; tt += 4) {
       const int t0 = tt * 16;
       T av[KZ];
-      load_run<T, KZ>(kbase + (size_t)(t0 + arow) * nzp + ch * 4 * KZ + g * KZ, av);
+      load_frag<T, KZ>(khat + (((size_t)s * ntt + tt) * nchunk + ch) * (64 * KZ), l, av);
       typename M::acc_t acc = {0, 0, 0, 0};
       if (ch > 0 && col) {
         // accumulate onto the previous z-chunk's partial result
@@ -171,8 +199,6 @@ contract_adj_kernel(const T *__restrict__ khat, const T *__restrict__ vin, T *__
   const int q = c >> 1;
   const bool col = (c < 8) && sl.valid[q & 3];
   const T *vcol = vin + ((size_t)sl.f[q & 3] * 2 + (c & 1)) * ntp;
-  const int arow = M::row_of(l & 15);
-  const T *kbase = khat + (size_t)s * nzp * ntp;
   typename M::acc_t acc[ZT];
 #pragma unroll
   for (int zt = 0; zt < ZT; ++zt) acc[zt] = {0, 0, 0, 0};
@@ -187,7 +213,7 @@ contract_adj_kernel(const T *__restrict__ khat, const T *__restrict__ vin, T *__
 #pragma unroll
     for (int zt = 0; zt < ZT; ++zt) {
       T av[4];
-      load_run<T, 4>(kbase + (size_t)(zt * 16 + arow) * ntp + t0, av);
+      load_frag<T, 4>(khat + (((size_t)s * (ntp / 16) + ch) * ZT + zt) * 256, l, av);
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) acc[zt] = M::step(av[kk], bv[kk], acc[zt]);
     }
@@ -225,7 +251,7 @@ __device__ inline void split_bf16(float v, __bf16 &hi, __bf16 &lo) {
 }
 
 __device__ __forceinline__ v8bf load_bf8(const __bf16 *p) {
-  const uint4 u = *reinterpret_cast<const uint4 *>(p);
+  const nt_u4 u = __builtin_nontemporal_load(reinterpret_cast<const nt_u4 *>(p));
   v8bf r;
   __builtin_memcpy(&r, &u, 16);
   return r;
@@ -246,8 +272,7 @@ contract_fwd_bf16_kernel(const __bf16 *__restrict__ khi, const __bf16 *__restric
   const int nchunk = nzp / (4 * KZ);
   const float *vcol = vin + ((size_t)sl.f[q & 3] * 2 + (c & 1)) * nzp;
   float *ocol = vout + ((size_t)sl.f[q & 3] * 2 + (c & 1)) * ntp;
-  const int arow = l & 15;
-  const size_t kb = (size_t)s * ntp * nzp;
+  const int ntt = ntp / 16;
   for (int ch = 0; ch < nchunk; ++ch) {
     v8bf bh[KZ / 8], bl[KZ / 8];
 #pragma unroll
@@ -263,7 +288,7 @@ contract_fwd_bf16_kernel(const __bf16 *__restrict__ khi, const __bf16 *__restric
     }
     for (int tt = w; tt < ntp / 16; tt += 4) {
       const int t0 = tt * 16;
-      const size_t off = kb + (size_t)(t0 + arow) * nzp + ch * 4 * KZ + g * KZ;
+      const size_t blk = (((size_t)s * ntt + tt) * nchunk + ch) * (64 * KZ);
       v4f acc = {0, 0, 0, 0};
       if (ch > 0 && col) {
         const float *o = ocol + t0 + 4 * g;
@@ -271,11 +296,12 @@ contract_fwd_bf16_kernel(const __bf16 *__restrict__ khi, const __bf16 *__restric
       }
 #pragma unroll
       for (int e = 0; e < KZ / 8; ++e) {
-        const v8bf ah = load_bf8(khi + off + e * 8);
+        const size_t off = blk + ((size_t)e * 64 + l) * 8;
+        const v8bf ah = load_bf8(khi + off);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[e], acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[e], acc, 0, 0, 0);
         if (KIND == 2) {
-          const v8bf al = load_bf8(klo + off + e * 8);
+          const v8bf al = load_bf8(klo + off);
           acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[e], acc, 0, 0, 0);
         }
       }
@@ -299,8 +325,6 @@ contract_adj_bf16_kernel(const __bf16 *__restrict__ khi, const __bf16 *__restric
   const int q = c >> 1;
   const bool col = (c < 8) && sl.valid[q & 3];
   const float *vcol = vin + ((size_t)sl.f[q & 3] * 2 + (c & 1)) * ntp;
-  const int arow = l & 15;
-  const size_t kb = (size_t)s * nzp * ntp;
   v4f acc[ZT];
 #pragma unroll
   for (int zt = 0; zt < ZT; ++zt) acc[zt] = {0, 0, 0, 0};
@@ -317,7 +341,7 @@ contract_adj_bf16_kernel(const __bf16 *__restrict__ khi, const __bf16 *__restric
     }
 #pragma unroll
     for (int zt = 0; zt < ZT; ++zt) {
-      const size_t off = kb + (size_t)(zt * 16 + arow) * ntp + t0;
+      const size_t off = (((size_t)s * (ntp / 32) + ch) * ZT + zt) * 512 + (size_t)l * 8;
       const v8bf ah = load_bf8(khi + off);
       acc[zt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[zt], 0, 0, 0);
       acc[zt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[zt], 0, 0, 0);

@@ -51,6 +51,35 @@ struct KhatLayout {
 
 KhatLayout khat_layout(const Dims &d, ctof_precision prec);
 
+// Fragment order of the packed spectrum: every 16-byte vector load of the
+// contraction kernels reads one contiguous 1 KB run per wavefront.
+//   v     elements per 16 bytes (4 float, 2 double, 8 bf16)
+//   kz    forward: layers per lane group per 64-layer chunk (min(nzp,64)/4)
+//   tc    adjoint: bins per chunk (16, or 32 for bf16); tl = tc/4 per lane group
+// forward element (s, tt, ch, q, lane, e):
+//   t = 16 tt + row(lane % 16),  z = 4 kz ch + kz (lane / 16) + v q + e
+// adjoint element (s, tc_i, zt, q, lane, e):
+//   z = 16 zt + row(lane % 16),  t = tc tc_i + tl (lane / 16) + v q + e
+// row() is the identity except for FP64, whose 16x16x4 result interleaves
+// rows (item r of lane group g holds row 4r + g): row(i) = 4 (i % 4) + i / 4.
+struct Frag {
+  int v, kz, tc, tl;
+  bool f64;
+};
+
+__host__ __device__ inline Frag frag_of(const Dims &d, ctof_precision prec) {
+  Frag f;
+  f.f64 = prec == CTOF_FP64;
+  const bool bf = prec == CTOF_BF16X3 || prec == CTOF_BF16;
+  f.v = f.f64 ? 2 : (bf ? 8 : 4);
+  f.kz = (d.nzp >= 64 ? 64 : d.nzp) / 4;
+  f.tc = bf ? 32 : 16;
+  f.tl = f.tc / 4;
+  return f;
+}
+
+__host__ __device__ inline int frag_row(bool f64, int i) { return f64 ? 4 * (i & 3) + (i >> 2) : i; }
+
 }  // namespace ctof
 
 struct ctof_kernel_s {

@@ -148,6 +148,13 @@ __device__ __forceinline__ void dft_stage2_unit(const T *br, const T *bi, int ld
   dft_reg<T, R2, DIR>(zr, zi);
 }
 
+// Planes per block: 32 (128-byte runs) when that still gives enough blocks to
+// fill the chip, else 16; FP64 always 16.
+inline int batch_block(const Dims &d, int B, bool fp64) {
+  if (fp64 || (B % 32) != 0) return 16;
+  return ((d.h + 1) * (B / 32) >= 1024) ? 32 : 16;
+}
+
 template <int P>
 struct Fac {
   static constexpr int R1 = P == 256 ? 16 : P == 128 ? 16 : P == 64 ? 8 : P == 32 ? 8 : P == 16 ? 4 : P == 8 ? 4 : 2;
@@ -155,116 +162,172 @@ struct Fac {
 };
 
 // ---- column pass ---------------------------------------------------------------
+// One block per (ky, BB planes).  Stage 1 reads its R1 inputs straight from
+// global memory into registers (lanes run along the planes, so every load
+// instruction covers contiguous runs), stage 2 gets its inputs through LDS.
+// The exchange goes through one real-valued LDS array, first the real then
+// the imaginary parts, to keep the block's LDS small.
 template <typename T, int P, int BB, bool INV>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(512)
 col_pass_kernel(int n, int B, const T *__restrict__ in, T *__restrict__ out) {
   constexpr int R1 = Fac<P>::R1, R2 = Fac<P>::R2;
   constexpr int DIR = INV ? 1 : -1;
   constexpr int ld = BB + 1;
-  extern __shared__ unsigned char smem_raw[];
-  T *br = reinterpret_cast<T *>(smem_raw);
-  T *bi = br + P * ld;
-  T *twc = bi + P * ld;
-  T *tws = twc + P;
+  static_assert(R1 * BB <= 512 && R2 * BB <= 512, "one unit per thread");
+  __shared__ T lds[P * ld];
+  __shared__ T twc[P], tws[P];
   const int ky = blockIdx.x;
   const int b0 = blockIdx.y * BB;
   const int rows_in = INV ? P : n;
   const int rows_out = INV ? n : P;
+  const int tid = threadIdx.x;
   build_twiddles<T, P>(twc, tws);
   const T *src = in + (size_t)ky * rows_in * 2 * B + b0;
-  for (int e = threadIdx.x; e < P * 2 * BB; e += blockDim.x) {
-    const int b = e % BB;
-    const int r = e / BB;
-    const int row = r >> 1, reim = r & 1;
-    T v = (T)0;
-    if (row < rows_in) v = src[((size_t)row * 2 + reim) * B + b];
-    (reim ? bi : br)[row * ld + b] = v;
+  const bool act1 = tid < R2 * BB;
+  const int b1 = tid % BB, n2 = tid / BB;
+  T yr[R1], yi[R1];
+  if (act1) {
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) {
+      const int row = R2 * n1 + n2;
+      if (row < rows_in) {
+        yr[n1] = src[((size_t)row * 2) * B + b1];
+        yi[n1] = src[((size_t)row * 2 + 1) * B + b1];
+      } else {
+        yr[n1] = (T)0;
+        yi[n1] = (T)0;
+      }
+    }
+  }
+  __syncthreads();  // twiddle table ready
+  if (act1) {
+    dft_reg<T, R1, DIR>(yr, yi);
+#pragma unroll
+    for (int k1 = 1; k1 < R1; ++k1) {
+      const int m = (n2 * k1) & (P - 1);
+      const T c = twc[m], sn = (T)DIR * tws[m];
+      const T tr = yr[k1] * c - yi[k1] * sn;
+      yi[k1] = yr[k1] * sn + yi[k1] * c;
+      yr[k1] = tr;
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) lds[(R2 * k1 + n2) * ld + b1] = yr[k1];
   }
   __syncthreads();
-  dft_stage1<T, R1, R2, BB, DIR>(br, bi, ld, twc, tws, 1, P - 1);
+  const bool act2 = tid < R1 * BB;
+  const int b2 = tid % BB, k1 = tid / BB;
+  T zr[R2], zi[R2];
+  if (act2) {
+#pragma unroll
+    for (int m = 0; m < R2; ++m) zr[m] = lds[(R2 * k1 + m) * ld + b2];
+  }
   __syncthreads();
-  T *dst = out + (size_t)ky * rows_out * 2 * B + b0;
-  for (int u = threadIdx.x; u < R1 * BB; u += blockDim.x) {
-    const int b = u % BB, k1 = u / BB;
-    T zr[R2], zi[R2];
-    dft_stage2_unit<T, R1, R2, DIR>(br, bi, ld, k1, b, zr, zi);
+  if (act1) {
+#pragma unroll
+    for (int kk = 0; kk < R1; ++kk) lds[(R2 * kk + n2) * ld + b1] = yi[kk];
+  }
+  __syncthreads();
+  if (act2) {
+#pragma unroll
+    for (int m = 0; m < R2; ++m) zi[m] = lds[(R2 * k1 + m) * ld + b2];
+    dft_reg<T, R2, DIR>(zr, zi);
+    T *dst = out + (size_t)ky * rows_out * 2 * B + b0;
 #pragma unroll
     for (int k2 = 0; k2 < R2; ++k2) {
       const int row = k1 + R1 * k2;
       if (row < rows_out) {
-        dst[((size_t)row * 2) * B + b] = zr[k2];
-        dst[((size_t)row * 2 + 1) * B + b] = zi[k2];
+        dst[((size_t)row * 2) * B + b2] = zr[k2];
+        dst[((size_t)row * 2 + 1) * B + b2] = zi[k2];
       }
     }
   }
 }
 
-// ---- row pass --------------------------------------------------------------------
-template <typename T, int P, int BB>
-__global__ void __launch_bounds__(256)
-row_pass_kernel(int n, RowArgs a) {
-  constexpr int H = P / 2;
+// Two-stage length-H DFT in place on (wr, wi)[m * ld + b], natural order in
+// and out; every thread holds at most one stage-2 unit.
+template <typename T, int H, int BB, int DIR>
+__device__ __forceinline__ void dft_lds_inplace(T *wr, T *wi, const T *twc, const T *tws) {
   constexpr int R1 = Fac<H>::R1, R2 = Fac<H>::R2;
   constexpr int ld = BB + 1;
-  extern __shared__ unsigned char smem_raw[];
-  T *xr = reinterpret_cast<T *>(smem_raw);
-  T *xi = xr + (H + 1) * ld;
-  T *wr = xi + (H + 1) * ld;
-  T *wi = wr + H * ld;
-  T *twc = wi + H * ld;
-  T *tws = twc + P;
-  double *red = reinterpret_cast<double *>(tws + P + (P & 1));
+  // stage-1 twiddles W_H^m live at index 2m of the length-2H table
+  dft_stage1<T, R1, R2, BB, DIR>(wr, wi, ld, twc, tws, 2, 2 * H - 1);
+  __syncthreads();
+  const int tid = threadIdx.x;
+  const bool act = tid < R1 * BB;
+  const int b = tid % BB, k1 = tid / BB;
+  T zr[R2], zi[R2];
+  if (act) dft_stage2_unit<T, R1, R2, DIR>(wr, wi, ld, k1, b, zr, zi);
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) {
+      const int m = k1 + R1 * k2;
+      wr[m * ld + b] = zr[k2];
+      wi[m * ld + b] = zi[k2];
+    }
+  }
+  __syncthreads();
+}
+
+// ---- row pass --------------------------------------------------------------------
+// One block per (scan row i, BB planes): c2r along ky, crop, pointwise step,
+// pad, r2c.  A real DFT of length P is a complex DFT of length H = P/2 on
+// (even, odd) sample pairs; the pre/post-processing pairs bins k and H - k.
+template <typename T, int P, int BB>
+__global__ void __launch_bounds__(512)
+row_pass_kernel(int n, RowArgs a) {
+  constexpr int H = P / 2;
+  constexpr int ld = BB + 1;
+  constexpr int NT = 512;
+  __shared__ T wr[H * ld], wi[H * ld];
+  __shared__ T twc[P], tws[P];
+  __shared__ double red[2 * NT];
 
   const int op = a.op;
   const int i = blockIdx.x;
   const int b0 = blockIdx.y * BB;
   const int B = a.B;
+  const int tid = threadIdx.x;
   const bool spec_in = (op != ROW_SPATIAL_TO_SPEC) && (op != ROW_SCALE_TO_SPEC);
   const bool spec_out = (op == ROW_SPATIAL_TO_SPEC) || (op == ROW_SCALE_TO_SPEC) ||
                         (op == ROW_RESIDUAL) || (op == ROW_PASS) || (op == ROW_FISTA);
   const int nh = (n + 1) / 2;
   build_twiddles<T, P>(twc, tws);
+  __syncthreads();
 
   if (spec_in) {
+    // Z[k] = A + i B,  A = X[k] + conj(X[H-k]),  B = (X[k] - conj(X[H-k])) e^{+2 pi i k/P}
     const T *src = reinterpret_cast<const T *>(a.spec_in) + b0;
-    for (int e = threadIdx.x; e < (H + 1) * 2 * BB; e += blockDim.x) {
-      const int b = e % BB;
-      const int r = e / BB;
-      const int ky = r >> 1, reim = r & 1;
-      const T v = src[(((size_t)ky * n + i) * 2 + reim) * B + b];
-      (reim ? xi : xr)[ky * ld + b] = v;
-    }
-    __syncthreads();
-    // Z[k] = A[k] + i B[k], A = X[k] + conj(X[H-k]), B = (X[k] - conj(X[H-k])) e^{+2 pi i k/P}
-    for (int u = threadIdx.x; u < H * BB; u += blockDim.x) {
+    for (int u = tid; u < (H / 2 + 1) * BB; u += NT) {
       const int b = u % BB, k = u / BB;
-      const T x1r = xr[k * ld + b], x1i = xi[k * ld + b];
-      const T x2r = xr[(H - k) * ld + b], x2i = -xi[(H - k) * ld + b];
-      const T ar = x1r + x2r, ai = x1i + x2i;
-      const T dr = x1r - x2r, di = x1i - x2i;
-      const T c = twc[k], s = tws[k];
-      const T br_ = dr * c - di * s, bi_ = dr * s + di * c;
-      wr[k * ld + b] = ar - bi_;
-      wi[k * ld + b] = ai + br_;
-    }
-    __syncthreads();
-    dft_stage1<T, R1, R2, BB, 1>(wr, wi, ld, twc, tws, 2, P - 1);
-    __syncthreads();
-    for (int u = threadIdx.x; u < R1 * BB; u += blockDim.x) {
-      const int b = u % BB, k1 = u / BB;
-      T zr[R2], zi[R2];
-      dft_stage2_unit<T, R1, R2, 1>(wr, wi, ld, k1, b, zr, zi);
-#pragma unroll
-      for (int k2 = 0; k2 < R2; ++k2) {
-        const int m = k1 + R1 * k2;
-        xr[m * ld + b] = zr[k2];
-        xi[m * ld + b] = zi[k2];
+      const size_t o1 = (((size_t)k * n + i) * 2) * B + b;
+      const size_t o2 = (((size_t)(H - k) * n + i) * 2) * B + b;
+      const T x1r = src[o1], x1i = src[o1 + B];
+      const T x2r = src[o2], x2i = src[o2 + B];
+      {
+        const T ar = x1r + x2r, ai = x1i - x2i;
+        const T dr = x1r - x2r, di = x1i + x2i;
+        const T c = twc[k], s = tws[k];
+        const T br_ = dr * c - di * s, bi_ = dr * s + di * c;
+        wr[k * ld + b] = ar - bi_;
+        wi[k * ld + b] = ai + br_;
+      }
+      if (k > 0 && k < H / 2) {
+        const int kk = H - k;
+        const T ar = x2r + x1r, ai = x2i - x1i;
+        const T dr = x2r - x1r, di = x2i + x1i;
+        const T c = twc[kk], s = tws[kk];
+        const T br_ = dr * c - di * s, bi_ = dr * s + di * c;
+        wr[kk * ld + b] = ar - bi_;
+        wi[kk * ld + b] = ai + br_;
       }
     }
     __syncthreads();
+    dft_lds_inplace<T, H, BB, 1>(wr, wi, twc, tws);
   }
 
-  // pointwise step on the cropped real row x[j], j < n
+  // pointwise step on the cropped real row x[j], j < n (in place: the value
+  // x[j] lives in the slot that receives r[j])
   double acc0 = 0.0, acc1 = 0.0;
   const T tau = (T)a.tau, lam = (T)a.lambda, beta = (T)a.beta;
   T scale = (T)1;
@@ -272,13 +335,14 @@ row_pass_kernel(int n, RowArgs a) {
   const T *sp_in = reinterpret_cast<const T *>(a.sp_in);
   T *sp_out = reinterpret_cast<T *>(a.sp_out);
   T *sp_aux = reinterpret_cast<T *>(a.sp_aux);
-  for (int u = threadIdx.x; u < n * BB; u += blockDim.x) {
+  for (int u = tid; u < n * BB; u += NT) {
     const int j = u % n, b = u / n;
     const int pl = b0 + b;
     const bool valid = pl < a.nplanes;
     const size_t idx = ((size_t)pl * n + i) * n + j;
+    T *slot = ((j & 1) ? wi : wr) + (j >> 1) * ld + b;
     T x = (T)0;
-    if (spec_in) x = (j & 1) ? xi[(j >> 1) * ld + b] : xr[(j >> 1) * ld + b];
+    if (spec_in) x = *slot;
     T r = (T)0;
     switch (op) {
       case ROW_SPEC_TO_SPATIAL:
@@ -335,16 +399,10 @@ row_pass_kernel(int n, RowArgs a) {
       default:
         break;
     }
-    if (spec_out) {
-      if (j & 1)
-        wi[(j >> 1) * ld + b] = r;
-      else
-        wr[(j >> 1) * ld + b] = r;
-    }
+    if (spec_out) *slot = r;
   }
   if (spec_out) {
-    // zero the padded part of the half-length sequence
-    for (int u = threadIdx.x; u < H * BB; u += blockDim.x) {
+    for (int u = tid; u < H * BB; u += NT) {
       const int b = u % BB, m = u / BB;
       if (m >= nh) {
         wr[m * ld + b] = (T)0;
@@ -355,96 +413,85 @@ row_pass_kernel(int n, RowArgs a) {
     }
   }
   if (a.partials) {
-    red[threadIdx.x] = acc0;
-    red[blockDim.x + threadIdx.x] = acc1;
+    red[tid] = acc0;
+    red[NT + tid] = acc1;
   }
   __syncthreads();
   if (a.partials) {
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-      if ((int)threadIdx.x < s) {
-        red[threadIdx.x] += red[threadIdx.x + s];
-        red[blockDim.x + threadIdx.x] += red[blockDim.x + threadIdx.x + s];
+    for (int s = NT / 2; s > 0; s >>= 1) {
+      if (tid < s) {
+        red[tid] += red[tid + s];
+        red[NT + tid] += red[NT + tid + s];
       }
       __syncthreads();
     }
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
       const size_t blk = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
       a.partials[2 * blk] = red[0];
-      a.partials[2 * blk + 1] = red[blockDim.x];
+      a.partials[2 * blk + 1] = red[NT];
     }
   }
   if (!spec_out) return;
 
   // r2c: Z' = DFT_H(r_even + i r_odd); X'[k] = Ev[k] + e^{-2 pi i k/P} Od[k]
-  dft_stage1<T, R1, R2, BB, -1>(wr, wi, ld, twc, tws, 2, P - 1);
-  __syncthreads();
-  for (int u = threadIdx.x; u < R1 * BB; u += blockDim.x) {
-    const int b = u % BB, k1 = u / BB;
-    T zr[R2], zi[R2];
-    dft_stage2_unit<T, R1, R2, -1>(wr, wi, ld, k1, b, zr, zi);
-#pragma unroll
-    for (int k2 = 0; k2 < R2; ++k2) {
-      const int m = k1 + R1 * k2;
-      xr[m * ld + b] = zr[k2];
-      xi[m * ld + b] = zi[k2];
+  dft_lds_inplace<T, H, BB, -1>(wr, wi, twc, tws);
+  T *dst = reinterpret_cast<T *>(a.spec_out) + b0;
+  for (int u = tid; u < (H / 2 + 1) * BB; u += NT) {
+    const int b = u % BB, k = u / BB;
+    const int k2 = (k == 0) ? 0 : H - k;
+    const T z1r = wr[k * ld + b], z1i = wi[k * ld + b];
+    const T z2r = wr[k2 * ld + b], z2i = wi[k2 * ld + b];
+    // bin k from (Z'[k], Z'[H-k]); bin H-k from the same pair swapped
+    // (bin H from Z'[0] with e^{-i pi} = -1)
+    {
+      const T evr = (T)0.5 * (z1r + z2r), evi = (T)0.5 * (z1i - z2i);
+      const T odr = (T)0.5 * (z1i + z2i), odi = (T)(-0.5) * (z1r - z2r);
+      const T c = twc[k], s = -tws[k];
+      dst[(((size_t)k * n + i) * 2) * B + b] = evr + odr * c - odi * s;
+      dst[(((size_t)k * n + i) * 2 + 1) * B + b] = evi + odr * s + odi * c;
+      if (k == 0) {
+        dst[(((size_t)H * n + i) * 2) * B + b] = evr - odr;
+        dst[(((size_t)H * n + i) * 2 + 1) * B + b] = evi - odi;
+      }
+    }
+    if (k > 0 && k < H / 2) {
+      const int kk = H - k;
+      const T evr = (T)0.5 * (z2r + z1r), evi = (T)0.5 * (z2i - z1i);
+      const T odr = (T)0.5 * (z2i + z1i), odi = (T)(-0.5) * (z2r - z1r);
+      const T c = twc[kk], s = -tws[kk];
+      dst[(((size_t)kk * n + i) * 2) * B + b] = evr + odr * c - odi * s;
+      dst[(((size_t)kk * n + i) * 2 + 1) * B + b] = evi + odr * s + odi * c;
     }
   }
-  __syncthreads();
-  T *dst = reinterpret_cast<T *>(a.spec_out) + b0;
-  for (int u = threadIdx.x; u < (H + 1) * BB; u += blockDim.x) {
-    const int b = u % BB, k = u / BB;
-    const int k1 = (k == H) ? 0 : k;
-    const int k2 = (k == 0) ? 0 : H - k;
-    const T z1r = xr[k1 * ld + b], z1i = xi[k1 * ld + b];
-    const T z2r = xr[k2 * ld + b], z2i = -xi[k2 * ld + b];
-    const T evr = (T)0.5 * (z1r + z2r), evi = (T)0.5 * (z1i + z2i);
-    // Od = (Z1 - conj(Z2)) / (2 i)
-    const T dr = z1r - z2r, di = z1i - z2i;
-    const T odr = (T)0.5 * di, odi = (T)(-0.5) * dr;
-    const T c = twc[k], s = -tws[k];
-    const T outr = evr + odr * c - odi * s;
-    const T outi = evi + odr * s + odi * c;
-    dst[(((size_t)k * n + i) * 2) * B + b] = outr;
-    dst[(((size_t)k * n + i) * 2 + 1) * B + b] = outi;
-  }
-}
-
-template <typename T>
-constexpr int pick_bb(int B) {
-  return sizeof(T) == 8 ? 16 : ((B % 32) == 0 ? 32 : 16);
 }
 
 template <typename T, int P, int BB>
 hipError_t col_dispatch_bb(const Dims &d, int B, bool inverse, const T *in, T *out,
                            hipStream_t st) {
-  const size_t shm = (size_t)(2 * P * (BB + 1) + 2 * P) * sizeof(T);
   dim3 grid((unsigned)(d.h + 1), (unsigned)(B / BB));
   if (inverse)
-    hipLaunchKernelGGL((col_pass_kernel<T, P, BB, true>), grid, dim3(256), shm, st, d.n, B, in, out);
+    hipLaunchKernelGGL((col_pass_kernel<T, P, BB, true>), grid, dim3(512), 0, st, d.n, B, in, out);
   else
-    hipLaunchKernelGGL((col_pass_kernel<T, P, BB, false>), grid, dim3(256), shm, st, d.n, B, in, out);
+    hipLaunchKernelGGL((col_pass_kernel<T, P, BB, false>), grid, dim3(512), 0, st, d.n, B, in, out);
   return hipGetLastError();
 }
 
 template <typename T, int P>
 hipError_t col_dispatch(const Dims &d, int B, bool inverse, const T *in, T *out, hipStream_t st) {
-  if (pick_bb<T>(B) == 32) return col_dispatch_bb<T, P, 32>(d, B, inverse, in, out, st);
+  if (batch_block(d, B, sizeof(T) == 8) == 32) return col_dispatch_bb<T, P, 32>(d, B, inverse, in, out, st);
   return col_dispatch_bb<T, P, 16>(d, B, inverse, in, out, st);
 }
 
 template <typename T, int P, int BB>
 hipError_t row_dispatch_bb(const Dims &d, const RowArgs &a, hipStream_t st) {
-  constexpr int H = P / 2;
-  const size_t shm = (size_t)((2 * (H + 1) + 2 * H) * (BB + 1) + 2 * P + 1) * sizeof(T) +
-                     2 * 256 * sizeof(double) + 16;
   dim3 grid((unsigned)d.n, (unsigned)(a.B / BB));
-  hipLaunchKernelGGL((row_pass_kernel<T, P, BB>), grid, dim3(256), shm, st, d.n, a);
+  hipLaunchKernelGGL((row_pass_kernel<T, P, BB>), grid, dim3(512), 0, st, d.n, a);
   return hipGetLastError();
 }
 
 template <typename T, int P>
 hipError_t row_dispatch(const Dims &d, const RowArgs &a, hipStream_t st) {
-  if (pick_bb<T>(a.B) == 32) return row_dispatch_bb<T, P, 32>(d, a, st);
+  if (batch_block(d, a.B, sizeof(T) == 8) == 32) return row_dispatch_bb<T, P, 32>(d, a, st);
   return row_dispatch_bb<T, P, 16>(d, a, st);
 }
 
@@ -475,10 +522,7 @@ hipError_t launch_row_pass(const Dims &d, const RowArgs &a, hipStream_t st) {
   }
 }
 
-int row_pass_blocks(const Dims &d, int B, bool fp64) {
-  const int bb = fp64 ? 16 : ((B % 32) == 0 ? 32 : 16);
-  return d.n * (B / bb);
-}
+int row_pass_blocks(const Dims &d, int B, bool fp64) { return d.n * (B / batch_block(d, B, fp64)); }
 
 template hipError_t launch_col_pass<float>(const Dims &, int, bool, const float *, float *, hipStream_t);
 template hipError_t launch_col_pass<double>(const Dims &, int, bool, const double *, double *, hipStream_t);

@@ -201,57 +201,59 @@ __device__ inline void matrix_ab(int s, int &a, int &b) {
   a = s - bb * (bb + 1) / 2;
 }
 
-template <typename T>
-__device__ inline void store_val(T *p, size_t i, double v) { p[i] = (T)v; }
-
-// Pack the FP64 spectrum k64[a][b][k][z] (a, b in [0, h]) into the contraction
-// layouts fwd[s][ntp][nzp] and adj[s][nzp][ntp], s = b(b+1)/2 + a for a <= b,
-// scaled by `scale` (the 1/p^2 of the unnormalised inverse FFTs).
-constexpr int PK = 16;
-
+// Pack the FP64 spectrum k64[a][b][k][z] (a, b in [0, h]) into the
+// fragment-ordered forward and adjoint layouts (see Frag), s = b(b+1)/2 + a
+// for a <= b, scaled by `scale` (the 1/p^2 of the unnormalised inverse FFTs);
+// padded bins and layers are zero.  One thread per packed element.
 template <int KIND>  // 0 double, 1 float, 2 bf16 hi+lo, 3 bf16 hi
 __global__ void __launch_bounds__(256)
-pack_kernel(Dims d, const double *__restrict__ k64, char *__restrict__ khat, KhatLayout lay,
-            double scale) {
-  extern __shared__ double tile[];  // [PK][nzp + 1]
-  const int s = blockIdx.x;
-  const int k0 = blockIdx.y * PK;
+pack_kernel(Dims d, Frag fr, const double *__restrict__ k64, char *__restrict__ khat,
+            KhatLayout lay, double scale, int adjoint) {
+  const size_t per = (size_t)d.ntp * d.nzp;
+  const size_t total = (size_t)d.nmat * per;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int s = (int)(idx / per);
+  size_t r = idx % per;
+  const int e = (int)(r % fr.v);
+  r /= fr.v;
+  const int lane = (int)(r % 64);
+  r /= 64;
+  int t, z;
+  if (!adjoint) {
+    const int nq = fr.kz / fr.v;
+    const int nch = d.nzp / (4 * fr.kz);
+    const int q = (int)(r % nq);
+    r /= nq;
+    const int ch = (int)(r % nch);
+    const int tt = (int)(r / nch);
+    t = 16 * tt + frag_row(fr.f64, lane % 16);
+    z = 4 * fr.kz * ch + fr.kz * (lane / 16) + fr.v * q + e;
+  } else {
+    const int nq = fr.tl / fr.v;
+    const int nzt = d.nzp / 16;
+    const int q = (int)(r % nq);
+    r /= nq;
+    const int zt = (int)(r % nzt);
+    const int tci = (int)(r / nzt);
+    z = 16 * zt + frag_row(fr.f64, lane % 16);
+    t = fr.tc * tci + fr.tl * (lane / 16) + fr.v * q + e;
+  }
   int a, b;
   matrix_ab(s, a, b);
-  const int ld = d.nzp + 1;
-  const double *src = k64 + (((size_t)a * (d.h + 1) + b) * d.nt) * d.nz;
-  for (int e = threadIdx.x; e < PK * d.nzp; e += blockDim.x) {
-    const int kk = e / d.nzp, z = e % d.nzp;
-    const int k = k0 + kk;
-    tile[kk * ld + z] = (k < d.nt && z < d.nz) ? src[(size_t)k * d.nz + z] * scale : 0.0;
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < PK * d.nzp; e += blockDim.x) {
-    const int kk = e / d.nzp, z = e % d.nzp;
-    const double v = tile[kk * ld + z];
-    const size_t i = ((size_t)s * d.ntp + k0 + kk) * d.nzp + z;
-    if (KIND == 0) {
-      reinterpret_cast<double *>(khat + lay.fwd)[i] = v;
-    } else if (KIND == 1) {
-      reinterpret_cast<float *>(khat + lay.fwd)[i] = (float)v;
-    } else {
-      const __bf16 hi = (__bf16)(float)v;
-      reinterpret_cast<__bf16 *>(khat + lay.fwd)[i] = hi;
-      if (KIND == 2) reinterpret_cast<__bf16 *>(khat + lay.fwd_lo)[i] = (__bf16)(float)(v - (double)(float)hi);
-    }
-  }
-  for (int e = threadIdx.x; e < PK * d.nzp; e += blockDim.x) {
-    const int z = e / PK, kk = e % PK;
-    const double v = tile[kk * ld + z];
-    const size_t i = ((size_t)s * d.nzp + z) * d.ntp + k0 + kk;
-    if (KIND == 0) {
-      reinterpret_cast<double *>(khat + lay.adj)[i] = v;
-    } else if (KIND == 1) {
-      reinterpret_cast<float *>(khat + lay.adj)[i] = (float)v;
-    } else {
-      const __bf16 hi = (__bf16)(float)v;
-      reinterpret_cast<__bf16 *>(khat + lay.adj)[i] = hi;
-      if (KIND == 2) reinterpret_cast<__bf16 *>(khat + lay.adj_lo)[i] = (__bf16)(float)(v - (double)(float)hi);
+  double v = 0.0;
+  if (t < d.nt && z < d.nz) v = k64[(((size_t)a * (d.h + 1) + b) * d.nt + t) * d.nz + z] * scale;
+  const size_t off = adjoint ? lay.adj : lay.fwd;
+  if (KIND == 0) {
+    reinterpret_cast<double *>(khat + off)[idx] = v;
+  } else if (KIND == 1) {
+    reinterpret_cast<float *>(khat + off)[idx] = (float)v;
+  } else {
+    const __bf16 hi = (__bf16)(float)v;
+    reinterpret_cast<__bf16 *>(khat + off)[idx] = hi;
+    if (KIND == 2) {
+      const size_t lo = adjoint ? lay.adj_lo : lay.fwd_lo;
+      reinterpret_cast<__bf16 *>(khat + lo)[idx] = (__bf16)(float)(v - (double)(float)hi);
     }
   }
 }
@@ -286,24 +288,29 @@ hipError_t launch_gemm_f64(int M, long long N, int K, const double *A, int lda, 
 
 hipError_t launch_pack(const Dims &d, ctof_precision prec, const double *k64, void *khat,
                        const KhatLayout &lay, double scale, hipStream_t st) {
-  dim3 grid((unsigned)d.nmat, (unsigned)(d.ntp / PK));
-  const size_t shm = (size_t)PK * (d.nzp + 1) * sizeof(double);
+  const size_t total = (size_t)d.nmat * d.ntp * d.nzp;
+  const dim3 grid((unsigned)((total + 255) / 256));
+  const Frag fr = frag_of(d, prec);
   char *kh = reinterpret_cast<char *>(khat);
-  switch (prec) {
-    case CTOF_FP64:
-      hipLaunchKernelGGL(pack_kernel<0>, grid, dim3(256), shm, st, d, k64, kh, lay, scale);
-      break;
-    case CTOF_FP32:
-      hipLaunchKernelGGL(pack_kernel<1>, grid, dim3(256), shm, st, d, k64, kh, lay, scale);
-      break;
-    case CTOF_BF16X3:
-      hipLaunchKernelGGL(pack_kernel<2>, grid, dim3(256), shm, st, d, k64, kh, lay, scale);
-      break;
-    default:
-      hipLaunchKernelGGL(pack_kernel<3>, grid, dim3(256), shm, st, d, k64, kh, lay, scale);
-      break;
+  for (int adj = 0; adj < 2; ++adj) {
+    switch (prec) {
+      case CTOF_FP64:
+        hipLaunchKernelGGL(pack_kernel<0>, grid, dim3(256), 0, st, d, fr, k64, kh, lay, scale, adj);
+        break;
+      case CTOF_FP32:
+        hipLaunchKernelGGL(pack_kernel<1>, grid, dim3(256), 0, st, d, fr, k64, kh, lay, scale, adj);
+        break;
+      case CTOF_BF16X3:
+        hipLaunchKernelGGL(pack_kernel<2>, grid, dim3(256), 0, st, d, fr, k64, kh, lay, scale, adj);
+        break;
+      default:
+        hipLaunchKernelGGL(pack_kernel<3>, grid, dim3(256), 0, st, d, fr, k64, kh, lay, scale, adj);
+        break;
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 }  // namespace ctof

@@ -14,12 +14,26 @@ def to_np(t):
     return t.detach().cpu().numpy().astype(np.float64)
 
 
-def khat_matrices(k, dims_p, nmat, ntp, nzp, prec_bytes):
-    """View the forward-layout spectrum [s][ntp][nzp] of a handle as numpy."""
-    import torch
-    dt = {8: torch.float64, 4: torch.float32}[prec_bytes]
-    n = nmat * ntp * nzp
-    return k.khat[: n * prec_bytes].view(dt).reshape(nmat, ntp, nzp).cpu().numpy().astype(np.float64)
+def unpack_forward_fragments(flat, nmat, ntp, nzp, v, f64):
+    """Decode the documented fragment order of the forward spectrum layout.
+
+    Element (s, tt, ch, q, lane, e) holds K_s[t][z] with
+    t = 16 tt + row(lane % 16), z = 4 kz ch + kz (lane // 16) + v q + e,
+    kz = min(nzp, 64) / 4, row(i) = 4 (i % 4) + i // 4 for FP64 else i.
+    Returns [nmat][ntp][nzp].
+    """
+    kz = min(nzp, 64) // 4
+    nq, nch, ntt = kz // v, nzp // (4 * kz), ntp // 16
+    a = np.asarray(flat).reshape(nmat, ntt, nch, nq, 64, v)
+    tt, ch, q, lane, e = np.meshgrid(np.arange(ntt), np.arange(nch), np.arange(nq),
+                                     np.arange(64), np.arange(v), indexing="ij")
+    i = lane % 16
+    row = 4 * (i % 4) + i // 4 if f64 else i
+    t = 16 * tt + row
+    z = 4 * kz * ch + kz * (lane // 16) + v * q + e
+    out = np.zeros((nmat, ntp, nzp), dtype=np.float64)
+    out[:, t.ravel(), z.ravel()] = a.reshape(nmat, -1)
+    return out
 
 
 def matrix_index(a, b):

@@ -16,7 +16,7 @@ from oracle import operator as oop
 from oracle import solver as osolver
 from synth import noise, phantoms, workloads
 from synth.workloads import Geometry, even_layers
-from tests.gpu_common import matrix_index, rel_l2, to_np
+from tests.gpu_common import matrix_index, rel_l2, to_np, unpack_forward_fragments
 
 pytestmark = pytest.mark.gpu
 
@@ -96,7 +96,8 @@ def test_khat_fp64_matches_oracle_spectrum():
     P = i.p
     nzp = ((g.nz + 15) // 16) * 16
     ntp = ((g.nt + 31) // 32) * 32
-    KH = k.khat[: i.nmat * ntp * nzp * 8].view(torch.float64).reshape(i.nmat, ntp, nzp).cpu().numpy()
+    flat = k.khat[: i.nmat * ntp * nzp * 8].view(torch.float64).cpu().numpy()
+    KH = unpack_forward_fragments(flat, i.nmat, ntp, nzp, 2, True)
     ref = oracle_fft(g).Khat.real / (P * P)       # [nz][nt][P][P/2+1]
     H = P // 2
     worst = 0.0
