@@ -42,24 +42,20 @@ __device__ inline void matrix_ab(int s, int &a, int &b) {
   a = s - bb * (bb + 1) / 2;
 }
 
-struct Slots {
-  int f[4];
-  bool valid[4];
-};
-
-__device__ inline Slots matrix_slots(int s, int h, int p) {
+// Frequency index and validity of slot q (0..3) of matrix s = (a, b):
+// (kx, ky) = (a, b), (P-a, b), (b, a), (P-b, a); duplicates are invalid.
+// Selected with conditionals so the lane's slot never indexes a local array
+// (which would live in scratch memory).
+__device__ inline int matrix_slot(int s, int h, int p, int q, bool &valid) {
   int a, b;
   matrix_ab(s, a, b);
-  Slots sl;
-  sl.f[0] = b * p + a;
-  sl.valid[0] = true;
-  sl.f[1] = b * p + (p - a);
-  sl.valid[1] = (a > 0 && a < h);
-  sl.f[2] = a * p + b;
-  sl.valid[2] = (a != b);
-  sl.f[3] = a * p + (p - b);
-  sl.valid[3] = (a != b && b > 0 && b < h);
-  return sl;
+  const int lo = (q < 2) ? a : b;   // kx before reflection
+  const int ky = (q < 2) ? b : a;
+  const bool refl = (q & 1) != 0;
+  const int kx = refl ? p - lo : lo;
+  valid = (q == 0) || (q == 1 && a > 0 && a < h) || (q == 2 && a != b) ||
+          (q == 3 && a != b && b > 0 && b < h);
+  return ky * p + kx;
 }
 
 template <typename T>
@@ -151,12 +147,13 @@ contract_fwd_kernel(const T *__restrict__ khat, const T *__restrict__ vin, T *__
   const int w = threadIdx.x >> 6;
   const int l = threadIdx.x & 63;
   const int c = l & 15, g = l >> 4;
-  const Slots sl = matrix_slots(s, h, p);
-  const int q = c >> 1;
-  const bool col = (c < 8) && sl.valid[q & 3];
+  const int q = (c >> 1) & 3;
+  bool slot_ok;
+  const int f = matrix_slot(s, h, p, q, slot_ok);
+  const bool col = (c < 8) && slot_ok;
   const int nchunk = nzp / (4 * KZ);
-  const T *vcol = vin + ((size_t)sl.f[q & 3] * 2 + (c & 1)) * nzp;
-  T *ocol = vout + ((size_t)sl.f[q & 3] * 2 + (c & 1)) * ntp;
+  const T *vcol = vin + ((size_t)f * 2 + (c & 1)) * nzp;
+  T *ocol = vout + ((size_t)f * 2 + (c & 1)) * ntp;
   const int ntt = ntp / 16;
   for (int ch = 0; ch < nchunk; ++ch) {
     T bv[KZ];
@@ -195,10 +192,11 @@ contract_adj_kernel(const T *__restrict__ khat, const T *__restrict__ vin, T *__
   const int w = threadIdx.x >> 6;
   const int l = threadIdx.x & 63;
   const int c = l & 15, g = l >> 4;
-  const Slots sl = matrix_slots(s, h, p);
-  const int q = c >> 1;
-  const bool col = (c < 8) && sl.valid[q & 3];
-  const T *vcol = vin + ((size_t)sl.f[q & 3] * 2 + (c & 1)) * ntp;
+  const int q = (c >> 1) & 3;
+  bool slot_ok;
+  const int f = matrix_slot(s, h, p, q, slot_ok);
+  const bool col = (c < 8) && slot_ok;
+  const T *vcol = vin + ((size_t)f * 2 + (c & 1)) * ntp;
   typename M::acc_t acc[ZT];
 #pragma unroll
   for (int zt = 0; zt < ZT; ++zt) acc[zt] = {0, 0, 0, 0};
@@ -226,7 +224,7 @@ contract_adj_kernel(const T *__restrict__ khat, const T *__restrict__ vin, T *__
     for (int r = 0; r < 4; ++r) red[((w * ZT + zt) * 64 + l) * 4 + r] = acc[zt][r];
   __syncthreads();
   if (w == 0 && col) {
-    T *ocol = vout + ((size_t)sl.f[q & 3] * 2 + (c & 1)) * nzp;
+    T *ocol = vout + ((size_t)f * 2 + (c & 1)) * nzp;
 #pragma unroll
     for (int zt = 0; zt < ZT; ++zt) {
       typename M::acc_t o;
@@ -266,12 +264,13 @@ contract_fwd_bf16_kernel(const __bf16 *__restrict__ khi, const __bf16 *__restric
   const int w = threadIdx.x >> 6;
   const int l = threadIdx.x & 63;
   const int c = l & 15, g = l >> 4;
-  const Slots sl = matrix_slots(s, h, p);
-  const int q = c >> 1;
-  const bool col = (c < 8) && sl.valid[q & 3];
+  const int q = (c >> 1) & 3;
+  bool slot_ok;
+  const int f = matrix_slot(s, h, p, q, slot_ok);
+  const bool col = (c < 8) && slot_ok;
   const int nchunk = nzp / (4 * KZ);
-  const float *vcol = vin + ((size_t)sl.f[q & 3] * 2 + (c & 1)) * nzp;
-  float *ocol = vout + ((size_t)sl.f[q & 3] * 2 + (c & 1)) * ntp;
+  const float *vcol = vin + ((size_t)f * 2 + (c & 1)) * nzp;
+  float *ocol = vout + ((size_t)f * 2 + (c & 1)) * ntp;
   const int ntt = ntp / 16;
   for (int ch = 0; ch < nchunk; ++ch) {
     v8bf bh[KZ / 8], bl[KZ / 8];
@@ -321,10 +320,11 @@ contract_adj_bf16_kernel(const __bf16 *__restrict__ khi, const __bf16 *__restric
   const int w = threadIdx.x >> 6;
   const int l = threadIdx.x & 63;
   const int c = l & 15, g = l >> 4;
-  const Slots sl = matrix_slots(s, h, p);
-  const int q = c >> 1;
-  const bool col = (c < 8) && sl.valid[q & 3];
-  const float *vcol = vin + ((size_t)sl.f[q & 3] * 2 + (c & 1)) * ntp;
+  const int q = (c >> 1) & 3;
+  bool slot_ok;
+  const int f = matrix_slot(s, h, p, q, slot_ok);
+  const bool col = (c < 8) && slot_ok;
+  const float *vcol = vin + ((size_t)f * 2 + (c & 1)) * ntp;
   v4f acc[ZT];
 #pragma unroll
   for (int zt = 0; zt < ZT; ++zt) acc[zt] = {0, 0, 0, 0};
@@ -357,7 +357,7 @@ contract_adj_bf16_kernel(const __bf16 *__restrict__ khi, const __bf16 *__restric
     for (int r = 0; r < 4; ++r) red[((w * ZT + zt) * 64 + l) * 4 + r] = acc[zt][r];
   __syncthreads();
   if (w == 0 && col) {
-    float *ocol = vout + ((size_t)sl.f[q & 3] * 2 + (c & 1)) * nzp;
+    float *ocol = vout + ((size_t)f * 2 + (c & 1)) * nzp;
 #pragma unroll
     for (int zt = 0; zt < ZT; ++zt) {
       float o[4];
