@@ -34,9 +34,9 @@
  *     and CTOF_BF16.  Arrays are C-contiguous:
  *       volume mu, g          [nz][n][n]
  *       histogram m, d, r     [nt][n][n]
- *   - A ctof_kernel handle is immutable after tabulation and may be used
- *     concurrently from several streams as long as each call has its own
- *     workspace.
+ *   - A ctof_kernel handle is immutable after tabulation (apart from its FFT
+ *     tuning, see ctof_kernel_set_tuning) and may be used concurrently from
+ *     several streams as long as each call has its own workspace.
  */
 #ifndef CTOF_H
 #define CTOF_H
@@ -222,6 +222,48 @@ typedef struct {
 ctof_status ctof_reconstruct(ctof_kernel k, const void *d_dev, void *mu_inout_dev,
                              const ctof_solver_opts *opts, ctof_solver_report *report,
                              void *ws_dev, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Batched reconstruction of nscan independent scans (the same FISTA as
+ * ctof_reconstruct, run for every scan).  Scans whose handles are the same
+ * pointer form a shape class and share that handle's kernel spectrum: the
+ * class's volumes are extra columns of one matrix-core contraction per
+ * frequency (the spectrum is read once per class and pass, not once per
+ * scan) and extra planes of the same FFT launches.  Handles must share one
+ * precision; shapes may differ between classes.  L and lambda come from one
+ * power iteration per class (or from opts).  Iterations run in chunks of
+ * min(check_every, 50) (min(max_iter, 50) when rel_tol == 0), each chunk of
+ * every live class captured once as a HIP graph on an internal stream and
+ * replayed on `stream`; with rel_tol > 0 a scan whose gradient-mapping ratio
+ * is <= rel_tol at a chunk end is frozen (its mu keeps that iterate) and a
+ * class whose scans are all frozen leaves the graph.
+ *   d_dev[i]        [nt][n][n] of scan i's handle
+ *   mu_inout_dev[i] [nz][n][n] (start if warm_start, result on return)
+ *   reports[i]      per scan; iters = iterations until frozen (or run)
+ * opts.history_dev and opts.timing must be NULL / 0.  Synchronises `stream`.
+ */
+ctof_status ctof_workspace_bytes_batched(int32_t nscan, const ctof_kernel *k, int32_t max_iter,
+                                        size_t *ws_bytes);
+ctof_status ctof_reconstruct_batched(int32_t nscan, const ctof_kernel *k, const void *const *d_dev,
+                                     void *const *mu_inout_dev, const ctof_solver_opts *opts,
+                                     ctof_solver_report *reports, void *ws_dev, size_t ws_bytes,
+                                     hipStream_t stream);
+
+/*
+ * Tuning of a handle's FFT passes: planes per block on the bin side (bb_t)
+ * and on the layer side (bb_z), each 16 or 32 (0 = built-in rule: 32 when
+ * the pass still has >= 1024 blocks).  The value changes launch shapes and
+ * workspace sizes, not results.  ctof_tune times the operator passes of a
+ * class of nvol volumes for every legal pair (ms[4] receives the average
+ * milliseconds per iteration for (16,16), (32,16), (16,32), (32,32); -1 when
+ * not legal), keeps the fastest in the handle and returns it.  Synchronises
+ * `stream`.  Handles under tuning must not be in use on other streams.
+ */
+ctof_status ctof_kernel_set_tuning(ctof_kernel k, int32_t bb_t, int32_t bb_z);
+ctof_status ctof_kernel_get_tuning(ctof_kernel k, int32_t *bb_t, int32_t *bb_z);
+ctof_status ctof_tune_workspace_bytes(ctof_kernel k, int32_t nvol, size_t *ws_bytes);
+ctof_status ctof_tune(ctof_kernel k, int32_t nvol, int32_t iters, void *ws_dev, size_t ws_bytes,
+                      hipStream_t stream, float *ms, int32_t *bb_t, int32_t *bb_z);
 
 const char *ctof_last_error(void);
 

@@ -168,86 +168,120 @@ TabWs tab_ws(const ctof::Dims &d) {
   return w;
 }
 
-// Workspace carve-up for forward/adjoint/reconstruct.
-struct OpWs {
+// Workspace of one shape class holding nvol volumes: spectra and column-pass
+// intermediates carry every volume's planes, solver state is per volume.
+struct ClassWs {
   size_t yhat, mhat, xt, xz, op_total;
-  size_t y, v, w, hist, scal, part, solve_total;
+  size_t y, v, w, hist, scal, g0sq, part, beta, ctr, active, solve_total;
   int nblk_t, nblk_z;
   size_t part_stride;  // doubles per iteration
 };
 
-OpWs op_ws(const ctof::Dims &d, ctof_precision prec, int max_iter) {
-  OpWs o;
-  const size_t es = elem_size(prec);
-  const bool f64 = prec == CTOF_FP64;
+ClassWs class_ws(const ctof_kernel_s *k, int nvol, int max_iter) {
+  const ctof::Dims &d = k->dims;
+  ClassWs o;
+  const size_t es = elem_size(k->prec);
+  const bool f64 = k->prec == CTOF_FP64;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t at = off;
     off += ctof::round_up(bytes, 256);
     return at;
   };
-  o.yhat = take((size_t)(d.h + 1) * d.p * 2 * d.nzp * es);
-  o.mhat = take((size_t)(d.h + 1) * d.p * 2 * d.ntp * es);
-  o.xt = take((size_t)(d.h + 1) * d.n * 2 * d.ntp * es);
-  o.xz = take((size_t)(d.h + 1) * d.n * 2 * d.nzp * es);
+  o.yhat = take((size_t)(d.h + 1) * d.p * 2 * nvol * d.nzp * es);
+  o.mhat = take((size_t)(d.h + 1) * d.p * 2 * nvol * d.ntp * es);
+  o.xt = take((size_t)(d.h + 1) * d.n * 2 * nvol * d.ntp * es);
+  o.xz = take((size_t)(d.h + 1) * d.n * 2 * nvol * d.nzp * es);
   o.op_total = off;
   const size_t vol = (size_t)d.nz * d.n * d.n * es;
-  o.y = take(vol);
+  o.y = take(vol * nvol);
   o.v = take(vol);
   o.w = take(vol);
-  o.nblk_t = ctof::row_pass_blocks(d, d.ntp, f64);
-  o.nblk_z = ctof::row_pass_blocks(d, d.nzp, f64);
+  o.nblk_t = ctof::row_pass_blocks(d, nvol * d.ntp, d.ntp, f64, k->bb_t);
+  o.nblk_z = ctof::row_pass_blocks(d, nvol * d.nzp, d.nzp, f64, k->bb_z);
   o.part_stride = 2 * (size_t)(o.nblk_t + o.nblk_z);
   const int iters = std::max(max_iter, 1);
-  o.hist = take((size_t)iters * 2 * 8);
-  o.scal = take(64 * 8);
+  o.hist = take((size_t)iters * nvol * 2 * 8);
+  o.scal = take((size_t)(64 + nvol) * 8);  // [0..7] scalars, [8..8+nvol) final fits
+  o.g0sq = take((size_t)nvol * 8);
   o.part = take((size_t)(iters + 2) * o.part_stride * 8);
+  o.beta = take((size_t)iters * 8);
+  o.ctr = take(64);
+  o.active = take((size_t)nvol * 4);
   o.solve_total = off;
   return o;
 }
 
+// Launch helpers for one shape class (nvol volumes, one kernel spectrum).
 template <typename T>
-struct Ops {
+struct Engine {
   const ctof_kernel_s *k;
+  int nvol;
   char *ws;
-  OpWs lay;
+  ClassWs L;
   hipStream_t st;
 
-  T *yhat() const { return reinterpret_cast<T *>(ws + lay.yhat); }
-  T *mhat() const { return reinterpret_cast<T *>(ws + lay.mhat); }
-  T *xt() const { return reinterpret_cast<T *>(ws + lay.xt); }
-  T *xz() const { return reinterpret_cast<T *>(ws + lay.xz); }
+  const ctof::Dims &dm() const { return k->dims; }
+  T *yhat() const { return reinterpret_cast<T *>(ws + L.yhat); }
+  T *mhat() const { return reinterpret_cast<T *>(ws + L.mhat); }
+  T *xt() const { return reinterpret_cast<T *>(ws + L.xt); }
+  T *xz() const { return reinterpret_cast<T *>(ws + L.xz); }
+  T *y(int v) const { return reinterpret_cast<T *>(ws + L.y) + (size_t)v * dm().nz * dm().n * dm().n; }
+  T *pv() const { return reinterpret_cast<T *>(ws + L.v); }
+  T *pw() const { return reinterpret_cast<T *>(ws + L.w); }
+  double *hist() const { return reinterpret_cast<double *>(ws + L.hist); }
+  double *scal() const { return reinterpret_cast<double *>(ws + L.scal); }
+  double *g0sq() const { return reinterpret_cast<double *>(ws + L.g0sq); }
+  double *part() const { return reinterpret_cast<double *>(ws + L.part); }
+  double *beta() const { return reinterpret_cast<double *>(ws + L.beta); }
+  int *ctr() const { return reinterpret_cast<int *>(ws + L.ctr); }
+  int *active() const { return reinterpret_cast<int *>(ws + L.active); }
+  int Bt() const { return nvol * dm().ntp; }
+  int Bz() const { return nvol * dm().nzp; }
 
   ctof::RowArgs row(int op, bool tside) const {
     ctof::RowArgs a;
     std::memset(&a, 0, sizeof(a));
     a.op = op;
-    a.B = tside ? k->dims.ntp : k->dims.nzp;
-    a.nplanes = tside ? k->dims.nt : k->dims.nz;
+    a.B = tside ? Bt() : Bz();
+    a.ppv = tside ? dm().ntp : dm().nzp;
+    a.nplanes = tside ? dm().nt : dm().nz;
+    a.nvol = nvol;
+    a.bb = tside ? k->bb_t : k->bb_z;
     a.spec_in = tside ? (void *)xt() : (void *)xz();
-    a.spec_out = a.spec_in == nullptr ? nullptr : const_cast<void *>(a.spec_in);
+    a.spec_out = const_cast<void *>(a.spec_in);
     return a;
   }
-
-  // spatial volume -> yhat
-  hipError_t mu_to_spec(ctof::RowArgs a) const {
-    hipError_t e = ctof::launch_row_pass<T>(k->dims, a, st);
-    if (e != hipSuccess) return e;
-    return ctof::launch_col_pass<T>(k->dims, k->dims.nzp, false, xz(), yhat(), st);
+  hipError_t run_row(const ctof::RowArgs &a) const { return ctof::launch_row_pass<T>(dm(), a, st); }
+  // t side: inverse mhat -> xt, forward xt -> mhat;  z side: inverse yhat -> xz, forward xz -> yhat
+  hipError_t col_t(bool inverse) const {
+    return inverse ? ctof::launch_col_pass<T>(dm(), Bt(), true, mhat(), xt(), st, dm().ntp, k->bb_t)
+                   : ctof::launch_col_pass<T>(dm(), Bt(), false, xt(), mhat(), st, dm().ntp, k->bb_t);
   }
-  // yhat -> (contraction) -> mhat -> xt (inverse column pass)
+  hipError_t col_z(bool inverse) const {
+    return inverse ? ctof::launch_col_pass<T>(dm(), Bz(), true, yhat(), xz(), st, dm().nzp, k->bb_z)
+                   : ctof::launch_col_pass<T>(dm(), Bz(), false, xz(), yhat(), st, dm().nzp, k->bb_z);
+  }
+  hipError_t contract(bool adjoint) const {
+    return adjoint ? ctof::launch_contract(k, true, mhat(), yhat(), st, nvol)
+                   : ctof::launch_contract(k, false, yhat(), mhat(), st, nvol);
+  }
+  // spatial volume(s) -> yhat
+  hipError_t mu_to_spec(const ctof::RowArgs &a) const {
+    hipError_t e = run_row(a);
+    return e != hipSuccess ? e : col_z(false);
+  }
+  // yhat -> mhat -> xt
   hipError_t fwd_to_xt() const {
-    hipError_t e = ctof::launch_contract(k, false, yhat(), mhat(), st);
-    if (e != hipSuccess) return e;
-    return ctof::launch_col_pass<T>(k->dims, k->dims.ntp, true, mhat(), xt(), st);
+    hipError_t e = contract(false);
+    return e != hipSuccess ? e : col_t(true);
   }
-  // xt (row-pass output spectrum) -> mhat -> (adjoint contraction) -> yhat -> xz
+  // xt (row-pass output) -> mhat -> yhat -> xz
   hipError_t adj_to_xz() const {
-    hipError_t e = ctof::launch_col_pass<T>(k->dims, k->dims.ntp, false, xt(), mhat(), st);
+    hipError_t e = col_t(false);
     if (e != hipSuccess) return e;
-    e = ctof::launch_contract(k, true, mhat(), yhat(), st);
-    if (e != hipSuccess) return e;
-    return ctof::launch_col_pass<T>(k->dims, k->dims.nzp, true, yhat(), xz(), st);
+    e = contract(true);
+    return e != hipSuccess ? e : col_z(true);
   }
 };
 
@@ -258,28 +292,33 @@ ctof_status check_kernel(ctof_kernel k) {
 }
 
 template <typename T>
+Engine<T> engine(const ctof_kernel_s *k, int nvol, void *ws, int max_iter, hipStream_t st) {
+  return Engine<T>{k, nvol, reinterpret_cast<char *>(ws), class_ws(k, nvol, max_iter), st};
+}
+
+template <typename T>
 ctof_status run_forward(ctof_kernel k, const void *mu, void *m, void *ws, hipStream_t st) {
-  Ops<T> ops{k, reinterpret_cast<char *>(ws), op_ws(k->dims, k->prec, 1), st};
-  ctof::RowArgs a = ops.row(ctof::ROW_SPATIAL_TO_SPEC, false);
-  a.sp_in = mu;
-  HIP_TRY(ops.mu_to_spec(a));
-  HIP_TRY(ops.fwd_to_xt());
-  ctof::RowArgs b = ops.row(ctof::ROW_SPEC_TO_SPATIAL, true);
-  b.sp_out = m;
-  HIP_TRY(ctof::launch_row_pass<T>(k->dims, b, st));
+  const Engine<T> E = engine<T>(k, 1, ws, 1, st);
+  ctof::RowArgs a = E.row(ctof::ROW_SPATIAL_TO_SPEC, false);
+  a.sp_in[0] = mu;
+  HIP_TRY(E.mu_to_spec(a));
+  HIP_TRY(E.fwd_to_xt());
+  ctof::RowArgs b = E.row(ctof::ROW_SPEC_TO_SPATIAL, true);
+  b.sp_out[0] = m;
+  HIP_TRY(E.run_row(b));
   return CTOF_OK;
 }
 
 template <typename T>
 ctof_status run_adjoint(ctof_kernel k, const void *r, void *g, void *ws, hipStream_t st) {
-  Ops<T> ops{k, reinterpret_cast<char *>(ws), op_ws(k->dims, k->prec, 1), st};
-  ctof::RowArgs a = ops.row(ctof::ROW_SPATIAL_TO_SPEC, true);
-  a.sp_in = r;
-  HIP_TRY(ctof::launch_row_pass<T>(k->dims, a, st));
-  HIP_TRY(ops.adj_to_xz());
-  ctof::RowArgs b = ops.row(ctof::ROW_SPEC_TO_SPATIAL, false);
-  b.sp_out = g;
-  HIP_TRY(ctof::launch_row_pass<T>(k->dims, b, st));
+  const Engine<T> E = engine<T>(k, 1, ws, 1, st);
+  ctof::RowArgs a = E.row(ctof::ROW_SPATIAL_TO_SPEC, true);
+  a.sp_in[0] = r;
+  HIP_TRY(E.run_row(a));
+  HIP_TRY(E.adj_to_xz());
+  ctof::RowArgs b = E.row(ctof::ROW_SPEC_TO_SPATIAL, false);
+  b.sp_out[0] = g;
+  HIP_TRY(E.run_row(b));
   return CTOF_OK;
 }
 
@@ -294,63 +333,139 @@ std::vector<double> fista_betas(int iters) {
   return b;
 }
 
+// L_A of one class by power iteration on a single vector (FP64 Rayleigh
+// quotients); enqueued on the engine's stream, result in scal()[1].
+template <typename T>
+ctof_status enqueue_power_iteration(const Engine<T> &E1, int iters) {
+  const ctof::Dims &dm = E1.dm();
+  const size_t vol = (size_t)dm.nz * dm.n * dm.n;
+  if (sizeof(T) == 8)
+    HIP_TRY(ctof::launch_fill_value_f64(reinterpret_cast<double *>(E1.pv()), vol, 1.0 / std::sqrt((double)vol), E1.st));
+  else
+    HIP_TRY(ctof::launch_fill_value(reinterpret_cast<float *>(E1.pv()), vol, (float)(1.0 / std::sqrt((double)vol)), E1.st));
+  for (int j = 0; j < iters; ++j) {
+    ctof::RowArgs a = E1.row(j == 0 ? ctof::ROW_SPATIAL_TO_SPEC : ctof::ROW_SCALE_TO_SPEC, false);
+    a.sp_in[0] = j == 0 ? (const void *)E1.pv() : (const void *)E1.pw();
+    a.sp_out[0] = E1.pv();
+    a.scalar = E1.scal() + 0;
+    HIP_TRY(E1.mu_to_spec(a));
+    HIP_TRY(E1.fwd_to_xt());
+    HIP_TRY(E1.run_row(E1.row(ctof::ROW_PASS, true)));
+    HIP_TRY(E1.adj_to_xz());
+    ctof::RowArgs c = E1.row(ctof::ROW_POWER_W, false);
+    c.sp_in[0] = E1.pv();
+    c.sp_out[0] = E1.pw();
+    c.partials = E1.part();
+    HIP_TRY(E1.run_row(c));
+    HIP_TRY(ctof::launch_reduce_rows(E1.part(), E1.L.nblk_z, 2, 2, E1.scal() + 0, E1.st));
+  }
+  return CTOF_OK;
+}
+
+// ||max(0, A^T d_v)||^2 per volume into g0sq()[v]
+template <typename T>
+ctof_status enqueue_gmap0(const Engine<T> &E, const void *const *d) {
+  ctof::RowArgs a = E.row(ctof::ROW_SPATIAL_TO_SPEC, true);
+  for (int v = 0; v < E.nvol; ++v) a.sp_in[v] = d[v];
+  HIP_TRY(E.run_row(a));
+  HIP_TRY(E.adj_to_xz());
+  ctof::RowArgs b = E.row(ctof::ROW_GMAP0, false);
+  b.partials = E.part();
+  HIP_TRY(E.run_row(b));
+  HIP_TRY(ctof::launch_reduce_volumes(E.part(), E.L.nblk_z, E.nvol, E.g0sq(), E.st));
+  return CTOF_OK;
+}
+
+// one FISTA iteration of every volume of the class; partials and beta come
+// from the device iteration counter when `by_counter`, else from `it`
+template <typename T>
+ctof_status enqueue_iteration(const Engine<T> &E, const void *const *d, void *const *mu, double tau,
+                              double lam, bool by_counter, int it, double beta) {
+  HIP_TRY(E.contract(false));
+  HIP_TRY(E.col_t(true));
+  ctof::RowArgs a = E.row(ctof::ROW_RESIDUAL, true);
+  for (int v = 0; v < E.nvol; ++v) a.sp_in[v] = d[v];
+  a.partials = E.part() + (by_counter ? 0 : (size_t)it * E.L.part_stride);
+  if (by_counter) {
+    a.iter_ctr = E.ctr();
+    a.part_stride = E.L.part_stride;
+  }
+  HIP_TRY(E.run_row(a));
+  HIP_TRY(E.col_t(false));
+  HIP_TRY(E.contract(true));
+  HIP_TRY(E.col_z(true));
+  ctof::RowArgs b = E.row(ctof::ROW_FISTA, false);
+  for (int v = 0; v < E.nvol; ++v) {
+    b.sp_in[v] = E.y(v);
+    b.sp_out[v] = E.y(v);
+    b.sp_aux[v] = mu[v];
+  }
+  b.partials = E.part() + 2 * (size_t)E.L.nblk_t + (by_counter ? 0 : (size_t)it * E.L.part_stride);
+  b.tau = tau;
+  b.lambda = lam;
+  b.beta = beta;
+  if (by_counter) {
+    b.iter_ctr = E.ctr();
+    b.part_stride = E.L.part_stride;
+    b.beta_tab = E.beta();
+    b.active = E.active();
+  }
+  HIP_TRY(E.run_row(b));
+  HIP_TRY(E.col_z(false));
+  if (by_counter) HIP_TRY(ctof::launch_increment(E.ctr(), E.st));
+  return CTOF_OK;
+}
+
+// y_v = mu_v (zeroed first for a cold start) and the spectrum of y
+template <typename T>
+ctof_status enqueue_start(const Engine<T> &E, void *const *mu, bool warm) {
+  const ctof::Dims &dm = E.dm();
+  const size_t vol = (size_t)dm.nz * dm.n * dm.n;
+  for (int v = 0; v < E.nvol; ++v) {
+    if (!warm) HIP_TRY(ctof::launch_fill_zero(mu[v], vol * sizeof(T), E.st));
+    HIP_TRY(hipMemcpyAsync(E.y(v), mu[v], vol * sizeof(T), hipMemcpyDeviceToDevice, E.st));
+  }
+  ctof::RowArgs a = E.row(ctof::ROW_SPATIAL_TO_SPEC, false);
+  for (int v = 0; v < E.nvol; ++v) a.sp_in[v] = E.y(v);
+  HIP_TRY(E.mu_to_spec(a));
+  return CTOF_OK;
+}
+
+// 1/2 ||A mu_v - d_v||^2 per volume into out[v] (device)
+template <typename T>
+ctof_status enqueue_final_fit(const Engine<T> &E, const void *const *d, void *const *mu, double *pf,
+                              double *out) {
+  ctof::RowArgs a = E.row(ctof::ROW_SPATIAL_TO_SPEC, false);
+  for (int v = 0; v < E.nvol; ++v) a.sp_in[v] = mu[v];
+  HIP_TRY(E.mu_to_spec(a));
+  HIP_TRY(E.fwd_to_xt());
+  ctof::RowArgs b = E.row(ctof::ROW_RESIDUAL, true);
+  for (int v = 0; v < E.nvol; ++v) b.sp_in[v] = d[v];
+  b.partials = pf;
+  HIP_TRY(E.run_row(b));
+  HIP_TRY(ctof::launch_reduce_volumes(pf, E.L.nblk_t, E.nvol, out, E.st));
+  return CTOF_OK;
+}
+
 template <typename T>
 ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_solver_opts *opt,
                             ctof_solver_report *rep, void *ws, hipStream_t st) {
   const ctof::Dims &dm = k->dims;
-  const OpWs L = op_ws(dm, k->prec, opt->max_iter);
-  Ops<T> ops{k, reinterpret_cast<char *>(ws), L, st};
-  char *base = reinterpret_cast<char *>(ws);
-  T *y = reinterpret_cast<T *>(base + L.y);
-  T *v = reinterpret_cast<T *>(base + L.v);
-  T *w = reinterpret_cast<T *>(base + L.w);
-  double *hist = reinterpret_cast<double *>(base + L.hist);
-  double *scal = reinterpret_cast<double *>(base + L.scal);
-  double *part = reinterpret_cast<double *>(base + L.part);
-  const size_t vol = (size_t)dm.nz * dm.n * dm.n;
+  const Engine<T> E = engine<T>(k, 1, ws, opt->max_iter, st);
+  const void *dd[1] = {d};
+  void *mm[1] = {mu};
+  double *scal = E.scal();
   const int K = opt->max_iter;
-  // scalars: [0] |w|^2  [1] <v,w>  [2] |max(0, A^T d)|^2  [3..4] final fit  [5..6] last hist
+  // scalars: [0] |w|^2  [1] <v,w>  [3] final fit  [5..6] last history row
   HIP_TRY(ctof::launch_fill_zero(scal, 64 * 8, st));
-  if (!opt->warm_start) HIP_TRY(ctof::launch_fill_zero(mu, vol * sizeof(T), st));
-
-  // ||G(0)|| = ||max(0, A^T d)||
-  {
-    ctof::RowArgs a = ops.row(ctof::ROW_SPATIAL_TO_SPEC, true);
-    a.sp_in = d;
-    HIP_TRY(ctof::launch_row_pass<T>(dm, a, st));
-    HIP_TRY(ops.adj_to_xz());
-    ctof::RowArgs b = ops.row(ctof::ROW_GMAP0, false);
-    b.partials = part;
-    HIP_TRY(ctof::launch_row_pass<T>(dm, b, st));
-    HIP_TRY(ctof::launch_reduce_rows(part, L.nblk_z, 2, 1, scal + 2, st));
-  }
+  if (ctof_status s = enqueue_gmap0(E, dd); s != CTOF_OK) return s;
 
   double lam = opt->lambda_tikhonov, Lip = opt->lipschitz, LA = 0.0;
   if (Lip == 0.0) {
-    const int iters = opt->power_iters > 0 ? opt->power_iters : 50;
-    if (sizeof(T) == 8)
-      HIP_TRY(ctof::launch_fill_value_f64(reinterpret_cast<double *>(v), vol, 1.0 / std::sqrt((double)vol), st));
-    else
-      HIP_TRY(ctof::launch_fill_value(reinterpret_cast<float *>(v), vol, (float)(1.0 / std::sqrt((double)vol)), st));
-    for (int j = 0; j < iters; ++j) {
-      ctof::RowArgs a = ops.row(j == 0 ? ctof::ROW_SPATIAL_TO_SPEC : ctof::ROW_SCALE_TO_SPEC, false);
-      a.sp_in = j == 0 ? (const void *)v : (const void *)w;
-      a.sp_out = v;
-      a.scalar = scal + 0;
-      HIP_TRY(ops.mu_to_spec(a));
-      HIP_TRY(ops.fwd_to_xt());
-      ctof::RowArgs b = ops.row(ctof::ROW_PASS, true);
-      HIP_TRY(ctof::launch_row_pass<T>(dm, b, st));
-      HIP_TRY(ops.adj_to_xz());
-      ctof::RowArgs c = ops.row(ctof::ROW_POWER_W, false);
-      c.sp_in = v;
-      c.sp_out = w;
-      c.partials = part;
-      HIP_TRY(ctof::launch_row_pass<T>(dm, c, st));
-      HIP_TRY(ctof::launch_reduce_rows(part, L.nblk_z, 2, 2, scal + 0, st));
-    }
-    double hs[3];
-    HIP_TRY(hipMemcpyAsync(hs, scal, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (ctof_status s = enqueue_power_iteration(E, opt->power_iters > 0 ? opt->power_iters : 50); s != CTOF_OK)
+      return s;
+    double hs[2];
+    HIP_TRY(hipMemcpyAsync(hs, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     LA = hs[1];
     if (!std::isfinite(LA) || !(LA > 0)) {
@@ -365,15 +480,9 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
   rep->lambda = lam;
   rep->lipschitz_a = LA;
 
-  // FISTA: y_1 = mu_0
-  HIP_TRY(hipMemcpyAsync(y, mu, vol * sizeof(T), hipMemcpyDeviceToDevice, st));
-  {
-    ctof::RowArgs a = ops.row(ctof::ROW_SPATIAL_TO_SPEC, false);
-    a.sp_in = y;
-    HIP_TRY(ops.mu_to_spec(a));
-  }
+  if (ctof_status s = enqueue_start(E, mm, opt->warm_start != 0); s != CTOF_OK) return s;
   const std::vector<double> beta = fista_betas(K);
-  // optional stage timing: five events per iteration on the caller's stream
+  // optional stage timing: events around the contraction and FFT groups
   std::vector<hipEvent_t> ev;
   struct EventGuard {
     std::vector<hipEvent_t> *v;
@@ -390,35 +499,35 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
   };
   int done = 0;
   for (int it = 0; it < K; ++it) {
-    double *pk = part + (size_t)it * L.part_stride;
+    double *pk = E.part() + (size_t)it * E.L.part_stride;
     HIP_TRY(mark(it, 0));
-    HIP_TRY(ctof::launch_contract(k, false, ops.yhat(), ops.mhat(), st));
+    HIP_TRY(E.contract(false));
     HIP_TRY(mark(it, 1));
-    HIP_TRY(ctof::launch_col_pass<T>(dm, dm.ntp, true, ops.mhat(), ops.xt(), st));
-    ctof::RowArgs a = ops.row(ctof::ROW_RESIDUAL, true);
-    a.sp_in = d;
+    HIP_TRY(E.col_t(true));
+    ctof::RowArgs a = E.row(ctof::ROW_RESIDUAL, true);
+    a.sp_in[0] = d;
     a.partials = pk;
-    HIP_TRY(ctof::launch_row_pass<T>(dm, a, st));
-    HIP_TRY(ctof::launch_col_pass<T>(dm, dm.ntp, false, ops.xt(), ops.mhat(), st));
+    HIP_TRY(E.run_row(a));
+    HIP_TRY(E.col_t(false));
     HIP_TRY(mark(it, 2));
-    HIP_TRY(ctof::launch_contract(k, true, ops.mhat(), ops.yhat(), st));
+    HIP_TRY(E.contract(true));
     HIP_TRY(mark(it, 3));
-    HIP_TRY(ctof::launch_col_pass<T>(dm, dm.nzp, true, ops.yhat(), ops.xz(), st));
-    ctof::RowArgs b = ops.row(ctof::ROW_FISTA, false);
-    b.sp_in = y;
-    b.sp_out = y;
-    b.sp_aux = mu;
-    b.partials = pk + 2 * (size_t)L.nblk_t;
+    HIP_TRY(E.col_z(true));
+    ctof::RowArgs b = E.row(ctof::ROW_FISTA, false);
+    b.sp_in[0] = E.y(0);
+    b.sp_out[0] = E.y(0);
+    b.sp_aux[0] = mu;
+    b.partials = pk + 2 * (size_t)E.L.nblk_t;
     b.tau = tau;
     b.lambda = lam;
     b.beta = beta[it];
-    HIP_TRY(ctof::launch_row_pass<T>(dm, b, st));
-    HIP_TRY(ctof::launch_col_pass<T>(dm, dm.nzp, false, ops.xz(), ops.yhat(), st));
+    HIP_TRY(E.run_row(b));
+    HIP_TRY(E.col_z(false));
     HIP_TRY(mark(it, 4));
     done = it + 1;
     if (opt->rel_tol > 0 && (done % opt->check_every == 0) && done < K) {
-      HIP_TRY(ctof::launch_history_k(part + (size_t)it * L.part_stride, 1, L.nblk_t, L.nblk_z, tau,
-                                     scal + 2, scal + 5, nullptr, st));
+      HIP_TRY(ctof::launch_history(E.part() + (size_t)it * E.L.part_stride, 1, 1, E.L.nblk_t, E.L.nblk_z,
+                                   E.L.part_stride, tau, E.g0sq(), scal + 5, st));
       double h2[2];
       HIP_TRY(hipMemcpyAsync(h2, scal + 5, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
       HIP_TRY(hipStreamSynchronize(st));
@@ -426,27 +535,19 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
       if (h2[1] <= opt->rel_tol) break;
     }
   }
-  HIP_TRY(ctof::launch_history_k(part, done, L.nblk_t, L.nblk_z, tau, scal + 2, hist, scal + 5, st));
+  HIP_TRY(ctof::launch_history(E.part(), done, 1, E.L.nblk_t, E.L.nblk_z, E.L.part_stride, tau, E.g0sq(),
+                               E.hist(), st));
   if (opt->history_dev)
-    HIP_TRY(hipMemcpyAsync(opt->history_dev, hist, (size_t)done * 2 * sizeof(double),
+    HIP_TRY(hipMemcpyAsync(opt->history_dev, E.hist(), (size_t)done * 2 * sizeof(double),
                            hipMemcpyDeviceToDevice, st));
-  // final data fit 1/2 ||A mu - d||^2
-  {
-    double *pf = part + (size_t)(K) * L.part_stride;
-    ctof::RowArgs a = ops.row(ctof::ROW_SPATIAL_TO_SPEC, false);
-    a.sp_in = mu;
-    HIP_TRY(ops.mu_to_spec(a));
-    HIP_TRY(ops.fwd_to_xt());
-    ctof::RowArgs b = ops.row(ctof::ROW_RESIDUAL, true);
-    b.sp_in = d;
-    b.partials = pf;
-    HIP_TRY(ctof::launch_row_pass<T>(dm, b, st));
-    HIP_TRY(ctof::launch_reduce_rows(pf, L.nblk_t, 2, 1, scal + 3, st));
-  }
-  double hs[8];
-  double h0[2];
-  HIP_TRY(hipMemcpyAsync(hs, scal, 8 * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(h0, hist, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  if (ctof_status s = enqueue_final_fit(E, dd, mm, E.part() + (size_t)K * E.L.part_stride, scal + 3);
+      s != CTOF_OK)
+    return s;
+  double hs[4], h0[2], hl[2], g0;
+  HIP_TRY(hipMemcpyAsync(hs, scal, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(h0, E.hist(), 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(hl, E.hist() + 2 * (size_t)(done - 1), 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipMemcpyAsync(&g0, E.g0sq(), sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   if (opt->timing && done > 0) {
     double acc[4] = {0, 0, 0, 0};
@@ -468,15 +569,297 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
   rep->iters = done;
   rep->datafit0 = h0[0];
   rep->datafit = hs[3];
-  rep->gmap_ratio = hs[6];
-  rep->gmap0 = std::sqrt(hs[2]);
+  rep->gmap_ratio = hl[1];
+  rep->gmap0 = std::sqrt(g0);
   rep->status = CTOF_OK;
+  (void)dm;
   if (!std::isfinite(rep->datafit) || !std::isfinite(rep->datafit0) || !std::isfinite(rep->gmap_ratio) ||
       !std::isfinite(rep->gmap0)) {
     rep->status = CTOF_ENONFINITE;
     return set_error(CTOF_ENONFINITE, "non-finite FP64 norm during the solve");
   }
   return CTOF_OK;
+}
+
+// ---- batched reconstruction -----------------------------------------------------
+struct ClassPlan {
+  const ctof_kernel_s *k;
+  std::vector<int> scans;
+  size_t off;
+  ClassWs L;
+  double tau, lam, lip, lip_a;
+  bool active;
+};
+
+std::vector<ClassPlan> plan_classes(int nscan, const ctof_kernel *ks, int max_iter, size_t *total) {
+  std::vector<ClassPlan> cls;
+  for (int i = 0; i < nscan; ++i) {
+    ClassPlan *c = nullptr;
+    for (auto &x : cls)
+      if (x.k == ks[i] && (int)x.scans.size() < ctof::kMaxVol) c = &x;
+    if (!c) {
+      cls.push_back(ClassPlan{ks[i], {}, 0, ClassWs{}, 0, 0, 0, 0, true});
+      c = &cls.back();
+    }
+    c->scans.push_back(i);
+  }
+  size_t off = 0;
+  for (auto &c : cls) {
+    c.L = class_ws(c.k, (int)c.scans.size(), max_iter);
+    c.off = off;
+    off += ctof::round_up(c.L.solve_total, 256);
+  }
+  if (total) *total = off;
+  return cls;
+}
+
+struct StreamGuard {
+  hipStream_t s = nullptr;
+  hipGraph_t g = nullptr;
+  hipGraphExec_t x = nullptr;
+  void reset_graph() {
+    if (x) (void)hipGraphExecDestroy(x);
+    if (g) (void)hipGraphDestroy(g);
+    x = nullptr;
+    g = nullptr;
+  }
+  ~StreamGuard() {
+    reset_graph();
+    if (s) (void)hipStreamDestroy(s);
+  }
+};
+
+template <typename T>
+ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, void *const *mu,
+                        const ctof_solver_opts *opt, ctof_solver_report *rep, void *ws, hipStream_t st) {
+  const int K = opt->max_iter;
+  std::vector<ClassPlan> cls = plan_classes(nscan, ks, K, nullptr);
+  char *base = reinterpret_cast<char *>(ws);
+  std::vector<Engine<T>> E;
+  std::vector<std::vector<const void *>> dv(cls.size());
+  std::vector<std::vector<void *>> mv(cls.size());
+  for (size_t c = 0; c < cls.size(); ++c) {
+    E.push_back(Engine<T>{cls[c].k, (int)cls[c].scans.size(), base + cls[c].off, cls[c].L, st});
+    for (int i : cls[c].scans) {
+      dv[c].push_back(d[i]);
+      mv[c].push_back(mu[i]);
+    }
+  }
+  // set-up: ||G(0)|| per volume and L_A per class (one vector per class)
+  for (size_t c = 0; c < cls.size(); ++c) {
+    HIP_TRY(ctof::launch_fill_zero(E[c].scal(), 64 * 8, st));
+    if (ctof_status s = enqueue_gmap0(E[c], dv[c].data()); s != CTOF_OK) return s;
+    if (opt->lipschitz == 0.0) {
+      Engine<T> E1 = E[c];
+      const bool f64 = E1.k->prec == CTOF_FP64;
+      E1.nvol = 1;
+      E1.L.nblk_t = ctof::row_pass_blocks(E1.dm(), E1.dm().ntp, E1.dm().ntp, f64, E1.k->bb_t);
+      E1.L.nblk_z = ctof::row_pass_blocks(E1.dm(), E1.dm().nzp, E1.dm().nzp, f64, E1.k->bb_z);
+      if (ctof_status s = enqueue_power_iteration(E1, opt->power_iters > 0 ? opt->power_iters : 50); s != CTOF_OK)
+        return s;
+    }
+  }
+  for (size_t c = 0; c < cls.size(); ++c) {
+    double lam = opt->lambda_tikhonov, lip = opt->lipschitz, la = 0.0;
+    if (lip == 0.0) {
+      double hs[2];
+      HIP_TRY(hipMemcpyAsync(hs, E[c].scal(), 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      la = hs[1];
+      if (!std::isfinite(la) || !(la > 0))
+        return set_error(CTOF_ENONFINITE, "power iteration of class %zu gave ||A||^2 = %g", c, la);
+      if (lam < 0) lam = 1e-3 * la;
+      lip = 1.01 * la + lam;
+    }
+    cls[c].lam = lam;
+    cls[c].lip = lip;
+    cls[c].lip_a = la;
+    cls[c].tau = 1.0 / lip;
+    if (ctof_status s = enqueue_start(E[c], mv[c].data(), opt->warm_start != 0); s != CTOF_OK) return s;
+    HIP_TRY(ctof::launch_beta_table(E[c].beta(), K, st));
+    HIP_TRY(ctof::launch_fill_int(E[c].ctr(), 1, 0, st));
+    HIP_TRY(ctof::launch_fill_int(E[c].active(), E[c].nvol, 1, st));
+  }
+  // iterations: chunks of `chunk` iterations of every live class, captured once
+  // as a graph on an internal stream and replayed on the caller's stream
+  const int chunk = std::max(1, std::min(opt->rel_tol > 0 ? opt->check_every : K, 50));
+  StreamGuard sg;
+  HIP_TRY(hipStreamCreateWithFlags(&sg.s, hipStreamNonBlocking));
+  bool recapture = true;
+  std::vector<std::vector<int>> conv(cls.size());
+  for (size_t c = 0; c < cls.size(); ++c) conv[c].assign(E[c].nvol, 0);
+  int done = 0;
+  while (done < K) {
+    bool any = false;
+    for (auto &c : cls) any = any || c.active;
+    if (!any) break;
+    const int n_this = std::min(chunk, K - done);
+    if (n_this == chunk) {
+      if (recapture) {
+        sg.reset_graph();
+        HIP_TRY(hipStreamBeginCapture(sg.s, hipStreamCaptureModeThreadLocal));
+        ctof_status cap = CTOF_OK;
+        for (int i = 0; i < chunk && cap == CTOF_OK; ++i)
+          for (size_t c = 0; c < cls.size() && cap == CTOF_OK; ++c) {
+            if (!cls[c].active) continue;
+            Engine<T> Ec = E[c];
+            Ec.st = sg.s;
+            cap = enqueue_iteration(Ec, dv[c].data(), mv[c].data(), cls[c].tau, cls[c].lam, true, 0, 0.0);
+          }
+        hipGraph_t g = nullptr;
+        const hipError_t ee = hipStreamEndCapture(sg.s, &g);
+        sg.g = g;
+        if (cap != CTOF_OK) return cap;
+        HIP_TRY(ee);
+        HIP_TRY(hipGraphInstantiate(&sg.x, sg.g, nullptr, nullptr, 0));
+        recapture = false;
+      }
+      HIP_TRY(hipGraphLaunch(sg.x, st));
+    } else {
+      for (int i = 0; i < n_this; ++i)
+        for (size_t c = 0; c < cls.size(); ++c)
+          if (cls[c].active)
+            if (ctof_status s = enqueue_iteration(E[c], dv[c].data(), mv[c].data(), cls[c].tau, cls[c].lam,
+                                                  true, 0, 0.0);
+                s != CTOF_OK)
+              return s;
+    }
+    done += n_this;
+    if (opt->rel_tol > 0 && done < K) {
+      std::vector<std::vector<double>> last(cls.size());
+      for (size_t c = 0; c < cls.size(); ++c) {
+        if (!cls[c].active) continue;
+        const ClassWs &L = cls[c].L;
+        double *row = E[c].hist() + (size_t)(done - 1) * E[c].nvol * 2;
+        HIP_TRY(ctof::launch_history(E[c].part() + (size_t)(done - 1) * L.part_stride, 1, E[c].nvol, L.nblk_t,
+                                     L.nblk_z, L.part_stride, cls[c].tau, E[c].g0sq(), row, st));
+        last[c].resize((size_t)E[c].nvol * 2);
+        HIP_TRY(hipMemcpyAsync(last[c].data(), row, last[c].size() * sizeof(double), hipMemcpyDeviceToHost, st));
+      }
+      HIP_TRY(hipStreamSynchronize(st));
+      for (size_t c = 0; c < cls.size(); ++c) {
+        if (!cls[c].active) continue;
+        std::vector<int> act((size_t)E[c].nvol, 1);
+        int live = 0;
+        for (int v = 0; v < E[c].nvol; ++v) {
+          if (conv[c][v] == 0 && std::isfinite(last[c][2 * v + 1]) && last[c][2 * v + 1] <= opt->rel_tol)
+            conv[c][v] = done;
+          act[v] = conv[c][v] == 0 ? 1 : 0;
+          live += act[v];
+        }
+        HIP_TRY(hipMemcpyAsync(E[c].active(), act.data(), act.size() * sizeof(int), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (live == 0) {
+          cls[c].active = false;
+          recapture = true;
+        }
+      }
+    }
+  }
+  // reports: full history, final data fit per volume
+  std::vector<std::vector<double>> hist(cls.size()), fit(cls.size()), g0(cls.size());
+  for (size_t c = 0; c < cls.size(); ++c) {
+    const ClassWs &L = cls[c].L;
+    const int its = std::max(1, std::min(done, K));
+    HIP_TRY(ctof::launch_history(E[c].part(), its, E[c].nvol, L.nblk_t, L.nblk_z, L.part_stride, cls[c].tau,
+                                 E[c].g0sq(), E[c].hist(), st));
+    if (ctof_status s = enqueue_final_fit(E[c], dv[c].data(), mv[c].data(),
+                                          E[c].part() + (size_t)K * L.part_stride, E[c].scal() + 8);
+        s != CTOF_OK)
+      return s;
+    hist[c].resize((size_t)its * E[c].nvol * 2);
+    fit[c].resize(E[c].nvol);
+    g0[c].resize(E[c].nvol);
+    HIP_TRY(hipMemcpyAsync(hist[c].data(), E[c].hist(), hist[c].size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(fit[c].data(), E[c].scal() + 8, fit[c].size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(g0[c].data(), E[c].g0sq(), g0[c].size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  }
+  HIP_TRY(hipStreamSynchronize(st));
+  ctof_status worst = CTOF_OK;
+  for (size_t c = 0; c < cls.size(); ++c) {
+    const int nv = E[c].nvol;
+    for (int v = 0; v < nv; ++v) {
+      ctof_solver_report &r = rep[cls[c].scans[v]];
+      std::memset(&r, 0, sizeof(r));
+      const int its = conv[c][v] > 0 ? conv[c][v] : std::max(1, done);
+      r.iters = its;
+      r.datafit0 = hist[c][(size_t)v * 2];
+      r.gmap_ratio = hist[c][((size_t)(its - 1) * nv + v) * 2 + 1];
+      r.datafit = fit[c][v];
+      r.lipschitz = cls[c].lip;
+      r.lambda = cls[c].lam;
+      r.lipschitz_a = cls[c].lip_a;
+      r.gmap0 = std::sqrt(g0[c][v]);
+      r.status = CTOF_OK;
+      if (!std::isfinite(r.datafit) || !std::isfinite(r.datafit0) || !std::isfinite(r.gmap_ratio)) {
+        r.status = CTOF_ENONFINITE;
+        worst = CTOF_ENONFINITE;
+      }
+    }
+  }
+  if (worst != CTOF_OK) return set_error(worst, "non-finite FP64 norm in a batched solve");
+  return CTOF_OK;
+}
+
+// Times the operator passes of one class for each legal FFT planes-per-block
+// choice and keeps the fastest in the handle.
+template <typename T>
+ctof_status run_tune(ctof_kernel_s *k, int nvol, int iters, void *ws, hipStream_t st, float *ms,
+                     int32_t *bt, int32_t *bz) {
+  const int cand[4][2] = {{16, 16}, {32, 16}, {16, 32}, {32, 32}};
+  float best = 1e30f;
+  int bi = 0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  ctof_status status = CTOF_OK;
+  for (int c = 0; c < 4 && status == CTOF_OK; ++c) {
+    k->bb_t = cand[c][0];
+    k->bb_z = cand[c][1];
+    const Engine<T> E = engine<T>(k, nvol, ws, 1, st);
+    // skip choices the block rule would not honour (it falls back to 16)
+    const bool f64 = k->prec == CTOF_FP64;
+    if (ctof::batch_block(E.dm(), E.Bt(), E.dm().ntp, f64, cand[c][0]) != cand[c][0] ||
+        ctof::batch_block(E.dm(), E.Bz(), E.dm().nzp, f64, cand[c][1]) != cand[c][1]) {
+      if (ms) ms[c] = -1.f;
+      continue;
+    }
+    if (hipError_t e = ctof::launch_fill_zero(E.ws, E.L.op_total, st); e != hipSuccess) {
+      status = set_error(CTOF_EHIP, "fill failed: %s", hipGetErrorString(e));
+      break;
+    }
+    float t = 0.f;
+    for (int rep = 0; rep < 2 && status == CTOF_OK; ++rep) {  // first pass warms up
+      if (hipEventRecord(e0, st) != hipSuccess) status = CTOF_EHIP;
+      for (int i = 0; i < iters && status == CTOF_OK; ++i) {
+        ctof::RowArgs a = E.row(ctof::ROW_PASS, true);
+        ctof::RowArgs b = E.row(ctof::ROW_PASS, false);
+        hipError_t e = E.contract(false);
+        if (e == hipSuccess) e = E.col_t(true);
+        if (e == hipSuccess) e = E.run_row(a);
+        if (e == hipSuccess) e = E.col_t(false);
+        if (e == hipSuccess) e = E.contract(true);
+        if (e == hipSuccess) e = E.col_z(true);
+        if (e == hipSuccess) e = E.run_row(b);
+        if (e == hipSuccess) e = E.col_z(false);
+        if (e != hipSuccess) status = set_error(CTOF_EHIP, "tuning launch failed: %s", hipGetErrorString(e));
+      }
+      if (status == CTOF_OK && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess)
+        (void)hipEventElapsedTime(&t, e0, e1);
+    }
+    if (ms) ms[c] = t / std::max(iters, 1);
+    if (status == CTOF_OK && t < best) {
+      best = t;
+      bi = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  k->bb_t = cand[bi][0];
+  k->bb_z = cand[bi][1];
+  if (bt) *bt = k->bb_t;
+  if (bz) *bz = k->bb_z;
+  return status;
 }
 
 }  // namespace
@@ -584,6 +967,8 @@ ctof_status ctof_kernel_tabulate(const ctof_geometry *geom, ctof_precision prec,
   k->geom = tg;
   k->khat = khat_dev;
   k->layout = lay;
+  k->bb_t = 0;
+  k->bb_z = 0;
   *out = k;
   return CTOF_OK;
 }
@@ -623,7 +1008,7 @@ ctof_status ctof_workspace_bytes(ctof_kernel k, int32_t max_iter, size_t *op_ws_
   ctof_status s = check_kernel(k);
   if (s != CTOF_OK) return s;
   if (max_iter < 0) return set_error(CTOF_EINVAL, "max_iter must be >= 0");
-  const OpWs o = op_ws(k->dims, k->prec, max_iter);
+  const ClassWs o = class_ws(k, 1, max_iter);
   if (op_ws_bytes) *op_ws_bytes = o.op_total;
   if (solve_ws) *solve_ws = o.solve_total;
   return CTOF_OK;
@@ -634,7 +1019,7 @@ ctof_status ctof_forward(ctof_kernel k, const void *mu_dev, void *m_dev, void *w
   ctof_status s = check_kernel(k);
   if (s != CTOF_OK) return s;
   if (!mu_dev || !m_dev || !ws_dev) return set_error(CTOF_EINVAL, "device pointer is NULL");
-  const OpWs o = op_ws(k->dims, k->prec, 1);
+  const ClassWs o = class_ws(k, 1, 1);
   if (ws_bytes < o.op_total) return set_error(CTOF_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, o.op_total);
   if (k->prec == CTOF_FP64) return run_forward<double>(k, mu_dev, m_dev, ws_dev, stream);
   return run_forward<float>(k, mu_dev, m_dev, ws_dev, stream);
@@ -645,7 +1030,7 @@ ctof_status ctof_adjoint(ctof_kernel k, const void *r_dev, void *g_dev, void *ws
   ctof_status s = check_kernel(k);
   if (s != CTOF_OK) return s;
   if (!r_dev || !g_dev || !ws_dev) return set_error(CTOF_EINVAL, "device pointer is NULL");
-  const OpWs o = op_ws(k->dims, k->prec, 1);
+  const ClassWs o = class_ws(k, 1, 1);
   if (ws_bytes < o.op_total) return set_error(CTOF_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, o.op_total);
   if (k->prec == CTOF_FP64) return run_adjoint<double>(k, r_dev, g_dev, ws_dev, stream);
   return run_adjoint<float>(k, r_dev, g_dev, ws_dev, stream);
@@ -666,11 +1051,107 @@ ctof_status ctof_reconstruct(ctof_kernel k, const void *d_dev, void *mu_inout_de
   if (!(std::isfinite(opts->rel_tol) && opts->rel_tol >= 0)) return set_error(CTOF_EINVAL, "rel_tol must be >= 0");
   if (opts->rel_tol > 0 && opts->check_every < 1) return set_error(CTOF_EINVAL, "check_every must be >= 1");
   if (opts->warm_start != 0 && opts->warm_start != 1) return set_error(CTOF_EINVAL, "warm_start must be 0 or 1");
-  const OpWs o = op_ws(k->dims, k->prec, opts->max_iter);
+  const ClassWs o = class_ws(k, 1, opts->max_iter);
   if (ws_bytes < o.solve_total) return set_error(CTOF_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, o.solve_total);
   std::memset(report, 0, sizeof(*report));
   if (k->prec == CTOF_FP64) return run_reconstruct<double>(k, d_dev, mu_inout_dev, opts, report, ws_dev, stream);
   return run_reconstruct<float>(k, d_dev, mu_inout_dev, opts, report, ws_dev, stream);
+}
+
+ctof_status ctof_workspace_bytes_batched(int32_t nscan, const ctof_kernel *k, int32_t max_iter,
+                                        size_t *ws_bytes) {
+  if (nscan < 1 || !k) return set_error(CTOF_EINVAL, "need at least one scan and a handle array");
+  if (max_iter < 1) return set_error(CTOF_EINVAL, "max_iter must be >= 1");
+  for (int i = 0; i < nscan; ++i)
+    if (ctof_status s = check_kernel(k[i]); s != CTOF_OK) return s;
+  size_t total = 0;
+  plan_classes(nscan, k, max_iter, &total);
+  if (ws_bytes) *ws_bytes = total;
+  return CTOF_OK;
+}
+
+ctof_status ctof_reconstruct_batched(int32_t nscan, const ctof_kernel *k, const void *const *d_dev,
+                                     void *const *mu_inout_dev, const ctof_solver_opts *opts,
+                                     ctof_solver_report *reports, void *ws_dev, size_t ws_bytes,
+                                     hipStream_t stream) {
+  if (nscan < 1 || !k || !d_dev || !mu_inout_dev || !opts || !reports || !ws_dev)
+    return set_error(CTOF_EINVAL, "NULL argument or no scans");
+  const ctof_precision prec = k[0] ? k[0]->prec : CTOF_FP32;
+  for (int i = 0; i < nscan; ++i) {
+    if (ctof_status s = check_kernel(k[i]); s != CTOF_OK) return s;
+    if (k[i]->prec != prec) return set_error(CTOF_EINVAL, "all handles of a batch need one precision");
+    if (!d_dev[i] || !mu_inout_dev[i]) return set_error(CTOF_EINVAL, "device pointer of scan %d is NULL", i);
+  }
+  if (opts->max_iter < 1) return set_error(CTOF_EINVAL, "max_iter must be >= 1");
+  if (!std::isfinite(opts->lambda_tikhonov)) return set_error(CTOF_EINVAL, "lambda_tikhonov must be finite");
+  if (!(std::isfinite(opts->lipschitz) && opts->lipschitz >= 0)) return set_error(CTOF_EINVAL, "lipschitz must be >= 0");
+  if (opts->lipschitz > 0 && opts->lambda_tikhonov < 0)
+    return set_error(CTOF_EINVAL, "an explicit lipschitz needs lambda_tikhonov >= 0");
+  if (!(std::isfinite(opts->rel_tol) && opts->rel_tol >= 0)) return set_error(CTOF_EINVAL, "rel_tol must be >= 0");
+  if (opts->rel_tol > 0 && opts->check_every < 1) return set_error(CTOF_EINVAL, "check_every must be >= 1");
+  if (opts->warm_start != 0 && opts->warm_start != 1) return set_error(CTOF_EINVAL, "warm_start must be 0 or 1");
+  if (opts->history_dev || opts->timing)
+    return set_error(CTOF_EINVAL, "history_dev and timing are single-scan options");
+  size_t need = 0;
+  plan_classes(nscan, k, opts->max_iter, &need);
+  if (ws_bytes < need) return set_error(CTOF_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
+  if (prec == CTOF_FP64)
+    return run_batched<double>(nscan, k, d_dev, mu_inout_dev, opts, reports, ws_dev, stream);
+  return run_batched<float>(nscan, k, d_dev, mu_inout_dev, opts, reports, ws_dev, stream);
+}
+
+ctof_status ctof_kernel_set_tuning(ctof_kernel k, int32_t bb_t, int32_t bb_z) {
+  if (ctof_status s = check_kernel(k); s != CTOF_OK) return s;
+  auto ok = [](int32_t v) { return v == 0 || v == 16 || v == 32; };
+  if (!ok(bb_t) || !ok(bb_z)) return set_error(CTOF_EINVAL, "planes per block must be 0, 16 or 32");
+  k->bb_t = bb_t;
+  k->bb_z = bb_z;
+  return CTOF_OK;
+}
+
+ctof_status ctof_kernel_get_tuning(ctof_kernel k, int32_t *bb_t, int32_t *bb_z) {
+  if (ctof_status s = check_kernel(k); s != CTOF_OK) return s;
+  if (bb_t) *bb_t = k->bb_t;
+  if (bb_z) *bb_z = k->bb_z;
+  return CTOF_OK;
+}
+
+ctof_status ctof_tune(ctof_kernel k, int32_t nvol, int32_t iters, void *ws_dev, size_t ws_bytes,
+                      hipStream_t stream, float *ms, int32_t *bb_t, int32_t *bb_z) {
+  if (ctof_status s = check_kernel(k); s != CTOF_OK) return s;
+  if (nvol < 1 || nvol > ctof::kMaxVol) return set_error(CTOF_EINVAL, "nvol must be in [1, %d]", ctof::kMaxVol);
+  if (iters < 1) return set_error(CTOF_EINVAL, "iters must be >= 1");
+  if (!ws_dev) return set_error(CTOF_EINVAL, "workspace is NULL");
+  const int32_t save_t = k->bb_t, save_z = k->bb_z;
+  size_t need = 0;
+  for (int bt : {16, 32})
+    for (int bz : {16, 32}) {
+      k->bb_t = bt;
+      k->bb_z = bz;
+      need = std::max(need, class_ws(k, nvol, 1).solve_total);
+    }
+  k->bb_t = save_t;
+  k->bb_z = save_z;
+  if (ws_bytes < need) return set_error(CTOF_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
+  if (k->prec == CTOF_FP64) return run_tune<double>(k, nvol, iters, ws_dev, stream, ms, bb_t, bb_z);
+  return run_tune<float>(k, nvol, iters, ws_dev, stream, ms, bb_t, bb_z);
+}
+
+ctof_status ctof_tune_workspace_bytes(ctof_kernel k, int32_t nvol, size_t *ws_bytes) {
+  if (ctof_status s = check_kernel(k); s != CTOF_OK) return s;
+  if (nvol < 1 || nvol > ctof::kMaxVol) return set_error(CTOF_EINVAL, "nvol must be in [1, %d]", ctof::kMaxVol);
+  const int32_t save_t = k->bb_t, save_z = k->bb_z;
+  size_t need = 0;
+  for (int bt : {16, 32})
+    for (int bz : {16, 32}) {
+      k->bb_t = bt;
+      k->bb_z = bz;
+      need = std::max(need, class_ws(k, nvol, 1).solve_total);
+    }
+  k->bb_t = save_t;
+  k->bb_z = save_z;
+  if (ws_bytes) *ws_bytes = need;
+  return CTOF_OK;
 }
 
 }  // extern "C"

@@ -12,10 +12,14 @@
 // (P-b, a).  Their real and imaginary parts are 8 real columns, so each
 // matrix is one small dense GEMM:
 //   forward  [Nt x Nz] x [Nz x 8],  adjoint  [Nz x Nt] x [Nt x 8].
-// One workgroup streams one matrix (read once per pass: the kernel spectrum
-// is the dominant HBM traffic of an iteration).  MFMA 16x16x4 (FP32, FP64)
-// or 16x16x32 (BF16) tiles: the matrix occupies the A operand, the 8 columns
-// the first 8 of the 16 B columns.  The reduction dimension is assigned so
+// One workgroup streams one matrix for one pair of volumes: the matrix is the
+// A operand, the pair's 2 x 8 real columns fill the 16 B columns of an MFMA
+// 16x16x4 (FP32, FP64) or 16x16x32 (BF16) tile.  A single volume leaves the
+// second half empty.  With several pairs (volumes of one shape class share
+// the kernel spectrum) the workgroups of one matrix are mapped to the same
+// XCD, so the matrix comes from HBM once and from that XCD's L2 afterwards;
+// with one pair it is streamed with non-temporal loads (read once per pass:
+// the kernel spectrum is the dominant HBM traffic of an iteration).  The reduction dimension is assigned so
 // that every lane reads a contiguous run of the matrix row (vector loads):
 // in k-step kk, lane group g = lane/16 carries index g * KC + kk.
 //
@@ -106,7 +110,7 @@ __device__ __forceinline__ void load_run(const T *__restrict__ p, T (&v)[N]) {
 }
 
 // N elements of one lane from a fragment block: word q sits at (q*64 + lane)
-template <typename T, int N>
+template <typename T, int N, bool NT>
 __device__ __forceinline__ void load_frag(const T *__restrict__ blk, int lane, T (&v)[N]) {
   constexpr int PER = 16 / sizeof(T);
   static_assert(N % PER == 0, "fragments are whole 16-byte words");
@@ -114,13 +118,15 @@ __device__ __forceinline__ void load_frag(const T *__restrict__ blk, int lane, T
   for (int q = 0; q < N / PER; ++q) {
     const T *p = blk + ((size_t)q * 64 + lane) * PER;
     if constexpr (sizeof(T) == 4) {
-      const nt_f4 w = __builtin_nontemporal_load(reinterpret_cast<const nt_f4 *>(p));
+      const nt_f4 w = NT ? __builtin_nontemporal_load(reinterpret_cast<const nt_f4 *>(p))
+                         : *reinterpret_cast<const nt_f4 *>(p);
       v[q * 4 + 0] = w[0];
       v[q * 4 + 1] = w[1];
       v[q * 4 + 2] = w[2];
       v[q * 4 + 3] = w[3];
     } else {
-      const nt_d2 w = __builtin_nontemporal_load(reinterpret_cast<const nt_d2 *>(p));
+      const nt_d2 w = NT ? __builtin_nontemporal_load(reinterpret_cast<const nt_d2 *>(p))
+                         : *reinterpret_cast<const nt_d2 *>(p);
       v[q * 2 + 0] = w[0];
       v[q * 2 + 1] = w[1];
     }
@@ -137,73 +143,112 @@ __device__ __forceinline__ void store4(T *p, const typename Mfma<T>::acc_t &a) {
   }
 }
 
+// Launch geometry shared by all contraction kernels.
+struct CArgs {
+  const void *khat, *khat_lo;  // forward or adjoint layout (bf16: hi and lo parts)
+  const void *vin;
+  void *vout;
+  int h, p, nzp, ntp, nmat;
+  int nvol, npairs;
+};
+
+// Block -> (matrix, pair): block L runs on XCD L % 8; all pairs of matrix s
+// get blocks with the same residue so they share an L2.
+__device__ inline bool map_block(const CArgs &a, int &s, int &pair) {
+  const int L = blockIdx.x;
+  const int xcd = L & 7;
+  const int r = L >> 3;
+  const int grp = r / a.npairs;
+  pair = r - grp * a.npairs;
+  s = grp * 8 + xcd;
+  return s < a.nmat;
+}
+
+// Column c of the B tile: volume 2 pair + c/8, slot (c%8)/2, real/imag c%2.
+struct Col {
+  int f, vol, reim;
+  bool on;
+};
+
+__device__ inline Col column_of(const CArgs &a, int s, int pair, int c) {
+  Col k;
+  k.vol = 2 * pair + (c >> 3);
+  const int cc = c & 7;
+  k.reim = cc & 1;
+  bool ok;
+  k.f = matrix_slot(s, a.h, a.p, cc >> 1, ok);
+  k.on = ok && k.vol < a.nvol;
+  return k;
+}
+
 // ---- FP32 / FP64, forward: M = t (tiles of 16), K = z --------------------------
-template <typename T, int KZ>
+template <typename T, int KZ, bool NT>
 __global__ void __launch_bounds__(256)
-contract_fwd_kernel(const T *__restrict__ khat, const T *__restrict__ vin, T *__restrict__ vout,
-                    int h, int p, int nzp, int ntp) {
+contract_fwd_kernel(CArgs a) {
   using M = Mfma<T>;
-  const int s = blockIdx.x;
+  int s, pair;
+  if (!map_block(a, s, pair)) return;
   const int w = threadIdx.x >> 6;
   const int l = threadIdx.x & 63;
   const int c = l & 15, g = l >> 4;
-  const int q = (c >> 1) & 3;
-  bool slot_ok;
-  const int f = matrix_slot(s, h, p, q, slot_ok);
-  const bool col = (c < 8) && slot_ok;
+  const Col k = column_of(a, s, pair, c);
+  const int nzp = a.nzp, ntp = a.ntp;
   const int nchunk = nzp / (4 * KZ);
-  const T *vcol = vin + ((size_t)f * 2 + (c & 1)) * nzp;
-  T *ocol = vout + ((size_t)f * 2 + (c & 1)) * ntp;
+  const T *vcol = reinterpret_cast<const T *>(a.vin) + ((size_t)k.f * 2 + k.reim) * a.nvol * nzp +
+                  (size_t)k.vol * nzp;
+  T *ocol = reinterpret_cast<T *>(a.vout) + ((size_t)k.f * 2 + k.reim) * a.nvol * ntp +
+            (size_t)k.vol * ntp;
+  const T *khat = reinterpret_cast<const T *>(a.khat);
   const int ntt = ntp / 16;
   for (int ch = 0; ch < nchunk; ++ch) {
     T bv[KZ];
-    if (col) {
+    if (k.on) {
       load_run<T, KZ>(vcol + ch * 4 * KZ + g * KZ, bv);
     } else {
 #pragma unroll
       for (int kk = 0; kk < KZ; ++kk) bv[kk] = (T)0;
     }
-    for (int tt = w; tt < ntp / 16; tt += 4) {
+    for (int tt = w; tt < ntt; tt += 4) {
       const int t0 = tt * 16;
       T av[KZ];
-      load_frag<T, KZ>(khat + (((size_t)s * ntt + tt) * nchunk + ch) * (64 * KZ), l, av);
+      load_frag<T, KZ, NT>(khat + (((size_t)s * ntt + tt) * nchunk + ch) * (64 * KZ), l, av);
       typename M::acc_t acc = {0, 0, 0, 0};
-      if (ch > 0 && col) {
-        // accumulate onto the previous z-chunk's partial result
+      if (ch > 0 && k.on) {
+        // accumulate onto the previous layer chunk's partial result
         const T *o = ocol + t0 + 4 * g;
         acc[0] = o[0]; acc[1] = o[1]; acc[2] = o[2]; acc[3] = o[3];
       }
 #pragma unroll
       for (int kk = 0; kk < KZ; ++kk) acc = M::step(av[kk], bv[kk], acc);
-      if (col) store4<T>(ocol + t0 + 4 * g, acc);
+      if (k.on) store4<T>(ocol + t0 + 4 * g, acc);
     }
   }
 }
 
 // ---- FP32 / FP64, adjoint: M = z (tiles of 16), K = t (chunks of 16) -----------
-template <typename T, int ZT>
+template <typename T, int ZT, bool NT>
 __global__ void __launch_bounds__(256)
-contract_adj_kernel(const T *__restrict__ khat, const T *__restrict__ vin, T *__restrict__ vout,
-                    int h, int p, int nzp, int ntp) {
+contract_adj_kernel(CArgs a) {
   using M = Mfma<T>;
   extern __shared__ unsigned char smem_raw[];
   T *red = reinterpret_cast<T *>(smem_raw);  // [4 waves][ZT][64 lanes][4]
-  const int s = blockIdx.x;
+  int s, pair;
+  if (!map_block(a, s, pair)) return;
   const int w = threadIdx.x >> 6;
   const int l = threadIdx.x & 63;
   const int c = l & 15, g = l >> 4;
-  const int q = (c >> 1) & 3;
-  bool slot_ok;
-  const int f = matrix_slot(s, h, p, q, slot_ok);
-  const bool col = (c < 8) && slot_ok;
-  const T *vcol = vin + ((size_t)f * 2 + (c & 1)) * ntp;
+  const Col k = column_of(a, s, pair, c);
+  const int nzp = a.nzp, ntp = a.ntp;
+  const T *vcol = reinterpret_cast<const T *>(a.vin) + ((size_t)k.f * 2 + k.reim) * a.nvol * ntp +
+                  (size_t)k.vol * ntp;
+  const T *khat = reinterpret_cast<const T *>(a.khat);
   typename M::acc_t acc[ZT];
 #pragma unroll
   for (int zt = 0; zt < ZT; ++zt) acc[zt] = {0, 0, 0, 0};
   for (int ch = w; ch < ntp / 16; ch += 4) {
     const int t0 = ch * 16 + 4 * g;
     T bv[4];
-    if (col) {
+    if (k.on) {
       load_run<T, 4>(vcol + t0, bv);
     } else {
       bv[0] = bv[1] = bv[2] = bv[3] = (T)0;
@@ -211,7 +256,7 @@ contract_adj_kernel(const T *__restrict__ khat, const T *__restrict__ vin, T *__
 #pragma unroll
     for (int zt = 0; zt < ZT; ++zt) {
       T av[4];
-      load_frag<T, 4>(khat + (((size_t)s * (ntp / 16) + ch) * ZT + zt) * 256, l, av);
+      load_frag<T, 4, NT>(khat + (((size_t)s * (ntp / 16) + ch) * ZT + zt) * 256, l, av);
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) acc[zt] = M::step(av[kk], bv[kk], acc[zt]);
     }
@@ -223,8 +268,9 @@ contract_adj_kernel(const T *__restrict__ khat, const T *__restrict__ vin, T *__
 #pragma unroll
     for (int r = 0; r < 4; ++r) red[((w * ZT + zt) * 64 + l) * 4 + r] = acc[zt][r];
   __syncthreads();
-  if (w == 0 && col) {
-    T *ocol = vout + ((size_t)f * 2 + (c & 1)) * nzp;
+  if (w == 0 && k.on) {
+    T *ocol = reinterpret_cast<T *>(a.vout) + ((size_t)k.f * 2 + k.reim) * a.nvol * nzp +
+              (size_t)k.vol * nzp;
 #pragma unroll
     for (int zt = 0; zt < ZT; ++zt) {
       typename M::acc_t o;
@@ -248,29 +294,32 @@ __device__ inline void split_bf16(float v, __bf16 &hi, __bf16 &lo) {
   lo = (__bf16)(v - (float)hi);
 }
 
+template <bool NT>
 __device__ __forceinline__ v8bf load_bf8(const __bf16 *p) {
-  const nt_u4 u = __builtin_nontemporal_load(reinterpret_cast<const nt_u4 *>(p));
+  const nt_u4 u = NT ? __builtin_nontemporal_load(reinterpret_cast<const nt_u4 *>(p))
+                     : *reinterpret_cast<const nt_u4 *>(p);
   v8bf r;
   __builtin_memcpy(&r, &u, 16);
   return r;
 }
 
-template <int KIND, int KZ>  // KZ: z per lane group per chunk (multiple of 8)
+template <int KIND, int KZ, bool NT>  // KZ: z per lane group per chunk (multiple of 8)
 __global__ void __launch_bounds__(256)
-contract_fwd_bf16_kernel(const __bf16 *__restrict__ khi, const __bf16 *__restrict__ klo,
-                         const float *__restrict__ vin, float *__restrict__ vout, int h, int p,
-                         int nzp, int ntp) {
-  const int s = blockIdx.x;
+contract_fwd_bf16_kernel(CArgs a) {
+  int s, pair;
+  if (!map_block(a, s, pair)) return;
   const int w = threadIdx.x >> 6;
   const int l = threadIdx.x & 63;
   const int c = l & 15, g = l >> 4;
-  const int q = (c >> 1) & 3;
-  bool slot_ok;
-  const int f = matrix_slot(s, h, p, q, slot_ok);
-  const bool col = (c < 8) && slot_ok;
+  const Col k = column_of(a, s, pair, c);
+  const int nzp = a.nzp, ntp = a.ntp;
   const int nchunk = nzp / (4 * KZ);
-  const float *vcol = vin + ((size_t)f * 2 + (c & 1)) * nzp;
-  float *ocol = vout + ((size_t)f * 2 + (c & 1)) * ntp;
+  const float *vcol = reinterpret_cast<const float *>(a.vin) +
+                      ((size_t)k.f * 2 + k.reim) * a.nvol * nzp + (size_t)k.vol * nzp;
+  float *ocol = reinterpret_cast<float *>(a.vout) + ((size_t)k.f * 2 + k.reim) * a.nvol * ntp +
+                (size_t)k.vol * ntp;
+  const __bf16 *khi = reinterpret_cast<const __bf16 *>(a.khat);
+  const __bf16 *klo = reinterpret_cast<const __bf16 *>(a.khat_lo);
   const int ntt = ntp / 16;
   for (int ch = 0; ch < nchunk; ++ch) {
     v8bf bh[KZ / 8], bl[KZ / 8];
@@ -278,53 +327,53 @@ contract_fwd_bf16_kernel(const __bf16 *__restrict__ khi, const __bf16 *__restric
     for (int e = 0; e < KZ / 8; ++e) {
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const float v = col ? vcol[ch * 4 * KZ + g * KZ + e * 8 + u] : 0.0f;
+        const float v = k.on ? vcol[ch * 4 * KZ + g * KZ + e * 8 + u] : 0.0f;
         __bf16 hi, lo;
         split_bf16(v, hi, lo);
         bh[e][u] = hi;
         bl[e][u] = lo;
       }
     }
-    for (int tt = w; tt < ntp / 16; tt += 4) {
+    for (int tt = w; tt < ntt; tt += 4) {
       const int t0 = tt * 16;
       const size_t blk = (((size_t)s * ntt + tt) * nchunk + ch) * (64 * KZ);
       v4f acc = {0, 0, 0, 0};
-      if (ch > 0 && col) {
+      if (ch > 0 && k.on) {
         const float *o = ocol + t0 + 4 * g;
         acc[0] = o[0]; acc[1] = o[1]; acc[2] = o[2]; acc[3] = o[3];
       }
 #pragma unroll
       for (int e = 0; e < KZ / 8; ++e) {
         const size_t off = blk + ((size_t)e * 64 + l) * 8;
-        const v8bf ah = load_bf8(khi + off);
+        const v8bf ah = load_bf8<NT>(khi + off);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[e], acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[e], acc, 0, 0, 0);
         if (KIND == 2) {
-          const v8bf al = load_bf8(klo + off);
+          const v8bf al = load_bf8<NT>(klo + off);
           acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[e], acc, 0, 0, 0);
         }
       }
-      if (col) *reinterpret_cast<float4 *>(ocol + t0 + 4 * g) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+      if (k.on) *reinterpret_cast<float4 *>(ocol + t0 + 4 * g) = make_float4(acc[0], acc[1], acc[2], acc[3]);
     }
   }
 }
 
-template <int KIND, int ZT>
+template <int KIND, int ZT, bool NT>
 __global__ void __launch_bounds__(256)
-contract_adj_bf16_kernel(const __bf16 *__restrict__ khi, const __bf16 *__restrict__ klo,
-                         const float *__restrict__ vin, float *__restrict__ vout, int h, int p,
-                         int nzp, int ntp) {
+contract_adj_bf16_kernel(CArgs a) {
   extern __shared__ unsigned char smem_raw[];
   float *red = reinterpret_cast<float *>(smem_raw);
-  const int s = blockIdx.x;
+  int s, pair;
+  if (!map_block(a, s, pair)) return;
   const int w = threadIdx.x >> 6;
   const int l = threadIdx.x & 63;
   const int c = l & 15, g = l >> 4;
-  const int q = (c >> 1) & 3;
-  bool slot_ok;
-  const int f = matrix_slot(s, h, p, q, slot_ok);
-  const bool col = (c < 8) && slot_ok;
-  const float *vcol = vin + ((size_t)f * 2 + (c & 1)) * ntp;
+  const Col k = column_of(a, s, pair, c);
+  const int nzp = a.nzp, ntp = a.ntp;
+  const float *vcol = reinterpret_cast<const float *>(a.vin) +
+                      ((size_t)k.f * 2 + k.reim) * a.nvol * ntp + (size_t)k.vol * ntp;
+  const __bf16 *khi = reinterpret_cast<const __bf16 *>(a.khat);
+  const __bf16 *klo = reinterpret_cast<const __bf16 *>(a.khat_lo);
   v4f acc[ZT];
 #pragma unroll
   for (int zt = 0; zt < ZT; ++zt) acc[zt] = {0, 0, 0, 0};
@@ -333,7 +382,7 @@ contract_adj_bf16_kernel(const __bf16 *__restrict__ khi, const __bf16 *__restric
     v8bf bh, bl;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      const float v = col ? vcol[t0 + u] : 0.0f;
+      const float v = k.on ? vcol[t0 + u] : 0.0f;
       __bf16 hi, lo;
       split_bf16(v, hi, lo);
       bh[u] = hi;
@@ -342,11 +391,11 @@ contract_adj_bf16_kernel(const __bf16 *__restrict__ khi, const __bf16 *__restric
 #pragma unroll
     for (int zt = 0; zt < ZT; ++zt) {
       const size_t off = (((size_t)s * (ntp / 32) + ch) * ZT + zt) * 512 + (size_t)l * 8;
-      const v8bf ah = load_bf8(khi + off);
+      const v8bf ah = load_bf8<NT>(khi + off);
       acc[zt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[zt], 0, 0, 0);
       acc[zt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc[zt], 0, 0, 0);
       if (KIND == 2) {
-        const v8bf al = load_bf8(klo + off);
+        const v8bf al = load_bf8<NT>(klo + off);
         acc[zt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc[zt], 0, 0, 0);
       }
     }
@@ -356,8 +405,9 @@ contract_adj_bf16_kernel(const __bf16 *__restrict__ khi, const __bf16 *__restric
 #pragma unroll
     for (int r = 0; r < 4; ++r) red[((w * ZT + zt) * 64 + l) * 4 + r] = acc[zt][r];
   __syncthreads();
-  if (w == 0 && col) {
-    float *ocol = vout + ((size_t)f * 2 + (c & 1)) * nzp;
+  if (w == 0 && k.on) {
+    float *ocol = reinterpret_cast<float *>(a.vout) + ((size_t)k.f * 2 + k.reim) * a.nvol * nzp +
+                  (size_t)k.vol * nzp;
 #pragma unroll
     for (int zt = 0; zt < ZT; ++zt) {
       float o[4];
@@ -374,87 +424,94 @@ contract_adj_bf16_kernel(const __bf16 *__restrict__ khi, const __bf16 *__restric
   }
 }
 
-template <typename T>
-hipError_t launch_plain(const ctof_kernel_s *k, bool adjoint, const void *in, void *out,
-                        hipStream_t st) {
+template <typename T, bool NT>
+hipError_t launch_plain(const ctof_kernel_s *k, bool adjoint, const CArgs &a, hipStream_t st) {
   const Dims &d = k->dims;
-  const char *kh = reinterpret_cast<const char *>(k->khat);
-  const T *vin = reinterpret_cast<const T *>(in);
-  T *vout = reinterpret_cast<T *>(out);
-  const dim3 grid((unsigned)d.nmat), block(256);
+  const dim3 grid((unsigned)(8 * ((d.nmat + 7) / 8) * a.npairs)), block(256);
   if (!adjoint) {
-    const T *K = reinterpret_cast<const T *>(kh + k->layout.fwd);
     const int kz = (d.nzp >= 64 ? 64 : d.nzp) / 4;
     switch (kz) {
-      case 4: hipLaunchKernelGGL((contract_fwd_kernel<T, 4>), grid, block, 0, st, K, vin, vout, d.h, d.p, d.nzp, d.ntp); break;
-      case 8: hipLaunchKernelGGL((contract_fwd_kernel<T, 8>), grid, block, 0, st, K, vin, vout, d.h, d.p, d.nzp, d.ntp); break;
-      case 12: hipLaunchKernelGGL((contract_fwd_kernel<T, 12>), grid, block, 0, st, K, vin, vout, d.h, d.p, d.nzp, d.ntp); break;
-      case 16: hipLaunchKernelGGL((contract_fwd_kernel<T, 16>), grid, block, 0, st, K, vin, vout, d.h, d.p, d.nzp, d.ntp); break;
+      case 4: hipLaunchKernelGGL((contract_fwd_kernel<T, 4, NT>), grid, block, 0, st, a); break;
+      case 8: hipLaunchKernelGGL((contract_fwd_kernel<T, 8, NT>), grid, block, 0, st, a); break;
+      case 12: hipLaunchKernelGGL((contract_fwd_kernel<T, 12, NT>), grid, block, 0, st, a); break;
+      case 16: hipLaunchKernelGGL((contract_fwd_kernel<T, 16, NT>), grid, block, 0, st, a); break;
       default: return hipErrorInvalidValue;
     }
   } else {
-    const T *K = reinterpret_cast<const T *>(kh + k->layout.adj);
     const int zt = d.nzp / 16;
     const size_t shm = (size_t)4 * zt * 64 * 4 * sizeof(T);
     switch (zt) {
-      case 1: hipLaunchKernelGGL((contract_adj_kernel<T, 1>), grid, block, shm, st, K, vin, vout, d.h, d.p, d.nzp, d.ntp); break;
-      case 2: hipLaunchKernelGGL((contract_adj_kernel<T, 2>), grid, block, shm, st, K, vin, vout, d.h, d.p, d.nzp, d.ntp); break;
-      case 3: hipLaunchKernelGGL((contract_adj_kernel<T, 3>), grid, block, shm, st, K, vin, vout, d.h, d.p, d.nzp, d.ntp); break;
-      case 4: hipLaunchKernelGGL((contract_adj_kernel<T, 4>), grid, block, shm, st, K, vin, vout, d.h, d.p, d.nzp, d.ntp); break;
-      case 8: hipLaunchKernelGGL((contract_adj_kernel<T, 8>), grid, block, shm, st, K, vin, vout, d.h, d.p, d.nzp, d.ntp); break;
-      case 12: hipLaunchKernelGGL((contract_adj_kernel<T, 12>), grid, block, shm, st, K, vin, vout, d.h, d.p, d.nzp, d.ntp); break;
-      case 16: hipLaunchKernelGGL((contract_adj_kernel<T, 16>), grid, block, shm, st, K, vin, vout, d.h, d.p, d.nzp, d.ntp); break;
+      case 1: hipLaunchKernelGGL((contract_adj_kernel<T, 1, NT>), grid, block, shm, st, a); break;
+      case 2: hipLaunchKernelGGL((contract_adj_kernel<T, 2, NT>), grid, block, shm, st, a); break;
+      case 3: hipLaunchKernelGGL((contract_adj_kernel<T, 3, NT>), grid, block, shm, st, a); break;
+      case 4: hipLaunchKernelGGL((contract_adj_kernel<T, 4, NT>), grid, block, shm, st, a); break;
+      case 8: hipLaunchKernelGGL((contract_adj_kernel<T, 8, NT>), grid, block, shm, st, a); break;
+      case 12: hipLaunchKernelGGL((contract_adj_kernel<T, 12, NT>), grid, block, shm, st, a); break;
+      case 16: hipLaunchKernelGGL((contract_adj_kernel<T, 16, NT>), grid, block, shm, st, a); break;
       default: return hipErrorInvalidValue;
     }
   }
   return hipGetLastError();
 }
 
-template <int KIND>
-hipError_t launch_bf16(const ctof_kernel_s *k, bool adjoint, const void *in, void *out,
-                       hipStream_t st) {
+template <int KIND, bool NT>
+hipError_t launch_bf16(const ctof_kernel_s *k, bool adjoint, const CArgs &a, hipStream_t st) {
   const Dims &d = k->dims;
-  const char *kh = reinterpret_cast<const char *>(k->khat);
-  const float *vin = reinterpret_cast<const float *>(in);
-  float *vout = reinterpret_cast<float *>(out);
-  const dim3 grid((unsigned)d.nmat), block(256);
+  const dim3 grid((unsigned)(8 * ((d.nmat + 7) / 8) * a.npairs)), block(256);
   if (!adjoint) {
-    const __bf16 *hi = reinterpret_cast<const __bf16 *>(kh + k->layout.fwd);
-    const __bf16 *lo = KIND == 2 ? reinterpret_cast<const __bf16 *>(kh + k->layout.fwd_lo) : hi;
     const int kz = (d.nzp >= 64 ? 64 : d.nzp) / 4;
     switch (kz) {
-      case 8: hipLaunchKernelGGL((contract_fwd_bf16_kernel<KIND, 8>), grid, block, 0, st, hi, lo, vin, vout, d.h, d.p, d.nzp, d.ntp); break;
-      case 16: hipLaunchKernelGGL((contract_fwd_bf16_kernel<KIND, 16>), grid, block, 0, st, hi, lo, vin, vout, d.h, d.p, d.nzp, d.ntp); break;
+      case 8: hipLaunchKernelGGL((contract_fwd_bf16_kernel<KIND, 8, NT>), grid, block, 0, st, a); break;
+      case 16: hipLaunchKernelGGL((contract_fwd_bf16_kernel<KIND, 16, NT>), grid, block, 0, st, a); break;
       default: return hipErrorInvalidValue;
     }
   } else {
-    const __bf16 *hi = reinterpret_cast<const __bf16 *>(kh + k->layout.adj);
-    const __bf16 *lo = KIND == 2 ? reinterpret_cast<const __bf16 *>(kh + k->layout.adj_lo) : hi;
     const int zt = d.nzp / 16;
     const size_t shm = (size_t)4 * zt * 64 * 4 * sizeof(float);
     switch (zt) {
-      case 2: hipLaunchKernelGGL((contract_adj_bf16_kernel<KIND, 2>), grid, block, shm, st, hi, lo, vin, vout, d.h, d.p, d.nzp, d.ntp); break;
-      case 4: hipLaunchKernelGGL((contract_adj_bf16_kernel<KIND, 4>), grid, block, shm, st, hi, lo, vin, vout, d.h, d.p, d.nzp, d.ntp); break;
-      case 8: hipLaunchKernelGGL((contract_adj_bf16_kernel<KIND, 8>), grid, block, shm, st, hi, lo, vin, vout, d.h, d.p, d.nzp, d.ntp); break;
-      case 12: hipLaunchKernelGGL((contract_adj_bf16_kernel<KIND, 12>), grid, block, shm, st, hi, lo, vin, vout, d.h, d.p, d.nzp, d.ntp); break;
-      case 16: hipLaunchKernelGGL((contract_adj_bf16_kernel<KIND, 16>), grid, block, shm, st, hi, lo, vin, vout, d.h, d.p, d.nzp, d.ntp); break;
+      case 2: hipLaunchKernelGGL((contract_adj_bf16_kernel<KIND, 2, NT>), grid, block, shm, st, a); break;
+      case 4: hipLaunchKernelGGL((contract_adj_bf16_kernel<KIND, 4, NT>), grid, block, shm, st, a); break;
+      case 8: hipLaunchKernelGGL((contract_adj_bf16_kernel<KIND, 8, NT>), grid, block, shm, st, a); break;
+      case 12: hipLaunchKernelGGL((contract_adj_bf16_kernel<KIND, 12, NT>), grid, block, shm, st, a); break;
+      case 16: hipLaunchKernelGGL((contract_adj_bf16_kernel<KIND, 16, NT>), grid, block, shm, st, a); break;
       default: return hipErrorInvalidValue;
     }
   }
   return hipGetLastError();
+}
+
+template <bool NT>
+hipError_t dispatch(const ctof_kernel_s *k, bool adjoint, const CArgs &a, hipStream_t st) {
+  switch (k->prec) {
+    case CTOF_FP64: return launch_plain<double, NT>(k, adjoint, a, st);
+    case CTOF_FP32: return launch_plain<float, NT>(k, adjoint, a, st);
+    case CTOF_BF16X3: return launch_bf16<2, NT>(k, adjoint, a, st);
+    case CTOF_BF16: return launch_bf16<3, NT>(k, adjoint, a, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
 
 hipError_t launch_contract(const ctof_kernel_s *k, bool adjoint, const void *in, void *out,
-                           hipStream_t st) {
-  switch (k->prec) {
-    case CTOF_FP64: return launch_plain<double>(k, adjoint, in, out, st);
-    case CTOF_FP32: return launch_plain<float>(k, adjoint, in, out, st);
-    case CTOF_BF16X3: return launch_bf16<2>(k, adjoint, in, out, st);
-    case CTOF_BF16: return launch_bf16<3>(k, adjoint, in, out, st);
-    default: return hipErrorInvalidValue;
-  }
+                           hipStream_t st, int nvol) {
+  const Dims &d = k->dims;
+  const char *kh = reinterpret_cast<const char *>(k->khat);
+  CArgs a;
+  a.khat = kh + (adjoint ? k->layout.adj : k->layout.fwd);
+  const size_t lo = adjoint ? k->layout.adj_lo : k->layout.fwd_lo;
+  a.khat_lo = (k->prec == CTOF_BF16X3) ? kh + lo : a.khat;
+  a.vin = in;
+  a.vout = out;
+  a.h = d.h;
+  a.p = d.p;
+  a.nzp = d.nzp;
+  a.ntp = d.ntp;
+  a.nmat = d.nmat;
+  a.nvol = nvol;
+  a.npairs = (nvol + 1) / 2;
+  if (a.npairs == 1) return dispatch<true>(k, adjoint, a, st);
+  return dispatch<false>(k, adjoint, a, st);
 }
 
 }  // namespace ctof

@@ -12,6 +12,7 @@ namespace ctof {
 constexpr int kMaxN = 128;      // largest scan side (FFT size <= 256)
 constexpr int kMaxLayers = 256; // layer depths travel as a kernel argument
 constexpr int kMinP = 16;       // smallest FFT size used
+constexpr int kMaxVol = 64;     // volumes of one shape class per batched launch
 
 inline size_t round_up(size_t v, size_t m) { return (v + m - 1) / m * m; }
 
@@ -88,6 +89,7 @@ struct ctof_kernel_s {
   ctof::TabGeom geom;
   void *khat;                 // caller-owned device buffer
   ctof::KhatLayout layout;
+  int bb_t, bb_z;             // FFT planes per block on the bin / layer side (0 = rule)
 };
 
 namespace ctof {
@@ -110,7 +112,7 @@ hipError_t launch_pack(const Dims &d, ctof_precision prec, const double *k64, vo
 //   forward: in [h+1][n][2][B] (rows >= n are zero) -> out [h+1][p][2][B]
 template <typename T>
 hipError_t launch_col_pass(const Dims &d, int B, bool inverse, const T *in, T *out,
-                           hipStream_t st);
+                           hipStream_t st, int ppv = 0, int bb = 0);
 
 enum RowOp : int {
   ROW_SPEC_TO_SPATIAL = 0,   // c2r -> crop -> store spatial (forward/adjoint output)
@@ -125,27 +127,39 @@ enum RowOp : int {
 
 struct RowArgs {
   int op;
-  int B;            // batch stride of spectra (ntp or nzp)
-  int nplanes;      // real planes (nt or nz); planes beyond read as zero
+  int B;            // plane-axis length of the spectra (nvol * ppv)
+  int ppv;          // spectrum planes per volume (ntp or nzp)
+  int nplanes;      // real planes per volume (nt or nz); the rest read as zero
+  int nvol;         // volumes (1 for the single-volume entry points)
+  int bb;           // planes per block (0 = default rule)
   const void *spec_in;   // [h+1][n][2][B]
   void *spec_out;        // [h+1][n][2][B] (may alias spec_in)
-  const void *sp_in;     // spatial input [planes][n][n] (d, y, v, ...)
-  void *sp_out;          // spatial output [planes][n][n]
-  void *sp_aux;          // second spatial buffer (mu for FISTA)
+  const void *sp_in[kMaxVol];   // per volume spatial input [planes][n][n] (d, y, v, ...)
+  void *sp_out[kMaxVol];        // per volume spatial output
+  void *sp_aux[kMaxVol];        // per volume second spatial buffer (mu for FISTA)
   double *partials;      // per-block FP64 partials (2 per block)
+  size_t part_stride;    // doubles per iteration when iter_ctr is set
+  const int *iter_ctr;   // device iteration counter: selects partials slot and beta
+  const double *beta_tab;  // device FISTA weights, indexed by *iter_ctr (or NULL: beta)
+  const int *active;     // per volume: 0 freezes the volume (NULL: all active)
   const double *scalar;  // device scalar (ROW_SCALE_TO_SPEC: |w|^2)
   double tau, lambda, beta;
 };
 
 template <typename T>
 hipError_t launch_row_pass(const Dims &d, const RowArgs &a, hipStream_t st);
-int row_pass_blocks(const Dims &d, int B, bool fp64);
+// Blocks of a row pass over B planes with ppv planes per volume and an
+// optional planes-per-block override (0 = default rule).
+int row_pass_blocks(const Dims &d, int B, int ppv, bool fp64, int bb = 0);
+int batch_block(const Dims &d, int B, int ppv, bool fp64, int bb = 0);
 
 // ---- contraction (contract.hip) ---------------------------------------------
 // forward:  out[f][re/im][t] = sum_z K_s(f)[t][z] in[f][re/im][z]
 // adjoint:  out[f][re/im][z] = sum_t K_s(f)[t][z] in[f][re/im][t]
+// nvol volumes of one shape class share the spectrum; their planes are
+// interleaved per frequency as [f][re/im][vol][plane].
 hipError_t launch_contract(const ctof_kernel_s *k, bool adjoint, const void *in, void *out,
-                           hipStream_t st);
+                           hipStream_t st, int nvol = 1);
 
 // ---- reductions and small kernels (solver.hip) --------------------------------
 // sums[j] = sum_i partials[i*stride + j] for j < count, over nrows rows (FP64,
@@ -153,8 +167,17 @@ hipError_t launch_contract(const ctof_kernel_s *k, bool adjoint, const void *in,
 hipError_t launch_reduce_rows(const double *partials, int nrows, int stride, int count,
                               double *sums, hipStream_t st);
 hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st);
-hipError_t launch_history_k(const double *partials, int iters, int nblk_t, int nblk_z, double tau,
-                            const double *g0sq, double *hist, double *last, hipStream_t st);
+// Per iteration (iters rows of `stride` doubles) and volume: hist[(it*nvol+v)*2] =
+// sum of the volume's bin-side partials (data fit), [..+1] = sqrt(sum of its
+// layer-side partials) / (tau * sqrt(g0sq[v])) (gradient-mapping ratio).  The
+// blocks of volume v are the v-th of nvol equal contiguous ranges.
+hipError_t launch_history(const double *partials, int iters, int nvol, int nblk_t, int nblk_z,
+                          size_t stride, double tau, const double *g0sq, double *hist, hipStream_t st);
+// out[v] = sum of partial 0 over the v-th of nvol equal block ranges
+hipError_t launch_reduce_volumes(const double *partials, int nblk, int nvol, double *out, hipStream_t st);
+hipError_t launch_increment(int *ctr, hipStream_t st);
+hipError_t launch_beta_table(double *beta, int iters, hipStream_t st);
+hipError_t launch_fill_int(int *p, int n, int v, hipStream_t st);
 hipError_t launch_fill_value(float *p, size_t n, float v, hipStream_t st);
 hipError_t launch_fill_value_f64(double *p, size_t n, double v, hipStream_t st);
 

@@ -148,12 +148,6 @@ __device__ __forceinline__ void dft_stage2_unit(const T *br, const T *bi, int ld
   dft_reg<T, R2, DIR>(zr, zi);
 }
 
-// Planes per block: 32 (128-byte runs) when that still gives enough blocks to
-// fill the chip, else 16; FP64 always 16.
-inline int batch_block(const Dims &d, int B, bool fp64) {
-  if (fp64 || (B % 32) != 0) return 16;
-  return ((d.h + 1) * (B / 32) >= 1024) ? 32 : 16;
-}
 
 template <int P>
 struct Fac {
@@ -288,6 +282,12 @@ row_pass_kernel(int n, RowArgs a) {
   const int b0 = blockIdx.y * BB;
   const int B = a.B;
   const int tid = threadIdx.x;
+  // a block's planes all belong to one volume (BB divides the planes per volume)
+  const int vol = b0 / a.ppv;
+  const int pb0 = b0 - vol * a.ppv;
+  const bool vol_on = vol < a.nvol;
+  const bool frozen = a.active != nullptr && vol_on && a.active[vol] == 0;
+  const int it = a.iter_ctr ? *a.iter_ctr : 0;
   const bool spec_in = (op != ROW_SPATIAL_TO_SPEC) && (op != ROW_SCALE_TO_SPEC);
   const bool spec_out = (op == ROW_SPATIAL_TO_SPEC) || (op == ROW_SCALE_TO_SPEC) ||
                         (op == ROW_RESIDUAL) || (op == ROW_PASS) || (op == ROW_FISTA);
@@ -329,16 +329,17 @@ row_pass_kernel(int n, RowArgs a) {
   // pointwise step on the cropped real row x[j], j < n (in place: the value
   // x[j] lives in the slot that receives r[j])
   double acc0 = 0.0, acc1 = 0.0;
-  const T tau = (T)a.tau, lam = (T)a.lambda, beta = (T)a.beta;
+  const T tau = (T)a.tau, lam = (T)a.lambda;
+  const T beta = a.beta_tab ? (T)a.beta_tab[it] : (T)a.beta;
   T scale = (T)1;
   if (op == ROW_SCALE_TO_SPEC) scale = (T)(1.0 / sqrt(*a.scalar));
-  const T *sp_in = reinterpret_cast<const T *>(a.sp_in);
-  T *sp_out = reinterpret_cast<T *>(a.sp_out);
-  T *sp_aux = reinterpret_cast<T *>(a.sp_aux);
+  const T *sp_in = vol_on ? reinterpret_cast<const T *>(a.sp_in[vol]) : nullptr;
+  T *sp_out = vol_on ? reinterpret_cast<T *>(a.sp_out[vol]) : nullptr;
+  T *sp_aux = vol_on ? reinterpret_cast<T *>(a.sp_aux[vol]) : nullptr;
   for (int u = tid; u < n * BB; u += NT) {
     const int j = u % n, b = u / n;
-    const int pl = b0 + b;
-    const bool valid = pl < a.nplanes;
+    const int pl = pb0 + b;
+    const bool valid = vol_on && pl < a.nplanes;
     const size_t idx = ((size_t)pl * n + i) * n + j;
     T *slot = ((j & 1) ? wi : wr) + (j >> 1) * ld + b;
     T x = (T)0;
@@ -370,7 +371,9 @@ row_pass_kernel(int n, RowArgs a) {
         }
         break;
       case ROW_FISTA:
-        if (valid) {
+        if (valid && frozen) {
+          r = sp_in[idx];  // converged volume: keep mu and y, re-emit y's spectrum
+        } else if (valid) {
           const T yk = sp_in[idx];
           const T mprev = sp_aux[idx];
           T mu = yk - tau * (x + lam * yk);
@@ -427,8 +430,9 @@ row_pass_kernel(int n, RowArgs a) {
     }
     if (tid == 0) {
       const size_t blk = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
-      a.partials[2 * blk] = red[0];
-      a.partials[2 * blk + 1] = red[NT];
+      double *part = a.partials + (a.iter_ctr ? (size_t)it * a.part_stride : 0);
+      part[2 * blk] = red[0];
+      part[2 * blk + 1] = red[NT];
     }
   }
   if (!spec_out) return;
@@ -477,8 +481,10 @@ hipError_t col_dispatch_bb(const Dims &d, int B, bool inverse, const T *in, T *o
 }
 
 template <typename T, int P>
-hipError_t col_dispatch(const Dims &d, int B, bool inverse, const T *in, T *out, hipStream_t st) {
-  if (batch_block(d, B, sizeof(T) == 8) == 32) return col_dispatch_bb<T, P, 32>(d, B, inverse, in, out, st);
+hipError_t col_dispatch(const Dims &d, int B, bool inverse, const T *in, T *out, hipStream_t st,
+                        int ppv, int bb) {
+  if (batch_block(d, B, ppv ? ppv : B, sizeof(T) == 8, bb) == 32)
+    return col_dispatch_bb<T, P, 32>(d, B, inverse, in, out, st);
   return col_dispatch_bb<T, P, 16>(d, B, inverse, in, out, st);
 }
 
@@ -491,7 +497,7 @@ hipError_t row_dispatch_bb(const Dims &d, const RowArgs &a, hipStream_t st) {
 
 template <typename T, int P>
 hipError_t row_dispatch(const Dims &d, const RowArgs &a, hipStream_t st) {
-  if (batch_block(d, a.B, sizeof(T) == 8) == 32) return row_dispatch_bb<T, P, 32>(d, a, st);
+  if (batch_block(d, a.B, a.ppv, sizeof(T) == 8, a.bb) == 32) return row_dispatch_bb<T, P, 32>(d, a, st);
   return row_dispatch_bb<T, P, 16>(d, a, st);
 }
 
@@ -499,13 +505,13 @@ hipError_t row_dispatch(const Dims &d, const RowArgs &a, hipStream_t st) {
 
 template <typename T>
 hipError_t launch_col_pass(const Dims &d, int B, bool inverse, const T *in, T *out,
-                           hipStream_t st) {
+                           hipStream_t st, int ppv, int bb) {
   switch (d.p) {
-    case 16: return col_dispatch<T, 16>(d, B, inverse, in, out, st);
-    case 32: return col_dispatch<T, 32>(d, B, inverse, in, out, st);
-    case 64: return col_dispatch<T, 64>(d, B, inverse, in, out, st);
-    case 128: return col_dispatch<T, 128>(d, B, inverse, in, out, st);
-    case 256: return col_dispatch<T, 256>(d, B, inverse, in, out, st);
+    case 16: return col_dispatch<T, 16>(d, B, inverse, in, out, st, ppv, bb);
+    case 32: return col_dispatch<T, 32>(d, B, inverse, in, out, st, ppv, bb);
+    case 64: return col_dispatch<T, 64>(d, B, inverse, in, out, st, ppv, bb);
+    case 128: return col_dispatch<T, 128>(d, B, inverse, in, out, st, ppv, bb);
+    case 256: return col_dispatch<T, 256>(d, B, inverse, in, out, st, ppv, bb);
     default: return hipErrorInvalidValue;
   }
 }
@@ -522,10 +528,21 @@ hipError_t launch_row_pass(const Dims &d, const RowArgs &a, hipStream_t st) {
   }
 }
 
-int row_pass_blocks(const Dims &d, int B, bool fp64) { return d.n * (B / batch_block(d, B, fp64)); }
+// Planes per block: 32 (128-byte runs) when that still gives enough blocks to
+// fill the chip, else 16; FP64 always 16.  A block never straddles two
+// volumes (the choice divides the planes per volume).
+int batch_block(const Dims &d, int B, int ppv, bool fp64, int bb) {
+  if (fp64 || (B % 32) != 0 || (ppv % 32) != 0) return 16;
+  if (bb == 16 || bb == 32) return bb;
+  return ((d.h + 1) * (B / 32) >= 1024) ? 32 : 16;
+}
 
-template hipError_t launch_col_pass<float>(const Dims &, int, bool, const float *, float *, hipStream_t);
-template hipError_t launch_col_pass<double>(const Dims &, int, bool, const double *, double *, hipStream_t);
+int row_pass_blocks(const Dims &d, int B, int ppv, bool fp64, int bb) {
+  return d.n * (B / batch_block(d, B, ppv, fp64, bb));
+}
+
+template hipError_t launch_col_pass<float>(const Dims &, int, bool, const float *, float *, hipStream_t, int, int);
+template hipError_t launch_col_pass<double>(const Dims &, int, bool, const double *, double *, hipStream_t, int, int);
 template hipError_t launch_row_pass<float>(const Dims &, const RowArgs &, hipStream_t);
 template hipError_t launch_row_pass<double>(const Dims &, const RowArgs &, hipStream_t);
 

@@ -34,32 +34,57 @@ reduce_rows_kernel(const double *__restrict__ partials, int nrows, int stride, i
   }
 }
 
-// Per iteration k (one block each): hist[k] = (sum of t-side partial 0,
-// sqrt(sum of z-side partial 0) * gscale), gscale = 1 / (tau * ||G(0)||).
+// Block (it, v): data fit and gradient-mapping ratio of volume v at iteration it.
 __global__ void __launch_bounds__(256)
-history_kernel(const double *__restrict__ partials, int nblk_t, int nblk_z, double tau,
-               const double *__restrict__ g0sq, double *__restrict__ hist, double *__restrict__ last,
-               int iters) {
+history_kernel(const double *__restrict__ partials, int nvol, int nblk_t, int nblk_z, size_t stride,
+               double tau, const double *__restrict__ g0sq, double *__restrict__ hist) {
   __shared__ double red[256];
-  const int k = blockIdx.x;
-  const size_t stride = 2 * (size_t)(nblk_t + nblk_z);
-  const double *pt = partials + (size_t)k * stride;
+  const int it = blockIdx.x, v = blockIdx.y;
+  const double *pt = partials + (size_t)it * stride;
   const double *pz = pt + 2 * (size_t)nblk_t;
+  const int bt = nblk_t / nvol, bz = nblk_z / nvol;
   double a = 0.0, b = 0.0;
-  for (int i = threadIdx.x; i < nblk_t; i += blockDim.x) a += pt[2 * i];
-  for (int i = threadIdx.x; i < nblk_z; i += blockDim.x) b += pz[2 * i];
+  for (int i = threadIdx.x; i < bt; i += blockDim.x) a += pt[2 * ((size_t)v * bt + i)];
+  for (int i = threadIdx.x; i < bz; i += blockDim.x) b += pz[2 * ((size_t)v * bz + i)];
   const double fit = block_sum(a, red);
   const double gm = block_sum(b, red);
   if (threadIdx.x == 0) {
-    const double g0 = sqrt(*g0sq);
+    const double g0 = sqrt(g0sq[v]);
     const double ratio = g0 > 0.0 ? sqrt(gm) / (tau * g0) : 0.0;
-    hist[2 * (size_t)k] = fit;
-    hist[2 * (size_t)k + 1] = ratio;
-    if (k == iters - 1 && last) {
-      last[0] = fit;
-      last[1] = ratio;
-    }
+    hist[2 * ((size_t)it * nvol + v)] = fit;
+    hist[2 * ((size_t)it * nvol + v) + 1] = ratio;
   }
+}
+
+__global__ void __launch_bounds__(256)
+reduce_volumes_kernel(const double *__restrict__ partials, int nblk, int nvol, double *__restrict__ out) {
+  __shared__ double red[256];
+  const int v = blockIdx.x;
+  const int per = nblk / nvol;
+  double a = 0.0;
+  for (int i = threadIdx.x; i < per; i += blockDim.x) a += partials[2 * ((size_t)v * per + i)];
+  const double tot = block_sum(a, red);
+  if (threadIdx.x == 0) out[v] = tot;
+}
+
+__global__ void increment_kernel(int *ctr) {
+  if (threadIdx.x == 0) *ctr += 1;
+}
+
+// beta_k = (t_k - 1) / t_{k+1}, t_1 = 1, t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2
+__global__ void beta_table_kernel(double *beta, int iters) {
+  if (threadIdx.x != 0) return;
+  double t = 1.0;
+  for (int k = 0; k < iters; ++k) {
+    const double tn = (1.0 + sqrt(1.0 + 4.0 * t * t)) / 2.0;
+    beta[k] = (t - 1.0) / tn;
+    t = tn;
+  }
+}
+
+__global__ void fill_int_kernel(int *p, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
 }
 
 __global__ void fill_zero_kernel(uint4 *__restrict__ p, size_t n16, unsigned char *tail, size_t ntail) {
@@ -83,10 +108,32 @@ hipError_t launch_reduce_rows(const double *partials, int nrows, int stride, int
   return hipGetLastError();
 }
 
-hipError_t launch_history_k(const double *partials, int iters, int nblk_t, int nblk_z, double tau,
-                            const double *g0sq, double *hist, double *last, hipStream_t st) {
-  hipLaunchKernelGGL(history_kernel, dim3((unsigned)iters), dim3(256), 0, st, partials, nblk_t,
-                     nblk_z, tau, g0sq, hist, last, iters);
+hipError_t launch_history(const double *partials, int iters, int nvol, int nblk_t, int nblk_z,
+                          size_t stride, double tau, const double *g0sq, double *hist, hipStream_t st) {
+  if (iters <= 0) return hipSuccess;
+  hipLaunchKernelGGL(history_kernel, dim3((unsigned)iters, (unsigned)nvol), dim3(256), 0, st, partials,
+                     nvol, nblk_t, nblk_z, stride, tau, g0sq, hist);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_volumes(const double *partials, int nblk, int nvol, double *out, hipStream_t st) {
+  hipLaunchKernelGGL(reduce_volumes_kernel, dim3((unsigned)nvol), dim3(256), 0, st, partials, nblk, nvol, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_increment(int *ctr, hipStream_t st) {
+  hipLaunchKernelGGL(increment_kernel, dim3(1), dim3(64), 0, st, ctr);
+  return hipGetLastError();
+}
+
+hipError_t launch_beta_table(double *beta, int iters, hipStream_t st) {
+  hipLaunchKernelGGL(beta_table_kernel, dim3(1), dim3(64), 0, st, beta, iters);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int *p, int n, int v, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_int_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
   return hipGetLastError();
 }
 

@@ -24,7 +24,9 @@ STATUS = {0: "CTOF_OK", -1: "CTOF_EINVAL", -2: "CTOF_ENOMEM", -3: "CTOF_EHIP",
 
 EXPORTS = ("ctof_kernel_bytes", "ctof_kernel_tabulate", "ctof_kernel_tabulate_quadrant",
            "ctof_kernel_free", "ctof_kernel_info", "ctof_workspace_bytes", "ctof_forward",
-           "ctof_adjoint", "ctof_reconstruct", "ctof_last_error")
+           "ctof_adjoint", "ctof_reconstruct", "ctof_workspace_bytes_batched",
+           "ctof_reconstruct_batched", "ctof_kernel_set_tuning", "ctof_kernel_get_tuning",
+           "ctof_tune_workspace_bytes", "ctof_tune", "ctof_last_error")
 
 
 class CtofError(RuntimeError):
@@ -83,6 +85,15 @@ def lib() -> ctypes.CDLL:
         L.ctof_adjoint.argtypes = [vp, vp, vp, vp, sz, vp]
         L.ctof_reconstruct.argtypes = [vp, vp, vp, ctypes.POINTER(_SolverOpts),
                                        ctypes.POINTER(_SolverReport), vp, sz, vp]
+        kp = ctypes.POINTER(vp)
+        L.ctof_workspace_bytes_batched.argtypes = [i32, kp, i32, ctypes.POINTER(sz)]
+        L.ctof_reconstruct_batched.argtypes = [i32, kp, kp, kp, ctypes.POINTER(_SolverOpts),
+                                               ctypes.POINTER(_SolverReport), vp, sz, vp]
+        L.ctof_kernel_set_tuning.argtypes = [vp, i32, i32]
+        L.ctof_kernel_get_tuning.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.ctof_tune_workspace_bytes.argtypes = [vp, i32, ctypes.POINTER(sz)]
+        L.ctof_tune.argtypes = [vp, i32, i32, vp, sz, vp, ctypes.POINTER(ctypes.c_float),
+                                ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.ctof_last_error.argtypes = []
         L.ctof_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -290,3 +301,93 @@ def reconstruct(k: Kernel, d, mu=None, max_iter: int = 200, lam: float = -1.0,
     if hist is not None:
         hist = hist[: rep.iters]
     return mu, report, hist
+
+
+def _report(rep) -> Report:
+    return Report(rep.iters, rep.status, rep.datafit0, rep.datafit, rep.gmap_ratio,
+                  rep.lipschitz, rep.lambda_, rep.lipschitz_a, rep.gmap0, rep.ms_contract_fwd,
+                  rep.ms_fft_t, rep.ms_contract_adj, rep.ms_fft_z, rep.ms_loop)
+
+
+def reconstruct_batched(kernels, ds, mus=None, max_iter: int = 200, lam: float = -1.0,
+                        lipschitz: float = 0.0, power_iters: int = 50, rel_tol: float = 0.0,
+                        check_every: int = 10, warm_start: bool = False, stream=None):
+    """FISTA for many scans at once; scans sharing a Kernel object form one
+    shape class.  Returns (list of mu, list of Report)."""
+    torch = _torch()
+    n = len(ds)
+    if len(kernels) != n:
+        raise ValueError("one kernel per scan")
+    if mus is None:
+        mus = [None] * n
+        warm_start = False
+    outs = []
+    for k, d, mu in zip(kernels, ds, mus):
+        i = k.info
+        _contig(d, _dtype(k.precision), (i.nt, i.n, i.n))
+        if mu is None:
+            mu = torch.empty((i.nz, i.n, i.n), dtype=d.dtype, device=d.device)
+        outs.append(_contig(mu, d.dtype, (i.nz, i.n, i.n)))
+    handles = (ctypes.c_void_p * n)(*[k.handle.value for k in kernels])
+    dptr = (ctypes.c_void_p * n)(*[d.data_ptr() for d in ds])
+    mptr = (ctypes.c_void_p * n)(*[m.data_ptr() for m in outs])
+    nb = ctypes.c_size_t()
+    _check(lib().ctof_workspace_bytes_batched(n, handles, int(max_iter), ctypes.byref(nb)))
+    ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=ds[0].device)
+    opts = _SolverOpts(int(max_iter), float(lam), float(lipschitz), int(power_iters),
+                       float(rel_tol), int(check_every), int(bool(warm_start)), None, 0)
+    reps = (_SolverReport * n)()
+    _check(lib().ctof_reconstruct_batched(n, handles, dptr, mptr, ctypes.byref(opts), reps,
+                                          ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
+    return outs, [_report(r) for r in reps]
+
+
+def set_tuning(k: Kernel, bb_t: int, bb_z: int) -> None:
+    _check(lib().ctof_kernel_set_tuning(k.handle, int(bb_t), int(bb_z)))
+    k._ws = {}
+
+
+def get_tuning(k: Kernel) -> tuple:
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().ctof_kernel_get_tuning(k.handle, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def tune(k: Kernel, nvol: int = 1, iters: int = 5, cache: Optional[str] = None, stream=None):
+    """Pick the FFT planes-per-block of a handle by timing, with a JSON cache.
+
+    The cache (default: $CTOF_TUNE_CACHE, else no cache) maps
+    "arch|n|nz|nt|precision|nvol" to the chosen (bb_t, bb_z) and the timings.
+    Returns (bb_t, bb_z, timings_ms or None when taken from the cache).
+    """
+    import json
+    torch = _torch()
+    cache = cache if cache is not None else os.environ.get("CTOF_TUNE_CACHE")
+    i = k.info
+    dev = k.khat.device
+    arch = torch.cuda.get_device_properties(dev).gcnArchName.split(":")[0]
+    key = f"{arch}|{i.n}|{i.nz}|{i.nt}|{i.precision}|{int(nvol)}"
+    table = {}
+    if cache and os.path.exists(cache):
+        with open(cache) as f:
+            table = json.load(f)
+        if key in table:
+            bt, bz = table[key]["bb"]
+            set_tuning(k, bt, bz)
+            return bt, bz, None
+    nb = ctypes.c_size_t()
+    _check(lib().ctof_tune_workspace_bytes(k.handle, int(nvol), ctypes.byref(nb)))
+    ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=dev)
+    ms = (ctypes.c_float * 4)()
+    bt, bz = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().ctof_tune(k.handle, int(nvol), int(iters), ws.data_ptr(), ws.numel(),
+                           _stream_ptr(stream), ms, ctypes.byref(bt), ctypes.byref(bz)))
+    k._ws = {}
+    times = [float(v) for v in ms]
+    if cache:
+        table[key] = {"bb": [bt.value, bz.value], "ms": times}
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+        os.replace(tmp, cache)
+    return bt.value, bz.value, times

@@ -16,7 +16,8 @@ from oracle import operator as oop
 from oracle import solver as osolver
 from synth import noise, phantoms, workloads
 from synth.workloads import Geometry, even_layers
-from tests.gpu_common import matrix_index, rel_l2, to_np, unpack_forward_fragments
+from tests.gpu_common import (matrix_index, rel_l2, sampled_adjoint, sampled_forward, to_np,
+                              unpack_forward_fragments)
 
 pytestmark = pytest.mark.gpu
 
@@ -270,16 +271,6 @@ def test_reconstruct_warm_start_from_solution():
 
 
 # -- full workload size: sampled outputs the oracle computes one by one ---------
-def _kernel_curves(g, z_idx, keys):
-    """dV * bin integrals for layer z_idx at squared offsets `keys` (oracle)."""
-    from oracle import physics
-    o = okernel.optics_of(g)
-    rho = g.pitch_mm * np.sqrt(np.asarray(keys, dtype=np.float64))
-    return okernel.voxel_volume(g) * physics.kernel_bins(rho, float(g.z_mm[z_idx]),
-                                                         okernel.time_edges(g), o,
-                                                         okernel.r_min(g))
-
-
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_full_size_forward_sampled(prec):
     """Full workload shape; the oracle sums the support voxels' kernels for
@@ -300,23 +291,12 @@ def test_full_size_forward_sampled(prec):
     cy, cx = int(np.median(ys)), int(np.median(xs))
     pix = [(int(pk[1]), int(pk[2])), (cy, cx), (0, 0), (127, 127), (cy, min(cx + 9, 127)),
            (max(cy - 20, 0), cx), (64, 3)]
-    got, ref = [], []
-    for (i, j) in pix:
-        r = np.zeros(g.nt)
-        for z in np.unique(zs):
-            sel = zs == z
-            dy = np.abs(ys[sel] - i)
-            dx = np.abs(xs[sel] - j)
-            keys = dy * dy + dx * dx
-            uk, inv = np.unique(keys, return_inverse=True)
-            curves = _kernel_curves(g, z, uk)
-            r += (curves[inv] * mu[z, ys[sel], xs[sel]][:, None]).sum(axis=0)
-        got.append(m[:, i, j])
-        ref.append(r)
-        print(f"{prec} pixel {(i, j)}: rel {rel_l2(m[:, i, j], r):.3e}")
-        if p == c.FP64 and np.abs(r).max() > 1e-6 * np.abs(m).max():
-            assert rel_l2(m[:, i, j], r) <= 1e-11
-    got, ref = np.array(got), np.array(ref)
+    ref = sampled_forward(g, mu, pix)
+    got = np.array([m[:, i, j] for (i, j) in pix])
+    for n, (i, j) in enumerate(pix):
+        print(f"{prec} pixel {(i, j)}: rel {rel_l2(got[n], ref[n]):.3e}")
+        if p == c.FP64 and np.abs(ref[n]).max() > 1e-6 * np.abs(m).max():
+            assert rel_l2(got[n], ref[n]) <= 1e-11
     tol = 1e-12 if p == c.FP64 else 1e-5
     assert rel_l2(got, ref) <= tol
     assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
@@ -337,11 +317,7 @@ def test_full_size_adjoint_sampled_fp32():
                                                         rng.integers(0, 128, 40))]
     samp += [(0, src[0][0], src[0][1]), (63, src[1][0], src[1][1])]
     got = np.array([gg[z, a, b] for z, a, b in samp])
-    ref = np.zeros(len(samp))
-    for n, (z, a, b) in enumerate(samp):
-        keys = [(i - a) ** 2 + (j - b) ** 2 for (i, j) in src]
-        curves = _kernel_curves(g, z, keys)
-        ref[n] = sum(float(curves[q] @ r[:, i, j]) for q, (i, j) in enumerate(src))
+    ref = sampled_adjoint(g, r, src, samp)
     err = rel_l2(got, ref)
     print(f"adjoint sampled rel {err:.3e}")
     assert err <= 1e-5
