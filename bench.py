@@ -95,6 +95,70 @@ def cpu_baseline(g, n_iter: int = 2):
     }
 
 
+def run_batching(args, ctof, torch, dev) -> int:
+    """64 uneven scans (N in {32..128}, Nz in {16,32,64}, 256 bins of 25 ps)
+    solved to gradient-mapping ratio <= rel_tol: plain FP32 one scan at a
+    time against batched shape classes (graph replay) in FP32 and in the
+    reduced-precision forms.  Tabulation and tuning are excluded; each
+    solver's own power iteration is included."""
+    from synth import noise, phantoms, workloads
+    scans = workloads.batching_scans(args.scans, seed=args.seed)
+    rec = dict(n_abs=(1, 4), radius=(0.5, 2.0), dmua=(0.01, 0.05), kinds=("sphere", "bar"))
+    geoms = []
+    for g, _, _ in scans:
+        if g not in geoms:
+            geoms.append(g)
+    log(f"{len(scans)} scans in {len(geoms)} shape classes")
+    precs = {"fp32": ctof.FP32, "bf16x3": ctof.BF16X3, "bf16": ctof.BF16}
+    kern = {name: {g: ctof.tabulate(g, p) for g in geoms} for name, p in precs.items()}
+    torch.cuda.synchronize()
+    ds = []
+    for g, seed, peak in scans:
+        mu = phantoms.phantom(g, seed, **rec)
+        m = ctof.forward(kern["fp32"][g], torch.tensor(mu, dtype=torch.float32, device=dev))
+        d = noise.poisson_histogram(m.double().cpu().numpy(), peak, seed + 7)
+        ds.append(torch.tensor(d, dtype=torch.float32, device=dev))
+    cache = os.path.join(ROOT, "gpurun_out", "tune_cache.json") if os.path.isdir(
+        os.path.join(ROOT, "gpurun_out")) else None
+    counts = {}
+    for g, _, _ in scans:
+        counts[g] = counts.get(g, 0) + 1
+    for name in precs:
+        for g in geoms:
+            ctof.tune(kern[name][g], nvol=counts[g], iters=3, cache=cache)
+    maxit = 3000
+    out = {"workload": (f"batching: {len(scans)} scans, N in {{32,48,64,96,128}}, Nz in {{16,32,64}} "
+                        f"over 1-20 mm, 256 bins of 25 ps, solved to gradient-mapping ratio "
+                        f"<= {args.rel_tol:g}"),
+           "classes": len(geoms), "rel_tol": args.rel_tol}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters_plain = []
+    for (g, _, _), d in zip(scans, ds):
+        _, rep, _ = ctof.reconstruct(kern["fp32"][g], d, max_iter=maxit, rel_tol=args.rel_tol,
+                                     check_every=10)
+        iters_plain.append(rep.iters)
+    torch.cuda.synchronize()
+    out["plain_fp32_s"] = time.perf_counter() - t0
+    out["plain_iters_mean"] = float(sum(iters_plain)) / len(iters_plain)
+    srt = sorted(iters_plain)
+    out["plain_iters_min_median_max"] = [srt[0], srt[len(srt) // 2], srt[-1]]
+    log(f"plain FP32 sequential: {out['plain_fp32_s']:.3f}s, mean iterations {out['plain_iters_mean']:.1f}")
+    for name in precs:
+        ks = [kern[name][g] for g, _, _ in scans]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, reps = ctof.reconstruct_batched(ks, ds, max_iter=maxit, rel_tol=args.rel_tol, check_every=10)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[f"batched_{name}_s"] = dt
+        out[f"batched_{name}_iters_mean"] = float(sum(r.iters for r in reps)) / len(reps)
+        out[f"speedup_{name}"] = out["plain_fp32_s"] / dt
+        log(f"batched {name}: {dt:.3f}s ({out['plain_fp32_s'] / dt:.2f}x)")
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +169,11 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--workload", default="precision", choices=["precision", "batching"],
+                    help="precision: the iteration-rate metric (default); batching: 64 uneven "
+                         "scans solved to gradient-mapping ratio 1e-3, plain vs batched")
+    ap.add_argument("--scans", type=int, default=64)
+    ap.add_argument("--rel-tol", type=float, default=1e-3)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -134,6 +203,8 @@ def main() -> int:
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": nbytes, "copies": 3}), flush=True)
         return 0
+    if args.workload == "batching":
+        return run_batching(args, ctof, torch, dev)
     prec = ctof.PRECISIONS[args.precision]
     dtype = torch.float64 if prec == ctof.FP64 else torch.float32
 

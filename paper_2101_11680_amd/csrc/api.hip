@@ -220,6 +220,7 @@ struct Engine {
   char *ws;
   ClassWs L;
   hipStream_t st;
+  const int *live = nullptr;  // per-volume flags honoured by every launch (batched solves)
 
   const ctof::Dims &dm() const { return k->dims; }
   T *yhat() const { return reinterpret_cast<T *>(ws + L.yhat); }
@@ -255,16 +256,16 @@ struct Engine {
   hipError_t run_row(const ctof::RowArgs &a) const { return ctof::launch_row_pass<T>(dm(), a, st); }
   // t side: inverse mhat -> xt, forward xt -> mhat;  z side: inverse yhat -> xz, forward xz -> yhat
   hipError_t col_t(bool inverse) const {
-    return inverse ? ctof::launch_col_pass<T>(dm(), Bt(), true, mhat(), xt(), st, dm().ntp, k->bb_t)
-                   : ctof::launch_col_pass<T>(dm(), Bt(), false, xt(), mhat(), st, dm().ntp, k->bb_t);
+    return inverse ? ctof::launch_col_pass<T>(dm(), Bt(), true, mhat(), xt(), st, dm().ntp, k->bb_t, live)
+                   : ctof::launch_col_pass<T>(dm(), Bt(), false, xt(), mhat(), st, dm().ntp, k->bb_t, live);
   }
   hipError_t col_z(bool inverse) const {
-    return inverse ? ctof::launch_col_pass<T>(dm(), Bz(), true, yhat(), xz(), st, dm().nzp, k->bb_z)
-                   : ctof::launch_col_pass<T>(dm(), Bz(), false, xz(), yhat(), st, dm().nzp, k->bb_z);
+    return inverse ? ctof::launch_col_pass<T>(dm(), Bz(), true, yhat(), xz(), st, dm().nzp, k->bb_z, live)
+                   : ctof::launch_col_pass<T>(dm(), Bz(), false, xz(), yhat(), st, dm().nzp, k->bb_z, live);
   }
   hipError_t contract(bool adjoint) const {
-    return adjoint ? ctof::launch_contract(k, true, mhat(), yhat(), st, nvol)
-                   : ctof::launch_contract(k, false, yhat(), mhat(), st, nvol);
+    return adjoint ? ctof::launch_contract(k, true, mhat(), yhat(), st, nvol, live)
+                   : ctof::launch_contract(k, false, yhat(), mhat(), st, nvol, live);
   }
   // spatial volume(s) -> yhat
   hipError_t mu_to_spec(const ctof::RowArgs &a) const {
@@ -389,6 +390,7 @@ ctof_status enqueue_iteration(const Engine<T> &E, const void *const *d, void *co
   if (by_counter) {
     a.iter_ctr = E.ctr();
     a.part_stride = E.L.part_stride;
+    a.active = E.live;
   }
   HIP_TRY(E.run_row(a));
   HIP_TRY(E.col_t(false));
@@ -408,7 +410,7 @@ ctof_status enqueue_iteration(const Engine<T> &E, const void *const *d, void *co
     b.iter_ctr = E.ctr();
     b.part_stride = E.L.part_stride;
     b.beta_tab = E.beta();
-    b.active = E.active();
+    b.active = E.live;
   }
   HIP_TRY(E.run_row(b));
   HIP_TRY(E.col_z(false));
@@ -613,8 +615,12 @@ std::vector<ClassPlan> plan_classes(int nscan, const ctof_kernel *ks, int max_it
   return cls;
 }
 
+// Internal streams and events for graph capture; destroyed on every exit.
+constexpr int kBranches = 4;
 struct StreamGuard {
   hipStream_t s = nullptr;
+  hipStream_t br[kBranches] = {};
+  hipEvent_t fork = nullptr, join[kBranches] = {};
   hipGraph_t g = nullptr;
   hipGraphExec_t x = nullptr;
   void reset_graph() {
@@ -625,6 +631,11 @@ struct StreamGuard {
   }
   ~StreamGuard() {
     reset_graph();
+    for (int b = 0; b < kBranches; ++b) {
+      if (join[b]) (void)hipEventDestroy(join[b]);
+      if (br[b]) (void)hipStreamDestroy(br[b]);
+    }
+    if (fork) (void)hipEventDestroy(fork);
     if (s) (void)hipStreamDestroy(s);
   }
 };
@@ -685,6 +696,11 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
   const int chunk = std::max(1, std::min(opt->rel_tol > 0 ? opt->check_every : K, 50));
   StreamGuard sg;
   HIP_TRY(hipStreamCreateWithFlags(&sg.s, hipStreamNonBlocking));
+  for (int b = 0; b < kBranches; ++b) {
+    HIP_TRY(hipStreamCreateWithFlags(&sg.br[b], hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&sg.join[b], hipEventDisableTiming));
+  }
+  HIP_TRY(hipEventCreateWithFlags(&sg.fork, hipEventDisableTiming));
   bool recapture = true;
   std::vector<std::vector<int>> conv(cls.size());
   for (size_t c = 0; c < cls.size(); ++c) conv[c].assign(E[c].nvol, 0);
@@ -696,20 +712,48 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
     const int n_this = std::min(chunk, K - done);
     if (n_this == chunk) {
       if (recapture) {
+        // live classes go to up to kBranches parallel branches (greedy by
+        // estimated bytes per iteration); each branch runs its classes'
+        // iterations in order, branches join at the end of the chunk
         sg.reset_graph();
+        std::vector<int> order;
+        for (size_t c = 0; c < cls.size(); ++c)
+          if (cls[c].active) order.push_back((int)c);
+        auto cost = [&](int c) {
+          const ctof::Dims &q = cls[c].k->dims;
+          return (double)q.nmat * q.ntp * q.nzp + (double)E[c].nvol * (q.h + 1) * q.p * (q.ntp + q.nzp);
+        };
+        std::sort(order.begin(), order.end(), [&](int a, int b) { return cost(a) > cost(b); });
+        const int nb = std::min<int>(kBranches, (int)order.size());
+        std::vector<std::vector<int>> branch(nb);
+        std::vector<double> load(nb, 0.0);
+        for (int c : order) {
+          const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+          branch[b].push_back(c);
+          load[b] += cost(c);
+        }
         HIP_TRY(hipStreamBeginCapture(sg.s, hipStreamCaptureModeThreadLocal));
         ctof_status cap = CTOF_OK;
-        for (int i = 0; i < chunk && cap == CTOF_OK; ++i)
-          for (size_t c = 0; c < cls.size() && cap == CTOF_OK; ++c) {
-            if (!cls[c].active) continue;
-            Engine<T> Ec = E[c];
-            Ec.st = sg.s;
-            cap = enqueue_iteration(Ec, dv[c].data(), mv[c].data(), cls[c].tau, cls[c].lam, true, 0, 0.0);
-          }
+        hipError_t ce = hipEventRecord(sg.fork, sg.s);
+        for (int b = 0; b < nb && ce == hipSuccess; ++b) ce = hipStreamWaitEvent(sg.br[b], sg.fork, 0);
+        for (int b = 0; b < nb && ce == hipSuccess && cap == CTOF_OK; ++b)
+          for (int i = 0; i < chunk && cap == CTOF_OK; ++i)
+            for (int c : branch[b]) {
+              Engine<T> Ec = E[c];
+              Ec.st = sg.br[b];
+              Ec.live = E[c].active();
+              cap = enqueue_iteration(Ec, dv[c].data(), mv[c].data(), cls[c].tau, cls[c].lam, true, 0, 0.0);
+              if (cap != CTOF_OK) break;
+            }
+        for (int b = 0; b < nb && ce == hipSuccess; ++b) {
+          ce = hipEventRecord(sg.join[b], sg.br[b]);
+          if (ce == hipSuccess) ce = hipStreamWaitEvent(sg.s, sg.join[b], 0);
+        }
         hipGraph_t g = nullptr;
         const hipError_t ee = hipStreamEndCapture(sg.s, &g);
         sg.g = g;
         if (cap != CTOF_OK) return cap;
+        HIP_TRY(ce);
         HIP_TRY(ee);
         HIP_TRY(hipGraphInstantiate(&sg.x, sg.g, nullptr, nullptr, 0));
         recapture = false;
@@ -718,11 +762,14 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
     } else {
       for (int i = 0; i < n_this; ++i)
         for (size_t c = 0; c < cls.size(); ++c)
-          if (cls[c].active)
-            if (ctof_status s = enqueue_iteration(E[c], dv[c].data(), mv[c].data(), cls[c].tau, cls[c].lam,
+          if (cls[c].active) {
+            Engine<T> Ec = E[c];
+            Ec.live = E[c].active();
+            if (ctof_status s = enqueue_iteration(Ec, dv[c].data(), mv[c].data(), cls[c].tau, cls[c].lam,
                                                   true, 0, 0.0);
                 s != CTOF_OK)
               return s;
+          }
     }
     done += n_this;
     if (opt->rel_tol > 0 && done < K) {

@@ -150,6 +150,7 @@ struct CArgs {
   void *vout;
   int h, p, nzp, ntp, nmat;
   int nvol, npairs;
+  const int *active;  // per volume, 0 = frozen (no loads, no stores); NULL = all live
 };
 
 // Block -> (matrix, pair): block L runs on XCD L % 8; all pairs of matrix s
@@ -177,8 +178,17 @@ __device__ inline Col column_of(const CArgs &a, int s, int pair, int c) {
   k.reim = cc & 1;
   bool ok;
   k.f = matrix_slot(s, a.h, a.p, cc >> 1, ok);
-  k.on = ok && k.vol < a.nvol;
+  k.on = ok && k.vol < a.nvol && (a.active == nullptr || a.active[k.vol] != 0);
   return k;
+}
+
+// true when neither volume of the pair takes part (the block has no work)
+__device__ inline bool pair_idle(const CArgs &a, int pair) {
+  if (a.active == nullptr) return false;
+  const int v0 = 2 * pair, v1 = 2 * pair + 1;
+  const bool on0 = v0 < a.nvol && a.active[v0] != 0;
+  const bool on1 = v1 < a.nvol && a.active[v1] != 0;
+  return !on0 && !on1;
 }
 
 // ---- FP32 / FP64, forward: M = t (tiles of 16), K = z --------------------------
@@ -187,7 +197,7 @@ __global__ void __launch_bounds__(256)
 contract_fwd_kernel(CArgs a) {
   using M = Mfma<T>;
   int s, pair;
-  if (!map_block(a, s, pair)) return;
+  if (!map_block(a, s, pair) || pair_idle(a, pair)) return;
   const int w = threadIdx.x >> 6;
   const int l = threadIdx.x & 63;
   const int c = l & 15, g = l >> 4;
@@ -233,7 +243,7 @@ contract_adj_kernel(CArgs a) {
   extern __shared__ unsigned char smem_raw[];
   T *red = reinterpret_cast<T *>(smem_raw);  // [4 waves][ZT][64 lanes][4]
   int s, pair;
-  if (!map_block(a, s, pair)) return;
+  if (!map_block(a, s, pair) || pair_idle(a, pair)) return;
   const int w = threadIdx.x >> 6;
   const int l = threadIdx.x & 63;
   const int c = l & 15, g = l >> 4;
@@ -307,7 +317,7 @@ template <int KIND, int KZ, bool NT>  // KZ: z per lane group per chunk (multipl
 __global__ void __launch_bounds__(256)
 contract_fwd_bf16_kernel(CArgs a) {
   int s, pair;
-  if (!map_block(a, s, pair)) return;
+  if (!map_block(a, s, pair) || pair_idle(a, pair)) return;
   const int w = threadIdx.x >> 6;
   const int l = threadIdx.x & 63;
   const int c = l & 15, g = l >> 4;
@@ -364,7 +374,7 @@ contract_adj_bf16_kernel(CArgs a) {
   extern __shared__ unsigned char smem_raw[];
   float *red = reinterpret_cast<float *>(smem_raw);
   int s, pair;
-  if (!map_block(a, s, pair)) return;
+  if (!map_block(a, s, pair) || pair_idle(a, pair)) return;
   const int w = threadIdx.x >> 6;
   const int l = threadIdx.x & 63;
   const int c = l & 15, g = l >> 4;
@@ -494,7 +504,7 @@ hipError_t dispatch(const ctof_kernel_s *k, bool adjoint, const CArgs &a, hipStr
 }  // namespace
 
 hipError_t launch_contract(const ctof_kernel_s *k, bool adjoint, const void *in, void *out,
-                           hipStream_t st, int nvol) {
+                           hipStream_t st, int nvol, const int *active) {
   const Dims &d = k->dims;
   const char *kh = reinterpret_cast<const char *>(k->khat);
   CArgs a;
@@ -510,6 +520,7 @@ hipError_t launch_contract(const ctof_kernel_s *k, bool adjoint, const void *in,
   a.nmat = d.nmat;
   a.nvol = nvol;
   a.npairs = (nvol + 1) / 2;
+  a.active = active;
   if (a.npairs == 1) return dispatch<true>(k, adjoint, a, st);
   return dispatch<false>(k, adjoint, a, st);
 }

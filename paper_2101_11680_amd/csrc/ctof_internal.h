@@ -110,9 +110,11 @@ hipError_t launch_pack(const Dims &d, ctof_precision prec, const double *k64, vo
 // Column pass along kx for every ky of a spectrum block.
 //   inverse: in [h+1][p][2][B] -> out [h+1][n][2][B] (rows >= n dropped)
 //   forward: in [h+1][n][2][B] (rows >= n are zero) -> out [h+1][p][2][B]
+// ppv: planes per volume; active: per-volume flags, blocks of frozen (0)
+// volumes do nothing (NULL: all live)
 template <typename T>
 hipError_t launch_col_pass(const Dims &d, int B, bool inverse, const T *in, T *out,
-                           hipStream_t st, int ppv = 0, int bb = 0);
+                           hipStream_t st, int ppv = 0, int bb = 0, const int *active = nullptr);
 
 enum RowOp : int {
   ROW_SPEC_TO_SPATIAL = 0,   // c2r -> crop -> store spatial (forward/adjoint output)
@@ -141,7 +143,7 @@ struct RowArgs {
   size_t part_stride;    // doubles per iteration when iter_ctr is set
   const int *iter_ctr;   // device iteration counter: selects partials slot and beta
   const double *beta_tab;  // device FISTA weights, indexed by *iter_ctr (or NULL: beta)
-  const int *active;     // per volume: 0 freezes the volume (NULL: all active)
+  const int *active;     // per volume: blocks of a frozen (0) volume do nothing (NULL: all live)
   const double *scalar;  // device scalar (ROW_SCALE_TO_SPEC: |w|^2)
   double tau, lambda, beta;
 };
@@ -159,7 +161,7 @@ int batch_block(const Dims &d, int B, int ppv, bool fp64, int bb = 0);
 // nvol volumes of one shape class share the spectrum; their planes are
 // interleaved per frequency as [f][re/im][vol][plane].
 hipError_t launch_contract(const ctof_kernel_s *k, bool adjoint, const void *in, void *out,
-                           hipStream_t st, int nvol = 1);
+                           hipStream_t st, int nvol = 1, const int *active = nullptr);
 
 // ---- reductions and small kernels (solver.hip) --------------------------------
 // sums[j] = sum_i partials[i*stride + j] for j < count, over nrows rows (FP64,

@@ -163,7 +163,8 @@ struct Fac {
 // the imaginary parts, to keep the block's LDS small.
 template <typename T, int P, int BB, bool INV>
 __global__ void __launch_bounds__(512)
-col_pass_kernel(int n, int B, const T *__restrict__ in, T *__restrict__ out) {
+col_pass_kernel(int n, int B, const T *__restrict__ in, T *__restrict__ out, int ppv,
+                const int *__restrict__ active) {
   constexpr int R1 = Fac<P>::R1, R2 = Fac<P>::R2;
   constexpr int DIR = INV ? 1 : -1;
   constexpr int ld = BB + 1;
@@ -172,6 +173,7 @@ col_pass_kernel(int n, int B, const T *__restrict__ in, T *__restrict__ out) {
   __shared__ T twc[P], tws[P];
   const int ky = blockIdx.x;
   const int b0 = blockIdx.y * BB;
+  if (active != nullptr && active[b0 / ppv] == 0) return;  // frozen volume
   const int rows_in = INV ? P : n;
   const int rows_out = INV ? n : P;
   const int tid = threadIdx.x;
@@ -286,7 +288,7 @@ row_pass_kernel(int n, RowArgs a) {
   const int vol = b0 / a.ppv;
   const int pb0 = b0 - vol * a.ppv;
   const bool vol_on = vol < a.nvol;
-  const bool frozen = a.active != nullptr && vol_on && a.active[vol] == 0;
+  if (a.active != nullptr && vol_on && a.active[vol] == 0) return;  // frozen volume
   const int it = a.iter_ctr ? *a.iter_ctr : 0;
   const bool spec_in = (op != ROW_SPATIAL_TO_SPEC) && (op != ROW_SCALE_TO_SPEC);
   const bool spec_out = (op == ROW_SPATIAL_TO_SPEC) || (op == ROW_SCALE_TO_SPEC) ||
@@ -371,9 +373,7 @@ row_pass_kernel(int n, RowArgs a) {
         }
         break;
       case ROW_FISTA:
-        if (valid && frozen) {
-          r = sp_in[idx];  // converged volume: keep mu and y, re-emit y's spectrum
-        } else if (valid) {
+        if (valid) {
           const T yk = sp_in[idx];
           const T mprev = sp_aux[idx];
           T mu = yk - tau * (x + lam * yk);
@@ -471,21 +471,22 @@ row_pass_kernel(int n, RowArgs a) {
 
 template <typename T, int P, int BB>
 hipError_t col_dispatch_bb(const Dims &d, int B, bool inverse, const T *in, T *out,
-                           hipStream_t st) {
+                           hipStream_t st, int ppv, const int *active) {
   dim3 grid((unsigned)(d.h + 1), (unsigned)(B / BB));
   if (inverse)
-    hipLaunchKernelGGL((col_pass_kernel<T, P, BB, true>), grid, dim3(512), 0, st, d.n, B, in, out);
+    hipLaunchKernelGGL((col_pass_kernel<T, P, BB, true>), grid, dim3(512), 0, st, d.n, B, in, out, ppv, active);
   else
-    hipLaunchKernelGGL((col_pass_kernel<T, P, BB, false>), grid, dim3(512), 0, st, d.n, B, in, out);
+    hipLaunchKernelGGL((col_pass_kernel<T, P, BB, false>), grid, dim3(512), 0, st, d.n, B, in, out, ppv, active);
   return hipGetLastError();
 }
 
 template <typename T, int P>
 hipError_t col_dispatch(const Dims &d, int B, bool inverse, const T *in, T *out, hipStream_t st,
-                        int ppv, int bb) {
-  if (batch_block(d, B, ppv ? ppv : B, sizeof(T) == 8, bb) == 32)
-    return col_dispatch_bb<T, P, 32>(d, B, inverse, in, out, st);
-  return col_dispatch_bb<T, P, 16>(d, B, inverse, in, out, st);
+                        int ppv, int bb, const int *active) {
+  ppv = ppv ? ppv : B;
+  if (batch_block(d, B, ppv, sizeof(T) == 8, bb) == 32)
+    return col_dispatch_bb<T, P, 32>(d, B, inverse, in, out, st, ppv, active);
+  return col_dispatch_bb<T, P, 16>(d, B, inverse, in, out, st, ppv, active);
 }
 
 template <typename T, int P, int BB>
@@ -505,13 +506,13 @@ hipError_t row_dispatch(const Dims &d, const RowArgs &a, hipStream_t st) {
 
 template <typename T>
 hipError_t launch_col_pass(const Dims &d, int B, bool inverse, const T *in, T *out,
-                           hipStream_t st, int ppv, int bb) {
+                           hipStream_t st, int ppv, int bb, const int *active) {
   switch (d.p) {
-    case 16: return col_dispatch<T, 16>(d, B, inverse, in, out, st, ppv, bb);
-    case 32: return col_dispatch<T, 32>(d, B, inverse, in, out, st, ppv, bb);
-    case 64: return col_dispatch<T, 64>(d, B, inverse, in, out, st, ppv, bb);
-    case 128: return col_dispatch<T, 128>(d, B, inverse, in, out, st, ppv, bb);
-    case 256: return col_dispatch<T, 256>(d, B, inverse, in, out, st, ppv, bb);
+    case 16: return col_dispatch<T, 16>(d, B, inverse, in, out, st, ppv, bb, active);
+    case 32: return col_dispatch<T, 32>(d, B, inverse, in, out, st, ppv, bb, active);
+    case 64: return col_dispatch<T, 64>(d, B, inverse, in, out, st, ppv, bb, active);
+    case 128: return col_dispatch<T, 128>(d, B, inverse, in, out, st, ppv, bb, active);
+    case 256: return col_dispatch<T, 256>(d, B, inverse, in, out, st, ppv, bb, active);
     default: return hipErrorInvalidValue;
   }
 }
@@ -541,8 +542,10 @@ int row_pass_blocks(const Dims &d, int B, int ppv, bool fp64, int bb) {
   return d.n * (B / batch_block(d, B, ppv, fp64, bb));
 }
 
-template hipError_t launch_col_pass<float>(const Dims &, int, bool, const float *, float *, hipStream_t, int, int);
-template hipError_t launch_col_pass<double>(const Dims &, int, bool, const double *, double *, hipStream_t, int, int);
+template hipError_t launch_col_pass<float>(const Dims &, int, bool, const float *, float *, hipStream_t, int, int,
+                                           const int *);
+template hipError_t launch_col_pass<double>(const Dims &, int, bool, const double *, double *, hipStream_t, int,
+                                            int, const int *);
 template hipError_t launch_row_pass<float>(const Dims &, const RowArgs &, hipStream_t);
 template hipError_t launch_row_pass<double>(const Dims &, const RowArgs &, hipStream_t);
 
