@@ -173,7 +173,13 @@ ctof_status ctof_adjoint(ctof_kernel k, const void *r_dev, void *g_dev, void *ws
  *                    ||y_k - mu_k|| / (tau ||max(0, A^T d)||) <= rel_tol,
  *                    checked every check_every iterations (0 = run max_iter)
  *   check_every      >= 1 when rel_tol > 0
- *   warm_start       0: mu_inout is zeroed first; 1: mu_inout is mu_0
+ *   warm_start       0: mu_inout is zeroed first; 1: mu_inout is mu_0;
+ *                    2: mu_inout is mu_0 with zero-start fallback: after the
+ *                    first iteration, a scan whose gradient-mapping ratio
+ *                    exceeds 1 (the ratio of a zero start is 1 by
+ *                    definition) restarts from mu = 0; the discarded
+ *                    iteration counts in `iters` and the restart continues
+ *                    the FISTA step-size sequence from its second term
  *   history_dev      optional device array double[max_iter][2] receiving
  *                    (1/2 ||A y_k - d||^2, gradient-mapping ratio) per
  *                    iteration; NULL for none
@@ -200,6 +206,7 @@ typedef struct {
  *   gmap_ratio  gradient-mapping ratio of the last iteration
  *   lipschitz, lambda   the L and lambda used;  lipschitz_a  L_A (0 if L given)
  *   gmap0       ||max(0, A^T d)||, the ratio's denominator
+ *   fell_back   1 if warm_start = 2 discarded the given start, else 0
  *   ms_*        with opts.timing: GPU milliseconds summed over the iterations
  *               for the forward contraction, the measurement-side FFT passes
  *               (inverse column, residual row, column), the adjoint
@@ -210,6 +217,7 @@ typedef struct {
   int32_t iters, status;
   double datafit0, datafit, gmap_ratio, lipschitz, lambda, lipschitz_a, gmap0;
   double ms_contract_fwd, ms_fft_t, ms_contract_adj, ms_fft_z, ms_loop;
+  int32_t fell_back;
 } ctof_solver_report;
 
 /*
@@ -264,6 +272,151 @@ ctof_status ctof_kernel_get_tuning(ctof_kernel k, int32_t *bb_t, int32_t *bb_z);
 ctof_status ctof_tune_workspace_bytes(ctof_kernel k, int32_t nvol, size_t *ws_bytes);
 ctof_status ctof_tune(ctof_kernel k, int32_t nvol, int32_t iters, void *ws_dev, size_t ws_bytes,
                       hipStream_t stream, float *ms, int32_t *bb_t, int32_t *bb_z);
+
+/* ===================================================================== *
+ * Learned warm start.
+ *
+ * A 3D convolutional network maps the scaled adjoint back-projection
+ * tau * A^T d of a scan to a starting volume for ctof_reconstruct
+ * (warm_start = 1).  The reconstruction problem is unchanged (section
+ * "Reconstruction Algorithm"); only its starting point is learned, and the
+ * solver's own residual decides whether the start is kept.  The entry
+ * points below are the network's layers, loss, optimiser step and the
+ * counter-based sampler of Poisson photon counts (the detector model of the
+ * section on multiplexed measurements) used to generate training data.
+ *
+ * Tensors are channels-last, [n][d][h][w][ld] rows of ld elements; a
+ * ctof_tensor names the channel slice [c0, c0 + c) of such a buffer.
+ * Activations and activation gradients are BF16 (uint16 storage), network
+ * outputs may be FP32.  For BF16 slices read by a convolution: ptr 16-byte
+ * aligned, ld and c0 multiples of 8 and c0 + roundup(c, 8) <= ld (the whole
+ * 8-channel groups of the slice are read; channels past c are ignored).
+ *
+ * Layer kinds (input grid n x d x h x w, ci -> co channels):
+ *   CTOF_CONV_K3  3x3x3 correlation, stride 1, zero padding 1 (same grid)
+ *   CTOF_CONV_DN  2x2x2, stride 2 (grid halves; d, h, w even)
+ *   CTOF_CONV_UP  2x2x2 transposed, stride 2 (grid doubles):
+ *                 y[2z+i][2y+j][2x+k][o] = sum_c W[i][j][k][o][c] x[z][y][x][c]
+ *   CTOF_CONV_K1  1x1x1
+ * Packed weights (float master copy and BF16 working copy share it), with
+ * cip = roundup(ci, 8), co_pad = roundup(co, 16), taps = 27 / 8 / 1 / 1
+ * (K3 / DN / UP / K1), kpad = roundup(taps * cip, 32):
+ *   K3, DN, K1: [co_pad][kpad], column tap * cip + ci, tap = (i*3+j)*3+k
+ *               (K3) or (i*2+j)*2+k (DN) for offsets (i, j, k) in z, y, x
+ *   UP:         [8][co_pad][kpad], leading index (i*2+j)*2+k, column ci
+ *   all other entries zero.  Biases: float [co].
+ * Supported channels: 1 <= ci <= 256; co_pad / 16 in {1, 2, 3, 4, 8}.
+ * Accumulation is FP32 everywhere; reductions over positions (weight and
+ * bias gradients, loss) are split in a fixed order (deterministic).
+ * ===================================================================== */
+typedef enum { CTOF_CONV_K3 = 0, CTOF_CONV_DN = 1, CTOF_CONV_UP = 2, CTOF_CONV_K1 = 3 } ctof_conv_kind;
+
+typedef struct {
+  int32_t kind;       /* ctof_conv_kind */
+  int32_t n, d, h, w; /* input grid, each >= 1 */
+  int32_t ci, co;     /* input / output channels */
+} ctof_conv_desc;
+
+typedef struct {
+  void *ptr;   /* device pointer to the buffer's first row */
+  int32_t ld;  /* elements per row */
+  int32_t c0;  /* first channel of the slice */
+} ctof_tensor;
+
+/* Elements of the packed weight layout (float master or BF16 copy). */
+ctof_status ctof_conv3d_weight_elems(const ctof_conv_desc *desc, size_t *elems);
+
+/*
+ * y = act(conv(x, w) + bias [+ y if accumulate]); act = ReLU if relu.
+ * x: BF16 slice of ci channels on the input grid; w: packed BF16 weights;
+ * bias: float [co] or NULL; y: slice of co channels on the output grid,
+ * float if y_fp32 else BF16 (stored rounded to nearest even).
+ */
+ctof_status ctof_conv3d_fwd(const ctof_conv_desc *desc, const ctof_tensor *x, const void *w_bf16,
+                            const float *bias, const ctof_tensor *y, int32_t y_fp32, int32_t relu,
+                            int32_t accumulate, hipStream_t stream);
+
+/*
+ * Input gradient: dx (BF16, ci channels, input grid) = conv^T(dy) [+ dx if
+ * accumulate]; dy: BF16 slice of co channels on the output grid.  Uses
+ * ws_dev (>= ctof_conv3d_bwd_data_ws_bytes) for the rearranged weights.
+ */
+ctof_status ctof_conv3d_bwd_data_ws_bytes(const ctof_conv_desc *desc, size_t *ws_bytes);
+ctof_status ctof_conv3d_bwd_data(const ctof_conv_desc *desc, const ctof_tensor *dy, const void *w_bf16,
+                                 const ctof_tensor *dx, int32_t accumulate, void *ws_dev, size_t ws_bytes,
+                                 hipStream_t stream);
+
+/*
+ * Weight and bias gradients: dw (float, packed layout, fully written, zero
+ * outside the real channels) = sum over positions of dy x~; db (float [co],
+ * or NULL) = sum of dy over output positions.  x: BF16 layer input; dy:
+ * BF16 gradient at the layer output (after the ReLU mask).
+ */
+ctof_status ctof_conv3d_bwd_weight_ws_bytes(const ctof_conv_desc *desc, size_t *ws_bytes);
+ctof_status ctof_conv3d_bwd_weight(const ctof_conv_desc *desc, const ctof_tensor *x, const ctof_tensor *dy,
+                                   float *dw_dev, float *db_dev, void *ws_dev, size_t ws_bytes,
+                                   hipStream_t stream);
+
+/* ReLU backward in place: dy[r][c] = 0 where y[r][c] <= 0 (BF16 slices, ch channels, rows rows). */
+ctof_status ctof_relu_bwd(int64_t rows, int32_t ch, const ctof_tensor *dy, const ctof_tensor *y, hipStream_t stream);
+
+/*
+ * Mean squared error of s y (s = y_scale, y = channel y.c0 of an FP32
+ * tensor) against a dense float target [n]: *loss_dev (double) =
+ * mean (s y - t)^2 and grad (BF16 slice, channel grad.c0) = d loss / d y =
+ * 2 s (s y - t) / n, or 0 where y <= 0 when relu_mask (y is then the output
+ * of a ReLU, whose backward this folds in).
+ */
+ctof_status ctof_mse_ws_bytes(int64_t n, size_t *ws_bytes);
+ctof_status ctof_mse(int64_t n, const ctof_tensor *y, float y_scale, const float *target_dev,
+                     const ctof_tensor *grad, int32_t relu_mask, double *loss_dev, void *ws_dev, size_t ws_bytes,
+                     hipStream_t stream);
+
+/*
+ * Adam (Kingma and Ba, 2015) with bias correction on n float master weights
+ * w, gradient g and moments m, v (step counts from 1); w_bf16 (or NULL)
+ * receives the updated weights rounded to BF16.
+ */
+ctof_status ctof_adam_step(int64_t n, float *w_dev, const float *g_dev, float *m_dev, float *v_dev,
+                           void *w_bf16_dev, float lr, float beta1, float beta2, float eps, int32_t step,
+                           hipStream_t stream);
+
+/* Dense float [n] -> BF16 channel out.c0 of n rows (times scale); zero_rest
+ * zeroes the row's other ld - 1 elements.  And back: out[i] = y[i][c0] * scale
+ * for an FP32 tensor y. */
+ctof_status ctof_to_channels_last(int64_t n, const float *x_dev, float scale, const ctof_tensor *out,
+                                  int32_t zero_rest, hipStream_t stream);
+ctof_status ctof_from_channels_last(int64_t n, const ctof_tensor *y, float scale, float *out_dev,
+                                    hipStream_t stream);
+
+/*
+ * Philox-4x32-10 (Salmon, Moraes, Dror and Shaw, SC 2011) with key (seed mod
+ * 2^32, seed div 2^32) and counter (i mod 2^32, i div 2^32, stream_id, 0)
+ * for i = first .. first + n - 1: out_dev[4 (i - first) + j] = word j.
+ */
+ctof_status ctof_philox4x32(uint64_t seed, uint32_t stream_id, int64_t first, int64_t n, uint32_t *out_dev,
+                            hipStream_t stream);
+
+/*
+ * Poisson counts with means lam_dev[i] (float, <= 0 gives 0) into float
+ * counts_dev[i] (exact below 2^24).  Element i draws from counters
+ * (i, stream_id, trial): for lam < 10 the inverse CDF at one uniform
+ * u = ((w0 >> 5) 2^26 + (w1 >> 6)) 2^-53 (w0, w1 = Philox words 0 and 1 of
+ * trial 0), for lam >= 10 Hoermann's transformed rejection with squeeze
+ * (1993), uniforms from words (0, 1) and (2, 3) of trial t = 0, 1, ...
+ * Decisions are taken in FP64.
+ */
+ctof_status ctof_poisson(int64_t n, const float *lam_dev, uint64_t seed, uint32_t stream_id, float *counts_dev,
+                         hipStream_t stream);
+
+/*
+ * Noisy histogram: d = Poisson(s m) / s with s = peak / max(m) (FP64), m
+ * and d float [n], not overlapping.  A histogram whose maximum is not
+ * positive gives d = 0.
+ */
+ctof_status ctof_noisy_histogram_ws_bytes(int64_t n, size_t *ws_bytes);
+ctof_status ctof_noisy_histogram(int64_t n, const float *m_dev, double peak, uint64_t seed, uint32_t stream_id,
+                                 float *d_dev, void *ws_dev, size_t ws_bytes, hipStream_t stream);
 
 const char *ctof_last_error(void);
 

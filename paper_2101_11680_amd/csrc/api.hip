@@ -23,7 +23,7 @@
 #include <string>
 #include <vector>
 
-namespace {
+namespace ctof {
 
 thread_local std::string g_err;
 
@@ -37,12 +37,13 @@ ctof_status set_error(ctof_status s, const char *fmt, ...) {
   return s;
 }
 
-#define HIP_TRY(expr)                                                                      \
-  do {                                                                                     \
-    hipError_t e_ = (expr);                                                                \
-    if (e_ != hipSuccess)                                                                  \
-      return set_error(CTOF_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));         \
-  } while (0)
+const char *last_error() { return g_err.c_str(); }
+
+}  // namespace ctof
+
+namespace {
+
+using ctof::set_error;
 
 int next_pow2(int v) {
   int p = 1;
@@ -433,6 +434,26 @@ ctof_status enqueue_start(const Engine<T> &E, void *const *mu, bool warm) {
   return CTOF_OK;
 }
 
+// Zero-start fallback: the flagged volumes restart from mu = 0 (mu and y
+// zeroed, spectrum of y recomputed for the class).
+template <typename T>
+ctof_status restart_from_zero(const Engine<T> &E, void *const *mu, const std::vector<int> &reset) {
+  const ctof::Dims &dm = E.dm();
+  const size_t vol = (size_t)dm.nz * dm.n * dm.n;
+  bool any = false;
+  for (int v = 0; v < E.nvol; ++v)
+    if (reset[v]) {
+      any = true;
+      HIP_TRY(ctof::launch_fill_zero(mu[v], vol * sizeof(T), E.st));
+      HIP_TRY(ctof::launch_fill_zero(E.y(v), vol * sizeof(T), E.st));
+    }
+  if (!any) return CTOF_OK;
+  ctof::RowArgs a = E.row(ctof::ROW_SPATIAL_TO_SPEC, false);
+  for (int v = 0; v < E.nvol; ++v) a.sp_in[v] = E.y(v);
+  HIP_TRY(E.mu_to_spec(a));
+  return CTOF_OK;
+}
+
 // 1/2 ||A mu_v - d_v||^2 per volume into out[v] (device)
 template <typename T>
 ctof_status enqueue_final_fit(const Engine<T> &E, const void *const *d, void *const *mu, double *pf,
@@ -527,6 +548,17 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
     HIP_TRY(E.col_z(false));
     HIP_TRY(mark(it, 4));
     done = it + 1;
+    if (opt->warm_start == 2 && it == 0) {
+      HIP_TRY(ctof::launch_history(E.part(), 1, 1, E.L.nblk_t, E.L.nblk_z, E.L.part_stride, tau, E.g0sq(),
+                                   scal + 5, st));
+      double h1[2];
+      HIP_TRY(hipMemcpyAsync(h1, scal + 5, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      if (!(h1[1] <= 1.0)) {
+        rep->fell_back = 1;
+        if (ctof_status s = restart_from_zero(E, mm, std::vector<int>{1}); s != CTOF_OK) return s;
+      }
+    }
     if (opt->rel_tol > 0 && (done % opt->check_every == 0) && done < K) {
       HIP_TRY(ctof::launch_history(E.part() + (size_t)it * E.L.part_stride, 1, 1, E.L.nblk_t, E.L.nblk_z,
                                    E.L.part_stride, tau, E.g0sq(), scal + 5, st));
@@ -702,9 +734,36 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
   }
   HIP_TRY(hipEventCreateWithFlags(&sg.fork, hipEventDisableTiming));
   bool recapture = true;
-  std::vector<std::vector<int>> conv(cls.size());
-  for (size_t c = 0; c < cls.size(); ++c) conv[c].assign(E[c].nvol, 0);
+  std::vector<std::vector<int>> conv(cls.size()), fell(cls.size());
+  for (size_t c = 0; c < cls.size(); ++c) {
+    conv[c].assign(E[c].nvol, 0);
+    fell[c].assign(E[c].nvol, 0);
+  }
   int done = 0;
+  if (opt->warm_start == 2) {
+    // first iteration from the given starts; a volume whose gradient-mapping
+    // ratio exceeds that of a zero start (1) restarts from zero
+    std::vector<std::vector<double>> first(cls.size());
+    for (size_t c = 0; c < cls.size(); ++c) {
+      Engine<T> Ec = E[c];
+      Ec.live = E[c].active();
+      if (ctof_status s = enqueue_iteration(Ec, dv[c].data(), mv[c].data(), cls[c].tau, cls[c].lam, true, 0, 0.0);
+          s != CTOF_OK)
+        return s;
+      const ClassWs &L = cls[c].L;
+      HIP_TRY(ctof::launch_history(E[c].part(), 1, E[c].nvol, L.nblk_t, L.nblk_z, L.part_stride, cls[c].tau,
+                                   E[c].g0sq(), E[c].hist(), st));
+      first[c].resize((size_t)E[c].nvol * 2);
+      HIP_TRY(hipMemcpyAsync(first[c].data(), E[c].hist(), first[c].size() * sizeof(double),
+                             hipMemcpyDeviceToHost, st));
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    for (size_t c = 0; c < cls.size(); ++c) {
+      for (int v = 0; v < E[c].nvol; ++v) fell[c][v] = (first[c][2 * v + 1] <= 1.0) ? 0 : 1;
+      if (ctof_status s = restart_from_zero(E[c], mv[c].data(), fell[c]); s != CTOF_OK) return s;
+    }
+    done = 1;
+  }
   while (done < K) {
     bool any = false;
     for (auto &c : cls) any = any || c.active;
@@ -837,6 +896,7 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
       r.lambda = cls[c].lam;
       r.lipschitz_a = cls[c].lip_a;
       r.gmap0 = std::sqrt(g0[c][v]);
+      r.fell_back = fell[c][v];
       r.status = CTOF_OK;
       if (!std::isfinite(r.datafit) || !std::isfinite(r.datafit0) || !std::isfinite(r.gmap_ratio)) {
         r.status = CTOF_ENONFINITE;
@@ -960,7 +1020,7 @@ KhatLayout khat_layout(const Dims &d, ctof_precision prec) {
 
 extern "C" {
 
-const char *ctof_last_error(void) { return g_err.c_str(); }
+const char *ctof_last_error(void) { return ctof::last_error(); }
 
 ctof_status ctof_kernel_bytes(const ctof_geometry *geom, ctof_precision prec, size_t *khat_bytes,
                               size_t *tab_ws_bytes) {
@@ -1097,7 +1157,7 @@ ctof_status ctof_reconstruct(ctof_kernel k, const void *d_dev, void *mu_inout_de
   if (opts->power_iters < 0) return set_error(CTOF_EINVAL, "power_iters must be >= 0");
   if (!(std::isfinite(opts->rel_tol) && opts->rel_tol >= 0)) return set_error(CTOF_EINVAL, "rel_tol must be >= 0");
   if (opts->rel_tol > 0 && opts->check_every < 1) return set_error(CTOF_EINVAL, "check_every must be >= 1");
-  if (opts->warm_start != 0 && opts->warm_start != 1) return set_error(CTOF_EINVAL, "warm_start must be 0 or 1");
+  if (opts->warm_start < 0 || opts->warm_start > 2) return set_error(CTOF_EINVAL, "warm_start must be 0, 1 or 2");
   const ClassWs o = class_ws(k, 1, opts->max_iter);
   if (ws_bytes < o.solve_total) return set_error(CTOF_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, o.solve_total);
   std::memset(report, 0, sizeof(*report));
@@ -1136,7 +1196,7 @@ ctof_status ctof_reconstruct_batched(int32_t nscan, const ctof_kernel *k, const 
     return set_error(CTOF_EINVAL, "an explicit lipschitz needs lambda_tikhonov >= 0");
   if (!(std::isfinite(opts->rel_tol) && opts->rel_tol >= 0)) return set_error(CTOF_EINVAL, "rel_tol must be >= 0");
   if (opts->rel_tol > 0 && opts->check_every < 1) return set_error(CTOF_EINVAL, "check_every must be >= 1");
-  if (opts->warm_start != 0 && opts->warm_start != 1) return set_error(CTOF_EINVAL, "warm_start must be 0 or 1");
+  if (opts->warm_start < 0 || opts->warm_start > 2) return set_error(CTOF_EINVAL, "warm_start must be 0, 1 or 2");
   if (opts->history_dev || opts->timing)
     return set_error(CTOF_EINVAL, "history_dev and timing are single-scan options");
   size_t need = 0;

@@ -1,0 +1,641 @@
+// 3D convolution layers of the learned warm start (gfx950).
+//
+// A small 3D U-Net maps the scaled adjoint back-projection of a scan to a
+// starting volume for the regularised least-squares iteration.  Activations
+// are BF16, channels-last [n][d][h][w][ld]; a tensor is a channel slice
+// [c0, c0 + c) of such a buffer, which is how skip concatenations are held
+// without copies.  Accumulation is FP32.  Four layer kinds:
+//   K3  3x3x3, stride 1, zero padding 1     (output grid = input grid)
+//   DN  2x2x2, stride 2                     (output grid = input grid / 2)
+//   UP  2x2x2 transposed, stride 2          (output grid = input grid * 2)
+//   K1  1x1x1
+// Packed weights (FP32 master and BF16 working copy share the layout):
+//   K3, DN, K1: [co_pad][kpad], column k = tap * cip + ci
+//   UP:         [8][co_pad][kpad], column k = ci
+// with cip = roundup(ci, 8), co_pad = roundup(co, 16), kpad = roundup(taps *
+// cip, 32) (taps = 27, 8, 1; 1 for UP, whose taps are the leading index);
+// entries outside the real channels are zero.
+//
+// Forward is an implicit GEMM on the matrix cores: Y[pos][co] = sum_k
+// W[co][k] X~[pos][k], X~ gathered on the fly, one 16x16x32 BF16 MFMA tile =
+// 16 output channels x 16 positions x 32 columns.  The input gradient runs the
+// same kernel with rearranged weights (K3: taps mirrored, channel roles
+// swapped; a DN layer's input gradient is an UP layer and vice versa).  The
+// weight gradient sums dY[pos][co] X~[pos][k] over positions in FP32 on the
+// matrix cores, with per-wave partial sums reduced in a fixed order.
+#include <cstdint>
+
+#include "ctof_internal.h"
+
+namespace ctof {
+
+namespace {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ v8bf load8(const __bf16 *p) {
+  const uint4 u = *reinterpret_cast<const uint4 *>(p);
+  v8bf r;
+  __builtin_memcpy(&r, &u, 16);
+  return r;
+}
+
+__device__ __forceinline__ v8bf zero8() {
+  v8bf r;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) r[i] = (__bf16)0.0f;
+  return r;
+}
+
+struct Pos {
+  int b, z, y, x;
+};
+
+__device__ __forceinline__ Pos unflatten(long long p, int d, int h, int w) {
+  Pos q;
+  q.x = (int)(p % w);
+  p /= w;
+  q.y = (int)(p % h);
+  p /= h;
+  q.z = (int)(p % d);
+  q.b = (int)(p / d);
+  return q;
+}
+
+__device__ __forceinline__ long long flat(int d, int h, int w, int b, int z, int y, int x) {
+  return (((long long)b * d + z) * h + y) * w + x;
+}
+
+__device__ __forceinline__ void advance(Pos &q, int d, int h, int w) {
+  if (++q.x == w) {
+    q.x = 0;
+    if (++q.y == h) {
+      q.y = 0;
+      if (++q.z == d) {
+        q.z = 0;
+        ++q.b;
+      }
+    }
+  }
+}
+
+__host__ __device__ __forceinline__ int ntaps_of(int kind) {
+  return kind == CNN_K3 ? 27 : (kind == CNN_DN ? 8 : 1);
+}
+
+// taps of the weight-gradient column space (UP's 8 taps included)
+__host__ __device__ __forceinline__ int wg_taps(int kind) { return kind == CNN_UP ? 8 : ntaps_of(kind); }
+
+// Row of the input feeding GEMM position q through `tap` (-1: zero padding).
+// For K3/DN/K1 q runs over the output grid; for UP over the input grid.
+__device__ __forceinline__ long long source_row(const ConvArgs &a, const Pos &q, int tap) {
+  if (a.kind == CNN_K3) {
+    const int zz = q.z + tap / 9 - 1, yy = q.y + (tap / 3) % 3 - 1, xx = q.x + tap % 3 - 1;
+    if (zz < 0 || zz >= a.d || yy < 0 || yy >= a.h || xx < 0 || xx >= a.w) return -1;
+    return flat(a.d, a.h, a.w, q.b, zz, yy, xx);
+  }
+  if (a.kind == CNN_DN)
+    return flat(a.d, a.h, a.w, q.b, 2 * q.z + tap / 4, 2 * q.y + (tap / 2) % 2, 2 * q.x + tap % 2);
+  return flat(a.d, a.h, a.w, q.b, q.z, q.y, q.x);
+}
+
+// Row of the output that GEMM position q feeds through `tap` (UP), else q.
+__device__ __forceinline__ long long target_row(const ConvArgs &a, const Pos &q, long long qflat, int tap) {
+  if (a.kind != CNN_UP) return qflat;
+  return flat(2 * a.d, 2 * a.h, 2 * a.w, q.b, 2 * q.z + tap / 4, 2 * q.y + (tap / 2) % 2, 2 * q.x + tap % 2);
+}
+
+__device__ __forceinline__ void gemm_grid(const ConvArgs &a, int &gd, int &gh, int &gw) {
+  if (a.kind == CNN_DN) {
+    gd = a.d / 2;
+    gh = a.h / 2;
+    gw = a.w / 2;
+  } else {
+    gd = a.d;
+    gh = a.h;
+    gw = a.w;
+  }
+}
+
+// ---- forward (and input-gradient) implicit GEMM ----------------------------------
+// Block: 4 waves x 16 GEMM positions; a wave keeps CT accumulators of 16
+// output channels.  For UP, blockIdx.y is the tap (it fixes the output parity).
+template <int CT>
+__global__ void __launch_bounds__(256)
+conv_fwd_kernel(ConvArgs a) {
+  const int wave = threadIdx.x >> 6;
+  const int l = threadIdx.x & 63;
+  const int col = l & 15, g = l >> 4;
+  int gd, gh, gw;
+  gemm_grid(a, gd, gh, gw);
+  const long long npos = (long long)a.n * gd * gh * gw;
+  const long long qf = ((long long)blockIdx.x * 4 + wave) * 16 + col;
+  const bool ok = qf < npos;
+  const Pos q = unflatten(ok ? qf : 0, gd, gh, gw);
+  const int tap_up = blockIdx.y;
+  const int ntap = ntaps_of(a.kind);
+  const __bf16 *wb = a.wt + (a.kind == CNN_UP ? (size_t)tap_up * a.co_pad * a.kpad : 0);
+  v4f acc[CT];
+#pragma unroll
+  for (int t = 0; t < CT; ++t) acc[t] = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k0 = 0; k0 < a.kpad; k0 += 32) {
+    const int k = k0 + 8 * g;  // this lane group's 8 consecutive columns
+    const int tap = k / a.cip, ci = k - tap * a.cip;
+    v8bf bx = zero8();
+    if (ok && tap < ntap) {
+      const long long src = source_row(a, q, tap);
+      if (src >= 0) {
+        bx = load8(a.x + (size_t)src * a.x_ld + a.x_c0 + ci);
+        if (ci + 8 > a.ci) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (ci + u >= a.ci) bx[u] = (__bf16)0.0f;
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+      const v8bf aw = load8(wb + (size_t)(16 * t + col) * a.kpad + k);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw, bx, acc[t], 0, 0, 0);
+    }
+  }
+  if (!ok) return;
+  const long long dst = target_row(a, q, qf, tap_up);
+#pragma unroll
+  for (int t = 0; t < CT; ++t) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int co = 16 * t + 4 * g + r;
+      if (co >= a.co) continue;
+      float v = acc[t][r] + (a.bias ? a.bias[co] : 0.0f);
+      const size_t o = (size_t)dst * a.y_ld + a.y_c0 + co;
+      if (a.y_fp32) {
+        float *yo = reinterpret_cast<float *>(a.y);
+        if (a.accumulate) v += yo[o];
+        if (a.relu) v = v > 0.0f ? v : 0.0f;
+        yo[o] = v;
+      } else {
+        __bf16 *yo = reinterpret_cast<__bf16 *>(a.y);
+        if (a.accumulate) v += (float)yo[o];
+        if (a.relu) v = v > 0.0f ? v : 0.0f;
+        yo[o] = (__bf16)v;
+      }
+    }
+  }
+}
+
+// ---- weight gradient --------------------------------------------------------------
+// Tiles: (16 output channels) x (tap, 16 input channels).  A wave owns
+// kWgTiles tiles of one output-channel tile over one range of GEMM positions
+// and writes FP32 partial sums part[wpart][co_pad][taps][cit * 16];
+// wgrad_reduce_kernel sums the parts in order into the packed weight layout.
+constexpr int kWgTiles = 8;
+
+__global__ void __launch_bounds__(256)
+conv_wgrad_kernel(ConvArgs a, WgradArgs w) {
+  const int wave = threadIdx.x >> 6;
+  const int l = threadIdx.x & 63;
+  const int col = l & 15, g = l >> 4;
+  const int part = blockIdx.x * 4 + wave;
+  if (part >= w.nparts) return;
+  const int taps = wg_taps(a.kind);
+  const int cit = (a.ci + 15) / 16;
+  const int ktiles = taps * cit;
+  const int kgroups = (ktiles + kWgTiles - 1) / kWgTiles;
+  const int cot = blockIdx.y / kgroups;
+  const int kt0 = (blockIdx.y % kgroups) * kWgTiles;
+  const int co0 = cot * 16;
+  int gd, gh, gw;
+  gemm_grid(a, gd, gh, gw);
+  const long long npos = (long long)a.n * gd * gh * gw;
+  const long long p_begin = (long long)part * w.per_part;
+  const long long p_end = p_begin + w.per_part < npos ? p_begin + w.per_part : npos;
+  const int co = co0 + col;
+  v4f acc[kWgTiles];
+#pragma unroll
+  for (int t = 0; t < kWgTiles; ++t) acc[t] = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (long long p0 = p_begin; p0 < p_end; p0 += 32) {
+    const long long qf0 = p0 + 8 * g;
+    Pos qs[8];
+    Pos q = unflatten(qf0 < npos ? qf0 : 0, gd, gh, gw);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      qs[j] = q;
+      advance(q, gd, gh, gw);
+    }
+    v8bf av = zero8();
+    if (a.kind != CNN_UP && co < a.co) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j)
+        if (qf0 + j < p_end) av[j] = w.dy[(size_t)(qf0 + j) * w.dy_ld + w.dy_c0 + co];
+    }
+#pragma unroll
+    for (int t = 0; t < kWgTiles; ++t) {
+      const int kt = kt0 + t;
+      if (kt < ktiles) {
+        const int tap = kt / cit;
+        const int ci = (kt - tap * cit) * 16 + col;
+        v8bf bv = zero8();
+        if (a.kind == CNN_UP && co < a.co) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            if (qf0 + j < p_end)
+              av[j] = w.dy[(size_t)target_row(a, qs[j], qf0 + j, tap) * w.dy_ld + w.dy_c0 + co];
+        }
+        if (ci < a.ci) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            if (qf0 + j < p_end) {
+              const long long src = source_row(a, qs[j], tap);
+              if (src >= 0) bv[j] = a.x[(size_t)src * a.x_ld + a.x_c0 + ci];
+            }
+          }
+        }
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[t], 0, 0, 0);
+      }
+    }
+  }
+  const size_t rowlen = (size_t)taps * cit * 16;
+  float *pp = w.part + (size_t)part * a.co_pad * rowlen;
+#pragma unroll
+  for (int t = 0; t < kWgTiles; ++t) {
+    const int kt = kt0 + t;
+    if (kt < ktiles) {
+      const int tap = kt / cit;
+      const int cc = (kt - tap * cit) * 16 + col;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        pp[(size_t)(co0 + 4 * g + r) * rowlen + (size_t)tap * cit * 16 + cc] = acc[t][r];
+    }
+  }
+}
+
+// dw (packed layout) = sum over parts, in part order.
+__global__ void wgrad_reduce_kernel(ConvArgs a, const float *__restrict__ part, int nparts, size_t elems,
+                                    float *__restrict__ dw) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= elems) return;
+  const int taps = wg_taps(a.kind);
+  const int cit = (a.ci + 15) / 16;
+  int co, tap, ci;
+  if (a.kind == CNN_UP) {
+    tap = (int)(e / ((size_t)a.co_pad * a.kpad));
+    const size_t r = e % ((size_t)a.co_pad * a.kpad);
+    co = (int)(r / a.kpad);
+    ci = (int)(r % a.kpad);
+  } else {
+    co = (int)(e / a.kpad);
+    const int k = (int)(e % a.kpad);
+    tap = k / a.cip;
+    ci = k - tap * a.cip;
+  }
+  float s = 0.0f;
+  if (co < a.co && tap < taps && ci < a.ci) {
+    const size_t rowlen = (size_t)taps * cit * 16;
+    const size_t off = (size_t)co * rowlen + (size_t)tap * cit * 16 + ci;
+    const size_t stride = (size_t)a.co_pad * rowlen;
+    for (int p = 0; p < nparts; ++p) s += part[(size_t)p * stride + off];
+  }
+  dw[e] = s;
+}
+
+// Bias gradient: per-block partial sums over a range of output rows, then a
+// fixed-order sum over blocks.
+constexpr int kBiasBlocks = 256;
+
+__global__ void __launch_bounds__(256)
+bias_partial_kernel(const __bf16 *__restrict__ dy, int ld, int c0, long long nrows, int co, long long per,
+                    float *__restrict__ part) {
+  __shared__ float red[16][17];
+  const int c16 = threadIdx.x & 15, rr = threadIdx.x >> 4;
+  const long long r0 = (long long)blockIdx.x * per;
+  const long long r1 = r0 + per < nrows ? r0 + per : nrows;
+  for (int cb = 0; cb < co; cb += 16) {
+    const int c = cb + c16;
+    float s = 0.0f;
+    if (c < co)
+      for (long long r = r0 + rr; r < r1; r += 16) s += (float)dy[(size_t)r * ld + c0 + c];
+    red[rr][c16] = s;
+    __syncthreads();
+    if (rr == 0) {
+      float t = 0.0f;
+      for (int i = 0; i < 16; ++i) t += red[i][c16];
+      if (c < co) part[(size_t)blockIdx.x * co + c] = t;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void bias_reduce_kernel(const float *__restrict__ part, int nblk, int co, float *__restrict__ db) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= co) return;
+  float s = 0.0f;
+  for (int b = 0; b < nblk; ++b) s += part[(size_t)b * co + c];
+  db[c] = s;
+}
+
+// Input-gradient weights t from forward weights f (layouts of the file header):
+//   K3 -> K3: wt[ci][tap][co] = w[co][26 - tap][ci]      K1 -> K1: wt[ci][co] = w[co][ci]
+//   DN -> UP: wt[tap][ci][co] = w[co][tap][ci]          UP -> DN: wt[ci][tap][co] = w[tap][co][ci]
+__global__ void transpose_weights_kernel(ConvArgs f, ConvArgs t, const __bf16 *__restrict__ w,
+                                         __bf16 *__restrict__ wt, size_t elems) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= elems) return;
+  int oc, tap, ic;  // target output channel (forward ci), tap, target input channel (forward co)
+  if (t.kind == CNN_UP) {
+    tap = (int)(e / ((size_t)t.co_pad * t.kpad));
+    const size_t r = e % ((size_t)t.co_pad * t.kpad);
+    oc = (int)(r / t.kpad);
+    ic = (int)(r % t.kpad);
+  } else {
+    oc = (int)(e / t.kpad);
+    const int k = (int)(e % t.kpad);
+    tap = k / t.cip;
+    ic = k - tap * t.cip;
+  }
+  float v = 0.0f;
+  if (oc < t.co && ic < t.ci && tap < wg_taps(t.kind)) {
+    size_t s;
+    if (f.kind == CNN_K3) s = (size_t)ic * f.kpad + (size_t)(26 - tap) * f.cip + oc;
+    else if (f.kind == CNN_K1) s = (size_t)ic * f.kpad + oc;
+    else if (f.kind == CNN_DN) s = (size_t)ic * f.kpad + (size_t)tap * f.cip + oc;
+    else s = ((size_t)tap * f.co_pad + ic) * f.kpad + oc;
+    v = (float)w[s];
+  }
+  wt[e] = (__bf16)v;
+}
+
+// dy[row][c] = 0 where y[row][c] <= 0
+__global__ void relu_mask_kernel(__bf16 *__restrict__ dy, int dld, int dc0, const __bf16 *__restrict__ y, int yld,
+                                 int yc0, long long nrows, int ch) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nrows * ch) return;
+  const long long r = i / ch;
+  const int c = (int)(i - r * ch);
+  if (!((float)y[(size_t)r * yld + yc0 + c] > 0.0f)) dy[(size_t)r * dld + dc0 + c] = (__bf16)0.0f;
+}
+
+// Mean squared error of ys * (channel yc0 of an FP32 tensor) against a dense
+// FP32 target: gradient 2 ys (ys y - t) / n into a BF16 slice (zero where
+// y <= 0 when relu_mask: y is then a ReLU output), FP64 partial sums.
+__global__ void __launch_bounds__(256)
+mse_kernel(const float *__restrict__ y, int yld, int yc0, float ys, const float *__restrict__ tg, long long n,
+           __bf16 *__restrict__ g, int gld, int gc0, int relu_mask, double *__restrict__ part) {
+  __shared__ double red[256];
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double e = 0.0;
+  if (i < n) {
+    const float yi = y[(size_t)i * yld + yc0];
+    const float d = ys * yi - tg[i];
+    e = (double)d * (double)d;
+    g[(size_t)i * gld + gc0] = (relu_mask && !(yi > 0.0f)) ? (__bf16)0.0f : (__bf16)(2.0f * ys * d / (float)n);
+  }
+  red[threadIdx.x] = e;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256)
+mse_total_kernel(const double *__restrict__ part, int nblk, long long n, double *__restrict__ loss) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += 256) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = red[0] / (double)n;
+}
+
+// Adam with bias correction on FP32 master weights; optional BF16 copy.
+__global__ void adam_kernel(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
+                            float *__restrict__ v, __bf16 *__restrict__ wb, long long n, float lr, float b1,
+                            float b2, float eps, float c1, float c2) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  w[i] = wi;
+  if (wb) wb[i] = (__bf16)wi;
+}
+
+// Dense FP32 volume -> BF16 channel c0 of rows of length ld (other channels
+// of each row zeroed when zero_rest), times scale.
+__global__ void to_channels_last_kernel(const float *__restrict__ x, long long n, float scale,
+                                        __bf16 *__restrict__ out, int ld, int c0, int zero_rest) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (zero_rest)
+    for (int c = 0; c < ld; ++c)
+      if (c != c0) out[(size_t)i * ld + c] = (__bf16)0.0f;
+  out[(size_t)i * ld + c0] = (__bf16)(x[i] * scale);
+}
+
+__global__ void from_channels_last_kernel(const float *__restrict__ y, int ld, int c0, long long n, float scale,
+                                          float *__restrict__ out) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  out[i] = y[(size_t)i * ld + c0] * scale;
+}
+
+inline unsigned blocks_for(long long n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
+
+}  // namespace
+
+int cnn_cip(int ci) { return (ci + 7) / 8 * 8; }
+int cnn_copad(int co) { return (co + 15) / 16 * 16; }
+int cnn_kpad(int kind, int ci) { return (ntaps_of(kind) * cnn_cip(ci) + 31) / 32 * 32; }
+size_t cnn_weight_elems(int kind, int co, int ci) {
+  return (size_t)(kind == CNN_UP ? 8 : 1) * cnn_copad(co) * cnn_kpad(kind, ci);
+}
+
+void conv_fill_layout(ConvArgs &a) {
+  a.cip = cnn_cip(a.ci);
+  a.co_pad = cnn_copad(a.co);
+  a.kpad = cnn_kpad(a.kind, a.ci);
+}
+
+long long conv_gemm_positions(const ConvArgs &a) {
+  if (a.kind == CNN_DN) return (long long)a.n * (a.d / 2) * (a.h / 2) * (a.w / 2);
+  return (long long)a.n * a.d * a.h * a.w;
+}
+
+long long conv_output_rows(const ConvArgs &a) {
+  if (a.kind == CNN_UP) return (long long)a.n * 8 * a.d * a.h * a.w;
+  return conv_gemm_positions(a);
+}
+
+ConvArgs conv_transposed(const ConvArgs &f) {
+  ConvArgs t{};
+  t.kind = f.kind == CNN_DN ? CNN_UP : (f.kind == CNN_UP ? CNN_DN : f.kind);
+  t.n = f.n;
+  if (f.kind == CNN_DN) {
+    t.d = f.d / 2;
+    t.h = f.h / 2;
+    t.w = f.w / 2;
+  } else if (f.kind == CNN_UP) {
+    t.d = 2 * f.d;
+    t.h = 2 * f.h;
+    t.w = 2 * f.w;
+  } else {
+    t.d = f.d;
+    t.h = f.h;
+    t.w = f.w;
+  }
+  t.ci = f.co;
+  t.co = f.ci;
+  conv_fill_layout(t);
+  return t;
+}
+
+hipError_t launch_conv_fwd(const ConvArgs &a, hipStream_t st) {
+  const long long npos = conv_gemm_positions(a);
+  if (npos == 0) return hipSuccess;
+  const dim3 grid(blocks_for(npos, 64), a.kind == CNN_UP ? 8 : 1);
+  switch (a.co_pad / 16) {
+    case 1: hipLaunchKernelGGL(conv_fwd_kernel<1>, grid, dim3(256), 0, st, a); break;
+    case 2: hipLaunchKernelGGL(conv_fwd_kernel<2>, grid, dim3(256), 0, st, a); break;
+    case 3: hipLaunchKernelGGL(conv_fwd_kernel<3>, grid, dim3(256), 0, st, a); break;
+    case 4: hipLaunchKernelGGL(conv_fwd_kernel<4>, grid, dim3(256), 0, st, a); break;
+    case 8: hipLaunchKernelGGL(conv_fwd_kernel<8>, grid, dim3(256), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+bool conv_co_supported(int co) {
+  const int t = cnn_copad(co) / 16;
+  return t == 1 || t == 2 || t == 3 || t == 4 || t == 8;
+}
+
+size_t conv_transposed_weight_bytes(const ConvArgs &f) {
+  const ConvArgs t = conv_transposed(f);
+  return cnn_weight_elems(t.kind, t.co, t.ci) * sizeof(__bf16);
+}
+
+hipError_t launch_transpose_weights(const ConvArgs &f, const __bf16 *w, __bf16 *wt, hipStream_t st) {
+  const ConvArgs t = conv_transposed(f);
+  const size_t elems = cnn_weight_elems(t.kind, t.co, t.ci);
+  hipLaunchKernelGGL(transpose_weights_kernel, dim3(blocks_for((long long)elems)), dim3(256), 0, st, f, t, w, wt,
+                     elems);
+  return hipGetLastError();
+}
+
+static void wgrad_plan(const ConvArgs &a, int &nparts, long long &per_part, int &groups, size_t &part_elems) {
+  const int taps = wg_taps(a.kind);
+  const int cit = (a.ci + 15) / 16;
+  const int ktiles = taps * cit;
+  groups = (a.co_pad / 16) * ((ktiles + kWgTiles - 1) / kWgTiles);
+  const long long npos = conv_gemm_positions(a);
+  part_elems = (size_t)a.co_pad * taps * cit * 16;
+  long long want = (8192 + groups - 1) / groups;
+  const long long cap_mem = (long long)((size_t)(16u << 20) / part_elems);
+  const long long cap_pos = (npos + 255) / 256;
+  if (want > cap_mem) want = cap_mem;
+  if (want > cap_pos) want = cap_pos;
+  if (want < 1) want = 1;
+  per_part = ((npos + want - 1) / want + 31) / 32 * 32;
+  if (per_part < 32) per_part = 32;
+  nparts = (int)((npos + per_part - 1) / per_part);
+  if (nparts < 1) nparts = 1;
+}
+
+size_t conv_wgrad_ws_bytes(const ConvArgs &a) {
+  int nparts, groups;
+  long long per;
+  size_t part_elems;
+  wgrad_plan(a, nparts, per, groups, part_elems);
+  return ((size_t)nparts * part_elems + (size_t)kBiasBlocks * a.co) * sizeof(float);
+}
+
+hipError_t launch_conv_wgrad(const ConvArgs &a, const __bf16 *dy, int dy_ld, int dy_c0, float *dw, float *db,
+                             float *ws, hipStream_t st) {
+  int nparts, groups;
+  long long per;
+  size_t part_elems;
+  wgrad_plan(a, nparts, per, groups, part_elems);
+  const long long npos = conv_gemm_positions(a);
+  const size_t elems = cnn_weight_elems(a.kind, a.co, a.ci);
+  hipError_t e;
+  if (npos > 0) {
+    WgradArgs w{dy, dy_ld, dy_c0, ws, nparts, per};
+    hipLaunchKernelGGL(conv_wgrad_kernel, dim3((unsigned)((nparts + 3) / 4), (unsigned)groups), dim3(256), 0, st,
+                       a, w);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(blocks_for((long long)elems)), dim3(256), 0, st, a, ws,
+                     npos > 0 ? nparts : 0, elems, dw);
+  e = hipGetLastError();
+  if (e != hipSuccess || !db) return e;
+  float *bpart = ws + (size_t)nparts * part_elems;
+  const long long rows = conv_output_rows(a);
+  const long long bper = rows > 0 ? (rows + kBiasBlocks - 1) / kBiasBlocks : 1;
+  const int nblk = rows > 0 ? (int)((rows + bper - 1) / bper) : 0;
+  if (nblk > 0) {
+    hipLaunchKernelGGL(bias_partial_kernel, dim3((unsigned)nblk), dim3(256), 0, st, dy, dy_ld, dy_c0, rows, a.co,
+                       bper, bpart);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(bias_reduce_kernel, dim3(blocks_for(a.co)), dim3(256), 0, st, bpart, nblk, a.co, db);
+  return hipGetLastError();
+}
+
+hipError_t launch_relu_mask(__bf16 *dy, int dld, int dc0, const __bf16 *y, int yld, int yc0, long long nrows,
+                            int ch, hipStream_t st) {
+  if (nrows * ch == 0) return hipSuccess;
+  hipLaunchKernelGGL(relu_mask_kernel, dim3(blocks_for(nrows * ch)), dim3(256), 0, st, dy, dld, dc0, y, yld, yc0,
+                     nrows, ch);
+  return hipGetLastError();
+}
+
+size_t mse_ws_bytes(long long n) { return (size_t)blocks_for(n) * sizeof(double); }
+
+hipError_t launch_mse(const float *y, int yld, int yc0, float ys, const float *t, long long n, __bf16 *g, int gld,
+                      int gc0, int relu_mask, double *part, double *loss, hipStream_t st) {
+  const unsigned nb = blocks_for(n);
+  hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, st, y, yld, yc0, ys, t, n, g, gld, gc0, relu_mask, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(mse_total_kernel, dim3(1), dim3(256), 0, st, part, (int)nb, n, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float *w, const float *g, float *m, float *v, __bf16 *wb, long long n, float lr, float b1,
+                       float b2, float eps, int step, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const float c1 = (float)(1.0 - pow((double)b1, (double)step));
+  const float c2 = (float)(1.0 - pow((double)b2, (double)step));
+  hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(n)), dim3(256), 0, st, w, g, m, v, wb, n, lr, b1, b2, eps, c1,
+                     c2);
+  return hipGetLastError();
+}
+
+hipError_t launch_to_channels_last(const float *x, long long n, float scale, __bf16 *out, int ld, int c0,
+                                   int zero_rest, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(to_channels_last_kernel, dim3(blocks_for(n)), dim3(256), 0, st, x, n, scale, out, ld, c0,
+                     zero_rest);
+  return hipGetLastError();
+}
+
+hipError_t launch_from_channels_last(const float *y, int ld, int c0, long long n, float scale, float *out,
+                                     hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(from_channels_last_kernel, dim3(blocks_for(n)), dim3(256), 0, st, y, ld, c0, n, scale, out);
+  return hipGetLastError();
+}
+
+}  // namespace ctof

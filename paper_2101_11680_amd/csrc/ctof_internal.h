@@ -183,4 +183,73 @@ hipError_t launch_fill_int(int *p, int n, int v, hipStream_t st);
 hipError_t launch_fill_value(float *p, size_t n, float v, hipStream_t st);
 hipError_t launch_fill_value_f64(double *p, size_t n, double v, hipStream_t st);
 
+
+// Thread-local error message of the C ABI (returns s).
+ctof_status set_error(ctof_status s, const char *fmt, ...);
+const char *last_error();
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      return ::ctof::set_error(CTOF_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));  \
+  } while (0)
+
+// ---- learned warm start: 3D convolution layers and sampling ------------------------
+enum { CNN_K3 = 0, CNN_DN = 1, CNN_UP = 2, CNN_K1 = 3 };
+
+struct ConvArgs {
+  int kind, n, d, h, w, ci, co;  // input grid and channels
+  int cip, co_pad, kpad;         // packed-weight layout
+  const __bf16 *x;
+  int x_ld, x_c0;
+  const __bf16 *wt;
+  const float *bias;
+  void *y;
+  int y_ld, y_c0, y_fp32, relu, accumulate;
+};
+
+struct WgradArgs {
+  const __bf16 *dy;
+  int dy_ld, dy_c0;
+  float *part;
+  int nparts;
+  long long per_part;
+};
+
+int cnn_cip(int ci);
+int cnn_copad(int co);
+int cnn_kpad(int kind, int ci);
+size_t cnn_weight_elems(int kind, int co, int ci);
+void conv_fill_layout(ConvArgs &a);
+long long conv_gemm_positions(const ConvArgs &a);
+long long conv_output_rows(const ConvArgs &a);
+ConvArgs conv_transposed(const ConvArgs &f);
+bool conv_co_supported(int co);
+hipError_t launch_conv_fwd(const ConvArgs &a, hipStream_t st);
+size_t conv_transposed_weight_bytes(const ConvArgs &f);
+hipError_t launch_transpose_weights(const ConvArgs &f, const __bf16 *w, __bf16 *wt, hipStream_t st);
+size_t conv_wgrad_ws_bytes(const ConvArgs &a);
+hipError_t launch_conv_wgrad(const ConvArgs &a, const __bf16 *dy, int dy_ld, int dy_c0, float *dw, float *db,
+                             float *ws, hipStream_t st);
+hipError_t launch_relu_mask(__bf16 *dy, int dld, int dc0, const __bf16 *y, int yld, int yc0, long long nrows,
+                            int ch, hipStream_t st);
+size_t mse_ws_bytes(long long n);
+hipError_t launch_mse(const float *y, int yld, int yc0, float ys, const float *t, long long n, __bf16 *g, int gld,
+                      int gc0, int relu_mask, double *part, double *loss, hipStream_t st);
+hipError_t launch_adam(float *w, const float *g, float *m, float *v, __bf16 *wb, long long n, float lr, float b1,
+                       float b2, float eps, int step, hipStream_t st);
+hipError_t launch_to_channels_last(const float *x, long long n, float scale, __bf16 *out, int ld, int c0,
+                                   int zero_rest, hipStream_t st);
+hipError_t launch_from_channels_last(const float *y, int ld, int c0, long long n, float scale, float *out,
+                                     hipStream_t st);
+
+hipError_t launch_philox(uint64_t seed, uint32_t stream_id, long long first, long long n, uint32_t *out,
+                         hipStream_t st);
+hipError_t launch_poisson(const float *lam, long long n, uint64_t seed, uint32_t stream_id, float *counts,
+                          hipStream_t st);
+size_t noisy_histogram_ws_bytes(long long n);
+hipError_t launch_noisy_histogram(const float *m, long long n, double peak, uint64_t seed, uint32_t stream_id,
+                                  float *d, void *ws, hipStream_t st);
+
 }  // namespace ctof

@@ -26,7 +26,12 @@ EXPORTS = ("ctof_kernel_bytes", "ctof_kernel_tabulate", "ctof_kernel_tabulate_qu
            "ctof_kernel_free", "ctof_kernel_info", "ctof_workspace_bytes", "ctof_forward",
            "ctof_adjoint", "ctof_reconstruct", "ctof_workspace_bytes_batched",
            "ctof_reconstruct_batched", "ctof_kernel_set_tuning", "ctof_kernel_get_tuning",
-           "ctof_tune_workspace_bytes", "ctof_tune", "ctof_last_error")
+           "ctof_tune_workspace_bytes", "ctof_tune", "ctof_last_error",
+           "ctof_conv3d_weight_elems", "ctof_conv3d_fwd", "ctof_conv3d_bwd_data_ws_bytes",
+           "ctof_conv3d_bwd_data", "ctof_conv3d_bwd_weight_ws_bytes", "ctof_conv3d_bwd_weight",
+           "ctof_relu_bwd", "ctof_mse_ws_bytes", "ctof_mse", "ctof_adam_step",
+           "ctof_to_channels_last", "ctof_from_channels_last", "ctof_philox4x32", "ctof_poisson",
+           "ctof_noisy_histogram_ws_bytes", "ctof_noisy_histogram")
 
 
 class CtofError(RuntimeError):
@@ -58,7 +63,18 @@ class _SolverReport(ctypes.Structure):
                 ("lambda_", ctypes.c_double), ("lipschitz_a", ctypes.c_double),
                 ("gmap0", ctypes.c_double), ("ms_contract_fwd", ctypes.c_double),
                 ("ms_fft_t", ctypes.c_double), ("ms_contract_adj", ctypes.c_double),
-                ("ms_fft_z", ctypes.c_double), ("ms_loop", ctypes.c_double)]
+                ("ms_fft_z", ctypes.c_double), ("ms_loop", ctypes.c_double),
+                ("fell_back", ctypes.c_int32)]
+
+
+class _ConvDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n", ctypes.c_int32), ("d", ctypes.c_int32),
+                ("h", ctypes.c_int32), ("w", ctypes.c_int32), ("ci", ctypes.c_int32),
+                ("co", ctypes.c_int32)]
+
+
+class _Tensor(ctypes.Structure):
+    _fields_ = [("ptr", ctypes.c_void_p), ("ld", ctypes.c_int32), ("c0", ctypes.c_int32)]
 
 
 _lib = None
@@ -94,6 +110,25 @@ def lib() -> ctypes.CDLL:
         L.ctof_tune_workspace_bytes.argtypes = [vp, i32, ctypes.POINTER(sz)]
         L.ctof_tune.argtypes = [vp, i32, i32, vp, sz, vp, ctypes.POINTER(ctypes.c_float),
                                 ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        dp = ctypes.POINTER(_ConvDesc)
+        tp = ctypes.POINTER(_Tensor)
+        i64, u64, u32, f32 = ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_float
+        L.ctof_conv3d_weight_elems.argtypes = [dp, ctypes.POINTER(sz)]
+        L.ctof_conv3d_fwd.argtypes = [dp, tp, vp, vp, tp, i32, i32, i32, vp]
+        L.ctof_conv3d_bwd_data_ws_bytes.argtypes = [dp, ctypes.POINTER(sz)]
+        L.ctof_conv3d_bwd_data.argtypes = [dp, tp, vp, tp, i32, vp, sz, vp]
+        L.ctof_conv3d_bwd_weight_ws_bytes.argtypes = [dp, ctypes.POINTER(sz)]
+        L.ctof_conv3d_bwd_weight.argtypes = [dp, tp, tp, vp, vp, vp, sz, vp]
+        L.ctof_relu_bwd.argtypes = [i64, i32, tp, tp, vp]
+        L.ctof_mse_ws_bytes.argtypes = [i64, ctypes.POINTER(sz)]
+        L.ctof_mse.argtypes = [i64, tp, f32, vp, tp, i32, vp, vp, sz, vp]
+        L.ctof_adam_step.argtypes = [i64, vp, vp, vp, vp, vp, f32, f32, f32, f32, i32, vp]
+        L.ctof_to_channels_last.argtypes = [i64, vp, f32, tp, i32, vp]
+        L.ctof_from_channels_last.argtypes = [i64, tp, f32, vp, vp]
+        L.ctof_philox4x32.argtypes = [u64, u32, i64, i64, vp, vp]
+        L.ctof_poisson.argtypes = [i64, vp, u64, u32, vp, vp]
+        L.ctof_noisy_histogram_ws_bytes.argtypes = [i64, ctypes.POINTER(sz)]
+        L.ctof_noisy_histogram.argtypes = [i64, vp, ctypes.c_double, u64, u32, vp, vp, sz, vp]
         L.ctof_last_error.argtypes = []
         L.ctof_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -272,13 +307,16 @@ class Report:
     ms_contract_adj: float = 0.0
     ms_fft_z: float = 0.0
     ms_loop: float = 0.0
+    fell_back: int = 0
 
 
 def reconstruct(k: Kernel, d, mu=None, max_iter: int = 200, lam: float = -1.0,
                 lipschitz: float = 0.0, power_iters: int = 50, rel_tol: float = 0.0,
                 check_every: int = 10, warm_start: bool = False, history: bool = False,
                 timing: bool = False, stream=None):
-    """FISTA reconstruction; returns (mu, Report, history or None)."""
+    """FISTA reconstruction; returns (mu, Report, history or None).  warm_start:
+    0/False zero start, 1/True start from ``mu``, 2 start from ``mu`` with the
+    zero-start fallback."""
     torch = _torch()
     i = k.info
     d = _contig(d, _dtype(k.precision), (i.nt, i.n, i.n))
@@ -288,16 +326,14 @@ def reconstruct(k: Kernel, d, mu=None, max_iter: int = 200, lam: float = -1.0,
     mu = _contig(mu, d.dtype, (i.nz, i.n, i.n))
     hist = torch.zeros((max_iter, 2), dtype=torch.float64, device=d.device) if history else None
     opts = _SolverOpts(int(max_iter), float(lam), float(lipschitz), int(power_iters),
-                       float(rel_tol), int(check_every), int(bool(warm_start)),
+                       float(rel_tol), int(check_every), int(warm_start),
                        hist.data_ptr() if hist is not None else None, int(bool(timing)))
     rep = _SolverReport()
     _, nb = k.workspace_bytes(max_iter)
     ws = k.workspace(nb, d.device)
     _check(lib().ctof_reconstruct(k.handle, d.data_ptr(), mu.data_ptr(), ctypes.byref(opts),
                                   ctypes.byref(rep), ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
-    report = Report(rep.iters, rep.status, rep.datafit0, rep.datafit, rep.gmap_ratio,
-                    rep.lipschitz, rep.lambda_, rep.lipschitz_a, rep.gmap0, rep.ms_contract_fwd,
-                    rep.ms_fft_t, rep.ms_contract_adj, rep.ms_fft_z, rep.ms_loop)
+    report = _report(rep)
     if hist is not None:
         hist = hist[: rep.iters]
     return mu, report, hist
@@ -306,7 +342,7 @@ def reconstruct(k: Kernel, d, mu=None, max_iter: int = 200, lam: float = -1.0,
 def _report(rep) -> Report:
     return Report(rep.iters, rep.status, rep.datafit0, rep.datafit, rep.gmap_ratio,
                   rep.lipschitz, rep.lambda_, rep.lipschitz_a, rep.gmap0, rep.ms_contract_fwd,
-                  rep.ms_fft_t, rep.ms_contract_adj, rep.ms_fft_z, rep.ms_loop)
+                  rep.ms_fft_t, rep.ms_contract_adj, rep.ms_fft_z, rep.ms_loop, rep.fell_back)
 
 
 def reconstruct_batched(kernels, ds, mus=None, max_iter: int = 200, lam: float = -1.0,
@@ -335,7 +371,7 @@ def reconstruct_batched(kernels, ds, mus=None, max_iter: int = 200, lam: float =
     _check(lib().ctof_workspace_bytes_batched(n, handles, int(max_iter), ctypes.byref(nb)))
     ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=ds[0].device)
     opts = _SolverOpts(int(max_iter), float(lam), float(lipschitz), int(power_iters),
-                       float(rel_tol), int(check_every), int(bool(warm_start)), None, 0)
+                       float(rel_tol), int(check_every), int(warm_start), None, 0)
     reps = (_SolverReport * n)()
     _check(lib().ctof_reconstruct_batched(n, handles, dptr, mptr, ctypes.byref(opts), reps,
                                           ws.data_ptr(), ws.numel(), _stream_ptr(stream)))

@@ -1,0 +1,359 @@
+"""Learned warm start: a 4-level 3D U-Net run on libctof's BF16 kernels.
+
+The network maps the scaled adjoint back-projection x = tau A^T d of a scan
+(tau = 1/L, the solver's step) to a non-negative starting volume for the
+FISTA reconstruction of the paper's regularised least-squares problem
+(section "Reconstruction Algorithm").  Only the start changes: the solver
+then runs to the same tolerance, and with warm_start = 2 it discards a start
+whose first gradient-mapping ratio is worse than a zero start's.
+
+Architecture (channels c1..c4 = 16/32/64/64 by default; every conv has a
+bias and a ReLU):
+  encoder level l = 1, 2, 3:  k3 (c_{l-1} -> c_l), k3 (c_l -> c_l) [skip],
+                              dn (c_l -> c_l, stride 2)
+  level 4:                    k3 (c3 -> c4), k3 (c4 -> c4)
+  decoder level l = 3, 2, 1:  up (c_{l+1} -> c_l, stride 2), concatenate
+                              [up, skip], k3 (2 c_l -> c_l), k3 (c_l -> c_l)
+  head:                       k1 (c1 -> 1)
+Activations are BF16 channels-last; the skip of level l is written straight
+into the upper half of that level's concatenation buffer.  Parameters are
+one flat FP32 master buffer (each layer's packed weights, then its bias) with
+a BF16 working copy, FP32 gradients and Adam moments; the optimiser is one
+launch over the whole buffer.
+
+Every arithmetic step runs in libctof (conv forward / input gradient /
+weight gradient, ReLU mask, loss, Adam, sampling, the operator and the
+solver); this module allocates buffers and sequences the calls.
+"""
+
+from __future__ import annotations
+
+import json
+import math
+import os
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional, Tuple
+
+import numpy as np
+
+from . import ctof, nn
+from .nn import DN, K1, K3, UP, Conv, Slice
+
+DEFAULT_CH = (16, 32, 64, 64)
+_KINDS = {"k3": K3, "dn": DN, "up": UP, "k1": K1}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def layer_list(ch=DEFAULT_CH) -> List[Tuple[str, int, int, int]]:
+    """(name, kind, co, ci) in execution order."""
+    c1, c2, c3, c4 = ch
+    out = []
+    prev = 1
+    for lvl, c in ((1, c1), (2, c2), (3, c3)):
+        out += [(f"e{lvl}a", K3, c, prev), (f"e{lvl}b", K3, c, c), (f"d{lvl}", DN, c, c)]
+        prev = c
+    out += [("m4a", K3, c4, c3), ("m4b", K3, c4, c4)]
+    below = c4
+    for lvl, c in ((3, c3), (2, c2), (1, c1)):
+        out += [(f"u{lvl}", UP, c, below), (f"c{lvl}a", K3, c, 2 * c), (f"c{lvl}b", K3, c, c)]
+        below = c
+    out.append(("head", K1, 1, c1))
+    return out
+
+
+def _align(n: int, a: int = 64) -> int:
+    return (n + a - 1) // a * a
+
+
+@dataclass
+class _Param:
+    kind: int
+    co: int
+    ci: int
+    w_off: int
+    w_len: int
+    b_off: int
+
+
+class UNet:
+    """Parameters, activation buffers and the forward/backward sequence."""
+
+    def __init__(self, ch=DEFAULT_CH, device="cuda", seed: int = 0):
+        torch = _torch()
+        for c in ch:
+            if c % 8 or c < 8:
+                raise ValueError("channel counts must be multiples of 8")
+        self.ch = tuple(int(c) for c in ch)
+        self.device = torch.device(device)
+        self.layers = layer_list(self.ch)
+        self.params: Dict[str, _Param] = {}
+        off = 0
+        for name, kind, co, ci in self.layers:
+            wl = nn.weight_elems(kind, co, ci)
+            w_off = off
+            off += _align(wl)
+            b_off = off
+            off += _align(co)
+            self.params[name] = _Param(kind, co, ci, w_off, wl, b_off)
+        self.size = off
+        f32 = dict(dtype=torch.float32, device=self.device)
+        self.master = torch.zeros(off, **f32)
+        self.work = torch.zeros(off, dtype=torch.bfloat16, device=self.device)
+        self.grad = torch.zeros(off, **f32)
+        self.m = torch.zeros(off, **f32)
+        self.v = torch.zeros(off, **f32)
+        self.step_count = 0
+        self.in_scale = 1.0   # network input = x * in_scale
+        self.out_scale = 1.0  # start volume = network output * out_scale
+        self._bufs = None
+        self._shape = None
+        self.loss_dev = torch.zeros(1, dtype=torch.float64, device=self.device)
+        self.init(seed)
+
+    # ---- parameters -----------------------------------------------------------
+    def init(self, seed: int) -> None:
+        """He-normal weights (fan-in = taps x ci), zero biases."""
+        rng = np.random.default_rng(seed)
+        logical = {}
+        for name, kind, co, ci in self.layers:
+            taps = {K3: 27, DN: 8, UP: 1, K1: 1}[kind]
+            shape = {K3: (co, 3, 3, 3, ci), DN: (co, 2, 2, 2, ci), UP: (2, 2, 2, co, ci), K1: (co, ci)}[kind]
+            logical[name + ".w"] = rng.normal(0.0, math.sqrt(2.0 / (taps * ci)), shape)
+            logical[name + ".b"] = np.zeros(co)
+        self.load_logical(logical)
+
+    def load_logical(self, P: Dict[str, np.ndarray]) -> None:
+        """Set parameters from logical arrays (shapes of the layer kinds)."""
+        torch = _torch()
+        host = np.zeros(self.size, np.float32)
+        for name, p in self.params.items():
+            host[p.w_off:p.w_off + p.w_len] = nn.pack_weights(p.kind, P[name + ".w"])
+            host[p.b_off:p.b_off + p.co] = np.asarray(P[name + ".b"], np.float32)
+        t = torch.from_numpy(host)
+        self.master.copy_(t)
+        self.work.copy_(t.to(torch.bfloat16))
+        self.m.zero_()
+        self.v.zero_()
+        self.step_count = 0
+
+    def logical(self, which: str = "master") -> Dict[str, np.ndarray]:
+        """Parameters ('master') or gradients ('grad') as logical arrays."""
+        src = (self.master if which == "master" else self.grad).detach().cpu().numpy()
+        out = {}
+        for name, p in self.params.items():
+            out[name + ".w"] = nn.unpack_weights(p.kind, src[p.w_off:p.w_off + p.w_len], p.co, p.ci)
+            out[name + ".b"] = src[p.b_off:p.b_off + p.co].astype(np.float64)
+        return out
+
+    def _w(self, name):
+        p = self.params[name]
+        return self.work[p.w_off:p.w_off + p.w_len], self.master[p.b_off:p.b_off + p.co]
+
+    def _g(self, name):
+        p = self.params[name]
+        return self.grad[p.w_off:p.w_off + p.w_len], self.grad[p.b_off:p.b_off + p.co]
+
+    # ---- buffers ----------------------------------------------------------------
+    def _alloc(self, n: int, D: int, H: int, W: int) -> None:
+        if self._shape == (n, D, H, W):
+            return
+        if D % 8 or H % 8 or W % 8:
+            raise ValueError("grid sizes must be divisible by 8 (three stride-2 levels)")
+        torch = _torch()
+        c1, c2, c3, c4 = self.ch
+        rows = [n * D * H * W >> (3 * l) for l in range(4)]
+        bf = dict(dtype=torch.bfloat16, device=self.device)
+
+        def z(r, c, dt=None):
+            return torch.zeros((r, c), **(bf if dt is None else dict(dtype=dt, device=self.device)))
+
+        A = {"input": z(rows[0], 8)}
+        G = {}
+        for l, c in ((1, c1), (2, c2), (3, c3)):
+            r = rows[l - 1]
+            A[f"e{l}a"] = z(r, c)
+            A[f"cat{l}"] = z(r, 2 * c)
+            A[f"d{l}"] = z(rows[l], c)
+            A[f"c{l}a"] = z(r, c)
+            A[f"c{l}b"] = z(r, c)
+            G[f"e{l}a"] = z(r, c)
+            G[f"cat{l}"] = z(r, 2 * c)
+            G[f"d{l}"] = z(rows[l], c)
+            G[f"c{l}a"] = z(r, c)
+            G[f"c{l}b"] = z(r, c)
+        A["m4a"] = z(rows[3], c4)
+        A["m4b"] = z(rows[3], c4)
+        G["m4a"] = z(rows[3], c4)
+        G["m4b"] = z(rows[3], c4)
+        A["head"] = z(rows[0], 1, torch.float32)
+        G["head"] = z(rows[0], 8)
+        self._bufs = (A, G)
+        self._shape = (n, D, H, W)
+        self._grids = [(n, D >> l, H >> l, W >> l) for l in range(4)]
+
+    def _conv(self, name: str, lvl: int) -> Conv:
+        """Conv descriptor of a layer whose INPUT is on level lvl (0-based)."""
+        p = self.params[name]
+        n, d, h, w = self._grids[lvl]
+        return Conv(p.kind, n, d, h, w, p.ci, p.co)
+
+    # ---- forward ----------------------------------------------------------------
+    def forward(self, x, scale=1.0, stream=None):
+        """x: float32 [n, D, H, W] back-projections A^T d; the network input
+        is x * scale * in_scale, scale a number or one per sample (tau of the
+        scan's class).  Returns the FP32 head buffer [rows, 1] (network
+        units: the start volume is head * out_scale)."""
+        n, D, H, W = x.shape
+        self._alloc(n, D, H, W)
+        A, _ = self._bufs
+        c = self.ch
+        x = x.contiguous()
+        if isinstance(scale, (int, float)):
+            nn.to_channels_last(x, float(scale) * self.in_scale, Slice(A["input"], 0, 1), stream=stream)
+        else:
+            R = D * H * W
+            for i in range(n):
+                nn.to_channels_last(x[i], float(scale[i]) * self.in_scale,
+                                    Slice(A["input"][i * R:(i + 1) * R], 0, 1), stream=stream)
+        run = lambda name, lvl, src, dst: nn.conv_fwd(self._conv(name, lvl), src, *self._w(name), dst,
+                                                      relu=True, stream=stream)
+        h = Slice(A["input"], 0, 1)
+        for l in (1, 2, 3):
+            cl = c[l - 1]
+            run(f"e{l}a", l - 1, h, Slice(A[f"e{l}a"]))
+            run(f"e{l}b", l - 1, Slice(A[f"e{l}a"]), Slice(A[f"cat{l}"], cl, cl))
+            run(f"d{l}", l - 1, Slice(A[f"cat{l}"], cl, cl), Slice(A[f"d{l}"]))
+            h = Slice(A[f"d{l}"])
+        run("m4a", 3, h, Slice(A["m4a"]))
+        run("m4b", 3, Slice(A["m4a"]), Slice(A["m4b"]))
+        h = Slice(A["m4b"])
+        for l in (3, 2, 1):
+            cl = c[l - 1]
+            run(f"u{l}", l, h, Slice(A[f"cat{l}"], 0, cl))
+            run(f"c{l}a", l - 1, Slice(A[f"cat{l}"]), Slice(A[f"c{l}a"]))
+            run(f"c{l}b", l - 1, Slice(A[f"c{l}a"]), Slice(A[f"c{l}b"]))
+            h = Slice(A[f"c{l}b"])
+        run("head", 0, h, Slice(A["head"], 0, 1))
+        return A["head"]
+
+    # ---- backward ----------------------------------------------------------------
+    def _back(self, name, lvl, x: Slice, dy: Slice, y: Optional[Slice], dx: Optional[Slice], accumulate=False,
+              stream=None):
+        """ReLU mask of dy by y (unless y is None), weight/bias gradients, and
+        the input gradient into dx (unless None)."""
+        cv = self._conv(name, lvl)
+        if y is not None:
+            nn.relu_bwd(cv.out_rows(), cv.co, dy, y, stream=stream)
+        gw, gb = self._g(name)
+        nn.conv_bwd_weight(cv, x, dy, gw, gb, stream=stream)
+        if dx is not None:
+            nn.conv_bwd_data(cv, dy, self._w(name)[0], dx, accumulate=accumulate, stream=stream)
+
+    def backward_from_output_grad(self, stream=None) -> None:
+        """Backward pass given the head gradient already in G['head'] (channel
+        0, the head's ReLU mask applied)."""
+        A, G = self._bufs
+        c = self.ch
+        S = Slice
+        self._back("head", 0, S(A["c1b"]), S(G["head"], 0, 1), None, S(G["c1b"]), stream=stream)
+        for l in (1, 2, 3):
+            cl = c[l - 1]
+            self._back(f"c{l}b", l - 1, S(A[f"c{l}a"]), S(G[f"c{l}b"]), S(A[f"c{l}b"]), S(G[f"c{l}a"]),
+                       stream=stream)
+            self._back(f"c{l}a", l - 1, S(A[f"cat{l}"]), S(G[f"c{l}a"]), S(A[f"c{l}a"]), S(G[f"cat{l}"]),
+                       stream=stream)
+            src_a, src_g = (A["m4b"], G["m4b"]) if l == 3 else (A[f"c{l + 1}b"], G[f"c{l + 1}b"])
+            self._back(f"u{l}", l, S(src_a), S(G[f"cat{l}"], 0, cl), S(A[f"cat{l}"], 0, cl), S(src_g),
+                       stream=stream)
+        self._back("m4b", 3, S(A["m4a"]), S(G["m4b"]), S(A["m4b"]), S(G["m4a"]), stream=stream)
+        self._back("m4a", 3, S(A["d3"]), S(G["m4a"]), S(A["m4a"]), S(G["d3"]), stream=stream)
+        for l in (3, 2, 1):
+            cl = c[l - 1]
+            skip_a, skip_g = S(A[f"cat{l}"], cl, cl), S(G[f"cat{l}"], cl, cl)
+            # the dn layer's input gradient is added to the skip's gradient
+            self._back(f"d{l}", l - 1, skip_a, S(G[f"d{l}"]), S(A[f"d{l}"]), skip_g, accumulate=True,
+                       stream=stream)
+            self._back(f"e{l}b", l - 1, S(A[f"e{l}a"]), skip_g, skip_a, S(G[f"e{l}a"]), stream=stream)
+            prev_a = S(A["input"], 0, 1) if l == 1 else S(A[f"d{l - 1}"])
+            prev_g = None if l == 1 else S(G[f"d{l - 1}"])
+            self._back(f"e{l}a", l - 1, prev_a, S(G[f"e{l}a"]), S(A[f"e{l}a"]), prev_g, stream=stream)
+
+    def loss_and_backward(self, target, stream=None):
+        """Mean squared error of the start volume (head * out_scale) against
+        target (float32 [n, D, H, W], physical units); fills the gradients;
+        returns the device loss (double [1])."""
+        A, G = self._bufs
+        rows = A["head"].shape[0]
+        nn.mse(rows, Slice(A["head"], 0, 1), target.contiguous(), Slice(G["head"], 0, 1), self.loss_dev,
+               relu_mask=True, y_scale=self.out_scale, stream=stream)
+        self.backward_from_output_grad(stream=stream)
+        return self.loss_dev
+
+    def adam(self, lr: float, stream=None) -> None:
+        self.step_count += 1
+        nn.adam_step(self.master, self.grad, self.m, self.v, self.work, lr, self.step_count, stream=stream)
+
+    # ---- inference ----------------------------------------------------------------
+    def predict(self, x, scale=1.0, stream=None):
+        """Start volumes (float32 [n, D, H, W]) from back-projections x with
+        the per-sample (or common) scale tau."""
+        torch = _torch()
+        head = self.forward(x, scale, stream=stream)
+        out = torch.empty(x.shape, dtype=torch.float32, device=self.device)
+        nn.from_channels_last(Slice(head, 0, 1), self.out_scale, out, stream=stream)
+        return out
+
+    # ---- checkpoints ----------------------------------------------------------------
+    def save(self, path: str, extra: Optional[dict] = None) -> None:
+        """FP32 master weights, Adam moments, step, scales (npz, no pickles)."""
+        meta = dict(ch=list(self.ch), step=self.step_count, in_scale=self.in_scale, out_scale=self.out_scale)
+        meta.update(extra or {})
+        np.savez(path, master=self.master.cpu().numpy(), m=self.m.cpu().numpy(), v=self.v.cpu().numpy(),
+                 meta=np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8))
+
+    @classmethod
+    def load(cls, path: str, device="cuda") -> "UNet":
+        torch = _torch()
+        z = np.load(path, allow_pickle=False)
+        meta = json.loads(bytes(z["meta"]).decode())
+        net = cls(tuple(meta["ch"]), device=device)
+        master = torch.from_numpy(z["master"])
+        if master.numel() != net.size:
+            raise ValueError("checkpoint does not match the architecture")
+        net.master.copy_(master)
+        net.work.copy_(master.to(torch.bfloat16))
+        net.m.copy_(torch.from_numpy(z["m"]))
+        net.v.copy_(torch.from_numpy(z["v"]))
+        net.step_count = int(meta["step"])
+        net.in_scale = float(meta["in_scale"])
+        net.out_scale = float(meta["out_scale"])
+        net.meta = meta
+        return net
+
+
+# ---- data and warm start -------------------------------------------------------------
+
+def warm_start_volumes(net: UNet, kernels, ds, taus, max_batch: int = 16, stream=None):
+    """Start volumes for a list of scans: the back-projection A^T d of each
+    scan, scaled by its class's tau, run through the network in batches of
+    one grid shape (at most max_batch scans per batch)."""
+    torch = _torch()
+    out = [None] * len(ds)
+    groups: Dict[tuple, List[int]] = {}
+    for i, k in enumerate(kernels):
+        inf = k.info
+        groups.setdefault((inf.nz, inf.n), []).append(i)
+    for (nz, n), idx in groups.items():
+        for b0 in range(0, len(idx), max_batch):
+            part = idx[b0:b0 + max_batch]
+            x = torch.empty((len(part), nz, n, n), dtype=torch.float32, device=net.device)
+            for j, i in enumerate(part):
+                ctof.adjoint(kernels[i], ds[i], out=x[j], stream=stream)
+            pred = net.predict(x, [taus[i] for i in part], stream=stream)
+            for j, i in enumerate(part):
+                out[i] = pred[j]
+    return out
