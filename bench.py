@@ -154,7 +154,54 @@ def run_batching(args, ctof, torch, dev) -> int:
         out[f"batched_{name}_s"] = dt
         out[f"batched_{name}_iters_mean"] = float(sum(r.iters for r in reps)) / len(reps)
         out[f"speedup_{name}"] = out["plain_fp32_s"] / dt
+        out[f"batched_{name}_iters"] = [r.iters for r in reps]
         log(f"batched {name}: {dt:.3f}s ({out['plain_fp32_s'] / dt:.2f}x)")
+    # accelerated: batched classes + learned start (CNN time included) with
+    # the zero-start fallback; L per class from one power iteration each
+    from paper_2101_11680_amd import unet
+    net = unet.load_default(device=dev)
+    first = {}
+    for i, (g, _, _) in enumerate(scans):
+        first.setdefault(g, i)
+    for name in precs:
+        ks = [kern[name][g] for g, _, _ in scans]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lip = {}
+        for g, i in first.items():
+            _, rep, _ = ctof.reconstruct(kern[name][g], ds[i], max_iter=1)
+            lip[g] = (rep.lipschitz, rep.lam)
+        starts = unet.warm_start_volumes(net, ks, ds, [1.0 / lip[g][0] for g, _, _ in scans])
+        torch.cuda.synchronize()
+        t_cnn = time.perf_counter() - t0
+        _, reps = ctof.reconstruct_batched(ks, ds, mus=starts, max_iter=maxit, rel_tol=args.rel_tol,
+                                           check_every=10, warm_start=2,
+                                           lipschitz=[lip[g][0] for g, _, _ in scans],
+                                           lam=[lip[g][1] for g, _, _ in scans])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        out[f"accelerated_{name}_s"] = dt
+        out[f"accelerated_{name}_setup_s"] = t_cnn
+        out[f"accelerated_{name}_iters_mean"] = float(sum(r.iters for r in reps)) / len(reps)
+        out[f"accelerated_{name}_fell_back"] = int(sum(r.fell_back for r in reps))
+        out[f"accelerated_{name}_not_converged"] = int(sum(r.gmap_ratio > args.rel_tol for r in reps))
+        out[f"speedup_accelerated_{name}"] = out["plain_fp32_s"] / dt
+        per = {}
+        for (g, _, _), r, rz in zip(scans, reps, out[f"batched_{name}_iters"]):
+            key = f"{g.nx}x{g.nz}"
+            c = per.setdefault(key, dict(scans=0, iters_zero=0, iters_warm=0, fell_back=0))
+            c["scans"] += 1
+            c["iters_zero"] += rz
+            c["iters_warm"] += r.iters
+            c["fell_back"] += r.fell_back
+        out[f"accelerated_{name}_per_class"] = {
+            k: dict(scans=c["scans"], iters_zero_mean=c["iters_zero"] / c["scans"],
+                    iters_warm_mean=c["iters_warm"] / c["scans"], fell_back=c["fell_back"])
+            for k, c in sorted(per.items())}
+        log(f"accelerated {name}: {dt:.3f}s ({out['plain_fp32_s'] / dt:.2f}x), setup+CNN {t_cnn:.3f}s, "
+            f"fell back {out[f'accelerated_{name}_fell_back']}")
+    for name in precs:
+        out.pop(f"batched_{name}_iters", None)
     print(json.dumps(out), flush=True)
     return 0
 

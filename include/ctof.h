@@ -186,6 +186,11 @@ ctof_status ctof_adjoint(ctof_kernel k, const void *r_dev, void *g_dev, void *ws
  *   timing           1: record HIP events on `stream` around the stages of
  *                    every iteration and fill the ms_* fields of the report
  *                    (adds event records between launches); 0: no events
+ *   lipschitz_scans, lambda_scans
+ *                    batched solves only (NULL otherwise): host arrays [nscan]
+ *                    giving each scan's L (> 0) and lambda (>= 0) in place of
+ *                    lipschitz / lambda_tikhonov; scans sharing a handle must
+ *                    agree.  NULL: lipschitz / lambda_tikhonov for all.
  */
 typedef struct {
   int32_t max_iter;
@@ -197,6 +202,8 @@ typedef struct {
   int32_t warm_start;
   double *history_dev;
   int32_t timing;
+  const double *lipschitz_scans;
+  const double *lambda_scans;
 } ctof_solver_opts;
 
 /*
@@ -373,6 +380,37 @@ ctof_status ctof_mse(int64_t n, const ctof_tensor *y, float y_scale, const float
                      hipStream_t stream);
 
 /*
+ * Training loss of the warm start, for nb (1..64) scans of one float handle
+ * (CTOF_FP32, CTOF_BF16X3 or CTOF_BF16).  Scan b's start is x_b = s_b y_b
+ * (s: host array [nb]),
+ * y_b = channel y.c0 of rows b V .. (b + 1) V - 1 of an FP32 tensor
+ * (V = nz n n, rows in [z][y][x] order: the network output); target_dev
+ * holds the solutions mu*_b (float [nb][nz][n][n]).  With e_b = x_b - mu*_b
+ * and H = A^T A + lambda I (the Hessian of the regularised objective of
+ * section "Reconstruction Algorithm"), H e_b is to first order the gradient
+ * of the objective at the start, i.e. what the solver's gradient-mapping
+ * ratio measures:
+ *   loss_b = w_b ||H e_b||^2 + v_b ||e_b||^2      (w, v: host arrays [nb])
+ * terms_dev (double [nb][2]) receives (||H e_b||^2, ||e_b||^2) (FP64 sums in
+ * a fixed order); grad (BF16 slice, channel grad.c0 of the same rows)
+ * receives d(mean_b loss_b)/dy = (s_b / nb)(2 w_b H^2 e_b +
+ * 2 v_b e_b), zeroed where y <= 0 when relu_mask (the backward of an output
+ * ReLU); relu_mask = 0 passes it through there (straight-through estimate,
+ * which keeps an output clamped at zero trainable).  H runs through the
+ * same operator kernels as ctof_forward / ctof_adjoint, all nb scans at once.
+ */
+ctof_status ctof_warmstart_loss_ws_bytes(ctof_kernel k, int32_t nb, size_t *ws_bytes);
+ctof_status ctof_warmstart_loss(ctof_kernel k, int32_t nb, const ctof_tensor *y, const double *s, const float *target_dev,
+                                const double *w, const double *v, double lambda, int32_t relu_mask,
+                                const ctof_tensor *grad, double *terms_dev, void *ws_dev, size_t ws_bytes,
+                                hipStream_t stream);
+
+/* Per-sample maximum magnitude: out_dev[b] = max_i |x_dev[b len + i]| (float). */
+ctof_status ctof_absmax_ws_bytes(int32_t nb, size_t *ws_bytes);
+ctof_status ctof_absmax(int32_t nb, int64_t len, const float *x_dev, float *out_dev, void *ws_dev, size_t ws_bytes,
+                        hipStream_t stream);
+
+/*
  * Adam (Kingma and Ba, 2015) with bias correction on n float master weights
  * w, gradient g and moments m, v (step counts from 1); w_bf16 (or NULL)
  * receives the updated weights rounded to BF16.
@@ -381,11 +419,12 @@ ctof_status ctof_adam_step(int64_t n, float *w_dev, const float *g_dev, float *m
                            void *w_bf16_dev, float lr, float beta1, float beta2, float eps, int32_t step,
                            hipStream_t stream);
 
-/* Dense float [n] -> BF16 channel out.c0 of n rows (times scale); zero_rest
- * zeroes the row's other ld - 1 elements.  And back: out[i] = y[i][c0] * scale
- * for an FP32 tensor y. */
+/* Dense float [n] -> BF16 channel out.c0 of n rows (v = x * scale rounded
+ * to BF16); with split, channel out.c0 + 1 receives BF16(v - BF16(v)), so the
+ * pair carries about 16 significant bits; zero_rest zeroes the row's other
+ * elements.  And back: out[i] = y[i][c0] * scale for an FP32 tensor y. */
 ctof_status ctof_to_channels_last(int64_t n, const float *x_dev, float scale, const ctof_tensor *out,
-                                  int32_t zero_rest, hipStream_t stream);
+                                  int32_t zero_rest, int32_t split, hipStream_t stream);
 ctof_status ctof_from_channels_last(int64_t n, const ctof_tensor *y, float scale, float *out_dev,
                                     hipStream_t stream);
 

@@ -324,6 +324,85 @@ ctof_status run_adjoint(ctof_kernel k, const void *r, void *g, void *ws, hipStre
   return CTOF_OK;
 }
 
+// out_v = A^T A in_v for the engine's volumes (spatial [nz][n][n])
+template <typename T>
+ctof_status enqueue_normal(const Engine<T> &E, const void *const *in, void *const *out) {
+  ctof::RowArgs a = E.row(ctof::ROW_SPATIAL_TO_SPEC, false);
+  for (int v = 0; v < E.nvol; ++v) a.sp_in[v] = in[v];
+  HIP_TRY(E.mu_to_spec(a));
+  HIP_TRY(E.fwd_to_xt());
+  HIP_TRY(E.run_row(E.row(ctof::ROW_PASS, true)));
+  HIP_TRY(E.adj_to_xz());
+  ctof::RowArgs b = E.row(ctof::ROW_SPEC_TO_SPATIAL, false);
+  for (int v = 0; v < E.nvol; ++v) b.sp_out[v] = out[v];
+  HIP_TRY(E.run_row(b));
+  return CTOF_OK;
+}
+
+// Warm-start training loss (see ctof_warmstart_loss).  Workspace: operator
+// regions for nb volumes, then e, h = H e, u = H h (float [nb][V] each) and
+// the FP64 partial sums.
+struct StartLossWs {
+  size_t op, e, h, u, part, total;
+};
+
+StartLossWs start_loss_ws(const ctof_kernel_s *k, int nb) {
+  StartLossWs o;
+  const ClassWs L = class_ws(k, nb, 1);
+  const ctof::Dims &d = k->dims;
+  const size_t vol = (size_t)nb * d.nz * d.n * d.n * sizeof(float);
+  size_t off = ctof::round_up(L.op_total, 256);
+  o.op = 0;
+  o.e = off;
+  off += ctof::round_up(vol, 256);
+  o.h = off;
+  off += ctof::round_up(vol, 256);
+  o.u = off;
+  off += ctof::round_up(vol, 256);
+  o.part = off;
+  off += ctof::round_up(ctof::sumsq_ws_bytes(nb), 256);
+  o.total = off;
+  return o;
+}
+
+ctof_status run_start_loss(const ctof_kernel_s *k, int nb, const ctof_tensor *y, const double *s, const float *target,
+                           const double *w, const double *v, double lambda, int relu_mask, const ctof_tensor *grad,
+                           double *terms, void *ws, hipStream_t st) {
+  const ctof::Dims &d = k->dims;
+  const long long V = (long long)d.nz * d.n * d.n;
+  const long long n = V * nb;
+  const StartLossWs o = start_loss_ws(k, nb);
+  char *base = reinterpret_cast<char *>(ws);
+  float *e = reinterpret_cast<float *>(base + o.e);
+  float *h = reinterpret_cast<float *>(base + o.h);
+  float *u = reinterpret_cast<float *>(base + o.u);
+  const Engine<float> E = engine<float>(k, nb, base + o.op, 1, st);
+  const float *yv = reinterpret_cast<const float *>(y->ptr);
+  ctof::StartCoef cf{};
+  for (int b = 0; b < nb; ++b) {
+    cf.s[b] = (float)s[b];
+    cf.ch[b] = (float)(2.0 * s[b] * w[b] / nb);
+    cf.ce[b] = (float)(2.0 * s[b] * v[b] / nb);
+  }
+  HIP_TRY(ctof::launch_start_error(yv, y->ld, y->c0, cf, V, target, n, e, st));
+  std::vector<const void *> ein(nb), hin(nb);
+  std::vector<void *> hout(nb), uout(nb);
+  for (int b = 0; b < nb; ++b) {
+    ein[b] = e + (size_t)b * V;
+    hout[b] = h + (size_t)b * V;
+    hin[b] = h + (size_t)b * V;
+    uout[b] = u + (size_t)b * V;
+  }
+  if (ctof_status r = enqueue_normal(E, ein.data(), hout.data()); r != CTOF_OK) return r;
+  HIP_TRY(ctof::launch_axpy(n, (float)lambda, e, h, st));
+  if (ctof_status r = enqueue_normal(E, hin.data(), uout.data()); r != CTOF_OK) return r;
+  HIP_TRY(ctof::launch_axpy(n, (float)lambda, h, u, st));
+  HIP_TRY(ctof::launch_sumsq(h, e, V, nb, reinterpret_cast<double *>(base + o.part), terms, st));
+  HIP_TRY(ctof::launch_start_grad(n, V, cf, u, e, yv, y->ld, y->c0, relu_mask, reinterpret_cast<__bf16 *>(grad->ptr),
+                                  grad->ld, grad->c0, st));
+  return CTOF_OK;
+}
+
 std::vector<double> fista_betas(int iters) {
   std::vector<double> b(iters);
   double t = 1.0;
@@ -692,7 +771,7 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
   for (size_t c = 0; c < cls.size(); ++c) {
     HIP_TRY(ctof::launch_fill_zero(E[c].scal(), 64 * 8, st));
     if (ctof_status s = enqueue_gmap0(E[c], dv[c].data()); s != CTOF_OK) return s;
-    if (opt->lipschitz == 0.0) {
+    if (opt->lipschitz == 0.0 && !opt->lipschitz_scans) {
       Engine<T> E1 = E[c];
       const bool f64 = E1.k->prec == CTOF_FP64;
       E1.nvol = 1;
@@ -704,7 +783,13 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
   }
   for (size_t c = 0; c < cls.size(); ++c) {
     double lam = opt->lambda_tikhonov, lip = opt->lipschitz, la = 0.0;
-    if (lip == 0.0) {
+    if (opt->lipschitz_scans) {
+      lip = opt->lipschitz_scans[cls[c].scans[0]];
+      lam = opt->lambda_scans[cls[c].scans[0]];
+      for (int i : cls[c].scans)
+        if (opt->lipschitz_scans[i] != lip || opt->lambda_scans[i] != lam)
+          return set_error(CTOF_EINVAL, "scans %d and %d share a handle but not L / lambda", cls[c].scans[0], i);
+    } else if (lip == 0.0) {
       double hs[2];
       HIP_TRY(hipMemcpyAsync(hs, E[c].scal(), 2 * sizeof(double), hipMemcpyDeviceToHost, st));
       HIP_TRY(hipStreamSynchronize(st));
@@ -1020,6 +1105,34 @@ KhatLayout khat_layout(const Dims &d, ctof_precision prec) {
 
 extern "C" {
 
+ctof_status ctof_warmstart_loss_ws_bytes(ctof_kernel k, int32_t nb, size_t *ws_bytes) {
+  if (ctof_status s = check_kernel(k); s != CTOF_OK) return s;
+  if (nb < 1 || nb > ctof::kMaxVol) return set_error(CTOF_EINVAL, "nb must be in [1, %d]", ctof::kMaxVol);
+  if (!ws_bytes) return set_error(CTOF_EINVAL, "ws_bytes is NULL");
+  *ws_bytes = start_loss_ws(k, nb).total;
+  return CTOF_OK;
+}
+
+ctof_status ctof_warmstart_loss(ctof_kernel k, int32_t nb, const ctof_tensor *y, const double *s, const float *target_dev,
+                                const double *w, const double *v, double lambda, int32_t relu_mask,
+                                const ctof_tensor *grad, double *terms_dev, void *ws_dev, size_t ws_bytes,
+                                hipStream_t stream) {
+  if (ctof_status r = check_kernel(k); r != CTOF_OK) return r;
+  if (k->prec == CTOF_FP64) return set_error(CTOF_EUNSUPPORTED, "the warm-start loss takes float handles");
+  if (nb < 1 || nb > ctof::kMaxVol) return set_error(CTOF_EINVAL, "nb must be in [1, %d]", ctof::kMaxVol);
+  if (!y || !y->ptr || !grad || !grad->ptr || !target_dev || !s || !w || !v || !terms_dev || !ws_dev)
+    return set_error(CTOF_EINVAL, "NULL argument");
+  if (y->c0 < 0 || y->c0 >= y->ld || grad->c0 < 0 || grad->c0 >= grad->ld)
+    return set_error(CTOF_EINVAL, "channel outside the row");
+  if (!std::isfinite(lambda) || lambda < 0) return set_error(CTOF_EINVAL, "lambda must be finite and >= 0");
+  for (int b = 0; b < nb; ++b)
+    if (!std::isfinite(s[b]) || !std::isfinite(w[b]) || !std::isfinite(v[b]))
+      return set_error(CTOF_EINVAL, "scales and weights must be finite");
+  const size_t need = start_loss_ws(k, nb).total;
+  if (ws_bytes < need) return set_error(CTOF_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
+  return run_start_loss(k, nb, y, s, target_dev, w, v, lambda, relu_mask ? 1 : 0, grad, terms_dev, ws_dev, stream);
+}
+
 const char *ctof_last_error(void) { return ctof::last_error(); }
 
 ctof_status ctof_kernel_bytes(const ctof_geometry *geom, ctof_precision prec, size_t *khat_bytes,
@@ -1158,6 +1271,8 @@ ctof_status ctof_reconstruct(ctof_kernel k, const void *d_dev, void *mu_inout_de
   if (!(std::isfinite(opts->rel_tol) && opts->rel_tol >= 0)) return set_error(CTOF_EINVAL, "rel_tol must be >= 0");
   if (opts->rel_tol > 0 && opts->check_every < 1) return set_error(CTOF_EINVAL, "check_every must be >= 1");
   if (opts->warm_start < 0 || opts->warm_start > 2) return set_error(CTOF_EINVAL, "warm_start must be 0, 1 or 2");
+  if (opts->lipschitz_scans || opts->lambda_scans)
+    return set_error(CTOF_EINVAL, "lipschitz_scans / lambda_scans are batched options");
   const ClassWs o = class_ws(k, 1, opts->max_iter);
   if (ws_bytes < o.solve_total) return set_error(CTOF_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, o.solve_total);
   std::memset(report, 0, sizeof(*report));
@@ -1199,6 +1314,13 @@ ctof_status ctof_reconstruct_batched(int32_t nscan, const ctof_kernel *k, const 
   if (opts->warm_start < 0 || opts->warm_start > 2) return set_error(CTOF_EINVAL, "warm_start must be 0, 1 or 2");
   if (opts->history_dev || opts->timing)
     return set_error(CTOF_EINVAL, "history_dev and timing are single-scan options");
+  if ((opts->lipschitz_scans == nullptr) != (opts->lambda_scans == nullptr))
+    return set_error(CTOF_EINVAL, "lipschitz_scans and lambda_scans go together");
+  if (opts->lipschitz_scans)
+    for (int i = 0; i < nscan; ++i)
+      if (!(std::isfinite(opts->lipschitz_scans[i]) && opts->lipschitz_scans[i] > 0) ||
+          !(std::isfinite(opts->lambda_scans[i]) && opts->lambda_scans[i] >= 0))
+        return set_error(CTOF_EINVAL, "scan %d: need L > 0 and lambda >= 0", i);
   size_t need = 0;
   plan_classes(nscan, k, opts->max_iter, &need);
   if (ws_bytes < need) return set_error(CTOF_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);

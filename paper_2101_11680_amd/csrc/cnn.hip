@@ -431,15 +431,20 @@ __global__ void adam_kernel(float *__restrict__ w, const float *__restrict__ g, 
 }
 
 // Dense FP32 volume -> BF16 channel c0 of rows of length ld (other channels
-// of each row zeroed when zero_rest), times scale.
+// of each row zeroed when zero_rest), times scale; with split, channel c0 + 1
+// receives the BF16 rounding of the remainder (a hi/lo pair carrying ~16
+// significant bits).
 __global__ void to_channels_last_kernel(const float *__restrict__ x, long long n, float scale,
-                                        __bf16 *__restrict__ out, int ld, int c0, int zero_rest) {
+                                        __bf16 *__restrict__ out, int ld, int c0, int zero_rest, int split) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   if (zero_rest)
     for (int c = 0; c < ld; ++c)
-      if (c != c0) out[(size_t)i * ld + c] = (__bf16)0.0f;
-  out[(size_t)i * ld + c0] = (__bf16)(x[i] * scale);
+      if (c != c0 && !(split && c == c0 + 1)) out[(size_t)i * ld + c] = (__bf16)0.0f;
+  const float v = x[i] * scale;
+  const __bf16 hi = (__bf16)v;
+  out[(size_t)i * ld + c0] = hi;
+  if (split) out[(size_t)i * ld + c0 + 1] = (__bf16)(v - (float)hi);
 }
 
 __global__ void from_channels_last_kernel(const float *__restrict__ y, int ld, int c0, long long n, float scale,
@@ -449,9 +454,151 @@ __global__ void from_channels_last_kernel(const float *__restrict__ y, int ld, i
   out[i] = y[(size_t)i * ld + c0] * scale;
 }
 
+// ---- warm-start training loss helpers --------------------------------------------
+// e[b][i] = s_b * y[(b V + i) ld + c0] - t[b][i]
+__global__ void start_error_kernel(const float *__restrict__ y, int ld, int c0, StartCoef cf, long long V,
+                                   const float *__restrict__ t, long long n, float *__restrict__ e) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  e[i] = cf.s[i / V] * y[(size_t)i * ld + c0] - t[i];
+}
+
+// y[i] += a * x[i]
+__global__ void axpy_kernel(long long n, float a, const float *__restrict__ x, float *__restrict__ y) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] += a * x[i];
+}
+
+// Block (c, b): FP64 partial sums of u^2 and v^2 over chunk c of sample b.
+constexpr int kSqChunks = 64;
+__global__ void __launch_bounds__(256)
+sumsq_partial_kernel(const float *__restrict__ u, const float *__restrict__ v, long long V,
+                     double *__restrict__ part) {
+  __shared__ double ra[256], rb[256];
+  const int c = blockIdx.x, b = blockIdx.y;
+  const long long per = (V + kSqChunks - 1) / kSqChunks;
+  const long long i0 = (long long)c * per, i1 = i0 + per < V ? i0 + per : V;
+  double a = 0.0, q = 0.0;
+  for (long long i = i0 + threadIdx.x; i < i1; i += 256) {
+    const double x = u[(size_t)b * V + i], z = v[(size_t)b * V + i];
+    a += x * x;
+    q += z * z;
+  }
+  ra[threadIdx.x] = a;
+  rb[threadIdx.x] = q;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) {
+      ra[threadIdx.x] += ra[threadIdx.x + k];
+      rb[threadIdx.x] += rb[threadIdx.x + k];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[((size_t)b * kSqChunks + c) * 2] = ra[0];
+    part[((size_t)b * kSqChunks + c) * 2 + 1] = rb[0];
+  }
+}
+
+__global__ void sumsq_total_kernel(const double *__restrict__ part, int nb, double *__restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  double a = 0.0, q = 0.0;
+  for (int c = 0; c < kSqChunks; ++c) {
+    a += part[((size_t)b * kSqChunks + c) * 2];
+    q += part[((size_t)b * kSqChunks + c) * 2 + 1];
+  }
+  out[2 * b] = a;
+  out[2 * b + 1] = q;
+}
+
+// grad[(b V + i) gld + gc0] = ch[b] u[b][i] + ce[b] e[b][i], zeroed where y <= 0
+// when relu_mask
+__global__ void start_grad_kernel(long long n, long long V, StartCoef cf, const float *__restrict__ u,
+                                  const float *__restrict__ e, const float *__restrict__ y, int yld, int yc0,
+                                  int relu_mask, __bf16 *__restrict__ g, int gld, int gc0) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int b = (int)(i / V);
+  const float yi = y[(size_t)i * yld + yc0];
+  const float v = (yi > 0.0f || !relu_mask) ? cf.ch[b] * u[i] + cf.ce[b] * e[i] : 0.0f;
+  g[(size_t)i * gld + gc0] = (__bf16)v;
+}
+
+// Block (c, b): max |x| over chunk c of sample b; then per sample.
+constexpr int kAbsChunks = 64;
+__global__ void __launch_bounds__(256)
+absmax_partial_kernel(const float *__restrict__ x, long long V, float *__restrict__ part) {
+  __shared__ float red[256];
+  const int c = blockIdx.x, b = blockIdx.y;
+  const long long per = (V + kAbsChunks - 1) / kAbsChunks;
+  const long long i0 = (long long)c * per, i1 = i0 + per < V ? i0 + per : V;
+  float m = 0.0f;
+  for (long long i = i0 + threadIdx.x; i < i1; i += 256) m = fmaxf(m, fabsf(x[(size_t)b * V + i]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + k]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(size_t)b * kAbsChunks + c] = red[0];
+}
+
+__global__ void absmax_total_kernel(const float *__restrict__ part, int nb, float *__restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nb) return;
+  float m = 0.0f;
+  for (int c = 0; c < kAbsChunks; ++c) m = fmaxf(m, part[(size_t)b * kAbsChunks + c]);
+  out[b] = m;
+}
+
 inline unsigned blocks_for(long long n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
+
+size_t absmax_ws_bytes(int nb) { return (size_t)nb * kAbsChunks * sizeof(float); }
+
+hipError_t launch_absmax(const float *x, long long V, int nb, float *part, float *out, hipStream_t st) {
+  if (V == 0 || nb == 0) return hipSuccess;
+  hipLaunchKernelGGL(absmax_partial_kernel, dim3(kAbsChunks, (unsigned)nb), dim3(256), 0, st, x, V, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(absmax_total_kernel, dim3((unsigned)((nb + 63) / 64)), dim3(64), 0, st, part, nb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_start_error(const float *y, int ld, int c0, const StartCoef &cf, long long V, const float *t,
+                              long long n, float *e, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(start_error_kernel, dim3(blocks_for(n)), dim3(256), 0, st, y, ld, c0, cf, V, t, n, e);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy(long long n, float a, const float *x, float *y, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(axpy_kernel, dim3(blocks_for(n)), dim3(256), 0, st, n, a, x, y);
+  return hipGetLastError();
+}
+
+size_t sumsq_ws_bytes(int nb) { return (size_t)nb * kSqChunks * 2 * sizeof(double); }
+
+hipError_t launch_sumsq(const float *u, const float *v, long long V, int nb, double *part, double *out,
+                        hipStream_t st) {
+  hipLaunchKernelGGL(sumsq_partial_kernel, dim3(kSqChunks, (unsigned)nb), dim3(256), 0, st, u, v, V, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(sumsq_total_kernel, dim3(1), dim3(64), 0, st, part, nb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_start_grad(long long n, long long V, const StartCoef &cf, const float *u, const float *e,
+                             const float *y, int yld, int yc0, int relu_mask, __bf16 *g, int gld, int gc0,
+                             hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(start_grad_kernel, dim3(blocks_for(n)), dim3(256), 0, st, n, V, cf, u, e, y, yld, yc0,
+                     relu_mask, g, gld, gc0);
+  return hipGetLastError();
+}
 
 int cnn_cip(int ci) { return (ci + 7) / 8 * 8; }
 int cnn_copad(int co) { return (co + 15) / 16 * 16; }
@@ -624,10 +771,10 @@ hipError_t launch_adam(float *w, const float *g, float *m, float *v, __bf16 *wb,
 }
 
 hipError_t launch_to_channels_last(const float *x, long long n, float scale, __bf16 *out, int ld, int c0,
-                                   int zero_rest, hipStream_t st) {
+                                   int zero_rest, int split, hipStream_t st) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(to_channels_last_kernel, dim3(blocks_for(n)), dim3(256), 0, st, x, n, scale, out, ld, c0,
-                     zero_rest);
+                     zero_rest, split);
   return hipGetLastError();
 }
 

@@ -209,11 +209,12 @@ ctof_status ctof_adam_step(int64_t n, float *w_dev, const float *g_dev, float *m
 }
 
 ctof_status ctof_to_channels_last(int64_t n, const float *x_dev, float scale, const ctof_tensor *out,
-                                  int32_t zero_rest, hipStream_t stream) {
+                                  int32_t zero_rest, int32_t split, hipStream_t stream) {
   if (n < 0 || n > kMaxRows) return set_error(CTOF_EINVAL, "bad n");
   if (!x_dev) return set_error(CTOF_EINVAL, "x is NULL");
-  CHECK(check_write(out, 1, 2, "out"));
-  HIP_TRY(ctof::launch_to_channels_last(x_dev, n, scale, bfw(out->ptr), out->ld, out->c0, zero_rest ? 1 : 0, stream));
+  CHECK(check_write(out, split ? 2 : 1, 2, "out"));
+  HIP_TRY(ctof::launch_to_channels_last(x_dev, n, scale, bfw(out->ptr), out->ld, out->c0, zero_rest ? 1 : 0,
+                                        split ? 1 : 0, stream));
   return CTOF_OK;
 }
 
@@ -258,6 +259,23 @@ ctof_status ctof_noisy_histogram(int64_t n, const float *m_dev, double peak, uin
   if (!ws_dev || (reinterpret_cast<uintptr_t>(ws_dev) & 15)) return set_error(CTOF_EINVAL, "workspace NULL or misaligned");
   if (ws_bytes < need) return set_error(CTOF_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
   HIP_TRY(ctof::launch_noisy_histogram(m_dev, n, peak, seed, stream_id, d_dev, ws_dev, stream));
+  return CTOF_OK;
+}
+
+ctof_status ctof_absmax_ws_bytes(int32_t nb, size_t *ws_bytes) {
+  if (nb < 1 || nb > 65535) return set_error(CTOF_EINVAL, "nb must be in [1, 65535]");
+  if (!ws_bytes) return set_error(CTOF_EINVAL, "ws_bytes is NULL");
+  *ws_bytes = (ctof::absmax_ws_bytes(nb) + 255) / 256 * 256;
+  return CTOF_OK;
+}
+
+ctof_status ctof_absmax(int32_t nb, int64_t len, const float *x_dev, float *out_dev, void *ws_dev, size_t ws_bytes,
+                        hipStream_t stream) {
+  if (nb < 1 || nb > 65535 || len < 0 || len > kMaxRows) return set_error(CTOF_EINVAL, "bad nb / len");
+  if (!x_dev || !out_dev || !ws_dev) return set_error(CTOF_EINVAL, "NULL argument");
+  const size_t need = ctof::absmax_ws_bytes(nb);
+  if (ws_bytes < need) return set_error(CTOF_ENOMEM, "workspace %zu bytes < %zu needed", ws_bytes, need);
+  HIP_TRY(ctof::launch_absmax(x_dev, len, nb, reinterpret_cast<float *>(ws_dev), out_dev, stream));
   return CTOF_OK;
 }
 

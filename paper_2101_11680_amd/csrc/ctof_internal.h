@@ -240,9 +240,24 @@ hipError_t launch_mse(const float *y, int yld, int yc0, float ys, const float *t
 hipError_t launch_adam(float *w, const float *g, float *m, float *v, __bf16 *wb, long long n, float lr, float b1,
                        float b2, float eps, int step, hipStream_t st);
 hipError_t launch_to_channels_last(const float *x, long long n, float scale, __bf16 *out, int ld, int c0,
-                                   int zero_rest, hipStream_t st);
+                                   int zero_rest, int split, hipStream_t st);
 hipError_t launch_from_channels_last(const float *y, int ld, int c0, long long n, float scale, float *out,
                                      hipStream_t st);
+
+struct StartCoef {
+  float s[kMaxVol], ch[kMaxVol], ce[kMaxVol];
+};
+hipError_t launch_start_error(const float *y, int ld, int c0, const StartCoef &cf, long long V, const float *t,
+                              long long n, float *e, hipStream_t st);
+size_t absmax_ws_bytes(int nb);
+hipError_t launch_absmax(const float *x, long long V, int nb, float *part, float *out, hipStream_t st);
+hipError_t launch_axpy(long long n, float a, const float *x, float *y, hipStream_t st);
+size_t sumsq_ws_bytes(int nb);
+hipError_t launch_sumsq(const float *u, const float *v, long long V, int nb, double *part, double *out,
+                        hipStream_t st);
+hipError_t launch_start_grad(long long n, long long V, const StartCoef &cf, const float *u, const float *e,
+                             const float *y, int yld, int yc0, int relu_mask, __bf16 *g, int gld, int gc0,
+                             hipStream_t st);
 
 hipError_t launch_philox(uint64_t seed, uint32_t stream_id, long long first, long long n, uint32_t *out,
                          hipStream_t st);

@@ -31,7 +31,8 @@ EXPORTS = ("ctof_kernel_bytes", "ctof_kernel_tabulate", "ctof_kernel_tabulate_qu
            "ctof_conv3d_bwd_data", "ctof_conv3d_bwd_weight_ws_bytes", "ctof_conv3d_bwd_weight",
            "ctof_relu_bwd", "ctof_mse_ws_bytes", "ctof_mse", "ctof_adam_step",
            "ctof_to_channels_last", "ctof_from_channels_last", "ctof_philox4x32", "ctof_poisson",
-           "ctof_noisy_histogram_ws_bytes", "ctof_noisy_histogram")
+           "ctof_noisy_histogram_ws_bytes", "ctof_noisy_histogram", "ctof_warmstart_loss_ws_bytes",
+           "ctof_warmstart_loss", "ctof_absmax_ws_bytes", "ctof_absmax")
 
 
 class CtofError(RuntimeError):
@@ -53,7 +54,8 @@ class _SolverOpts(ctypes.Structure):
                 ("lipschitz", ctypes.c_double), ("power_iters", ctypes.c_int32),
                 ("rel_tol", ctypes.c_double), ("check_every", ctypes.c_int32),
                 ("warm_start", ctypes.c_int32), ("history_dev", ctypes.c_void_p),
-                ("timing", ctypes.c_int32)]
+                ("timing", ctypes.c_int32), ("lipschitz_scans", ctypes.POINTER(ctypes.c_double)),
+                ("lambda_scans", ctypes.POINTER(ctypes.c_double))]
 
 
 class _SolverReport(ctypes.Structure):
@@ -123,12 +125,18 @@ def lib() -> ctypes.CDLL:
         L.ctof_mse_ws_bytes.argtypes = [i64, ctypes.POINTER(sz)]
         L.ctof_mse.argtypes = [i64, tp, f32, vp, tp, i32, vp, vp, sz, vp]
         L.ctof_adam_step.argtypes = [i64, vp, vp, vp, vp, vp, f32, f32, f32, f32, i32, vp]
-        L.ctof_to_channels_last.argtypes = [i64, vp, f32, tp, i32, vp]
+        L.ctof_to_channels_last.argtypes = [i64, vp, f32, tp, i32, i32, vp]
         L.ctof_from_channels_last.argtypes = [i64, tp, f32, vp, vp]
         L.ctof_philox4x32.argtypes = [u64, u32, i64, i64, vp, vp]
         L.ctof_poisson.argtypes = [i64, vp, u64, u32, vp, vp]
         L.ctof_noisy_histogram_ws_bytes.argtypes = [i64, ctypes.POINTER(sz)]
         L.ctof_noisy_histogram.argtypes = [i64, vp, ctypes.c_double, u64, u32, vp, vp, sz, vp]
+        dptr = ctypes.POINTER(ctypes.c_double)
+        L.ctof_warmstart_loss_ws_bytes.argtypes = [vp, i32, ctypes.POINTER(sz)]
+        L.ctof_warmstart_loss.argtypes = [vp, i32, tp, dptr, vp, dptr, dptr, ctypes.c_double, i32, tp, vp, vp, sz,
+                                          vp]
+        L.ctof_absmax_ws_bytes.argtypes = [i32, ctypes.POINTER(sz)]
+        L.ctof_absmax.argtypes = [i32, i64, vp, vp, vp, sz, vp]
         L.ctof_last_error.argtypes = []
         L.ctof_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -345,11 +353,13 @@ def _report(rep) -> Report:
                   rep.ms_fft_t, rep.ms_contract_adj, rep.ms_fft_z, rep.ms_loop, rep.fell_back)
 
 
-def reconstruct_batched(kernels, ds, mus=None, max_iter: int = 200, lam: float = -1.0,
-                        lipschitz: float = 0.0, power_iters: int = 50, rel_tol: float = 0.0,
-                        check_every: int = 10, warm_start: bool = False, stream=None):
+def reconstruct_batched(kernels, ds, mus=None, max_iter: int = 200, lam=-1.0, lipschitz=0.0,
+                        power_iters: int = 50, rel_tol: float = 0.0, check_every: int = 10,
+                        warm_start: bool = False, stream=None):
     """FISTA for many scans at once; scans sharing a Kernel object form one
-    shape class.  Returns (list of mu, list of Report)."""
+    shape class.  lam / lipschitz: one value for all scans or one per scan
+    (both sequences, then every scan's pair is used as given).  warm_start as
+    in reconstruct.  Returns (list of mu, list of Report)."""
     torch = _torch()
     n = len(ds)
     if len(kernels) != n:
@@ -370,8 +380,15 @@ def reconstruct_batched(kernels, ds, mus=None, max_iter: int = 200, lam: float =
     nb = ctypes.c_size_t()
     _check(lib().ctof_workspace_bytes_batched(n, handles, int(max_iter), ctypes.byref(nb)))
     ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=ds[0].device)
-    opts = _SolverOpts(int(max_iter), float(lam), float(lipschitz), int(power_iters),
-                       float(rel_tol), int(check_every), int(warm_start), None, 0)
+    per_scan = not isinstance(lipschitz, (int, float))
+    if per_scan:
+        la = (ctypes.c_double * n)(*[float(x) for x in lipschitz])
+        lb = (ctypes.c_double * n)(*[float(x) for x in lam])
+        opts = _SolverOpts(int(max_iter), 0.0, 0.0, int(power_iters), float(rel_tol), int(check_every),
+                           int(warm_start), None, 0, la, lb)
+    else:
+        opts = _SolverOpts(int(max_iter), float(lam), float(lipschitz), int(power_iters),
+                           float(rel_tol), int(check_every), int(warm_start), None, 0)
     reps = (_SolverReport * n)()
     _check(lib().ctof_reconstruct_batched(n, handles, dptr, mptr, ctypes.byref(opts), reps,
                                           ws.data_ptr(), ws.numel(), _stream_ptr(stream)))

@@ -182,9 +182,9 @@ def adam_step(w, g, m, v, w_bf16, lr, step, b1=0.9, b2=0.999, eps=1e-8, stream=N
                                 float(b2), float(eps), int(step), _stream_ptr(stream)))
 
 
-def to_channels_last(x, scale: float, out: Slice, zero_rest=False, stream=None):
+def to_channels_last(x, scale: float, out: Slice, zero_rest=False, split=False, stream=None):
     _check(lib().ctof_to_channels_last(int(x.numel()), x.data_ptr(), float(scale), ctypes.byref(out.t()),
-                                       int(bool(zero_rest)), _stream_ptr(stream)))
+                                       int(bool(zero_rest)), int(bool(split)), _stream_ptr(stream)))
 
 
 def from_channels_last(y: Slice, scale: float, out, stream=None):
@@ -216,4 +216,33 @@ def noisy_histogram(m, peak: float, seed: int, stream_id: int = 0, out=None, str
     ws = workspace(nb.value, m.device, "noisy")
     _check(lib().ctof_noisy_histogram(int(m.numel()), m.data_ptr(), float(peak), int(seed), int(stream_id),
                                       out.data_ptr(), ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
+    return out
+
+
+def warmstart_loss(kernel, nb: int, y: Slice, s, target, w, v, lam: float, grad: Slice, terms,
+                   relu_mask=True, stream=None):
+    """Operator-weighted start loss (see ctof_warmstart_loss); s (a number
+    or nb of them), w, v: host weights; terms: device float64 [>= nb, 2]."""
+    nbytes = ctypes.c_size_t()
+    _check(lib().ctof_warmstart_loss_ws_bytes(kernel.handle, int(nb), ctypes.byref(nbytes)))
+    ws = workspace(nbytes.value, target.device, "start_loss")
+    s = [float(s)] * nb if isinstance(s, (int, float)) else [float(x) for x in s]
+    sa = (ctypes.c_double * nb)(*s)
+    wa = (ctypes.c_double * nb)(*[float(x) for x in w])
+    va = (ctypes.c_double * nb)(*[float(x) for x in v])
+    _check(lib().ctof_warmstart_loss(kernel.handle, int(nb), ctypes.byref(y.t()), sa, target.data_ptr(), wa,
+                                     va, float(lam), int(bool(relu_mask)), ctypes.byref(grad.t()), terms.data_ptr(),
+                                     ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
+
+
+def absmax(x, nb: int, stream=None):
+    """max |x[b]| per sample of a float32 tensor with nb leading rows (device
+    float32 [nb])."""
+    torch = _torch()
+    out = torch.empty(nb, dtype=torch.float32, device=x.device)
+    nbytes = ctypes.c_size_t()
+    _check(lib().ctof_absmax_ws_bytes(int(nb), ctypes.byref(nbytes)))
+    ws = workspace(nbytes.value, x.device, "absmax")
+    _check(lib().ctof_absmax(int(nb), int(x.numel() // nb), x.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(),
+                             _stream_ptr(stream)))
     return out

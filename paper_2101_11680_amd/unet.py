@@ -48,11 +48,11 @@ def _torch():
     return torch
 
 
-def layer_list(ch=DEFAULT_CH) -> List[Tuple[str, int, int, int]]:
+def layer_list(ch=DEFAULT_CH, c_in: int = 1) -> List[Tuple[str, int, int, int]]:
     """(name, kind, co, ci) in execution order."""
     c1, c2, c3, c4 = ch
     out = []
-    prev = 1
+    prev = c_in
     for lvl, c in ((1, c1), (2, c2), (3, c3)):
         out += [(f"e{lvl}a", K3, c, prev), (f"e{lvl}b", K3, c, c), (f"d{lvl}", DN, c, c)]
         prev = c
@@ -82,14 +82,18 @@ class _Param:
 class UNet:
     """Parameters, activation buffers and the forward/backward sequence."""
 
-    def __init__(self, ch=DEFAULT_CH, device="cuda", seed: int = 0):
+    def __init__(self, ch=DEFAULT_CH, device="cuda", seed: int = 0, split_input: bool = True):
         torch = _torch()
         for c in ch:
             if c % 8 or c < 8:
                 raise ValueError("channel counts must be multiples of 8")
         self.ch = tuple(int(c) for c in ch)
         self.device = torch.device(device)
-        self.layers = layer_list(self.ch)
+        # the input volume enters as a BF16 hi/lo pair (two channels) or as
+        # one BF16 channel
+        self.split_input = bool(split_input)
+        self.c_in = 2 if self.split_input else 1
+        self.layers = layer_list(self.ch, self.c_in)
         self.params: Dict[str, _Param] = {}
         off = 0
         for name, kind, co, ci in self.layers:
@@ -107,8 +111,11 @@ class UNet:
         self.m = torch.zeros(off, **f32)
         self.v = torch.zeros(off, **f32)
         self.step_count = 0
-        self.in_scale = 1.0   # network input = x * in_scale
-        self.out_scale = 1.0  # start volume = network output * out_scale
+        # per-sample normalisation: the input is A^T d / max|A^T d| (times
+        # in_scale), the start is output * out_scale * tau * max|A^T d|, so the
+        # network sees unit-scale inputs whatever the absorbers' depth
+        self.in_scale = 1.0
+        self.out_scale = 1.0
         self._bufs = None
         self._shape = None
         self.loss_dev = torch.zeros(1, dtype=torch.float64, device=self.device)
@@ -213,15 +220,17 @@ class UNet:
         c = self.ch
         x = x.contiguous()
         if isinstance(scale, (int, float)):
-            nn.to_channels_last(x, float(scale) * self.in_scale, Slice(A["input"], 0, 1), stream=stream)
+            nn.to_channels_last(x, float(scale) * self.in_scale, Slice(A["input"], 0, self.c_in),
+                                split=self.split_input, stream=stream)
         else:
             R = D * H * W
             for i in range(n):
                 nn.to_channels_last(x[i], float(scale[i]) * self.in_scale,
-                                    Slice(A["input"][i * R:(i + 1) * R], 0, 1), stream=stream)
+                                    Slice(A["input"][i * R:(i + 1) * R], 0, self.c_in), split=self.split_input,
+                                    stream=stream)
         run = lambda name, lvl, src, dst: nn.conv_fwd(self._conv(name, lvl), src, *self._w(name), dst,
                                                       relu=True, stream=stream)
-        h = Slice(A["input"], 0, 1)
+        h = Slice(A["input"], 0, self.c_in)
         for l in (1, 2, 3):
             cl = c[l - 1]
             run(f"e{l}a", l - 1, h, Slice(A[f"e{l}a"]))
@@ -278,7 +287,7 @@ class UNet:
             self._back(f"d{l}", l - 1, skip_a, S(G[f"d{l}"]), S(A[f"d{l}"]), skip_g, accumulate=True,
                        stream=stream)
             self._back(f"e{l}b", l - 1, S(A[f"e{l}a"]), skip_g, skip_a, S(G[f"e{l}a"]), stream=stream)
-            prev_a = S(A["input"], 0, 1) if l == 1 else S(A[f"d{l - 1}"])
+            prev_a = S(A["input"], 0, self.c_in) if l == 1 else S(A[f"d{l - 1}"])
             prev_g = None if l == 1 else S(G[f"d{l - 1}"])
             self._back(f"e{l}a", l - 1, prev_a, S(G[f"e{l}a"]), S(A[f"e{l}a"]), prev_g, stream=stream)
 
@@ -293,46 +302,93 @@ class UNet:
         self.backward_from_output_grad(stream=stream)
         return self.loss_dev
 
+    def start_scales(self, x, tau, stream=None):
+        """Per-sample (input scale, output scale) of back-projections x
+        [n, ...] for step sizes tau (a number or one per sample)."""
+        n = x.shape[0]
+        m = nn.absmax(x.contiguous(), n, stream=stream).cpu().numpy().astype(np.float64)
+        taus = [float(tau)] * n if isinstance(tau, (int, float)) else [float(t) for t in tau]
+        s_in = [self.in_scale / mb if mb > 0 else 0.0 for mb in m]
+        s_out = [self.out_scale * t * mb for t, mb in zip(taus, m)]
+        return s_in, s_out
+
+    def loss_and_backward_operator(self, kernel, target, w, v, lam: float, s_out, straight_through: bool = True,
+                                   stream=None):
+        """Operator-weighted loss w_b ||H e_b||^2 + v_b ||e_b||^2 of the start
+        volumes (H = A^T A + lambda I of the scans' handle; e = start -
+        target); fills the gradients; returns the device terms [n, 2].  With
+        straight_through the head's ReLU passes the gradient where it clamps,
+        so outputs pushed below zero can recover."""
+        torch = _torch()
+        A, G = self._bufs
+        n = self._shape[0]
+        if getattr(self, "_terms", None) is None:
+            self._terms = torch.zeros((64, 2), dtype=torch.float64, device=self.device)
+        nn.warmstart_loss(kernel, n, Slice(A["head"], 0, 1), s_out, target.contiguous(), w, v, lam,
+                          Slice(G["head"], 0, 1), self._terms, relu_mask=not straight_through, stream=stream)
+        self.backward_from_output_grad(stream=stream)
+        return self._terms[:n]
+
     def adam(self, lr: float, stream=None) -> None:
         self.step_count += 1
         nn.adam_step(self.master, self.grad, self.m, self.v, self.work, lr, self.step_count, stream=stream)
 
     # ---- inference ----------------------------------------------------------------
-    def predict(self, x, scale=1.0, stream=None):
-        """Start volumes (float32 [n, D, H, W]) from back-projections x with
-        the per-sample (or common) scale tau."""
+    def predict(self, x, tau=1.0, stream=None):
+        """Start volumes (float32 [n, D, H, W]) from back-projections A^T d
+        (x) of scans with step sizes tau (a number or one per sample)."""
         torch = _torch()
-        head = self.forward(x, scale, stream=stream)
+        s_in, s_out = self.start_scales(x, tau, stream=stream)
+        head = self.forward(x, s_in, stream=stream)
         out = torch.empty(x.shape, dtype=torch.float32, device=self.device)
-        nn.from_channels_last(Slice(head, 0, 1), self.out_scale, out, stream=stream)
+        R = int(np.prod(x.shape[1:]))
+        for b in range(x.shape[0]):
+            nn.from_channels_last(Slice(head[b * R:(b + 1) * R], 0, 1), s_out[b], out[b], stream=stream)
         return out
 
     # ---- checkpoints ----------------------------------------------------------------
-    def save(self, path: str, extra: Optional[dict] = None) -> None:
-        """FP32 master weights, Adam moments, step, scales (npz, no pickles)."""
-        meta = dict(ch=list(self.ch), step=self.step_count, in_scale=self.in_scale, out_scale=self.out_scale)
+    def save(self, path: str, extra: Optional[dict] = None, weights_only: bool = False) -> None:
+        """FP32 master weights, Adam moments (unless weights_only), step and
+        scales (npz of plain arrays, no pickles)."""
+        meta = dict(ch=list(self.ch), split_input=self.split_input, step=self.step_count, in_scale=self.in_scale,
+                    out_scale=self.out_scale)
+        meta.update(getattr(self, "meta_extra", {}))
         meta.update(extra or {})
-        np.savez(path, master=self.master.cpu().numpy(), m=self.m.cpu().numpy(), v=self.v.cpu().numpy(),
-                 meta=np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8))
+        arrays = dict(master=self.master.cpu().numpy(), meta=np.frombuffer(json.dumps(meta).encode(), dtype=np.uint8))
+        if not weights_only:
+            arrays.update(m=self.m.cpu().numpy(), v=self.v.cpu().numpy())
+        np.savez(path, **arrays)
 
     @classmethod
     def load(cls, path: str, device="cuda") -> "UNet":
         torch = _torch()
         z = np.load(path, allow_pickle=False)
         meta = json.loads(bytes(z["meta"]).decode())
-        net = cls(tuple(meta["ch"]), device=device)
+        net = cls(tuple(meta["ch"]), device=device, split_input=bool(meta.get("split_input", False)))
         master = torch.from_numpy(z["master"])
         if master.numel() != net.size:
             raise ValueError("checkpoint does not match the architecture")
         net.master.copy_(master)
         net.work.copy_(master.to(torch.bfloat16))
-        net.m.copy_(torch.from_numpy(z["m"]))
-        net.v.copy_(torch.from_numpy(z["v"]))
+        if "m" in z.files:
+            net.m.copy_(torch.from_numpy(z["m"]))
+            net.v.copy_(torch.from_numpy(z["v"]))
         net.step_count = int(meta["step"])
         net.in_scale = float(meta["in_scale"])
         net.out_scale = float(meta["out_scale"])
         net.meta = meta
+        net.meta_extra = {k: v for k, v in meta.items()
+                          if k not in ("ch", "split_input", "step", "in_scale", "out_scale")}
         return net
+
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "warmstart_64x64x32.npz")
+
+
+def load_default(device="cuda") -> "UNet":
+    """The shipped network, trained on the 64 x 64 x 32-layer, 256-bin
+    geometry (see the checkpoint's metadata for the recipe)."""
+    return UNet.load(WEIGHTS, device=device)
 
 
 # ---- data and warm start -------------------------------------------------------------

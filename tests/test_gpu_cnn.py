@@ -256,7 +256,7 @@ def _net_and_data(seed=0, n=2, grid=(8, 16, 8)):
     for k in P:
         P[k] = _bf(P[k]) if k.endswith(".w") else r.uniform(0.0, 0.1, P[k].shape).astype(np.float32).astype(
             np.float64)
-    net = unet.UNet(CH, seed=seed)
+    net = unet.UNet(CH, seed=seed, split_input=False)
     net.load_logical(P)
     x = np.abs(r.standard_normal((n,) + grid)).astype(np.float32)
     t = np.abs(r.standard_normal((n,) + grid)).astype(np.float32)
@@ -265,11 +265,39 @@ def _net_and_data(seed=0, n=2, grid=(8, 16, 8)):
 
 def test_unet_forward_matches_oracle_with_bf16_storage():
     net, P, x, _ = _net_and_data()
-    y = net.predict(torch.tensor(x, device="cuda")).cpu().numpy()
-    ref, _ = ocnn.unet_forward(P, x[..., None].astype(np.float64), CH, store=_bf)
-    err = np.linalg.norm(y - ref[..., 0]) / np.linalg.norm(ref)
+    net.out_scale = 0.5
+    tau = 2.0
+    y = net.predict(torch.tensor(x, device="cuda"), tau).cpu().numpy()
+    # per-sample normalisation: input / max|x_b|, output * out_scale * tau * max|x_b|
+    m = np.abs(x).reshape(x.shape[0], -1).max(axis=1).astype(np.float64)
+    s_in = np.float32(1.0 / m)
+    xin = x.astype(np.float64) * s_in[:, None, None, None]
+    ref, _ = ocnn.unet_forward(P, xin[..., None], CH, store=_bf)
+    ref = ref[..., 0] * (0.5 * tau * m)[:, None, None, None]
+    err = np.linalg.norm(y - ref) / np.linalg.norm(ref)
     print("network forward rel L2", err)
     assert err <= 2e-2
+
+
+def test_unet_split_input_forward_matches_oracle():
+    """Input as a BF16 hi/lo channel pair (two input channels)."""
+    from paper_2101_11680_amd import unet
+    P = ocnn.init_params(CH, 7, c_in=2)
+    r = np.random.default_rng(8)
+    for k in P:
+        P[k] = _bf(P[k]) if k.endswith(".w") else r.uniform(0.0, 0.1, P[k].shape).astype(np.float32).astype(
+            np.float64)
+    net = unet.UNet(CH, seed=7, split_input=True)
+    net.load_logical(P)
+    x = np.abs(r.standard_normal((2, 8, 8, 16))).astype(np.float32)
+    y = net.predict(torch.tensor(x, device="cuda"), 1.0).cpu().numpy()
+    m = np.abs(x).reshape(2, -1).max(axis=1).astype(np.float64)
+    v = (x * np.float32(1.0 / m)[:, None, None, None].astype(np.float32)).astype(np.float32).astype(np.float64)
+    hi = _bf(v)
+    lo = _bf(v - hi)
+    ref, _ = ocnn.unet_forward(P, np.stack([hi, lo], axis=-1), CH, store=_bf)
+    ref = ref[..., 0] * m[:, None, None, None]
+    assert np.linalg.norm(y - ref) / np.linalg.norm(ref) <= 2e-2
 
 
 def test_unet_gradients_match_oracle_with_bf16_storage():
@@ -303,3 +331,50 @@ def test_unet_training_reduces_loss():
         net.adam(3e-3)
     print("loss", losses[0], "->", losses[-1])
     assert losses[-1] < 0.3 * losses[0]
+
+
+# ---- operator-weighted start loss -----------------------------------------------------------
+
+def test_warmstart_loss_matches_oracle_operator():
+    from oracle import kernel as okernel
+    from oracle import operator as oop
+    from paper_2101_11680_amd import ctof, nn
+    from synth import workloads
+    g = workloads.geometry_for("tiny")
+    F = oop.FFTOperator(okernel.tabulate(g))
+    k = ctof.tabulate(g, ctof.FP32)
+    i = k.info
+    V = i.nz * i.n * i.n
+    nb, s, lam = 3, 0.7, 2.5e-4 * 1.0
+    r = np.random.default_rng(30)
+    y = r.standard_normal((nb * V, 2)).astype(np.float32)
+    t = np.abs(r.standard_normal((nb, i.nz, i.n, i.n))).astype(np.float32)
+    w = [0.5, 1.5, 2.0]
+    v = [0.1, 0.2, 0.3]
+    grad = torch.zeros((nb * V, 8), dtype=torch.bfloat16, device="cuda")
+    terms = torch.zeros((nb, 2), dtype=torch.float64, device="cuda")
+    nn.warmstart_loss(k, nb, nn.Slice(torch.tensor(y, device="cuda"), 1, 1), s, torch.tensor(t, device="cuda"),
+                      w, v, lam, nn.Slice(grad, 0, 1), terms)
+    got_terms = terms.cpu().numpy()
+    got_grad = _host(grad)[:, 0]
+    yv = y[:, 1].astype(np.float64).reshape(nb, i.nz, i.n, i.n)
+    refs = []
+    for b in range(nb):
+        e = s * yv[b] - t[b]
+        H = lambda x: F.adjoint(F.forward(x)) + lam * x
+        h = H(e)
+        u = H(h)
+        assert got_terms[b, 0] == pytest.approx(np.sum(h * h), rel=1e-4)
+        assert got_terms[b, 1] == pytest.approx(np.sum(e * e), rel=1e-5)
+        full = ((s / nb) * (2 * w[b] * u + 2 * v[b] * e)).ravel()
+        ref = np.where(yv[b].ravel() > 0, full, 0.0)
+        gb = got_grad[b * V:(b + 1) * V]
+        tol = 2.0 ** -8 * np.abs(ref) + 1e-4 * np.max(np.abs(ref))
+        assert np.all(np.abs(gb - ref) <= tol)
+        refs.append(full)
+    # straight-through: the gradient also where the output is clamped
+    nn.warmstart_loss(k, nb, nn.Slice(torch.tensor(y, device="cuda"), 1, 1), s, torch.tensor(t, device="cuda"),
+                      w, v, lam, nn.Slice(grad, 0, 1), terms, relu_mask=False)
+    got = _host(grad)[:, 0]
+    ref = np.concatenate(refs)
+    assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-4 * np.max(np.abs(ref)))

@@ -1,0 +1,90 @@
+"""Warm starts and the zero-start fallback of the FISTA solvers.
+
+With warm_start = 2 the solver runs one iteration from the given start and
+keeps it only if its gradient-mapping ratio is at most 1, the ratio of a zero
+start by definition (same denominator ||G(0)|| for both); otherwise the scan
+restarts from zero.  A start at the solution itself is kept and converges at
+once; a grossly wrong start is discarded and the result matches the zero
+start's to the solver tolerance.
+"""
+
+import numpy as np
+import pytest
+
+from synth import noise, phantoms, workloads
+from tests.gpu_common import rel_l2, to_np
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _setup(n_scans=3):
+    from paper_2101_11680_amd import ctof
+    g = workloads.geometry_for("mid")
+    w = workloads.workload("mid")
+    k = ctof.tabulate(g, ctof.FP32)
+    ds, mus = [], []
+    for s in range(n_scans):
+        mu = phantoms.workload_phantom(w, g, 500 + s)
+        mut = torch.tensor(mu, dtype=torch.float32, device="cuda")
+        m = ctof.forward(k, mut)
+        d = noise.poisson_histogram(m.cpu().numpy().astype(np.float64), 1e5, 600 + s)
+        ds.append(torch.tensor(d, dtype=torch.float32, device="cuda"))
+        mus.append(mut)
+    return ctof, k, ds, mus
+
+
+def test_fallback_single_scan():
+    ctof, k, ds, mus = _setup(1)
+    d = ds[0]
+    _, rep0, _ = ctof.reconstruct(k, d, max_iter=1)
+    L, lam = rep0.lipschitz, rep0.lam
+    ref, rz, _ = ctof.reconstruct(k, d, max_iter=3000, lam=lam, lipschitz=L, rel_tol=1e-4, check_every=10)
+    assert rz.gmap_ratio <= 1e-4
+    # start at the solution: kept, converged at the first check
+    start = ref.clone()
+    mu, rw, _ = ctof.reconstruct(k, d, mu=start, max_iter=3000, lam=lam, lipschitz=L, rel_tol=1e-4,
+                                 check_every=10, warm_start=2)
+    assert rw.fell_back == 0 and rw.iters == 10
+    assert rel_l2(to_np(mu), to_np(ref)) <= 1e-3
+    # a start 100x the phantom: discarded, then the zero start's iterates
+    bad = (mus[0] * 100.0).contiguous()
+    mu, rb, _ = ctof.reconstruct(k, d, mu=bad, max_iter=3000, lam=lam, lipschitz=L, rel_tol=1e-4, check_every=10,
+                                 warm_start=2)
+    assert rb.fell_back == 1 and rb.gmap_ratio <= 1e-4
+    assert rel_l2(to_np(mu), to_np(ref)) <= 2e-2
+
+
+def test_fallback_batched_mixed():
+    ctof, k, ds, mus = _setup(3)
+    _, rep0, _ = ctof.reconstruct(k, ds[0], max_iter=1)
+    L, lam = rep0.lipschitz, rep0.lam
+    refs, rz = ctof.reconstruct_batched([k] * 3, ds, max_iter=3000, lam=lam, lipschitz=L, rel_tol=1e-4,
+                                        check_every=10)
+    starts = [refs[0].clone(), (mus[1] * 100.0).contiguous(), torch.zeros_like(refs[2])]
+    out, rw = ctof.reconstruct_batched([k] * 3, ds, mus=starts, max_iter=3000, lam=lam, lipschitz=L, rel_tol=1e-4,
+                                       check_every=10, warm_start=2)
+    assert [r.fell_back for r in rw] == [0, 1, 0]
+    for r in rw:
+        assert r.gmap_ratio <= 1e-4
+    assert rw[0].iters < rz[0].iters // 4
+    for a, b in zip(out, refs):
+        assert rel_l2(to_np(a), to_np(b)) <= 2e-2
+
+
+def test_learned_warm_start_gain():
+    """The shipped network against the zero start on 32 scans that were not
+    in its training set (phantom seeds 950000+; training used 100000+): both
+    solves run to gradient-mapping ratio 1e-3 with the same L and lambda."""
+    from paper_2101_11680_amd import train, unet
+    net = unet.load_default()
+    P = train.problem(workloads.geometry_for("learned"))
+    seeds = list(range(950000, 950032))
+    ds = train.simulate(P, workloads.workload("learned"), seeds, peak_seed=seeds[0])
+    res = train.evaluate(net, P, ds, tol=1e-3, max_iter=3000, batch=32)
+    print(res)
+    assert res["not_converged_zero"] == 0 and res["not_converged_warm"] == 0
+    assert res["iters_ratio"] >= 2.0
+    assert res["fell_back"] <= 2
+    # both stop at the same relative residual; their objectives agree on average
+    assert res["objective_rel_diff_mean"] <= 1e-2
