@@ -159,7 +159,8 @@ def run_batching(args, ctof, torch, dev) -> int:
     # accelerated: batched classes + learned start (CNN time included) with
     # the zero-start fallback; L per class from one power iteration each
     from paper_2101_11680_amd import unet
-    net = unet.load_default(device=dev)
+    net = unet.load_all(device=dev)
+    out["networks_for_layer_counts"] = sorted(net)
     first = {}
     for i, (g, _, _) in enumerate(scans):
         first.setdefault(g, i)

@@ -411,6 +411,18 @@ ctof_status ctof_absmax(int32_t nb, int64_t len, const float *x_dev, float *out_
                         hipStream_t stream);
 
 /*
+ * Depth resampling by 2 of nb volumes [nb][nz_in][plane] (float, out not
+ * overlapping x): mode 0 sums layer pairs, out[b][j] = x[b][2j] + x[b][2j+1]
+ * (nz_in even; nz_in / 2 layers out); mode 1 repeats layers, out[b][k] =
+ * x[b][k / 2] (2 nz_in layers out).  A back-projection on a grid with twice
+ * the layers over the same depth range, pair-summed, approximates the one on
+ * the coarse grid (each coarse voxel is two fine ones), so a network trained
+ * on the coarse grid can start the fine one.
+ */
+ctof_status ctof_depth_resample(int32_t nb, int32_t nz_in, int64_t plane, const float *x_dev, float *out_dev,
+                                int32_t mode, hipStream_t stream);
+
+/*
  * Adam (Kingma and Ba, 2015) with bias correction on n float master weights
  * w, gradient g and moments m, v (step counts from 1); w_bf16 (or NULL)
  * receives the updated weights rounded to BF16.

@@ -525,6 +525,27 @@ __global__ void start_grad_kernel(long long n, long long V, StartCoef cf, const 
   g[(size_t)i * gld + gc0] = (__bf16)v;
 }
 
+// Depth resampling of [nb][nz][plane] volumes by a factor 2:
+// mode 0: out[b][j] = x[b][2j] + x[b][2j + 1]  (nz even, nz / 2 layers out)
+// mode 1: out[b][k] = x[b][k / 2]              (2 nz layers out)
+__global__ void depth_resample_kernel(const float *__restrict__ x, float *__restrict__ out, int nz_out,
+                                      long long plane, long long n, int mode) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const long long p = i % plane;
+  const long long bz = i / plane;
+  const int k = (int)(bz % nz_out);
+  const long long b = bz / nz_out;
+  if (mode == 0) {
+    const long long nz_in = 2LL * nz_out;
+    const float *src = x + (b * nz_in + 2 * k) * plane + p;
+    out[i] = src[0] + src[plane];
+  } else {
+    const long long nz_in = nz_out / 2;
+    out[i] = x[(b * nz_in + k / 2) * plane + p];
+  }
+}
+
 // Block (c, b): max |x| over chunk c of sample b; then per sample.
 constexpr int kAbsChunks = 64;
 __global__ void __launch_bounds__(256)
@@ -557,6 +578,15 @@ inline unsigned blocks_for(long long n, int bs = 256) { return (unsigned)((n + b
 }  // namespace
 
 size_t absmax_ws_bytes(int nb) { return (size_t)nb * kAbsChunks * sizeof(float); }
+
+hipError_t launch_depth_resample(const float *x, float *out, int nb, int nz_in, long long plane, int mode,
+                                 hipStream_t st) {
+  const int nz_out = mode == 0 ? nz_in / 2 : 2 * nz_in;
+  const long long n = (long long)nb * nz_out * plane;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(depth_resample_kernel, dim3(blocks_for(n)), dim3(256), 0, st, x, out, nz_out, plane, n, mode);
+  return hipGetLastError();
+}
 
 hipError_t launch_absmax(const float *x, long long V, int nb, float *part, float *out, hipStream_t st) {
   if (V == 0 || nb == 0) return hipSuccess;

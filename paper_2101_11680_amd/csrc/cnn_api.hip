@@ -279,4 +279,15 @@ ctof_status ctof_absmax(int32_t nb, int64_t len, const float *x_dev, float *out_
   return CTOF_OK;
 }
 
+ctof_status ctof_depth_resample(int32_t nb, int32_t nz_in, int64_t plane, const float *x_dev, float *out_dev,
+                                int32_t mode, hipStream_t stream) {
+  if (nb < 1 || nz_in < 1 || plane < 1 || (long long)nb * nz_in * plane > kMaxRows / 2)
+    return set_error(CTOF_EINVAL, "bad sizes");
+  if (mode != 0 && mode != 1) return set_error(CTOF_EINVAL, "mode must be 0 (sum pairs) or 1 (repeat)");
+  if (mode == 0 && (nz_in & 1)) return set_error(CTOF_EINVAL, "summing layer pairs needs an even nz");
+  if (!x_dev || !out_dev) return set_error(CTOF_EINVAL, "NULL argument");
+  HIP_TRY(ctof::launch_depth_resample(x_dev, out_dev, nb, nz_in, plane, mode, stream));
+  return CTOF_OK;
+}
+
 }  // extern "C"

@@ -250,6 +250,8 @@ struct StartCoef {
 hipError_t launch_start_error(const float *y, int ld, int c0, const StartCoef &cf, long long V, const float *t,
                               long long n, float *e, hipStream_t st);
 size_t absmax_ws_bytes(int nb);
+hipError_t launch_depth_resample(const float *x, float *out, int nb, int nz_in, long long plane, int mode,
+                                 hipStream_t st);
 hipError_t launch_absmax(const float *x, long long V, int nb, float *part, float *out, hipStream_t st);
 hipError_t launch_axpy(long long n, float a, const float *x, float *y, hipStream_t st);
 size_t sumsq_ws_bytes(int nb);

@@ -32,7 +32,7 @@ EXPORTS = ("ctof_kernel_bytes", "ctof_kernel_tabulate", "ctof_kernel_tabulate_qu
            "ctof_relu_bwd", "ctof_mse_ws_bytes", "ctof_mse", "ctof_adam_step",
            "ctof_to_channels_last", "ctof_from_channels_last", "ctof_philox4x32", "ctof_poisson",
            "ctof_noisy_histogram_ws_bytes", "ctof_noisy_histogram", "ctof_warmstart_loss_ws_bytes",
-           "ctof_warmstart_loss", "ctof_absmax_ws_bytes", "ctof_absmax")
+           "ctof_warmstart_loss", "ctof_absmax_ws_bytes", "ctof_absmax", "ctof_depth_resample")
 
 
 class CtofError(RuntimeError):
@@ -137,6 +137,7 @@ def lib() -> ctypes.CDLL:
                                           vp]
         L.ctof_absmax_ws_bytes.argtypes = [i32, ctypes.POINTER(sz)]
         L.ctof_absmax.argtypes = [i32, i64, vp, vp, vp, sz, vp]
+        L.ctof_depth_resample.argtypes = [i32, i32, i64, vp, vp, i32, vp]
         L.ctof_last_error.argtypes = []
         L.ctof_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:

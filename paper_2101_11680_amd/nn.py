@@ -246,3 +246,16 @@ def absmax(x, nb: int, stream=None):
     _check(lib().ctof_absmax(int(nb), int(x.numel() // nb), x.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(),
                              _stream_ptr(stream)))
     return out
+
+
+def depth_resample(x, mode: int, stream=None):
+    """x float32 [nb, nz, h, w]: mode 0 sums layer pairs (nz / 2 out), mode 1
+    repeats layers (2 nz out)."""
+    torch = _torch()
+    nb, nz = int(x.shape[0]), int(x.shape[1])
+    plane = int(x[0, 0].numel())
+    nz_out = nz // 2 if mode == 0 else 2 * nz
+    out = torch.empty((nb, nz_out) + tuple(x.shape[2:]), dtype=torch.float32, device=x.device)
+    _check(lib().ctof_depth_resample(nb, nz, plane, x.contiguous().data_ptr(), out.data_ptr(), int(mode),
+                                     _stream_ptr(stream)))
+    return out

@@ -138,7 +138,7 @@ def target_norms(P: Problem, targets, chunk: int = 32):
 def train(net: "unet.UNet", P: Problem, xs, targets, steps: int, batch: int = 8, lr: float = 3e-4,
           lr_min: float = 1e-5, warmup: int = 300, seed: int = 0, log_every: int = 100, log=print,
           loss: str = "operator", alpha: float = 1.0, norms=None, maxima=None,
-          floor_pct: float = 10.0) -> List[float]:
+          floor_pct: float = 10.0, robust: bool = False) -> List[float]:
     """Adam with cosine learning-rate decay on random minibatches.
 
     loss = "operator": mean over the batch of ||H e||^2 / ||H mu*||^2 +
@@ -148,8 +148,11 @@ def train(net: "unet.UNet", P: Problem, xs, targets, steps: int, batch: int = 8,
     observed components, where the solver is slow, in the fit.  Both terms
     are 1 for a zero start.  The per-sample norms are floored at their
     floor_pct-th percentile so that scans whose solution is nearly zero do
-    not dominate the gradient.  The learning rate rises linearly over
-    `warmup` steps, then follows a cosine to lr_min."""
+    not dominate the gradient.  With robust, each sample's loss enters as
+    log(1 + loss_b) (its gradient divided by 1 + loss_b, found by a first
+    evaluation of the terms), which bounds the pull of a sample the network
+    overshoots.  The learning rate rises linearly over `warmup` steps, then
+    follows a cosine to lr_min."""
     torch = _torch()
     g = torch.Generator(device="cpu").manual_seed(seed)
     N = xs.shape[0]
@@ -175,6 +178,10 @@ def train(net: "unet.UNet", P: Problem, xs, targets, steps: int, batch: int = 8,
             nb = norms[idx_h.numpy()]
             w = 1.0 / np.maximum(nb[:, 0], 1e-300)
             v = alpha / np.maximum(nb[:, 1], 1e-300)
+            if robust:
+                terms = net.loss_terms_operator(P.kernel, tb, w, v, P.lam, s_out).cpu().numpy()
+                f = 1.0 / (1.0 + w * terms[:, 0] + v * terms[:, 1])
+                w, v = w * f, v * f
             terms = net.loss_and_backward_operator(P.kernel, tb, w, v, P.lam, s_out)
         else:
             raise ValueError(f"unknown loss {loss!r}")
@@ -269,6 +276,7 @@ def main(argv=None) -> int:
     from synth import workloads
     ap = argparse.ArgumentParser(description="train and evaluate the learned warm start")
     ap.add_argument("--workload", default="learned")
+    ap.add_argument("--nz", type=int, default=0, help="layer count (0: the workload's own)")
     ap.add_argument("--n-train", type=int, default=20000)
     ap.add_argument("--n-eval", type=int, default=512)
     ap.add_argument("--steps", type=int, default=6000)
@@ -279,13 +287,16 @@ def main(argv=None) -> int:
     ap.add_argument("--channels", default="16,32,64,64")
     ap.add_argument("--loss", default="operator", choices=("operator",))
     ap.add_argument("--alpha", type=float, default=1.0)
+    ap.add_argument("--robust", action="store_true", help="log(1 + loss) per sample")
     ap.add_argument("--out", default="gpurun_out/warmstart.npz")
     ap.add_argument("--report", default="gpurun_out/warmstart_report.json")
     a = ap.parse_args(argv)
     torch = _torch()
     log = lambda msg: print(msg, flush=True)
     w = workloads.workload(a.workload)
-    P = problem(workloads.geometry_for(a.workload))
+    geom = workloads.geometry_for(a.workload) if a.nz <= 0 else workloads.geometry_with_layers(a.workload, a.nz)
+    P = problem(geom)
+    log(f"geometry {geom.nx}x{geom.ny}, {geom.nz} layers {geom.z_mm[0]:g}-{geom.z_mm[-1]:g} mm, {geom.nt} bins")
     log(f"problem: L {P.lipschitz:.6e} lambda {P.lam:.6e}")
     train_seeds = list(range(100000, 100000 + a.n_train))
     eval_seeds = list(range(900000, 900000 + a.n_eval))
@@ -295,13 +306,14 @@ def main(argv=None) -> int:
     log(f"scales: in {net.in_scale:.4e} out {net.out_scale:.4e}")
     t0 = time.time()
     losses = train(net, P, xs, ts, a.steps, batch=a.batch, lr=a.lr, log=log, loss=a.loss, alpha=a.alpha,
-                   maxima=mx)
+                   maxima=mx, robust=a.robust)
     torch.cuda.synchronize()
     t_train = time.time() - t0
     del xs, ts
     os.makedirs(os.path.dirname(a.out) or ".", exist_ok=True)
-    net.save(a.out, extra=dict(workload=a.workload, n_train=a.n_train, steps=a.steps, batch=a.batch,
-                               tol=a.tol, lipschitz=P.lipschitz, lam=P.lam, loss=a.loss, alpha=a.alpha))
+    net.save(a.out, extra=dict(workload=a.workload, nz=geom.nz, n_train=a.n_train, steps=a.steps, batch=a.batch,
+                               tol=a.tol, lipschitz=P.lipschitz, lam=P.lam, loss=a.loss, alpha=a.alpha, lr=a.lr,
+                               robust=a.robust))
     ds = simulate(P, w, eval_seeds, peak_seed=eval_seeds[0])
     res = evaluate(net, P, ds, tol=a.tol, max_iter=a.max_iter)
     res.update(train_seconds=t_train, train_steps=a.steps, batch=a.batch, n_train=a.n_train,

@@ -312,6 +312,19 @@ class UNet:
         s_out = [self.out_scale * t * mb for t, mb in zip(taus, m)]
         return s_in, s_out
 
+    def loss_terms_operator(self, kernel, target, w, v, lam: float, s_out, stream=None):
+        """The loss terms (||H e_b||^2, ||e_b||^2) of the current forward
+        pass without a backward pass (device [n, 2]); the head gradient
+        buffer is overwritten."""
+        torch = _torch()
+        A, G = self._bufs
+        n = self._shape[0]
+        if getattr(self, "_terms", None) is None:
+            self._terms = torch.zeros((64, 2), dtype=torch.float64, device=self.device)
+        nn.warmstart_loss(kernel, n, Slice(A["head"], 0, 1), s_out, target.contiguous(), w, v, lam,
+                          Slice(G["head"], 0, 1), self._terms, relu_mask=False, stream=stream)
+        return self._terms[:n]
+
     def loss_and_backward_operator(self, kernel, target, w, v, lam: float, s_out, straight_through: bool = True,
                                    stream=None):
         """Operator-weighted loss w_b ||H e_b||^2 + v_b ||e_b||^2 of the start
@@ -382,21 +395,38 @@ class UNet:
         return net
 
 
-WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "warmstart_64x64x32.npz")
+WEIGHTS_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights")
+WEIGHTS = os.path.join(WEIGHTS_DIR, "warmstart_64x64x32.npz")
 
 
 def load_default(device="cuda") -> "UNet":
-    """The shipped network, trained on the 64 x 64 x 32-layer, 256-bin
-    geometry (see the checkpoint's metadata for the recipe)."""
+    """The shipped network trained on the 64 x 64 x 32-layer, 256-bin
+    geometry (the checkpoint's metadata holds the recipe)."""
     return UNet.load(WEIGHTS, device=device)
+
+
+def load_all(device="cuda") -> Dict[int, "UNet"]:
+    """Every shipped network, keyed by the layer count it was trained on
+    (files warmstart_64x64x<nz>.npz); each runs fully convolutionally on
+    any lateral size divisible by 8."""
+    nets = {}
+    for f in sorted(os.listdir(WEIGHTS_DIR)):
+        if f.startswith("warmstart_64x64x") and f.endswith(".npz"):
+            nz = int(f[len("warmstart_64x64x"):-4])
+            nets[nz] = UNet.load(os.path.join(WEIGHTS_DIR, f), device=device)
+    return nets
 
 
 # ---- data and warm start -------------------------------------------------------------
 
-def warm_start_volumes(net: UNet, kernels, ds, taus, max_batch: int = 16, stream=None):
+def warm_start_volumes(net, kernels, ds, taus, max_batch: int = 16, stream=None):
     """Start volumes for a list of scans: the back-projection A^T d of each
     scan, scaled by its class's tau, run through the network in batches of
-    one grid shape (at most max_batch scans per batch)."""
+    one grid shape (at most max_batch scans per batch).  `net` is one UNet
+    or a dict {layer count: UNet}.  A layer count without its own network
+    but twice one that has one is started through that network on the
+    pair-summed back-projection (tau halved), its output repeated into both
+    sub-layers; other scans, and grids not divisible by 8, start from zero."""
     torch = _torch()
     out = [None] * len(ds)
     groups: Dict[tuple, List[int]] = {}
@@ -404,12 +434,25 @@ def warm_start_volumes(net: UNet, kernels, ds, taus, max_batch: int = 16, stream
         inf = k.info
         groups.setdefault((inf.nz, inf.n), []).append(i)
     for (nz, n), idx in groups.items():
+        model = net.get(nz) if isinstance(net, dict) else net
+        coarse = False
+        if model is None and isinstance(net, dict) and nz % 2 == 0 and (nz // 2) in net:
+            model, coarse = net[nz // 2], True
+        if model is None or (nz // (2 if coarse else 1)) % 8 or n % 8:
+            for i in idx:
+                out[i] = torch.zeros((nz, n, n), dtype=torch.float32, device=ds[i].device)
+            continue
         for b0 in range(0, len(idx), max_batch):
             part = idx[b0:b0 + max_batch]
-            x = torch.empty((len(part), nz, n, n), dtype=torch.float32, device=net.device)
+            x = torch.empty((len(part), nz, n, n), dtype=torch.float32, device=model.device)
             for j, i in enumerate(part):
                 ctof.adjoint(kernels[i], ds[i], out=x[j], stream=stream)
-            pred = net.predict(x, [taus[i] for i in part], stream=stream)
+            if coarse:
+                pred = model.predict(nn.depth_resample(x, 0, stream=stream), [0.5 * taus[i] for i in part],
+                                     stream=stream)
+                pred = nn.depth_resample(pred, 1, stream=stream)
+            else:
+                pred = model.predict(x, [taus[i] for i in part], stream=stream)
             for j, i in enumerate(part):
                 out[i] = pred[j]
     return out

@@ -113,6 +113,16 @@ def geometry_for(name: str, seed: int = 0) -> Geometry:
     return g
 
 
+def geometry_with_layers(name: str, nz: int, seed: int = 0) -> Geometry:
+    """The workload's geometry with nz layers evenly spaced over the same
+    depth range (the layer counts of the batching workload)."""
+    g = geometry_for(name, seed)
+    z, dz = even_layers(g.z_mm[0], g.z_mm[-1], nz)
+    return Geometry(nx=g.nx, ny=g.ny, pitch_mm=g.pitch_mm, z_mm=z, dz_mm=dz, nt=g.nt, dt_ps=g.dt_ps,
+                    t0_ps=g.t0_ps, mus_prime_per_mm=g.mus_prime_per_mm, mua_per_mm=g.mua_per_mm,
+                    n_medium=g.n_medium)
+
+
 def batching_scans(n_scans: int = 64, seed: int = 0):
     """The batching workload's list of (geometry, phantom seed, peak) triples.
 

@@ -378,3 +378,13 @@ def test_warmstart_loss_matches_oracle_operator():
     got = _host(grad)[:, 0]
     ref = np.concatenate(refs)
     assert np.all(np.abs(got - ref) <= 2.0 ** -8 * np.abs(ref) + 1e-4 * np.max(np.abs(ref)))
+
+
+def test_depth_resample():
+    nn = _nn()
+    x = np.random.default_rng(40).standard_normal((3, 6, 5, 4)).astype(np.float32)
+    xt = torch.tensor(x, device="cuda")
+    pooled = nn.depth_resample(xt, 0).cpu().numpy()
+    np.testing.assert_array_equal(pooled, x[:, 0::2] + x[:, 1::2])
+    rep = nn.depth_resample(xt, 1).cpu().numpy()
+    np.testing.assert_array_equal(rep, np.repeat(x, 2, axis=1))
