@@ -207,6 +207,26 @@ def run_batching(args, ctof, torch, dev) -> int:
     return 0
 
 
+def run_warmstart(args, ctof, torch, dev) -> int:
+    """Learned warm start on the 64 x 64 x 32-layer, 256-bin geometry: held-out
+    scans (phantom seeds 900000+, never trained on) solved to gradient-mapping
+    ratio rel_tol from zero and from the shipped network's start (zero-start
+    fallback on, CNN time included), same L and lambda."""
+    from paper_2101_11680_amd import train, unet
+    from synth import workloads
+    net = unet.load_default(device=dev)
+    P = train.problem(workloads.geometry_for("learned"))
+    seeds = list(range(900000, 900000 + args.scans))
+    ds = train.simulate(P, workloads.workload("learned"), seeds, peak_seed=seeds[0])
+    torch.cuda.synchronize()
+    res = train.evaluate(net, P, ds, tol=args.rel_tol, max_iter=3000)
+    res["workload"] = ("learned warm start: 64x64 scan, 32 layers 1-20 mm, 256 bins of 25 ps, "
+                       f"{args.scans} held-out phantoms (1-4 spheres/bars), Poisson noise at 1e4-1e6 peak counts")
+    res["network"] = {k: net.meta.get(k) for k in ("n_train", "steps", "batch", "loss", "alpha", "recipe")}
+    print(json.dumps(res), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -217,9 +237,11 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
-    ap.add_argument("--workload", default="precision", choices=["precision", "batching"],
+    ap.add_argument("--workload", default="precision", choices=["precision", "batching", "warmstart"],
                     help="precision: the iteration-rate metric (default); batching: 64 uneven "
-                         "scans solved to gradient-mapping ratio 1e-3, plain vs batched")
+                         "scans solved to gradient-mapping ratio 1e-3, plain vs batched vs batched with "
+                         "the learned start; warmstart: held-out scans of the learned geometry, zero vs "
+                         "learned start (--scans, default 64; 512 for the full evaluation)")
     ap.add_argument("--scans", type=int, default=64)
     ap.add_argument("--rel-tol", type=float, default=1e-3)
     args = ap.parse_args()
@@ -253,6 +275,8 @@ def main() -> int:
         return 0
     if args.workload == "batching":
         return run_batching(args, ctof, torch, dev)
+    if args.workload == "warmstart":
+        return run_warmstart(args, ctof, torch, dev)
     prec = ctof.PRECISIONS[args.precision]
     dtype = torch.float64 if prec == ctof.FP64 else torch.float32
 
