@@ -227,6 +227,49 @@ def run_warmstart(args, ctof, torch, dev) -> int:
     return 0
 
 
+def run_cnn(args, ctof, torch, dev) -> int:
+    """Training step of the warm-start U-Net (16/32/64/64 channels, BF16
+    activations, FP32 accumulation) on 64 x 64 x 32-layer inputs: forward,
+    MSE loss, backward (input and weight gradients), Adam.  FLOP/s counts
+    the convolutions' algorithmic multiply-adds (unpadded channels):
+    forward, weight gradient, and input gradient for every layer but the
+    first."""
+    from paper_2101_11680_amd import nn, unet
+    net = unet.load_default(device=dev)
+    n, D, H, W = args.batch, 32, 64, 64
+    g = torch.Generator(device="cpu").manual_seed(args.seed)
+    x = torch.rand((n, D, H, W), generator=g).to(dev)
+    t = torch.rand((n, D, H, W), generator=g).to(dev)
+    flops = 0.0
+    for name, kind, co, ci in net.layers:
+        taps = {nn.K3: 27, nn.DN: 8, nn.UP: 8, nn.K1: 1}[kind]
+        lvl_in = {"e1": 0, "e2": 1, "e3": 2, "d1": 0, "d2": 1, "d3": 2, "m4": 3, "u3": 3, "u2": 2, "u1": 1,
+                  "c1": 0, "c2": 1, "c3": 2, "he": 0}[name[:2]]
+        pos_in = n * (D >> lvl_in) * (H >> lvl_in) * (W >> lvl_in)
+        # multiply-adds: output positions x co x taps x ci (UP: input positions x 8 taps)
+        pos = pos_in // 8 if kind == nn.DN else pos_in
+        macs = pos * co * taps * ci
+        flops += 2.0 * macs * (2 if name == "e1a" else 3)
+    for _ in range(args.warmup):
+        net.forward(x)
+        net.loss_and_backward(t)
+        net.adam(1e-6)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        net.forward(x)
+        net.loss_and_backward(t)
+        net.adam(1e-6)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    out = {"workload": f"U-Net training step, batch {n}, {D}x{H}x{W} voxels, channels {list(net.ch)}",
+           "ms_per_step": dt * 1e3, "tflop_per_step": flops / 1e12, "tflops": flops / dt / 1e12,
+           "peak_tflops_bf16_dense": 2500.0, "frac": flops / dt / 1e12 / 2500.0,
+           "samples_per_s": n / dt}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -237,7 +280,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
-    ap.add_argument("--workload", default="precision", choices=["precision", "batching", "warmstart"],
+    ap.add_argument("--batch", type=int, default=8, help="cnn workload: samples per step")
+    ap.add_argument("--workload", default="precision", choices=["precision", "batching", "warmstart", "cnn"],
                     help="precision: the iteration-rate metric (default); batching: 64 uneven "
                          "scans solved to gradient-mapping ratio 1e-3, plain vs batched vs batched with "
                          "the learned start; warmstart: held-out scans of the learned geometry, zero vs "
@@ -277,6 +321,8 @@ def main() -> int:
         return run_batching(args, ctof, torch, dev)
     if args.workload == "warmstart":
         return run_warmstart(args, ctof, torch, dev)
+    if args.workload == "cnn":
+        return run_cnn(args, ctof, torch, dev)
     prec = ctof.PRECISIONS[args.precision]
     dtype = torch.float64 if prec == ctof.FP64 else torch.float32
 
