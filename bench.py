@@ -278,6 +278,8 @@ def main() -> int:
     ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "bf16", "fp64"])
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", dest="variants", action="store_false",
+                    help="skip the BF16 contraction variants of the default run")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     ap.add_argument("--batch", type=int, default=8, help="cnn workload: samples per step")
@@ -429,6 +431,29 @@ def main() -> int:
                    "gmap_ratio": rep.gmap_ratio},
         "cpu_baseline": None,
     }
+    if args.precision == "fp32" and args.variants:
+        # the reduced-precision contraction forms on the same scan, same L and
+        # lambda (their errors against the FP64 oracle are in the precision
+        # report of the GPU tests)
+        del k
+        torch.cuda.empty_cache()
+        variants = {}
+        for name in ("bf16x3", "bf16"):
+            kv = ctof.tabulate(g, ctof.PRECISIONS[name])
+            ctof.reconstruct(kv, d, max_iter=args.warmup, lam=lam, lipschitz=L)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, rv, _ = ctof.reconstruct(kv, d, max_iter=args.steps, lam=lam, lipschitz=L, timing=True)
+            torch.cuda.synchronize()
+            wv = time.perf_counter() - t0
+            variants[name] = {"iters_per_s": args.steps / wv, "ms_per_step": 1e3 * wv / args.steps,
+                              "contract_fwd_ms": rv.ms_contract_fwd / rv.iters,
+                              "contract_adj_ms": rv.ms_contract_adj / rv.iters,
+                              "datafit_rel_to_fp32": rv.datafit / rep.datafit - 1.0}
+            log(f"{name}: {args.steps / wv:.1f} iters/s")
+            del kv
+            torch.cuda.empty_cache()
+        out["precision_variants"] = variants
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host (bounded sample)")
         out["cpu_baseline"] = cpu_baseline(g)

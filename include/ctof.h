@@ -191,6 +191,14 @@ ctof_status ctof_adjoint(ctof_kernel k, const void *r_dev, void *g_dev, void *ws
  *                    giving each scan's L (> 0) and lambda (>= 0) in place of
  *                    lipschitz / lambda_tikhonov; scans sharing a handle must
  *                    agree.  NULL: lipschitz / lambda_tikhonov for all.
+ *   lambda_l1_z      NULL, or a host array [nz] of per-layer L1 weights
+ *                    (>= 0): the objective gains sum_z lambda_l1_z[z] *
+ *                    ||mu_z||_1, the paper's sparsity term with its
+ *                    layer-wise weights (Eqs. 8 and 10); with mu >= 0 its
+ *                    prox shifts each voxel by tau * lambda_l1_z[z] before
+ *                    the clamp, and the gradient-mapping ratio's
+ *                    denominator becomes ||max(0, A^T d - lambda_l1_z)||.
+ *                    Batched solves need one layer count for all scans.
  */
 typedef struct {
   int32_t max_iter;
@@ -204,6 +212,7 @@ typedef struct {
   int32_t timing;
   const double *lipschitz_scans;
   const double *lambda_scans;
+  const double *lambda_l1_z;
 } ctof_solver_opts;
 
 /*
@@ -421,6 +430,20 @@ ctof_status ctof_absmax(int32_t nb, int64_t len, const float *x_dev, float *out_
  */
 ctof_status ctof_depth_resample(int32_t nb, int32_t nz_in, int64_t plane, const float *x_dev, float *out_dev,
                                 int32_t mode, hipStream_t stream);
+
+/* FP64 sums of squares of nb float vectors of length len: out_dev[b] (double). */
+ctof_status ctof_sumsq_ws_bytes(int32_t nb, size_t *ws_bytes);
+ctof_status ctof_sumsq(int32_t nb, int64_t len, const float *x_dev, double *out_dev, void *ws_dev, size_t ws_bytes,
+                       hipStream_t stream);
+
+/*
+ * Layer-wise threshold of a reconstruction (the paper's post-processing of
+ * its 3D results): in each of the nz layers [plane] of mu_dev (float, in
+ * place), values below frac * (the layer's maximum magnitude) are set to 0.
+ */
+ctof_status ctof_layer_threshold_ws_bytes(int32_t nz, size_t *ws_bytes);
+ctof_status ctof_layer_threshold(int32_t nz, int64_t plane, float *mu_dev, float frac, void *ws_dev,
+                                 size_t ws_bytes, hipStream_t stream);
 
 /*
  * Adam (Kingma and Ba, 2015) with bias correction on n float master weights

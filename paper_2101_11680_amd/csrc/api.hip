@@ -173,7 +173,7 @@ TabWs tab_ws(const ctof::Dims &d) {
 // intermediates carry every volume's planes, solver state is per volume.
 struct ClassWs {
   size_t yhat, mhat, xt, xz, op_total;
-  size_t y, v, w, hist, scal, g0sq, part, beta, ctr, active, solve_total;
+  size_t y, v, w, hist, scal, g0sq, part, beta, ctr, active, l1, solve_total;
   int nblk_t, nblk_z;
   size_t part_stride;  // doubles per iteration
 };
@@ -209,6 +209,7 @@ ClassWs class_ws(const ctof_kernel_s *k, int nvol, int max_iter) {
   o.beta = take((size_t)iters * 8);
   o.ctr = take(64);
   o.active = take((size_t)nvol * 4);
+  o.l1 = take((size_t)d.nz * 8);
   o.solve_total = off;
   return o;
 }
@@ -222,6 +223,7 @@ struct Engine {
   ClassWs L;
   hipStream_t st;
   const int *live = nullptr;  // per-volume flags honoured by every launch (batched solves)
+  const double *l1dev = nullptr;  // per-layer L1 weights in the workspace when the objective has them
 
   const ctof::Dims &dm() const { return k->dims; }
   T *yhat() const { return reinterpret_cast<T *>(ws + L.yhat); }
@@ -238,6 +240,7 @@ struct Engine {
   double *beta() const { return reinterpret_cast<double *>(ws + L.beta); }
   int *ctr() const { return reinterpret_cast<int *>(ws + L.ctr); }
   int *active() const { return reinterpret_cast<int *>(ws + L.active); }
+  double *l1() const { return reinterpret_cast<double *>(ws + L.l1); }
   int Bt() const { return nvol * dm().ntp; }
   int Bz() const { return nvol * dm().nzp; }
 
@@ -252,6 +255,7 @@ struct Engine {
     a.bb = tside ? k->bb_t : k->bb_z;
     a.spec_in = tside ? (void *)xt() : (void *)xz();
     a.spec_out = const_cast<void *>(a.spec_in);
+    a.l1 = tside ? nullptr : l1dev;
     return a;
   }
   hipError_t run_row(const ctof::RowArgs &a) const { return ctof::launch_row_pass<T>(dm(), a, st); }
@@ -553,13 +557,17 @@ template <typename T>
 ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_solver_opts *opt,
                             ctof_solver_report *rep, void *ws, hipStream_t st) {
   const ctof::Dims &dm = k->dims;
-  const Engine<T> E = engine<T>(k, 1, ws, opt->max_iter, st);
+  Engine<T> E = engine<T>(k, 1, ws, opt->max_iter, st);
   const void *dd[1] = {d};
   void *mm[1] = {mu};
   double *scal = E.scal();
   const int K = opt->max_iter;
   // scalars: [0] |w|^2  [1] <v,w>  [3] final fit  [5..6] last history row
   HIP_TRY(ctof::launch_fill_zero(scal, 64 * 8, st));
+  if (opt->lambda_l1_z) {
+    HIP_TRY(hipMemcpyAsync(E.l1(), opt->lambda_l1_z, (size_t)dm.nz * sizeof(double), hipMemcpyHostToDevice, st));
+    E.l1dev = E.l1();
+  }
   if (ctof_status s = enqueue_gmap0(E, dd); s != CTOF_OK) return s;
 
   double lam = opt->lambda_tikhonov, Lip = opt->lipschitz, LA = 0.0;
@@ -762,6 +770,11 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
   std::vector<std::vector<void *>> mv(cls.size());
   for (size_t c = 0; c < cls.size(); ++c) {
     E.push_back(Engine<T>{cls[c].k, (int)cls[c].scans.size(), base + cls[c].off, cls[c].L, st});
+    if (opt->lambda_l1_z) {
+      HIP_TRY(hipMemcpyAsync(E.back().l1(), opt->lambda_l1_z, (size_t)cls[c].k->dims.nz * sizeof(double),
+                             hipMemcpyHostToDevice, st));
+      E.back().l1dev = E.back().l1();
+    }
     for (int i : cls[c].scans) {
       dv[c].push_back(d[i]);
       mv[c].push_back(mu[i]);
@@ -1273,6 +1286,10 @@ ctof_status ctof_reconstruct(ctof_kernel k, const void *d_dev, void *mu_inout_de
   if (opts->warm_start < 0 || opts->warm_start > 2) return set_error(CTOF_EINVAL, "warm_start must be 0, 1 or 2");
   if (opts->lipschitz_scans || opts->lambda_scans)
     return set_error(CTOF_EINVAL, "lipschitz_scans / lambda_scans are batched options");
+  if (opts->lambda_l1_z)
+    for (int z = 0; z < k->dims.nz; ++z)
+      if (!(std::isfinite(opts->lambda_l1_z[z]) && opts->lambda_l1_z[z] >= 0))
+        return set_error(CTOF_EINVAL, "lambda_l1_z[%d] must be finite and >= 0", z);
   const ClassWs o = class_ws(k, 1, opts->max_iter);
   if (ws_bytes < o.solve_total) return set_error(CTOF_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, o.solve_total);
   std::memset(report, 0, sizeof(*report));
@@ -1316,6 +1333,14 @@ ctof_status ctof_reconstruct_batched(int32_t nscan, const ctof_kernel *k, const 
     return set_error(CTOF_EINVAL, "history_dev and timing are single-scan options");
   if ((opts->lipschitz_scans == nullptr) != (opts->lambda_scans == nullptr))
     return set_error(CTOF_EINVAL, "lipschitz_scans and lambda_scans go together");
+  if (opts->lambda_l1_z) {
+    for (int i = 1; i < nscan; ++i)
+      if (k[i]->dims.nz != k[0]->dims.nz)
+        return set_error(CTOF_EINVAL, "per-layer L1 weights need one layer count for all scans");
+    for (int z = 0; z < k[0]->dims.nz; ++z)
+      if (!(std::isfinite(opts->lambda_l1_z[z]) && opts->lambda_l1_z[z] >= 0))
+        return set_error(CTOF_EINVAL, "lambda_l1_z[%d] must be finite and >= 0", z);
+  }
   if (opts->lipschitz_scans)
     for (int i = 0; i < nscan; ++i)
       if (!(std::isfinite(opts->lipschitz_scans[i]) && opts->lipschitz_scans[i] > 0) ||

@@ -271,11 +271,126 @@ conv_wgrad_kernel(ConvArgs a, WgradArgs w) {
   }
 }
 
-// dw (packed layout) = sum over parts, in part order.
-__global__ void wgrad_reduce_kernel(ConvArgs a, const float *__restrict__ part, int nparts, size_t elems,
-                                    float *__restrict__ dw) {
-  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= elems) return;
+// ---- weight gradient of 3x3x3 layers, staged in LDS -----------------------------------
+// A block owns one 16-channel output tile, one chunk of up to 32 input
+// channels and a contiguous range of spatial tiles; a spatial tile is ry
+// whole rows of one plane (ry * w positions, a multiple of 32).  Per tile
+// the block copies the input halo (3 planes x (ry + 2) rows x (w + 2)
+// columns x 32 channels, zero outside the grid) and dY (positions x 16
+// channels) into LDS, channels-last, with 16-byte moves; each wave then adds
+// its (tap, 16 input channels) tiles with one MFMA per 32 positions, both
+// operands read from LDS (8 positions of one channel per lane).  Partial
+// sums use the layout of conv_wgrad_kernel and the same reduction.
+constexpr int kK3Chunk = 32;
+constexpr int kK3WaveTiles = 14;  // ceil(27 taps * 2 channel tiles / 4 waves)
+
+__global__ void __launch_bounds__(256)
+conv_wgrad_k3_kernel(ConvArgs a, WgradArgs w, int ry, long long ntiles, long long tpb) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __bf16 *halo = reinterpret_cast<__bf16 *>(lds_raw);
+  const int W2 = a.w + 2, R2 = ry + 2;
+  __bf16 *dys = halo + (size_t)3 * R2 * W2 * kK3Chunk;
+  const int tpos = ry * a.w;
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, col = l & 15, g = l >> 4;
+  const int co_tiles = a.co_pad / 16;
+  const int cot = blockIdx.y % co_tiles, chunk = blockIdx.y / co_tiles;
+  const int co0 = cot * 16, cc0 = chunk * kK3Chunk;
+  const int rem_ci = a.ci - cc0;
+  const int citc = rem_ci >= 32 ? 2 : (rem_ci + 15) / 16;
+  const int ntl = 27 * citc;
+  const int tiles_per_plane = a.h / ry;
+  const long long t_begin = (long long)blockIdx.x * tpb;
+  const long long t_end = t_begin + tpb < ntiles ? t_begin + tpb : ntiles;
+  v4f acc[kK3WaveTiles];
+#pragma unroll
+  for (int i = 0; i < kK3WaveTiles; ++i) acc[i] = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (long long st = t_begin; st < t_end; ++st) {
+    const long long plane = st / tiles_per_plane;
+    const int y0 = (int)(st % tiles_per_plane) * ry;
+    const int b = (int)(plane / a.d), z = (int)(plane % a.d);
+    __syncthreads();
+    const int nsite = 3 * R2 * W2;
+    for (int v = threadIdx.x; v < nsite * 4; v += 256) {
+      const int site = v >> 2, q = v & 3;
+      const int pl = site / (R2 * W2), rem = site - pl * (R2 * W2);
+      const int hr = rem / W2, hc = rem - hr * W2;
+      const int zz = z + pl - 1, yy = y0 + hr - 1, xx = hc - 1;
+      const int c = cc0 + 8 * q;
+      v8bf val = zero8();
+      if (zz >= 0 && zz < a.d && yy >= 0 && yy < a.h && xx >= 0 && xx < a.w && c < a.ci) {
+        const long long row = (((long long)b * a.d + zz) * a.h + yy) * a.w + xx;
+        val = load8(a.x + (size_t)row * a.x_ld + a.x_c0 + c);
+        if (c + 8 > a.ci) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (c + u >= a.ci) val[u] = (__bf16)0.0f;
+        }
+      }
+      *reinterpret_cast<v8bf *>(halo + (size_t)site * kK3Chunk + 8 * q) = val;
+    }
+    const long long prow0 = ((long long)plane * a.h + y0) * a.w;
+    for (int v = threadIdx.x; v < tpos * 2; v += 256) {
+      const int pp = v >> 1, q = v & 1;
+      const int co = co0 + 8 * q;
+      v8bf val = zero8();
+      const __bf16 *src = w.dy + (size_t)(prow0 + pp) * w.dy_ld + w.dy_c0 + co;
+      if (co + 8 <= a.co) {
+        val = load8(src);
+      } else {
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (co + u < a.co) val[u] = src[u];
+      }
+      *reinterpret_cast<v8bf *>(dys + (size_t)pp * 16 + 8 * q) = val;
+    }
+    __syncthreads();
+    for (int s = 0; s < tpos / 32; ++s) {
+      const int q0 = 32 * s + 8 * g;
+      const int r = q0 / a.w, x0 = q0 - r * a.w;
+      v8bf av;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) av[j] = dys[(size_t)(q0 + j) * 16 + col];
+#pragma unroll
+      for (int i = 0; i < kK3WaveTiles; ++i) {
+        const int t = wave + 4 * i;
+        if (t < ntl) {
+          const int tap = t / citc, cib = t - tap * citc;
+          const int dz = tap / 9, dyy = (tap / 3) % 3, dxx = tap % 3;
+          const __bf16 *hb = halo + ((size_t)(dz * R2 + r + dyy) * W2 + x0 + dxx) * kK3Chunk + cib * 16 + col;
+          v8bf bv;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) bv[j] = hb[j * kK3Chunk];
+          acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[i], 0, 0, 0);
+        }
+      }
+    }
+  }
+  const int cit = (a.ci + 15) / 16;
+  const size_t rowlen = (size_t)27 * cit * 16;
+  float *pp = w.part + (size_t)blockIdx.x * a.co_pad * rowlen;
+#pragma unroll
+  for (int i = 0; i < kK3WaveTiles; ++i) {
+    const int t = wave + 4 * i;
+    if (t < ntl) {
+      const int tap = t / citc, cib = t - tap * citc;
+      const int ci = cc0 + cib * 16 + col;
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr)
+        pp[(size_t)(co0 + 4 * g + rr) * rowlen + (size_t)tap * cit * 16 + ci] = acc[i][rr];
+    }
+  }
+}
+
+// dw (packed layout) = sum over parts.  T threads per element (a power of
+// two dividing 256): thread t sums parts t, t + T, ... in order, then the T
+// sums are added pairwise in a fixed tree (deterministic).
+__global__ void __launch_bounds__(256)
+wgrad_reduce_kernel(ConvArgs a, const float *__restrict__ part, int nparts, size_t elems, int T,
+                    float *__restrict__ dw) {
+  __shared__ float red[256];
+  const int per_block = 256 / T;
+  const int t = threadIdx.x % T;
+  const size_t e = (size_t)blockIdx.x * per_block + threadIdx.x / T;
   const int taps = wg_taps(a.kind);
   const int cit = (a.ci + 15) / 16;
   int co, tap, ci;
@@ -291,18 +406,24 @@ __global__ void wgrad_reduce_kernel(ConvArgs a, const float *__restrict__ part, 
     ci = k - tap * a.cip;
   }
   float s = 0.0f;
-  if (co < a.co && tap < taps && ci < a.ci) {
+  if (e < elems && co < a.co && tap < taps && ci < a.ci) {
     const size_t rowlen = (size_t)taps * cit * 16;
     const size_t off = (size_t)co * rowlen + (size_t)tap * cit * 16 + ci;
     const size_t stride = (size_t)a.co_pad * rowlen;
-    for (int p = 0; p < nparts; ++p) s += part[(size_t)p * stride + off];
+    for (int p = t; p < nparts; p += T) s += part[(size_t)p * stride + off];
   }
-  dw[e] = s;
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = T / 2; k > 0; k >>= 1) {
+    if (t < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (t == 0 && e < elems) dw[e] = red[threadIdx.x];
 }
 
 // Bias gradient: per-block partial sums over a range of output rows, then a
 // fixed-order sum over blocks.
-constexpr int kBiasBlocks = 256;
+constexpr int kBiasBlocks = 2048;
 
 __global__ void __launch_bounds__(256)
 bias_partial_kernel(const __bf16 *__restrict__ dy, int ld, int c0, long long nrows, int co, long long per,
@@ -327,12 +448,20 @@ bias_partial_kernel(const __bf16 *__restrict__ dy, int ld, int c0, long long nro
   }
 }
 
-__global__ void bias_reduce_kernel(const float *__restrict__ part, int nblk, int co, float *__restrict__ db) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= co) return;
+// Block c: thread b loads partial b of channel c; fixed-order tree sum.
+__global__ void __launch_bounds__(256)
+bias_reduce_kernel(const float *__restrict__ part, int nblk, int co, float *__restrict__ db) {
+  __shared__ float red[256];
+  const int c = blockIdx.x;
   float s = 0.0f;
-  for (int b = 0; b < nblk; ++b) s += part[(size_t)b * co + c];
-  db[c] = s;
+  for (int b = threadIdx.x; b < nblk; b += 256) s += part[(size_t)b * co + c];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) db[c] = red[0];
 }
 
 // Input-gradient weights t from forward weights f (layouts of the file header):
@@ -573,9 +702,26 @@ __global__ void absmax_total_kernel(const float *__restrict__ part, int nb, floa
   out[b] = m;
 }
 
+// mu[z][i] = 0 where |mu[z][i]| < frac * maxes[z]
+__global__ void layer_threshold_kernel(float *__restrict__ mu, long long plane, long long n,
+                                       const float *__restrict__ maxes, float frac) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float t = frac * maxes[i / plane];
+  if (fabsf(mu[i]) < t) mu[i] = 0.0f;
+}
+
 inline unsigned blocks_for(long long n, int bs = 256) { return (unsigned)((n + bs - 1) / bs); }
 
 }  // namespace
+
+hipError_t launch_layer_threshold(float *mu, int nz, long long plane, const float *maxes, float frac,
+                                  hipStream_t st) {
+  const long long n = (long long)nz * plane;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(layer_threshold_kernel, dim3(blocks_for(n)), dim3(256), 0, st, mu, plane, n, maxes, frac);
+  return hipGetLastError();
+}
 
 size_t absmax_ws_bytes(int nb) { return (size_t)nb * kAbsChunks * sizeof(float); }
 
@@ -716,7 +862,8 @@ static void wgrad_plan(const ConvArgs &a, int &nparts, long long &per_part, int 
   groups = (a.co_pad / 16) * ((ktiles + kWgTiles - 1) / kWgTiles);
   const long long npos = conv_gemm_positions(a);
   part_elems = (size_t)a.co_pad * taps * cit * 16;
-  long long want = (8192 + groups - 1) / groups;
+  long long want = (4096 + groups - 1) / groups;
+  if (want > 1024) want = 1024;
   const long long cap_mem = (long long)((size_t)(16u << 20) / part_elems);
   const long long cap_pos = (npos + 255) / 256;
   if (want > cap_mem) want = cap_mem;
@@ -728,11 +875,43 @@ static void wgrad_plan(const ConvArgs &a, int &nparts, long long &per_part, int 
   if (nparts < 1) nparts = 1;
 }
 
+// Plan of the LDS-staged 3x3x3 weight gradient, or false when the layer
+// does not fit it (then the generic kernel runs).
+struct K3Plan {
+  int ry, groups, nparts;
+  long long ntiles, tpb;
+  size_t lds;
+};
+
+static bool k3_plan(const ConvArgs &a, int dy_ld, int dy_c0, K3Plan &p) {
+  if (a.kind != CNN_K3 || a.w % 8 != 0 || (dy_ld % 8) || (dy_c0 % 8)) return false;
+  int ry = a.w >= 128 ? 1 : 128 / a.w;
+  if (ry > a.h) ry = a.h;
+  while (ry > 1 && a.h % ry) --ry;
+  if ((ry * a.w) % 32 || a.h % ry) return false;
+  p.ry = ry;
+  p.lds = ((size_t)3 * (ry + 2) * (a.w + 2) * kK3Chunk + (size_t)ry * a.w * 16) * sizeof(__bf16);
+  if (p.lds > 64 * 1024) return false;
+  p.groups = (a.co_pad / 16) * ((a.ci + kK3Chunk - 1) / kK3Chunk);
+  p.ntiles = (long long)a.n * a.d * (a.h / ry);
+  const size_t part_elems = (size_t)a.co_pad * 27 * ((a.ci + 15) / 16) * 16;
+  long long want = (2048 + p.groups - 1) / p.groups;
+  const long long cap_mem = (long long)((size_t)(16u << 20) / part_elems);
+  if (want > cap_mem) want = cap_mem;
+  if (want > p.ntiles) want = p.ntiles;
+  if (want < 1) want = 1;
+  p.tpb = (p.ntiles + want - 1) / want;
+  p.nparts = (int)((p.ntiles + p.tpb - 1) / p.tpb);
+  return p.ntiles > 0;
+}
+
 size_t conv_wgrad_ws_bytes(const ConvArgs &a) {
   int nparts, groups;
   long long per;
   size_t part_elems;
   wgrad_plan(a, nparts, per, groups, part_elems);
+  K3Plan kp;
+  if (k3_plan(a, 8, 0, kp) && kp.nparts > nparts) nparts = kp.nparts;
   return ((size_t)nparts * part_elems + (size_t)kBiasBlocks * a.co) * sizeof(float);
 }
 
@@ -745,15 +924,30 @@ hipError_t launch_conv_wgrad(const ConvArgs &a, const __bf16 *dy, int dy_ld, int
   const long long npos = conv_gemm_positions(a);
   const size_t elems = cnn_weight_elems(a.kind, a.co, a.ci);
   hipError_t e;
-  if (npos > 0) {
+  K3Plan kp;
+  const bool staged = npos > 0 && k3_plan(a, dy_ld, dy_c0, kp) &&
+                      (reinterpret_cast<uintptr_t>(dy) & 15) == 0 && (reinterpret_cast<uintptr_t>(a.x) & 15) == 0;
+  if (staged) {
+    WgradArgs w{dy, dy_ld, dy_c0, ws, kp.nparts, 0};
+    hipLaunchKernelGGL(conv_wgrad_k3_kernel, dim3((unsigned)kp.nparts, (unsigned)kp.groups), dim3(256), kp.lds, st,
+                       a, w, kp.ry, kp.ntiles, kp.tpb);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    nparts = kp.nparts;
+  } else if (npos > 0) {
     WgradArgs w{dy, dy_ld, dy_c0, ws, nparts, per};
     hipLaunchKernelGGL(conv_wgrad_kernel, dim3((unsigned)((nparts + 3) / 4), (unsigned)groups), dim3(256), 0, st,
                        a, w);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3(blocks_for((long long)elems)), dim3(256), 0, st, a, ws,
-                     npos > 0 ? nparts : 0, elems, dw);
+  // threads per element: enough to keep about 64K threads busy, at most 64
+  const int np_eff = npos > 0 ? nparts : 0;
+  int T = 1;
+  while (T < 64 && (size_t)T * elems < 65536 && T < np_eff) T *= 2;
+  const size_t per_block = 256 / T;
+  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((unsigned)((elems + per_block - 1) / per_block)), dim3(256), 0, st,
+                     a, ws, np_eff, elems, T, dw);
   e = hipGetLastError();
   if (e != hipSuccess || !db) return e;
   float *bpart = ws + (size_t)nparts * part_elems;
@@ -766,7 +960,7 @@ hipError_t launch_conv_wgrad(const ConvArgs &a, const __bf16 *dy, int dy_ld, int
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(bias_reduce_kernel, dim3(blocks_for(a.co)), dim3(256), 0, st, bpart, nblk, a.co, db);
+  hipLaunchKernelGGL(bias_reduce_kernel, dim3((unsigned)a.co), dim3(256), 0, st, bpart, nblk, a.co, db);
   return hipGetLastError();
 }
 

@@ -290,4 +290,41 @@ ctof_status ctof_depth_resample(int32_t nb, int32_t nz_in, int64_t plane, const 
   return CTOF_OK;
 }
 
+ctof_status ctof_sumsq_ws_bytes(int32_t nb, size_t *ws_bytes) {
+  if (nb < 1 || nb > 65535) return set_error(CTOF_EINVAL, "nb must be in [1, 65535]");
+  if (!ws_bytes) return set_error(CTOF_EINVAL, "ws_bytes is NULL");
+  *ws_bytes = (ctof::sumsq_ws_bytes(nb) + 255) / 256 * 256;
+  return CTOF_OK;
+}
+
+ctof_status ctof_sumsq(int32_t nb, int64_t len, const float *x_dev, double *out_dev, void *ws_dev, size_t ws_bytes,
+                       hipStream_t stream) {
+  if (nb < 1 || nb > 65535 || len < 1 || len > kMaxRows) return set_error(CTOF_EINVAL, "bad nb / len");
+  if (!x_dev || !out_dev || !ws_dev) return set_error(CTOF_EINVAL, "NULL argument");
+  if (ws_bytes < ctof::sumsq_ws_bytes(nb)) return set_error(CTOF_ENOMEM, "workspace too small");
+  HIP_TRY(ctof::launch_sumsq(x_dev, x_dev, len, nb, reinterpret_cast<double *>(ws_dev), out_dev, stream));
+  return CTOF_OK;
+}
+
+ctof_status ctof_layer_threshold_ws_bytes(int32_t nz, size_t *ws_bytes) {
+  if (nz < 1 || nz > 65535) return set_error(CTOF_EINVAL, "nz must be in [1, 65535]");
+  if (!ws_bytes) return set_error(CTOF_EINVAL, "ws_bytes is NULL");
+  *ws_bytes = (ctof::absmax_ws_bytes(nz) + (size_t)nz * sizeof(float) + 511) / 256 * 256;
+  return CTOF_OK;
+}
+
+ctof_status ctof_layer_threshold(int32_t nz, int64_t plane, float *mu_dev, float frac, void *ws_dev,
+                                 size_t ws_bytes, hipStream_t stream) {
+  if (nz < 1 || nz > 65535 || plane < 1 || (long long)nz * plane > kMaxRows) return set_error(CTOF_EINVAL, "bad sizes");
+  if (!mu_dev || !ws_dev) return set_error(CTOF_EINVAL, "NULL argument");
+  if (!(frac >= 0.0f && frac <= 1.0f)) return set_error(CTOF_EINVAL, "frac must be in [0, 1]");
+  const size_t part = (ctof::absmax_ws_bytes(nz) + 255) / 256 * 256;
+  if (ws_bytes < part + (size_t)nz * sizeof(float)) return set_error(CTOF_ENOMEM, "workspace too small");
+  float *partials = reinterpret_cast<float *>(ws_dev);
+  float *maxes = reinterpret_cast<float *>(reinterpret_cast<char *>(ws_dev) + part);
+  HIP_TRY(ctof::launch_absmax(mu_dev, plane, nz, partials, maxes, stream));
+  HIP_TRY(ctof::launch_layer_threshold(mu_dev, nz, plane, maxes, frac, stream));
+  return CTOF_OK;
+}
+
 }  // extern "C"

@@ -145,6 +145,7 @@ struct RowArgs {
   const double *beta_tab;  // device FISTA weights, indexed by *iter_ctr (or NULL: beta)
   const int *active;     // per volume: blocks of a frozen (0) volume do nothing (NULL: all live)
   const double *scalar;  // device scalar (ROW_SCALE_TO_SPEC: |w|^2)
+  const double *l1;      // device per-layer L1 weights (ROW_FISTA, ROW_GMAP0), or NULL
   double tau, lambda, beta;
 };
 
@@ -244,6 +245,9 @@ hipError_t launch_to_channels_last(const float *x, long long n, float scale, __b
 hipError_t launch_from_channels_last(const float *y, int ld, int c0, long long n, float scale, float *out,
                                      hipStream_t st);
 
+size_t sumsq_ws_bytes(int nb);
+hipError_t launch_layer_threshold(float *mu, int nz, long long plane, const float *maxes, float frac, hipStream_t st);
+
 struct StartCoef {
   float s[kMaxVol], ch[kMaxVol], ce[kMaxVol];
 };
@@ -254,7 +258,6 @@ hipError_t launch_depth_resample(const float *x, float *out, int nb, int nz_in, 
                                  hipStream_t st);
 hipError_t launch_absmax(const float *x, long long V, int nb, float *part, float *out, hipStream_t st);
 hipError_t launch_axpy(long long n, float a, const float *x, float *y, hipStream_t st);
-size_t sumsq_ws_bytes(int nb);
 hipError_t launch_sumsq(const float *u, const float *v, long long V, int nb, double *part, double *out,
                         hipStream_t st);
 hipError_t launch_start_grad(long long n, long long V, const StartCoef &cf, const float *u, const float *e,

@@ -377,6 +377,7 @@ row_pass_kernel(int n, RowArgs a) {
           const T yk = sp_in[idx];
           const T mprev = sp_aux[idx];
           T mu = yk - tau * (x + lam * yk);
+          if (a.l1) mu -= tau * (T)a.l1[pl];  // prox of the per-layer L1 term
           mu = mu > (T)0 ? mu : (T)0;
           const T ynew = mu + beta * (mu - mprev);
           sp_aux[idx] = mu;
@@ -395,7 +396,8 @@ row_pass_kernel(int n, RowArgs a) {
         break;
       case ROW_GMAP0:
         if (valid) {
-          const double g = x > (T)0 ? (double)x : 0.0;
+          const double v = (double)x - (a.l1 ? a.l1[pl] : 0.0);
+          const double g = v > 0.0 ? v : 0.0;
           acc0 += g * g;
         }
         break;

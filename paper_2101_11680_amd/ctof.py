@@ -32,7 +32,8 @@ EXPORTS = ("ctof_kernel_bytes", "ctof_kernel_tabulate", "ctof_kernel_tabulate_qu
            "ctof_relu_bwd", "ctof_mse_ws_bytes", "ctof_mse", "ctof_adam_step",
            "ctof_to_channels_last", "ctof_from_channels_last", "ctof_philox4x32", "ctof_poisson",
            "ctof_noisy_histogram_ws_bytes", "ctof_noisy_histogram", "ctof_warmstart_loss_ws_bytes",
-           "ctof_warmstart_loss", "ctof_absmax_ws_bytes", "ctof_absmax", "ctof_depth_resample")
+           "ctof_warmstart_loss", "ctof_absmax_ws_bytes", "ctof_absmax", "ctof_depth_resample",
+           "ctof_sumsq_ws_bytes", "ctof_sumsq", "ctof_layer_threshold_ws_bytes", "ctof_layer_threshold")
 
 
 class CtofError(RuntimeError):
@@ -55,7 +56,8 @@ class _SolverOpts(ctypes.Structure):
                 ("rel_tol", ctypes.c_double), ("check_every", ctypes.c_int32),
                 ("warm_start", ctypes.c_int32), ("history_dev", ctypes.c_void_p),
                 ("timing", ctypes.c_int32), ("lipschitz_scans", ctypes.POINTER(ctypes.c_double)),
-                ("lambda_scans", ctypes.POINTER(ctypes.c_double))]
+                ("lambda_scans", ctypes.POINTER(ctypes.c_double)),
+                ("lambda_l1_z", ctypes.POINTER(ctypes.c_double))]
 
 
 class _SolverReport(ctypes.Structure):
@@ -138,6 +140,10 @@ def lib() -> ctypes.CDLL:
         L.ctof_absmax_ws_bytes.argtypes = [i32, ctypes.POINTER(sz)]
         L.ctof_absmax.argtypes = [i32, i64, vp, vp, vp, sz, vp]
         L.ctof_depth_resample.argtypes = [i32, i32, i64, vp, vp, i32, vp]
+        L.ctof_sumsq_ws_bytes.argtypes = [i32, ctypes.POINTER(sz)]
+        L.ctof_sumsq.argtypes = [i32, i64, vp, vp, vp, sz, vp]
+        L.ctof_layer_threshold_ws_bytes.argtypes = [i32, ctypes.POINTER(sz)]
+        L.ctof_layer_threshold.argtypes = [i32, i64, vp, f32, vp, sz, vp]
         L.ctof_last_error.argtypes = []
         L.ctof_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -319,13 +325,22 @@ class Report:
     fell_back: int = 0
 
 
+def _l1_array(l1, nz):
+    if l1 is None:
+        return None
+    vals = [float(v) for v in l1]
+    if len(vals) != nz:
+        raise ValueError(f"need {nz} per-layer L1 weights, got {len(vals)}")
+    return (ctypes.c_double * nz)(*vals)
+
+
 def reconstruct(k: Kernel, d, mu=None, max_iter: int = 200, lam: float = -1.0,
                 lipschitz: float = 0.0, power_iters: int = 50, rel_tol: float = 0.0,
                 check_every: int = 10, warm_start: bool = False, history: bool = False,
-                timing: bool = False, stream=None):
+                timing: bool = False, l1=None, stream=None):
     """FISTA reconstruction; returns (mu, Report, history or None).  warm_start:
     0/False zero start, 1/True start from ``mu``, 2 start from ``mu`` with the
-    zero-start fallback."""
+    zero-start fallback.  l1: per-layer L1 weights (nz numbers) or None."""
     torch = _torch()
     i = k.info
     d = _contig(d, _dtype(k.precision), (i.nt, i.n, i.n))
@@ -334,9 +349,10 @@ def reconstruct(k: Kernel, d, mu=None, max_iter: int = 200, lam: float = -1.0,
         warm_start = False
     mu = _contig(mu, d.dtype, (i.nz, i.n, i.n))
     hist = torch.zeros((max_iter, 2), dtype=torch.float64, device=d.device) if history else None
+    l1a = _l1_array(l1, i.nz)
     opts = _SolverOpts(int(max_iter), float(lam), float(lipschitz), int(power_iters),
                        float(rel_tol), int(check_every), int(warm_start),
-                       hist.data_ptr() if hist is not None else None, int(bool(timing)))
+                       hist.data_ptr() if hist is not None else None, int(bool(timing)), None, None, l1a)
     rep = _SolverReport()
     _, nb = k.workspace_bytes(max_iter)
     ws = k.workspace(nb, d.device)
@@ -356,7 +372,7 @@ def _report(rep) -> Report:
 
 def reconstruct_batched(kernels, ds, mus=None, max_iter: int = 200, lam=-1.0, lipschitz=0.0,
                         power_iters: int = 50, rel_tol: float = 0.0, check_every: int = 10,
-                        warm_start: bool = False, stream=None):
+                        warm_start: bool = False, l1=None, stream=None):
     """FISTA for many scans at once; scans sharing a Kernel object form one
     shape class.  lam / lipschitz: one value for all scans or one per scan
     (both sequences, then every scan's pair is used as given).  warm_start as
@@ -382,14 +398,15 @@ def reconstruct_batched(kernels, ds, mus=None, max_iter: int = 200, lam=-1.0, li
     _check(lib().ctof_workspace_bytes_batched(n, handles, int(max_iter), ctypes.byref(nb)))
     ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=ds[0].device)
     per_scan = not isinstance(lipschitz, (int, float))
+    l1a = _l1_array(l1, kernels[0].info.nz)
     if per_scan:
         la = (ctypes.c_double * n)(*[float(x) for x in lipschitz])
         lb = (ctypes.c_double * n)(*[float(x) for x in lam])
         opts = _SolverOpts(int(max_iter), 0.0, 0.0, int(power_iters), float(rel_tol), int(check_every),
-                           int(warm_start), None, 0, la, lb)
+                           int(warm_start), None, 0, la, lb, l1a)
     else:
         opts = _SolverOpts(int(max_iter), float(lam), float(lipschitz), int(power_iters),
-                           float(rel_tol), int(check_every), int(warm_start), None, 0)
+                           float(rel_tol), int(check_every), int(warm_start), None, 0, None, None, l1a)
     reps = (_SolverReport * n)()
     _check(lib().ctof_reconstruct_batched(n, handles, dptr, mptr, ctypes.byref(opts), reps,
                                           ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
@@ -445,3 +462,48 @@ def tune(k: Kernel, nvol: int = 1, iters: int = 5, cache: Optional[str] = None, 
             json.dump(table, f, indent=1, sort_keys=True)
         os.replace(tmp, cache)
     return bt.value, bz.value, times
+
+
+def layer_energy(k: Kernel, stream=None):
+    """Per-layer sensitivity ||A e_z||^2 (host float64 [nz]): the forward
+    model's response to a unit absorber at the window centre of each layer,
+    squared and summed on the GPU (FP64)."""
+    torch = _torch()
+    i = k.info
+    dt = _dtype(k.precision)
+    if dt != torch.float32:
+        raise ValueError("layer_energy takes a float handle")
+    out = torch.zeros(i.nz, dtype=torch.float64, device="cuda")
+    nb = ctypes.c_size_t()
+    _check(lib().ctof_sumsq_ws_bytes(1, ctypes.byref(nb)))
+    ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device="cuda")
+    mu = torch.zeros((i.nz, i.n, i.n), dtype=dt, device="cuda")
+    for z in range(i.nz):
+        mu.zero_()
+        mu[z, i.n // 2, i.n // 2] = 1.0
+        m = forward(k, mu, stream=stream)
+        _check(lib().ctof_sumsq(1, int(m.numel()), m.data_ptr(), out[z:].data_ptr(), ws.data_ptr(), ws.numel(),
+                                _stream_ptr(stream)))
+    return out.cpu().numpy()
+
+
+def l1_depth_weights(k: Kernel, lam1: float, stream=None):
+    """Per-layer L1 weights lam1 * e(z) / max e(z), e(z) = ||A e_z||^2: a
+    voxel's soft threshold in absorption units, lambda(z) / e(z), is then the
+    same at every depth (the layer-wise weights of Eq. 10 counter the loss of
+    sensitivity with depth)."""
+    e = layer_energy(k, stream=stream)
+    return [float(lam1 * v / e.max()) for v in e]
+
+
+def layer_threshold(mu, frac: float, stream=None):
+    """In place: zero the values of each layer of mu (float32 [nz, n, n])
+    below frac times the layer's maximum magnitude."""
+    torch = _torch()
+    nz = int(mu.shape[0])
+    nb = ctypes.c_size_t()
+    _check(lib().ctof_layer_threshold_ws_bytes(nz, ctypes.byref(nb)))
+    ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=mu.device)
+    _check(lib().ctof_layer_threshold(nz, int(mu[0].numel()), mu.data_ptr(), float(frac), ws.data_ptr(),
+                                      ws.numel(), _stream_ptr(stream)))
+    return mu

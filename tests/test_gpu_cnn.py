@@ -169,7 +169,13 @@ def test_conv_input_gradient(kind, grid, ci, co):
     assert np.all(_host(dx)[:, :5] == 0)
 
 
-@pytest.mark.parametrize("kind,grid,ci,co", CASES)
+# 3x3x3 layers whose rows are multiples of 8 take the LDS-staged weight
+# gradient (one or two 32-channel chunks, one to three output tiles)
+STAGED = [("k3", (2, 4, 8, 16), 40, 48), ("k3", (1, 4, 8, 32), 2, 16), ("k3", (1, 3, 4, 32), 64, 32),
+          ("k3", (2, 2, 8, 8), 16, 16)]
+
+
+@pytest.mark.parametrize("kind,grid,ci,co", CASES + STAGED)
 def test_conv_weight_gradient(kind, grid, ci, co):
     nn = _nn()
     x, W, b = _setup(kind, grid, ci, co, 15)
