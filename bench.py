@@ -270,6 +270,52 @@ def run_cnn(args, ctof, torch, dev) -> int:
     return 0
 
 
+def run_2d(args, ctof, torch, dev) -> int:
+    """The 2D single-plane settings (32x32 scan at 1 mm and 128x128 at
+    0.25 mm over a 32 mm field, one absorbing plane at 6.5 mm, 256 bins):
+    wall time of one FP32 reconstruction to gradient-mapping ratio rel_tol,
+    power iteration included (tabulation excluded), median of repeats; and
+    per scan when many scans of the shape are solved in one batched call."""
+    from synth import noise, phantoms, workloads
+    out = {"workload": "2D single plane (Eq. 9 model), FP32, solve to gradient-mapping ratio "
+                       f"<= {args.rel_tol:g}", "paper_context_ms": 8.0}
+    for name in ("2d32", "2d128"):
+        g = workloads.geometry_for(name)
+        w = workloads.workload(name)
+        k = ctof.tabulate(g, ctof.FP32)
+        ds = []
+        for s in range(args.scans):
+            mu = phantoms.workload_phantom(w, g, 200 + s)
+            m = ctof.forward(k, torch.tensor(mu, dtype=torch.float32, device=dev))
+            ds.append(torch.tensor(noise.poisson_histogram(m.double().cpu().numpy(), 1e5, 300 + s),
+                                   dtype=torch.float32, device=dev))
+        ctof.reconstruct(k, ds[0], max_iter=20)  # warm-up
+        times, iters = [], []
+        for d in ds[:min(len(ds), 11)]:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, rep, _ = ctof.reconstruct(k, d, max_iter=3000, rel_tol=args.rel_tol, check_every=10)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            iters.append(rep.iters)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, reps = ctof.reconstruct_batched([k] * len(ds), ds, max_iter=3000, rel_tol=args.rel_tol, check_every=10)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        out[name] = {"n": g.nx, "pitch_mm": g.pitch_mm, "single_ms_median": 1e3 * float(np.median(times)),
+                     "single_iters_median": float(np.median(iters)),
+                     "ms_per_iter": 1e3 * float(np.median(times)) / float(np.median(iters)),
+                     "batched_scans": len(ds), "batched_ms_per_scan": 1e3 * tb / len(ds),
+                     "batched_iters_mean": float(np.mean([r.iters for r in reps]))}
+        log(f"{name}: {out[name]['single_ms_median']:.2f} ms per reconstruction "
+            f"({out[name]['single_iters_median']:.0f} iterations); batched {out[name]['batched_ms_per_scan']:.3f} ms/scan")
+        del k
+        torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -280,10 +326,13 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", dest="variants", action="store_false",
                     help="skip the BF16 contraction variants of the default run")
+    ap.add_argument("--no-tune", dest="tune", action="store_false",
+                    help="keep the built-in FFT planes-per-block rule instead of timing the choices")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     ap.add_argument("--batch", type=int, default=8, help="cnn workload: samples per step")
-    ap.add_argument("--workload", default="precision", choices=["precision", "batching", "warmstart", "cnn"],
+    ap.add_argument("--workload", default="precision",
+                    choices=["precision", "batching", "warmstart", "cnn", "2d"],
                     help="precision: the iteration-rate metric (default); batching: 64 uneven "
                          "scans solved to gradient-mapping ratio 1e-3, plain vs batched vs batched with "
                          "the learned start; warmstart: held-out scans of the learned geometry, zero vs "
@@ -303,6 +352,7 @@ def main() -> int:
     from paper_2101_11680_amd import ctof
     from synth import noise, phantoms, workloads
 
+    globals()["np"] = np
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
@@ -325,6 +375,8 @@ def main() -> int:
         return run_warmstart(args, ctof, torch, dev)
     if args.workload == "cnn":
         return run_cnn(args, ctof, torch, dev)
+    if args.workload == "2d":
+        return run_2d(args, ctof, torch, dev)
     prec = ctof.PRECISIONS[args.precision]
     dtype = torch.float64 if prec == ctof.FP64 else torch.float32
 
@@ -340,6 +392,13 @@ def main() -> int:
     torch.cuda.empty_cache()
     i = k.info
     log(f"tabulated P={i.p} matrices={i.nmat} in {t_tab:.3f}s")
+    tuning = None
+    if args.tune:
+        # FFT planes per block for this shape and one volume (set-up, untimed,
+        # like tabulation)
+        bt, bz, times = ctof.tune(k, nvol=1, iters=5)
+        tuning = {"bb_t": bt, "bb_z": bz, "ms_per_iter_candidates": times}
+        log(f"tuned FFT planes per block: bins {bt}, layers {bz} (candidates {times})")
 
     mu_true = phantoms.workload_phantom(w, g, args.seed)
     m_true = ctof.forward(k, torch.tensor(mu_true, dtype=dtype, device=dev))
@@ -404,6 +463,7 @@ def main() -> int:
                          "512 bins of 20 ps, one volume, FISTA non-negative Tikhonov"),
             "n": g.nx, "nz": g.nz, "nt": g.nt, "fft_size": i.p, "matrices": i.nmat,
             "precision": args.precision, "mus_prime_per_mm": g.mus_prime_per_mm,
+            "fft_tuning": tuning,
         },
         "roofline": {
             "bound": "hbm",
@@ -440,6 +500,8 @@ def main() -> int:
         variants = {}
         for name in ("bf16x3", "bf16"):
             kv = ctof.tabulate(g, ctof.PRECISIONS[name])
+            if args.tune:
+                ctof.tune(kv, nvol=1, iters=5)
             ctof.reconstruct(kv, d, max_iter=args.warmup, lam=lam, lipschitz=L)
             torch.cuda.synchronize()
             t0 = time.perf_counter()

@@ -218,10 +218,11 @@ contract_fwd_kernel(CArgs a) {
 #pragma unroll
       for (int kk = 0; kk < KZ; ++kk) bv[kk] = (T)0;
     }
-    for (int tt = w; tt < ntt; tt += 4) {
+    // the next tile's kernel fragment is loaded before the current one's
+    // products, so each wave keeps a tile of loads in flight
+    auto frag = [&](int tt) { return khat + (((size_t)s * ntt + tt) * nchunk + ch) * (64 * KZ); };
+    auto tile = [&](int tt, const T (&av)[KZ]) {
       const int t0 = tt * 16;
-      T av[KZ];
-      load_frag<T, KZ, NT>(khat + (((size_t)s * ntt + tt) * nchunk + ch) * (64 * KZ), l, av);
       typename M::acc_t acc = {0, 0, 0, 0};
       if (ch > 0 && k.on) {
         // accumulate onto the previous layer chunk's partial result
@@ -231,6 +232,16 @@ contract_fwd_kernel(CArgs a) {
 #pragma unroll
       for (int kk = 0; kk < KZ; ++kk) acc = M::step(av[kk], bv[kk], acc);
       if (k.on) store4<T>(ocol + t0 + 4 * g, acc);
+    };
+    T a0[KZ], a1[KZ];
+    int tt = w;
+    if (tt < ntt) load_frag<T, KZ, NT>(frag(tt), l, a0);
+    for (; tt < ntt; tt += 8) {
+      if (tt + 4 < ntt) load_frag<T, KZ, NT>(frag(tt + 4), l, a1);
+      tile(tt, a0);
+      if (tt + 4 >= ntt) break;
+      if (tt + 8 < ntt) load_frag<T, KZ, NT>(frag(tt + 8), l, a0);
+      tile(tt + 4, a1);
     }
   }
 }
@@ -255,21 +266,33 @@ contract_adj_kernel(CArgs a) {
   typename M::acc_t acc[ZT];
 #pragma unroll
   for (int zt = 0; zt < ZT; ++zt) acc[zt] = {0, 0, 0, 0};
-  for (int ch = w; ch < ntp / 16; ch += 4) {
-    const int t0 = ch * 16 + 4 * g;
-    T bv[4];
+  // next chunk's kernel fragments and data are loaded before the current
+  // chunk's products (one chunk of loads in flight per wave)
+  const int nch = ntp / 16;
+  auto load_chunk = [&](int ch, T (&av)[ZT][4], T (&bv)[4]) {
     if (k.on) {
-      load_run<T, 4>(vcol + t0, bv);
+      load_run<T, 4>(vcol + ch * 16 + 4 * g, bv);
     } else {
       bv[0] = bv[1] = bv[2] = bv[3] = (T)0;
     }
 #pragma unroll
-    for (int zt = 0; zt < ZT; ++zt) {
-      T av[4];
-      load_frag<T, 4, NT>(khat + (((size_t)s * (ntp / 16) + ch) * ZT + zt) * 256, l, av);
+    for (int zt = 0; zt < ZT; ++zt) load_frag<T, 4, NT>(khat + (((size_t)s * nch + ch) * ZT + zt) * 256, l, av[zt]);
+  };
+  auto mul_chunk = [&](const T (&av)[ZT][4], const T (&bv)[4]) {
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) acc[zt] = M::step(av[kk], bv[kk], acc[zt]);
-    }
+    for (int zt = 0; zt < ZT; ++zt)
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) acc[zt] = M::step(av[zt][kk], bv[kk], acc[zt]);
+  };
+  T a0[ZT][4], a1[ZT][4], b0[4], b1[4];
+  int ch = w;
+  if (ch < nch) load_chunk(ch, a0, b0);
+  for (; ch < nch; ch += 8) {
+    if (ch + 4 < nch) load_chunk(ch + 4, a1, b1);
+    mul_chunk(a0, b0);
+    if (ch + 4 >= nch) break;
+    if (ch + 8 < nch) load_chunk(ch + 8, a0, b0);
+    mul_chunk(a1, b1);
   }
   // sum the four waves' partial products (fixed order); output rows 4g..4g+3
   // of every tile sit in lane group g, so all 64 lanes take part

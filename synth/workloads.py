@@ -13,6 +13,8 @@ Monte-Carlo data are not available, so every workload here is synthetic:
 * ``batching``  64 scans, N in {32,48,64,96,128}, Nz in {16,32,64} over
                 1..20 mm, 256 bins of 25 ps
 * ``learned``   64x64, 32 layers 1..20 mm, 256 bins of 25 ps
+* ``2d32``      32x32 scan at 1 mm, one plane at 6.5 mm, 256 bins of 25 ps
+* ``2d128``     128x128 scan at 0.25 mm, one plane at 6.5 mm, 256 bins
 
 All share mu_a = 0.01/mm and n = 1.4 for the homogeneous background
 (section "Transient Light Transport: Forward Model": homogeneous background
@@ -92,6 +94,19 @@ WORKLOADS: Dict[str, dict] = {
         geometry=_geom(64, 0.5, 1.0, 20.0, 32, 256, 25.0),
         n_abs=(1, 4), radius=(0.5, 2.0), dmua=(0.01, 0.05), kinds=("sphere", "bar"),
         peak=(1e4, 1e6), iters=200, precision="fp32"),
+    # 2D single-plane settings: a 32 x 32 mm field behind 6.5 mm of tissue
+    # (mu_s = 9/mm read with anisotropy 0.9 as mu_s' = 0.9/mm), one absorbing
+    # plane 0.5 mm thick, 256 bins of 25 ps
+    "2d32": dict(
+        geometry=Geometry(nx=32, ny=32, pitch_mm=1.0, z_mm=(6.5,), dz_mm=0.5, nt=256, dt_ps=25.0,
+                          mus_prime_per_mm=0.9),
+        n_abs=(1, 3), radius=(1.0, 3.0), dmua=(0.01, 0.05), kinds=("sphere", "bar"),
+        peak=(1e5, 1e5), iters=200, precision="fp32"),
+    "2d128": dict(
+        geometry=Geometry(nx=128, ny=128, pitch_mm=0.25, z_mm=(6.5,), dz_mm=0.5, nt=256, dt_ps=25.0,
+                          mus_prime_per_mm=0.9),
+        n_abs=(1, 3), radius=(1.0, 3.0), dmua=(0.01, 0.05), kinds=("sphere", "bar"),
+        peak=(1e5, 1e5), iters=200, precision="fp32"),
 }
 
 BATCH_SIZES = (32, 48, 64, 96, 128)
