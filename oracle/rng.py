@@ -156,3 +156,13 @@ def noisy_histogram(m, peak: float, seed: int, stream: int = 0):
     c = poisson_sample(lam, seed, stream)
     d = np.zeros(m.shape, dtype=np.float32) if s == 0 else (c.astype(np.float64) / s).astype(np.float32)
     return d.reshape(m.shape)
+
+
+def noisy_counts(m, scale: float, background: float, seed: int, stream: int = 0):
+    """Counting noise with dark counts (the multiplexing simulations of the
+    paper): c = Poisson(scale max(m, 0) + background), returned as
+    (c - background) / scale (float32 out, float64 inside)."""
+    m = np.asarray(m, dtype=np.float32)
+    lam = np.maximum(m.astype(np.float64), 0.0) * scale + background
+    c = poisson_sample(lam.ravel(), seed, stream).reshape(m.shape)
+    return ((c.astype(np.float64) - background) / scale).astype(np.float32)
