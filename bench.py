@@ -316,6 +316,122 @@ def run_2d(args, ctof, torch, dev) -> int:
     return 0
 
 
+def run_mux(args, ctof, torch, dev) -> int:
+    """Multiplexed reconstruction (Eq. 12) on the 128x128 scan, 64 layers, 512
+    bins: the scan cut into 8x8 tiles of sources, each tile measured with the
+    128 on/off patterns of the 64x64 Hadamard matrix, counting noise at
+    5 Mcps for the brightest measurement plus 200 cps of dark counts over
+    --integration-ms.  Reports FISTA iterations/s on S A (power iteration
+    excluded) beside the unmultiplexed iteration on the same grid, and the
+    fused kernel r = S^T (S m - y) timed alone against its roofline.  Then
+    the 2D single-plane setting (32x32 scan, one 8x8 tile pattern set per
+    tile): one reconstruction to gradient-mapping ratio rel_tol, power
+    iteration included."""
+    from synth import mux as smux
+    from synth import noise, phantoms, workloads
+    rate, dark, t_int = 5e6, 200.0, args.integration_ms * 1e-3
+    w = workloads.workload("precision")
+    g = workloads.geometry_for("precision", seed=args.seed)
+    k = ctof.tabulate(g, ctof.FP32)
+    if args.tune:
+        ctof.tune(k, nvol=1, iters=5)
+    i = k.info
+    S = smux.onoff(64)
+    mx = ctof.Mux(torch.tensor(S, dtype=torch.float32, device=dev), 8, 8)
+    M, P, ntiles = S.shape[0], S.shape[1], mx.ntiles(g.nx)
+    mu = torch.tensor(phantoms.workload_phantom(w, g, args.seed), dtype=torch.float32, device=dev)
+    m = ctof.forward(k, mu)
+    y = ctof.mux_forward(k, mx, m)
+    # counts: the brightest measurement reaches rate * T photons; dark counts
+    # spread evenly over the bins
+    scale = rate * t_int / float(y.sum(dim=0).max())
+    bg = dark * t_int / g.nt
+    yn = ctof.noisy_counts(y, scale, bg, 1 + args.seed, 7)
+    d = torch.tensor(noise.poisson_histogram(m.double().cpu().numpy(), w["peak"][0], 1000 + args.seed),
+                     dtype=torch.float32, device=dev)
+    _, rep0, _ = ctof.reconstruct(k, yn, max_iter=1, mux=mx)
+    L, lam = rep0.lipschitz, rep0.lam
+    _, rp0, _ = ctof.reconstruct(k, d, max_iter=1)
+    Lp, lamp = rp0.lipschitz, rp0.lam
+    res = {}
+    for name, data, kw, LL, ll in (("multiplexed", yn, {"mux": mx}, L, lam), ("plain", d, {}, Lp, lamp)):
+        if args.warmup > 0:
+            ctof.reconstruct(k, data, max_iter=args.warmup, lam=ll, lipschitz=LL, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, rep, _ = ctof.reconstruct(k, data, max_iter=args.steps, lam=ll, lipschitz=LL, timing=True, **kw)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        res[name] = {"iters_per_s": args.steps / wall, "ms_per_iter": 1e3 * wall / args.steps,
+                     "ms_fft_t_per_iter": rep.ms_fft_t / rep.iters, "gmap_ratio": rep.gmap_ratio}
+        log(f"{name}: {res[name]['iters_per_s']:.1f} iters/s")
+    # the fused multiplexing kernel alone, on the solver's shapes
+    r = torch.empty_like(m)
+    reps = 50
+    for _ in range(3):
+        ctof.mux_normal(k, mx, m, yn, out=r)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        ctof.mux_normal(k, mx, m, yn, out=r)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    ncol = g.nt * ntiles
+    flops = 4.0 * M * P * ncol
+    nbytes = 4.0 * (2 * g.nt * g.ny * g.nx + g.nt * M * ntiles)
+    tf = flops / (ms * 1e-3) / 1e12
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    mfma_bound = flops / 157.3e12 > nbytes / 8.0e12
+    log(f"mux kernel {1e3 * ms:.1f} us: {tf:.1f} TFLOP/s, {gbs:.0f} GB/s")
+
+    # 2D single plane: 32x32 at 1 mm, one plane at 6.5 mm, 16 tiles of 8x8
+    g2 = workloads.geometry_for("2d32")
+    w2 = workloads.workload("2d32")
+    k2 = ctof.tabulate(g2, ctof.FP32)
+    times, iters = [], []
+    for s in range(11):
+        mu2 = torch.tensor(phantoms.workload_phantom(w2, g2, 200 + s), dtype=torch.float32, device=dev)
+        y2 = ctof.mux_forward(k2, mx, ctof.forward(k2, mu2))
+        sc2 = rate * t_int / float(y2.sum(dim=0).max())
+        y2n = ctof.noisy_counts(y2, sc2, dark * t_int / g2.nt, 300 + s, 7)
+        if s == 0:
+            ctof.reconstruct(k2, y2n, max_iter=20, mux=mx)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, rep2, _ = ctof.reconstruct(k2, y2n, max_iter=3000, rel_tol=args.rel_tol, check_every=10, mux=mx)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        iters.append(rep2.iters)
+    out = {
+        "metric": "multiplexed recon iters/s at 128^2x64 vox, 512 bins, 8x8 tiles x 128 on/off Hadamard patterns",
+        "value": res["multiplexed"]["iters_per_s"], "unit": "iters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["multiplexed"]["ms_per_iter"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": ("multiplexed: 128x128 scan at 0.5 mm in 8x8 source tiles, 128 on/off Hadamard "
+                                "patterns per tile, 64 layers 1-30 mm, 512 bins of 20 ps; counts at 5 Mcps "
+                                f"peak plus 200 cps dark over {args.integration_ms:g} ms"),
+                   "rows": M, "tile": [8, 8], "ntiles": ntiles},
+        "plain_iters_per_s": res["plain"]["iters_per_s"],
+        "overhead_vs_plain": res["plain"]["iters_per_s"] / res["multiplexed"]["iters_per_s"] - 1.0,
+        "stages_ms_per_iter": {"fft_t_multiplexed": res["multiplexed"]["ms_fft_t_per_iter"],
+                               "fft_t_plain": res["plain"]["ms_fft_t_per_iter"]},
+        "roofline": {"bound": "mfma" if mfma_bound else "hbm",
+                     "kernel": "mux_kernel (fused r = S^T (S m - y), FP32 MFMA 16x16x4)",
+                     "achieved": tf if mfma_bound else gbs, "peak": 157.3 if mfma_bound else 8000.0,
+                     "unit": "TFLOP/s" if mfma_bound else "GB/s",
+                     "frac": (tf / 157.3) if mfma_bound else (gbs / 8000.0), "traffic": None,
+                     "us_per_launch": 1e3 * ms, "flops_per_launch": flops, "bytes_per_launch": nbytes,
+                     "hbm_frac": gbs / 8000.0, "mfma_frac": tf / 157.3},
+        "mux_2d32": {"single_ms_median": 1e3 * float(np.median(times)),
+                     "single_iters_median": float(np.median(iters)), "tiles": mx.ntiles(g2.nx)},
+        "cpu_baseline": None,
+    }
+    log(f"2d32 multiplexed: {out['mux_2d32']['single_ms_median']:.2f} ms per reconstruction")
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -332,13 +448,15 @@ def main() -> int:
                     help="only run a plain device copy of MIB MiB (counter calibration)")
     ap.add_argument("--batch", type=int, default=8, help="cnn workload: samples per step")
     ap.add_argument("--workload", default="precision",
-                    choices=["precision", "batching", "warmstart", "cnn", "2d"],
+                    choices=["precision", "batching", "warmstart", "cnn", "2d", "mux"],
                     help="precision: the iteration-rate metric (default); batching: 64 uneven "
                          "scans solved to gradient-mapping ratio 1e-3, plain vs batched vs batched with "
                          "the learned start; warmstart: held-out scans of the learned geometry, zero vs "
                          "learned start (--scans, default 64; 512 for the full evaluation)")
     ap.add_argument("--scans", type=int, default=64)
     ap.add_argument("--rel-tol", type=float, default=1e-3)
+    ap.add_argument("--integration-ms", type=float, default=10.0,
+                    help="mux workload: integration time per measurement")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -377,6 +495,8 @@ def main() -> int:
         return run_cnn(args, ctof, torch, dev)
     if args.workload == "2d":
         return run_2d(args, ctof, torch, dev)
+    if args.workload == "mux":
+        return run_mux(args, ctof, torch, dev)
     prec = ctof.PRECISIONS[args.precision]
     dtype = torch.float64 if prec == ctof.FP64 else torch.float32
 

@@ -159,6 +159,53 @@ ctof_status ctof_forward(ctof_kernel k, const void *mu_dev, void *m_dev, void *w
 ctof_status ctof_adjoint(ctof_kernel k, const void *r_dev, void *g_dev, void *ws_dev,
                          size_t ws_bytes, hipStream_t stream);
 
+/* ===================================================================== *
+ * Source multiplexing (subsection "Multiplexed Confocal ToF-DOT", Eq. 12).
+ *
+ * With several sources on at once, each multiplexed measurement is a fixed
+ * linear combination of the confocal transients: y = S m = S A mu.  The
+ * scan grid is cut into tiles of tile_x x tile_y positions (P = tile_x *
+ * tile_y; the paper's 8 x 8 source array is one tile of 64) and the same S
+ * (rows x P) combines the P transients of every tile in every time bin:
+ *     y[t][i][g] = sum_j S[i][j] m[t][gy*tile_y + jy][gx*tile_x + jx]
+ * with tile g = gy * (n / tile_x) + gx and position j = jy * tile_x + jx.
+ * S may be any matrix: a +-1 Hadamard matrix (y = H m), its on/off pattern
+ * pair stacked as a 2P x P 0/1 matrix, a selection, ...
+ * ===================================================================== */
+
+typedef struct {
+  int32_t tile_x, tile_y;  /* tile of scan positions; both divide n */
+  int32_t rows;            /* M, measurements per tile and bin (1..128); P = tile_x * tile_y <= 128 */
+  const void *s_dev;       /* S [rows][P], row-major, device memory, element type of the data */
+} ctof_mux;
+
+/*
+ * y = S m:  m_dev [nt][n][n]  ->  y_dev [nt][rows][ntiles], ntiles =
+ * (n / tile_x) * (n / tile_y), element type of k's precision.  The buffers
+ * must not overlap.  Asynchronous.  Both multiply on the matrix cores
+ * (16x16x4 MFMA in the data's precision) with S held in registers.
+ */
+ctof_status ctof_mux_forward(ctof_kernel k, const ctof_mux *mux, const void *m_dev, void *y_dev,
+                             hipStream_t stream);
+
+/* m = S^T y:  y_dev [nt][rows][ntiles]  ->  m_dev [nt][n][n] (every
+ * element written).  The buffers must not overlap.  Asynchronous. */
+ctof_status ctof_mux_adjoint(ctof_kernel k, const ctof_mux *mux, const void *y_dev, void *m_dev,
+                             hipStream_t stream);
+
+/*
+ * Gradient input of the multiplexed data term, fused in one pass over m:
+ * r = S^T (S m - y) (y_dev NULL: r = S^T S m), with m_dev, r_dev [nt][n][n]
+ * (r_dev may equal m_dev; no other overlap) and y_dev [nt][rows][ntiles].
+ * fit_dev: NULL, or a device double receiving 1/2 ||S m - y||^2 (FP64
+ * per-block partial sums added in a fixed order).  ws_dev: at least
+ * ctof_mux_normal_ws_bytes bytes of device memory, 16-byte aligned.
+ * Asynchronous.
+ */
+ctof_status ctof_mux_normal_ws_bytes(ctof_kernel k, const ctof_mux *mux, size_t *ws_bytes);
+ctof_status ctof_mux_normal(ctof_kernel k, const ctof_mux *mux, const void *m_dev, const void *y_dev, void *r_dev,
+                            double *fit_dev, void *ws_dev, size_t ws_bytes, hipStream_t stream);
+
 /*
  * Solver options (section "Reconstruction Algorithm"; FISTA with constant
  * step, no restart):
@@ -199,6 +246,13 @@ ctof_status ctof_adjoint(ctof_kernel k, const void *r_dev, void *g_dev, void *ws
  *                    the clamp, and the gradient-mapping ratio's
  *                    denominator becomes ||max(0, A^T d - lambda_l1_z)||.
  *                    Batched solves need one layer count for all scans.
+ *   mux              NULL, or the multiplexing of the measurements (Eq. 12):
+ *                    ctof_reconstruct then fits y = S A mu, d_dev holds y
+ *                    [nt][rows][ntiles], every A and A^T of the solver
+ *                    becomes S A and A^T S^T (L_A = ||S A||^2, the
+ *                    gradient-mapping denominator ||max(0, A^T S^T y)||,
+ *                    datafit = 1/2 ||S A mu - y||^2), and no extra
+ *                    workspace is needed.  Single-scan solves only.
  */
 typedef struct {
   int32_t max_iter;
@@ -213,6 +267,7 @@ typedef struct {
   const double *lipschitz_scans;
   const double *lambda_scans;
   const double *lambda_l1_z;
+  const ctof_mux *mux;
 } ctof_solver_opts;
 
 /*
@@ -491,6 +546,17 @@ ctof_status ctof_poisson(int64_t n, const float *lam_dev, uint64_t seed, uint32_
 ctof_status ctof_noisy_histogram_ws_bytes(int64_t n, size_t *ws_bytes);
 ctof_status ctof_noisy_histogram(int64_t n, const float *m_dev, double peak, uint64_t seed, uint32_t stream_id,
                                  float *d_dev, void *ws_dev, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Counting noise with dark counts (section "Advantages of Multiplexing"):
+ * out = (c - background) / scale with c ~ Poisson(scale * max(m, 0) +
+ * background), m and out float [n] (may be the same buffer).  scale
+ * converts the model to expected signal counts, background is the expected
+ * dark count of one element.  Counters and sampler as in ctof_poisson; the
+ * mean is computed in FP64 without contraction.
+ */
+ctof_status ctof_noisy_counts(int64_t n, const float *m_dev, double scale, double background, uint64_t seed,
+                              uint32_t stream_id, float *out_dev, hipStream_t stream);
 
 const char *ctof_last_error(void);
 

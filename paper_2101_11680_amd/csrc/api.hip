@@ -224,6 +224,7 @@ struct Engine {
   hipStream_t st;
   const int *live = nullptr;  // per-volume flags honoured by every launch (batched solves)
   const double *l1dev = nullptr;  // per-layer L1 weights in the workspace when the objective has them
+  const ctof::MuxArgs *mux = nullptr;  // source multiplexing of the measurements (single-scan solves)
 
   const ctof::Dims &dm() const { return k->dims; }
   T *yhat() const { return reinterpret_cast<T *>(ws + L.yhat); }
@@ -290,6 +291,34 @@ struct Engine {
     return e != hipSuccess ? e : col_z(true);
   }
 };
+
+// Multiplexing descriptor -> kernel arguments (sizes from the kernel handle).
+ctof_status make_mux(const ctof_kernel_s *k, const ctof_mux *mx, ctof::MuxArgs *a) {
+  if (!mx) return set_error(CTOF_EINVAL, "mux is NULL");
+  const int n = k->dims.n;
+  if (mx->tile_x < 1 || mx->tile_y < 1 || n % mx->tile_x != 0 || n % mx->tile_y != 0)
+    return set_error(CTOF_EINVAL, "mux tile %dx%d must divide the scan side %d", mx->tile_x, mx->tile_y, n);
+  const int P = mx->tile_x * mx->tile_y;
+  if (P > ctof::kMuxMaxDim)
+    return set_error(CTOF_EINVAL, "mux tile of %d positions exceeds %d", P, ctof::kMuxMaxDim);
+  if (mx->rows < 1 || mx->rows > ctof::kMuxMaxDim)
+    return set_error(CTOF_EINVAL, "mux rows %d must be in [1, %d]", mx->rows, ctof::kMuxMaxDim);
+  const size_t es = k->prec == CTOF_FP64 ? 8 : 4;
+  if (!mx->s_dev || (reinterpret_cast<uintptr_t>(mx->s_dev) % es) != 0)
+    return set_error(CTOF_EINVAL, "mux s_dev is NULL or not aligned to its element");
+  std::memset(a, 0, sizeof(*a));
+  a->n = n;
+  a->nt = k->dims.nt;
+  a->tx = mx->tile_x;
+  a->ty = mx->tile_y;
+  a->M = mx->rows;
+  a->P = P;
+  a->ntx = n / mx->tile_x;
+  a->ntiles = a->ntx * (n / mx->tile_y);
+  a->S = mx->s_dev;
+  if ((long long)a->nt * a->ntiles >= (1LL << 31)) return set_error(CTOF_EINVAL, "too many mux columns");
+  return CTOF_OK;
+}
 
 ctof_status check_kernel(ctof_kernel k) {
   if (!k) return set_error(CTOF_EINVAL, "kernel handle is NULL");
@@ -418,6 +447,27 @@ std::vector<double> fista_betas(int iters) {
   return b;
 }
 
+// Bin-side pass of a multiplexed solve (Eq. 12): the spectra in xt back to
+// the histogram m (held in the idle mhat buffer), r = S^T (S m - y) in
+// place (y NULL: r = S^T S m), FP64 half squares of S m - y into
+// `partials` (nblk_t pairs) when given, and r back to spectra in xt.
+template <typename T>
+ctof_status enqueue_mux_residual(const Engine<T> &E, const void *y, double *partials) {
+  ctof::RowArgs a = E.row(ctof::ROW_SPEC_TO_SPATIAL, true);
+  a.sp_out[0] = E.mhat();
+  HIP_TRY(E.run_row(a));
+  ctof::MuxArgs m = *E.mux;
+  m.in = E.mhat();
+  m.out = E.mhat();
+  m.y = y;
+  m.partials = partials;
+  HIP_TRY(ctof::launch_mux(ctof::MUX_NORMAL, sizeof(T) == 8, m, E.L.nblk_t, E.st));
+  ctof::RowArgs b = E.row(ctof::ROW_SPATIAL_TO_SPEC, true);
+  b.sp_in[0] = E.mhat();
+  HIP_TRY(E.run_row(b));
+  return CTOF_OK;
+}
+
 // L_A of one class by power iteration on a single vector (FP64 Rayleigh
 // quotients); enqueued on the engine's stream, result in scal()[1].
 template <typename T>
@@ -435,7 +485,11 @@ ctof_status enqueue_power_iteration(const Engine<T> &E1, int iters) {
     a.scalar = E1.scal() + 0;
     HIP_TRY(E1.mu_to_spec(a));
     HIP_TRY(E1.fwd_to_xt());
-    HIP_TRY(E1.run_row(E1.row(ctof::ROW_PASS, true)));
+    if (E1.mux) {
+      if (ctof_status s = enqueue_mux_residual(E1, nullptr, nullptr); s != CTOF_OK) return s;
+    } else {
+      HIP_TRY(E1.run_row(E1.row(ctof::ROW_PASS, true)));
+    }
     HIP_TRY(E1.adj_to_xz());
     ctof::RowArgs c = E1.row(ctof::ROW_POWER_W, false);
     c.sp_in[0] = E1.pv();
@@ -545,10 +599,14 @@ ctof_status enqueue_final_fit(const Engine<T> &E, const void *const *d, void *co
   for (int v = 0; v < E.nvol; ++v) a.sp_in[v] = mu[v];
   HIP_TRY(E.mu_to_spec(a));
   HIP_TRY(E.fwd_to_xt());
-  ctof::RowArgs b = E.row(ctof::ROW_RESIDUAL, true);
-  for (int v = 0; v < E.nvol; ++v) b.sp_in[v] = d[v];
-  b.partials = pf;
-  HIP_TRY(E.run_row(b));
+  if (E.mux) {
+    if (ctof_status s = enqueue_mux_residual(E, d[0], pf); s != CTOF_OK) return s;
+  } else {
+    ctof::RowArgs b = E.row(ctof::ROW_RESIDUAL, true);
+    for (int v = 0; v < E.nvol; ++v) b.sp_in[v] = d[v];
+    b.partials = pf;
+    HIP_TRY(E.run_row(b));
+  }
   HIP_TRY(ctof::launch_reduce_volumes(pf, E.L.nblk_t, E.nvol, out, E.st));
   return CTOF_OK;
 }
@@ -568,7 +626,20 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
     HIP_TRY(hipMemcpyAsync(E.l1(), opt->lambda_l1_z, (size_t)dm.nz * sizeof(double), hipMemcpyHostToDevice, st));
     E.l1dev = E.l1();
   }
-  if (ctof_status s = enqueue_gmap0(E, dd); s != CTOF_OK) return s;
+  ctof::MuxArgs mux;
+  if (opt->mux) {
+    if (ctof_status s = make_mux(k, opt->mux, &mux); s != CTOF_OK) return s;
+    E.mux = &mux;
+    // the gradient-mapping denominator needs A^T S^T y: S^T y into mhat first
+    ctof::MuxArgs a = mux;
+    a.in = d;
+    a.out = E.mhat();
+    HIP_TRY(ctof::launch_mux(ctof::MUX_ADJ, sizeof(T) == 8, a, ctof::mux_default_blocks(a), st));
+    const void *sty[1] = {E.mhat()};
+    if (ctof_status s = enqueue_gmap0(E, sty); s != CTOF_OK) return s;
+  } else {
+    if (ctof_status s = enqueue_gmap0(E, dd); s != CTOF_OK) return s;
+  }
 
   double lam = opt->lambda_tikhonov, Lip = opt->lipschitz, LA = 0.0;
   if (Lip == 0.0) {
@@ -614,10 +685,14 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
     HIP_TRY(E.contract(false));
     HIP_TRY(mark(it, 1));
     HIP_TRY(E.col_t(true));
-    ctof::RowArgs a = E.row(ctof::ROW_RESIDUAL, true);
-    a.sp_in[0] = d;
-    a.partials = pk;
-    HIP_TRY(E.run_row(a));
+    if (E.mux) {
+      if (ctof_status s = enqueue_mux_residual(E, d, pk); s != CTOF_OK) return s;
+    } else {
+      ctof::RowArgs a = E.row(ctof::ROW_RESIDUAL, true);
+      a.sp_in[0] = d;
+      a.partials = pk;
+      HIP_TRY(E.run_row(a));
+    }
     HIP_TRY(E.col_t(false));
     HIP_TRY(mark(it, 2));
     HIP_TRY(E.contract(true));
@@ -1269,6 +1344,64 @@ ctof_status ctof_adjoint(ctof_kernel k, const void *r_dev, void *g_dev, void *ws
   return run_adjoint<float>(k, r_dev, g_dev, ws_dev, stream);
 }
 
+ctof_status ctof_mux_forward(ctof_kernel k, const ctof_mux *mux, const void *m_dev, void *y_dev,
+                             hipStream_t stream) {
+  if (ctof_status s = check_kernel(k); s != CTOF_OK) return s;
+  ctof::MuxArgs a;
+  if (ctof_status s = make_mux(k, mux, &a); s != CTOF_OK) return s;
+  if (!m_dev || !y_dev || (reinterpret_cast<uintptr_t>(m_dev) & 15))
+    return set_error(CTOF_EINVAL, "m or y is NULL, or m is not 16-byte aligned");
+  a.in = m_dev;
+  a.out = y_dev;
+  HIP_TRY(ctof::launch_mux(ctof::MUX_FWD, k->prec == CTOF_FP64, a, ctof::mux_default_blocks(a), stream));
+  return CTOF_OK;
+}
+
+ctof_status ctof_mux_adjoint(ctof_kernel k, const ctof_mux *mux, const void *y_dev, void *m_dev,
+                             hipStream_t stream) {
+  if (ctof_status s = check_kernel(k); s != CTOF_OK) return s;
+  ctof::MuxArgs a;
+  if (ctof_status s = make_mux(k, mux, &a); s != CTOF_OK) return s;
+  if (!m_dev || !y_dev || (reinterpret_cast<uintptr_t>(m_dev) & 15))
+    return set_error(CTOF_EINVAL, "m or y is NULL, or m is not 16-byte aligned");
+  a.in = y_dev;
+  a.out = m_dev;
+  HIP_TRY(ctof::launch_mux(ctof::MUX_ADJ, k->prec == CTOF_FP64, a, ctof::mux_default_blocks(a), stream));
+  return CTOF_OK;
+}
+
+ctof_status ctof_mux_normal_ws_bytes(ctof_kernel k, const ctof_mux *mux, size_t *ws_bytes) {
+  if (ctof_status s = check_kernel(k); s != CTOF_OK) return s;
+  ctof::MuxArgs a;
+  if (ctof_status s = make_mux(k, mux, &a); s != CTOF_OK) return s;
+  if (!ws_bytes) return set_error(CTOF_EINVAL, "ws_bytes is NULL");
+  *ws_bytes = ctof::round_up((size_t)ctof::mux_default_blocks(a) * 2 * sizeof(double), 256);
+  return CTOF_OK;
+}
+
+ctof_status ctof_mux_normal(ctof_kernel k, const ctof_mux *mux, const void *m_dev, const void *y_dev, void *r_dev,
+                            double *fit_dev, void *ws_dev, size_t ws_bytes, hipStream_t stream) {
+  if (ctof_status s = check_kernel(k); s != CTOF_OK) return s;
+  ctof::MuxArgs a;
+  if (ctof_status s = make_mux(k, mux, &a); s != CTOF_OK) return s;
+  if (!m_dev || !r_dev || (reinterpret_cast<uintptr_t>(m_dev) & 15) || (reinterpret_cast<uintptr_t>(r_dev) & 15))
+    return set_error(CTOF_EINVAL, "m or r is NULL or not 16-byte aligned");
+  const int blocks = ctof::mux_default_blocks(a);
+  const size_t need = (size_t)blocks * 2 * sizeof(double);
+  if (fit_dev) {
+    if (!ws_dev || (reinterpret_cast<uintptr_t>(ws_dev) & 15))
+      return set_error(CTOF_EINVAL, "workspace NULL or not 16-byte aligned");
+    if (ws_bytes < need) return set_error(CTOF_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
+  }
+  a.in = m_dev;
+  a.y = y_dev;
+  a.out = r_dev;
+  a.partials = fit_dev ? reinterpret_cast<double *>(ws_dev) : nullptr;
+  HIP_TRY(ctof::launch_mux(ctof::MUX_NORMAL, k->prec == CTOF_FP64, a, blocks, stream));
+  if (fit_dev) HIP_TRY(ctof::launch_reduce_rows(a.partials, blocks, 2, 1, fit_dev, stream));
+  return CTOF_OK;
+}
+
 ctof_status ctof_reconstruct(ctof_kernel k, const void *d_dev, void *mu_inout_dev, const ctof_solver_opts *opts,
                              ctof_solver_report *report, void *ws_dev, size_t ws_bytes, hipStream_t stream) {
   ctof_status s = check_kernel(k);
@@ -1290,6 +1423,10 @@ ctof_status ctof_reconstruct(ctof_kernel k, const void *d_dev, void *mu_inout_de
     for (int z = 0; z < k->dims.nz; ++z)
       if (!(std::isfinite(opts->lambda_l1_z[z]) && opts->lambda_l1_z[z] >= 0))
         return set_error(CTOF_EINVAL, "lambda_l1_z[%d] must be finite and >= 0", z);
+  if (opts->mux) {
+    ctof::MuxArgs m;
+    if (ctof_status e = make_mux(k, opts->mux, &m); e != CTOF_OK) return e;
+  }
   const ClassWs o = class_ws(k, 1, opts->max_iter);
   if (ws_bytes < o.solve_total) return set_error(CTOF_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, o.solve_total);
   std::memset(report, 0, sizeof(*report));
@@ -1321,6 +1458,7 @@ ctof_status ctof_reconstruct_batched(int32_t nscan, const ctof_kernel *k, const 
     if (k[i]->prec != prec) return set_error(CTOF_EINVAL, "all handles of a batch need one precision");
     if (!d_dev[i] || !mu_inout_dev[i]) return set_error(CTOF_EINVAL, "device pointer of scan %d is NULL", i);
   }
+  if (opts->mux) return set_error(CTOF_EINVAL, "mux is a single-scan option");
   if (opts->max_iter < 1) return set_error(CTOF_EINVAL, "max_iter must be >= 1");
   if (!std::isfinite(opts->lambda_tikhonov)) return set_error(CTOF_EINVAL, "lambda_tikhonov must be finite");
   if (!(std::isfinite(opts->lipschitz) && opts->lipschitz >= 0)) return set_error(CTOF_EINVAL, "lipschitz must be >= 0");

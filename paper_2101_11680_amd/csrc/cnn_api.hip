@@ -262,6 +262,16 @@ ctof_status ctof_noisy_histogram(int64_t n, const float *m_dev, double peak, uin
   return CTOF_OK;
 }
 
+ctof_status ctof_noisy_counts(int64_t n, const float *m_dev, double scale, double background, uint64_t seed,
+                              uint32_t stream_id, float *out_dev, hipStream_t stream) {
+  if (n < 0 || n > kMaxRows) return set_error(CTOF_EINVAL, "bad n");
+  if (!m_dev || !out_dev) return set_error(CTOF_EINVAL, "m or out is NULL");
+  if (!(scale > 0.0 && scale < 1e15)) return set_error(CTOF_EINVAL, "scale must be in (0, 1e15)");
+  if (!(background >= 0.0 && background < 1e15)) return set_error(CTOF_EINVAL, "background must be in [0, 1e15)");
+  HIP_TRY(ctof::launch_noisy_counts(m_dev, n, scale, background, seed, stream_id, out_dev, stream));
+  return CTOF_OK;
+}
+
 ctof_status ctof_absmax_ws_bytes(int32_t nb, size_t *ws_bytes) {
   if (nb < 1 || nb > 65535) return set_error(CTOF_EINVAL, "nb must be in [1, 65535]");
   if (!ws_bytes) return set_error(CTOF_EINVAL, "ws_bytes is NULL");

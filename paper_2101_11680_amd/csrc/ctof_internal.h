@@ -164,6 +164,28 @@ int batch_block(const Dims &d, int B, int ppv, bool fp64, int bb = 0);
 hipError_t launch_contract(const ctof_kernel_s *k, bool adjoint, const void *in, void *out,
                            hipStream_t st, int nvol = 1, const int *active = nullptr);
 
+// ---- source multiplexing (mux.hip) --------------------------------------------
+// Tiles of tx x ty scan positions (P = tx ty) combined per time bin by S
+// (M x P, row-major, element type of the data): y[t][i][g] = sum_j S[i][j]
+// m[t][pos(g, j)].  MUX_FWD: out = y = S m;  MUX_ADJ: out = m = S^T y (in =
+// y);  MUX_NORMAL: out = S^T (S m - y) (y may be NULL: zero), FP64 partials
+// (1/2 |S m - y|^2, 0) per block when `partials` is set; out may alias in.
+enum { MUX_FWD = 0, MUX_ADJ = 1, MUX_NORMAL = 2 };
+constexpr int kMuxMaxDim = 128;  // largest M and P
+
+struct MuxArgs {
+  int n, nt, tx, ty, M, P, ntx, ntiles;
+  const void *S;
+  const void *in;    // MUX_FWD, MUX_NORMAL: m [nt][n][n];  MUX_ADJ: y [nt][M][ntiles]
+  const void *y;     // MUX_NORMAL: y [nt][M][ntiles] or NULL
+  void *out;         // MUX_FWD: y;  otherwise [nt][n][n]
+  double *partials;  // MUX_NORMAL: 2 doubles per block, or NULL
+};
+
+size_t mux_lds_bytes(int M, int P, bool f64);
+int mux_default_blocks(const MuxArgs &a);
+hipError_t launch_mux(int mode, bool f64, const MuxArgs &a, int blocks, hipStream_t st);
+
 // ---- reductions and small kernels (solver.hip) --------------------------------
 // sums[j] = sum_i partials[i*stride + j] for j < count, over nrows rows (FP64,
 // fixed order).
@@ -268,6 +290,8 @@ hipError_t launch_philox(uint64_t seed, uint32_t stream_id, long long first, lon
                          hipStream_t st);
 hipError_t launch_poisson(const float *lam, long long n, uint64_t seed, uint32_t stream_id, float *counts,
                           hipStream_t st);
+hipError_t launch_noisy_counts(const float *m, long long n, double scale, double background, uint64_t seed,
+                               uint32_t stream_id, float *out, hipStream_t st);
 size_t noisy_histogram_ws_bytes(long long n);
 hipError_t launch_noisy_histogram(const float *m, long long n, double peak, uint64_t seed, uint32_t stream_id,
                                   float *d, void *ws, hipStream_t st);

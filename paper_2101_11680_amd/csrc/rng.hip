@@ -147,6 +147,19 @@ noisy_kernel(const float *__restrict__ m, long long n, const float *__restrict__
   d[i] = (float)(poisson_one(lam, seed, i, stream) / s);
 }
 
+// out = (Poisson(scale max(m, 0) + background) - background) / scale: counts
+// of a measurement with a dark-count background, offset and scaled back.
+__global__ void __launch_bounds__(256)
+noisy_counts_kernel(const float *m, long long n, double scale, double background, uint64_t seed,
+                    uint32_t stream, float *out) {
+#pragma clang fp contract(off)
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double mi = (double)m[i];
+  const double lam = (mi > 0.0 ? mi : 0.0) * scale + background;
+  out[i] = (float)((poisson_one(lam, seed, i, stream) - background) / scale);
+}
+
 inline unsigned blocks_for(long long n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
@@ -162,6 +175,14 @@ hipError_t launch_poisson(const float *lam, long long n, uint64_t seed, uint32_t
                           hipStream_t st) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(poisson_kernel, dim3(blocks_for(n)), dim3(256), 0, st, lam, n, seed, stream_id, counts);
+  return hipGetLastError();
+}
+
+hipError_t launch_noisy_counts(const float *m, long long n, double scale, double background, uint64_t seed,
+                               uint32_t stream_id, float *out, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(noisy_counts_kernel, dim3(blocks_for(n)), dim3(256), 0, st, m, n, scale, background, seed,
+                     stream_id, out);
   return hipGetLastError();
 }
 

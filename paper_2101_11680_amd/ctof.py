@@ -33,7 +33,9 @@ EXPORTS = ("ctof_kernel_bytes", "ctof_kernel_tabulate", "ctof_kernel_tabulate_qu
            "ctof_to_channels_last", "ctof_from_channels_last", "ctof_philox4x32", "ctof_poisson",
            "ctof_noisy_histogram_ws_bytes", "ctof_noisy_histogram", "ctof_warmstart_loss_ws_bytes",
            "ctof_warmstart_loss", "ctof_absmax_ws_bytes", "ctof_absmax", "ctof_depth_resample",
-           "ctof_sumsq_ws_bytes", "ctof_sumsq", "ctof_layer_threshold_ws_bytes", "ctof_layer_threshold")
+           "ctof_sumsq_ws_bytes", "ctof_sumsq", "ctof_layer_threshold_ws_bytes", "ctof_layer_threshold",
+           "ctof_mux_forward", "ctof_mux_adjoint", "ctof_mux_normal_ws_bytes", "ctof_mux_normal",
+           "ctof_noisy_counts")
 
 
 class CtofError(RuntimeError):
@@ -50,6 +52,11 @@ class _Geometry(ctypes.Structure):
                 ("mua_per_mm", ctypes.c_double), ("n_medium", ctypes.c_double)]
 
 
+class _Mux(ctypes.Structure):
+    _fields_ = [("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("rows", ctypes.c_int32),
+                ("s_dev", ctypes.c_void_p)]
+
+
 class _SolverOpts(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("lambda_tikhonov", ctypes.c_double),
                 ("lipschitz", ctypes.c_double), ("power_iters", ctypes.c_int32),
@@ -57,7 +64,8 @@ class _SolverOpts(ctypes.Structure):
                 ("warm_start", ctypes.c_int32), ("history_dev", ctypes.c_void_p),
                 ("timing", ctypes.c_int32), ("lipschitz_scans", ctypes.POINTER(ctypes.c_double)),
                 ("lambda_scans", ctypes.POINTER(ctypes.c_double)),
-                ("lambda_l1_z", ctypes.POINTER(ctypes.c_double))]
+                ("lambda_l1_z", ctypes.POINTER(ctypes.c_double)),
+                ("mux", ctypes.POINTER(_Mux))]
 
 
 class _SolverReport(ctypes.Structure):
@@ -144,6 +152,12 @@ def lib() -> ctypes.CDLL:
         L.ctof_sumsq.argtypes = [i32, i64, vp, vp, vp, sz, vp]
         L.ctof_layer_threshold_ws_bytes.argtypes = [i32, ctypes.POINTER(sz)]
         L.ctof_layer_threshold.argtypes = [i32, i64, vp, f32, vp, sz, vp]
+        mp = ctypes.POINTER(_Mux)
+        L.ctof_mux_forward.argtypes = [vp, mp, vp, vp, vp]
+        L.ctof_mux_adjoint.argtypes = [vp, mp, vp, vp, vp]
+        L.ctof_mux_normal_ws_bytes.argtypes = [vp, mp, ctypes.POINTER(sz)]
+        L.ctof_mux_normal.argtypes = [vp, mp, vp, vp, vp, vp, vp, sz, vp]
+        L.ctof_noisy_counts.argtypes = [i64, vp, ctypes.c_double, ctypes.c_double, u64, u32, vp, vp]
         L.ctof_last_error.argtypes = []
         L.ctof_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
@@ -334,25 +348,117 @@ def _l1_array(l1, nz):
     return (ctypes.c_double * nz)(*vals)
 
 
+class Mux:
+    """Source multiplexing of the measurements (Eq. 12): tiles of tile_x x
+    tile_y scan positions combined per time bin by S (rows x tile_x*tile_y),
+    held on the device in the data's element type."""
+
+    def __init__(self, S, tile_x: int, tile_y: int):
+        if S.dim() != 2 or S.shape[1] != tile_x * tile_y:
+            raise ValueError("S must be rows x (tile_x * tile_y)")
+        self.S = S.contiguous()
+        self.tile_x, self.tile_y = int(tile_x), int(tile_y)
+        self.rows = int(S.shape[0])
+
+    def desc(self, k: Kernel) -> _Mux:
+        if self.S.dtype != _dtype(k.precision):
+            raise TypeError(f"S must be {_dtype(k.precision)} for this kernel")
+        return _Mux(self.tile_x, self.tile_y, self.rows, self.S.data_ptr())
+
+    def ntiles(self, n: int) -> int:
+        return (n // self.tile_x) * (n // self.tile_y)
+
+
+def mux_forward(k: Kernel, mux: Mux, m, out=None, stream=None):
+    """y = S m per tile and bin: m [nt][n][n] -> y [nt][rows][ntiles]."""
+    torch = _torch()
+    i = k.info
+    m = _contig(m, _dtype(k.precision), (i.nt, i.n, i.n))
+    shape = (i.nt, mux.rows, mux.ntiles(i.n))
+    if out is None:
+        out = torch.empty(shape, dtype=m.dtype, device=m.device)
+    out = _contig(out, m.dtype, shape)
+    desc = mux.desc(k)
+    _check(lib().ctof_mux_forward(k.handle, ctypes.byref(desc), m.data_ptr(), out.data_ptr(),
+                                  _stream_ptr(stream)))
+    return out
+
+
+def mux_adjoint(k: Kernel, mux: Mux, y, out=None, stream=None):
+    """m = S^T y: y [nt][rows][ntiles] -> m [nt][n][n]."""
+    torch = _torch()
+    i = k.info
+    y = _contig(y, _dtype(k.precision), (i.nt, mux.rows, mux.ntiles(i.n)))
+    if out is None:
+        out = torch.empty((i.nt, i.n, i.n), dtype=y.dtype, device=y.device)
+    out = _contig(out, y.dtype, (i.nt, i.n, i.n))
+    desc = mux.desc(k)
+    _check(lib().ctof_mux_adjoint(k.handle, ctypes.byref(desc), y.data_ptr(), out.data_ptr(),
+                                  _stream_ptr(stream)))
+    return out
+
+
+def mux_normal(k: Kernel, mux: Mux, m, y=None, out=None, fit: bool = False, stream=None):
+    """r = S^T (S m - y) (y None: S^T S m); returns r, or (r, 1/2 ||S m - y||^2
+    as a device float64 scalar) with fit=True.  out may be m itself."""
+    torch = _torch()
+    i = k.info
+    m = _contig(m, _dtype(k.precision), (i.nt, i.n, i.n))
+    if y is not None:
+        y = _contig(y, m.dtype, (i.nt, mux.rows, mux.ntiles(i.n)))
+    if out is None:
+        out = torch.empty_like(m)
+    out = _contig(out, m.dtype, (i.nt, i.n, i.n))
+    desc = mux.desc(k)
+    f = torch.zeros((), dtype=torch.float64, device=m.device) if fit else None
+    nb = ctypes.c_size_t()
+    _check(lib().ctof_mux_normal_ws_bytes(k.handle, ctypes.byref(desc), ctypes.byref(nb)))
+    ws = k.workspace(nb.value, m.device) if fit else None
+    _check(lib().ctof_mux_normal(k.handle, ctypes.byref(desc), m.data_ptr(),
+                                 y.data_ptr() if y is not None else None, out.data_ptr(),
+                                 f.data_ptr() if f is not None else None,
+                                 ws.data_ptr() if ws is not None else None, ws.numel() if ws is not None else 0,
+                                 _stream_ptr(stream)))
+    return (out, f) if fit else out
+
+
+def noisy_counts(m, scale: float, background: float, seed: int, stream_id: int = 0, out=None, stream=None):
+    """(Poisson(scale max(m, 0) + background) - background) / scale, float32."""
+    torch = _torch()
+    if m.dtype != torch.float32 or not m.is_contiguous():
+        raise TypeError("m must be contiguous float32")
+    if out is None:
+        out = torch.empty_like(m)
+    _check(lib().ctof_noisy_counts(m.numel(), m.data_ptr(), float(scale), float(background), int(seed),
+                                   int(stream_id), out.data_ptr(), _stream_ptr(stream)))
+    return out
+
+
 def reconstruct(k: Kernel, d, mu=None, max_iter: int = 200, lam: float = -1.0,
                 lipschitz: float = 0.0, power_iters: int = 50, rel_tol: float = 0.0,
                 check_every: int = 10, warm_start: bool = False, history: bool = False,
-                timing: bool = False, l1=None, stream=None):
+                timing: bool = False, l1=None, mux: Optional[Mux] = None, stream=None):
     """FISTA reconstruction; returns (mu, Report, history or None).  warm_start:
     0/False zero start, 1/True start from ``mu``, 2 start from ``mu`` with the
-    zero-start fallback.  l1: per-layer L1 weights (nz numbers) or None."""
+    zero-start fallback.  l1: per-layer L1 weights (nz numbers) or None.
+    mux: a Mux when d holds multiplexed measurements y [nt][rows][ntiles]."""
     torch = _torch()
     i = k.info
-    d = _contig(d, _dtype(k.precision), (i.nt, i.n, i.n))
+    if mux is None:
+        d = _contig(d, _dtype(k.precision), (i.nt, i.n, i.n))
+    else:
+        d = _contig(d, _dtype(k.precision), (i.nt, mux.rows, mux.ntiles(i.n)))
     if mu is None:
         mu = torch.empty((i.nz, i.n, i.n), dtype=d.dtype, device=d.device)
         warm_start = False
     mu = _contig(mu, d.dtype, (i.nz, i.n, i.n))
     hist = torch.zeros((max_iter, 2), dtype=torch.float64, device=d.device) if history else None
     l1a = _l1_array(l1, i.nz)
+    mdesc = mux.desc(k) if mux is not None else None
     opts = _SolverOpts(int(max_iter), float(lam), float(lipschitz), int(power_iters),
                        float(rel_tol), int(check_every), int(warm_start),
-                       hist.data_ptr() if hist is not None else None, int(bool(timing)), None, None, l1a)
+                       hist.data_ptr() if hist is not None else None, int(bool(timing)), None, None, l1a,
+                       ctypes.pointer(mdesc) if mdesc is not None else None)
     rep = _SolverReport()
     _, nb = k.workspace_bytes(max_iter)
     ws = k.workspace(nb, d.device)

@@ -1,0 +1,244 @@
+"""GPU parity of source multiplexing (paper Eq. 12) against the FP64 oracle.
+
+The multiplexing products y = S m and m = S^T y must match the oracle for
+tile shapes that are not multiples of the matrix-core tile (ragged M and P),
+for the paper's 8 x 8 tile with the Hadamard on/off patterns and for the
+largest supported sizes; the multiplexed FISTA must follow the oracle's
+iterates on the composed operator S A (1e-10 in FP64, 1e-5 in FP32), also at
+the full 128 x 128 x 64 x 512 workload in the launch configuration of the
+benchmark; the dark-count noise must reproduce the oracle's counts exactly.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import kernel as okernel
+from oracle import mux as omux
+from oracle import operator as oop
+from oracle import rng as orng
+from oracle import solver as osolver
+from synth import mux as smux
+from synth import noise, phantoms, workloads
+from synth.workloads import Geometry, even_layers
+from tests.gpu_common import rel_l2, to_np
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _geom(n, nz=2, nt=48):
+    z, dz = even_layers(2.0, 10.0, nz)
+    return Geometry(nx=n, ny=n, pitch_mm=1.0, z_mm=z, dz_mm=dz, nt=nt, dt_ps=50.0)
+
+
+# (n, tile_x, tile_y, rows): ragged P and M, the paper's tile, the maxima
+CASES = [(12, 3, 2, 5), (16, 4, 4, 32), (16, 8, 8, 128), (32, 8, 8, 64), (32, 16, 8, 128), (24, 4, 6, 17)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("case", CASES)
+def test_mux_products_match_oracle(case, prec):
+    from paper_2101_11680_amd import ctof as c
+    n, tx, ty, M = case
+    g = _geom(n)
+    p = c.FP64 if prec == "fp64" else c.FP32
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    k = c.tabulate(g, p)
+    S = smux.random_matrix(M, tx * ty, seed=n + M)
+    rng = np.random.default_rng(7)
+    m = rng.standard_normal((g.nt, n, n))
+    ntiles = (n // tx) * (n // ty)
+    y = rng.standard_normal((g.nt, M, ntiles))
+    mx = c.Mux(torch.tensor(S, dtype=dt, device="cuda"), tx, ty)
+    y_gpu = to_np(c.mux_forward(k, mx, torch.tensor(m, dtype=dt, device="cuda")))
+    m_gpu = to_np(c.mux_adjoint(k, mx, torch.tensor(y, dtype=dt, device="cuda")))
+    tol = 1e-13 if prec == "fp64" else 1e-6
+    ref_y = omux.forward(S, m, tx, ty)
+    ref_m = omux.adjoint(S, y, tx, ty, n)
+    assert rel_l2(y_gpu, ref_y) <= tol
+    assert rel_l2(m_gpu, ref_m) <= tol
+    # element-wise bound on top of the norm: no single entry may be off
+    etol = 1e-12 if prec == "fp64" else 1e-5
+    assert np.max(np.abs(y_gpu - ref_y)) <= etol * np.abs(ref_y).max()
+    assert np.max(np.abs(m_gpu - ref_m)) <= etol * np.abs(ref_m).max()
+
+
+def test_mux_hadamard_patterns_and_identity():
+    from paper_2101_11680_amd import ctof as c
+    g = _geom(16)
+    k = c.tabulate(g, c.FP64)
+    rng = np.random.default_rng(9)
+    m = rng.standard_normal((g.nt, 16, 16))
+    mt = torch.tensor(m, device="cuda")
+    # on/off Hadamard patterns of the paper's 8 x 8 tile
+    S = smux.onoff(64)
+    y = to_np(c.mux_forward(k, c.Mux(torch.tensor(S, device="cuda"), 8, 8), mt))
+    np.testing.assert_allclose(y, omux.forward(S, m, 8, 8), rtol=0, atol=1e-12 * np.abs(m).max() * 64)
+    # S = I: a pure gather, bit-exact
+    y = to_np(c.mux_forward(k, c.Mux(torch.eye(16, dtype=torch.float64, device="cuda"), 4, 4), mt))
+    np.testing.assert_array_equal(y, omux.forward(np.eye(16), m, 4, 4))
+
+
+def test_mux_adjoint_identity_on_gpu():
+    from paper_2101_11680_amd import ctof as c
+    g = _geom(24)
+    k = c.tabulate(g, c.FP64)
+    S = torch.tensor(smux.random_matrix(40, 24, 3), device="cuda")
+    mx = c.Mux(S, 4, 6)
+    rng = np.random.default_rng(10)
+    m = torch.tensor(rng.standard_normal((g.nt, 24, 24)), device="cuda")
+    y = torch.tensor(rng.standard_normal((g.nt, 40, mx.ntiles(24))), device="cuda")
+    lhs = float((c.mux_forward(k, mx, m) * y).sum())
+    rhs = float((m * c.mux_adjoint(k, mx, y)).sum())
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+def _mux_problem(g, S, tx, ty, seed, peak=1e5):
+    F = oop.FFTOperator(okernel.tabulate(g))
+    Fm = omux.MuxOperator(F, S, tx, ty)
+    mu = phantoms.phantom(g, seed, n_abs=(1, 3), radius=(1.0, 2.0), dmua=(0.01, 0.05), kinds=("sphere", "bar"))
+    y = noise.poisson_histogram(Fm.forward(mu), peak, seed + 1)
+    return F, Fm, y
+
+
+def test_mux_fista_fp64_matches_oracle():
+    from paper_2101_11680_amd import ctof as c
+    g = workloads.geometry_for("tiny")
+    S = smux.onoff(16)
+    F, Fm, y = _mux_problem(g, S, 4, 4, 21)
+    LA = osolver.power_iteration(Fm, 50)
+    L, lam = osolver.step_constants(LA)
+    ref, hist = osolver.fista(Fm, y, L, lam, 60)
+    k = c.tabulate(g, c.FP64)
+    mx = c.Mux(torch.tensor(S, device="cuda"), 4, 4)
+    yt = torch.tensor(y, device="cuda")
+    mu, rep, h = c.reconstruct(k, yt, max_iter=60, lam=lam, lipschitz=L, mux=mx, history=True)
+    assert rel_l2(to_np(mu), ref) <= 1e-10
+    np.testing.assert_allclose(to_np(h)[:, 0], hist[:, 0], rtol=1e-9)
+    np.testing.assert_allclose(to_np(h)[:, 1], hist[:, 1], rtol=1e-8, atol=1e-14)
+    assert rep.datafit == pytest.approx(osolver.datafit(Fm, y, ref), rel=1e-9)
+    assert rep.gmap0 == pytest.approx(osolver.gmap_denominator(Fm, y), rel=1e-10)
+    # the library's own power iteration on S A
+    _, rep2, _ = c.reconstruct(k, yt, max_iter=1, mux=mx)
+    assert rep2.lipschitz_a == pytest.approx(LA, rel=1e-10)
+
+
+def test_mux_fista_fp32_matches_oracle():
+    from paper_2101_11680_amd import ctof as c
+    z, dz = even_layers(1.0, 12.0, 16)
+    g = Geometry(nx=32, ny=32, pitch_mm=0.5, z_mm=z, dz_mm=dz, nt=128, dt_ps=25.0)
+    S = smux.onoff(64)
+    F, Fm, y = _mux_problem(g, S, 8, 8, 31)
+    LA = osolver.power_iteration(Fm, 50)
+    L, lam = osolver.step_constants(LA)
+    ref, hist = osolver.fista(Fm, y, L, lam, 80)
+    k = c.tabulate(g, c.FP32)
+    mx = c.Mux(torch.tensor(S, dtype=torch.float32, device="cuda"), 8, 8)
+    mu, rep, _ = c.reconstruct(k, torch.tensor(y, dtype=torch.float32, device="cuda"), max_iter=80, lam=lam,
+                               lipschitz=L, mux=mx)
+    err = rel_l2(to_np(mu), ref)
+    print("fp32 mux iterate rel L2", err)
+    assert err <= 1e-5
+    assert rep.datafit == pytest.approx(osolver.datafit(Fm, y, ref), rel=1e-4)
+
+
+def test_mux_hadamard_with_l1_and_tolerance_stop():
+    # +-1 Hadamard: the solve runs to the stopping rule with per-layer L1
+    # weights; the result must satisfy the oracle's optimality at that point
+    from paper_2101_11680_amd import ctof as c
+    g = workloads.geometry_for("tiny")
+    H = smux.hadamard(16)
+    F, Fm, y = _mux_problem(g, H, 4, 4, 41)
+    e = osolver.layer_energy(F)
+    l1 = 0.02 * float(np.max(Fm.adjoint(y))) * e / e.max()
+    LA = osolver.power_iteration(Fm, 50)
+    L, lam = osolver.step_constants(LA)
+    k = c.tabulate(g, c.FP64)
+    mx = c.Mux(torch.tensor(H, device="cuda"), 4, 4)
+    mu, rep, _ = c.reconstruct(k, torch.tensor(y, device="cuda"), max_iter=2000, lam=lam, lipschitz=L, mux=mx,
+                               rel_tol=1e-4, check_every=10, l1=l1)
+    ref, hist = osolver.fista(Fm, y, L, lam, rep.iters, l1=l1)
+    assert rel_l2(to_np(mu), ref) <= 1e-9
+    assert rep.gmap_ratio <= 1e-4 and hist[-1, 1] <= 1e-4
+
+
+def test_mux_full_size_fp32_sampled():
+    # the benchmark's configuration: 128 x 128 scan, 64 layers, 512 bins,
+    # 8 x 8 tiles with the on/off Hadamard patterns (128 measurements per
+    # tile); 3 iterations against the oracle on the whole volume
+    from paper_2101_11680_amd import ctof as c
+    g = workloads.geometry_for("precision")
+    S = smux.onoff(64)
+    F = oop.FFTOperator(okernel.tabulate(g))
+    Fm = omux.MuxOperator(F, S, 8, 8)
+    w = workloads.workload("precision")
+    mu = phantoms.workload_phantom(w, g, 3)
+    y = noise.poisson_histogram(Fm.forward(mu), 1e5, 4)
+    k = c.tabulate(g, c.FP32)
+    mx = c.Mux(torch.tensor(S, dtype=torch.float32, device="cuda"), 8, 8)
+    yt = torch.tensor(y, dtype=torch.float32, device="cuda")
+    _, rep0, _ = c.reconstruct(k, yt, max_iter=1, mux=mx)
+    L, lam = rep0.lipschitz, rep0.lam
+    got, rep, _ = c.reconstruct(k, yt, max_iter=3, lam=lam, lipschitz=L, mux=mx)
+    ref, _ = osolver.fista(Fm, y, L, lam, 3)
+    err = rel_l2(to_np(got), ref)
+    print("full-size mux FP32 rel L2 after 3 iterations", err)
+    assert err <= 1e-5
+
+
+def test_noisy_counts_match_oracle():
+    from paper_2101_11680_amd import ctof as c
+    rng = np.random.default_rng(14)
+    m = rng.uniform(-0.5, 40.0, 300000).astype(np.float32)
+    m[:1000] = 0.0
+    for scale, bg, seed in [(3.0, 0.25, 5), (0.5, 12.0, 6), (1.0, 0.0, 7)]:
+        got = c.noisy_counts(torch.tensor(m, device="cuda"), scale, bg, seed, 3).cpu().numpy()
+        np.testing.assert_array_equal(got, orng.noisy_counts(m, scale, bg, seed, 3))
+
+
+def test_mux_argument_checks():
+    from paper_2101_11680_amd import ctof as c
+    g = _geom(12)
+    k = c.tabulate(g, c.FP32)
+    m = torch.zeros((g.nt, 12, 12), dtype=torch.float32, device="cuda")
+    with pytest.raises(c.CtofError):  # tile does not divide the scan
+        c.mux_forward(k, c.Mux(torch.zeros((4, 25), dtype=torch.float32, device="cuda"), 5, 5), m)
+    with pytest.raises(c.CtofError):  # too many rows
+        c.mux_forward(k, c.Mux(torch.zeros((129, 4), dtype=torch.float32, device="cuda"), 2, 2), m)
+    with pytest.raises(TypeError):  # element type of the kernel
+        c.mux_forward(k, c.Mux(torch.zeros((4, 4), dtype=torch.float64, device="cuda"), 2, 2), m)
+    mx = c.Mux(torch.zeros((4, 4), dtype=torch.float32, device="cuda"), 2, 2)
+    y = torch.zeros((g.nt, 4, 36), dtype=torch.float32, device="cuda")
+    import ctypes
+    with pytest.raises(c.CtofError):  # batched solves take no mux
+        opts = c._SolverOpts(5, 0.0, 1.0, 0, 0.0, 1, 0, None, 0, None, None, None,
+                             ctypes.pointer(mx.desc(k)))
+        reps = (c._SolverReport * 1)()
+        handles = (ctypes.c_void_p * 1)(k.handle.value)
+        dptr = (ctypes.c_void_p * 1)(y.data_ptr())
+        mptr = (ctypes.c_void_p * 1)(m.data_ptr())
+        ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+        c._check(c.lib().ctof_reconstruct_batched(1, handles, dptr, mptr, ctypes.byref(opts), reps,
+                                                  ws.data_ptr(), ws.numel(), c._stream_ptr()))
+
+
+@pytest.mark.parametrize("case", [(16, 4, 4, 32), (24, 4, 6, 17), (32, 8, 8, 128)])
+def test_mux_normal_matches_oracle(case):
+    from paper_2101_11680_amd import ctof as c
+    n, tx, ty, M = case
+    g = _geom(n)
+    k = c.tabulate(g, c.FP64)
+    S = smux.random_matrix(M, tx * ty, seed=M)
+    rng = np.random.default_rng(15)
+    m = rng.standard_normal((g.nt, n, n))
+    y = rng.standard_normal((g.nt, M, (n // tx) * (n // ty)))
+    mx = c.Mux(torch.tensor(S, device="cuda"), tx, ty)
+    mt = torch.tensor(m, device="cuda")
+    r, fit = c.mux_normal(k, mx, mt, torch.tensor(y, device="cuda"), fit=True)
+    u = omux.forward(S, m, tx, ty) - y
+    assert rel_l2(to_np(r), omux.adjoint(S, u, tx, ty, n)) <= 1e-13
+    assert float(fit) == pytest.approx(0.5 * float(np.vdot(u, u)), rel=1e-13)
+    # in place, and without data: S^T S m
+    r2 = c.mux_normal(k, mx, mt, None, out=mt)
+    assert r2.data_ptr() == mt.data_ptr()
+    assert rel_l2(to_np(r2), omux.adjoint(S, omux.forward(S, m, tx, ty), tx, ty, n)) <= 1e-13
