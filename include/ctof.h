@@ -175,7 +175,8 @@ ctof_status ctof_adjoint(ctof_kernel k, const void *r_dev, void *g_dev, void *ws
 
 typedef struct {
   int32_t tile_x, tile_y;  /* tile of scan positions; both divide n */
-  int32_t rows;            /* M, measurements per tile and bin (1..128); P = tile_x * tile_y <= 128 */
+  int32_t rows;            /* M, measurements per tile and bin (1..128); P = tile_x * tile_y <= 128;
+                              m [nt][n][n] and y [nt][rows][ntiles] must each be below 2 GiB */
   const void *s_dev;       /* S [rows][P], row-major, device memory, element type of the data */
 } ctof_mux;
 

@@ -316,7 +316,9 @@ ctof_status make_mux(const ctof_kernel_s *k, const ctof_mux *mx, ctof::MuxArgs *
   a->ntx = n / mx->tile_x;
   a->ntiles = a->ntx * (n / mx->tile_y);
   a->S = mx->s_dev;
-  if ((long long)a->nt * a->ntiles >= (1LL << 31)) return set_error(CTOF_EINVAL, "too many mux columns");
+  if ((long long)a->nt * a->M * a->ntiles * (long long)es >= (1LL << 31) ||
+      (long long)a->nt * n * n * (long long)es >= (1LL << 31))
+    return set_error(CTOF_EINVAL, "multiplexed arrays must stay below 2 GiB");
   return CTOF_OK;
 }
 
@@ -461,7 +463,9 @@ ctof_status enqueue_mux_residual(const Engine<T> &E, const void *y, double *part
   m.out = E.mhat();
   m.y = y;
   m.partials = partials;
-  HIP_TRY(ctof::launch_mux(ctof::MUX_NORMAL, sizeof(T) == 8, m, E.L.nblk_t, E.st));
+  m.npart = E.L.nblk_t;
+  const int blocks = std::min(ctof::mux_default_blocks(m, sizeof(T) == 8), E.L.nblk_t);
+  HIP_TRY(ctof::launch_mux(ctof::MUX_NORMAL, sizeof(T) == 8, m, blocks, E.st));
   ctof::RowArgs b = E.row(ctof::ROW_SPATIAL_TO_SPEC, true);
   b.sp_in[0] = E.mhat();
   HIP_TRY(E.run_row(b));
@@ -634,7 +638,7 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
     ctof::MuxArgs a = mux;
     a.in = d;
     a.out = E.mhat();
-    HIP_TRY(ctof::launch_mux(ctof::MUX_ADJ, sizeof(T) == 8, a, ctof::mux_default_blocks(a), st));
+    HIP_TRY(ctof::launch_mux(ctof::MUX_ADJ, sizeof(T) == 8, a, ctof::mux_default_blocks(a, sizeof(T) == 8), st));
     const void *sty[1] = {E.mhat()};
     if (ctof_status s = enqueue_gmap0(E, sty); s != CTOF_OK) return s;
   } else {
@@ -1353,7 +1357,8 @@ ctof_status ctof_mux_forward(ctof_kernel k, const ctof_mux *mux, const void *m_d
     return set_error(CTOF_EINVAL, "m or y is NULL, or m is not 16-byte aligned");
   a.in = m_dev;
   a.out = y_dev;
-  HIP_TRY(ctof::launch_mux(ctof::MUX_FWD, k->prec == CTOF_FP64, a, ctof::mux_default_blocks(a), stream));
+  HIP_TRY(ctof::launch_mux(ctof::MUX_FWD, k->prec == CTOF_FP64, a, ctof::mux_default_blocks(a, k->prec == CTOF_FP64),
+                           stream));
   return CTOF_OK;
 }
 
@@ -1366,7 +1371,8 @@ ctof_status ctof_mux_adjoint(ctof_kernel k, const ctof_mux *mux, const void *y_d
     return set_error(CTOF_EINVAL, "m or y is NULL, or m is not 16-byte aligned");
   a.in = y_dev;
   a.out = m_dev;
-  HIP_TRY(ctof::launch_mux(ctof::MUX_ADJ, k->prec == CTOF_FP64, a, ctof::mux_default_blocks(a), stream));
+  HIP_TRY(ctof::launch_mux(ctof::MUX_ADJ, k->prec == CTOF_FP64, a, ctof::mux_default_blocks(a, k->prec == CTOF_FP64),
+                           stream));
   return CTOF_OK;
 }
 
@@ -1375,7 +1381,7 @@ ctof_status ctof_mux_normal_ws_bytes(ctof_kernel k, const ctof_mux *mux, size_t 
   ctof::MuxArgs a;
   if (ctof_status s = make_mux(k, mux, &a); s != CTOF_OK) return s;
   if (!ws_bytes) return set_error(CTOF_EINVAL, "ws_bytes is NULL");
-  *ws_bytes = ctof::round_up((size_t)ctof::mux_default_blocks(a) * 2 * sizeof(double), 256);
+  *ws_bytes = ctof::round_up((size_t)ctof::mux_default_blocks(a, k->prec == CTOF_FP64) * 2 * sizeof(double), 256);
   return CTOF_OK;
 }
 
@@ -1386,7 +1392,7 @@ ctof_status ctof_mux_normal(ctof_kernel k, const ctof_mux *mux, const void *m_de
   if (ctof_status s = make_mux(k, mux, &a); s != CTOF_OK) return s;
   if (!m_dev || !r_dev || (reinterpret_cast<uintptr_t>(m_dev) & 15) || (reinterpret_cast<uintptr_t>(r_dev) & 15))
     return set_error(CTOF_EINVAL, "m or r is NULL or not 16-byte aligned");
-  const int blocks = ctof::mux_default_blocks(a);
+  const int blocks = ctof::mux_default_blocks(a, k->prec == CTOF_FP64);
   const size_t need = (size_t)blocks * 2 * sizeof(double);
   if (fit_dev) {
     if (!ws_dev || (reinterpret_cast<uintptr_t>(ws_dev) & 15))
@@ -1397,6 +1403,7 @@ ctof_status ctof_mux_normal(ctof_kernel k, const ctof_mux *mux, const void *m_de
   a.y = y_dev;
   a.out = r_dev;
   a.partials = fit_dev ? reinterpret_cast<double *>(ws_dev) : nullptr;
+  a.npart = blocks;
   HIP_TRY(ctof::launch_mux(ctof::MUX_NORMAL, k->prec == CTOF_FP64, a, blocks, stream));
   if (fit_dev) HIP_TRY(ctof::launch_reduce_rows(a.partials, blocks, 2, 1, fit_dev, stream));
   return CTOF_OK;

@@ -179,11 +179,14 @@ struct MuxArgs {
   const void *in;    // MUX_FWD, MUX_NORMAL: m [nt][n][n];  MUX_ADJ: y [nt][M][ntiles]
   const void *y;     // MUX_NORMAL: y [nt][M][ntiles] or NULL
   void *out;         // MUX_FWD: y;  otherwise [nt][n][n]
-  double *partials;  // MUX_NORMAL: 2 doubles per block, or NULL
+  double *partials;  // MUX_NORMAL: npart pairs (block b's sum at pair b, zeros past the grid), or NULL
+  int npart;         // >= the launch's blocks when partials is set
+  int sstr;          // set by launch_mux
 };
 
-size_t mux_lds_bytes(int M, int P, bool f64);
-int mux_default_blocks(const MuxArgs &a);
+// Grid of a multiplexing launch (persistent blocks, at most one per compute
+// unit in FP32).
+int mux_default_blocks(const MuxArgs &a, bool f64);
 hipError_t launch_mux(int mode, bool f64, const MuxArgs &a, int blocks, hipStream_t st);
 
 // ---- reductions and small kernels (solver.hip) --------------------------------
