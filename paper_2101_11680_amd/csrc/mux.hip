@@ -97,7 +97,8 @@ __device__ __forceinline__ void st(T *p, uint32_t off, V v) {
 // KB1: 16-wide k blocks of the first product (>= ceil(P/16)), which are also
 // the second product's row tiles; the first product's row tiles (ceil(M/16))
 // are a runtime loop.
-template <typename T, int MODE, int KB1>
+// VEC: tile width and scan side are multiples of 4 (16-byte column runs).
+template <typename T, int MODE, int KB1, bool VEC>
 __global__ void __launch_bounds__(64 * Mma<T>::kWaves)
 mux_kernel(MuxArgs a) {
   constexpr int kWaves = Mma<T>::kWaves;
@@ -109,9 +110,8 @@ mux_kernel(MuxArgs a) {
   const T *__restrict__ S = static_cast<const T *>(a.S);
   const int lane = threadIdx.x & 63, g = lane >> 4, i16 = lane & 15;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int M = a.M, P = a.P, MT = (M + 15) / 16, PT = (P + 15) / 16;
+  const int M = a.M, P = a.P, MT = (M + 15) / 16;
   const int str = a.sstr;
-  const bool vec = (a.tx & 3) == 0 && (a.n & 3) == 0;
   if constexpr (kLds) {
     for (int e = threadIdx.x; e < 16 * MT * str; e += 64 * kWaves) {
       const int i = e / str, j = e - (e / str) * str;
@@ -156,12 +156,19 @@ mux_kernel(MuxArgs a) {
 #pragma unroll
       for (int b = 0; b < KB1; ++b) {
         const int j0 = 16 * b + 4 * g;
-        if (vec && j0 + 3 < P) {
-          xb[b] = cl.valid ? ld<quad_t>(m, cl.base + pos_off32(j0, a.tx, a.n)) : quad_t(0);
+        if constexpr (VEC) {
+          // P is a multiple of 4: a quad is wholly inside or outside; loads
+          // outside read element 0 and are discarded (no branch)
+          const bool in = cl.valid && j0 < P;
+          const quad_t v = ld<quad_t>(m, in ? cl.base + pos_off32(j0, a.tx, a.n) : 0u);
+          xb[b] = in ? v : quad_t(0);
         } else {
 #pragma unroll
-          for (int e = 0; e < 4; ++e)
-            xb[b][e] = (cl.valid && j0 + e < P) ? ld<T>(m, cl.base + pos_off32(j0 + e, a.tx, a.n)) : T(0);
+          for (int e = 0; e < 4; ++e) {
+            const bool in = cl.valid && j0 + e < P;
+            const T v = ld<T>(m, in ? cl.base + pos_off32(j0 + e, a.tx, a.n) : 0u);
+            xb[b][e] = in ? v : T(0);
+          }
         }
       }
     }
@@ -169,19 +176,27 @@ mux_kernel(MuxArgs a) {
     acc_t rv[MODE == MUX_FWD ? 1 : KB1];
 #pragma unroll
     for (int jt = 0; jt < (MODE == MUX_FWD ? 1 : KB1); ++jt) rv[jt] = acc_t(0);
-    // one row tile of U at a time (not unrolled: the fragments of S for one
-    // tile stay in flight, not all of them)
+    // one row tile of U at a time (the loop is not unrolled: only this
+    // tile's fragments of S are in flight); the first product's chain is
+    // split over even and odd k blocks and the second product's steps cycle
+    // through its accumulators, so consecutive MFMAs are independent
 #pragma unroll 1
     for (int b = 0; b < MT; ++b) {
       acc_t ub = acc_t(0);
       if constexpr (MODE != MUX_ADJ) {
+        acc_t uo = acc_t(0);
+        // k blocks past P hold zero fragments of S and zero X (no branch)
 #pragma unroll
         for (int kb = 0; kb < KB1; ++kb) {
-          if (kb >= PT) continue;
           const quad_t av = a1(b, kb);
 #pragma unroll
-          for (int e = 0; e < 4; ++e) ub = Mma<T>::step(av[e], xb[kb][e], ub);
+          for (int e = 0; e < 4; ++e) {
+            if (kb & 1) uo = Mma<T>::step(av[e], xb[kb][e], uo);
+            else ub = Mma<T>::step(av[e], xb[kb][e], ub);
+          }
+          __asm__ volatile("" ::: "memory");  // bounds the S fragments in flight
         }
+        ub += uo;
       }
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
@@ -191,20 +206,21 @@ mux_kernel(MuxArgs a) {
         if constexpr (MODE == MUX_FWD) {
           if (live) st<T>(out, yo, ub[r]);
         } else if constexpr (MODE == MUX_ADJ) {
-          ub[r] = live ? ld<T>(yv, yo) : T(0);
+          const T v = ld<T>(yv, live ? yo : 0u);
+          ub[r] = live ? v : T(0);
         } else {
-          T v = T(0);
-          if (live) v = yv ? ub[r] - ld<T>(yv, yo) : ub[r];
+          const T d = yv ? ld<T>(yv, live ? yo : 0u) : T(0);
+          const T v = live ? ub[r] - d : T(0);
           ub[r] = v;
           fit += 0.5 * (double)v * (double)v;
         }
       }
       if constexpr (MODE != MUX_FWD) {
 #pragma unroll
-        for (int jt = 0; jt < KB1; ++jt) {
-          if (jt >= PT) continue;
+        for (int e = 0; e < 4; ++e) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) rv[jt] = Mma<T>::step(a2(jt, b, e), ub[e], rv[jt]);
+          for (int jt = 0; jt < KB1; ++jt) rv[jt] = Mma<T>::step(a2(jt, b, e), ub[e], rv[jt]);
+          __asm__ volatile("" ::: "memory");
         }
       }
     }
@@ -212,10 +228,9 @@ mux_kernel(MuxArgs a) {
       if (cl.valid) {
 #pragma unroll
         for (int jt = 0; jt < KB1; ++jt) {
-          if (jt >= PT) continue;
           const int j0 = 16 * jt + 4 * g;
-          if (vec && j0 + 3 < P) {
-            st<quad_t>(out, cl.base + pos_off32(j0, a.tx, a.n), rv[jt]);
+          if constexpr (VEC) {
+            if (j0 < P) st<quad_t>(out, cl.base + pos_off32(j0, a.tx, a.n), rv[jt]);
           } else {
 #pragma unroll
             for (int r = 0; r < 4; ++r)
@@ -260,7 +275,12 @@ inline int lds_stride(int M, int P) {
 
 template <typename T, int MODE, int KB1>
 hipError_t launch_one(const MuxArgs &a, int blocks, size_t lds, hipStream_t st) {
-  hipLaunchKernelGGL((mux_kernel<T, MODE, KB1>), dim3((unsigned)blocks), dim3(64 * Mma<T>::kWaves), lds, st, a);
+  if ((a.tx & 3) == 0 && (a.n & 3) == 0)
+    hipLaunchKernelGGL((mux_kernel<T, MODE, KB1, true>), dim3((unsigned)blocks), dim3(64 * Mma<T>::kWaves), lds, st,
+                       a);
+  else
+    hipLaunchKernelGGL((mux_kernel<T, MODE, KB1, false>), dim3((unsigned)blocks), dim3(64 * Mma<T>::kWaves), lds,
+                       st, a);
   return hipGetLastError();
 }
 
