@@ -15,7 +15,11 @@ and detector collocated.  Readings:
 * time bin k is [t0 + k dt, t0 + (k+1) dt), no instrument response;
 * K_z[dy, dx, k] = dV * integral over bin k of (Phi0 (*)_t R), with
   dV = pitch^2 * dz the voxel volume (detector area 1 mm^2 implicit);
-* the source-to-voxel distance is floored at r_min = (3 dV / 4 pi)^(1/3).
+* the source-to-voxel distance is floored at r_min = (3 dV / 4 pi)^(1/3);
+* fluorescence mode (section "Materials and Methods"): the geometry's
+  reduced scattering is the excitation one, ``mus_em`` the emission one,
+  both share mu_a and n, and ``tau`` is the lifetime (ps, 0 = none); the
+  bins are those of Phi0_ex (*) E_tau (*) R_em (``physics.fluorescence_bins``).
 """
 
 from __future__ import annotations
@@ -65,6 +69,36 @@ def tabulate(g) -> np.ndarray:
     for iz, z in enumerate(g.z_mm):
         vals = dv * physics.kernel_bins(rho, float(z), te, o, rmin)
         out[iz] = vals[inv].reshape(n_y, n_x, g.nt)
+    return out
+
+
+def fluorescence_entries(g, mus_em: float, tau: float, iz, dy, dx) -> np.ndarray:
+    """Fluorescence-mode kernel time curves for (layer, |dy|, |dx|) triples: [n, nt]."""
+    ox = optics_of(g)
+    om = physics.optics(mus_em, g.mua_per_mm, g.n_medium)
+    dv = voxel_volume(g)
+    rmin = r_min(g)
+    te = time_edges(g)
+    iz, dy, dx = np.atleast_1d(iz), np.atleast_1d(dy), np.atleast_1d(dx)
+    out = np.zeros((iz.size, g.nt))
+    for n in range(iz.size):
+        rho = g.pitch_mm * math.sqrt(float(dy[n] * dy[n] + dx[n] * dx[n]))
+        out[n] = dv * physics.fluorescence_bins(rho, float(g.z_mm[iz[n]]), te, ox, om, tau, rmin)
+    return out
+
+
+def tabulate_fluorescence(g, mus_em: float, tau: float) -> np.ndarray:
+    """Kq[z, dy, dx, k] in fluorescence mode (small grids: adaptive quadrature per bin)."""
+    n_y, n_x = g.ny, g.nx
+    out = np.zeros((g.nz, n_y, n_x, g.nt))
+    seen = {}
+    for iz in range(g.nz):
+        for dy in range(n_y):
+            for dx in range(n_x):
+                key = (iz, dy * dy + dx * dx)
+                if key not in seen:
+                    seen[key] = fluorescence_entries(g, mus_em, tau, iz, dy, dx)[0]
+                out[iz, dy, dx] = seen[key]
     return out
 
 
