@@ -126,6 +126,34 @@ ctof_status ctof_kernel_tabulate(const ctof_geometry *geom, ctof_precision prec,
 ctof_status ctof_kernel_tabulate_quadrant(const ctof_geometry *geom, double *quad_dev,
                                           size_t quad_bytes, hipStream_t stream);
 
+/*
+ * Fluorescence mode (section "Materials and Methods": the optical
+ * properties of the excitation and the emission wavelength, and the
+ * fluorescence lifetime).  The kernel becomes the sensitivity of the
+ * emission histogram to the fluorophore yield of a voxel,
+ *     W = Phi0_ex (*)_t E_tau (*)_t R_em,   E_tau(t) = exp(-t/tau)/tau,
+ * with the excitation fluence from the geometry's optics (mus_prime_per_mm
+ * is the excitation value) and the flux back to the detector from the
+ * emission optics; both wavelengths share mua_per_mm and n_medium.  Each
+ * bin is exact (closed form, as in absorption mode).  lifetime_ps = 0 means
+ * instantaneous emission; a lifetime must exceed 1/(mua c) (c = 0.2998/n
+ * mm/ps; 467 ps at mua 0.01/mm, n 1.4), else CTOF_EUNSUPPORTED.  The
+ * forward model, adjoint and solvers are unchanged (m = W mu with mu the
+ * fluorophore yield); the spectrum layout and sizes are those of
+ * ctof_kernel_bytes.  fl NULL: absorption mode, identical to
+ * ctof_kernel_tabulate / ctof_kernel_tabulate_quadrant.
+ */
+typedef struct {
+  double mus_prime_em_per_mm;  /* reduced scattering at the emission wavelength (> 0) */
+  double lifetime_ps;          /* fluorescence lifetime tau (>= 0) */
+} ctof_fluorescence;
+
+ctof_status ctof_kernel_tabulate_ex(const ctof_geometry *geom, const ctof_fluorescence *fl, ctof_precision prec,
+                                    void *khat_dev, size_t khat_bytes, void *tab_ws_dev, size_t tab_ws_bytes,
+                                    hipStream_t stream, ctof_kernel *out);
+ctof_status ctof_kernel_tabulate_quadrant_ex(const ctof_geometry *geom, const ctof_fluorescence *fl, double *quad_dev,
+                                             size_t quad_bytes, hipStream_t stream);
+
 /* Frees the host handle only; the spectrum buffer stays the caller's. */
 void ctof_kernel_free(ctof_kernel k);
 

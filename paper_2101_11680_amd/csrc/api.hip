@@ -141,9 +141,35 @@ ctof_status check_geometry(const ctof_geometry *g, ctof::TabGeom *tg, ctof::Laye
     tg->dv = g->pitch_mm * g->pitch_mm * dz;
     tg->rmin = std::cbrt(3.0 * tg->dv / (4.0 * M_PI));
     tg->o = o;
+    tg->Dm = o.D;
+    tg->zbm = o.zb;
+    tg->tau = 0.0;
   }
   if (zs) {
     for (int k = 0; k < ctof::kMaxLayers; ++k) zs->z[k] = k < g->nz ? g->z_mm[k] : 0.0;
+  }
+  return CTOF_OK;
+}
+
+// Fluorescence mode: emission optics and lifetime on top of a checked geometry.
+ctof_status apply_fluorescence(const ctof_geometry *g, const ctof_fluorescence *fl, ctof::TabGeom *tg) {
+  if (!fl) return CTOF_OK;
+  if (!(std::isfinite(fl->mus_prime_em_per_mm) && fl->mus_prime_em_per_mm > 0))
+    return set_error(CTOF_EINVAL, "mus_prime_em_per_mm must be > 0");
+  if (!(std::isfinite(fl->lifetime_ps) && fl->lifetime_ps >= 0))
+    return set_error(CTOF_EINVAL, "lifetime_ps must be >= 0");
+  const double c = 0.299792458 / g->n_medium;
+  if (fl->lifetime_ps > 0 && !(1.0 / fl->lifetime_ps < g->mua_per_mm * c))
+    return set_error(CTOF_EUNSUPPORTED,
+                     "lifetime %g ps is not above 1/(mu_a c) = %g ps (the closed form then needs the complex "
+                     "error function)", fl->lifetime_ps, 1.0 / (g->mua_per_mm * c));
+  if (tg) {
+    const double n = g->n_medium;
+    const double reff = -1.440 / (n * n) + 0.710 / n + 0.668 + 0.0636 * n;
+    const double A = (1.0 + reff) / (1.0 - reff);
+    tg->Dm = 1.0 / (3.0 * (g->mua_per_mm + fl->mus_prime_em_per_mm));
+    tg->zbm = 2.0 * A * tg->Dm;
+    tg->tau = fl->lifetime_ps;
   }
   return CTOF_OK;
 }
@@ -1241,10 +1267,17 @@ ctof_status ctof_kernel_bytes(const ctof_geometry *geom, ctof_precision prec, si
 ctof_status ctof_kernel_tabulate(const ctof_geometry *geom, ctof_precision prec, void *khat_dev,
                                  size_t khat_bytes, void *tab_ws_dev, size_t tab_ws_bytes,
                                  hipStream_t stream, ctof_kernel *out) {
+  return ctof_kernel_tabulate_ex(geom, nullptr, prec, khat_dev, khat_bytes, tab_ws_dev, tab_ws_bytes, stream, out);
+}
+
+ctof_status ctof_kernel_tabulate_ex(const ctof_geometry *geom, const ctof_fluorescence *fl, ctof_precision prec,
+                                    void *khat_dev, size_t khat_bytes, void *tab_ws_dev, size_t tab_ws_bytes,
+                                    hipStream_t stream, ctof_kernel *out) {
   ctof::TabGeom tg;
   ctof::LayerDepths zs;
   ctof_status s = check_geometry(geom, &tg, &zs);
   if (s != CTOF_OK) return s;
+  if ((s = apply_fluorescence(geom, fl, &tg)) != CTOF_OK) return s;
   if (!valid_prec(prec)) return set_error(CTOF_EINVAL, "unknown precision %d", (int)prec);
   if (!out) return set_error(CTOF_EINVAL, "out handle pointer is NULL");
   if (!khat_dev || !tab_ws_dev) return set_error(CTOF_EINVAL, "device buffer is NULL");
@@ -1287,10 +1320,16 @@ ctof_status ctof_kernel_tabulate(const ctof_geometry *geom, ctof_precision prec,
 
 ctof_status ctof_kernel_tabulate_quadrant(const ctof_geometry *geom, double *quad_dev, size_t quad_bytes,
                                           hipStream_t stream) {
+  return ctof_kernel_tabulate_quadrant_ex(geom, nullptr, quad_dev, quad_bytes, stream);
+}
+
+ctof_status ctof_kernel_tabulate_quadrant_ex(const ctof_geometry *geom, const ctof_fluorescence *fl, double *quad_dev,
+                                             size_t quad_bytes, hipStream_t stream) {
   ctof::TabGeom tg;
   ctof::LayerDepths zs;
   ctof_status s = check_geometry(geom, &tg, &zs);
   if (s != CTOF_OK) return s;
+  if ((s = apply_fluorescence(geom, fl, &tg)) != CTOF_OK) return s;
   if (!quad_dev) return set_error(CTOF_EINVAL, "quad_dev is NULL");
   const size_t n = geom->nx;
   const size_t need = (size_t)geom->nz * geom->nt * n * n * sizeof(double);

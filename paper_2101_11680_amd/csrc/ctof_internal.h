@@ -42,7 +42,9 @@ struct GaussLegendre16 {
 struct TabGeom {
   int n, nz, nt;
   double pitch, dt, t0, dv, rmin;
-  Optics o;
+  Optics o;         // excitation optics (the only optics in absorption mode)
+  double Dm, zbm;   // emission diffusion coefficient and boundary (= o.D, o.zb in absorption mode)
+  double tau;       // fluorescence lifetime in ps (0: none)
 };
 
 // Byte layout of a packed spectrum (offsets into khat_dev).

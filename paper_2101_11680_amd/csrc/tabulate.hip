@@ -17,6 +17,19 @@
 // Gauss-Legendre on the integrand.  Each value is scaled by the voxel
 // volume.
 //
+// Fluorescence mode (section "Materials and Methods": excitation and
+// emission optics, lifetime convolution): the fluence comes from the
+// excitation optics, the flux back to the detector from the emission
+// optics, and the emission is delayed by E_tau(t) = exp(-t/tau)/tau.  With
+// a shared mu_a the two diffusion wavenumbers are proportional, so every
+// image term keeps the form above with D = D_em, a = r1 sqrt(D_em/D_ex) + r2
+// and amp = sigma w / (16 pi^2 D_ex r1 r2^2) (absorption mode is D_em = D_ex).
+// The lifetime convolution h = k (*) E_tau of a term has the exact
+// antiderivative
+//   Q(T) = F_beta(T) - exp(-T/tau) F_beta'(T),   beta' = beta - 1/tau > 0,
+// since h(T) = exp(-T/tau) F_beta'(T) / tau; bins use Q like F above, with
+// Gauss-Legendre on h where the difference cancels.
+//
 // The kernel is even in both lateral offsets, so its spectrum on a P x P
 // torus is real and equals a cosine transform:
 //   Khat(a, b) = sum_{dy, dx} w_dy w_dx K[dy][dx] cos(2 pi a dy / P) cos(2 pi b dx / P)
@@ -51,6 +64,20 @@ __device__ inline double integrand(double alpha, double beta, double g, double s
   return inv * sqrt(inv) * exp(-alpha * inv - beta * s) * (2.0 * alpha * inv + g - 1.0);
 }
 
+// Antiderivative of a term's bin integrand: F (no lifetime) or Q (lifetime).
+struct TermCurve {
+  double alpha, sa, g, beta, sb, betap, sbp, tau;
+  __device__ double prim(double T) const {
+    const double f = antiderivative(alpha, sa, beta, sb, g, T);
+    if (tau == 0.0) return f;
+    return f - exp(-T / tau) * antiderivative(alpha, sa, betap, sbp, g, T);
+  }
+  __device__ double density(double s) const {
+    if (tau == 0.0) return integrand(alpha, beta, g, s);
+    return exp(-s / tau) * antiderivative(alpha, sa, betap, sbp, g, s) / tau;
+  }
+};
+
 // One thread per (layer, dy, dx); loops over the time bins so that F at the
 // upper edge of bin k is reused as the lower edge of bin k+1.
 __global__ void __launch_bounds__(128)
@@ -74,31 +101,37 @@ tab_values_kernel(TabGeom g, LayerDepths zs, GaussLegendre16 gl, double *__restr
   const Optics o = g.o;
   const double zz = zs.z[z];
   const double rho2 = g.pitch * g.pitch * (double)(dy * dy + dx * dx);
-  const double Dc = o.D * o.c;
+  const double Dc = g.Dm * o.c;
   const double beta = o.mua * o.c;
-  const double sqrt_beta = sqrt(beta);
   const double norm = 1.0 / (2.0 * sqrt(kPi * Dc));
+  const double scale = sqrt(g.Dm / o.D);  // exactly 1 in absorption mode
 
   const double r11 = fmax(sqrt(rho2 + (zz - o.z0) * (zz - o.z0)), g.rmin);
   const double zs1 = zz + o.z0 + 2.0 * o.zb;
   const double r12 = sqrt(rho2 + zs1 * zs1);
-  const double zi = zz + 2.0 * o.zb;
+  const double zi = zz + 2.0 * g.zbm;
   const double r21 = sqrt(rho2 + zz * zz);
   const double r22 = sqrt(rho2 + zi * zi);
 
-  double amp[4], alpha[4], sa[4], gg[4], flo[4];
+  double amp[4], flo[4];
+  TermCurve tc[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     const double sigma = (q < 2) ? 1.0 : -1.0;
     const double r1 = (q < 2) ? r11 : r12;
     const double w = (q & 1) ? zi : zz;
     const double r2 = (q & 1) ? r22 : r21;
-    const double a = r1 + r2;
+    const double a = r1 * scale + r2;
     amp[q] = sigma * w / (16.0 * kPi * kPi * o.D * r1 * r2 * r2) * norm;
-    alpha[q] = a * a / (4.0 * Dc);
-    sa[q] = sqrt(alpha[q]);
-    gg[q] = a / r2;
-    flo[q] = antiderivative(alpha[q], sa[q], beta, sqrt_beta, gg[q], g.t0);
+    tc[q].alpha = a * a / (4.0 * Dc);
+    tc[q].sa = sqrt(tc[q].alpha);
+    tc[q].g = a / r2;
+    tc[q].beta = beta;
+    tc[q].sb = sqrt(beta);
+    tc[q].tau = g.tau;
+    tc[q].betap = g.tau > 0.0 ? beta - 1.0 / g.tau : beta;
+    tc[q].sbp = sqrt(tc[q].betap);
+    flo[q] = tc[q].prim(g.t0);
   }
   double *dst = out + (size_t)dy * s_dy + (size_t)dx * s_dx + (size_t)z * s_z;
   for (int k = 0; k < g.nt; ++k) {
@@ -109,7 +142,7 @@ tab_values_kernel(TabGeom g, LayerDepths zs, GaussLegendre16 gl, double *__restr
     double sum = 0.0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const double fhi = antiderivative(alpha[q], sa[q], beta, sqrt_beta, gg[q], thi);
+      const double fhi = tc[q].prim(thi);
       const double df = fhi - flo[q];
       double bin;
       if (flo[q] <= 100.0 * fabs(df)) {
@@ -117,7 +150,7 @@ tab_values_kernel(TabGeom g, LayerDepths zs, GaussLegendre16 gl, double *__restr
       } else {
         double acc = 0.0;
 #pragma unroll 4
-        for (int e = 0; e < 16; ++e) acc += gl.w[e] * integrand(alpha[q], beta, gg[q], mid + half * gl.x[e]);
+        for (int e = 0; e < 16; ++e) acc += gl.w[e] * tc[q].density(mid + half * gl.x[e]);
         bin = acc * half;
       }
       sum += amp[q] * bin;

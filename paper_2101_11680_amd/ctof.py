@@ -23,6 +23,7 @@ STATUS = {0: "CTOF_OK", -1: "CTOF_EINVAL", -2: "CTOF_ENOMEM", -3: "CTOF_EHIP",
           -4: "CTOF_ENONFINITE", -5: "CTOF_EUNSUPPORTED"}
 
 EXPORTS = ("ctof_kernel_bytes", "ctof_kernel_tabulate", "ctof_kernel_tabulate_quadrant",
+           "ctof_kernel_tabulate_ex", "ctof_kernel_tabulate_quadrant_ex",
            "ctof_kernel_free", "ctof_kernel_info", "ctof_workspace_bytes", "ctof_forward",
            "ctof_adjoint", "ctof_reconstruct", "ctof_workspace_bytes_batched",
            "ctof_reconstruct_batched", "ctof_kernel_set_tuning", "ctof_kernel_get_tuning",
@@ -50,6 +51,10 @@ class _Geometry(ctypes.Structure):
                 ("dz_mm", ctypes.c_double), ("nt", ctypes.c_int32), ("dt_ps", ctypes.c_double),
                 ("t0_ps", ctypes.c_double), ("mus_prime_per_mm", ctypes.c_double),
                 ("mua_per_mm", ctypes.c_double), ("n_medium", ctypes.c_double)]
+
+
+class _Fluorescence(ctypes.Structure):
+    _fields_ = [("mus_prime_em_per_mm", ctypes.c_double), ("lifetime_ps", ctypes.c_double)]
 
 
 class _Mux(ctypes.Structure):
@@ -105,6 +110,9 @@ def lib() -> ctypes.CDLL:
         L.ctof_kernel_bytes.argtypes = [gp, ctypes.c_int, ctypes.POINTER(sz), ctypes.POINTER(sz)]
         L.ctof_kernel_tabulate.argtypes = [gp, ctypes.c_int, vp, sz, vp, sz, vp, ctypes.POINTER(vp)]
         L.ctof_kernel_tabulate_quadrant.argtypes = [gp, vp, sz, vp]
+        fp = ctypes.POINTER(_Fluorescence)
+        L.ctof_kernel_tabulate_ex.argtypes = [gp, fp, ctypes.c_int, vp, sz, vp, sz, vp, ctypes.POINTER(vp)]
+        L.ctof_kernel_tabulate_quadrant_ex.argtypes = [gp, fp, vp, sz, vp]
         L.ctof_kernel_free.argtypes = [vp]
         L.ctof_kernel_free.restype = None
         L.ctof_kernel_info.argtypes = [vp] + [ctypes.POINTER(i32)] * 6
@@ -257,28 +265,38 @@ class Kernel:
         return ws
 
 
-def tabulate(geometry, precision: int = FP32, device="cuda", stream=None) -> Kernel:
+def _fluorescence(fl):
+    """(mus_prime_em_per_mm, lifetime_ps) -> descriptor pointer, or None (absorption mode)."""
+    if fl is None:
+        return None
+    mus_em, tau = fl
+    return ctypes.pointer(_Fluorescence(float(mus_em), float(tau)))
+
+
+def tabulate(geometry, precision: int = FP32, device="cuda", stream=None, fluorescence=None) -> Kernel:
+    """Tabulate the kernel; fluorescence = (emission mus' per mm, lifetime ps)
+    for the fluorescence-mode kernel (the geometry's mus' is the excitation one)."""
     torch = _torch()
     gs, _z = _geometry(geometry)
     kb, wb = kernel_bytes(geometry, precision)
     khat = torch.empty(kb, dtype=torch.uint8, device=device)
     ws = torch.empty(max(wb, 256), dtype=torch.uint8, device=device)
     out = ctypes.c_void_p()
-    _check(lib().ctof_kernel_tabulate(ctypes.byref(gs), int(precision), khat.data_ptr(), kb,
-                                      ws.data_ptr(), ws.numel(), _stream_ptr(stream),
-                                      ctypes.byref(out)))
+    _check(lib().ctof_kernel_tabulate_ex(ctypes.byref(gs), _fluorescence(fluorescence), int(precision),
+                                         khat.data_ptr(), kb, ws.data_ptr(), ws.numel(), _stream_ptr(stream),
+                                         ctypes.byref(out)))
     del ws
     return Kernel(out.value, khat, precision)
 
 
-def tabulate_quadrant(geometry, device="cuda", stream=None):
+def tabulate_quadrant(geometry, device="cuda", stream=None, fluorescence=None):
     """FP64 kernel values [nz][nt][n][n] for offsets dy, dx >= 0 (test hook)."""
     torch = _torch()
     gs, _z = _geometry(geometry)
     n = int(geometry.nx)
     out = torch.empty((len(geometry.z_mm), int(geometry.nt), n, n), dtype=torch.float64, device=device)
-    _check(lib().ctof_kernel_tabulate_quadrant(ctypes.byref(gs), out.data_ptr(),
-                                               out.numel() * 8, _stream_ptr(stream)))
+    _check(lib().ctof_kernel_tabulate_quadrant_ex(ctypes.byref(gs), _fluorescence(fluorescence), out.data_ptr(),
+                                                  out.numel() * 8, _stream_ptr(stream)))
     return out
 
 
