@@ -277,7 +277,7 @@ row_pass_kernel(int n, RowArgs a) {
   constexpr int NT = 512;
   __shared__ T wr[H * ld], wi[H * ld];
   __shared__ T twc[P], tws[P];
-  __shared__ double red[2 * NT];
+  __shared__ double red[2 * (NT / 64)];
 
   const int op = a.op;
   const int i = blockIdx.x;
@@ -417,25 +417,29 @@ row_pass_kernel(int n, RowArgs a) {
       }
     }
   }
+  constexpr int NW = NT / 64;
   if (a.partials) {
-    red[tid] = acc0;
-    red[NT + tid] = acc1;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      acc0 += __shfl_xor(acc0, off, 64);
+      acc1 += __shfl_xor(acc1, off, 64);
+    }
+    if ((tid & 63) == 0) {
+      red[tid >> 6] = acc0;
+      red[NW + (tid >> 6)] = acc1;
+    }
   }
   __syncthreads();
-  if (a.partials) {
-    for (int s = NT / 2; s > 0; s >>= 1) {
-      if (tid < s) {
-        red[tid] += red[tid + s];
-        red[NT + tid] += red[NT + tid + s];
-      }
-      __syncthreads();
+  if (a.partials && tid == 0) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int w = 0; w < NW; ++w) {
+      s0 += red[w];
+      s1 += red[NW + w];
     }
-    if (tid == 0) {
-      const size_t blk = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
-      double *part = a.partials + (a.iter_ctr ? (size_t)it * a.part_stride : 0);
-      part[2 * blk] = red[0];
-      part[2 * blk + 1] = red[NT];
-    }
+    const size_t blk = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+    double *part = a.partials + (a.iter_ctr ? (size_t)it * a.part_stride : 0);
+    part[2 * blk] = s0;
+    part[2 * blk + 1] = s1;
   }
   if (!spec_out) return;
 

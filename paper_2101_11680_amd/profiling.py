@@ -3,6 +3,11 @@
   python -m paper_2101_11680_amd.profiling trace  DIR OUT.txt TITLE COMMAND
       kernel-trace CSV (rocprofv3 --kernel-trace --stats --output-format csv
       -d DIR -o run) -> per-kernel table (calls, average/min duration, share)
+  python -m paper_2101_11680_amd.profiling iteration TRACE_DIR FETCH_DIR WRITE_DIR COPY_FETCH_DIR \\
+          COPY_WRITE_DIR COPY_MIB MOPS_DIR BUSY_DIR OUT.txt COMMAND...
+      the eight stages of an FP32 FISTA iteration picked out of the dispatch
+      sequences: duration, calibrated HBM bytes and GB/s per stage, and for the
+      contractions SQ_INSTS_VALU_MFMA_MOPS_F32 / SQ_VALU_MFMA_BUSY_CYCLES
   python -m paper_2101_11680_amd.profiling traffic KERNEL COPY_MIB OUT.json \\
           FETCH_DIR WRITE_DIR COPY_FETCH_DIR COPY_WRITE_DIR COMMAND...
       FETCH_SIZE / WRITE_SIZE counter CSVs (one counter per rocprofv3 --pmc
@@ -106,6 +111,90 @@ def traffic(kernel: str, copy_mib: int, out: str, fetch_dir: str, write_dir: str
     return res
 
 
+FISTA_STAGES = ("contract_fwd", "col_t_inverse", "row_t_residual", "col_t_forward", "contract_adj",
+                "col_z_inverse", "row_z_prox", "col_z_forward")
+_STAGE_KERNELS = ("contract_fwd_kernel<float", "col_pass_kernel<float", "row_pass_kernel<float",
+                  "col_pass_kernel<float", "contract_adj_kernel<float", "col_pass_kernel<float",
+                  "row_pass_kernel<float", "col_pass_kernel<float")
+
+
+def _dispatches(d: str, counter: bool):
+    """[(name, value or duration_us)] in dispatch order."""
+    if counter:
+        rows = list(csv.DictReader(open(os.path.join(d, "run_counter_collection.csv"))))
+        rows.sort(key=lambda r: int(r["Dispatch_Id"]))
+        return [(_short(r["Kernel_Name"]), float(r["Counter_Value"])) for r in rows]
+    rows = list(csv.DictReader(open(os.path.join(d, "run_kernel_trace.csv"))))
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    return [(_short(r["Kernel_Name"]), (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1000.0) for r in rows]
+
+
+def _fista_groups(seq):
+    """Values of the eight stages of every FP32 FISTA iteration in a dispatch
+    sequence (power-iteration groups end in a reduction, not a column pass)."""
+    out = []
+    for i in range(len(seq) - 7):
+        if all(seq[i + j][0].startswith(_STAGE_KERNELS[j]) for j in range(8)):
+            out.append([seq[i + j][1] for j in range(8)])
+    return out
+
+
+def iteration_table(trace_dir, fetch_dir, write_dir, cfetch_dir, cwrite_dir, copy_mib, mops_dir, busy_dir,
+                    out, command, clock_hz=2.4e9, simds=1024, hbm_peak=8.0e12, mfma_peak=157.3e12):
+    """Per stage of a FISTA iteration: duration (trace), HBM bytes (calibrated
+    FETCH_SIZE + WRITE_SIZE), achieved GB/s and share of the HBM peak; for
+    the contractions also executed MFMA flops (MOPS x 512), TFLOP/s and the
+    MFMA-busy share of the SIMD cycles."""
+    copy_bytes = copy_mib * (1 << 20)
+    f_fac = copy_bytes / (_copy_kib(cfetch_dir) * 1024.0)
+    w_fac = copy_bytes / (_copy_kib(cwrite_dir) * 1024.0)
+    med = lambda groups, j: statistics.median(g[j] for g in groups)
+    gt = _fista_groups(_dispatches(trace_dir, False))
+    gf = _fista_groups(_dispatches(fetch_dir, True))
+    gw = _fista_groups(_dispatches(write_dir, True))
+    gm = _fista_groups(_dispatches(mops_dir, True))
+    gb = _fista_groups(_dispatches(busy_dir, True))
+    if not (gt and gf and gw and gm and gb):
+        raise RuntimeError("no FISTA iteration found in one of the runs")
+    rows = []
+    for j, name in enumerate(FISTA_STAGES):
+        us = med(gt, j)
+        nbytes = med(gf, j) * 1024.0 * f_fac + med(gw, j) * 1024.0 * w_fac
+        row = dict(stage=name, us=us, hbm_bytes=nbytes, gbs=nbytes / (us * 1e-6) / 1e9,
+                   hbm_frac=nbytes / (us * 1e-6) / hbm_peak)
+        if name.startswith("contract"):
+            flops = med(gm, j) * 512.0
+            row.update(mfma_flops=flops, tflops=flops / (us * 1e-6) / 1e12, mfma_frac=flops / (us * 1e-6) / mfma_peak,
+                       mfma_busy=med(gb, j) / (simds * us * 1e-6 * clock_hz))
+        rows.append(row)
+    tot_us = sum(r["us"] for r in rows)
+    tot_b = sum(r["hbm_bytes"] for r in rows)
+    lines = ["# FP32 FISTA iteration, 128x128 scan, 64 layers, 512 bins: per-stage HBM and MFMA counters", "",
+             "command (run from /tmp with TMPDIR=/tmp; R = repository root):", f"  {command}", "",
+             f"iterations found: trace {len(gt)}, FETCH {len(gf)}, WRITE {len(gw)}, MOPS {len(gm)}, BUSY {len(gb)}; "
+             f"medians over them", f"HBM bytes = FETCH_SIZE x {f_fac:.4f} + WRITE_SIZE x {w_fac:.4f} (factors from a "
+             f"{copy_mib} MiB copy); peaks: HBM 8 TB/s, FP32 MFMA 157.3 TFLOP/s; {simds} SIMDs at "
+             f"{clock_hz / 1e9:.1f} GHz", "",
+             f"{'stage':16s} {'us':>8s} {'HBM MB':>9s} {'GB/s':>8s} {'%HBM':>6s} {'MFMA TF/s':>10s} {'%MFMA':>6s} "
+             f"{'MFMA busy':>9s}"]
+    for r in rows:
+        extra = (f"{r['tflops']:10.1f} {100 * r['mfma_frac']:5.1f}% {100 * r['mfma_busy']:8.1f}%"
+                 if "tflops" in r else f"{'':10s} {'':6s} {'':9s}")
+        lines.append(f"{r['stage']:16s} {r['us']:8.1f} {r['hbm_bytes'] / 1e6:9.1f} {r['gbs']:8.0f} "
+                     f"{100 * r['hbm_frac']:5.1f}% {extra}")
+    lines.append(f"{'iteration':16s} {tot_us:8.1f} {tot_b / 1e6:9.1f} {tot_b / (tot_us * 1e-6) / 1e9:8.0f} "
+                 f"{100 * tot_b / (tot_us * 1e-6) / hbm_peak:5.1f}%")
+    lines.append("")
+    lines.append("MFMA flops are executed flops (MOPS x 512); the contraction fills 8 of the 16 B columns of each "
+                 "16x16x4 tile with one volume, so half of them are useful work.")
+    text = "\n".join(lines) + "\n"
+    with open(out, "w") as f:
+        f.write(text)
+    with open(os.path.splitext(out)[0] + ".json", "w") as f:
+        json.dump(dict(command=command, stages=rows), f, indent=1)
+    return text
+
+
 def main(argv) -> int:
     if len(argv) >= 5 and argv[0] == "trace":
         print(summarize_trace(argv[1], argv[2], argv[3], " ".join(argv[4:])))
@@ -114,6 +203,10 @@ def main(argv) -> int:
         src = os.path.join(HERE, "csrc", "contract.hip")
         print(json.dumps(traffic(argv[1], int(argv[2]), argv[3], argv[4], argv[5], argv[6], argv[7],
                                  " ".join(argv[8:]), src), indent=1))
+        return 0
+    if len(argv) >= 11 and argv[0] == "iteration":
+        print(iteration_table(argv[1], argv[2], argv[3], argv[4], argv[5], int(argv[6]), argv[7], argv[8], argv[9],
+                              " ".join(argv[10:])))
         return 0
     print(__doc__)
     return 2
