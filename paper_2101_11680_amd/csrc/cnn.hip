@@ -185,6 +185,111 @@ conv_fwd_kernel(ConvArgs a) {
   }
 }
 
+constexpr int kK3Chunk = 32;  // input channels per LDS stage of the 3x3x3 kernels
+
+// ---- forward (and input-gradient) 3x3x3 layers, staged in LDS -----------------------
+// A block owns one spatial tile of ry whole rows of one plane, ry * w = 64 *
+// NPT positions (NPT 16-position tiles per wave), and every output channel.
+// Per 32-channel input chunk it copies the input halo (3 planes x (ry + 2)
+// rows x (w + 2) columns x 32 channels, zero outside the grid and past ci)
+// into LDS with 16-byte moves; each wave then runs the 27 taps with one
+// 16-byte LDS read per position tile (8 channels of one position per lane:
+// the B operand) and one 16-byte weight read per output-channel tile (the A
+// operand, shared by the block's waves through L1), CT x NPT MFMAs per tap
+// and chunk.
+template <int CT, int NPT>
+__global__ void __launch_bounds__(256)
+conv_fwd_k3_kernel(ConvArgs a, int ry) {
+  extern __shared__ __align__(16) unsigned char lds_raw[];
+  __bf16 *halo = reinterpret_cast<__bf16 *>(lds_raw);
+  const int W2 = a.w + 2, R2 = ry + 2;
+  const int wave = threadIdx.x >> 6, l = threadIdx.x & 63, col = l & 15, g = l >> 4;
+  const int tiles_per_plane = a.h / ry;
+  const long long plane = blockIdx.x / tiles_per_plane;
+  const int y0 = (int)(blockIdx.x % tiles_per_plane) * ry;
+  const int b = (int)(plane / a.d), z = (int)(plane % a.d);
+  // this lane's position in each of its tiles
+  int pr[NPT], px[NPT];
+#pragma unroll
+  for (int p = 0; p < NPT; ++p) {
+    const int q = 16 * (wave * NPT + p) + col;
+    pr[p] = q / a.w;
+    px[p] = q - pr[p] * a.w;
+  }
+  v4f acc[NPT][CT];
+#pragma unroll
+  for (int p = 0; p < NPT; ++p)
+#pragma unroll
+    for (int t = 0; t < CT; ++t) acc[p][t] = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int cc0 = 0; cc0 < a.ci; cc0 += kK3Chunk) {
+    __syncthreads();  // the previous chunk's halo is no longer read
+    const int nsite = 3 * R2 * W2;
+    for (int v = threadIdx.x; v < nsite * 4; v += 256) {
+      const int site = v >> 2, q = v & 3;
+      const int pl = site / (R2 * W2), rem = site - pl * (R2 * W2);
+      const int hr = rem / W2, hc = rem - hr * W2;
+      const int zz = z + pl - 1, yy = y0 + hr - 1, xx = hc - 1;
+      const int c = cc0 + 8 * q;
+      v8bf val = zero8();
+      if (zz >= 0 && zz < a.d && yy >= 0 && yy < a.h && xx >= 0 && xx < a.w && c < a.ci) {
+        const long long row = (((long long)b * a.d + zz) * a.h + yy) * a.w + xx;
+        val = load8(a.x + (size_t)row * a.x_ld + a.x_c0 + c);
+        if (c + 8 > a.ci) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (c + u >= a.ci) val[u] = (__bf16)0.0f;
+        }
+      }
+      *reinterpret_cast<v8bf *>(halo + (size_t)site * kK3Chunk + 8 * q) = val;
+    }
+    __syncthreads();
+    // weight columns of this lane group: tap * cip + cc0 + 8 g (none past cip)
+    const int kc = cc0 + 8 * g;
+    const bool kin = kc < a.cip;
+    for (int tap = 0; tap < 27; ++tap) {
+      const int dz = tap / 9, dyy = (tap / 3) % 3, dxx = tap % 3;
+      v8bf bv[NPT];
+#pragma unroll
+      for (int p = 0; p < NPT; ++p)
+        bv[p] = *reinterpret_cast<const v8bf *>(
+            halo + ((size_t)(dz * R2 + pr[p] + dyy) * W2 + px[p] + dxx) * kK3Chunk + 8 * g);
+#pragma unroll
+      for (int t = 0; t < CT; ++t) {
+        const v8bf aw = kin ? load8(a.wt + (size_t)(16 * t + col) * a.kpad + tap * a.cip + kc) : zero8();
+#pragma unroll
+        for (int p = 0; p < NPT; ++p)
+          acc[p][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aw, bv[p], acc[p][t], 0, 0, 0);
+      }
+    }
+  }
+  const long long row0 = ((long long)plane * a.h + y0) * a.w;
+#pragma unroll
+  for (int p = 0; p < NPT; ++p) {
+    const long long dst = row0 + (long long)pr[p] * a.w + px[p];
+#pragma unroll
+    for (int t = 0; t < CT; ++t) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int co = 16 * t + 4 * g + r;
+        if (co >= a.co) continue;
+        float v = acc[p][t][r] + (a.bias ? a.bias[co] : 0.0f);
+        const size_t o = (size_t)dst * a.y_ld + a.y_c0 + co;
+        if (a.y_fp32) {
+          float *yo = reinterpret_cast<float *>(a.y);
+          if (a.accumulate) v += yo[o];
+          if (a.relu) v = v > 0.0f ? v : 0.0f;
+          yo[o] = v;
+        } else {
+          __bf16 *yo = reinterpret_cast<__bf16 *>(a.y);
+          if (a.accumulate) v += (float)yo[o];
+          if (a.relu) v = v > 0.0f ? v : 0.0f;
+          yo[o] = (__bf16)v;
+        }
+      }
+    }
+  }
+}
+
 // ---- weight gradient --------------------------------------------------------------
 // Tiles: (16 output channels) x (tap, 16 input channels).  A wave owns
 // kWgTiles tiles of one output-channel tile over one range of GEMM positions
@@ -281,7 +386,6 @@ conv_wgrad_kernel(ConvArgs a, WgradArgs w) {
 // its (tap, 16 input channels) tiles with one MFMA per 32 positions, both
 // operands read from LDS (8 positions of one channel per lane).  Partial
 // sums use the layout of conv_wgrad_kernel and the same reduction.
-constexpr int kK3Chunk = 32;
 constexpr int kK3WaveTiles = 14;  // ceil(27 taps * 2 channel tiles / 4 waves)
 
 __global__ void __launch_bounds__(256)
@@ -822,9 +926,50 @@ ConvArgs conv_transposed(const ConvArgs &f) {
   return t;
 }
 
+// Rows per tile of the LDS-staged 3x3x3 forward kernel (ry * w = 64 * npt),
+// or false when the layer does not fit it (then the generic kernel runs):
+// at least 32 input channels, rows of 8 to 64 columns, 16-byte rows.
+static bool k3f_plan(const ConvArgs &a, int &ry, int &npt, size_t &lds) {
+  const int ct = a.co_pad / 16;
+  // below 32 input channels a 32-channel stage would be half empty (the
+  // generic kernel packs the taps' channels densely into its k steps)
+  if (a.kind != CNN_K3 || a.ci < kK3Chunk || a.w % 8 != 0 || (a.x_ld % 8) || (a.x_c0 % 8) || ct < 1 || ct > 4 ||
+      (reinterpret_cast<uintptr_t>(a.x) & 15))
+    return false;
+  for (npt = 2; npt >= 1; --npt) {
+    const int pos = 64 * npt;
+    if (pos % a.w) continue;
+    ry = pos / a.w;
+    if (ry > a.h || a.h % ry) continue;
+    lds = (size_t)3 * (ry + 2) * (a.w + 2) * kK3Chunk * sizeof(__bf16);
+    if (lds <= 64 * 1024) return true;
+  }
+  return false;
+}
+
+template <int CT>
+static void launch_k3f(const ConvArgs &a, int ry, int npt, size_t lds, unsigned blocks, hipStream_t st) {
+  if (npt == 2)
+    hipLaunchKernelGGL((conv_fwd_k3_kernel<CT, 2>), dim3(blocks), dim3(256), lds, st, a, ry);
+  else
+    hipLaunchKernelGGL((conv_fwd_k3_kernel<CT, 1>), dim3(blocks), dim3(256), lds, st, a, ry);
+}
+
 hipError_t launch_conv_fwd(const ConvArgs &a, hipStream_t st) {
   const long long npos = conv_gemm_positions(a);
   if (npos == 0) return hipSuccess;
+  int ry, npt;
+  size_t lds;
+  if (k3f_plan(a, ry, npt, lds)) {
+    const unsigned blocks = (unsigned)((long long)a.n * a.d * (a.h / ry));
+    switch (a.co_pad / 16) {
+      case 1: launch_k3f<1>(a, ry, npt, lds, blocks, st); break;
+      case 2: launch_k3f<2>(a, ry, npt, lds, blocks, st); break;
+      case 3: launch_k3f<3>(a, ry, npt, lds, blocks, st); break;
+      default: launch_k3f<4>(a, ry, npt, lds, blocks, st); break;
+    }
+    return hipGetLastError();
+  }
   const dim3 grid(blocks_for(npos, 64), a.kind == CNN_UP ? 8 : 1);
   switch (a.co_pad / 16) {
     case 1: hipLaunchKernelGGL(conv_fwd_kernel<1>, grid, dim3(256), 0, st, a); break;

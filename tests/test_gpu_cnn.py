@@ -103,6 +103,15 @@ CASES = [
 ]
 
 
+# 3x3x3 layers with at least 32 input channels and rows of 8 to 64 columns
+# take the LDS-staged forward kernel (the input gradient too, with the roles
+# of ci and co swapped): one or two position tiles per wave, one or two
+# 32-channel chunks, one to four output-channel tiles; the last cases fall
+# back to the generic kernel
+STAGED_FWD = [("k3", (2, 4, 8, 16), 40, 48), ("k3", (1, 3, 4, 32), 64, 64), ("k3", (2, 2, 8, 8), 32, 16),
+              ("k3", (1, 2, 2, 64), 32, 32), ("k3", (1, 4, 8, 32), 2, 16), ("k3", (1, 2, 2, 64), 24, 32)]
+
+
 def _setup(kind, grid, ci, co, seed):
     r = np.random.default_rng(seed)
     x = _bf(r.standard_normal(grid + (ci,)))
@@ -115,7 +124,7 @@ def _conv(nn, kind, grid, ci, co):
     return nn.Conv(nn.KIND[kind], *grid, ci, co)
 
 
-@pytest.mark.parametrize("kind,grid,ci,co", CASES)
+@pytest.mark.parametrize("kind,grid,ci,co", CASES + STAGED_FWD)
 def test_conv_forward_fp32_output(kind, grid, ci, co):
     nn = _nn()
     x, W, b = _setup(kind, grid, ci, co, 10)
@@ -134,7 +143,7 @@ def test_conv_forward_fp32_output(kind, grid, ci, co):
     assert np.all(_host(y)[:, :2] == 0) and np.all(_host(y)[:, 2 + co:] == 0)
 
 
-@pytest.mark.parametrize("kind,grid,ci,co", CASES[:3] + CASES[4:8])
+@pytest.mark.parametrize("kind,grid,ci,co", CASES[:3] + CASES[4:8] + STAGED_FWD)
 def test_conv_forward_bf16_relu_accumulate(kind, grid, ci, co):
     nn = _nn()
     x, W, b = _setup(kind, grid, ci, co, 11)
@@ -152,7 +161,7 @@ def test_conv_forward_bf16_relu_accumulate(kind, grid, ci, co):
     assert np.all(np.abs(got - ref) <= tol)
 
 
-@pytest.mark.parametrize("kind,grid,ci,co", [c for c in CASES if c[2] <= 128])
+@pytest.mark.parametrize("kind,grid,ci,co", [c for c in CASES if c[2] <= 128] + STAGED_FWD)
 def test_conv_input_gradient(kind, grid, ci, co):
     nn = _nn()
     x, W, b = _setup(kind, grid, ci, co, 13)
