@@ -211,8 +211,8 @@ typedef struct {
 /*
  * y = S m:  m_dev [nt][n][n]  ->  y_dev [nt][rows][ntiles], ntiles =
  * (n / tile_x) * (n / tile_y), element type of k's precision.  The buffers
- * must not overlap.  Asynchronous.  Both multiply on the matrix cores
- * (16x16x4 MFMA in the data's precision) with S held in registers.
+ * must not overlap.  Asynchronous.  The products run on the matrix cores
+ * (16x16x4 MFMA in the data's precision; S staged in LDS in FP32).
  */
 ctof_status ctof_mux_forward(ctof_kernel k, const ctof_mux *mux, const void *m_dev, void *y_dev,
                              hipStream_t stream);

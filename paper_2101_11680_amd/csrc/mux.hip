@@ -146,9 +146,6 @@ mux_kernel(MuxArgs a) {
   const uint32_t nti = (uint32_t)a.ntiles;
   double fit = 0.0;
   for (int q = blockIdx.x * kWaves + wave; q < ntile16; q += gridDim.x * kWaves) {
-    // S in LDS is loop-invariant: keep its fragment reads inside the loop
-    // (hoisted, they would hold every fragment in registers at once)
-    __asm__ volatile("" ::: "memory");
     const Column cl = column(a, 16LL * q + i16, ncol);
     // X columns as the first product's B operands
     quad_t xb[MODE == MUX_ADJ ? 1 : KB1];
@@ -194,7 +191,6 @@ mux_kernel(MuxArgs a) {
             if (kb & 1) uo = Mma<T>::step(av[e], xb[kb][e], uo);
             else ub = Mma<T>::step(av[e], xb[kb][e], ub);
           }
-          __asm__ volatile("" ::: "memory");  // bounds the S fragments in flight
         }
         ub += uo;
       }
@@ -220,7 +216,6 @@ mux_kernel(MuxArgs a) {
         for (int e = 0; e < 4; ++e) {
 #pragma unroll
           for (int jt = 0; jt < KB1; ++jt) rv[jt] = Mma<T>::step(a2(jt, b, e), ub[e], rv[jt]);
-          __asm__ volatile("" ::: "memory");
         }
       }
     }
