@@ -242,3 +242,25 @@ def test_mux_normal_matches_oracle(case):
     r2 = c.mux_normal(k, mx, mt, None, out=mt)
     assert r2.data_ptr() == mt.data_ptr()
     assert rel_l2(to_np(r2), omux.adjoint(S, omux.forward(S, m, tx, ty), tx, ty, n)) <= 1e-13
+
+
+def test_mux_with_reduced_precision_contraction():
+    # the multiplexing step runs on the FP32 histogram whatever the
+    # contraction's precision: the BF16 hi+lo and hi-only solves must stay
+    # within the reduced-precision bar of the FP64 oracle's iterates
+    from paper_2101_11680_amd import ctof as c
+    z, dz = even_layers(1.0, 12.0, 8)
+    g = Geometry(nx=32, ny=32, pitch_mm=0.5, z_mm=z, dz_mm=dz, nt=64, dt_ps=40.0)
+    S = smux.onoff(16)
+    F, Fm, y = _mux_problem(g, S, 4, 4, 51)
+    LA = osolver.power_iteration(Fm, 50)
+    L, lam = osolver.step_constants(LA)
+    ref, _ = osolver.fista(Fm, y, L, lam, 40)
+    yt = torch.tensor(y, dtype=torch.float32, device="cuda")
+    mx = c.Mux(torch.tensor(S, dtype=torch.float32, device="cuda"), 4, 4)
+    for prec, tol in ((c.FP32, 1e-5), (c.BF16X3, 1e-4), (c.BF16, 2e-3)):
+        k = c.tabulate(g, prec)
+        got, rep, _ = c.reconstruct(k, yt, max_iter=40, lam=lam, lipschitz=L, mux=mx)
+        err = rel_l2(to_np(got), ref)
+        print("mux precision", prec, "iterate rel L2", err)
+        assert err <= tol
