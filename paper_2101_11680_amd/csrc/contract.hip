@@ -12,10 +12,12 @@
 // (P-b, a).  Their real and imaginary parts are 8 real columns, so each
 // matrix is one small dense GEMM:
 //   forward  [Nt x Nz] x [Nz x 8],  adjoint  [Nz x Nt] x [Nt x 8].
-// One workgroup streams one matrix for one pair of volumes: the matrix is the
-// A operand, the pair's 2 x 8 real columns fill the 16 B columns of an MFMA
-// 16x16x4 (FP32, FP64) or 16x16x32 (BF16) tile.  A single volume leaves the
-// second half empty.  With several pairs (volumes of one shape class share
+// One workgroup streams one matrix for one pair of volumes (the forward
+// splits the matrix into up to four runs of t rows, one workgroup each, which
+// shortens the drain at the end of the launch): the matrix is the A operand,
+// the pair's 2 x 8 real columns fill the 16 B columns of an MFMA 16x16x4
+// (FP32, FP64) or 16x16x32 (BF16) tile.  A single volume leaves the second
+// half empty.  With several pairs (volumes of one shape class share
 // the kernel spectrum) the workgroups of one matrix are mapped to the same
 // XCD, so the matrix comes from HBM once and from that XCD's L2 afterwards;
 // with one pair it is streamed with non-temporal loads (read once per pass:
@@ -150,17 +152,20 @@ struct CArgs {
   void *vout;
   int h, p, nzp, ntp, nmat;
   int nvol, npairs;
+  int parts;          // forward: blocks per (matrix, pair), each a contiguous run of t tiles; adjoint: 1
   const int *active;  // per volume, 0 = frozen (no loads, no stores); NULL = all live
 };
 
-// Block -> (matrix, pair): block L runs on XCD L % 8; all pairs of matrix s
-// get blocks with the same residue so they share an L2.
-__device__ inline bool map_block(const CArgs &a, int &s, int &pair) {
+// Block -> (matrix, pair, part): block L runs on XCD L % 8; all pairs and
+// parts of matrix s get blocks with the same residue so they share an L2.
+__device__ inline bool map_block(const CArgs &a, int &s, int &pair, int &part) {
   const int L = blockIdx.x;
   const int xcd = L & 7;
   const int r = L >> 3;
-  const int grp = r / a.npairs;
-  pair = r - grp * a.npairs;
+  const int q = r / a.parts;
+  part = r - q * a.parts;
+  const int grp = q / a.npairs;
+  pair = q - grp * a.npairs;
   s = grp * 8 + xcd;
   return s < a.nmat;
 }
@@ -196,8 +201,8 @@ template <typename T, int KZ, bool NT>
 __global__ void __launch_bounds__(256)
 contract_fwd_kernel(CArgs a) {
   using M = Mfma<T>;
-  int s, pair;
-  if (!map_block(a, s, pair) || pair_idle(a, pair)) return;
+  int s, pair, part;
+  if (!map_block(a, s, pair, part) || pair_idle(a, pair)) return;
   const int w = threadIdx.x >> 6;
   const int l = threadIdx.x & 63;
   const int c = l & 15, g = l >> 4;
@@ -233,14 +238,16 @@ contract_fwd_kernel(CArgs a) {
       for (int kk = 0; kk < KZ; ++kk) acc = M::step(av[kk], bv[kk], acc);
       if (k.on) store4<T>(ocol + t0 + 4 * g, acc);
     };
+    // this block's run of t tiles
+    const int tend = (part + 1) * ntt / a.parts;
     T a0[KZ], a1[KZ];
-    int tt = w;
-    if (tt < ntt) load_frag<T, KZ, NT>(frag(tt), l, a0);
-    for (; tt < ntt; tt += 8) {
-      if (tt + 4 < ntt) load_frag<T, KZ, NT>(frag(tt + 4), l, a1);
+    int tt = part * ntt / a.parts + w;
+    if (tt < tend) load_frag<T, KZ, NT>(frag(tt), l, a0);
+    for (; tt < tend; tt += 8) {
+      if (tt + 4 < tend) load_frag<T, KZ, NT>(frag(tt + 4), l, a1);
       tile(tt, a0);
-      if (tt + 4 >= ntt) break;
-      if (tt + 8 < ntt) load_frag<T, KZ, NT>(frag(tt + 8), l, a0);
+      if (tt + 4 >= tend) break;
+      if (tt + 8 < tend) load_frag<T, KZ, NT>(frag(tt + 8), l, a0);
       tile(tt + 4, a1);
     }
   }
@@ -253,8 +260,8 @@ contract_adj_kernel(CArgs a) {
   using M = Mfma<T>;
   extern __shared__ unsigned char smem_raw[];
   T *red = reinterpret_cast<T *>(smem_raw);  // [4 waves][ZT][64 lanes][4]
-  int s, pair;
-  if (!map_block(a, s, pair) || pair_idle(a, pair)) return;
+  int s, pair, part;
+  if (!map_block(a, s, pair, part) || pair_idle(a, pair)) return;
   const int w = threadIdx.x >> 6;
   const int l = threadIdx.x & 63;
   const int c = l & 15, g = l >> 4;
@@ -339,8 +346,8 @@ __device__ __forceinline__ v8bf load_bf8(const __bf16 *p) {
 template <int KIND, int KZ, bool NT>  // KZ: z per lane group per chunk (multiple of 8)
 __global__ void __launch_bounds__(256)
 contract_fwd_bf16_kernel(CArgs a) {
-  int s, pair;
-  if (!map_block(a, s, pair) || pair_idle(a, pair)) return;
+  int s, pair, part;
+  if (!map_block(a, s, pair, part) || pair_idle(a, pair)) return;
   const int w = threadIdx.x >> 6;
   const int l = threadIdx.x & 63;
   const int c = l & 15, g = l >> 4;
@@ -367,7 +374,8 @@ contract_fwd_bf16_kernel(CArgs a) {
         bl[e][u] = lo;
       }
     }
-    for (int tt = w; tt < ntt; tt += 4) {
+    const int tend = (part + 1) * ntt / a.parts;
+    for (int tt = part * ntt / a.parts + w; tt < tend; tt += 4) {
       const int t0 = tt * 16;
       const size_t blk = (((size_t)s * ntt + tt) * nchunk + ch) * (64 * KZ);
       v4f acc = {0, 0, 0, 0};
@@ -396,8 +404,8 @@ __global__ void __launch_bounds__(256)
 contract_adj_bf16_kernel(CArgs a) {
   extern __shared__ unsigned char smem_raw[];
   float *red = reinterpret_cast<float *>(smem_raw);
-  int s, pair;
-  if (!map_block(a, s, pair) || pair_idle(a, pair)) return;
+  int s, pair, part;
+  if (!map_block(a, s, pair, part) || pair_idle(a, pair)) return;
   const int w = threadIdx.x >> 6;
   const int l = threadIdx.x & 63;
   const int c = l & 15, g = l >> 4;
@@ -460,7 +468,7 @@ contract_adj_bf16_kernel(CArgs a) {
 template <typename T, bool NT>
 hipError_t launch_plain(const ctof_kernel_s *k, bool adjoint, const CArgs &a, hipStream_t st) {
   const Dims &d = k->dims;
-  const dim3 grid((unsigned)(8 * ((d.nmat + 7) / 8) * a.npairs)), block(256);
+  const dim3 grid((unsigned)(8 * ((d.nmat + 7) / 8) * a.npairs * a.parts)), block(256);
   if (!adjoint) {
     const int kz = (d.nzp >= 64 ? 64 : d.nzp) / 4;
     switch (kz) {
@@ -490,7 +498,7 @@ hipError_t launch_plain(const ctof_kernel_s *k, bool adjoint, const CArgs &a, hi
 template <int KIND, bool NT>
 hipError_t launch_bf16(const ctof_kernel_s *k, bool adjoint, const CArgs &a, hipStream_t st) {
   const Dims &d = k->dims;
-  const dim3 grid((unsigned)(8 * ((d.nmat + 7) / 8) * a.npairs)), block(256);
+  const dim3 grid((unsigned)(8 * ((d.nmat + 7) / 8) * a.npairs * a.parts)), block(256);
   if (!adjoint) {
     const int kz = (d.nzp >= 64 ? 64 : d.nzp) / 4;
     switch (kz) {
@@ -543,6 +551,9 @@ hipError_t launch_contract(const ctof_kernel_s *k, bool adjoint, const void *in,
   a.nmat = d.nmat;
   a.nvol = nvol;
   a.npairs = (nvol + 1) / 2;
+  // forward: up to four blocks per matrix, at least 8 t tiles (2 per wave)
+  // each; shorter blocks shorten the tail of the launch
+  a.parts = adjoint ? 1 : std::max(1, std::min(4, d.ntp / 128));
   a.active = active;
   if (a.npairs == 1) return dispatch<true>(k, adjoint, a, st);
   return dispatch<false>(k, adjoint, a, st);
