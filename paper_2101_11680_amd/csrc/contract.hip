@@ -12,9 +12,9 @@
 // (P-b, a).  Their real and imaginary parts are 8 real columns, so each
 // matrix is one small dense GEMM:
 //   forward  [Nt x Nz] x [Nz x 8],  adjoint  [Nz x Nt] x [Nt x 8].
-// One workgroup streams one matrix for one pair of volumes (the forward
-// splits the matrix into up to four runs of t rows, one workgroup each, which
-// shortens the drain at the end of the launch): the matrix is the A operand,
+// One workgroup streams one matrix for one pair of volumes (the FP32/FP64
+// forward splits the matrix into up to four runs of t rows, one workgroup
+// each, which shortens the drain at the end of the launch): the matrix is the A operand,
 // the pair's 2 x 8 real columns fill the 16 B columns of an MFMA 16x16x4
 // (FP32, FP64) or 16x16x32 (BF16) tile.  A single volume leaves the second
 // half empty.  With several pairs (volumes of one shape class share
@@ -496,9 +496,13 @@ hipError_t launch_plain(const ctof_kernel_s *k, bool adjoint, const CArgs &a, hi
 }
 
 template <int KIND, bool NT>
-hipError_t launch_bf16(const ctof_kernel_s *k, bool adjoint, const CArgs &a, hipStream_t st) {
+hipError_t launch_bf16(const ctof_kernel_s *k, bool adjoint, const CArgs &a0, hipStream_t st) {
   const Dims &d = k->dims;
-  const dim3 grid((unsigned)(8 * ((d.nmat + 7) / 8) * a.npairs * a.parts)), block(256);
+  // one block per matrix: split into t runs, the BF16 forward measured slower
+  // (each block splits its data columns into hi and lo parts again)
+  CArgs a = a0;
+  a.parts = 1;
+  const dim3 grid((unsigned)(8 * ((d.nmat + 7) / 8) * a.npairs)), block(256);
   if (!adjoint) {
     const int kz = (d.nzp >= 64 ? 64 : d.nzp) / 4;
     switch (kz) {
