@@ -133,3 +133,23 @@ def test_tuner_choices_keep_results_and_cache(tmp_path):
         c.set_tuning(k, *bb)
         mu, _, _ = c.reconstruct(k, d, max_iter=30, lam=rep0.lam, lipschitz=rep0.lipschitz)
         assert rel_l2(to_np(mu), to_np(base)) <= 1e-6
+
+
+@pytest.mark.parametrize("nt", [512, 384, 320])
+def test_split_forward_blocks_single_and_batched(nt):
+    # the FP32 forward gives each matrix to up to four blocks of t tiles
+    # (nt 512: four blocks of 8 tiles; 384: three of 8; 320: two of 10, so a
+    # wavefront's share is uneven); batched classes map pairs and blocks of
+    # one matrix together: both must reproduce the oracle and each other
+    from paper_2101_11680_amd import ctof as c
+    g = geom(16, 4, nt, z2=8.0, dt=10.0)
+    F = oop.FFTOperator(okernel.tabulate(g))
+    k = c.tabulate(g, c.FP32)
+    mu = phantoms.phantom(g, 7, n_abs=(1, 2), radius=(1.0, 1.5), dmua=(0.02, 0.04), kinds=("sphere",))
+    assert rel_l2(to_np(c.forward(k, torch.tensor(mu, dtype=torch.float32, device="cuda"))), F.forward(mu)) <= 1e-5
+    ds = [torch.tensor(_data(g, 20 + s, F)[0], dtype=torch.float32, device="cuda") for s in range(3)]
+    _, rep0, _ = c.reconstruct(k, ds[0], max_iter=1)
+    singles = [c.reconstruct(k, d, max_iter=30, lam=rep0.lam, lipschitz=rep0.lipschitz)[0] for d in ds]
+    mus, _ = c.reconstruct_batched([k] * 3, ds, max_iter=30, lam=rep0.lam, lipschitz=rep0.lipschitz)
+    for mu1, mub in zip(singles, mus):
+        assert rel_l2(to_np(mub), to_np(mu1)) <= 1e-6
