@@ -12,7 +12,10 @@ Prints one JSON line.  The timed region is one ctof_reconstruct call of
 exactly --steps iterations with L and lambda fixed beforehand (the power
 iteration and the kernel tabulation are set-up and are reported apart).
 Per-kernel durations come from HIP events that the library records on its
-stream inside the same timed call.
+stream inside the same timed call.  Beside the 8 TB/s peak, the iteration's
+byte rates are also given as fractions of a measured device copy (read +
+write), for the floor (kernel spectrum twice, data once, volume state) and
+for the bytes this design moves (its FFT passes' round trips included).
 """
 
 from __future__ import annotations
@@ -54,6 +57,25 @@ def measured_traffic(n_launch_units: float):
     if t.get("source_sha256") != source_digest(src):
         return None
     return t.get("bytes_per_launch")
+
+
+def copy_bandwidth(torch, dev, mib=1024, reps=5):
+    """Device-to-device copy rate (bytes read + written per second, GB/s) of
+    a plain copy of `mib` MiB, timed with events on torch's stream."""
+    src = torch.ones((mib << 20) // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * (mib << 20) / (ms * 1e-3) / 1e9
 
 
 def cpu_baseline(g, n_iter: int = 2):
@@ -612,6 +634,16 @@ def main() -> int:
     # whole-iteration floor: kernel spectrum twice, data once, volume state
     vol = g.nz * g.ny * g.nx * vs
     floor_bytes = 2 * khat_bytes + g.nt * g.ny * g.nx * vs + 5 * vol
+    # bytes this design moves per iteration: the two contractions plus, on
+    # each side, column pass (P rows in, n rows out), row pass (spectrum rows
+    # in and out, data or volume state) and column pass back
+    def spec(planes, rows):
+        return planes * rows * (i.p // 2 + 1) * 2 * vs
+    side_t = 2 * (spec(g.nt, i.p) + spec(g.nt, g.ny)) + 2 * spec(g.nt, g.ny) + g.nt * g.ny * g.nx * vs
+    side_z = 2 * (spec(g.nz, i.p) + spec(g.nz, g.ny)) + 2 * spec(g.nz, g.ny) + 4 * vol
+    design_bytes = fwd_bytes + adj_bytes + side_t + side_z
+    copy_gbs = copy_bandwidth(torch, dev)
+    log(f"device copy {copy_gbs:.0f} GB/s (read + write)")
     traffic = measured_traffic(1.0)
 
     out = {
@@ -654,7 +686,13 @@ def main() -> int:
         },
         "iteration_floor": {"bytes": floor_bytes,
                             "achieved_GBs": floor_bytes * value / 1e9,
-                            "frac": floor_bytes * value / 1e9 / HBM_PEAK_GBS},
+                            "frac": floor_bytes * value / 1e9 / HBM_PEAK_GBS,
+                            "frac_of_copy": floor_bytes * value / 1e9 / copy_gbs},
+        "iteration_design": {"bytes": design_bytes,
+                             "achieved_GBs": design_bytes * value / 1e9,
+                             "frac": design_bytes * value / 1e9 / HBM_PEAK_GBS,
+                             "frac_of_copy": design_bytes * value / 1e9 / copy_gbs},
+        "copy_GBs": copy_gbs,
         "setup_s": {"tabulate": t_tab, "power_iteration_and_one_iter": t_setup},
         "report": {"datafit0": rep.datafit0, "datafit": rep.datafit,
                    "gmap_ratio": rep.gmap_ratio},
