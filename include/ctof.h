@@ -71,7 +71,7 @@ typedef enum {
  * collocated source/detector pair scanned over an n x n grid; the voxel
  * grid is the scan grid, aligned, one voxel layer per entry of z_mm).
  *   nx, ny            scan points per side; this build requires nx == ny,
- *                     1 <= n <= 128 (CTOF_EUNSUPPORTED otherwise)
+ *                     1 <= n <= 256 (CTOF_EUNSUPPORTED otherwise)
  *   pitch_mm          lateral pitch (> 0), equal in x and y
  *   nz, z_mm          number of layers (>= 1) and a HOST array of layer
  *                     centre depths, strictly increasing, > 0

@@ -15,28 +15,34 @@
 //
 // Spectra are laid out [ky][row][re/im][plane] with ky in [0, P/2].  All
 // transforms are unnormalised; the 1/P^2 of the inverse is folded into the
-// packed kernel spectrum.  A length-R DFT (R <= 16) runs in registers
+// packed kernel spectrum.  A length-R DFT (R <= 32) runs in registers
 // (radix-2, fully unrolled); a length-P pass is two such stages through
-// LDS with a twiddle table built per block in double precision.  Real DFTs
-// of length P use one complex DFT of length P/2 plus the standard
-// even/odd split.
+// LDS with a twiddle table built per block in double precision (P = 512:
+// 16 x 32, with the column held in LDS whole).  Real DFTs of length P use
+// one complex DFT of length P/2 plus the standard even/odd split.
 #include "ctof_internal.h"
 
 namespace ctof {
 
 namespace {
 
-__host__ __device__ constexpr double cos16(int k) {
-  // cos(2 pi k / 16)
-  return k == 0 ? 1.0 : k == 1 ? 0.92387953251128675613 : k == 2 ? 0.70710678118654752440
-       : k == 3 ? 0.38268343236508977173 : k == 4 ? 0.0 : k == 5 ? -0.38268343236508977173
-       : k == 6 ? -0.70710678118654752440 : k == 7 ? -0.92387953251128675613 : -1.0;
+// cos(2 pi k / 32) and sin(2 pi k / 32) for k in [0, 16], written out (no
+// recursion: the unrolled DFTs fold every call into a literal)
+__host__ __device__ constexpr double cos32(int k) {
+  return k == 0 ? 1.0 : k == 1 ? 0.98078528040323044913 : k == 2 ? 0.92387953251128675613
+       : k == 3 ? 0.83146961230254523708 : k == 4 ? 0.70710678118654752440 : k == 5 ? 0.55557023301960222474
+       : k == 6 ? 0.38268343236508977173 : k == 7 ? 0.19509032201612826785 : k == 8 ? 0.0
+       : k == 9 ? -0.19509032201612826785 : k == 10 ? -0.38268343236508977173 : k == 11 ? -0.55557023301960222474
+       : k == 12 ? -0.70710678118654752440 : k == 13 ? -0.83146961230254523708 : k == 14 ? -0.92387953251128675613
+       : k == 15 ? -0.98078528040323044913 : -1.0;
 }
-__host__ __device__ constexpr double sin16(int k) {
-  // sin(2 pi k / 16), k in [0, 8)
-  return k == 0 ? 0.0 : k == 1 ? 0.38268343236508977173 : k == 2 ? 0.70710678118654752440
-       : k == 3 ? 0.92387953251128675613 : k == 4 ? 1.0 : k == 5 ? 0.92387953251128675613
-       : k == 6 ? 0.70710678118654752440 : 0.38268343236508977173;
+__host__ __device__ constexpr double sin32(int k) {
+  return k == 0 ? 0.0 : k == 1 ? 0.19509032201612826785 : k == 2 ? 0.38268343236508977173
+       : k == 3 ? 0.55557023301960222474 : k == 4 ? 0.70710678118654752440 : k == 5 ? 0.83146961230254523708
+       : k == 6 ? 0.92387953251128675613 : k == 7 ? 0.98078528040323044913 : k == 8 ? 1.0
+       : k == 9 ? 0.98078528040323044913 : k == 10 ? 0.92387953251128675613 : k == 11 ? 0.83146961230254523708
+       : k == 12 ? 0.70710678118654752440 : k == 13 ? 0.55557023301960222474 : k == 14 ? 0.38268343236508977173
+       : k == 15 ? 0.19509032201612826785 : 0.0;
 }
 
 template <int R>
@@ -47,10 +53,46 @@ __host__ __device__ constexpr int bitrev(int i) {
   return r;
 }
 
-// In-register DFT of length R (power of two <= 16):
+// In-register DFT of length R (power of two <= 32):
 //   X[k] = sum_n x[n] exp(DIR * 2 pi i n k / R)   (DIR = -1 forward, +1 inverse)
 template <typename T, int R, int DIR>
 __device__ __forceinline__ void dft_reg(T (&xr)[R], T (&xi)[R]) {
+  static_assert(R >= 1 && R <= 32 && (R & (R - 1)) == 0, "power of two up to 32");
+  if constexpr (R == 32) {
+    // two length-16 DFTs of the even and odd samples, then one radix-2 step
+    // (keeps the live values near 2R instead of the fully unrolled tree's)
+    T er[16], ei[16], orr[16], oi[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      er[i] = xr[2 * i];
+      ei[i] = xi[2 * i];
+      orr[i] = xr[2 * i + 1];
+      oi[i] = xi[2 * i + 1];
+    }
+    dft_reg<T, 16, DIR>(er, ei);
+    dft_reg<T, 16, DIR>(orr, oi);
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      T vr, vi;
+      if (k == 0) {
+        vr = orr[k];
+        vi = oi[k];
+      } else if (k == 8) {  // multiply by DIR * i
+        vr = (T)(-DIR) * oi[k];
+        vi = (T)DIR * orr[k];
+      } else {
+        const T wr = (T)cos32(k);
+        const T wi = (T)(DIR * sin32(k));
+        vr = orr[k] * wr - oi[k] * wi;
+        vi = orr[k] * wi + oi[k] * wr;
+      }
+      xr[k] = er[k] + vr;
+      xi[k] = ei[k] + vi;
+      xr[k + 16] = er[k] - vr;
+      xi[k + 16] = ei[k] - vi;
+    }
+    return;
+  }
   T tr[R], ti[R];
 #pragma unroll
   for (int i = 0; i < R; ++i) {
@@ -63,18 +105,18 @@ __device__ __forceinline__ void dft_reg(T (&xr)[R], T (&xi)[R]) {
     for (int s = 0; s < R; s += len) {
 #pragma unroll
       for (int j = 0; j < len / 2; ++j) {
-        const int idx = j * (16 / len);
+        const int idx = j * (32 / len);  // W_len^j = exp(DIR 2 pi i idx / 32)
         const int a = s + j, b = s + j + len / 2;
         T vr, vi;
         if (idx == 0) {
           vr = tr[b];
           vi = ti[b];
-        } else if (idx == 4) {  // multiply by DIR * i
+        } else if (idx == 8) {  // multiply by DIR * i
           vr = (T)(-DIR) * ti[b];
           vi = (T)DIR * tr[b];
         } else {
-          const T wr = (T)cos16(idx);
-          const T wi = (T)(DIR * sin16(idx));
+          const T wr = (T)cos32(idx);
+          const T wi = (T)(DIR * sin32(idx));
           vr = tr[b] * wr - ti[b] * wi;
           vi = tr[b] * wi + ti[b] * wr;
         }
@@ -151,7 +193,8 @@ __device__ __forceinline__ void dft_stage2_unit(const T *br, const T *bi, int ld
 
 template <int P>
 struct Fac {
-  static constexpr int R1 = P == 256 ? 16 : P == 128 ? 16 : P == 64 ? 8 : P == 32 ? 8 : P == 16 ? 4 : P == 8 ? 4 : 2;
+  static constexpr int R1 = P == 512 ? 16 : P == 256 ? 16 : P == 128 ? 16 : P == 64 ? 8 : P == 32 ? 8 : P == 16 ? 4
+                           : P == 8 ? 4 : 2;
   static constexpr int R2 = P / R1;
 };
 
@@ -241,12 +284,12 @@ col_pass_kernel(int n, int B, const T *__restrict__ in, T *__restrict__ out, int
 
 // Two-stage length-H DFT in place on (wr, wi)[m * ld + b], natural order in
 // and out; every thread holds at most one stage-2 unit.
-template <typename T, int H, int BB, int DIR>
+template <typename T, int H, int BB, int DIR, int TSTEP = 2>
 __device__ __forceinline__ void dft_lds_inplace(T *wr, T *wi, const T *twc, const T *tws) {
   constexpr int R1 = Fac<H>::R1, R2 = Fac<H>::R2;
   constexpr int ld = BB + 1;
-  // stage-1 twiddles W_H^m live at index 2m of the length-2H table
-  dft_stage1<T, R1, R2, BB, DIR>(wr, wi, ld, twc, tws, 2, 2 * H - 1);
+  // stage-1 twiddles W_H^m live at index TSTEP m of the length-(TSTEP H) table
+  dft_stage1<T, R1, R2, BB, DIR>(wr, wi, ld, twc, tws, TSTEP, TSTEP * H - 1);
   __syncthreads();
   const int tid = threadIdx.x;
   const bool act = tid < R1 * BB;
@@ -263,6 +306,48 @@ __device__ __forceinline__ void dft_lds_inplace(T *wr, T *wi, const T *twc, cons
     }
   }
   __syncthreads();
+}
+
+// Column pass for FFT sizes above 256: a radix-32 stage does not fit in the
+// registers beside its global addresses, so the block's columns (P x BB
+// complex) go through LDS whole and the DFT runs in place there.
+template <typename T, int P, int BB, bool INV>
+__global__ void __launch_bounds__(512)
+col_pass_lds_kernel(int n, int B, const T *__restrict__ in, T *__restrict__ out, int ppv,
+                    const int *__restrict__ active) {
+  constexpr int DIR = INV ? 1 : -1;
+  constexpr int ld = BB + 1;
+  constexpr int NT = 512;
+  __shared__ T wr[P * ld], wi[P * ld];
+  __shared__ T twc[P], tws[P];
+  const int ky = blockIdx.x;
+  const int b0 = blockIdx.y * BB;
+  if (active != nullptr && active[b0 / ppv] == 0) return;  // frozen volume
+  const int rows_in = INV ? P : n;
+  const int rows_out = INV ? n : P;
+  const int tid = threadIdx.x;
+  build_twiddles<T, P>(twc, tws);
+  const T *src = in + (size_t)ky * rows_in * 2 * B + b0;
+#pragma unroll 4
+  for (int u = tid; u < P * BB; u += NT) {
+    const int b = u % BB, row = u / BB;
+    T xr = (T)0, xi = (T)0;
+    if (row < rows_in) {
+      xr = src[((size_t)row * 2) * B + b];
+      xi = src[((size_t)row * 2 + 1) * B + b];
+    }
+    wr[row * ld + b] = xr;
+    wi[row * ld + b] = xi;
+  }
+  __syncthreads();
+  dft_lds_inplace<T, P, BB, DIR, 1>(wr, wi, twc, tws);
+  T *dst = out + (size_t)ky * rows_out * 2 * B + b0;
+#pragma unroll 4
+  for (int u = tid; u < rows_out * BB; u += NT) {
+    const int b = u % BB, row = u / BB;
+    dst[((size_t)row * 2) * B + b] = wr[row * ld + b];
+    dst[((size_t)row * 2 + 1) * B + b] = wi[row * ld + b];
+  }
 }
 
 // ---- row pass --------------------------------------------------------------------
@@ -479,10 +564,17 @@ template <typename T, int P, int BB>
 hipError_t col_dispatch_bb(const Dims &d, int B, bool inverse, const T *in, T *out,
                            hipStream_t st, int ppv, const int *active) {
   dim3 grid((unsigned)(d.h + 1), (unsigned)(B / BB));
-  if (inverse)
-    hipLaunchKernelGGL((col_pass_kernel<T, P, BB, true>), grid, dim3(512), 0, st, d.n, B, in, out, ppv, active);
-  else
-    hipLaunchKernelGGL((col_pass_kernel<T, P, BB, false>), grid, dim3(512), 0, st, d.n, B, in, out, ppv, active);
+  if constexpr (P > 256) {
+    if (inverse)
+      hipLaunchKernelGGL((col_pass_lds_kernel<T, P, BB, true>), grid, dim3(512), 0, st, d.n, B, in, out, ppv, active);
+    else
+      hipLaunchKernelGGL((col_pass_lds_kernel<T, P, BB, false>), grid, dim3(512), 0, st, d.n, B, in, out, ppv, active);
+  } else {
+    if (inverse)
+      hipLaunchKernelGGL((col_pass_kernel<T, P, BB, true>), grid, dim3(512), 0, st, d.n, B, in, out, ppv, active);
+    else
+      hipLaunchKernelGGL((col_pass_kernel<T, P, BB, false>), grid, dim3(512), 0, st, d.n, B, in, out, ppv, active);
+  }
   return hipGetLastError();
 }
 
@@ -490,8 +582,11 @@ template <typename T, int P>
 hipError_t col_dispatch(const Dims &d, int B, bool inverse, const T *in, T *out, hipStream_t st,
                         int ppv, int bb, const int *active) {
   ppv = ppv ? ppv : B;
-  if (batch_block(d, B, ppv, sizeof(T) == 8, bb) == 32)
-    return col_dispatch_bb<T, P, 32>(d, B, inverse, in, out, st, ppv, active);
+  // 32 planes per block only where every thread still holds one DFT unit
+  if constexpr (Fac<P>::R1 * 32 <= 512 && Fac<P>::R2 * 32 <= 512) {
+    if (batch_block(d, B, ppv, sizeof(T) == 8, bb) == 32)
+      return col_dispatch_bb<T, P, 32>(d, B, inverse, in, out, st, ppv, active);
+  }
   return col_dispatch_bb<T, P, 16>(d, B, inverse, in, out, st, ppv, active);
 }
 
@@ -504,7 +599,9 @@ hipError_t row_dispatch_bb(const Dims &d, const RowArgs &a, hipStream_t st) {
 
 template <typename T, int P>
 hipError_t row_dispatch(const Dims &d, const RowArgs &a, hipStream_t st) {
-  if (batch_block(d, a.B, a.ppv, sizeof(T) == 8, a.bb) == 32) return row_dispatch_bb<T, P, 32>(d, a, st);
+  if constexpr (P <= 256) {
+    if (batch_block(d, a.B, a.ppv, sizeof(T) == 8, a.bb) == 32) return row_dispatch_bb<T, P, 32>(d, a, st);
+  }
   return row_dispatch_bb<T, P, 16>(d, a, st);
 }
 
@@ -519,6 +616,7 @@ hipError_t launch_col_pass(const Dims &d, int B, bool inverse, const T *in, T *o
     case 64: return col_dispatch<T, 64>(d, B, inverse, in, out, st, ppv, bb, active);
     case 128: return col_dispatch<T, 128>(d, B, inverse, in, out, st, ppv, bb, active);
     case 256: return col_dispatch<T, 256>(d, B, inverse, in, out, st, ppv, bb, active);
+    case 512: return col_dispatch<T, 512>(d, B, inverse, in, out, st, ppv, bb, active);
     default: return hipErrorInvalidValue;
   }
 }
@@ -531,15 +629,17 @@ hipError_t launch_row_pass(const Dims &d, const RowArgs &a, hipStream_t st) {
     case 64: return row_dispatch<T, 64>(d, a, st);
     case 128: return row_dispatch<T, 128>(d, a, st);
     case 256: return row_dispatch<T, 256>(d, a, st);
+    case 512: return row_dispatch<T, 512>(d, a, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 // Planes per block: 32 (128-byte runs) when that still gives enough blocks to
-// fill the chip, else 16; FP64 always 16.  A block never straddles two
-// volumes (the choice divides the planes per volume).
+// fill the chip, else 16; FP64 and FFT sizes above 256 (a radix-32 column
+// stage) always 16.  A block never straddles two volumes (the choice divides
+// the planes per volume).
 int batch_block(const Dims &d, int B, int ppv, bool fp64, int bb) {
-  if (fp64 || (B % 32) != 0 || (ppv % 32) != 0) return 16;
+  if (fp64 || d.p > 256 || (B % 32) != 0 || (ppv % 32) != 0) return 16;
   if (bb == 16 || bb == 32) return bb;
   return ((d.h + 1) * (B / 32) >= 1024) ? 32 : 16;
 }
