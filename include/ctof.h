@@ -32,8 +32,8 @@
  *     is asynchronous unless stated otherwise.
  *   - Element type: double for CTOF_FP64, float for CTOF_FP32, CTOF_BF16X3
  *     and CTOF_BF16.  Arrays are C-contiguous:
- *       volume mu, g          [nz][n][n]
- *       histogram m, d, r     [nt][n][n]
+ *       volume mu, g          [nz][ny][nx]
+ *       histogram m, d, r     [nt][ny][nx]
  *   - A ctof_kernel handle is immutable after tabulation (apart from its FFT
  *     tuning, see ctof_kernel_set_tuning) and may be used concurrently from
  *     several streams as long as each call has its own workspace.
@@ -68,10 +68,12 @@ typedef enum {
 
 /*
  * Scan geometry and background optics (section "Confocal ToF-DOT": a
- * collocated source/detector pair scanned over an n x n grid; the voxel
+ * collocated source/detector pair scanned over an ny x nx grid; the voxel
  * grid is the scan grid, aligned, one voxel layer per entry of z_mm).
- *   nx, ny            scan points per side; this build requires nx == ny,
- *                     1 <= n <= 256 (CTOF_EUNSUPPORTED otherwise)
+ *   nx, ny            scan points per row and rows, 1..256 each
+ *                     (CTOF_EUNSUPPORTED above); spatial arrays are
+ *                     [..][ny][nx]; both lateral axes use the FFT size of
+ *                     the longer side.  Source multiplexing needs nx == ny
  *   pitch_mm          lateral pitch (> 0), equal in x and y
  *   nz, z_mm          number of layers (>= 1) and a HOST array of layer
  *                     centre depths, strictly increasing, > 0
@@ -119,7 +121,7 @@ ctof_status ctof_kernel_tabulate(const ctof_geometry *geom, ctof_precision prec,
 
 /*
  * Test hook: the same FP64 kernel values as ctof_kernel_tabulate, before the
- * transform, for lateral offsets 0 <= dy, dx < n:
+ * transform, for lateral offsets 0 <= dy, dx < n, n = max(nx, ny):
  *   quad_dev[z][k][dy][dx] = K_z[dy][dx][k]   (double, nz*nt*n*n entries).
  * Enqueues on `stream`; asynchronous.
  */
@@ -159,12 +161,20 @@ void ctof_kernel_free(ctof_kernel k);
 
 /*
  * Shape facts of a handle (any pointer may be NULL):
- *   n, nz, nt   grid, layers, bins;   p   FFT size (power of two >= 2n-1)
+ *   n           max(nx, ny), the side that sets the FFT size
+ *   nz, nt      layers, bins;   p   FFT size (power of two >= 2n-1)
  *   nmat        distinct spectrum matrices, (p/2+1)(p/2+2)/2
  *   prec        precision the handle was tabulated for
  */
 ctof_status ctof_kernel_info(ctof_kernel k, int32_t *n, int32_t *nz, int32_t *nt,
                              int32_t *p, int32_t *nmat, int32_t *prec);
+
+/*
+ * Scan grid of a handle: ny rows and nx columns, the shape of every spatial
+ * array the handle's calls take ([nz][ny][nx] volumes, [nt][ny][nx]
+ * histograms).  Either pointer may be NULL.
+ */
+ctof_status ctof_kernel_grid(ctof_kernel k, int32_t *ny, int32_t *nx);
 
 /*
  * Workspace bytes for ctof_forward / ctof_adjoint (op_ws) and for
@@ -174,7 +184,7 @@ ctof_status ctof_workspace_bytes(ctof_kernel k, int32_t max_iter, size_t *op_ws,
                                  size_t *solve_ws);
 
 /*
- * Forward model (Eq. 11): m = A mu.  mu_dev [nz][n][n], m_dev [nt][n][n],
+ * Forward model (Eq. 11): m = A mu.  mu_dev [nz][ny][nx], m_dev [nt][ny][nx],
  * element type of the handle's precision.  Asynchronous.
  */
 ctof_status ctof_forward(ctof_kernel k, const void *mu_dev, void *m_dev, void *ws_dev,
@@ -182,7 +192,7 @@ ctof_status ctof_forward(ctof_kernel k, const void *mu_dev, void *m_dev, void *w
 
 /*
  * Adjoint (the transpose of A; the kernel is real): g = A^T r.
- * r_dev [nt][n][n], g_dev [nz][n][n].  Asynchronous.
+ * r_dev [nt][ny][nx], g_dev [nz][ny][nx].  Asynchronous.
  */
 ctof_status ctof_adjoint(ctof_kernel k, const void *r_dev, void *g_dev, void *ws_dev,
                          size_t ws_bytes, hipStream_t stream);
@@ -321,8 +331,8 @@ typedef struct {
 } ctof_solver_report;
 
 /*
- * FISTA reconstruction.  d_dev [nt][n][n] (the measured histogram),
- * mu_inout_dev [nz][n][n] (start point if warm_start, result on return).
+ * FISTA reconstruction.  d_dev [nt][ny][nx] (the measured histogram),
+ * mu_inout_dev [nz][ny][nx] (start point if warm_start, result on return).
  * Enqueues on `stream` and synchronises it before returning (the report is
  * filled from device scalars); also synchronises every check_every
  * iterations when rel_tol > 0.  Reaching max_iter is not an error.
@@ -345,8 +355,8 @@ ctof_status ctof_reconstruct(ctof_kernel k, const void *d_dev, void *mu_inout_de
  * replayed on `stream`; with rel_tol > 0 a scan whose gradient-mapping ratio
  * is <= rel_tol at a chunk end is frozen (its mu keeps that iterate) and a
  * class whose scans are all frozen leaves the graph.
- *   d_dev[i]        [nt][n][n] of scan i's handle
- *   mu_inout_dev[i] [nz][n][n] (start if warm_start, result on return)
+ *   d_dev[i]        [nt][ny][nx] of scan i's handle
+ *   mu_inout_dev[i] [nz][ny][nx] (start if warm_start, result on return)
  *   reports[i]      per scan; iters = iterations until frozen (or run)
  * opts.history_dev and opts.timing must be NULL / 0.  Synchronises `stream`.
  */
@@ -478,7 +488,7 @@ ctof_status ctof_mse(int64_t n, const ctof_tensor *y, float y_scale, const float
  * (s: host array [nb]),
  * y_b = channel y.c0 of rows b V .. (b + 1) V - 1 of an FP32 tensor
  * (V = nz n n, rows in [z][y][x] order: the network output); target_dev
- * holds the solutions mu*_b (float [nb][nz][n][n]).  With e_b = x_b - mu*_b
+ * holds the solutions mu*_b (float [nb][nz][ny][nx]).  With e_b = x_b - mu*_b
  * and H = A^T A + lambda I (the Hessian of the regularised objective of
  * section "Reconstruction Algorithm"), H e_b is to first order the gradient
  * of the objective at the start, i.e. what the solver's gradient-mapping

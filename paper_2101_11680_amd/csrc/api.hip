@@ -116,8 +116,8 @@ ctof_status check_geometry(const ctof_geometry *g, ctof::TabGeom *tg, ctof::Laye
   }
   const double total = (double)g->nz * g->nx * g->ny * (double)g->nt;
   if (total > 9.0e18) return set_error(CTOF_EINVAL, "nz*ny*nx*nt overflows");
-  if (g->nx != g->ny) return set_error(CTOF_EUNSUPPORTED, "only square scan grids (nx == ny) are implemented");
-  if (g->nx > ctof::kMaxN) return set_error(CTOF_EUNSUPPORTED, "n > %d needs an FFT size above 512", ctof::kMaxN);
+  if (g->nx > ctof::kMaxN || g->ny > ctof::kMaxN)
+    return set_error(CTOF_EUNSUPPORTED, "a scan side above %d needs an FFT size above 512", ctof::kMaxN);
   if (g->nz > ctof::kMaxLayers) return set_error(CTOF_EUNSUPPORTED, "nz > %d", ctof::kMaxLayers);
   if (g->nt > (1 << 20)) return set_error(CTOF_EUNSUPPORTED, "nt > 2^20");
   if (tg) {
@@ -132,7 +132,7 @@ ctof_status check_geometry(const ctof_geometry *g, ctof::TabGeom *tg, ctof::Laye
     o.zb = 2.0 * A * o.D;
     o.mua = mua;
     o.mueff = std::sqrt(mua / o.D);
-    tg->n = g->nx;
+    tg->n = std::max(g->nx, g->ny);  // kernel offsets cover the longer side in both axes
     tg->nz = g->nz;
     tg->nt = g->nt;
     tg->pitch = g->pitch_mm;
@@ -217,10 +217,10 @@ ClassWs class_ws(const ctof_kernel_s *k, int nvol, int max_iter) {
   };
   o.yhat = take((size_t)(d.h + 1) * d.p * 2 * nvol * d.nzp * es);
   o.mhat = take((size_t)(d.h + 1) * d.p * 2 * nvol * d.ntp * es);
-  o.xt = take((size_t)(d.h + 1) * d.n * 2 * nvol * d.ntp * es);
-  o.xz = take((size_t)(d.h + 1) * d.n * 2 * nvol * d.nzp * es);
+  o.xt = take((size_t)(d.h + 1) * d.ny * 2 * nvol * d.ntp * es);
+  o.xz = take((size_t)(d.h + 1) * d.ny * 2 * nvol * d.nzp * es);
   o.op_total = off;
-  const size_t vol = (size_t)d.nz * d.n * d.n * es;
+  const size_t vol = (size_t)d.nz * d.ny * d.nx * es;
   o.y = take(vol * nvol);
   o.v = take(vol);
   o.w = take(vol);
@@ -257,7 +257,7 @@ struct Engine {
   T *mhat() const { return reinterpret_cast<T *>(ws + L.mhat); }
   T *xt() const { return reinterpret_cast<T *>(ws + L.xt); }
   T *xz() const { return reinterpret_cast<T *>(ws + L.xz); }
-  T *y(int v) const { return reinterpret_cast<T *>(ws + L.y) + (size_t)v * dm().nz * dm().n * dm().n; }
+  T *y(int v) const { return reinterpret_cast<T *>(ws + L.y) + (size_t)v * dm().nz * dm().ny * dm().nx; }
   T *pv() const { return reinterpret_cast<T *>(ws + L.v); }
   T *pw() const { return reinterpret_cast<T *>(ws + L.w); }
   double *hist() const { return reinterpret_cast<double *>(ws + L.hist); }
@@ -321,6 +321,7 @@ struct Engine {
 // Multiplexing descriptor -> kernel arguments (sizes from the kernel handle).
 ctof_status make_mux(const ctof_kernel_s *k, const ctof_mux *mx, ctof::MuxArgs *a) {
   if (!mx) return set_error(CTOF_EINVAL, "mux is NULL");
+  if (k->dims.nx != k->dims.ny) return set_error(CTOF_EUNSUPPORTED, "multiplexing needs a square scan grid");
   const int n = k->dims.n;
   if (mx->tile_x < 1 || mx->tile_y < 1 || n % mx->tile_x != 0 || n % mx->tile_y != 0)
     return set_error(CTOF_EINVAL, "mux tile %dx%d must divide the scan side %d", mx->tile_x, mx->tile_y, n);
@@ -385,7 +386,7 @@ ctof_status run_adjoint(ctof_kernel k, const void *r, void *g, void *ws, hipStre
   return CTOF_OK;
 }
 
-// out_v = A^T A in_v for the engine's volumes (spatial [nz][n][n])
+// out_v = A^T A in_v for the engine's volumes (spatial [nz][ny][nx])
 template <typename T>
 ctof_status enqueue_normal(const Engine<T> &E, const void *const *in, void *const *out) {
   ctof::RowArgs a = E.row(ctof::ROW_SPATIAL_TO_SPEC, false);
@@ -411,7 +412,7 @@ StartLossWs start_loss_ws(const ctof_kernel_s *k, int nb) {
   StartLossWs o;
   const ClassWs L = class_ws(k, nb, 1);
   const ctof::Dims &d = k->dims;
-  const size_t vol = (size_t)nb * d.nz * d.n * d.n * sizeof(float);
+  const size_t vol = (size_t)nb * d.nz * d.ny * d.nx * sizeof(float);
   size_t off = ctof::round_up(L.op_total, 256);
   o.op = 0;
   o.e = off;
@@ -430,7 +431,7 @@ ctof_status run_start_loss(const ctof_kernel_s *k, int nb, const ctof_tensor *y,
                            const double *w, const double *v, double lambda, int relu_mask, const ctof_tensor *grad,
                            double *terms, void *ws, hipStream_t st) {
   const ctof::Dims &d = k->dims;
-  const long long V = (long long)d.nz * d.n * d.n;
+  const long long V = (long long)d.nz * d.ny * d.nx;
   const long long n = V * nb;
   const StartLossWs o = start_loss_ws(k, nb);
   char *base = reinterpret_cast<char *>(ws);
@@ -503,7 +504,7 @@ ctof_status enqueue_mux_residual(const Engine<T> &E, const void *y, double *part
 template <typename T>
 ctof_status enqueue_power_iteration(const Engine<T> &E1, int iters) {
   const ctof::Dims &dm = E1.dm();
-  const size_t vol = (size_t)dm.nz * dm.n * dm.n;
+  const size_t vol = (size_t)dm.nz * dm.ny * dm.nx;
   if (sizeof(T) == 8)
     HIP_TRY(ctof::launch_fill_value_f64(reinterpret_cast<double *>(E1.pv()), vol, 1.0 / std::sqrt((double)vol), E1.st));
   else
@@ -590,7 +591,7 @@ ctof_status enqueue_iteration(const Engine<T> &E, const void *const *d, void *co
 template <typename T>
 ctof_status enqueue_start(const Engine<T> &E, void *const *mu, bool warm) {
   const ctof::Dims &dm = E.dm();
-  const size_t vol = (size_t)dm.nz * dm.n * dm.n;
+  const size_t vol = (size_t)dm.nz * dm.ny * dm.nx;
   for (int v = 0; v < E.nvol; ++v) {
     if (!warm) HIP_TRY(ctof::launch_fill_zero(mu[v], vol * sizeof(T), E.st));
     HIP_TRY(hipMemcpyAsync(E.y(v), mu[v], vol * sizeof(T), hipMemcpyDeviceToDevice, E.st));
@@ -606,7 +607,7 @@ ctof_status enqueue_start(const Engine<T> &E, void *const *mu, bool warm) {
 template <typename T>
 ctof_status restart_from_zero(const Engine<T> &E, void *const *mu, const std::vector<int> &reset) {
   const ctof::Dims &dm = E.dm();
-  const size_t vol = (size_t)dm.nz * dm.n * dm.n;
+  const size_t vol = (size_t)dm.nz * dm.ny * dm.nx;
   bool any = false;
   for (int v = 0; v < E.nvol; ++v)
     if (reset[v]) {
@@ -1176,9 +1177,12 @@ ctof_status run_tune(ctof_kernel_s *k, int nvol, int iters, void *ws, hipStream_
 
 namespace ctof {
 
-Dims make_dims(int n, int nz, int nt, ctof_precision prec) {
+Dims make_dims(int nx, int ny, int nz, int nt, ctof_precision prec) {
   Dims d;
+  const int n = std::max(nx, ny);
   d.n = n;
+  d.ny = ny;
+  d.nx = nx;
   d.nz = nz;
   d.nt = nt;
   d.p = std::max(kMinP, next_pow2(2 * n - 1));
@@ -1258,7 +1262,7 @@ ctof_status ctof_kernel_bytes(const ctof_geometry *geom, ctof_precision prec, si
   ctof_status s = check_geometry(geom, nullptr, nullptr);
   if (s != CTOF_OK) return s;
   if (!valid_prec(prec)) return set_error(CTOF_EINVAL, "unknown precision %d", (int)prec);
-  const ctof::Dims d = ctof::make_dims(geom->nx, geom->nz, geom->nt, prec);
+  const ctof::Dims d = ctof::make_dims(geom->nx, geom->ny, geom->nz, geom->nt, prec);
   if (khat_bytes) *khat_bytes = ctof::khat_layout(d, prec).total;
   if (tab_ws_bytes) *tab_ws_bytes = tab_ws(d).total;
   return CTOF_OK;
@@ -1281,7 +1285,7 @@ ctof_status ctof_kernel_tabulate_ex(const ctof_geometry *geom, const ctof_fluore
   if (!valid_prec(prec)) return set_error(CTOF_EINVAL, "unknown precision %d", (int)prec);
   if (!out) return set_error(CTOF_EINVAL, "out handle pointer is NULL");
   if (!khat_dev || !tab_ws_dev) return set_error(CTOF_EINVAL, "device buffer is NULL");
-  const ctof::Dims d = ctof::make_dims(geom->nx, geom->nz, geom->nt, prec);
+  const ctof::Dims d = ctof::make_dims(geom->nx, geom->ny, geom->nz, geom->nt, prec);
   const ctof::KhatLayout lay = ctof::khat_layout(d, prec);
   const TabWs tw = tab_ws(d);
   if (khat_bytes < lay.total) return set_error(CTOF_ENOMEM, "khat buffer %zu < %zu bytes", khat_bytes, lay.total);
@@ -1331,7 +1335,7 @@ ctof_status ctof_kernel_tabulate_quadrant_ex(const ctof_geometry *geom, const ct
   if (s != CTOF_OK) return s;
   if ((s = apply_fluorescence(geom, fl, &tg)) != CTOF_OK) return s;
   if (!quad_dev) return set_error(CTOF_EINVAL, "quad_dev is NULL");
-  const size_t n = geom->nx;
+  const size_t n = tg.n;  // max(nx, ny)
   const size_t need = (size_t)geom->nz * geom->nt * n * n * sizeof(double);
   if (quad_bytes < need) return set_error(CTOF_ENOMEM, "quadrant buffer %zu < %zu bytes", quad_bytes, need);
   const ctof::GaussLegendre16 gl = gauss_legendre16();
@@ -1352,6 +1356,14 @@ ctof_status ctof_kernel_info(ctof_kernel k, int32_t *n, int32_t *nz, int32_t *nt
   if (p) *p = k->dims.p;
   if (nmat) *nmat = k->dims.nmat;
   if (prec) *prec = (int32_t)k->prec;
+  return CTOF_OK;
+}
+
+ctof_status ctof_kernel_grid(ctof_kernel k, int32_t *ny, int32_t *nx) {
+  ctof_status s = check_kernel(k);
+  if (s != CTOF_OK) return s;
+  if (ny) *ny = k->dims.ny;
+  if (nx) *nx = k->dims.nx;
   return CTOF_OK;
 }
 

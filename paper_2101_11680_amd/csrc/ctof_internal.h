@@ -16,14 +16,17 @@ constexpr int kMaxVol = 64;     // volumes of one shape class per batched launch
 
 inline size_t round_up(size_t v, size_t m) { return (v + m - 1) / m * m; }
 
-// Sizes derived from a geometry.  p: FFT size (power of two >= 2n-1);
-// h = p/2; nmat = distinct real spectrum matrices (a <= b <= h);
-// nzp / ntp: layer / bin counts padded for the matrix-core tiles.
+// Sizes derived from a geometry.  ny x nx: the scan grid (rows, columns);
+// n = max(ny, nx) sets the FFT size p (power of two >= 2n-1) of both
+// lateral axes, so the spectrum keeps its kx <-> ky symmetry; h = p/2;
+// nmat = distinct real spectrum matrices (a <= b <= h); nzp / ntp: layer /
+// bin counts padded for the matrix-core tiles.
 struct Dims {
   int n, nz, nt, p, h, nmat, nzp, ntp;
+  int ny, nx;
 };
 
-Dims make_dims(int n, int nz, int nt, ctof_precision prec);
+Dims make_dims(int nx, int ny, int nz, int nt, ctof_precision prec);
 
 // Background optics and the per-voxel constants of the kernel closed form.
 struct Optics {
@@ -110,8 +113,8 @@ hipError_t launch_pack(const Dims &d, ctof_precision prec, const double *k64, vo
 
 // ---- FFT passes (fft.hip) ---------------------------------------------------
 // Column pass along kx for every ky of a spectrum block.
-//   inverse: in [h+1][p][2][B] -> out [h+1][n][2][B] (rows >= n dropped)
-//   forward: in [h+1][n][2][B] (rows >= n are zero) -> out [h+1][p][2][B]
+//   inverse: in [h+1][p][2][B] -> out [h+1][ny][2][B] (rows >= ny dropped)
+//   forward: in [h+1][ny][2][B] (rows >= ny are zero) -> out [h+1][p][2][B]
 // ppv: planes per volume; active: per-volume flags, blocks of frozen (0)
 // volumes do nothing (NULL: all live)
 template <typename T>
@@ -136,9 +139,9 @@ struct RowArgs {
   int nplanes;      // real planes per volume (nt or nz); the rest read as zero
   int nvol;         // volumes (1 for the single-volume entry points)
   int bb;           // planes per block (0 = default rule)
-  const void *spec_in;   // [h+1][n][2][B]
-  void *spec_out;        // [h+1][n][2][B] (may alias spec_in)
-  const void *sp_in[kMaxVol];   // per volume spatial input [planes][n][n] (d, y, v, ...)
+  const void *spec_in;   // [h+1][ny][2][B]
+  void *spec_out;        // [h+1][ny][2][B] (may alias spec_in)
+  const void *sp_in[kMaxVol];   // per volume spatial input [planes][ny][nx] (d, y, v, ...)
   void *sp_out[kMaxVol];        // per volume spatial output
   void *sp_aux[kMaxVol];        // per volume second spatial buffer (mu for FISTA)
   double *partials;      // per-block FP64 partials (2 per block)

@@ -206,7 +206,7 @@ struct Fac {
 // the imaginary parts, to keep the block's LDS small.
 template <typename T, int P, int BB, bool INV>
 __global__ void __launch_bounds__(512)
-col_pass_kernel(int n, int B, const T *__restrict__ in, T *__restrict__ out, int ppv,
+col_pass_kernel(int ny, int B, const T *__restrict__ in, T *__restrict__ out, int ppv,
                 const int *__restrict__ active) {
   constexpr int R1 = Fac<P>::R1, R2 = Fac<P>::R2;
   constexpr int DIR = INV ? 1 : -1;
@@ -217,8 +217,8 @@ col_pass_kernel(int n, int B, const T *__restrict__ in, T *__restrict__ out, int
   const int ky = blockIdx.x;
   const int b0 = blockIdx.y * BB;
   if (active != nullptr && active[b0 / ppv] == 0) return;  // frozen volume
-  const int rows_in = INV ? P : n;
-  const int rows_out = INV ? n : P;
+  const int rows_in = INV ? P : ny;
+  const int rows_out = INV ? ny : P;
   const int tid = threadIdx.x;
   build_twiddles<T, P>(twc, tws);
   const T *src = in + (size_t)ky * rows_in * 2 * B + b0;
@@ -313,7 +313,7 @@ __device__ __forceinline__ void dft_lds_inplace(T *wr, T *wi, const T *twc, cons
 // complex) go through LDS whole and the DFT runs in place there.
 template <typename T, int P, int BB, bool INV>
 __global__ void __launch_bounds__(512)
-col_pass_lds_kernel(int n, int B, const T *__restrict__ in, T *__restrict__ out, int ppv,
+col_pass_lds_kernel(int ny, int B, const T *__restrict__ in, T *__restrict__ out, int ppv,
                     const int *__restrict__ active) {
   constexpr int DIR = INV ? 1 : -1;
   constexpr int ld = BB + 1;
@@ -323,8 +323,8 @@ col_pass_lds_kernel(int n, int B, const T *__restrict__ in, T *__restrict__ out,
   const int ky = blockIdx.x;
   const int b0 = blockIdx.y * BB;
   if (active != nullptr && active[b0 / ppv] == 0) return;  // frozen volume
-  const int rows_in = INV ? P : n;
-  const int rows_out = INV ? n : P;
+  const int rows_in = INV ? P : ny;
+  const int rows_out = INV ? ny : P;
   const int tid = threadIdx.x;
   build_twiddles<T, P>(twc, tws);
   const T *src = in + (size_t)ky * rows_in * 2 * B + b0;
@@ -356,7 +356,7 @@ col_pass_lds_kernel(int n, int B, const T *__restrict__ in, T *__restrict__ out,
 // (even, odd) sample pairs; the pre/post-processing pairs bins k and H - k.
 template <typename T, int P, int BB>
 __global__ void __launch_bounds__(512)
-row_pass_kernel(int n, RowArgs a) {
+row_pass_kernel(int ny, int nx, RowArgs a) {
   constexpr int H = P / 2;
   constexpr int ld = BB + 1;
   constexpr int NT = 512;
@@ -378,7 +378,7 @@ row_pass_kernel(int n, RowArgs a) {
   const bool spec_in = (op != ROW_SPATIAL_TO_SPEC) && (op != ROW_SCALE_TO_SPEC);
   const bool spec_out = (op == ROW_SPATIAL_TO_SPEC) || (op == ROW_SCALE_TO_SPEC) ||
                         (op == ROW_RESIDUAL) || (op == ROW_PASS) || (op == ROW_FISTA);
-  const int nh = (n + 1) / 2;
+  const int nh = (nx + 1) / 2;
   build_twiddles<T, P>(twc, tws);
   __syncthreads();
 
@@ -387,8 +387,8 @@ row_pass_kernel(int n, RowArgs a) {
     const T *src = reinterpret_cast<const T *>(a.spec_in) + b0;
     for (int u = tid; u < (H / 2 + 1) * BB; u += NT) {
       const int b = u % BB, k = u / BB;
-      const size_t o1 = (((size_t)k * n + i) * 2) * B + b;
-      const size_t o2 = (((size_t)(H - k) * n + i) * 2) * B + b;
+      const size_t o1 = (((size_t)k * ny + i) * 2) * B + b;
+      const size_t o2 = (((size_t)(H - k) * ny + i) * 2) * B + b;
       const T x1r = src[o1], x1i = src[o1 + B];
       const T x2r = src[o2], x2i = src[o2 + B];
       {
@@ -423,11 +423,11 @@ row_pass_kernel(int n, RowArgs a) {
   const T *sp_in = vol_on ? reinterpret_cast<const T *>(a.sp_in[vol]) : nullptr;
   T *sp_out = vol_on ? reinterpret_cast<T *>(a.sp_out[vol]) : nullptr;
   T *sp_aux = vol_on ? reinterpret_cast<T *>(a.sp_aux[vol]) : nullptr;
-  for (int u = tid; u < n * BB; u += NT) {
-    const int j = u % n, b = u / n;
+  for (int u = tid; u < nx * BB; u += NT) {
+    const int j = u % nx, b = u / nx;
     const int pl = pb0 + b;
     const bool valid = vol_on && pl < a.nplanes;
-    const size_t idx = ((size_t)pl * n + i) * n + j;
+    const size_t idx = ((size_t)pl * ny + i) * nx + j;
     T *slot = ((j & 1) ? wi : wr) + (j >> 1) * ld + b;
     T x = (T)0;
     if (spec_in) x = *slot;
@@ -497,7 +497,7 @@ row_pass_kernel(int n, RowArgs a) {
       if (m >= nh) {
         wr[m * ld + b] = (T)0;
         wi[m * ld + b] = (T)0;
-      } else if ((n & 1) && m == nh - 1) {
+      } else if ((nx & 1) && m == nh - 1) {
         wi[m * ld + b] = (T)0;
       }
     }
@@ -542,11 +542,11 @@ row_pass_kernel(int n, RowArgs a) {
       const T evr = (T)0.5 * (z1r + z2r), evi = (T)0.5 * (z1i - z2i);
       const T odr = (T)0.5 * (z1i + z2i), odi = (T)(-0.5) * (z1r - z2r);
       const T c = twc[k], s = -tws[k];
-      dst[(((size_t)k * n + i) * 2) * B + b] = evr + odr * c - odi * s;
-      dst[(((size_t)k * n + i) * 2 + 1) * B + b] = evi + odr * s + odi * c;
+      dst[(((size_t)k * ny + i) * 2) * B + b] = evr + odr * c - odi * s;
+      dst[(((size_t)k * ny + i) * 2 + 1) * B + b] = evi + odr * s + odi * c;
       if (k == 0) {
-        dst[(((size_t)H * n + i) * 2) * B + b] = evr - odr;
-        dst[(((size_t)H * n + i) * 2 + 1) * B + b] = evi - odi;
+        dst[(((size_t)H * ny + i) * 2) * B + b] = evr - odr;
+        dst[(((size_t)H * ny + i) * 2 + 1) * B + b] = evi - odi;
       }
     }
     if (k > 0 && k < H / 2) {
@@ -554,8 +554,8 @@ row_pass_kernel(int n, RowArgs a) {
       const T evr = (T)0.5 * (z2r + z1r), evi = (T)0.5 * (z2i - z1i);
       const T odr = (T)0.5 * (z2i + z1i), odi = (T)(-0.5) * (z2r - z1r);
       const T c = twc[kk], s = -tws[kk];
-      dst[(((size_t)kk * n + i) * 2) * B + b] = evr + odr * c - odi * s;
-      dst[(((size_t)kk * n + i) * 2 + 1) * B + b] = evi + odr * s + odi * c;
+      dst[(((size_t)kk * ny + i) * 2) * B + b] = evr + odr * c - odi * s;
+      dst[(((size_t)kk * ny + i) * 2 + 1) * B + b] = evi + odr * s + odi * c;
     }
   }
 }
@@ -566,14 +566,14 @@ hipError_t col_dispatch_bb(const Dims &d, int B, bool inverse, const T *in, T *o
   dim3 grid((unsigned)(d.h + 1), (unsigned)(B / BB));
   if constexpr (P > 256) {
     if (inverse)
-      hipLaunchKernelGGL((col_pass_lds_kernel<T, P, BB, true>), grid, dim3(512), 0, st, d.n, B, in, out, ppv, active);
+      hipLaunchKernelGGL((col_pass_lds_kernel<T, P, BB, true>), grid, dim3(512), 0, st, d.ny, B, in, out, ppv, active);
     else
-      hipLaunchKernelGGL((col_pass_lds_kernel<T, P, BB, false>), grid, dim3(512), 0, st, d.n, B, in, out, ppv, active);
+      hipLaunchKernelGGL((col_pass_lds_kernel<T, P, BB, false>), grid, dim3(512), 0, st, d.ny, B, in, out, ppv, active);
   } else {
     if (inverse)
-      hipLaunchKernelGGL((col_pass_kernel<T, P, BB, true>), grid, dim3(512), 0, st, d.n, B, in, out, ppv, active);
+      hipLaunchKernelGGL((col_pass_kernel<T, P, BB, true>), grid, dim3(512), 0, st, d.ny, B, in, out, ppv, active);
     else
-      hipLaunchKernelGGL((col_pass_kernel<T, P, BB, false>), grid, dim3(512), 0, st, d.n, B, in, out, ppv, active);
+      hipLaunchKernelGGL((col_pass_kernel<T, P, BB, false>), grid, dim3(512), 0, st, d.ny, B, in, out, ppv, active);
   }
   return hipGetLastError();
 }
@@ -592,8 +592,8 @@ hipError_t col_dispatch(const Dims &d, int B, bool inverse, const T *in, T *out,
 
 template <typename T, int P, int BB>
 hipError_t row_dispatch_bb(const Dims &d, const RowArgs &a, hipStream_t st) {
-  dim3 grid((unsigned)d.n, (unsigned)(a.B / BB));
-  hipLaunchKernelGGL((row_pass_kernel<T, P, BB>), grid, dim3(512), 0, st, d.n, a);
+  dim3 grid((unsigned)d.ny, (unsigned)(a.B / BB));
+  hipLaunchKernelGGL((row_pass_kernel<T, P, BB>), grid, dim3(512), 0, st, d.ny, d.nx, a);
   return hipGetLastError();
 }
 
@@ -645,7 +645,7 @@ int batch_block(const Dims &d, int B, int ppv, bool fp64, int bb) {
 }
 
 int row_pass_blocks(const Dims &d, int B, int ppv, bool fp64, int bb) {
-  return d.n * (B / batch_block(d, B, ppv, fp64, bb));
+  return d.ny * (B / batch_block(d, B, ppv, fp64, bb));
 }
 
 template hipError_t launch_col_pass<float>(const Dims &, int, bool, const float *, float *, hipStream_t, int, int,

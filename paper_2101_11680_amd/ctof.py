@@ -24,7 +24,7 @@ STATUS = {0: "CTOF_OK", -1: "CTOF_EINVAL", -2: "CTOF_ENOMEM", -3: "CTOF_EHIP",
 
 EXPORTS = ("ctof_kernel_bytes", "ctof_kernel_tabulate", "ctof_kernel_tabulate_quadrant",
            "ctof_kernel_tabulate_ex", "ctof_kernel_tabulate_quadrant_ex",
-           "ctof_kernel_free", "ctof_kernel_info", "ctof_workspace_bytes", "ctof_forward",
+           "ctof_kernel_free", "ctof_kernel_info", "ctof_kernel_grid", "ctof_workspace_bytes", "ctof_forward",
            "ctof_adjoint", "ctof_reconstruct", "ctof_workspace_bytes_batched",
            "ctof_reconstruct_batched", "ctof_kernel_set_tuning", "ctof_kernel_get_tuning",
            "ctof_tune_workspace_bytes", "ctof_tune", "ctof_last_error",
@@ -116,6 +116,7 @@ def lib() -> ctypes.CDLL:
         L.ctof_kernel_free.argtypes = [vp]
         L.ctof_kernel_free.restype = None
         L.ctof_kernel_info.argtypes = [vp] + [ctypes.POINTER(i32)] * 6
+        L.ctof_kernel_grid.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.ctof_workspace_bytes.argtypes = [vp, i32, ctypes.POINTER(sz), ctypes.POINTER(sz)]
         L.ctof_forward.argtypes = [vp, vp, vp, vp, sz, vp]
         L.ctof_adjoint.argtypes = [vp, vp, vp, vp, sz, vp]
@@ -215,12 +216,14 @@ def kernel_bytes(geometry, precision: int) -> tuple:
 
 @dataclass
 class KernelInfo:
-    n: int
+    n: int          # max(ny, nx): the side that sets the FFT size
     nz: int
     nt: int
     p: int
     nmat: int
     precision: int
+    ny: int = 0     # scan rows
+    nx: int = 0     # scan columns
 
 
 class Kernel:
@@ -232,7 +235,9 @@ class Kernel:
         self.precision = precision
         vals = [ctypes.c_int32() for _ in range(6)]
         _check(lib().ctof_kernel_info(self._h, *[ctypes.byref(v) for v in vals]))
-        self.info = KernelInfo(*[v.value for v in vals])
+        ny, nx = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().ctof_kernel_grid(self._h, ctypes.byref(ny), ctypes.byref(nx)))
+        self.info = KernelInfo(*[v.value for v in vals], ny=ny.value, nx=nx.value)
         self._ws = {}
 
     @property
@@ -293,7 +298,7 @@ def tabulate_quadrant(geometry, device="cuda", stream=None, fluorescence=None):
     """FP64 kernel values [nz][nt][n][n] for offsets dy, dx >= 0 (test hook)."""
     torch = _torch()
     gs, _z = _geometry(geometry)
-    n = int(geometry.nx)
+    n = max(int(geometry.nx), int(geometry.ny))
     out = torch.empty((len(geometry.z_mm), int(geometry.nt), n, n), dtype=torch.float64, device=device)
     _check(lib().ctof_kernel_tabulate_quadrant_ex(ctypes.byref(gs), _fluorescence(fluorescence), out.data_ptr(),
                                                   out.numel() * 8, _stream_ptr(stream)))
@@ -313,10 +318,10 @@ def _contig(x, dtype, shape):
 def forward(k: Kernel, mu, out=None, stream=None):
     torch = _torch()
     i = k.info
-    mu = _contig(mu, _dtype(k.precision), (i.nz, i.n, i.n))
+    mu = _contig(mu, _dtype(k.precision), (i.nz, i.ny, i.nx))
     if out is None:
-        out = torch.empty((i.nt, i.n, i.n), dtype=mu.dtype, device=mu.device)
-    out = _contig(out, mu.dtype, (i.nt, i.n, i.n))
+        out = torch.empty((i.nt, i.ny, i.nx), dtype=mu.dtype, device=mu.device)
+    out = _contig(out, mu.dtype, (i.nt, i.ny, i.nx))
     nb, _ = k.workspace_bytes(1)
     ws = k.workspace(nb, mu.device)
     _check(lib().ctof_forward(k.handle, mu.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(),
@@ -327,10 +332,10 @@ def forward(k: Kernel, mu, out=None, stream=None):
 def adjoint(k: Kernel, r, out=None, stream=None):
     torch = _torch()
     i = k.info
-    r = _contig(r, _dtype(k.precision), (i.nt, i.n, i.n))
+    r = _contig(r, _dtype(k.precision), (i.nt, i.ny, i.nx))
     if out is None:
-        out = torch.empty((i.nz, i.n, i.n), dtype=r.dtype, device=r.device)
-    out = _contig(out, r.dtype, (i.nz, i.n, i.n))
+        out = torch.empty((i.nz, i.ny, i.nx), dtype=r.dtype, device=r.device)
+    out = _contig(out, r.dtype, (i.nz, i.ny, i.nx))
     nb, _ = k.workspace_bytes(1)
     ws = k.workspace(nb, r.device)
     _check(lib().ctof_adjoint(k.handle, r.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(),
@@ -391,7 +396,7 @@ def mux_forward(k: Kernel, mux: Mux, m, out=None, stream=None):
     """y = S m per tile and bin: m [nt][n][n] -> y [nt][rows][ntiles]."""
     torch = _torch()
     i = k.info
-    m = _contig(m, _dtype(k.precision), (i.nt, i.n, i.n))
+    m = _contig(m, _dtype(k.precision), (i.nt, i.ny, i.nx))
     shape = (i.nt, mux.rows, mux.ntiles(i.n))
     if out is None:
         out = torch.empty(shape, dtype=m.dtype, device=m.device)
@@ -408,8 +413,8 @@ def mux_adjoint(k: Kernel, mux: Mux, y, out=None, stream=None):
     i = k.info
     y = _contig(y, _dtype(k.precision), (i.nt, mux.rows, mux.ntiles(i.n)))
     if out is None:
-        out = torch.empty((i.nt, i.n, i.n), dtype=y.dtype, device=y.device)
-    out = _contig(out, y.dtype, (i.nt, i.n, i.n))
+        out = torch.empty((i.nt, i.ny, i.nx), dtype=y.dtype, device=y.device)
+    out = _contig(out, y.dtype, (i.nt, i.ny, i.nx))
     desc = mux.desc(k)
     _check(lib().ctof_mux_adjoint(k.handle, ctypes.byref(desc), y.data_ptr(), out.data_ptr(),
                                   _stream_ptr(stream)))
@@ -421,12 +426,12 @@ def mux_normal(k: Kernel, mux: Mux, m, y=None, out=None, fit: bool = False, stre
     as a device float64 scalar) with fit=True.  out may be m itself."""
     torch = _torch()
     i = k.info
-    m = _contig(m, _dtype(k.precision), (i.nt, i.n, i.n))
+    m = _contig(m, _dtype(k.precision), (i.nt, i.ny, i.nx))
     if y is not None:
         y = _contig(y, m.dtype, (i.nt, mux.rows, mux.ntiles(i.n)))
     if out is None:
         out = torch.empty_like(m)
-    out = _contig(out, m.dtype, (i.nt, i.n, i.n))
+    out = _contig(out, m.dtype, (i.nt, i.ny, i.nx))
     desc = mux.desc(k)
     f = torch.zeros((), dtype=torch.float64, device=m.device) if fit else None
     nb = ctypes.c_size_t()
@@ -463,13 +468,13 @@ def reconstruct(k: Kernel, d, mu=None, max_iter: int = 200, lam: float = -1.0,
     torch = _torch()
     i = k.info
     if mux is None:
-        d = _contig(d, _dtype(k.precision), (i.nt, i.n, i.n))
+        d = _contig(d, _dtype(k.precision), (i.nt, i.ny, i.nx))
     else:
         d = _contig(d, _dtype(k.precision), (i.nt, mux.rows, mux.ntiles(i.n)))
     if mu is None:
-        mu = torch.empty((i.nz, i.n, i.n), dtype=d.dtype, device=d.device)
+        mu = torch.empty((i.nz, i.ny, i.nx), dtype=d.dtype, device=d.device)
         warm_start = False
-    mu = _contig(mu, d.dtype, (i.nz, i.n, i.n))
+    mu = _contig(mu, d.dtype, (i.nz, i.ny, i.nx))
     hist = torch.zeros((max_iter, 2), dtype=torch.float64, device=d.device) if history else None
     l1a = _l1_array(l1, i.nz)
     mdesc = mux.desc(k) if mux is not None else None
@@ -511,10 +516,10 @@ def reconstruct_batched(kernels, ds, mus=None, max_iter: int = 200, lam=-1.0, li
     outs = []
     for k, d, mu in zip(kernels, ds, mus):
         i = k.info
-        _contig(d, _dtype(k.precision), (i.nt, i.n, i.n))
+        _contig(d, _dtype(k.precision), (i.nt, i.ny, i.nx))
         if mu is None:
-            mu = torch.empty((i.nz, i.n, i.n), dtype=d.dtype, device=d.device)
-        outs.append(_contig(mu, d.dtype, (i.nz, i.n, i.n)))
+            mu = torch.empty((i.nz, i.ny, i.nx), dtype=d.dtype, device=d.device)
+        outs.append(_contig(mu, d.dtype, (i.nz, i.ny, i.nx)))
     handles = (ctypes.c_void_p * n)(*[k.handle.value for k in kernels])
     dptr = (ctypes.c_void_p * n)(*[d.data_ptr() for d in ds])
     mptr = (ctypes.c_void_p * n)(*[m.data_ptr() for m in outs])
@@ -561,7 +566,7 @@ def tune(k: Kernel, nvol: int = 1, iters: int = 5, cache: Optional[str] = None, 
     i = k.info
     dev = k.khat.device
     arch = torch.cuda.get_device_properties(dev).gcnArchName.split(":")[0]
-    key = f"{arch}|{i.n}|{i.nz}|{i.nt}|{i.precision}|{int(nvol)}"
+    key = f"{arch}|{i.ny}x{i.nx}|{i.nz}|{i.nt}|{i.precision}|{int(nvol)}"
     table = {}
     if cache and os.path.exists(cache):
         with open(cache) as f:
@@ -601,10 +606,10 @@ def layer_energy(k: Kernel, stream=None):
     nb = ctypes.c_size_t()
     _check(lib().ctof_sumsq_ws_bytes(1, ctypes.byref(nb)))
     ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device="cuda")
-    mu = torch.zeros((i.nz, i.n, i.n), dtype=dt, device="cuda")
+    mu = torch.zeros((i.nz, i.ny, i.nx), dtype=dt, device="cuda")
     for z in range(i.nz):
         mu.zero_()
-        mu[z, i.n // 2, i.n // 2] = 1.0
+        mu[z, i.ny // 2, i.nx // 2] = 1.0
         m = forward(k, mu, stream=stream)
         _check(lib().ctof_sumsq(1, int(m.numel()), m.data_ptr(), out[z:].data_ptr(), ws.data_ptr(), ws.numel(),
                                 _stream_ptr(stream)))

@@ -76,8 +76,8 @@ def test_kernel_bytes_sizes(ctof):
     (dict(mus_prime_per_mm=0.0), "CTOF_EINVAL"),
     (dict(mua_per_mm=0.0), "CTOF_EINVAL"),
     (dict(n_medium=0.9), "CTOF_EINVAL"),
-    (dict(nx=16, ny=8), "CTOF_EUNSUPPORTED"),
     (dict(nx=257, ny=257), "CTOF_EUNSUPPORTED"),
+    (dict(nx=16, ny=257), "CTOF_EUNSUPPORTED"),
 ])
 def test_geometry_validation(ctof, bad, status):
     with pytest.raises(ctof.CtofError) as ei:
@@ -113,3 +113,12 @@ def test_null_arguments_rejected_before_any_launch(ctof):
     assert st == -2
     assert lib.ctof_forward(None, None, None, None, 0, None) == -1
     assert lib.ctof_reconstruct(None, None, None, None, None, None, 0, None) == -1
+
+
+def test_non_square_grid_sizes(ctof):
+    # ny x nx grids use the FFT size of the longer side on both axes: the
+    # spectrum matches the square grid of that side
+    kb_sq, _ = ctof.kernel_bytes(_geom(nx=24, ny=24), ctof.FP32)
+    kb_ns, _ = ctof.kernel_bytes(_geom(nx=24, ny=9), ctof.FP32)
+    kb_ns2, _ = ctof.kernel_bytes(_geom(nx=9, ny=24), ctof.FP32)
+    assert kb_ns == kb_sq == kb_ns2

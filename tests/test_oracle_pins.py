@@ -210,6 +210,22 @@ def test_p12_fft_tier_rectangular_grid():
     F = operator.FFTOperator(Kq)
     m0 = operator.forward_direct(Kq, x)
     assert np.linalg.norm(F.forward(x) - m0) <= 1e-13 * np.linalg.norm(m0)
+    r = np.random.default_rng(1).standard_normal((12, 5, 7))
+    g0 = operator.adjoint_direct(Kq, r)
+    assert np.linalg.norm(F.adjoint(r) - g0) <= 1e-13 * np.linalg.norm(g0)
+    # the 5 x 7 operator is the 7 x 7 one restricted to voxels and scan
+    # points of the first five rows (absorbers elsewhere zero, the other
+    # rows' measurements dropped), with the same kernel values
+    gs = Geometry(nx=7, ny=7, pitch_mm=0.8, z_mm=zz, dz_mm=dz, nt=12, dt_ps=40.0)
+    Ks = kernel.tabulate(gs)
+    assert np.array_equal(Ks[:, :5, :, :], Kq)
+    xs = np.zeros((2, 7, 7))
+    xs[:, :5, :] = x
+    ms = operator.forward_direct(Ks, xs)
+    assert np.linalg.norm(ms[:, :5, :] - m0) <= 1e-14 * np.linalg.norm(m0)
+    rs = np.zeros((12, 7, 7))
+    rs[:, :5, :] = r
+    assert np.linalg.norm(operator.adjoint_direct(Ks, rs)[:, :5, :] - g0) <= 1e-14 * np.linalg.norm(g0)
 
 
 # -- P13: FISTA reaches the constrained least-squares minimiser -------------
