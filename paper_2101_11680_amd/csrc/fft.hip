@@ -18,7 +18,7 @@
 // packed kernel spectrum.  A length-R DFT (R <= 32) runs in registers
 // (radix-2, fully unrolled); a length-P pass is two such stages through
 // LDS with a twiddle table built per block in double precision (P = 512:
-// 16 x 32, with the column held in LDS whole).  Real DFTs of length P use
+// 16 x 32, P = 1024: 32 x 32, with the column held in LDS whole).  Real DFTs of length P use
 // one complex DFT of length P/2 plus the standard even/odd split.
 #include "ctof_internal.h"
 
@@ -193,7 +193,7 @@ __device__ __forceinline__ void dft_stage2_unit(const T *br, const T *bi, int ld
 
 template <int P>
 struct Fac {
-  static constexpr int R1 = P == 512 ? 16 : P == 256 ? 16 : P == 128 ? 16 : P == 64 ? 8 : P == 32 ? 8 : P == 16 ? 4
+  static constexpr int R1 = P == 1024 ? 32 : P == 512 ? 16 : P == 256 ? 16 : P == 128 ? 16 : P == 64 ? 8 : P == 32 ? 8 : P == 16 ? 4
                            : P == 8 ? 4 : 2;
   static constexpr int R2 = P / R1;
 };
@@ -582,12 +582,19 @@ template <typename T, int P>
 hipError_t col_dispatch(const Dims &d, int B, bool inverse, const T *in, T *out, hipStream_t st,
                         int ppv, int bb, const int *active) {
   ppv = ppv ? ppv : B;
-  // 32 planes per block only where every thread still holds one DFT unit
-  if constexpr (Fac<P>::R1 * 32 <= 512 && Fac<P>::R2 * 32 <= 512) {
-    if (batch_block(d, B, ppv, sizeof(T) == 8, bb) == 32)
-      return col_dispatch_bb<T, P, 32>(d, B, inverse, in, out, st, ppv, active);
+  if constexpr (P > 512) {
+    // the whole column block lives in LDS: 16 FP32 or 4 FP64 planes fit
+    if constexpr (sizeof(T) == 8) return col_dispatch_bb<T, P, 4>(d, B, inverse, in, out, st, ppv, active);
+    else return col_dispatch_bb<T, P, 16>(d, B, inverse, in, out, st, ppv, active);
   }
-  return col_dispatch_bb<T, P, 16>(d, B, inverse, in, out, st, ppv, active);
+  else {
+    // 32 planes per block only where every thread still holds one DFT unit
+    if constexpr (Fac<P>::R1 * 32 <= 512 && Fac<P>::R2 * 32 <= 512) {
+      if (batch_block(d, B, ppv, sizeof(T) == 8, bb) == 32)
+        return col_dispatch_bb<T, P, 32>(d, B, inverse, in, out, st, ppv, active);
+    }
+    return col_dispatch_bb<T, P, 16>(d, B, inverse, in, out, st, ppv, active);
+  }
 }
 
 template <typename T, int P, int BB>
@@ -599,10 +606,16 @@ hipError_t row_dispatch_bb(const Dims &d, const RowArgs &a, hipStream_t st) {
 
 template <typename T, int P>
 hipError_t row_dispatch(const Dims &d, const RowArgs &a, hipStream_t st) {
-  if constexpr (P <= 256) {
-    if (batch_block(d, a.B, a.ppv, sizeof(T) == 8, a.bb) == 32) return row_dispatch_bb<T, P, 32>(d, a, st);
+  if constexpr (P > 512) {
+    if constexpr (sizeof(T) == 8) return row_dispatch_bb<T, P, 4>(d, a, st);
+    else return row_dispatch_bb<T, P, 16>(d, a, st);
   }
-  return row_dispatch_bb<T, P, 16>(d, a, st);
+  else {
+    if constexpr (P <= 256) {
+      if (batch_block(d, a.B, a.ppv, sizeof(T) == 8, a.bb) == 32) return row_dispatch_bb<T, P, 32>(d, a, st);
+    }
+    return row_dispatch_bb<T, P, 16>(d, a, st);
+  }
 }
 
 }  // namespace
@@ -617,6 +630,7 @@ hipError_t launch_col_pass(const Dims &d, int B, bool inverse, const T *in, T *o
     case 128: return col_dispatch<T, 128>(d, B, inverse, in, out, st, ppv, bb, active);
     case 256: return col_dispatch<T, 256>(d, B, inverse, in, out, st, ppv, bb, active);
     case 512: return col_dispatch<T, 512>(d, B, inverse, in, out, st, ppv, bb, active);
+    case 1024: return col_dispatch<T, 1024>(d, B, inverse, in, out, st, ppv, bb, active);
     default: return hipErrorInvalidValue;
   }
 }
@@ -630,15 +644,18 @@ hipError_t launch_row_pass(const Dims &d, const RowArgs &a, hipStream_t st) {
     case 128: return row_dispatch<T, 128>(d, a, st);
     case 256: return row_dispatch<T, 256>(d, a, st);
     case 512: return row_dispatch<T, 512>(d, a, st);
+    case 1024: return row_dispatch<T, 1024>(d, a, st);
     default: return hipErrorInvalidValue;
   }
 }
 
 // Planes per block: 32 (128-byte runs) when that still gives enough blocks to
 // fill the chip, else 16; FP64 and FFT sizes above 256 (a radix-32 column
-// stage) always 16.  A block never straddles two volumes (the choice divides
-// the planes per volume).
+// stage) always 16; at FFT size 1024 the column block lives in LDS whole,
+// which holds 16 FP32 or 4 FP64 planes.  A block never straddles two volumes
+// (the choice divides the planes per volume).
 int batch_block(const Dims &d, int B, int ppv, bool fp64, int bb) {
+  if (d.p > 512) return fp64 ? 4 : 16;
   if (fp64 || d.p > 256 || (B % 32) != 0 || (ppv % 32) != 0) return 16;
   if (bb == 16 || bb == 32) return bb;
   return ((d.h + 1) * (B / 32) >= 1024) ? 32 : 16;

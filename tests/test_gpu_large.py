@@ -1,9 +1,10 @@
-"""Scan sides above 128 (FFT size 512: a radix-32 column stage, the 512-point
-column DFT held in LDS) against the FP64 oracle: forward and adjoint in
+"""Scan sides above 128 (FFT sizes 512 and 1024: radix-32 column stages with
+the column DFT held in LDS) against the FP64 oracle: forward and adjoint in
 FP64, FP32 and BF16 hi+lo, a short FISTA run in FP64, FP64 kernel values
-before the transform, and batched solves at that size.  Sides 129 (the
-smallest with P = 512, so half of every column is padding), 200 and 256
-(the largest supported) are covered; 257 is refused.
+before the transform, and batched solves.  Sides 129 (the smallest with
+P = 512, so half of every column is padding), 200, 256, 300 (P = 1024),
+512 (the largest supported) and a 512 x 96 rectangle are covered; 513 is
+refused.
 """
 
 import numpy as np
@@ -19,9 +20,9 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 
-def _geom(n, nz=3, nt=20):
+def _geom(n, nz=3, nt=20, nx=None):
     z, dz = even_layers(2.0, 8.0, nz)
-    return Geometry(nx=n, ny=n, pitch_mm=0.5, z_mm=z, dz_mm=dz, nt=nt, dt_ps=50.0)
+    return Geometry(nx=nx or n, ny=n, pitch_mm=0.5, z_mm=z, dz_mm=dz, nt=nt, dt_ps=50.0)
 
 
 _ORACLE = {}
@@ -100,8 +101,37 @@ def test_batched_equals_single_at_200():
         assert rel_l2(to_np(mub), to_np(mu1)) <= 1e-6
 
 
-def test_side_257_is_refused():
+@pytest.mark.parametrize("ny,nx", [(300, 300), (512, 512), (512, 96)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_fft_size_1024_matches_oracle(ny, nx, prec):
+    from paper_2101_11680_amd import ctof as c
+    g = _geom(ny, nz=2, nt=8, nx=nx)
+    F = oop.FFTOperator(okernel.tabulate(g))
+    tol = {"fp64": 1e-12, "fp32": 1e-5}[prec]
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    k = c.tabulate(g, c.PRECISIONS[prec])
+    assert k.info.p == 1024
+    rng = np.random.default_rng(ny + nx)
+    mu = rng.uniform(0.0, 0.05, (g.nz, ny, nx))
+    r = rng.standard_normal((g.nt, ny, nx))
+    m = to_np(c.forward(k, torch.tensor(mu, dtype=dt, device="cuda")))
+    a = to_np(c.adjoint(k, torch.tensor(r, dtype=dt, device="cuda")))
+    em, ea = rel_l2(m, F.forward(mu)), rel_l2(a, F.adjoint(r))
+    print(f"{ny}x{nx} {prec}: forward {em:.2e} adjoint {ea:.2e}")
+    assert em <= tol and ea <= tol
+    if prec == "fp64" and nx == ny == 300:
+        d = F.forward(mu)
+        LA = osolver.power_iteration(F, 20)
+        L, lam = osolver.step_constants(LA)
+        ref, _ = osolver.fista(F, d, L, lam, 8)
+        got, _, _ = c.reconstruct(k, torch.tensor(d, device="cuda"), max_iter=8, lam=lam, lipschitz=L)
+        assert rel_l2(to_np(got), ref) <= 1e-10
+
+
+def test_side_513_is_refused():
     from paper_2101_11680_amd import ctof as c
     with pytest.raises(c.CtofError) as e:
-        c.tabulate(_geom(257), c.FP32)
+        c.tabulate(_geom(513), c.FP32)
     assert e.value.status == -5
+    with pytest.raises(c.CtofError):
+        c.tabulate(_geom(8, nx=513), c.FP32)
