@@ -70,7 +70,7 @@ typedef enum {
  * Scan geometry and background optics (section "Confocal ToF-DOT": a
  * collocated source/detector pair scanned over an ny x nx grid; the voxel
  * grid is the scan grid, aligned, one voxel layer per entry of z_mm).
- *   nx, ny            scan points per row and rows, 1..512 each
+ *   nx, ny            scan points per row and rows, 1..1024 each
  *                     (CTOF_EUNSUPPORTED above); spatial arrays are
  *                     [..][ny][nx]; both lateral axes use the FFT size of
  *                     the longer side.  Source multiplexing needs nx == ny

@@ -117,7 +117,7 @@ ctof_status check_geometry(const ctof_geometry *g, ctof::TabGeom *tg, ctof::Laye
   const double total = (double)g->nz * g->nx * g->ny * (double)g->nt;
   if (total > 9.0e18) return set_error(CTOF_EINVAL, "nz*ny*nx*nt overflows");
   if (g->nx > ctof::kMaxN || g->ny > ctof::kMaxN)
-    return set_error(CTOF_EUNSUPPORTED, "a scan side above %d needs an FFT size above 1024", ctof::kMaxN);
+    return set_error(CTOF_EUNSUPPORTED, "a scan side above %d needs an FFT size above 2048", ctof::kMaxN);
   if (g->nz > ctof::kMaxLayers) return set_error(CTOF_EUNSUPPORTED, "nz > %d", ctof::kMaxLayers);
   if (g->nt > (1 << 20)) return set_error(CTOF_EUNSUPPORTED, "nt > 2^20");
   if (tg) {

@@ -9,7 +9,7 @@
 
 namespace ctof {
 
-constexpr int kMaxN = 512;      // largest scan side (FFT size <= 1024)
+constexpr int kMaxN = 1024;     // largest scan side (FFT size <= 2048)
 constexpr int kMaxLayers = 256; // layer depths travel as a kernel argument
 constexpr int kMinP = 16;       // smallest FFT size used
 constexpr int kMaxVol = 64;     // volumes of one shape class per batched launch

@@ -350,6 +350,117 @@ col_pass_lds_kernel(int ny, int B, const T *__restrict__ in, T *__restrict__ out
   }
 }
 
+// Length-64 DFTs in place on 32 blocks of 64 consecutive rows (block s
+// covers rows 64 s .. 64 s + 63), BB planes each, natural order in and out,
+// as two radix-8 steps; W_64^m is entry (P/64) m of the length-P table.
+// Every thread keeps at most two units of the second step in registers.
+template <typename T, int P, int BB, int DIR>
+__device__ __forceinline__ void dft64_blocks(T *wr, T *wi, const T *twc, const T *tws) {
+  constexpr int ld = BB + 1;
+  constexpr int NU = 32 * 8 * BB;  // (block, n2 or k1, plane) units of each step
+  constexpr int NT = 512;
+  static_assert(NU <= 2 * NT, "two units per thread");
+  const int tid = threadIdx.x;
+  for (int u = tid; u < NU; u += NT) {
+    const int b = u % BB, n2 = (u / BB) % 8, sb = u / (8 * BB);
+    T xr[8], xi[8];
+#pragma unroll
+    for (int n1 = 0; n1 < 8; ++n1) {
+      xr[n1] = wr[(64 * sb + 8 * n1 + n2) * ld + b];
+      xi[n1] = wi[(64 * sb + 8 * n1 + n2) * ld + b];
+    }
+    dft_reg<T, 8, DIR>(xr, xi);
+#pragma unroll
+    for (int k1 = 0; k1 < 8; ++k1) {
+      T yr = xr[k1], yi = xi[k1];
+      if (k1 != 0) {
+        const int m = (n2 * k1 * (P / 64)) & (P - 1);
+        const T c = twc[m], sn = (T)DIR * tws[m];
+        const T tr = yr * c - yi * sn;
+        yi = yr * sn + yi * c;
+        yr = tr;
+      }
+      wr[(64 * sb + 8 * k1 + n2) * ld + b] = yr;
+      wi[(64 * sb + 8 * k1 + n2) * ld + b] = yi;
+    }
+  }
+  __syncthreads();
+  T zr[2][8], zi[2][8];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int u = tid + h * NT;
+    if (u < NU) {
+      const int b = u % BB, k1 = (u / BB) % 8, sb = u / (8 * BB);
+#pragma unroll
+      for (int n2 = 0; n2 < 8; ++n2) {
+        zr[h][n2] = wr[(64 * sb + 8 * k1 + n2) * ld + b];
+        zi[h][n2] = wi[(64 * sb + 8 * k1 + n2) * ld + b];
+      }
+      dft_reg<T, 8, DIR>(zr[h], zi[h]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int u = tid + h * NT;
+    if (u < NU) {
+      const int b = u % BB, k1 = (u / BB) % 8, sb = u / (8 * BB);
+#pragma unroll
+      for (int k2 = 0; k2 < 8; ++k2) {
+        wr[(64 * sb + k1 + 8 * k2) * ld + b] = zr[h][k2];
+        wi[(64 * sb + k1 + 8 * k2) * ld + b] = zi[h][k2];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Column pass for FFT size 2048: 32 x 64 through LDS (a radix-32 step with
+// twiddles, then the 64-point blocks of dft64_blocks); output row
+// r = k1 + 32 k2 sits in LDS row 64 k1 + k2.
+template <typename T, int BB, bool INV>
+__global__ void __launch_bounds__(512)
+col_pass_2048_kernel(int ny, int B, const T *__restrict__ in, T *__restrict__ out, int ppv,
+                     const int *__restrict__ active) {
+  constexpr int P = 2048;
+  constexpr int DIR = INV ? 1 : -1;
+  constexpr int ld = BB + 1;
+  constexpr int NT = 512;
+  __shared__ T wr[P * ld], wi[P * ld];
+  __shared__ T twc[P], tws[P];
+  const int ky = blockIdx.x;
+  const int b0 = blockIdx.y * BB;
+  if (active != nullptr && active[b0 / ppv] == 0) return;  // frozen volume
+  const int rows_in = INV ? P : ny;
+  const int rows_out = INV ? ny : P;
+  const int tid = threadIdx.x;
+  build_twiddles<T, P>(twc, tws);
+  const T *src = in + (size_t)ky * rows_in * 2 * B + b0;
+#pragma unroll 4
+  for (int u = tid; u < P * BB; u += NT) {
+    const int b = u % BB, row = u / BB;
+    T xr = (T)0, xi = (T)0;
+    if (row < rows_in) {
+      xr = src[((size_t)row * 2) * B + b];
+      xi = src[((size_t)row * 2 + 1) * B + b];
+    }
+    wr[row * ld + b] = xr;
+    wi[row * ld + b] = xi;
+  }
+  __syncthreads();
+  dft_stage1<T, 32, 64, BB, DIR>(wr, wi, ld, twc, tws, 1, P - 1);
+  __syncthreads();
+  dft64_blocks<T, P, BB, DIR>(wr, wi, twc, tws);
+  T *dst = out + (size_t)ky * rows_out * 2 * B + b0;
+#pragma unroll 4
+  for (int u = tid; u < rows_out * BB; u += NT) {
+    const int b = u % BB, r = u / BB;
+    const int lr = 64 * (r & 31) + (r >> 5);
+    dst[((size_t)r * 2) * B + b] = wr[lr * ld + b];
+    dst[((size_t)r * 2 + 1) * B + b] = wi[lr * ld + b];
+  }
+}
+
 // ---- row pass --------------------------------------------------------------------
 // One block per (scan row i, BB planes): c2r along ky, crop, pointwise step,
 // pad, r2c.  A real DFT of length P is a complex DFT of length H = P/2 on
@@ -582,7 +693,16 @@ template <typename T, int P>
 hipError_t col_dispatch(const Dims &d, int B, bool inverse, const T *in, T *out, hipStream_t st,
                         int ppv, int bb, const int *active) {
   ppv = ppv ? ppv : B;
-  if constexpr (P > 512) {
+  if constexpr (P == 2048) {
+    // three-stage column DFT, the whole block in LDS: 4 FP32 or 2 FP64 planes
+    constexpr int BB = sizeof(T) == 8 ? 2 : 4;
+    dim3 grid((unsigned)(d.h + 1), (unsigned)(B / BB));
+    if (inverse)
+      hipLaunchKernelGGL((col_pass_2048_kernel<T, BB, true>), grid, dim3(512), 0, st, d.ny, B, in, out, ppv, active);
+    else
+      hipLaunchKernelGGL((col_pass_2048_kernel<T, BB, false>), grid, dim3(512), 0, st, d.ny, B, in, out, ppv, active);
+    return hipGetLastError();
+  } else if constexpr (P > 512) {
     // the whole column block lives in LDS: 16 FP32 or 4 FP64 planes fit
     if constexpr (sizeof(T) == 8) return col_dispatch_bb<T, P, 4>(d, B, inverse, in, out, st, ppv, active);
     else return col_dispatch_bb<T, P, 16>(d, B, inverse, in, out, st, ppv, active);
@@ -631,6 +751,7 @@ hipError_t launch_col_pass(const Dims &d, int B, bool inverse, const T *in, T *o
     case 256: return col_dispatch<T, 256>(d, B, inverse, in, out, st, ppv, bb, active);
     case 512: return col_dispatch<T, 512>(d, B, inverse, in, out, st, ppv, bb, active);
     case 1024: return col_dispatch<T, 1024>(d, B, inverse, in, out, st, ppv, bb, active);
+    case 2048: return col_dispatch<T, 2048>(d, B, inverse, in, out, st, ppv, bb, active);
     default: return hipErrorInvalidValue;
   }
 }
@@ -645,6 +766,7 @@ hipError_t launch_row_pass(const Dims &d, const RowArgs &a, hipStream_t st) {
     case 256: return row_dispatch<T, 256>(d, a, st);
     case 512: return row_dispatch<T, 512>(d, a, st);
     case 1024: return row_dispatch<T, 1024>(d, a, st);
+    case 2048: return row_dispatch<T, 2048>(d, a, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -76,8 +76,8 @@ def test_kernel_bytes_sizes(ctof):
     (dict(mus_prime_per_mm=0.0), "CTOF_EINVAL"),
     (dict(mua_per_mm=0.0), "CTOF_EINVAL"),
     (dict(n_medium=0.9), "CTOF_EINVAL"),
-    (dict(nx=513, ny=513), "CTOF_EUNSUPPORTED"),
-    (dict(nx=16, ny=513), "CTOF_EUNSUPPORTED"),
+    (dict(nx=1025, ny=1025), "CTOF_EUNSUPPORTED"),
+    (dict(nx=16, ny=1025), "CTOF_EUNSUPPORTED"),
 ])
 def test_geometry_validation(ctof, bad, status):
     with pytest.raises(ctof.CtofError) as ei:

@@ -1,9 +1,10 @@
-"""Scan sides above 128 (FFT sizes 512 and 1024: radix-32 column stages with
-the column DFT held in LDS) against the FP64 oracle: forward and adjoint in
-FP64, FP32 and BF16 hi+lo, a short FISTA run in FP64, FP64 kernel values
-before the transform, and batched solves.  Sides 129 (the smallest with
-P = 512, so half of every column is padding), 200, 256, 300 (P = 1024),
-512 (the largest supported) and a 512 x 96 rectangle are covered; 513 is
+"""Scan sides above 128 (FFT sizes 512, 1024 and 2048: radix-32 column
+stages with the column DFT held in LDS, three stages at 2048) against the
+FP64 oracle: forward and adjoint in FP64, FP32 and BF16 hi+lo, short FISTA
+runs in FP64, FP64 kernel values before the transform, and batched solves.
+Sides 129 (the smallest with P = 512, so half of every column is padding),
+200, 256, 300 (P = 1024), 512, 600 (P = 2048), 1024 (the largest
+supported) and the rectangles 512 x 96 and 40 x 1024 are covered; 1025 is
 refused.
 """
 
@@ -101,16 +102,17 @@ def test_batched_equals_single_at_200():
         assert rel_l2(to_np(mub), to_np(mu1)) <= 1e-6
 
 
-@pytest.mark.parametrize("ny,nx", [(300, 300), (512, 512), (512, 96)])
+@pytest.mark.parametrize("ny,nx,p", [(300, 300, 1024), (512, 512, 1024), (512, 96, 1024), (600, 600, 2048),
+                                    (1024, 1024, 2048), (40, 1024, 2048)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_fft_size_1024_matches_oracle(ny, nx, prec):
+def test_fft_sizes_1024_2048_match_oracle(ny, nx, p, prec):
     from paper_2101_11680_amd import ctof as c
     g = _geom(ny, nz=2, nt=8, nx=nx)
     F = oop.FFTOperator(okernel.tabulate(g))
     tol = {"fp64": 1e-12, "fp32": 1e-5}[prec]
     dt = torch.float64 if prec == "fp64" else torch.float32
     k = c.tabulate(g, c.PRECISIONS[prec])
-    assert k.info.p == 1024
+    assert k.info.p == p
     rng = np.random.default_rng(ny + nx)
     mu = rng.uniform(0.0, 0.05, (g.nz, ny, nx))
     r = rng.standard_normal((g.nt, ny, nx))
@@ -119,7 +121,7 @@ def test_fft_size_1024_matches_oracle(ny, nx, prec):
     em, ea = rel_l2(m, F.forward(mu)), rel_l2(a, F.adjoint(r))
     print(f"{ny}x{nx} {prec}: forward {em:.2e} adjoint {ea:.2e}")
     assert em <= tol and ea <= tol
-    if prec == "fp64" and nx == ny == 300:
+    if prec == "fp64" and nx == ny and nx in (300, 600):
         d = F.forward(mu)
         LA = osolver.power_iteration(F, 20)
         L, lam = osolver.step_constants(LA)
@@ -128,10 +130,10 @@ def test_fft_size_1024_matches_oracle(ny, nx, prec):
         assert rel_l2(to_np(got), ref) <= 1e-10
 
 
-def test_side_513_is_refused():
+def test_side_1025_is_refused():
     from paper_2101_11680_amd import ctof as c
     with pytest.raises(c.CtofError) as e:
-        c.tabulate(_geom(513), c.FP32)
+        c.tabulate(_geom(1025), c.FP32)
     assert e.value.status == -5
     with pytest.raises(c.CtofError):
-        c.tabulate(_geom(8, nx=513), c.FP32)
+        c.tabulate(_geom(8, nx=1025), c.FP32)
