@@ -73,7 +73,7 @@ typedef enum {
  *   nx, ny            scan points per row and rows, 1..1024 each
  *                     (CTOF_EUNSUPPORTED above); spatial arrays are
  *                     [..][ny][nx]; both lateral axes use the FFT size of
- *                     the longer side.  Source multiplexing needs nx == ny
+ *                     the longer side
  *   pitch_mm          lateral pitch (> 0), equal in x and y
  *   nz, z_mm          number of layers (>= 1) and a HOST array of layer
  *                     centre depths, strictly increasing, > 0
@@ -206,35 +206,35 @@ ctof_status ctof_adjoint(ctof_kernel k, const void *r_dev, void *g_dev, void *ws
  * tile_y; the paper's 8 x 8 source array is one tile of 64) and the same S
  * (rows x P) combines the P transients of every tile in every time bin:
  *     y[t][i][g] = sum_j S[i][j] m[t][gy*tile_y + jy][gx*tile_x + jx]
- * with tile g = gy * (n / tile_x) + gx and position j = jy * tile_x + jx.
+ * with tile g = gy * (nx / tile_x) + gx and position j = jy * tile_x + jx.
  * S may be any matrix: a +-1 Hadamard matrix (y = H m), its on/off pattern
  * pair stacked as a 2P x P 0/1 matrix, a selection, ...
  * ===================================================================== */
 
 typedef struct {
-  int32_t tile_x, tile_y;  /* tile of scan positions; both divide n */
+  int32_t tile_x, tile_y;  /* tile of scan positions; tile_x divides nx, tile_y divides ny */
   int32_t rows;            /* M, measurements per tile and bin (1..128); P = tile_x * tile_y <= 128;
-                              m [nt][n][n] and y [nt][rows][ntiles] must each be below 2 GiB */
+                              m [nt][ny][nx] and y [nt][rows][ntiles] must each be below 2 GiB */
   const void *s_dev;       /* S [rows][P], row-major, device memory, element type of the data */
 } ctof_mux;
 
 /*
- * y = S m:  m_dev [nt][n][n]  ->  y_dev [nt][rows][ntiles], ntiles =
- * (n / tile_x) * (n / tile_y), element type of k's precision.  The buffers
+ * y = S m:  m_dev [nt][ny][nx]  ->  y_dev [nt][rows][ntiles], ntiles =
+ * (nx / tile_x) * (ny / tile_y), element type of k's precision.  The buffers
  * must not overlap.  Asynchronous.  The products run on the matrix cores
  * (16x16x4 MFMA in the data's precision; S staged in LDS in FP32).
  */
 ctof_status ctof_mux_forward(ctof_kernel k, const ctof_mux *mux, const void *m_dev, void *y_dev,
                              hipStream_t stream);
 
-/* m = S^T y:  y_dev [nt][rows][ntiles]  ->  m_dev [nt][n][n] (every
+/* m = S^T y:  y_dev [nt][rows][ntiles]  ->  m_dev [nt][ny][nx] (every
  * element written).  The buffers must not overlap.  Asynchronous. */
 ctof_status ctof_mux_adjoint(ctof_kernel k, const ctof_mux *mux, const void *y_dev, void *m_dev,
                              hipStream_t stream);
 
 /*
  * Gradient input of the multiplexed data term, fused in one pass over m:
- * r = S^T (S m - y) (y_dev NULL: r = S^T S m), with m_dev, r_dev [nt][n][n]
+ * r = S^T (S m - y) (y_dev NULL: r = S^T S m), with m_dev, r_dev [nt][ny][nx]
  * (r_dev may equal m_dev; no other overlap) and y_dev [nt][rows][ntiles].
  * fit_dev: NULL, or a device double receiving 1/2 ||S m - y||^2 (FP64
  * per-block partial sums added in a fixed order).  ws_dev: at least

@@ -321,10 +321,10 @@ struct Engine {
 // Multiplexing descriptor -> kernel arguments (sizes from the kernel handle).
 ctof_status make_mux(const ctof_kernel_s *k, const ctof_mux *mx, ctof::MuxArgs *a) {
   if (!mx) return set_error(CTOF_EINVAL, "mux is NULL");
-  if (k->dims.nx != k->dims.ny) return set_error(CTOF_EUNSUPPORTED, "multiplexing needs a square scan grid");
-  const int n = k->dims.n;
-  if (mx->tile_x < 1 || mx->tile_y < 1 || n % mx->tile_x != 0 || n % mx->tile_y != 0)
-    return set_error(CTOF_EINVAL, "mux tile %dx%d must divide the scan side %d", mx->tile_x, mx->tile_y, n);
+  const int ny = k->dims.ny, nx = k->dims.nx;
+  if (mx->tile_x < 1 || mx->tile_y < 1 || nx % mx->tile_x != 0 || ny % mx->tile_y != 0)
+    return set_error(CTOF_EINVAL, "mux tile %dx%d must divide the %dx%d scan (columns x rows)", mx->tile_x,
+                     mx->tile_y, nx, ny);
   const int P = mx->tile_x * mx->tile_y;
   if (P > ctof::kMuxMaxDim)
     return set_error(CTOF_EINVAL, "mux tile of %d positions exceeds %d", P, ctof::kMuxMaxDim);
@@ -334,17 +334,18 @@ ctof_status make_mux(const ctof_kernel_s *k, const ctof_mux *mx, ctof::MuxArgs *
   if (!mx->s_dev || (reinterpret_cast<uintptr_t>(mx->s_dev) % es) != 0)
     return set_error(CTOF_EINVAL, "mux s_dev is NULL or not aligned to its element");
   std::memset(a, 0, sizeof(*a));
-  a->n = n;
+  a->ny = ny;
+  a->nx = nx;
   a->nt = k->dims.nt;
   a->tx = mx->tile_x;
   a->ty = mx->tile_y;
   a->M = mx->rows;
   a->P = P;
-  a->ntx = n / mx->tile_x;
-  a->ntiles = a->ntx * (n / mx->tile_y);
+  a->ntx = nx / mx->tile_x;
+  a->ntiles = a->ntx * (ny / mx->tile_y);
   a->S = mx->s_dev;
   if ((long long)a->nt * a->M * a->ntiles * (long long)es >= (1LL << 31) ||
-      (long long)a->nt * n * n * (long long)es >= (1LL << 31))
+      (long long)a->nt * ny * nx * (long long)es >= (1LL << 31))
     return set_error(CTOF_EINVAL, "multiplexed arrays must stay below 2 GiB");
   return CTOF_OK;
 }

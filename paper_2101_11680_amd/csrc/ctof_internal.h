@@ -179,11 +179,11 @@ enum { MUX_FWD = 0, MUX_ADJ = 1, MUX_NORMAL = 2 };
 constexpr int kMuxMaxDim = 128;  // largest M and P
 
 struct MuxArgs {
-  int n, nt, tx, ty, M, P, ntx, ntiles;
+  int ny, nx, nt, tx, ty, M, P, ntx, ntiles;  // scan rows and columns; tiles per row, tiles
   const void *S;
-  const void *in;    // MUX_FWD, MUX_NORMAL: m [nt][n][n];  MUX_ADJ: y [nt][M][ntiles]
+  const void *in;    // MUX_FWD, MUX_NORMAL: m [nt][ny][nx];  MUX_ADJ: y [nt][M][ntiles]
   const void *y;     // MUX_NORMAL: y [nt][M][ntiles] or NULL
-  void *out;         // MUX_FWD: y;  otherwise [nt][n][n]
+  void *out;         // MUX_FWD: y;  otherwise [nt][ny][nx]
   double *partials;  // MUX_NORMAL: npart pairs (block b's sum at pair b, zeros past the grid), or NULL
   int npart;         // >= the launch's blocks when partials is set
   int sstr;          // set by launch_mux

@@ -74,15 +74,17 @@ __device__ __forceinline__ Column column(const MuxArgs &a, long long c, long lon
     const int t = ci / a.ntiles;
     const int tile = ci - t * a.ntiles;
     const int gy = tile / a.ntx, gx = tile - gy * a.ntx;
-    k.base = ((uint32_t)t * a.n + (uint32_t)(gy * a.ty)) * (uint32_t)a.n + (uint32_t)(gx * a.tx);
+    k.base = ((uint32_t)t * a.ny + (uint32_t)(gy * a.ty)) * (uint32_t)a.nx + (uint32_t)(gx * a.tx);
     k.ybase = (uint32_t)t * (uint32_t)a.M * (uint32_t)a.ntiles + (uint32_t)tile;
   }
   return k;
 }
 
-__device__ __forceinline__ uint32_t pos_off32(int j, int tx, int n) {
+// offset of tile position j (row j / tx, column j % tx) from the tile origin
+// on a grid of nx columns
+__device__ __forceinline__ uint32_t pos_off32(int j, int tx, int nx) {
   const int jy = j / tx;
-  return (uint32_t)(jy * n + (j - jy * tx));
+  return (uint32_t)(jy * nx + (j - jy * tx));
 }
 
 template <typename V, typename T>
@@ -157,13 +159,13 @@ mux_kernel(MuxArgs a) {
           // P is a multiple of 4: a quad is wholly inside or outside; loads
           // outside read element 0 and are discarded (no branch)
           const bool in = cl.valid && j0 < P;
-          const quad_t v = ld<quad_t>(m, in ? cl.base + pos_off32(j0, a.tx, a.n) : 0u);
+          const quad_t v = ld<quad_t>(m, in ? cl.base + pos_off32(j0, a.tx, a.nx) : 0u);
           xb[b] = in ? v : quad_t(0);
         } else {
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const bool in = cl.valid && j0 + e < P;
-            const T v = ld<T>(m, in ? cl.base + pos_off32(j0 + e, a.tx, a.n) : 0u);
+            const T v = ld<T>(m, in ? cl.base + pos_off32(j0 + e, a.tx, a.nx) : 0u);
             xb[b][e] = in ? v : T(0);
           }
         }
@@ -225,11 +227,11 @@ mux_kernel(MuxArgs a) {
         for (int jt = 0; jt < KB1; ++jt) {
           const int j0 = 16 * jt + 4 * g;
           if constexpr (VEC) {
-            if (j0 < P) st<quad_t>(out, cl.base + pos_off32(j0, a.tx, a.n), rv[jt]);
+            if (j0 < P) st<quad_t>(out, cl.base + pos_off32(j0, a.tx, a.nx), rv[jt]);
           } else {
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-              if (j0 + r < P) st<T>(out, cl.base + pos_off32(j0 + r, a.tx, a.n), rv[jt][r]);
+              if (j0 + r < P) st<T>(out, cl.base + pos_off32(j0 + r, a.tx, a.nx), rv[jt][r]);
           }
         }
       }
@@ -270,7 +272,7 @@ inline int lds_stride(int M, int P) {
 
 template <typename T, int MODE, int KB1>
 hipError_t launch_one(const MuxArgs &a, int blocks, size_t lds, hipStream_t st) {
-  if ((a.tx & 3) == 0 && (a.n & 3) == 0)
+  if ((a.tx & 3) == 0 && (a.nx & 3) == 0)
     hipLaunchKernelGGL((mux_kernel<T, MODE, KB1, true>), dim3((unsigned)blocks), dim3(64 * Mma<T>::kWaves), lds, st,
                        a);
   else

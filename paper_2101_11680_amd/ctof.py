@@ -388,16 +388,18 @@ class Mux:
             raise TypeError(f"S must be {_dtype(k.precision)} for this kernel")
         return _Mux(self.tile_x, self.tile_y, self.rows, self.S.data_ptr())
 
-    def ntiles(self, n: int) -> int:
-        return (n // self.tile_x) * (n // self.tile_y)
+    def ntiles(self, ny: int, nx: int | None = None) -> int:
+        """Tiles of an ny x nx scan (nx defaults to ny)."""
+        nx = ny if nx is None else nx
+        return (nx // self.tile_x) * (ny // self.tile_y)
 
 
 def mux_forward(k: Kernel, mux: Mux, m, out=None, stream=None):
-    """y = S m per tile and bin: m [nt][n][n] -> y [nt][rows][ntiles]."""
+    """y = S m per tile and bin: m [nt][ny][nx] -> y [nt][rows][ntiles]."""
     torch = _torch()
     i = k.info
     m = _contig(m, _dtype(k.precision), (i.nt, i.ny, i.nx))
-    shape = (i.nt, mux.rows, mux.ntiles(i.n))
+    shape = (i.nt, mux.rows, mux.ntiles(i.ny, i.nx))
     if out is None:
         out = torch.empty(shape, dtype=m.dtype, device=m.device)
     out = _contig(out, m.dtype, shape)
@@ -408,10 +410,10 @@ def mux_forward(k: Kernel, mux: Mux, m, out=None, stream=None):
 
 
 def mux_adjoint(k: Kernel, mux: Mux, y, out=None, stream=None):
-    """m = S^T y: y [nt][rows][ntiles] -> m [nt][n][n]."""
+    """m = S^T y: y [nt][rows][ntiles] -> m [nt][ny][nx]."""
     torch = _torch()
     i = k.info
-    y = _contig(y, _dtype(k.precision), (i.nt, mux.rows, mux.ntiles(i.n)))
+    y = _contig(y, _dtype(k.precision), (i.nt, mux.rows, mux.ntiles(i.ny, i.nx)))
     if out is None:
         out = torch.empty((i.nt, i.ny, i.nx), dtype=y.dtype, device=y.device)
     out = _contig(out, y.dtype, (i.nt, i.ny, i.nx))
@@ -428,7 +430,7 @@ def mux_normal(k: Kernel, mux: Mux, m, y=None, out=None, fit: bool = False, stre
     i = k.info
     m = _contig(m, _dtype(k.precision), (i.nt, i.ny, i.nx))
     if y is not None:
-        y = _contig(y, m.dtype, (i.nt, mux.rows, mux.ntiles(i.n)))
+        y = _contig(y, m.dtype, (i.nt, mux.rows, mux.ntiles(i.ny, i.nx)))
     if out is None:
         out = torch.empty_like(m)
     out = _contig(out, m.dtype, (i.nt, i.ny, i.nx))
@@ -470,7 +472,7 @@ def reconstruct(k: Kernel, d, mu=None, max_iter: int = 200, lam: float = -1.0,
     if mux is None:
         d = _contig(d, _dtype(k.precision), (i.nt, i.ny, i.nx))
     else:
-        d = _contig(d, _dtype(k.precision), (i.nt, mux.rows, mux.ntiles(i.n)))
+        d = _contig(d, _dtype(k.precision), (i.nt, mux.rows, mux.ntiles(i.ny, i.nx)))
     if mu is None:
         mu = torch.empty((i.nz, i.ny, i.nx), dtype=d.dtype, device=d.device)
         warm_start = False

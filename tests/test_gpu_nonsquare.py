@@ -4,15 +4,18 @@ to twice its own side; the library pads both to the FFT size of the longer
 side).  Forward and adjoint in FP64, FP32 and BF16 hi+lo for wide, tall,
 odd and one-row grids; FISTA in FP64; a batch mixing a rectangular and a
 square class; the transposed scan giving the transposed result; and
-multiplexing refusing a rectangular grid.
+source multiplexing with tiles that divide each axis (products and a
+multiplexed FISTA run against the oracle's rectangular tiling).
 """
 
 import numpy as np
 import pytest
 
 from oracle import kernel as okernel
+from oracle import mux as omux
 from oracle import operator as oop
 from oracle import solver as osolver
+from synth import mux as smux
 from synth.workloads import Geometry, even_layers
 from tests.gpu_common import rel_l2, to_np
 
@@ -102,12 +105,47 @@ def test_batched_rectangular_and_square_classes():
         assert rel_l2(to_np(mu), to_np(mu1)) <= 1e-6
 
 
-def test_multiplexing_needs_a_square_grid():
+@pytest.mark.parametrize("ny,nx,tx,ty,M", [(8, 16, 4, 2, 12), (12, 8, 4, 4, 32), (6, 10, 5, 3, 15)])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_multiplexing_on_rectangular_grids(ny, nx, tx, ty, M, prec):
+    from paper_2101_11680_amd import ctof as c
+    g = _geom(ny, nx)
+    tol = 1e-13 if prec == "fp64" else 1e-6
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    k = c.tabulate(g, c.PRECISIONS[prec])
+    rng = np.random.default_rng(ny * 31 + nx)
+    S = rng.standard_normal((M, tx * ty))
+    mx = c.Mux(torch.tensor(S, dtype=dt, device="cuda"), tx, ty)
+    ntiles = (nx // tx) * (ny // ty)
+    assert mx.ntiles(ny, nx) == ntiles
+    m = rng.standard_normal((g.nt, ny, nx))
+    yy = rng.standard_normal((g.nt, M, ntiles))
+    y = to_np(c.mux_forward(k, mx, torch.tensor(m, dtype=dt, device="cuda")))
+    assert rel_l2(y, omux.forward(S, m, tx, ty)) <= tol
+    back = to_np(c.mux_adjoint(k, mx, torch.tensor(yy, dtype=dt, device="cuda")))
+    assert rel_l2(back, omux.adjoint(S, yy, tx, ty, ny, nx)) <= tol
+    r = to_np(c.mux_normal(k, mx, torch.tensor(m, dtype=dt, device="cuda"), y=torch.tensor(yy, dtype=dt, device="cuda")))
+    assert rel_l2(r, omux.adjoint(S, omux.forward(S, m, tx, ty) - yy, tx, ty, ny, nx)) <= tol
+
+
+def test_multiplexed_fista_fp64_on_a_rectangle():
     from paper_2101_11680_amd import ctof as c
     g = _geom(8, 16)
-    k = c.tabulate(g, c.FP32)
-    S = torch.ones((4, 4), dtype=torch.float32, device="cuda")
-    m = torch.zeros((g.nt, 8, 16), dtype=torch.float32, device="cuda")
-    with pytest.raises(c.CtofError) as e:
-        c.mux_forward(k, c.Mux(S, 2, 2), m)
-    assert e.value.status == -5
+    S = smux.onoff(8)  # 4 x 2 tiles, on/off Hadamard patterns
+    F = oop.FFTOperator(okernel.tabulate(g))
+    Fm = omux.MuxOperator(F, S, 4, 2)
+    mu = np.zeros((g.nz, 8, 16))
+    mu[1, 2:5, 6:11] = 0.03
+    y = Fm.forward(mu) * (1.0 + 0.01 * np.random.default_rng(8).standard_normal(Fm.forward(mu).shape))
+    LA = osolver.power_iteration(Fm, 50)
+    L, lam = osolver.step_constants(LA)
+    ref, hist = osolver.fista(Fm, y, L, lam, 40)
+    k = c.tabulate(g, c.FP64)
+    mx = c.Mux(torch.tensor(S, device="cuda"), 4, 2)
+    got, rep, h = c.reconstruct(k, torch.tensor(y, device="cuda"), max_iter=40, lam=lam, lipschitz=L, mux=mx,
+                                history=True)
+    assert rel_l2(to_np(got), ref) <= 1e-10
+    np.testing.assert_allclose(to_np(h)[:, 1], hist[:, 1], rtol=1e-8, atol=1e-14)
+    with pytest.raises(c.CtofError):  # a tile must divide its axis
+        c.mux_forward(k, c.Mux(torch.tensor(smux.random_matrix(18, 9, 1), device="cuda"), 3, 3),
+                      torch.zeros((g.nt, 8, 16), dtype=torch.float64, device="cuda"))

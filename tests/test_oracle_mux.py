@@ -63,6 +63,25 @@ def test_identity_gather_matches_reshape():
     np.testing.assert_array_equal(np.sort(pos.ravel()), np.arange(n * n))
 
 
+@pytest.mark.parametrize("ny,nx,tx,ty", [(6, 12, 4, 3), (12, 4, 2, 4), (3, 10, 5, 1)])
+def test_rectangular_gather_matches_reshape(ny, nx, tx, ty):
+    # a ny x nx grid: the tiles partition it, and with S = I the forward is
+    # the same reshape gather as on a square grid, tiles row by row
+    rng = np.random.default_rng(ny * 100 + nx)
+    nt = 4
+    m = rng.standard_normal((nt, ny, nx))
+    y = omux.forward(np.eye(tx * ty), m, tx, ty)
+    ref = m.reshape(nt, ny // ty, ty, nx // tx, tx).transpose(0, 1, 3, 2, 4).reshape(nt, -1, ty * tx)
+    np.testing.assert_array_equal(y, ref.transpose(0, 2, 1))
+    pos = omux.tile_positions(ny, tx, ty, nx)
+    np.testing.assert_array_equal(np.sort(pos.ravel()), np.arange(ny * nx))
+    S = rng.standard_normal((7, tx * ty))
+    yy = rng.standard_normal((nt, 7, (nx // tx) * (ny // ty)))
+    lhs = np.vdot(omux.forward(S, m, tx, ty), yy)
+    rhs = np.vdot(m, omux.adjoint(S, yy, tx, ty, ny, nx))
+    assert lhs == pytest.approx(rhs, rel=1e-13)
+
+
 def test_adjoint_identity():
     rng = np.random.default_rng(4)
     nt, n, tx, ty, M = 3, 8, 4, 2, 13
