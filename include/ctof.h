@@ -291,7 +291,9 @@ ctof_status ctof_mux_normal(ctof_kernel k, const ctof_mux *mux, const void *m_de
  *                    becomes S A and A^T S^T (L_A = ||S A||^2, the
  *                    gradient-mapping denominator ||max(0, A^T S^T y)||,
  *                    datafit = 1/2 ||S A mu - y||^2), and no extra
- *                    workspace is needed.  Single-scan solves only.
+ *                    workspace is needed.  In batched solves the same
+ *                    descriptor (S and the tile) applies to every scan,
+ *                    whose grid it must tile; d_dev[i] holds scan i's y.
  */
 typedef struct {
   int32_t max_iter;

@@ -250,7 +250,7 @@ struct Engine {
   hipStream_t st;
   const int *live = nullptr;  // per-volume flags honoured by every launch (batched solves)
   const double *l1dev = nullptr;  // per-layer L1 weights in the workspace when the objective has them
-  const ctof::MuxArgs *mux = nullptr;  // source multiplexing of the measurements (single-scan solves)
+  const ctof::MuxArgs *mux = nullptr;  // source multiplexing of the measurements (Eq. 12), or NULL
 
   const ctof::Dims &dm() const { return k->dims; }
   T *yhat() const { return reinterpret_cast<T *>(ws + L.yhat); }
@@ -478,25 +478,58 @@ std::vector<double> fista_betas(int iters) {
 }
 
 // Bin-side pass of a multiplexed solve (Eq. 12): the spectra in xt back to
-// the histogram m (held in the idle mhat buffer), r = S^T (S m - y) in
-// place (y NULL: r = S^T S m), FP64 half squares of S m - y into
-// `partials` (nblk_t pairs) when given, and r back to spectra in xt.
+// the histograms m_v (held in the idle mhat buffer), r_v = S^T (S m_v - y_v)
+// in place (y NULL: r = S^T S m), FP64 half squares of S m - y into
+// `partials` (nblk_t pairs, each volume's run of nblk_t / nvol in turn) when
+// given, and r back to spectra in xt.  by_counter: inside a captured
+// iteration, partials advance with the device counter and frozen volumes are
+// skipped.
 template <typename T>
-ctof_status enqueue_mux_residual(const Engine<T> &E, const void *y, double *partials) {
+ctof_status enqueue_mux_residual(const Engine<T> &E, const void *const *y, double *partials, bool by_counter) {
+  const ctof::Dims &dm = E.dm();
+  const size_t vt = (size_t)dm.nt * dm.ny * dm.nx;
   ctof::RowArgs a = E.row(ctof::ROW_SPEC_TO_SPATIAL, true);
-  a.sp_out[0] = E.mhat();
+  for (int v = 0; v < E.nvol; ++v) a.sp_out[v] = E.mhat() + (size_t)v * vt;
+  if (by_counter) a.active = E.live;
   HIP_TRY(E.run_row(a));
-  ctof::MuxArgs m = *E.mux;
-  m.in = E.mhat();
-  m.out = E.mhat();
-  m.y = y;
-  m.partials = partials;
-  m.npart = E.L.nblk_t;
-  const int blocks = std::min(ctof::mux_default_blocks(m, sizeof(T) == 8), E.L.nblk_t);
-  HIP_TRY(ctof::launch_mux(ctof::MUX_NORMAL, sizeof(T) == 8, m, blocks, E.st));
+  const int per = E.L.nblk_t / E.nvol;
+  for (int v = 0; v < E.nvol; ++v) {
+    ctof::MuxArgs m = *E.mux;
+    m.in = E.mhat() + (size_t)v * vt;
+    m.out = E.mhat() + (size_t)v * vt;
+    m.y = y ? y[v] : nullptr;
+    m.partials = partials ? partials + 2 * (size_t)v * per : nullptr;
+    m.npart = per;
+    if (by_counter) {
+      m.ctr = E.ctr();
+      m.part_stride = E.L.part_stride;
+      m.active = E.live;
+      m.vol = v;
+    }
+    const int blocks = std::min(ctof::mux_default_blocks(m, sizeof(T) == 8), per);
+    HIP_TRY(ctof::launch_mux(ctof::MUX_NORMAL, sizeof(T) == 8, m, blocks, E.st));
+  }
   ctof::RowArgs b = E.row(ctof::ROW_SPATIAL_TO_SPEC, true);
-  b.sp_in[0] = E.mhat();
+  for (int v = 0; v < E.nvol; ++v) b.sp_in[v] = E.mhat() + (size_t)v * vt;
+  if (by_counter) b.active = E.live;
   HIP_TRY(E.run_row(b));
+  return CTOF_OK;
+}
+
+// S^T y_v of every volume into its histogram slot of mhat (set-up of a
+// multiplexed solve: the gradient-mapping denominator needs A^T S^T y)
+template <typename T>
+ctof_status enqueue_mux_adjoint_data(const Engine<T> &E, const void *const *y, std::vector<const void *> &sty) {
+  const ctof::Dims &dm = E.dm();
+  const size_t vt = (size_t)dm.nt * dm.ny * dm.nx;
+  sty.resize(E.nvol);
+  for (int v = 0; v < E.nvol; ++v) {
+    ctof::MuxArgs a = *E.mux;
+    a.in = y[v];
+    a.out = E.mhat() + (size_t)v * vt;
+    sty[v] = a.out;
+    HIP_TRY(ctof::launch_mux(ctof::MUX_ADJ, sizeof(T) == 8, a, ctof::mux_default_blocks(a, sizeof(T) == 8), E.st));
+  }
   return CTOF_OK;
 }
 
@@ -518,7 +551,7 @@ ctof_status enqueue_power_iteration(const Engine<T> &E1, int iters) {
     HIP_TRY(E1.mu_to_spec(a));
     HIP_TRY(E1.fwd_to_xt());
     if (E1.mux) {
-      if (ctof_status s = enqueue_mux_residual(E1, nullptr, nullptr); s != CTOF_OK) return s;
+      if (ctof_status s = enqueue_mux_residual(E1, nullptr, nullptr, false); s != CTOF_OK) return s;
     } else {
       HIP_TRY(E1.run_row(E1.row(ctof::ROW_PASS, true)));
     }
@@ -554,15 +587,22 @@ ctof_status enqueue_iteration(const Engine<T> &E, const void *const *d, void *co
                               double lam, bool by_counter, int it, double beta) {
   HIP_TRY(E.contract(false));
   HIP_TRY(E.col_t(true));
-  ctof::RowArgs a = E.row(ctof::ROW_RESIDUAL, true);
-  for (int v = 0; v < E.nvol; ++v) a.sp_in[v] = d[v];
-  a.partials = E.part() + (by_counter ? 0 : (size_t)it * E.L.part_stride);
-  if (by_counter) {
-    a.iter_ctr = E.ctr();
-    a.part_stride = E.L.part_stride;
-    a.active = E.live;
+  if (E.mux) {
+    if (ctof_status s = enqueue_mux_residual(E, d, E.part() + (by_counter ? 0 : (size_t)it * E.L.part_stride),
+                                             by_counter);
+        s != CTOF_OK)
+      return s;
+  } else {
+    ctof::RowArgs a = E.row(ctof::ROW_RESIDUAL, true);
+    for (int v = 0; v < E.nvol; ++v) a.sp_in[v] = d[v];
+    a.partials = E.part() + (by_counter ? 0 : (size_t)it * E.L.part_stride);
+    if (by_counter) {
+      a.iter_ctr = E.ctr();
+      a.part_stride = E.L.part_stride;
+      a.active = E.live;
+    }
+    HIP_TRY(E.run_row(a));
   }
-  HIP_TRY(E.run_row(a));
   HIP_TRY(E.col_t(false));
   HIP_TRY(E.contract(true));
   HIP_TRY(E.col_z(true));
@@ -632,7 +672,7 @@ ctof_status enqueue_final_fit(const Engine<T> &E, const void *const *d, void *co
   HIP_TRY(E.mu_to_spec(a));
   HIP_TRY(E.fwd_to_xt());
   if (E.mux) {
-    if (ctof_status s = enqueue_mux_residual(E, d[0], pf); s != CTOF_OK) return s;
+    if (ctof_status s = enqueue_mux_residual(E, d, pf, false); s != CTOF_OK) return s;
   } else {
     ctof::RowArgs b = E.row(ctof::ROW_RESIDUAL, true);
     for (int v = 0; v < E.nvol; ++v) b.sp_in[v] = d[v];
@@ -663,12 +703,9 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
     if (ctof_status s = make_mux(k, opt->mux, &mux); s != CTOF_OK) return s;
     E.mux = &mux;
     // the gradient-mapping denominator needs A^T S^T y: S^T y into mhat first
-    ctof::MuxArgs a = mux;
-    a.in = d;
-    a.out = E.mhat();
-    HIP_TRY(ctof::launch_mux(ctof::MUX_ADJ, sizeof(T) == 8, a, ctof::mux_default_blocks(a, sizeof(T) == 8), st));
-    const void *sty[1] = {E.mhat()};
-    if (ctof_status s = enqueue_gmap0(E, sty); s != CTOF_OK) return s;
+    std::vector<const void *> sty;
+    if (ctof_status s = enqueue_mux_adjoint_data(E, dd, sty); s != CTOF_OK) return s;
+    if (ctof_status s = enqueue_gmap0(E, sty.data()); s != CTOF_OK) return s;
   } else {
     if (ctof_status s = enqueue_gmap0(E, dd); s != CTOF_OK) return s;
   }
@@ -718,7 +755,7 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
     HIP_TRY(mark(it, 1));
     HIP_TRY(E.col_t(true));
     if (E.mux) {
-      if (ctof_status s = enqueue_mux_residual(E, d, pk); s != CTOF_OK) return s;
+      if (ctof_status s = enqueue_mux_residual(E, dd, pk, false); s != CTOF_OK) return s;
     } else {
       ctof::RowArgs a = E.row(ctof::ROW_RESIDUAL, true);
       a.sp_in[0] = d;
@@ -875,8 +912,13 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
   std::vector<Engine<T>> E;
   std::vector<std::vector<const void *>> dv(cls.size());
   std::vector<std::vector<void *>> mv(cls.size());
+  std::vector<ctof::MuxArgs> muxes(cls.size());  // sized once: the engines keep pointers into it
   for (size_t c = 0; c < cls.size(); ++c) {
     E.push_back(Engine<T>{cls[c].k, (int)cls[c].scans.size(), base + cls[c].off, cls[c].L, st});
+    if (opt->mux) {
+      if (ctof_status s = make_mux(cls[c].k, opt->mux, &muxes[c]); s != CTOF_OK) return s;
+      E.back().mux = &muxes[c];
+    }
     if (opt->lambda_l1_z) {
       HIP_TRY(hipMemcpyAsync(E.back().l1(), opt->lambda_l1_z, (size_t)cls[c].k->dims.nz * sizeof(double),
                              hipMemcpyHostToDevice, st));
@@ -890,7 +932,13 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
   // set-up: ||G(0)|| per volume and L_A per class (one vector per class)
   for (size_t c = 0; c < cls.size(); ++c) {
     HIP_TRY(ctof::launch_fill_zero(E[c].scal(), 64 * 8, st));
-    if (ctof_status s = enqueue_gmap0(E[c], dv[c].data()); s != CTOF_OK) return s;
+    if (E[c].mux) {
+      std::vector<const void *> sty;
+      if (ctof_status s = enqueue_mux_adjoint_data(E[c], dv[c].data(), sty); s != CTOF_OK) return s;
+      if (ctof_status s = enqueue_gmap0(E[c], sty.data()); s != CTOF_OK) return s;
+    } else {
+      if (ctof_status s = enqueue_gmap0(E[c], dv[c].data()); s != CTOF_OK) return s;
+    }
     if (opt->lipschitz == 0.0 && !opt->lipschitz_scans) {
       Engine<T> E1 = E[c];
       const bool f64 = E1.k->prec == CTOF_FP64;
@@ -1517,7 +1565,11 @@ ctof_status ctof_reconstruct_batched(int32_t nscan, const ctof_kernel *k, const 
     if (k[i]->prec != prec) return set_error(CTOF_EINVAL, "all handles of a batch need one precision");
     if (!d_dev[i] || !mu_inout_dev[i]) return set_error(CTOF_EINVAL, "device pointer of scan %d is NULL", i);
   }
-  if (opts->mux) return set_error(CTOF_EINVAL, "mux is a single-scan option");
+  if (opts->mux)
+    for (int i = 0; i < nscan; ++i) {
+      ctof::MuxArgs m;
+      if (ctof_status e = make_mux(k[i], opts->mux, &m); e != CTOF_OK) return e;
+    }
   if (opts->max_iter < 1) return set_error(CTOF_EINVAL, "max_iter must be >= 1");
   if (!std::isfinite(opts->lambda_tikhonov)) return set_error(CTOF_EINVAL, "lambda_tikhonov must be finite");
   if (!(std::isfinite(opts->lipschitz) && opts->lipschitz >= 0)) return set_error(CTOF_EINVAL, "lipschitz must be >= 0");

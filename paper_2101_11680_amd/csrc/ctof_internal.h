@@ -187,6 +187,10 @@ struct MuxArgs {
   double *partials;  // MUX_NORMAL: npart pairs (block b's sum at pair b, zeros past the grid), or NULL
   int npart;         // >= the launch's blocks when partials is set
   int sstr;          // set by launch_mux
+  const int *ctr;    // device iteration counter: partials advance by part_stride doubles per count (or NULL)
+  size_t part_stride;
+  const int *active; // per-volume flags: the launch does nothing when active[vol] == 0 (or NULL)
+  int vol;
 };
 
 // Grid of a multiplexing launch (persistent blocks, at most one per compute

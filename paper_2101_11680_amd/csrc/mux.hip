@@ -112,6 +112,7 @@ mux_kernel(MuxArgs a) {
   const T *__restrict__ S = static_cast<const T *>(a.S);
   const int lane = threadIdx.x & 63, g = lane >> 4, i16 = lane & 15;
   const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  if (a.active != nullptr && a.active[a.vol] == 0) return;  // frozen volume (uniform)
   const int M = a.M, P = a.P, MT = (M + 15) / 16;
   const int str = a.sstr;
   if constexpr (kLds) {
@@ -249,9 +250,10 @@ mux_kernel(MuxArgs a) {
       if (threadIdx.x == 0) {
         double tot = 0.0;
         for (int w = 0; w < kWaves; ++w) tot += red[w];
+        double *part = a.partials + (a.ctr ? (size_t)(*a.ctr) * a.part_stride : 0);
         for (int b = blockIdx.x; b < a.npart; b += gridDim.x) {
-          a.partials[2 * (size_t)b] = b == (int)blockIdx.x ? tot : 0.0;
-          a.partials[2 * (size_t)b + 1] = 0.0;
+          part[2 * (size_t)b] = b == (int)blockIdx.x ? tot : 0.0;
+          part[2 * (size_t)b + 1] = 0.0;
         }
       }
     }

@@ -503,11 +503,12 @@ def _report(rep) -> Report:
 
 def reconstruct_batched(kernels, ds, mus=None, max_iter: int = 200, lam=-1.0, lipschitz=0.0,
                         power_iters: int = 50, rel_tol: float = 0.0, check_every: int = 10,
-                        warm_start: bool = False, l1=None, stream=None):
+                        warm_start: bool = False, l1=None, mux: Optional[Mux] = None, stream=None):
     """FISTA for many scans at once; scans sharing a Kernel object form one
     shape class.  lam / lipschitz: one value for all scans or one per scan
     (both sequences, then every scan's pair is used as given).  warm_start as
-    in reconstruct.  Returns (list of mu, list of Report)."""
+    in reconstruct.  mux: one Mux for every scan, each ds[i] then holding
+    scan i's multiplexed measurements.  Returns (list of mu, list of Report)."""
     torch = _torch()
     n = len(ds)
     if len(kernels) != n:
@@ -518,7 +519,10 @@ def reconstruct_batched(kernels, ds, mus=None, max_iter: int = 200, lam=-1.0, li
     outs = []
     for k, d, mu in zip(kernels, ds, mus):
         i = k.info
-        _contig(d, _dtype(k.precision), (i.nt, i.ny, i.nx))
+        if mux is None:
+            _contig(d, _dtype(k.precision), (i.nt, i.ny, i.nx))
+        else:
+            _contig(d, _dtype(k.precision), (i.nt, mux.rows, mux.ntiles(i.ny, i.nx)))
         if mu is None:
             mu = torch.empty((i.nz, i.ny, i.nx), dtype=d.dtype, device=d.device)
         outs.append(_contig(mu, d.dtype, (i.nz, i.ny, i.nx)))
@@ -530,14 +534,17 @@ def reconstruct_batched(kernels, ds, mus=None, max_iter: int = 200, lam=-1.0, li
     ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=ds[0].device)
     per_scan = not isinstance(lipschitz, (int, float))
     l1a = _l1_array(l1, kernels[0].info.nz)
+    mdesc = mux.desc(kernels[0]) if mux is not None else None
+    mptr_desc = ctypes.pointer(mdesc) if mdesc is not None else None
     if per_scan:
         la = (ctypes.c_double * n)(*[float(x) for x in lipschitz])
         lb = (ctypes.c_double * n)(*[float(x) for x in lam])
         opts = _SolverOpts(int(max_iter), 0.0, 0.0, int(power_iters), float(rel_tol), int(check_every),
-                           int(warm_start), None, 0, la, lb, l1a)
+                           int(warm_start), None, 0, la, lb, l1a, mptr_desc)
     else:
         opts = _SolverOpts(int(max_iter), float(lam), float(lipschitz), int(power_iters),
-                           float(rel_tol), int(check_every), int(warm_start), None, 0, None, None, l1a)
+                           float(rel_tol), int(check_every), int(warm_start), None, 0, None, None, l1a,
+                           mptr_desc)
     reps = (_SolverReport * n)()
     _check(lib().ctof_reconstruct_batched(n, handles, dptr, mptr, ctypes.byref(opts), reps,
                                           ws.data_ptr(), ws.numel(), _stream_ptr(stream)))

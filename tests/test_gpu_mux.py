@@ -207,19 +207,43 @@ def test_mux_argument_checks():
         c.mux_forward(k, c.Mux(torch.zeros((129, 4), dtype=torch.float32, device="cuda"), 2, 2), m)
     with pytest.raises(TypeError):  # element type of the kernel
         c.mux_forward(k, c.Mux(torch.zeros((4, 4), dtype=torch.float64, device="cuda"), 2, 2), m)
-    mx = c.Mux(torch.zeros((4, 4), dtype=torch.float32, device="cuda"), 2, 2)
     y = torch.zeros((g.nt, 4, 36), dtype=torch.float32, device="cuda")
-    import ctypes
-    with pytest.raises(c.CtofError):  # batched solves take no mux
-        opts = c._SolverOpts(5, 0.0, 1.0, 0, 0.0, 1, 0, None, 0, None, None, None,
-                             ctypes.pointer(mx.desc(k)))
-        reps = (c._SolverReport * 1)()
-        handles = (ctypes.c_void_p * 1)(k.handle.value)
-        dptr = (ctypes.c_void_p * 1)(y.data_ptr())
-        mptr = (ctypes.c_void_p * 1)(m.data_ptr())
-        ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
-        c._check(c.lib().ctof_reconstruct_batched(1, handles, dptr, mptr, ctypes.byref(opts), reps,
-                                                  ws.data_ptr(), ws.numel(), c._stream_ptr()))
+    with pytest.raises(c.CtofError):  # batched solves check the tile against every scan
+        bad = c.Mux(torch.zeros((4, 25), dtype=torch.float32, device="cuda"), 5, 5)
+        c.reconstruct_batched([k], [torch.zeros((g.nt, 4, 4), dtype=torch.float32, device="cuda")], max_iter=5,
+                              mux=bad)
+
+
+def test_batched_multiplexed_solves_equal_single_solves():
+    # two shape classes (16 x 16 and 24 x 16 scans, 4 x 4 on/off Hadamard
+    # tiles): per-class power iteration, a tolerance stop that freezes
+    # volumes at different iterations, and graph chunks; each scan must
+    # match its own multiplexed solve run for the iterations it was given
+    from paper_2101_11680_amd import ctof as c
+    S = smux.onoff(16)
+    gs = [_geom(16), Geometry(nx=16, ny=24, pitch_mm=1.0, z_mm=_geom(16).z_mm, dz_mm=_geom(16).dz_mm,
+                              nt=_geom(16).nt, dt_ps=_geom(16).dt_ps)]
+    plan = [0, 1, 0]
+    for prec, tol in (("fp64", 1e-10), ("fp32", 1e-5)):
+        dt = torch.float64 if prec == "fp64" else torch.float32
+        ks = [c.tabulate(g, c.PRECISIONS[prec]) for g in gs]
+        mx = c.Mux(torch.tensor(S, dtype=dt, device="cuda"), 4, 4)
+        ys = []
+        for q, gi in enumerate(plan):
+            F, Fm, y = _mux_problem(gs[gi], S, 4, 4, 40 + q)
+            ys.append(torch.tensor(y, dtype=dt, device="cuda"))
+        for max_iter, rel_tol in ((120, 0.0), (400, 2e-2)):
+            mus, reps = c.reconstruct_batched([ks[gi] for gi in plan], ys, max_iter=max_iter, rel_tol=rel_tol,
+                                              check_every=10, mux=mx)
+            for q, gi in enumerate(plan):
+                mu1, rep1, _ = c.reconstruct(ks[gi], ys[q], max_iter=reps[q].iters, mux=mx)
+                print(f"{prec} scan {q}: iters {reps[q].iters} gmap {reps[q].gmap_ratio:.2e}")
+                assert abs(reps[q].lipschitz / rep1.lipschitz - 1) <= 1e-12
+                assert abs(reps[q].gmap0 / rep1.gmap0 - 1) <= 1e-12
+                assert rel_l2(to_np(mus[q]), to_np(mu1)) <= tol
+                assert abs(reps[q].datafit / rep1.datafit - 1) <= 10 * tol
+                if rel_tol > 0 and reps[q].iters < max_iter:
+                    assert reps[q].gmap_ratio <= rel_tol
 
 
 @pytest.mark.parametrize("case", [(16, 4, 4, 32), (24, 4, 6, 17), (32, 8, 8, 128)])
