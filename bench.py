@@ -705,20 +705,29 @@ def main() -> int:
         del k
         torch.cuda.empty_cache()
         variants = {}
-        for name in ("bf16x3", "bf16"):
-            kv = ctof.tabulate(g, ctof.PRECISIONS[name])
+        mu_ref = mu.clone()
+        for name in ("bf16x3", "bf16", "fp32_banded"):
+            kv = ctof.tabulate(g, ctof.PRECISIONS[name.split("_")[0]])
+            kept = 1.0
+            if name == "fp32_banded":
+                # the spectrum band below FP32 resolution of its largest entry
+                kept = ctof.set_band(kv, 1e-9)
             if args.tune:
                 ctof.tune(kv, nvol=1, iters=5)
             ctof.reconstruct(kv, d, max_iter=args.warmup, lam=lam, lipschitz=L)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            _, rv, _ = ctof.reconstruct(kv, d, max_iter=args.steps, lam=lam, lipschitz=L, timing=True)
+            muv, rv, _ = ctof.reconstruct(kv, d, max_iter=args.steps, lam=lam, lipschitz=L, timing=True)
             torch.cuda.synchronize()
             wv = time.perf_counter() - t0
             variants[name] = {"iters_per_s": args.steps / wv, "ms_per_step": 1e3 * wv / args.steps,
                               "contract_fwd_ms": rv.ms_contract_fwd / rv.iters,
                               "contract_adj_ms": rv.ms_contract_adj / rv.iters,
-                              "datafit_rel_to_fp32": rv.datafit / rep.datafit - 1.0}
+                              "datafit_rel_to_fp32": rv.datafit / rep.datafit - 1.0,
+                              "iterate_rel_l2_to_fp32": float((muv.double() - mu_ref.double()).norm()
+                                                              / mu_ref.double().norm())}
+            if name == "fp32_banded":
+                variants[name].update({"band_rel": 1e-9, "tiles_read": kept})
             log(f"{name}: {args.steps / wv:.1f} iters/s")
             del kv
             torch.cuda.empty_cache()

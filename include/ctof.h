@@ -35,8 +35,9 @@
  *       volume mu, g          [nz][ny][nx]
  *       histogram m, d, r     [nt][ny][nx]
  *   - A ctof_kernel handle is immutable after tabulation (apart from its FFT
- *     tuning, see ctof_kernel_set_tuning) and may be used concurrently from
- *     several streams as long as each call has its own workspace.
+ *     tuning and its band, see ctof_kernel_set_tuning, ctof_kernel_set_band)
+ *     and may be used concurrently from several streams as long as each call
+ *     has its own workspace.
  */
 #ifndef CTOF_H
 #define CTOF_H
@@ -384,6 +385,27 @@ ctof_status ctof_kernel_get_tuning(ctof_kernel k, int32_t *bb_t, int32_t *bb_z);
 ctof_status ctof_tune_workspace_bytes(ctof_kernel k, int32_t nvol, size_t *ws_bytes);
 ctof_status ctof_tune(ctof_kernel k, int32_t nvol, int32_t iters, void *ws_dev, size_t ws_bytes,
                       hipStream_t stream, float *ms, int32_t *bb_t, int32_t *bb_z);
+
+/*
+ * Band of a handle's kernel spectrum (optional; an approximation of the
+ * operator, off by default).  Each layer has its own kernel (Eq. 11), and
+ * diffusion makes a deeper layer's kernel broader and later, so at high
+ * lateral frequencies only early bins of shallow layers carry weight.  ctof_kernel_set_band finds, for each
+ * spectrum matrix, the range of 16-bin tiles holding every entry >= rel *
+ * max |entry| and from then on the forward and adjoint products read only
+ * those tiles (outputs of the skipped forward tiles are zero).  The operator
+ * then differs from the full one by entries below rel * max |entry|: per
+ * lateral frequency f and bin t, |dm^(f)[t]| <= rel * max|K| * sum_z |mu^_z(f)|
+ * (and likewise for the adjoint).  rel = 1e-9 is below FP32 resolution
+ * relative to the largest entry.  rel = 0 removes the band (full products);
+ * otherwise 0 < rel < 1.  band_dev: caller-owned device memory of
+ * ctof_kernel_band_bytes bytes, 256-byte aligned, kept alive while the handle
+ * uses it.  Enqueued on `stream`; the handle must not be in use on other
+ * streams meanwhile.  CTOF_EUNSUPPORTED with more than 1024 tiles (16384
+ * bins).
+ */
+ctof_status ctof_kernel_band_bytes(ctof_kernel k, size_t *bytes);
+ctof_status ctof_kernel_set_band(ctof_kernel k, double rel, void *band_dev, size_t band_bytes, hipStream_t stream);
 
 /* ===================================================================== *
  * Learned warm start.

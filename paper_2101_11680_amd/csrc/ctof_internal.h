@@ -95,6 +95,8 @@ struct ctof_kernel_s {
   void *khat;                 // caller-owned device buffer
   ctof::KhatLayout layout;
   int bb_t, bb_z;             // FFT planes per block on the bin / layer side (0 = rule)
+  const int *band = nullptr;  // caller-owned device table: per matrix [lo, hi) of 16-bin tiles (NULL = all)
+  double band_rel = 0.0;      // threshold the table was made with (0 = none)
 };
 
 namespace ctof {
@@ -166,6 +168,13 @@ int batch_block(const Dims &d, int B, int ppv, bool fp64, int bb = 0);
 // adjoint:  out[f][re/im][z] = sum_t K_s(f)[t][z] in[f][re/im][t]
 // nvol volumes of one shape class share the spectrum; their planes are
 // interleaved per frequency as [f][re/im][vol][plane].
+// Per matrix s, band[2 s], band[2 s + 1] = the range of 16-bin tiles holding
+// every entry >= rel * max |entry| of the packed spectrum (forward layout;
+// 0, 0 when none); scratch: one device unsigned int.  At most
+// band_max_tiles() tiles per matrix.
+hipError_t launch_band(const ctof_kernel_s *k, double rel, int *band, unsigned int *scratch, hipStream_t st);
+int band_max_tiles();
+
 hipError_t launch_contract(const ctof_kernel_s *k, bool adjoint, const void *in, void *out,
                            hipStream_t st, int nvol = 1, const int *active = nullptr);
 

@@ -24,7 +24,8 @@ STATUS = {0: "CTOF_OK", -1: "CTOF_EINVAL", -2: "CTOF_ENOMEM", -3: "CTOF_EHIP",
 
 EXPORTS = ("ctof_kernel_bytes", "ctof_kernel_tabulate", "ctof_kernel_tabulate_quadrant",
            "ctof_kernel_tabulate_ex", "ctof_kernel_tabulate_quadrant_ex",
-           "ctof_kernel_free", "ctof_kernel_info", "ctof_kernel_grid", "ctof_workspace_bytes", "ctof_forward",
+           "ctof_kernel_free", "ctof_kernel_info", "ctof_kernel_grid", "ctof_kernel_band_bytes",
+           "ctof_kernel_set_band", "ctof_workspace_bytes", "ctof_forward",
            "ctof_adjoint", "ctof_reconstruct", "ctof_workspace_bytes_batched",
            "ctof_reconstruct_batched", "ctof_kernel_set_tuning", "ctof_kernel_get_tuning",
            "ctof_tune_workspace_bytes", "ctof_tune", "ctof_last_error",
@@ -117,6 +118,8 @@ def lib() -> ctypes.CDLL:
         L.ctof_kernel_free.restype = None
         L.ctof_kernel_info.argtypes = [vp] + [ctypes.POINTER(i32)] * 6
         L.ctof_kernel_grid.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.ctof_kernel_band_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+        L.ctof_kernel_set_band.argtypes = [vp, ctypes.c_double, vp, sz, vp]
         L.ctof_workspace_bytes.argtypes = [vp, i32, ctypes.POINTER(sz), ctypes.POINTER(sz)]
         L.ctof_forward.argtypes = [vp, vp, vp, vp, sz, vp]
         L.ctof_adjoint.argtypes = [vp, vp, vp, vp, sz, vp]
@@ -239,6 +242,7 @@ class Kernel:
         _check(lib().ctof_kernel_grid(self._h, ctypes.byref(ny), ctypes.byref(nx)))
         self.info = KernelInfo(*[v.value for v in vals], ny=ny.value, nx=nx.value)
         self._ws = {}
+        self._band = None  # device table of the spectrum band, when one is set
 
     @property
     def handle(self) -> ctypes.c_void_p:
@@ -549,6 +553,26 @@ def reconstruct_batched(kernels, ds, mus=None, max_iter: int = 200, lam=-1.0, li
     _check(lib().ctof_reconstruct_batched(n, handles, dptr, mptr, ctypes.byref(opts), reps,
                                           ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
     return outs, [_report(r) for r in reps]
+
+
+def set_band(k: Kernel, rel: float, stream=None) -> float:
+    """Restrict the handle's products to the band of its kernel spectrum
+    holding every entry >= rel * max |entry| (rel = 0: full products again).
+    Returns the fraction of 16-bin tiles the products still read."""
+    torch = _torch()
+    if rel == 0.0:
+        _check(lib().ctof_kernel_set_band(k.handle, 0.0, None, 0, _stream_ptr(stream)))
+        k._band = None
+        return 1.0
+    nb = ctypes.c_size_t()
+    _check(lib().ctof_kernel_band_bytes(k.handle, ctypes.byref(nb)))
+    band = torch.zeros(nb.value, dtype=torch.uint8, device="cuda")
+    _check(lib().ctof_kernel_set_band(k.handle, float(rel), band.data_ptr(), band.numel(), _stream_ptr(stream)))
+    k._band = band  # the handle reads it from now on
+    i = k.info
+    table = band[: i.nmat * 8].view(torch.int32).view(i.nmat, 2).long()
+    ntt = (i.nt + 31) // 32 * 2
+    return float((table[:, 1] - table[:, 0]).sum().item()) / (i.nmat * ntt)
 
 
 def set_tuning(k: Kernel, bb_t: int, bb_z: int) -> None:

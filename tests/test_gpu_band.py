@@ -1,0 +1,114 @@
+"""The optional band of the kernel spectrum (ctof_kernel_set_band): the
+products read, per spectrum matrix, only the 16-bin tiles holding entries
+>= rel * max |entry|.  Against the FP64 oracle with a depth range where the
+band drops most tiles: forward and adjoint within the precision bars (FP32
+1e-5, FP64 1e-12 at rel 1e-15, BF16 hi+lo 2e-3), the per-frequency bound of
+the header checked on an input with all its weight at high frequencies in
+deep layers, FISTA in FP32, batched solves, rel = 0 restoring the full
+products bit for bit, and argument checks.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import kernel as okernel
+from oracle import operator as oop
+from oracle import solver as osolver
+from synth.workloads import Geometry, even_layers
+from tests.gpu_common import rel_l2, to_np
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def _geom(n=32, nz=16, nt=256):
+    # the depth range and 10 ns window of the benchmark at a smaller grid:
+    # the band keeps about 31% of the tiles at rel 1e-9, 83% at 1e-15
+    z, dz = even_layers(1.0, 30.0, nz)
+    return Geometry(nx=n, ny=n, pitch_mm=0.5, z_mm=z, dz_mm=dz, nt=nt, dt_ps=40.0)
+
+
+@pytest.mark.parametrize("prec,rel,tol", [("fp32", 1e-9, 1e-5), ("fp64", 1e-15, 1e-12), ("bf16x3", 1e-9, 2e-3)])
+def test_banded_products_match_oracle(prec, rel, tol):
+    from paper_2101_11680_amd import ctof as c
+    g = _geom()
+    F = oop.FFTOperator(okernel.tabulate(g))
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    k = c.tabulate(g, c.PRECISIONS[prec])
+    rng = np.random.default_rng(1)
+    mu = rng.uniform(0.0, 0.05, (g.nz, 32, 32))
+    r = rng.standard_normal((g.nt, 32, 32))
+    full_m = to_np(c.forward(k, torch.tensor(mu, dtype=dt, device="cuda")))
+    kept = c.set_band(k, rel)
+    print(f"{prec} rel {rel:g}: tiles kept {kept:.3f}")
+    assert 0.0 < kept < (1.0 if prec == "fp64" else 0.5)
+    m = to_np(c.forward(k, torch.tensor(mu, dtype=dt, device="cuda")))
+    a = to_np(c.adjoint(k, torch.tensor(r, dtype=dt, device="cuda")))
+    assert rel_l2(m, F.forward(mu)) <= tol and rel_l2(a, F.adjoint(r)) <= tol
+    # rel = 0 gives the full products back, bit for bit
+    assert c.set_band(k, 0.0) == 1.0
+    assert np.array_equal(to_np(c.forward(k, torch.tensor(mu, dtype=dt, device="cuda"))), full_m)
+
+
+def test_band_bound_on_high_frequency_input():
+    # all weight in the deepest layer at the highest lateral frequency: the
+    # banded forward may drop it, but only within the header's bound
+    from paper_2101_11680_amd import ctof as c
+    g = _geom()
+    k = c.tabulate(g, c.FP64)
+    kept = c.set_band(k, 1e-9)
+    mu = np.zeros((g.nz, 32, 32))
+    yy, xx = np.meshgrid(np.arange(32), np.arange(32), indexing="ij")
+    mu[-1] = np.where((yy + xx) % 2 == 0, 1.0, -1.0)
+    banded = to_np(c.forward(k, torch.tensor(mu, device="cuda")))
+    c.set_band(k, 0.0)
+    full = to_np(c.forward(k, torch.tensor(mu, device="cuda")))
+    # per frequency |dm^(f)[t]| <= rel max|Kp| sum_z |mu^_z(f)| (Kp: the
+    # packed spectrum, which carries the 1/P^2 of the inverse transform);
+    # with unnormalised transforms on the P x P torus Parseval gives
+    # ||dm[t]|| <= P ||dm^[t]|| and ||mu^_z|| = P ||mu_z||, so with one
+    # layer nonzero ||dm|| <= rel max|Kp| P^2 ||mu|| sqrt(nt)
+    F = oop.FFTOperator(okernel.tabulate(g))
+    P = F.py
+    kmax = np.abs(F.Khat).max() / (P * P)
+    bound = 1e-9 * kmax * P * P * np.linalg.norm(mu) * np.sqrt(g.nt)
+    print(f"kept {kept:.3f}: |dm| {np.linalg.norm(banded - full):.3e} bound {bound:.3e} |m| {np.linalg.norm(full):.3e}")
+    assert np.linalg.norm(banded - full) <= bound
+
+
+def test_banded_fista_fp32_and_batched():
+    from paper_2101_11680_amd import ctof as c
+    g = _geom()
+    F = oop.FFTOperator(okernel.tabulate(g))
+    rng = np.random.default_rng(3)
+    ds = []
+    for s in range(3):
+        mu = np.zeros((g.nz, 32, 32))
+        mu[2 + s, 10:16, 12:20] = 0.03
+        ds.append(F.forward(mu) * (1.0 + 0.01 * rng.standard_normal((g.nt, 32, 32))))
+    LA = osolver.power_iteration(F, 50)
+    L, lam = osolver.step_constants(LA)
+    ref, _ = osolver.fista(F, ds[0], L, lam, 60)
+    k = c.tabulate(g, c.FP32)
+    c.set_band(k, 1e-9)
+    dts = [torch.tensor(d, dtype=torch.float32, device="cuda") for d in ds]
+    got, rep, _ = c.reconstruct(k, dts[0], max_iter=60, lam=lam, lipschitz=L)
+    assert rel_l2(to_np(got), ref) <= 1e-5
+    singles = [c.reconstruct(k, d, max_iter=60, lam=lam, lipschitz=L)[0] for d in dts]
+    mus, _ = c.reconstruct_batched([k] * 3, dts, max_iter=60, lam=lam, lipschitz=L)
+    for a, b in zip(singles, mus):
+        assert rel_l2(to_np(b), to_np(a)) <= 1e-6
+
+
+def test_band_argument_checks():
+    from paper_2101_11680_amd import ctof as c
+    import ctypes
+    k = c.tabulate(_geom(n=8, nz=3, nt=32), c.FP32)
+    buf = torch.zeros(1 << 16, dtype=torch.uint8, device="cuda")
+    for bad in (-1e-9, 1.0, float("nan")):
+        with pytest.raises(c.CtofError):
+            c._check(c.lib().ctof_kernel_set_band(k.handle, bad, buf.data_ptr(), buf.numel(), c._stream_ptr()))
+    with pytest.raises(c.CtofError):  # too small
+        c._check(c.lib().ctof_kernel_set_band(k.handle, 1e-9, buf.data_ptr(), 64, c._stream_ptr()))
+    with pytest.raises(c.CtofError):  # misaligned
+        c._check(c.lib().ctof_kernel_set_band(k.handle, 1e-9, buf.data_ptr() + 4, buf.numel() - 4, c._stream_ptr()))
