@@ -49,7 +49,7 @@ def problem(geometry, precision=ctof.FP32, device="cuda") -> Problem:
     torch = _torch()
     k = ctof.tabulate(geometry, precision, device=device)
     i = k.info
-    d = torch.zeros((i.nt, i.n, i.n), dtype=torch.float32, device=device)
+    d = torch.zeros((i.nt, i.ny, i.nx), dtype=torch.float32, device=device)
     _, rep, _ = ctof.reconstruct(k, d, max_iter=1)
     return Problem(geometry, k, rep.lipschitz, rep.lam)
 
@@ -74,7 +74,7 @@ def back_projections(P: Problem, ds, out=None):
     torch = _torch()
     i = P.kernel.info
     if out is None:
-        out = torch.empty((len(ds), i.nz, i.n, i.n), dtype=torch.float32, device=ds[0].device)
+        out = torch.empty((len(ds), i.nz, i.ny, i.nx), dtype=torch.float32, device=ds[0].device)
     for j, d in enumerate(ds):
         ctof.adjoint(P.kernel, d, out=out[j])
     return out
@@ -121,7 +121,7 @@ def target_norms(P: Problem, targets, chunk: int = 32):
     lambda I, from the loss kernel at a zero start."""
     torch = _torch()
     i = P.kernel.info
-    V = i.nz * i.n * i.n
+    V = i.nz * i.ny * i.nx
     N = targets.shape[0]
     out = np.zeros((N, 2))
     y0 = torch.zeros((chunk * V, 1), dtype=torch.float32, device=targets.device)
@@ -252,7 +252,7 @@ def build_training_set(P: Problem, workload: dict, seeds, tol: float, max_iter: 
     torch = _torch()
     i = P.kernel.info
     N = len(seeds)
-    xs = torch.empty((N, i.nz, i.n, i.n), dtype=torch.float32, device="cuda")
+    xs = torch.empty((N, i.nz, i.ny, i.nx), dtype=torch.float32, device="cuda")
     ts = torch.empty_like(xs)
     t0 = time.time()
     iters = []

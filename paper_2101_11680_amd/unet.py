@@ -432,19 +432,19 @@ def warm_start_volumes(net, kernels, ds, taus, max_batch: int = 16, stream=None)
     groups: Dict[tuple, List[int]] = {}
     for i, k in enumerate(kernels):
         inf = k.info
-        groups.setdefault((inf.nz, inf.n), []).append(i)
-    for (nz, n), idx in groups.items():
+        groups.setdefault((inf.nz, inf.ny, inf.nx), []).append(i)
+    for (nz, ny, nx), idx in groups.items():
         model = net.get(nz) if isinstance(net, dict) else net
         coarse = False
         if model is None and isinstance(net, dict) and nz % 2 == 0 and (nz // 2) in net:
             model, coarse = net[nz // 2], True
-        if model is None or (nz // (2 if coarse else 1)) % 8 or n % 8:
+        if model is None or (nz // (2 if coarse else 1)) % 8 or ny % 8 or nx % 8:
             for i in idx:
-                out[i] = torch.zeros((nz, n, n), dtype=torch.float32, device=ds[i].device)
+                out[i] = torch.zeros((nz, ny, nx), dtype=torch.float32, device=ds[i].device)
             continue
         for b0 in range(0, len(idx), max_batch):
             part = idx[b0:b0 + max_batch]
-            x = torch.empty((len(part), nz, n, n), dtype=torch.float32, device=model.device)
+            x = torch.empty((len(part), nz, ny, nx), dtype=torch.float32, device=model.device)
             for j, i in enumerate(part):
                 ctof.adjoint(kernels[i], ds[i], out=x[j], stream=stream)
             if coarse:
