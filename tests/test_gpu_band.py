@@ -112,3 +112,31 @@ def test_band_argument_checks():
         c._check(c.lib().ctof_kernel_set_band(k.handle, 1e-9, buf.data_ptr(), 64, c._stream_ptr()))
     with pytest.raises(c.CtofError):  # misaligned
         c._check(c.lib().ctof_kernel_set_band(k.handle, 1e-9, buf.data_ptr() + 4, buf.numel() - 4, c._stream_ptr()))
+
+
+def test_band_with_rectangular_grid_and_multiplexing():
+    # the band composes with a rectangular scan and with source multiplexing
+    from oracle import mux as omux
+    from synth import mux as smux
+    from paper_2101_11680_amd import ctof as c
+    z, dz = even_layers(1.0, 30.0, 16)
+    g = Geometry(nx=32, ny=16, pitch_mm=0.5, z_mm=z, dz_mm=dz, nt=256, dt_ps=40.0)
+    F = oop.FFTOperator(okernel.tabulate(g))
+    k = c.tabulate(g, c.FP32)
+    kept = c.set_band(k, 1e-9)
+    assert 0.0 < kept < 0.5
+    rng = np.random.default_rng(9)
+    mu = rng.uniform(0.0, 0.05, (g.nz, 16, 32))
+    assert rel_l2(to_np(c.forward(k, torch.tensor(mu, dtype=torch.float32, device="cuda"))), F.forward(mu)) <= 1e-5
+    S = smux.onoff(16)
+    Fm = omux.MuxOperator(F, S, 4, 4)
+    mut = np.zeros((g.nz, 16, 32))
+    mut[3, 4:9, 10:18] = 0.03
+    y = Fm.forward(mut)
+    LA = osolver.power_iteration(Fm, 50)
+    L, lam = osolver.step_constants(LA)
+    ref, _ = osolver.fista(Fm, y, L, lam, 40)
+    mx = c.Mux(torch.tensor(S, dtype=torch.float32, device="cuda"), 4, 4)
+    got, _, _ = c.reconstruct(k, torch.tensor(y, dtype=torch.float32, device="cuda"), max_iter=40, lam=lam,
+                              lipschitz=L, mux=mx)
+    assert rel_l2(to_np(got), ref) <= 1e-5
