@@ -391,10 +391,13 @@ ctof_status ctof_tune(ctof_kernel k, int32_t nvol, int32_t iters, void *ws_dev, 
  * operator, off by default).  Each layer has its own kernel (Eq. 11), and
  * diffusion makes a deeper layer's kernel broader and later, so at high
  * lateral frequencies only early bins of shallow layers carry weight.  ctof_kernel_set_band finds, for each
- * spectrum matrix, the range of 16-bin tiles holding every entry >= rel *
- * max |entry| and from then on the forward and adjoint products read only
- * those tiles (outputs of the skipped forward tiles are zero).  The operator
- * then differs from the full one by entries below rel * max |entry|: per
+ * spectrum matrix, the range of 16-bin tiles and the leading layers (in
+ * groups of nzp/4 layers up to 64 layers, 16 from 64 on; nzp = nz rounded up
+ * as the precision's kernels pack it) holding every entry >= rel * max |entry|,
+ * and from then on the forward and adjoint products read only that block of
+ * the matrix (outputs of the skipped forward tiles and adjoint layers are
+ * zero).  The operator then differs from the full one by entries below
+ * rel * max |entry|: per
  * lateral frequency f and bin t, |dm^(f)[t]| <= rel * max|K| * sum_z |mu^_z(f)|
  * (and likewise for the adjoint).  rel = 1e-9 is below FP32 resolution
  * relative to the largest entry.  rel = 0 removes the band (full products);

@@ -1412,7 +1412,7 @@ ctof_status ctof_kernel_band_bytes(ctof_kernel k, size_t *bytes) {
   ctof_status s = check_kernel(k);
   if (s != CTOF_OK) return s;
   if (!bytes) return set_error(CTOF_EINVAL, "bytes is NULL");
-  *bytes = ctof::round_up((size_t)k->dims.nmat * 2 * sizeof(int32_t), 256) + 256;  // table, scratch word
+  *bytes = ctof::round_up((size_t)k->dims.nmat * 4 * sizeof(int32_t), 256) + 256;  // table, scratch word
   return CTOF_OK;
 }
 
@@ -1427,7 +1427,7 @@ ctof_status ctof_kernel_set_band(ctof_kernel k, double rel, void *band_dev, size
   if (!(std::isfinite(rel) && rel > 0.0 && rel < 1.0)) return set_error(CTOF_EINVAL, "rel must be 0 or in (0, 1)");
   if (!band_dev || (reinterpret_cast<uintptr_t>(band_dev) & 255))
     return set_error(CTOF_EINVAL, "band_dev is NULL or not 256-byte aligned");
-  const size_t table = (size_t)k->dims.nmat * 2 * sizeof(int32_t);
+  const size_t table = (size_t)k->dims.nmat * 4 * sizeof(int32_t);
   const size_t need = ctof::round_up(table, 256) + 256;
   if (band_bytes < need) return set_error(CTOF_ENOMEM, "band buffer %zu < %zu bytes", band_bytes, need);
   if (k->dims.ntp / 16 > ctof::band_max_tiles())

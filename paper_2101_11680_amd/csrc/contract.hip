@@ -154,16 +154,23 @@ struct CArgs {
   int nvol, npairs;
   int parts;          // forward: blocks per (matrix, pair), each a contiguous run of t tiles; adjoint: 1
   const int *active;  // per volume, 0 = frozen (no loads, no stores); NULL = all live
-  const int *band;    // per matrix [lo, hi) of 16-bin tiles holding its significant entries; NULL = all
+  const int *band;    // per matrix {lo, hi, zend, 0}: 16-bin tiles [lo, hi) and layers [0, zend)
+                      // holding its significant entries; NULL = all
 };
 
-// Tiles [lo, hi) of matrix s inside the band (all of [0, ntt) without one)
-__device__ inline void band_of(const CArgs &a, int s, int ntt, int &lo, int &hi) {
+// Tiles [lo, hi) and layers [0, zend) of matrix s inside the band (all of
+// [0, ntt) x [0, nzp) without one).  BAND: the kernel is launched with a band
+// table; kernels without one compile without any of its logic.
+template <bool BAND>
+__device__ inline void band_of(const CArgs &a, int s, int ntt, int &lo, int &hi, int &zend) {
   lo = 0;
   hi = ntt;
-  if (a.band != nullptr) {
-    lo = a.band[2 * s];
-    hi = a.band[2 * s + 1];
+  zend = a.nzp;
+  if (BAND) {
+    const int4 b = *reinterpret_cast<const int4 *>(a.band + 4 * s);
+    lo = b.x;
+    hi = b.y;
+    zend = b.z;
   }
 }
 
@@ -208,7 +215,7 @@ __device__ inline bool pair_idle(const CArgs &a, int pair) {
 }
 
 // ---- FP32 / FP64, forward: M = t (tiles of 16), K = z --------------------------
-template <typename T, int KZ, bool NT>
+template <typename T, int KZ, bool NT, bool BAND>
 __global__ void __launch_bounds__(256)
 contract_fwd_kernel(CArgs a) {
   using M = Mfma<T>;
@@ -226,7 +233,14 @@ contract_fwd_kernel(CArgs a) {
             (size_t)k.vol * ntp;
   const T *khat = reinterpret_cast<const T *>(a.khat);
   const int ntt = ntp / 16;
+  int blo0, bhi0, zend;
+  band_of<BAND>(a, s, ntt, blo0, bhi0, zend);
   for (int ch = 0; ch < nchunk; ++ch) {
+    // layer chunks past the band's layers add nothing (the first one still
+    // runs: it writes the tiles)
+    if (BAND && ch > 0 && ch * 4 * KZ >= zend) break;
+    // this lane group's layers hold significant entries
+    const bool zon = !BAND || ch * 4 * KZ + g * KZ < zend;
     T bv[KZ];
     if (k.on) {
       load_run<T, KZ>(vcol + ch * 4 * KZ + g * KZ, bv);
@@ -252,31 +266,38 @@ contract_fwd_kernel(CArgs a) {
     // this block's run of t tiles, restricted to the matrix's band; tiles
     // outside it are written as zeros (with the first layer chunk)
     const int r0 = part * ntt / a.parts, r1 = (part + 1) * ntt / a.parts;
-    int blo, bhi;
-    band_of(a, s, ntt, blo, bhi);
-    blo = max(blo, r0);
-    bhi = max(blo, min(bhi, r1));
+    const int blo = max(blo0, r0);
+    const int bhi = max(blo, min(bhi0, r1));
     if (ch == 0 && k.on && (blo > r0 || bhi < r1)) {
       const typename M::acc_t zero = {0, 0, 0, 0};
       for (int zt = r0 + w; zt < r1; zt += 4)
         if (zt < blo || zt >= bhi) store4<T>(ocol + zt * 16 + 4 * g, zero);
     }
     const int tend = bhi;
+    // lane groups past the band's layers read nothing and multiply zeros
+    auto fetch = [&](int t, T (&av)[KZ]) {
+      if (!BAND || zon) {
+        load_frag<T, KZ, NT>(frag(t), l, av);
+      } else {
+#pragma unroll
+        for (int kk = 0; kk < KZ; ++kk) av[kk] = (T)0;
+      }
+    };
     T a0[KZ], a1[KZ];
     int tt = blo + w;
-    if (tt < tend) load_frag<T, KZ, NT>(frag(tt), l, a0);
+    if (tt < tend) fetch(tt, a0);
     for (; tt < tend; tt += 8) {
-      if (tt + 4 < tend) load_frag<T, KZ, NT>(frag(tt + 4), l, a1);
+      if (tt + 4 < tend) fetch(tt + 4, a1);
       tile(tt, a0);
       if (tt + 4 >= tend) break;
-      if (tt + 8 < tend) load_frag<T, KZ, NT>(frag(tt + 8), l, a0);
+      if (tt + 8 < tend) fetch(tt + 8, a0);
       tile(tt + 4, a1);
     }
   }
 }
 
 // ---- FP32 / FP64, adjoint: M = z (tiles of 16), K = t (chunks of 16) -----------
-template <typename T, int ZT, bool NT>
+template <typename T, int ZT, bool NT, bool BAND>
 __global__ void __launch_bounds__(256)
 contract_adj_kernel(CArgs a) {
   using M = Mfma<T>;
@@ -298,6 +319,10 @@ contract_adj_kernel(CArgs a) {
   // next chunk's kernel fragments and data are loaded before the current
   // chunk's products (one chunk of loads in flight per wave)
   const int nch = ntp / 16;
+  // chunks of 16 bins and z tiles inside the matrix's band (the rest of the
+  // sum is below the band's threshold; z tiles past it stay zero)
+  int c0, c1, zend;
+  band_of<BAND>(a, s, nch, c0, c1, zend);
   auto load_chunk = [&](int ch, T (&av)[ZT][4], T (&bv)[4]) {
     if (k.on) {
       load_run<T, 4>(vcol + ch * 16 + 4 * g, bv);
@@ -305,18 +330,16 @@ contract_adj_kernel(CArgs a) {
       bv[0] = bv[1] = bv[2] = bv[3] = (T)0;
     }
 #pragma unroll
-    for (int zt = 0; zt < ZT; ++zt) load_frag<T, 4, NT>(khat + (((size_t)s * nch + ch) * ZT + zt) * 256, l, av[zt]);
+    for (int zt = 0; zt < ZT; ++zt)
+      if (!BAND || zt * 16 < zend) load_frag<T, 4, NT>(khat + (((size_t)s * nch + ch) * ZT + zt) * 256, l, av[zt]);
   };
   auto mul_chunk = [&](const T (&av)[ZT][4], const T (&bv)[4]) {
 #pragma unroll
     for (int zt = 0; zt < ZT; ++zt)
+      if (!BAND || zt * 16 < zend)
 #pragma unroll
-      for (int kk = 0; kk < 4; ++kk) acc[zt] = M::step(av[zt][kk], bv[kk], acc[zt]);
+        for (int kk = 0; kk < 4; ++kk) acc[zt] = M::step(av[zt][kk], bv[kk], acc[zt]);
   };
-  // chunks of 16 bins inside the matrix's band (the rest of the sum is
-  // below the band's threshold)
-  int c0, c1;
-  band_of(a, s, nch, c0, c1);
   T a0[ZT][4], a1[ZT][4], b0[4], b1[4];
   int ch = c0 + w;
   if (ch < c1) load_chunk(ch, a0, b0);
@@ -369,7 +392,7 @@ __device__ __forceinline__ v8bf load_bf8(const __bf16 *p) {
   return r;
 }
 
-template <int KIND, int KZ, bool NT>  // KZ: z per lane group per chunk (multiple of 8)
+template <int KIND, int KZ, bool NT, bool BAND>  // KZ: z per lane group per chunk (multiple of 8)
 __global__ void __launch_bounds__(256)
 contract_fwd_bf16_kernel(CArgs a) {
   int s, pair, part;
@@ -387,7 +410,11 @@ contract_fwd_bf16_kernel(CArgs a) {
   const __bf16 *khi = reinterpret_cast<const __bf16 *>(a.khat);
   const __bf16 *klo = reinterpret_cast<const __bf16 *>(a.khat_lo);
   const int ntt = ntp / 16;
+  int blo0, bhi0, zend;
+  band_of<BAND>(a, s, ntt, blo0, bhi0, zend);
   for (int ch = 0; ch < nchunk; ++ch) {
+    if (BAND && ch > 0 && ch * 4 * KZ >= zend) break;
+    const bool zon = !BAND || ch * 4 * KZ + g * KZ < zend;
     v8bf bh[KZ / 8], bl[KZ / 8];
 #pragma unroll
     for (int e = 0; e < KZ / 8; ++e) {
@@ -401,10 +428,8 @@ contract_fwd_bf16_kernel(CArgs a) {
       }
     }
     const int r0 = part * ntt / a.parts, r1 = (part + 1) * ntt / a.parts;
-    int blo, bhi;
-    band_of(a, s, ntt, blo, bhi);
-    blo = max(blo, r0);
-    bhi = max(blo, min(bhi, r1));
+    const int blo = max(blo0, r0);
+    const int bhi = max(blo, min(bhi0, r1));
     if (ch == 0 && k.on && (blo > r0 || bhi < r1)) {
       for (int zt = r0 + w; zt < r1; zt += 4)
         if (zt < blo || zt >= bhi) *reinterpret_cast<float4 *>(ocol + zt * 16 + 4 * g) = make_float4(0, 0, 0, 0);
@@ -421,11 +446,12 @@ contract_fwd_bf16_kernel(CArgs a) {
 #pragma unroll
       for (int e = 0; e < KZ / 8; ++e) {
         const size_t off = blk + ((size_t)e * 64 + l) * 8;
-        const v8bf ah = load_bf8<NT>(khi + off);
+        const v8bf zero8 = {};
+        const v8bf ah = (!BAND || zon) ? load_bf8<NT>(khi + off) : zero8;
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[e], acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[e], acc, 0, 0, 0);
         if (KIND == 2) {
-          const v8bf al = load_bf8<NT>(klo + off);
+          const v8bf al = (!BAND || zon) ? load_bf8<NT>(klo + off) : zero8;
           acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[e], acc, 0, 0, 0);
         }
       }
@@ -434,7 +460,7 @@ contract_fwd_bf16_kernel(CArgs a) {
   }
 }
 
-template <int KIND, int ZT, bool NT>
+template <int KIND, int ZT, bool NT, bool BAND>
 __global__ void __launch_bounds__(256)
 contract_adj_bf16_kernel(CArgs a) {
   extern __shared__ unsigned char smem_raw[];
@@ -454,8 +480,8 @@ contract_adj_bf16_kernel(CArgs a) {
 #pragma unroll
   for (int zt = 0; zt < ZT; ++zt) acc[zt] = {0, 0, 0, 0};
   // chunks of 32 bins covering the matrix's band of 16-bin tiles
-  int c0, c1;
-  band_of(a, s, ntp / 16, c0, c1);
+  int c0, c1, zend;
+  band_of<BAND>(a, s, ntp / 16, c0, c1, zend);
   c0 = c0 / 2;
   c1 = (c1 + 1) / 2;
   for (int ch = c0 + w; ch < c1; ch += 4) {
@@ -471,6 +497,7 @@ contract_adj_bf16_kernel(CArgs a) {
     }
 #pragma unroll
     for (int zt = 0; zt < ZT; ++zt) {
+      if (BAND && zt * 16 >= zend) continue;  // z tiles past the band stay zero
       const size_t off = (((size_t)s * (ntp / 32) + ch) * ZT + zt) * 512 + (size_t)l * 8;
       const v8bf ah = load_bf8<NT>(khi + off);
       acc[zt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc[zt], 0, 0, 0);
@@ -505,37 +532,37 @@ contract_adj_bf16_kernel(CArgs a) {
   }
 }
 
-template <typename T, bool NT>
+template <typename T, bool NT, bool BAND>
 hipError_t launch_plain(const ctof_kernel_s *k, bool adjoint, const CArgs &a, hipStream_t st) {
   const Dims &d = k->dims;
   const dim3 grid((unsigned)(8 * ((d.nmat + 7) / 8) * a.npairs * a.parts)), block(256);
   if (!adjoint) {
     const int kz = (d.nzp >= 64 ? 64 : d.nzp) / 4;
     switch (kz) {
-      case 4: hipLaunchKernelGGL((contract_fwd_kernel<T, 4, NT>), grid, block, 0, st, a); break;
-      case 8: hipLaunchKernelGGL((contract_fwd_kernel<T, 8, NT>), grid, block, 0, st, a); break;
-      case 12: hipLaunchKernelGGL((contract_fwd_kernel<T, 12, NT>), grid, block, 0, st, a); break;
-      case 16: hipLaunchKernelGGL((contract_fwd_kernel<T, 16, NT>), grid, block, 0, st, a); break;
+      case 4: hipLaunchKernelGGL((contract_fwd_kernel<T, 4, NT, BAND>), grid, block, 0, st, a); break;
+      case 8: hipLaunchKernelGGL((contract_fwd_kernel<T, 8, NT, BAND>), grid, block, 0, st, a); break;
+      case 12: hipLaunchKernelGGL((contract_fwd_kernel<T, 12, NT, BAND>), grid, block, 0, st, a); break;
+      case 16: hipLaunchKernelGGL((contract_fwd_kernel<T, 16, NT, BAND>), grid, block, 0, st, a); break;
       default: return hipErrorInvalidValue;
     }
   } else {
     const int zt = d.nzp / 16;
     const size_t shm = (size_t)4 * zt * 64 * 4 * sizeof(T);
     switch (zt) {
-      case 1: hipLaunchKernelGGL((contract_adj_kernel<T, 1, NT>), grid, block, shm, st, a); break;
-      case 2: hipLaunchKernelGGL((contract_adj_kernel<T, 2, NT>), grid, block, shm, st, a); break;
-      case 3: hipLaunchKernelGGL((contract_adj_kernel<T, 3, NT>), grid, block, shm, st, a); break;
-      case 4: hipLaunchKernelGGL((contract_adj_kernel<T, 4, NT>), grid, block, shm, st, a); break;
-      case 8: hipLaunchKernelGGL((contract_adj_kernel<T, 8, NT>), grid, block, shm, st, a); break;
-      case 12: hipLaunchKernelGGL((contract_adj_kernel<T, 12, NT>), grid, block, shm, st, a); break;
-      case 16: hipLaunchKernelGGL((contract_adj_kernel<T, 16, NT>), grid, block, shm, st, a); break;
+      case 1: hipLaunchKernelGGL((contract_adj_kernel<T, 1, NT, BAND>), grid, block, shm, st, a); break;
+      case 2: hipLaunchKernelGGL((contract_adj_kernel<T, 2, NT, BAND>), grid, block, shm, st, a); break;
+      case 3: hipLaunchKernelGGL((contract_adj_kernel<T, 3, NT, BAND>), grid, block, shm, st, a); break;
+      case 4: hipLaunchKernelGGL((contract_adj_kernel<T, 4, NT, BAND>), grid, block, shm, st, a); break;
+      case 8: hipLaunchKernelGGL((contract_adj_kernel<T, 8, NT, BAND>), grid, block, shm, st, a); break;
+      case 12: hipLaunchKernelGGL((contract_adj_kernel<T, 12, NT, BAND>), grid, block, shm, st, a); break;
+      case 16: hipLaunchKernelGGL((contract_adj_kernel<T, 16, NT, BAND>), grid, block, shm, st, a); break;
       default: return hipErrorInvalidValue;
     }
   }
   return hipGetLastError();
 }
 
-template <int KIND, bool NT>
+template <int KIND, bool NT, bool BAND>
 hipError_t launch_bf16(const ctof_kernel_s *k, bool adjoint, const CArgs &a0, hipStream_t st) {
   const Dims &d = k->dims;
   // one block per matrix: split into t runs, the BF16 forward measured slower
@@ -546,34 +573,40 @@ hipError_t launch_bf16(const ctof_kernel_s *k, bool adjoint, const CArgs &a0, hi
   if (!adjoint) {
     const int kz = (d.nzp >= 64 ? 64 : d.nzp) / 4;
     switch (kz) {
-      case 8: hipLaunchKernelGGL((contract_fwd_bf16_kernel<KIND, 8, NT>), grid, block, 0, st, a); break;
-      case 16: hipLaunchKernelGGL((contract_fwd_bf16_kernel<KIND, 16, NT>), grid, block, 0, st, a); break;
+      case 8: hipLaunchKernelGGL((contract_fwd_bf16_kernel<KIND, 8, NT, BAND>), grid, block, 0, st, a); break;
+      case 16: hipLaunchKernelGGL((contract_fwd_bf16_kernel<KIND, 16, NT, BAND>), grid, block, 0, st, a); break;
       default: return hipErrorInvalidValue;
     }
   } else {
     const int zt = d.nzp / 16;
     const size_t shm = (size_t)4 * zt * 64 * 4 * sizeof(float);
     switch (zt) {
-      case 2: hipLaunchKernelGGL((contract_adj_bf16_kernel<KIND, 2, NT>), grid, block, shm, st, a); break;
-      case 4: hipLaunchKernelGGL((contract_adj_bf16_kernel<KIND, 4, NT>), grid, block, shm, st, a); break;
-      case 8: hipLaunchKernelGGL((contract_adj_bf16_kernel<KIND, 8, NT>), grid, block, shm, st, a); break;
-      case 12: hipLaunchKernelGGL((contract_adj_bf16_kernel<KIND, 12, NT>), grid, block, shm, st, a); break;
-      case 16: hipLaunchKernelGGL((contract_adj_bf16_kernel<KIND, 16, NT>), grid, block, shm, st, a); break;
+      case 2: hipLaunchKernelGGL((contract_adj_bf16_kernel<KIND, 2, NT, BAND>), grid, block, shm, st, a); break;
+      case 4: hipLaunchKernelGGL((contract_adj_bf16_kernel<KIND, 4, NT, BAND>), grid, block, shm, st, a); break;
+      case 8: hipLaunchKernelGGL((contract_adj_bf16_kernel<KIND, 8, NT, BAND>), grid, block, shm, st, a); break;
+      case 12: hipLaunchKernelGGL((contract_adj_bf16_kernel<KIND, 12, NT, BAND>), grid, block, shm, st, a); break;
+      case 16: hipLaunchKernelGGL((contract_adj_bf16_kernel<KIND, 16, NT, BAND>), grid, block, shm, st, a); break;
       default: return hipErrorInvalidValue;
     }
   }
   return hipGetLastError();
 }
 
-template <bool NT>
-hipError_t dispatch(const ctof_kernel_s *k, bool adjoint, const CArgs &a, hipStream_t st) {
+template <bool NT, bool BAND>
+hipError_t dispatch_prec(const ctof_kernel_s *k, bool adjoint, const CArgs &a, hipStream_t st) {
   switch (k->prec) {
-    case CTOF_FP64: return launch_plain<double, NT>(k, adjoint, a, st);
-    case CTOF_FP32: return launch_plain<float, NT>(k, adjoint, a, st);
-    case CTOF_BF16X3: return launch_bf16<2, NT>(k, adjoint, a, st);
-    case CTOF_BF16: return launch_bf16<3, NT>(k, adjoint, a, st);
+    case CTOF_FP64: return launch_plain<double, NT, BAND>(k, adjoint, a, st);
+    case CTOF_FP32: return launch_plain<float, NT, BAND>(k, adjoint, a, st);
+    case CTOF_BF16X3: return launch_bf16<2, NT, BAND>(k, adjoint, a, st);
+    case CTOF_BF16: return launch_bf16<3, NT, BAND>(k, adjoint, a, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <bool NT>
+hipError_t dispatch(const ctof_kernel_s *k, bool adjoint, const CArgs &a, hipStream_t st) {
+  if (a.band != nullptr) return dispatch_prec<NT, true>(k, adjoint, a, st);
+  return dispatch_prec<NT, false>(k, adjoint, a, st);
 }
 
 }  // namespace
@@ -608,9 +641,12 @@ hipError_t launch_contract(const ctof_kernel_s *k, bool adjoint, const void *in,
 
 // ---- band of significant tiles ---------------------------------------------------
 // The entries of a matrix's 16-bin tile (s, tt) are contiguous in the forward
-// layout: elements [(s ntt + tt) 16 nzp, + 16 nzp).  |x| of a non-negative
-// float orders like its bit pattern as an unsigned integer, so an integer
-// maximum over the bits is the float maximum (order-independent).
+// layout: elements [(s ntt + tt) 16 nzp, + 16 nzp).  Inside a tile, layer
+// chunk ch holds 64 KZ elements in 16-byte words, word q of lane l at
+// (64 q + l); lane group g = l / 16 carries the layers 4 KZ ch + KZ g ..
+// + KZ - 1, layer group ch * 4 + g.  |x| of a non-negative float orders like
+// its bit pattern as an unsigned integer, so an integer maximum over the bits
+// is the float maximum (order-independent).
 namespace {
 
 template <typename E>
@@ -632,33 +668,50 @@ __global__ void __launch_bounds__(256) band_absmax_kernel(const E *__restrict__ 
   if (threadIdx.x == 0) atomicMax(out, __float_as_uint(red[0]));
 }
 
-// One block per matrix: band[2 s], band[2 s + 1] = first and one past the last
-// tile holding an entry >= rel * max |entry| (0, 0 when none does).
+// One block per matrix: band[4 s] = first tile, band[4 s + 1] = one past the
+// last tile, band[4 s + 2] = one past the last layer group, in layers (a
+// multiple of kz), holding an entry >= rel * max |entry|; all 0 when none
+// does.  Threads only ever set a flag to 1, so their stores may race.
 template <typename E>
 __global__ void __launch_bounds__(256) band_range_kernel(const E *__restrict__ k, int nmat, int ntt, int tile_elems,
-                                                         double rel, const unsigned int *gmax, int *band) {
-  __shared__ int on[1024];
+                                                         int kz, double rel, const unsigned int *gmax, int *band) {
+  constexpr int PER = 16 / (int)sizeof(E);
+  __shared__ int ton[1024];
+  __shared__ int zon[16];
   const int s = blockIdx.x;
   if (s >= nmat) return;
+  for (int i = threadIdx.x; i < ntt; i += 256) ton[i] = 0;
+  if (threadIdx.x < 16) zon[threadIdx.x] = 0;
+  __syncthreads();
   const float thr = (float)(rel * (double)__uint_as_float(*gmax));
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  for (int tt = w; tt < ntt; tt += 4) {
-    const E *t = k + ((size_t)s * ntt + tt) * tile_elems;
-    float m = 0.f;
-    for (int i = l; i < tile_elems; i += 64) m = fmaxf(m, mag(t[i]));
-    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
-    if (l == 0) on[tt] = (m >= thr && m > 0.f) ? 1 : 0;
+  const E *base = k + (size_t)s * ntt * tile_elems;
+  const int chunk = 64 * kz;
+  for (int tt = 0; tt < ntt; ++tt) {
+    const E *t = base + (size_t)tt * tile_elems;
+    for (int r = threadIdx.x; r < tile_elems; r += 256) {
+      const float v = mag(t[r]);
+      if (v >= thr && v > 0.f) {
+        const int ch = r / chunk;
+        const int lane = ((r - ch * chunk) / PER) & 63;
+        ton[tt] = 1;
+        zon[ch * 4 + (lane >> 4)] = 1;
+      }
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    int lo = -1, hi = -1;
+    int lo = -1, hi = -1, zg = 0;
     for (int tt = 0; tt < ntt; ++tt)
-      if (on[tt]) {
+      if (ton[tt]) {
         if (lo < 0) lo = tt;
         hi = tt + 1;
       }
-    band[2 * s] = lo < 0 ? 0 : lo;
-    band[2 * s + 1] = lo < 0 ? 0 : hi;
+    for (int q = 0; q < 16; ++q)
+      if (zon[q]) zg = q + 1;
+    band[4 * s] = lo < 0 ? 0 : lo;
+    band[4 * s + 1] = lo < 0 ? 0 : hi;
+    band[4 * s + 2] = lo < 0 ? 0 : zg * kz;
+    band[4 * s + 3] = 0;
   }
 }
 
@@ -667,13 +720,16 @@ hipError_t band_typed(const ctof_kernel_s *k, double rel, int *band, unsigned in
   const Dims &d = k->dims;
   const int ntt = d.ntp / 16;
   const int tile = 16 * d.nzp;
+  // layers per lane group and chunk, as the forward kernels are launched
+  const int kz = (d.nzp >= 64 ? 64 : d.nzp) / 4;
+  if (d.nzp / kz > 16) return hipErrorInvalidValue;
   const E *kh = reinterpret_cast<const E *>(reinterpret_cast<const char *>(k->khat) + k->layout.fwd);
   const size_t n = (size_t)d.nmat * ntt * tile;
   hipError_t e = launch_fill_zero(scratch, sizeof(unsigned int), st);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(band_absmax_kernel<E>, dim3(2048), dim3(256), 0, st, kh, n, scratch);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(band_range_kernel<E>, dim3((unsigned)d.nmat), dim3(256), 0, st, kh, d.nmat, ntt, tile, rel,
+  hipLaunchKernelGGL(band_range_kernel<E>, dim3((unsigned)d.nmat), dim3(256), 0, st, kh, d.nmat, ntt, tile, kz, rel,
                      scratch, band);
   return hipGetLastError();
 }

@@ -95,7 +95,7 @@ struct ctof_kernel_s {
   void *khat;                 // caller-owned device buffer
   ctof::KhatLayout layout;
   int bb_t, bb_z;             // FFT planes per block on the bin / layer side (0 = rule)
-  const int *band = nullptr;  // caller-owned device table: per matrix [lo, hi) of 16-bin tiles (NULL = all)
+  const int *band = nullptr;  // caller-owned device table: per matrix {lo, hi, zend, 0} (NULL = all)
   double band_rel = 0.0;      // threshold the table was made with (0 = none)
 };
 
@@ -168,10 +168,12 @@ int batch_block(const Dims &d, int B, int ppv, bool fp64, int bb = 0);
 // adjoint:  out[f][re/im][z] = sum_t K_s(f)[t][z] in[f][re/im][t]
 // nvol volumes of one shape class share the spectrum; their planes are
 // interleaved per frequency as [f][re/im][vol][plane].
-// Per matrix s, band[2 s], band[2 s + 1] = the range of 16-bin tiles holding
-// every entry >= rel * max |entry| of the packed spectrum (forward layout;
-// 0, 0 when none); scratch: one device unsigned int.  At most
-// band_max_tiles() tiles per matrix.
+// Per matrix s, band[4 s], band[4 s + 1] = the range [lo, hi) of 16-bin tiles
+// and band[4 s + 2] = the end zend of the leading layers (a multiple of the
+// forward's layers per lane group) holding every entry >= rel * max |entry|
+// of the packed spectrum (forward layout; all 0 when none); band[4 s + 3] = 0.
+// scratch: one device unsigned int.  At most band_max_tiles() tiles per
+// matrix.
 hipError_t launch_band(const ctof_kernel_s *k, double rel, int *band, unsigned int *scratch, hipStream_t st);
 int band_max_tiles();
 

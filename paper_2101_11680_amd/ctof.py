@@ -558,7 +558,9 @@ def reconstruct_batched(kernels, ds, mus=None, max_iter: int = 200, lam=-1.0, li
 def set_band(k: Kernel, rel: float, stream=None) -> float:
     """Restrict the handle's products to the band of its kernel spectrum
     holding every entry >= rel * max |entry| (rel = 0: full products again).
-    Returns the fraction of 16-bin tiles the products still read."""
+    Returns the fraction of the forward's kernel-spectrum bytes the products
+    still read: per matrix the 16-bin tiles [lo, hi) times the leading
+    layers [0, zend) of the band table."""
     torch = _torch()
     if rel == 0.0:
         _check(lib().ctof_kernel_set_band(k.handle, 0.0, None, 0, _stream_ptr(stream)))
@@ -570,9 +572,29 @@ def set_band(k: Kernel, rel: float, stream=None) -> float:
     _check(lib().ctof_kernel_set_band(k.handle, float(rel), band.data_ptr(), band.numel(), _stream_ptr(stream)))
     k._band = band  # the handle reads it from now on
     i = k.info
-    table = band[: i.nmat * 8].view(torch.int32).view(i.nmat, 2).long()
+    table = band[: i.nmat * 16].view(torch.int32).view(i.nmat, 4).long()
     ntt = (i.nt + 31) // 32 * 2
-    return float((table[:, 1] - table[:, 0]).sum().item()) / (i.nmat * ntt)
+    nzp = _layers_packed(i.nz, i.precision)
+    kept = ((table[:, 1] - table[:, 0]) * table[:, 2]).sum().item()
+    return float(kept) / (i.nmat * ntt * nzp)
+
+
+def band_table(k: Kernel):
+    """The band table of a handle as an (nmat, 3) int64 CPU tensor of
+    (lo, hi, zend), or None without a band."""
+    if k._band is None:
+        return None
+    i = k.info
+    return k._band[: i.nmat * 16].view(_torch().int32).view(i.nmat, 4)[:, :3].long().cpu()
+
+
+def _layers_packed(nz: int, prec: int) -> int:
+    # layers as the contraction kernels pack them: a multiple of 16 (32 for
+    # the BF16 forms) up to 64 layers, of 64 above
+    if nz > 64:
+        return (nz + 63) // 64 * 64
+    m = 32 if prec in (BF16, BF16X3) else 16
+    return (nz + m - 1) // m * m
 
 
 def set_tuning(k: Kernel, bb_t: int, bb_z: int) -> None:

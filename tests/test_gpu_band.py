@@ -1,11 +1,15 @@
 """The optional band of the kernel spectrum (ctof_kernel_set_band): the
-products read, per spectrum matrix, only the 16-bin tiles holding entries
->= rel * max |entry|.  Against the FP64 oracle with a depth range where the
-band drops most tiles: forward and adjoint within the precision bars (FP32
-1e-5, FP64 1e-12 at rel 1e-15, BF16 hi+lo 2e-3), the per-frequency bound of
-the header checked on an input with all its weight at high frequencies in
-deep layers, FISTA in FP32, batched solves, rel = 0 restoring the full
-products bit for bit, and argument checks.
+products read, per spectrum matrix, only the 16-bin tiles and the leading
+layer groups holding entries >= rel * max |entry|.  The band table is pinned
+to the oracle's spectrum (every entry well above the threshold inside the
+box, the box's edges each holding an entry near or above it).  Against the
+FP64 oracle with a depth range where the band drops most of the spectrum:
+forward and adjoint within the precision bars (FP32 1e-5, FP64 1e-12 at
+rel 1e-15, BF16 hi+lo 2e-3) at 16, 64 and 80 layers (layer groups of 4 and
+16, one and two layer chunks), the per-frequency bound of the header checked
+on an input with all its weight at high frequencies in deep layers, FISTA in
+FP32, batched solves, rel = 0 restoring the full products bit for bit, and
+argument checks.
 """
 
 import numpy as np
@@ -22,8 +26,7 @@ torch = pytest.importorskip("torch")
 
 
 def _geom(n=32, nz=16, nt=256):
-    # the depth range and 10 ns window of the benchmark at a smaller grid:
-    # the band keeps about 31% of the tiles at rel 1e-9, 83% at 1e-15
+    # the depth range and 10 ns window of the benchmark at a smaller grid
     z, dz = even_layers(1.0, 30.0, nz)
     return Geometry(nx=n, ny=n, pitch_mm=0.5, z_mm=z, dz_mm=dz, nt=nt, dt_ps=40.0)
 
@@ -40,7 +43,7 @@ def test_banded_products_match_oracle(prec, rel, tol):
     r = rng.standard_normal((g.nt, 32, 32))
     full_m = to_np(c.forward(k, torch.tensor(mu, dtype=dt, device="cuda")))
     kept = c.set_band(k, rel)
-    print(f"{prec} rel {rel:g}: tiles kept {kept:.3f}")
+    print(f"{prec} rel {rel:g}: spectrum bytes kept {kept:.3f}")
     assert 0.0 < kept < (1.0 if prec == "fp64" else 0.5)
     m = to_np(c.forward(k, torch.tensor(mu, dtype=dt, device="cuda")))
     a = to_np(c.adjoint(k, torch.tensor(r, dtype=dt, device="cuda")))
@@ -140,3 +143,68 @@ def test_band_with_rectangular_grid_and_multiplexing():
     got, _, _ = c.reconstruct(k, torch.tensor(y, dtype=torch.float32, device="cuda"), max_iter=40, lam=lam,
                               lipschitz=L, mux=mx)
     assert rel_l2(to_np(got), ref) <= 1e-5
+
+
+@pytest.mark.parametrize("prec,nz", [("fp32", 64), ("bf16x3", 64), ("fp32", 80), ("fp64", 80)])
+def test_banded_products_layer_groups(prec, nz):
+    # 64 layers: groups of 16 per lane group, 4 adjoint z tiles; 80 layers:
+    # two layer chunks of 64 (the second one skipped for most matrices)
+    from paper_2101_11680_amd import ctof as c
+    g = _geom(n=16, nz=nz)
+    F = oop.FFTOperator(okernel.tabulate(g))
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    rel, tol = {"fp32": (1e-9, 1e-5), "fp64": (1e-15, 1e-12), "bf16x3": (1e-9, 2e-3)}[prec]
+    k = c.tabulate(g, c.PRECISIONS[prec])
+    kept = c.set_band(k, rel)
+    tab = c.band_table(k)
+    nzp = c._layers_packed(nz, k.info.precision)
+    print(f"{prec} nz {nz}: bytes kept {kept:.3f}, matrices with fewer layers {(tab[:, 2] < nzp).float().mean():.3f}")
+    assert bool((tab[:, 2] < nzp).any())
+    rng = np.random.default_rng(5)
+    mu = rng.uniform(0.0, 0.05, (nz, 16, 16))
+    r = rng.standard_normal((g.nt, 16, 16))
+    m = to_np(c.forward(k, torch.tensor(mu, dtype=dt, device="cuda")))
+    a = to_np(c.adjoint(k, torch.tensor(r, dtype=dt, device="cuda")))
+    assert rel_l2(m, F.forward(mu)) <= tol and rel_l2(a, F.adjoint(r)) <= tol
+
+
+def test_band_table_is_the_box_of_the_oracle_spectrum():
+    # matrix s = (a, b), b (b + 1)/2 <= s, holds the spectrum at (kx, ky) =
+    # (a, b) (the same as at (b, a) on the square grid), rows t, columns z.
+    # FP64 tabulates entries near rel * max to ~1e-15 max, so entries
+    # above 2 rel max must lie inside the box and each edge of the box (first
+    # and last tile, last layer group) must hold one above rel max / 2
+    from paper_2101_11680_amd import ctof as c
+    g = _geom()
+    F = oop.FFTOperator(okernel.tabulate(g))
+    A = np.abs(F.Khat.real)  # [z][t][ky][kx]
+    amax = A.max()
+    k = c.tabulate(g, c.FP64)
+    for rel in (1e-9, 1e-6):
+        c.set_band(k, rel)
+        tab = c.band_table(k).numpy()
+        kz = 4  # 16 layers: groups of nzp / 4
+        P = F.py
+        h = P // 2
+        assert tab.shape[0] == (h + 1) * (h + 2) // 2
+        shrunk_t = shrunk_z = 0
+        for s in range(tab.shape[0]):
+            b = int((np.sqrt(8 * s + 1) - 1) // 2)
+            a = s - b * (b + 1) // 2
+            M = A[:, :, b, a].T / amax  # [t][z]
+            lo, hi, zend = (int(v) for v in tab[s])
+            big = np.argwhere(M >= 2 * rel)
+            if hi == lo:  # no entry at or above the threshold
+                assert len(big) == 0 and (lo, hi, zend) == (0, 0, 0)
+                continue
+            if len(big):
+                assert big[:, 0].min() >= 16 * lo and big[:, 0].max() < 16 * hi
+                assert big[:, 1].max() < zend
+            assert (M[16 * lo:16 * lo + 16] >= rel / 2).any()
+            assert (M[16 * hi - 16:16 * hi] >= rel / 2).any()
+            assert zend % kz == 0 and (M[:, zend - kz:zend] >= rel / 2).any()
+            shrunk_t += (hi - lo) < tab[:, 1].max()
+            shrunk_z += zend < g.nz
+        print(f"rel {rel:g}: matrices with a shorter t range {shrunk_t}, with fewer layers {shrunk_z}")
+        assert shrunk_z > 0
+    c.set_band(k, 0.0)
