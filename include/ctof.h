@@ -403,7 +403,10 @@ ctof_status ctof_tune(ctof_kernel k, int32_t nvol, int32_t iters, void *ws_dev, 
  * relative to the largest entry.  rel = 0 removes the band (full products);
  * otherwise 0 < rel < 1.  band_dev: caller-owned device memory of
  * ctof_kernel_band_bytes bytes, 256-byte aligned, kept alive while the handle
- * uses it.  Enqueued on `stream`; the handle must not be in use on other
+ * uses it; its first 16 * nmat bytes receive the table, per matrix s = (a, b)
+ * (s = b (b + 1)/2 + a, a <= b <= P/2) four int32 {lo, hi, zend, 0}: 16-bin
+ * tiles [lo, hi) and layers [0, zend) ({0, 0, 0, 0} when the matrix holds no
+ * entry at or above the threshold); the rest is scratch.  Enqueued on `stream`; the handle must not be in use on other
  * streams meanwhile.  CTOF_EUNSUPPORTED with more than 1024 tiles (16384
  * bins).
  */
