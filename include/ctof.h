@@ -270,9 +270,11 @@ ctof_status ctof_mux_normal(ctof_kernel k, const ctof_mux *mux, const void *m_de
  *   history_dev      optional device array double[max_iter][2] receiving
  *                    (1/2 ||A y_k - d||^2, gradient-mapping ratio) per
  *                    iteration; NULL for none
- *   timing           1: record HIP events on `stream` around the stages of
- *                    every iteration and fill the ms_* fields of the report
- *                    (adds event records between launches); 0: no events
+ *   timing           n >= 1: record HIP events on `stream` around the stages
+ *                    of every n-th iteration (0, n, 2n, ...) and at the end
+ *                    of the loop, and fill the ms_* fields and timed_iters of
+ *                    the report (each timed iteration adds five event records
+ *                    between its launches); 0: no events; < 0: CTOF_EINVAL
  *   lipschitz_scans, lambda_scans
  *                    batched solves only (NULL otherwise): host arrays [nscan]
  *                    giving each scan's L (> 0) and lambda (>= 0) in place of
@@ -320,17 +322,20 @@ typedef struct {
  *   lipschitz, lambda   the L and lambda used;  lipschitz_a  L_A (0 if L given)
  *   gmap0       ||max(0, A^T d)||, the ratio's denominator
  *   fell_back   1 if warm_start = 2 discarded the given start, else 0
- *   ms_*        with opts.timing: GPU milliseconds summed over the iterations
- *               for the forward contraction, the measurement-side FFT passes
- *               (inverse column, residual row, column), the adjoint
- *               contraction, the volume-side FFT passes (inverse column,
- *               prox row, column), and the whole iteration loop
+ *   ms_*        with opts.timing: GPU milliseconds summed over the timed
+ *               iterations for the forward contraction, the measurement-side
+ *               FFT passes (inverse column, residual row, column), the adjoint
+ *               contraction and the volume-side FFT passes (inverse column,
+ *               prox row, column); ms_loop: the whole iteration loop (all
+ *               iterations, from the first iteration's start to the end)
+ *   timed_iters the number of timed iterations (0 without opts.timing)
  */
 typedef struct {
   int32_t iters, status;
   double datafit0, datafit, gmap_ratio, lipschitz, lambda, lipschitz_a, gmap0;
   double ms_contract_fwd, ms_fft_t, ms_contract_adj, ms_fft_z, ms_loop;
   int32_t fell_back;
+  int32_t timed_iters;
 } ctof_solver_report;
 
 /*

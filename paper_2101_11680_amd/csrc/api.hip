@@ -732,7 +732,10 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
 
   if (ctof_status s = enqueue_start(E, mm, opt->warm_start != 0); s != CTOF_OK) return s;
   const std::vector<double> beta = fista_betas(K);
-  // optional stage timing: events around the contraction and FFT groups
+  // optional stage timing: events around the contraction and FFT groups of
+  // every `timing`-th iteration (0, n, 2n, ...) and one at the loop's end
+  const int tstride = opt->timing;
+  const int nsamp = tstride > 0 ? (K + tstride - 1) / tstride : 0;
   std::vector<hipEvent_t> ev;
   struct EventGuard {
     std::vector<hipEvent_t> *v;
@@ -740,12 +743,13 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
       for (hipEvent_t e : *v) (void)hipEventDestroy(e);
     }
   } guard{&ev};
-  if (opt->timing) {
-    ev.resize((size_t)K * 5, nullptr);
+  if (tstride > 0) {
+    ev.resize((size_t)nsamp * 5 + 1, nullptr);
     for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
   }
   auto mark = [&](int it, int j) -> hipError_t {
-    return opt->timing ? hipEventRecord(ev[(size_t)it * 5 + j], st) : hipSuccess;
+    return (tstride > 0 && it % tstride == 0) ? hipEventRecord(ev[(size_t)(it / tstride) * 5 + j], st)
+                                              : hipSuccess;
   };
   int done = 0;
   for (int it = 0; it < K; ++it) {
@@ -800,6 +804,7 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
       if (h2[1] <= opt->rel_tol) break;
     }
   }
+  if (tstride > 0) HIP_TRY(hipEventRecord(ev[(size_t)nsamp * 5], st));  // end of the loop
   HIP_TRY(ctof::launch_history(E.part(), done, 1, E.L.nblk_t, E.L.nblk_z, E.L.part_stride, tau, E.g0sq(),
                                E.hist(), st));
   if (opt->history_dev)
@@ -814,22 +819,26 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
   HIP_TRY(hipMemcpyAsync(hl, E.hist() + 2 * (size_t)(done - 1), 2 * sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipMemcpyAsync(&g0, E.g0sq(), sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  if (opt->timing && done > 0) {
+  if (tstride > 0 && done > 0) {
+    // iterations 0, n, ... below `done` were timed (an early stop leaves the
+    // later samples unrecorded)
+    const int ntimed = (done + tstride - 1) / tstride;
     double acc[4] = {0, 0, 0, 0};
-    for (int it = 0; it < done; ++it) {
+    for (int q = 0; q < ntimed; ++q) {
       for (int j = 0; j < 4; ++j) {
         float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, ev[(size_t)it * 5 + j], ev[(size_t)it * 5 + j + 1]));
+        HIP_TRY(hipEventElapsedTime(&ms, ev[(size_t)q * 5 + j], ev[(size_t)q * 5 + j + 1]));
         acc[j] += ms;
       }
     }
     float loop = 0.f;
-    HIP_TRY(hipEventElapsedTime(&loop, ev[0], ev[(size_t)(done - 1) * 5 + 4]));
+    HIP_TRY(hipEventElapsedTime(&loop, ev[0], ev[(size_t)nsamp * 5]));
     rep->ms_contract_fwd = acc[0];
     rep->ms_fft_t = acc[1];
     rep->ms_contract_adj = acc[2];
     rep->ms_fft_z = acc[3];
     rep->ms_loop = loop;
+    rep->timed_iters = ntimed;
   }
   rep->iters = done;
   rep->datafit0 = h0[0];
@@ -1556,6 +1565,7 @@ ctof_status ctof_reconstruct(ctof_kernel k, const void *d_dev, void *mu_inout_de
   if (!(std::isfinite(opts->rel_tol) && opts->rel_tol >= 0)) return set_error(CTOF_EINVAL, "rel_tol must be >= 0");
   if (opts->rel_tol > 0 && opts->check_every < 1) return set_error(CTOF_EINVAL, "check_every must be >= 1");
   if (opts->warm_start < 0 || opts->warm_start > 2) return set_error(CTOF_EINVAL, "warm_start must be 0, 1 or 2");
+  if (opts->timing < 0) return set_error(CTOF_EINVAL, "timing must be >= 0");
   if (opts->lipschitz_scans || opts->lambda_scans)
     return set_error(CTOF_EINVAL, "lipschitz_scans / lambda_scans are batched options");
   if (opts->lambda_l1_z)

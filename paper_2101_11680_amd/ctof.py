@@ -82,7 +82,7 @@ class _SolverReport(ctypes.Structure):
                 ("gmap0", ctypes.c_double), ("ms_contract_fwd", ctypes.c_double),
                 ("ms_fft_t", ctypes.c_double), ("ms_contract_adj", ctypes.c_double),
                 ("ms_fft_z", ctypes.c_double), ("ms_loop", ctypes.c_double),
-                ("fell_back", ctypes.c_int32)]
+                ("fell_back", ctypes.c_int32), ("timed_iters", ctypes.c_int32)]
 
 
 class _ConvDesc(ctypes.Structure):
@@ -364,6 +364,7 @@ class Report:
     ms_fft_z: float = 0.0
     ms_loop: float = 0.0
     fell_back: int = 0
+    timed_iters: int = 0
 
 
 def _l1_array(l1, nz):
@@ -466,11 +467,13 @@ def noisy_counts(m, scale: float, background: float, seed: int, stream_id: int =
 def reconstruct(k: Kernel, d, mu=None, max_iter: int = 200, lam: float = -1.0,
                 lipschitz: float = 0.0, power_iters: int = 50, rel_tol: float = 0.0,
                 check_every: int = 10, warm_start: bool = False, history: bool = False,
-                timing: bool = False, l1=None, mux: Optional[Mux] = None, stream=None):
+                timing: int = 0, l1=None, mux: Optional[Mux] = None, stream=None):
     """FISTA reconstruction; returns (mu, Report, history or None).  warm_start:
     0/False zero start, 1/True start from ``mu``, 2 start from ``mu`` with the
     zero-start fallback.  l1: per-layer L1 weights (nz numbers) or None.
-    mux: a Mux when d holds multiplexed measurements y [nt][rows][ntiles]."""
+    mux: a Mux when d holds multiplexed measurements y [nt][rows][ntiles].
+    timing: 0 no stage events; n >= 1 (True = 1) events around the stages of
+    every n-th iteration, summed in the report's ms_* over timed_iters."""
     torch = _torch()
     i = k.info
     if mux is None:
@@ -486,7 +489,7 @@ def reconstruct(k: Kernel, d, mu=None, max_iter: int = 200, lam: float = -1.0,
     mdesc = mux.desc(k) if mux is not None else None
     opts = _SolverOpts(int(max_iter), float(lam), float(lipschitz), int(power_iters),
                        float(rel_tol), int(check_every), int(warm_start),
-                       hist.data_ptr() if hist is not None else None, int(bool(timing)), None, None, l1a,
+                       hist.data_ptr() if hist is not None else None, int(timing), None, None, l1a,
                        ctypes.pointer(mdesc) if mdesc is not None else None)
     rep = _SolverReport()
     _, nb = k.workspace_bytes(max_iter)
@@ -502,7 +505,8 @@ def reconstruct(k: Kernel, d, mu=None, max_iter: int = 200, lam: float = -1.0,
 def _report(rep) -> Report:
     return Report(rep.iters, rep.status, rep.datafit0, rep.datafit, rep.gmap_ratio,
                   rep.lipschitz, rep.lambda_, rep.lipschitz_a, rep.gmap0, rep.ms_contract_fwd,
-                  rep.ms_fft_t, rep.ms_contract_adj, rep.ms_fft_z, rep.ms_loop, rep.fell_back)
+                  rep.ms_fft_t, rep.ms_contract_adj, rep.ms_fft_z, rep.ms_loop, rep.fell_back,
+                  rep.timed_iters)
 
 
 def reconstruct_batched(kernels, ds, mus=None, max_iter: int = 200, lam=-1.0, lipschitz=0.0,

@@ -111,3 +111,30 @@ def test_mux_whole_scan_tile_and_single_row():
         yy = rng.standard_normal(y.shape)
         back = to_np(c.mux_adjoint(k, mx, torch.tensor(yy, device="cuda")))
         assert rel_l2(back, omux.adjoint(S, yy, tx, ty, 8)) <= 1e-13
+
+
+def test_stage_timing_stride():
+    # stage events on every n-th iteration: the counts of timed iterations,
+    # an early stop, the same iterates as without events, a negative stride
+    # refused
+    from paper_2101_11680_amd import ctof as c
+    z, dz = even_layers(2.0, 10.0, 8)
+    g = Geometry(nx=16, ny=16, pitch_mm=0.5, z_mm=z, dz_mm=dz, nt=64, dt_ps=50.0)
+    k = c.tabulate(g, c.FP32)
+    rng = np.random.default_rng(4)
+    d = torch.tensor(rng.uniform(0.0, 1.0, (g.nt, 16, 16)), dtype=torch.float32, device="cuda")
+    _, r0, _ = c.reconstruct(k, d, max_iter=1)
+    kw = dict(max_iter=20, lam=r0.lam, lipschitz=r0.lipschitz)
+    base, rb, _ = c.reconstruct(k, d, **kw)
+    assert rb.timed_iters == 0 and rb.ms_loop == 0.0
+    for stride, want in ((1, 20), (8, 3), (20, 1), (64, 1)):
+        mu, rep, _ = c.reconstruct(k, d, timing=stride, **kw)
+        assert rep.timed_iters == want
+        assert rep.ms_contract_fwd > 0 and rep.ms_contract_adj > 0 and rep.ms_fft_t > 0 and rep.ms_fft_z > 0
+        assert rep.ms_loop >= rep.ms_contract_fwd + rep.ms_contract_adj
+        assert torch.equal(mu, base)
+    # a stop after 10 iterations leaves the samples at 0 and 8
+    _, rep, _ = c.reconstruct(k, d, timing=8, rel_tol=1e9, check_every=10, **kw)
+    assert rep.iters == 10 and rep.timed_iters == 2
+    with pytest.raises(c.CtofError):
+        c.reconstruct(k, d, timing=-1, **kw)
