@@ -45,23 +45,29 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def band_time_fraction(ctof, k) -> float:
-    """Fraction of the residual spectrum's (frequency, bin) entries that the
-    banded adjoint reads: per spectrum matrix s = (a, b), b (b + 1)/2 <= s,
-    its range of 16-bin tiles, weighted by the rfft frequencies (kx, ky) in
-    {(a, b), (P - a, b), (b, a), (P - b, a)} it serves (1.0 without a band)."""
+def matrix_frequency_counts(p: int):
+    """Per spectrum matrix s = (a, b), a <= b <= p/2, s = b (b + 1)/2 + a:
+    the number of distinct rfft frequencies (kx, ky) among (a, b),
+    (p - a, b), (b, a), (p - b, a) that it serves (1, 2 or 4)."""
     import numpy as np
-    tab = ctof.band_table(k)
-    if tab is None:
-        return 1.0
-    i = k.info
-    h = i.p // 2
-    s = np.arange(i.nmat)
+    h = p // 2
+    s = np.arange((h + 1) * (h + 2) // 2)
     b = np.floor((np.sqrt(8 * s + 1) - 1) / 2).astype(np.int64)
     b -= b * (b + 1) // 2 > s
     b += (b + 1) * (b + 2) // 2 <= s
     a = s - b * (b + 1) // 2
-    w = 1 + ((a > 0) & (a < h)) + (a != b) + ((a != b) & (b > 0) & (b < h))
+    return 1 + ((a > 0) & (a < h)) + (a != b) + ((a != b) & (b > 0) & (b < h))
+
+
+def band_time_fraction(ctof, k) -> float:
+    """Fraction of the residual spectrum's (frequency, bin) entries that the
+    banded adjoint reads: per spectrum matrix its range of 16-bin tiles,
+    weighted by the rfft frequencies it serves (1.0 without a band)."""
+    tab = ctof.band_table(k)
+    if tab is None:
+        return 1.0
+    i = k.info
+    w = matrix_frequency_counts(i.p)
     t = tab.numpy()
     ntt = (i.nt + 31) // 32 * 2
     return float((w * (t[:, 1] - t[:, 0])).sum()) / float(w.sum() * ntt)
@@ -562,7 +568,7 @@ def main() -> int:
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               f"(asked for --gpus {args.gpus}, WORLD_SIZE={world})", file=sys.stderr)
         return 2
 
