@@ -496,28 +496,51 @@ row_pass_kernel(int ny, int nx, RowArgs a) {
   if (spec_in) {
     // Z[k] = A + i B,  A = X[k] + conj(X[H-k]),  B = (X[k] - conj(X[H-k])) e^{+2 pi i k/P}
     const T *src = reinterpret_cast<const T *>(a.spec_in) + b0;
-    for (int u = tid; u < (H / 2 + 1) * BB; u += NT) {
-      const int b = u % BB, k = u / BB;
-      const size_t o1 = (((size_t)k * ny + i) * 2) * B + b;
-      const size_t o2 = (((size_t)(H - k) * ny + i) * 2) * B + b;
-      const T x1r = src[o1], x1i = src[o1 + B];
-      const T x2r = src[o2], x2i = src[o2 + B];
-      {
-        const T ar = x1r + x2r, ai = x1i - x2i;
-        const T dr = x1r - x2r, di = x1i + x2i;
-        const T c = twc[k], s = tws[k];
-        const T br_ = dr * c - di * s, bi_ = dr * s + di * c;
-        wr[k * ld + b] = ar - bi_;
-        wi[k * ld + b] = ai + br_;
+    // three rounds of loads are issued before any is used (indices clamped
+    // into range, so every load is in bounds): three times the loads in
+    // flight per thread at the same occupancy (FP32: 60 registers)
+    constexpr int NU = (H / 2 + 1) * BB;
+    constexpr int NI = (NU + NT - 1) / NT;
+#pragma unroll
+    for (int j0 = 0; j0 < NI; j0 += 3) {
+      T xv[3][4];
+#pragma unroll
+      for (int jj = 0; jj < 3; ++jj) {
+        if (j0 + jj < NI) {
+          const int u = min(tid + (j0 + jj) * NT, NU - 1);
+          const int b = u % BB, k = u / BB;
+          const size_t o1 = (((size_t)k * ny + i) * 2) * B + b;
+          const size_t o2 = (((size_t)(H - k) * ny + i) * 2) * B + b;
+          xv[jj][0] = src[o1];
+          xv[jj][1] = src[o1 + B];
+          xv[jj][2] = src[o2];
+          xv[jj][3] = src[o2 + B];
+        }
       }
-      if (k > 0 && k < H / 2) {
-        const int kk = H - k;
-        const T ar = x2r + x1r, ai = x2i - x1i;
-        const T dr = x2r - x1r, di = x2i + x1i;
-        const T c = twc[kk], s = tws[kk];
-        const T br_ = dr * c - di * s, bi_ = dr * s + di * c;
-        wr[kk * ld + b] = ar - bi_;
-        wi[kk * ld + b] = ai + br_;
+#pragma unroll
+      for (int jj = 0; jj < 3; ++jj) {
+        const int u = tid + (j0 + jj) * NT;
+        if (j0 + jj >= NI || u >= NU) continue;
+        const int b = u % BB, k = u / BB;
+        const T x1r = xv[jj][0], x1i = xv[jj][1];
+        const T x2r = xv[jj][2], x2i = xv[jj][3];
+        {
+          const T ar = x1r + x2r, ai = x1i - x2i;
+          const T dr = x1r - x2r, di = x1i + x2i;
+          const T c = twc[k], s = tws[k];
+          const T br_ = dr * c - di * s, bi_ = dr * s + di * c;
+          wr[k * ld + b] = ar - bi_;
+          wi[k * ld + b] = ai + br_;
+        }
+        if (k > 0 && k < H / 2) {
+          const int kk = H - k;
+          const T ar = x2r + x1r, ai = x2i - x1i;
+          const T dr = x2r - x1r, di = x2i + x1i;
+          const T c = twc[kk], s = tws[kk];
+          const T br_ = dr * c - di * s, bi_ = dr * s + di * c;
+          wr[kk * ld + b] = ar - bi_;
+          wi[kk * ld + b] = ai + br_;
+        }
       }
     }
     __syncthreads();
@@ -534,73 +557,97 @@ row_pass_kernel(int ny, int nx, RowArgs a) {
   const T *sp_in = vol_on ? reinterpret_cast<const T *>(a.sp_in[vol]) : nullptr;
   T *sp_out = vol_on ? reinterpret_cast<T *>(a.sp_out[vol]) : nullptr;
   T *sp_aux = vol_on ? reinterpret_cast<T *>(a.sp_aux[vol]) : nullptr;
-  for (int u = tid; u < nx * BB; u += NT) {
-    const int j = u % nx, b = u / nx;
-    const int pl = pb0 + b;
-    const bool valid = vol_on && pl < a.nplanes;
-    const size_t idx = ((size_t)pl * ny + i) * nx + j;
-    T *slot = ((j & 1) ? wi : wr) + (j >> 1) * ld + b;
-    T x = (T)0;
-    if (spec_in) x = *slot;
-    T r = (T)0;
-    switch (op) {
-      case ROW_SPEC_TO_SPATIAL:
-        if (valid) sp_out[idx] = x;
-        break;
-      case ROW_SPATIAL_TO_SPEC:
-        r = valid ? sp_in[idx] : (T)0;
-        break;
-      case ROW_SCALE_TO_SPEC:
-        if (valid) {
-          r = sp_in[idx] * scale;
-          sp_out[idx] = r;
-        }
-        break;
-      case ROW_RESIDUAL:
-        if (valid) {
-          r = x - sp_in[idx];
-          acc0 += 0.5 * (double)r * (double)r;
-        }
-        break;
-      case ROW_PASS:
-        if (valid) {
-          r = x;
-          acc0 += 0.5 * (double)x * (double)x;
-        }
-        break;
-      case ROW_FISTA:
-        if (valid) {
-          const T yk = sp_in[idx];
-          const T mprev = sp_aux[idx];
-          T mu = yk - tau * (x + lam * yk);
-          if (a.l1) mu -= tau * (T)a.l1[pl];  // prox of the per-layer L1 term
-          mu = mu > (T)0 ? mu : (T)0;
-          const T ynew = mu + beta * (mu - mprev);
-          sp_aux[idx] = mu;
-          sp_out[idx] = ynew;
-          const double dd = (double)yk - (double)mu;
-          acc0 += dd * dd;
-          r = ynew;
-        }
-        break;
-      case ROW_POWER_W:
-        if (valid) {
-          sp_out[idx] = x;
-          acc0 += (double)x * (double)x;
-          acc1 += (double)sp_in[idx] * (double)x;
-        }
-        break;
-      case ROW_GMAP0:
-        if (valid) {
-          const double v = (double)x - (a.l1 ? a.l1[pl] : 0.0);
-          const double g = v > 0.0 ? v : 0.0;
-          acc0 += g * g;
-        }
-        break;
-      default:
-        break;
+  // the spatial inputs of four rounds are loaded before any is used (the
+  // same units in the same order per thread as one round at a time); each
+  // element is read and written by one thread, so outputs that alias an
+  // input (FISTA's y) stay correct
+  const bool rd_in = op == ROW_SPATIAL_TO_SPEC || op == ROW_SCALE_TO_SPEC || op == ROW_RESIDUAL ||
+                     op == ROW_FISTA || op == ROW_POWER_W;
+  const bool rd_aux = op == ROW_FISTA;
+  constexpr int NQ = 4;
+  const int NP = nx * BB;
+  for (int u0 = tid; u0 < NP; u0 += NQ * NT) {
+    T yin[NQ], yaux[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int u = u0 + q * NT;
+      const int pl = pb0 + u / nx;
+      const bool ok = u < NP && vol_on && pl < a.nplanes;
+      const size_t idx = ((size_t)pl * ny + i) * nx + u % nx;
+      yin[q] = (rd_in && ok) ? sp_in[idx] : (T)0;
+      yaux[q] = (rd_aux && ok) ? sp_aux[idx] : (T)0;
     }
-    if (spec_out) *slot = r;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int u = u0 + q * NT;
+      if (u >= NP) break;
+      const int j = u % nx, b = u / nx;
+      const int pl = pb0 + b;
+      const bool valid = vol_on && pl < a.nplanes;
+      const size_t idx = ((size_t)pl * ny + i) * nx + j;
+      T *slot = ((j & 1) ? wi : wr) + (j >> 1) * ld + b;
+      T x = (T)0;
+      if (spec_in) x = *slot;
+      T r = (T)0;
+      switch (op) {
+        case ROW_SPEC_TO_SPATIAL:
+          if (valid) sp_out[idx] = x;
+          break;
+        case ROW_SPATIAL_TO_SPEC:
+          r = valid ? yin[q] : (T)0;
+          break;
+        case ROW_SCALE_TO_SPEC:
+          if (valid) {
+            r = yin[q] * scale;
+            sp_out[idx] = r;
+          }
+          break;
+        case ROW_RESIDUAL:
+          if (valid) {
+            r = x - yin[q];
+            acc0 += 0.5 * (double)r * (double)r;
+          }
+          break;
+        case ROW_PASS:
+          if (valid) {
+            r = x;
+            acc0 += 0.5 * (double)x * (double)x;
+          }
+          break;
+        case ROW_FISTA:
+          if (valid) {
+            const T yk = yin[q];
+            const T mprev = yaux[q];
+            T mu = yk - tau * (x + lam * yk);
+            if (a.l1) mu -= tau * (T)a.l1[pl];  // prox of the per-layer L1 term
+            mu = mu > (T)0 ? mu : (T)0;
+            const T ynew = mu + beta * (mu - mprev);
+            sp_aux[idx] = mu;
+            sp_out[idx] = ynew;
+            const double dd = (double)yk - (double)mu;
+            acc0 += dd * dd;
+            r = ynew;
+          }
+          break;
+        case ROW_POWER_W:
+          if (valid) {
+            sp_out[idx] = x;
+            acc0 += (double)x * (double)x;
+            acc1 += (double)yin[q] * (double)x;
+          }
+          break;
+        case ROW_GMAP0:
+          if (valid) {
+            const double v = (double)x - (a.l1 ? a.l1[pl] : 0.0);
+            const double g = v > 0.0 ? v : 0.0;
+            acc0 += g * g;
+          }
+          break;
+        default:
+          break;
+      }
+      if (spec_out) *slot = r;
+    }
   }
   if (spec_out) {
     for (int u = tid; u < H * BB; u += NT) {
