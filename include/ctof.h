@@ -264,12 +264,15 @@ ctof_status ctof_mux_normal(ctof_kernel k, const ctof_mux *mux, const void *m_de
  *                    2: mu_inout is mu_0 with zero-start fallback: after the
  *                    first iteration, a scan whose gradient-mapping ratio
  *                    exceeds 1 (the ratio of a zero start is 1 by
- *                    definition) restarts from mu = 0; the discarded
- *                    iteration counts in `iters` and the restart continues
- *                    the FISTA step-size sequence from its second term
+ *                    definition) restarts from mu = 0 as a fresh zero start
+ *                    (its FISTA sequence begins again at t_1 = 1, so the
+ *                    remaining max_iter - 1 iterations are exactly those of
+ *                    a zero-start solve); the discarded iteration counts in
+ *                    `iters` but not in the history, datafit0 or fista_k
  *   history_dev      optional device array double[max_iter][2] receiving
  *                    (1/2 ||A y_k - d||^2, gradient-mapping ratio) per
- *                    iteration; NULL for none
+ *                    iteration of the kept run (iters - fell_back rows);
+ *                    NULL for none
  *   timing           n >= 1: record HIP events on `stream` around the stages
  *                    of every n-th iteration (0, n, 2n, ...) and at the end
  *                    of the loop, and fill the ms_* fields and timed_iters of
@@ -297,6 +300,29 @@ ctof_status ctof_mux_normal(ctof_kernel k, const ctof_mux *mux, const void *m_de
  *                    workspace is needed.  In batched solves the same
  *                    descriptor (S and the tile) applies to every scan,
  *                    whose grid it must tile; d_dev[i] holds scan i's y.
+ *   k0, mu_prev_dev  resumption of an interrupted FISTA run (the state of
+ *                    section "Reconstruction Algorithm" is the iterate
+ *                    mu_k, its predecessor mu_{k-1} and the counter k of
+ *                    the step-size sequence t_k).  k0 = 0: a fresh run.
+ *                    k0 >= 1 (warm_start must be 1): mu_inout holds mu_k0
+ *                    and mu_prev_dev holds mu_{k0-1} (same layout); the
+ *                    first step starts from y = mu_k0 + beta_k0 (mu_k0 -
+ *                    mu_{k0-1}) and uses the step weights from index k0 on,
+ *                    so K1 iterations followed by a resumed K2 give the
+ *                    same iterates, bit for bit, as one run of K1 + K2
+ *                    (with the same L and lambda).  Output: when
+ *                    mu_prev_dev is not NULL it receives the iterate before
+ *                    the final one (for the next resumption, with k0 =
+ *                    report.fista_k); it may be given with k0 = 0 to start
+ *                    a resumable run.  It must not overlap mu_inout.  The
+ *                    gradient-mapping denominator is recomputed (it does
+ *                    not depend on the start), datafit0 and the first
+ *                    history row are taken at y_{k0+1}.
+ *   mu_prev_scans    batched solves only (NULL otherwise, and then
+ *                    mu_prev_dev must be NULL too): host array [nscan] of
+ *                    device pointers playing mu_prev_dev's role per scan; k0
+ *                    applies to every scan (scans frozen early in the
+ *                    interrupted call resume from their frozen state).
  */
 typedef struct {
   int32_t max_iter;
@@ -312,6 +338,9 @@ typedef struct {
   const double *lambda_scans;
   const double *lambda_l1_z;
   const ctof_mux *mux;
+  void *mu_prev_dev;
+  int32_t k0;
+  void *const *mu_prev_scans;
 } ctof_solver_opts;
 
 /*
@@ -329,6 +358,8 @@ typedef struct {
  *               prox row, column); ms_loop: the whole iteration loop (all
  *               iterations, from the first iteration's start to the end)
  *   timed_iters the number of timed iterations (0 without opts.timing)
+ *   fista_k     the FISTA counter after the call: k0 + iterations of the
+ *               kept run (the k0 that resumes it)
  */
 typedef struct {
   int32_t iters, status;
@@ -336,6 +367,7 @@ typedef struct {
   double ms_contract_fwd, ms_fft_t, ms_contract_adj, ms_fft_z, ms_loop;
   int32_t fell_back;
   int32_t timed_iters;
+  int32_t fista_k;
 } ctof_solver_report;
 
 /*
@@ -348,6 +380,23 @@ typedef struct {
 ctof_status ctof_reconstruct(ctof_kernel k, const void *d_dev, void *mu_inout_dev,
                              const ctof_solver_opts *opts, ctof_solver_report *report,
                              void *ws_dev, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Layer-wise L1 weights (Eqs. 8 and 10: the sparsity weights grow with
+ * depth to counter the loss of sensitivity).  energy_host[z] = e(z) =
+ * ||A e_z||^2, the squared norm of the forward model's response to a unit
+ * absorber at the window centre (row ny/2, column nx/2) of layer z,
+ * summed in FP64; weights_host[z] = lambda1 * e(z) / max_z e(z), the rule
+ * under which a voxel's soft threshold in absorption units,
+ * lambda1_z / e(z), is the same at every depth (a reading: the paper
+ * states only that the weights compensate the depth-dependent loss).
+ * Either host array [nz] may be NULL.  ws_dev: at least
+ * ctof_layer_energy_ws_bytes bytes.  Synchronises `stream`.
+ * CTOF_ENONFINITE when an energy is not finite or all are zero.
+ */
+ctof_status ctof_layer_energy_ws_bytes(ctof_kernel k, size_t *ws_bytes);
+ctof_status ctof_l1_depth_weights(ctof_kernel k, double lambda1, double *energy_host, double *weights_host,
+                                  void *ws_dev, size_t ws_bytes, hipStream_t stream);
 
 /*
  * Batched reconstruction of nscan independent scans (the same FISTA as

@@ -199,7 +199,7 @@ TabWs tab_ws(const ctof::Dims &d) {
 // intermediates carry every volume's planes, solver state is per volume.
 struct ClassWs {
   size_t yhat, mhat, xt, xz, op_total;
-  size_t y, v, w, hist, scal, g0sq, part, beta, ctr, active, l1, solve_total;
+  size_t y, v, w, hist, scal, g0sq, part, beta, ctr, active, boff, l1, solve_total;
   int nblk_t, nblk_z;
   size_t part_stride;  // doubles per iteration
 };
@@ -235,6 +235,7 @@ ClassWs class_ws(const ctof_kernel_s *k, int nvol, int max_iter) {
   o.beta = take((size_t)iters * 8);
   o.ctr = take(64);
   o.active = take((size_t)nvol * 4);
+  o.boff = take((size_t)nvol * 4);
   o.l1 = take((size_t)d.nz * 8);
   o.solve_total = off;
   return o;
@@ -267,6 +268,7 @@ struct Engine {
   double *beta() const { return reinterpret_cast<double *>(ws + L.beta); }
   int *ctr() const { return reinterpret_cast<int *>(ws + L.ctr); }
   int *active() const { return reinterpret_cast<int *>(ws + L.active); }
+  int *boff() const { return reinterpret_cast<int *>(ws + L.boff); }
   double *l1() const { return reinterpret_cast<double *>(ws + L.l1); }
   int Bt() const { return nvol * dm().ntp; }
   int Bz() const { return nvol * dm().nzp; }
@@ -283,6 +285,7 @@ struct Engine {
     a.spec_in = tside ? (void *)xt() : (void *)xz();
     a.spec_out = const_cast<void *>(a.spec_in);
     a.l1 = tside ? nullptr : l1dev;
+    a.gmap0_at = -1;
     return a;
   }
   hipError_t run_row(const ctof::RowArgs &a) const { return ctof::launch_row_pass<T>(dm(), a, st); }
@@ -347,6 +350,21 @@ ctof_status make_mux(const ctof_kernel_s *k, const ctof_mux *mx, ctof::MuxArgs *
   if ((long long)a->nt * a->M * a->ntiles * (long long)es >= (1LL << 31) ||
       (long long)a->nt * ny * nx * (long long)es >= (1LL << 31))
     return set_error(CTOF_EINVAL, "multiplexed arrays must stay below 2 GiB");
+  return CTOF_OK;
+}
+
+bool overlaps(const void *a, const void *b, size_t bytes) {
+  const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+  return x < y + bytes && y < x + bytes;
+}
+
+// Resumption fields shared by both solvers (see ctof_solver_opts).
+ctof_status check_resume(const ctof_solver_opts *o, bool have_prev) {
+  if (o->k0 < 0 || o->k0 > (1 << 30) - o->max_iter)
+    return set_error(CTOF_EINVAL, "k0 must be in [0, 2^30 - max_iter]");
+  if (o->k0 > 0 && o->warm_start != 1)
+    return set_error(CTOF_EINVAL, "a resumed solve (k0 > 0) needs warm_start = 1");
+  if (o->k0 > 0 && !have_prev) return set_error(CTOF_EINVAL, "a resumed solve (k0 > 0) needs mu_{k0-1}");
   return CTOF_OK;
 }
 
@@ -466,12 +484,14 @@ ctof_status run_start_loss(const ctof_kernel_s *k, int nb, const ctof_tensor *y,
   return CTOF_OK;
 }
 
-std::vector<double> fista_betas(int iters) {
-  std::vector<double> b(iters);
+// FISTA's step weights beta_k = (t_k - 1) / t_{k+1} (t_1 = 1,
+// t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2), for k = first .. first + count - 1
+std::vector<double> fista_betas(int first, int count) {
+  std::vector<double> b(count);
   double t = 1.0;
-  for (int k = 0; k < iters; ++k) {
+  for (int k = 0; k < first + count; ++k) {
     const double tn = (1.0 + std::sqrt(1.0 + 4.0 * t * t)) / 2.0;
-    b[k] = (t - 1.0) / tn;
+    if (k >= first) b[k - first] = (t - 1.0) / tn;
     t = tn;
   }
   return b;
@@ -566,6 +586,33 @@ ctof_status enqueue_power_iteration(const Engine<T> &E1, int iters) {
   return CTOF_OK;
 }
 
+// Per-layer sensitivity e(z) = ||A e_z||^2 of a unit absorber at the window
+// centre of layer z, into e_dev[z] (FP64): the forward model's bin-side
+// spectrum goes through the row pass that sums 1/2 x^2 per block.
+template <typename T>
+ctof_status enqueue_layer_energy(const Engine<T> &E, double *e_dev) {
+  const ctof::Dims &dm = E.dm();
+  const size_t vol = (size_t)dm.nz * dm.ny * dm.nx;
+  T *unit = E.pv();
+  for (int z = 0; z < dm.nz; ++z) {
+    HIP_TRY(ctof::launch_fill_zero(unit, vol * sizeof(T), E.st));
+    T *at = unit + ((size_t)z * dm.ny + dm.ny / 2) * dm.nx + dm.nx / 2;
+    if (sizeof(T) == 8)
+      HIP_TRY(ctof::launch_fill_value_f64(reinterpret_cast<double *>(at), 1, 1.0, E.st));
+    else
+      HIP_TRY(ctof::launch_fill_value(reinterpret_cast<float *>(at), 1, 1.0f, E.st));
+    ctof::RowArgs a = E.row(ctof::ROW_SPATIAL_TO_SPEC, false);
+    a.sp_in[0] = unit;
+    HIP_TRY(E.mu_to_spec(a));
+    HIP_TRY(E.fwd_to_xt());
+    ctof::RowArgs b = E.row(ctof::ROW_PASS, true);
+    b.partials = E.part();
+    HIP_TRY(E.run_row(b));
+    HIP_TRY(ctof::launch_reduce_rows(E.part(), E.L.nblk_t, 2, 1, e_dev + z, E.st));
+  }
+  return CTOF_OK;
+}
+
 // ||max(0, A^T d_v)||^2 per volume into g0sq()[v]
 template <typename T>
 ctof_status enqueue_gmap0(const Engine<T> &E, const void *const *d) {
@@ -584,7 +631,8 @@ ctof_status enqueue_gmap0(const Engine<T> &E, const void *const *d) {
 // from the device iteration counter when `by_counter`, else from `it`
 template <typename T>
 ctof_status enqueue_iteration(const Engine<T> &E, const void *const *d, void *const *mu, double tau,
-                              double lam, bool by_counter, int it, double beta) {
+                              double lam, bool by_counter, int it, double beta, void *const *prev = nullptr,
+                              bool g0_first = false) {
   HIP_TRY(E.contract(false));
   HIP_TRY(E.col_t(true));
   if (E.mux) {
@@ -611,15 +659,18 @@ ctof_status enqueue_iteration(const Engine<T> &E, const void *const *d, void *co
     b.sp_in[v] = E.y(v);
     b.sp_out[v] = E.y(v);
     b.sp_aux[v] = mu[v];
+    b.sp_prev[v] = prev ? prev[v] : nullptr;
   }
   b.partials = E.part() + 2 * (size_t)E.L.nblk_t + (by_counter ? 0 : (size_t)it * E.L.part_stride);
   b.tau = tau;
   b.lambda = lam;
   b.beta = beta;
+  if (g0_first) b.gmap0_at = 0;
   if (by_counter) {
     b.iter_ctr = E.ctr();
     b.part_stride = E.L.part_stride;
     b.beta_tab = E.beta();
+    b.beta_off = E.boff();
     b.active = E.live;
   }
   HIP_TRY(E.run_row(b));
@@ -628,17 +679,39 @@ ctof_status enqueue_iteration(const Engine<T> &E, const void *const *d, void *co
   return CTOF_OK;
 }
 
-// y_v = mu_v (zeroed first for a cold start) and the spectrum of y
+// y_v = mu_v (zeroed first for a cold start) and the spectrum of y (the
+// spectrum of a cold start is zero and is written as such)
 template <typename T>
 ctof_status enqueue_start(const Engine<T> &E, void *const *mu, bool warm) {
   const ctof::Dims &dm = E.dm();
   const size_t vol = (size_t)dm.nz * dm.ny * dm.nx;
-  for (int v = 0; v < E.nvol; ++v) {
-    if (!warm) HIP_TRY(ctof::launch_fill_zero(mu[v], vol * sizeof(T), E.st));
-    HIP_TRY(hipMemcpyAsync(E.y(v), mu[v], vol * sizeof(T), hipMemcpyDeviceToDevice, E.st));
+  if (!warm) {
+    for (int v = 0; v < E.nvol; ++v) {
+      HIP_TRY(ctof::launch_fill_zero(mu[v], vol * sizeof(T), E.st));
+      HIP_TRY(ctof::launch_fill_zero(E.y(v), vol * sizeof(T), E.st));
+    }
+    HIP_TRY(ctof::launch_fill_zero(E.yhat(), E.L.mhat - E.L.yhat, E.st));
+    return CTOF_OK;
   }
+  for (int v = 0; v < E.nvol; ++v)
+    HIP_TRY(hipMemcpyAsync(E.y(v), mu[v], vol * sizeof(T), hipMemcpyDeviceToDevice, E.st));
   ctof::RowArgs a = E.row(ctof::ROW_SPATIAL_TO_SPEC, false);
   for (int v = 0; v < E.nvol; ++v) a.sp_in[v] = E.y(v);
+  HIP_TRY(E.mu_to_spec(a));
+  return CTOF_OK;
+}
+
+// Resumed start: y_v = mu_v + beta (mu_v - prev_v) (mu_v = mu_k0, prev_v =
+// mu_{k0-1}, beta = beta_{k0}) and the spectrum of y.
+template <typename T>
+ctof_status enqueue_resume(const Engine<T> &E, void *const *mu, const void *const *prev, double beta) {
+  ctof::RowArgs a = E.row(ctof::ROW_EXTRAPOLATE, false);
+  for (int v = 0; v < E.nvol; ++v) {
+    a.sp_in[v] = mu[v];
+    a.sp_aux[v] = const_cast<void *>(prev[v]);
+    a.sp_out[v] = E.y(v);
+  }
+  a.beta = beta;
   HIP_TRY(E.mu_to_spec(a));
   return CTOF_OK;
 }
@@ -692,6 +765,8 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
   void *mm[1] = {mu};
   double *scal = E.scal();
   const int K = opt->max_iter;
+  const int k0 = opt->k0;
+  const size_t vol = (size_t)dm.nz * dm.ny * dm.nx;
   // scalars: [0] |w|^2  [1] <v,w>  [3] final fit  [5..6] last history row
   HIP_TRY(ctof::launch_fill_zero(scal, 64 * 8, st));
   if (opt->lambda_l1_z) {
@@ -702,12 +777,20 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
   if (opt->mux) {
     if (ctof_status s = make_mux(k, opt->mux, &mux); s != CTOF_OK) return s;
     E.mux = &mux;
-    // the gradient-mapping denominator needs A^T S^T y: S^T y into mhat first
-    std::vector<const void *> sty;
-    if (ctof_status s = enqueue_mux_adjoint_data(E, dd, sty); s != CTOF_OK) return s;
-    if (ctof_status s = enqueue_gmap0(E, sty.data()); s != CTOF_OK) return s;
-  } else {
-    if (ctof_status s = enqueue_gmap0(E, dd); s != CTOF_OK) return s;
+  }
+  // A zero start takes its first step from y = 0, where the gradient is
+  // -A^T d: the gradient-mapping denominator ||max(0, A^T d)|| is then
+  // accumulated inside that step instead of by a separate adjoint.
+  const bool fused_g0 = opt->warm_start == 0 && k0 == 0;
+  if (!fused_g0) {
+    if (E.mux) {
+      // the gradient-mapping denominator needs A^T S^T y: S^T y into mhat first
+      std::vector<const void *> sty;
+      if (ctof_status s = enqueue_mux_adjoint_data(E, dd, sty); s != CTOF_OK) return s;
+      if (ctof_status s = enqueue_gmap0(E, sty.data()); s != CTOF_OK) return s;
+    } else {
+      if (ctof_status s = enqueue_gmap0(E, dd); s != CTOF_OK) return s;
+    }
   }
 
   double lam = opt->lambda_tikhonov, Lip = opt->lipschitz, LA = 0.0;
@@ -730,8 +813,16 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
   rep->lambda = lam;
   rep->lipschitz_a = LA;
 
-  if (ctof_status s = enqueue_start(E, mm, opt->warm_start != 0); s != CTOF_OK) return s;
-  const std::vector<double> beta = fista_betas(K);
+  // step weights beta_k for k = kb .. k0 + K - 1 (beta_{k0-1} extrapolates a resumed start)
+  const int kb = std::max(k0 - 1, 0);
+  const std::vector<double> btab = fista_betas(kb, k0 + K - kb);
+  auto beta_at = [&](int kk) { return btab[(size_t)(kk - kb)]; };
+  if (k0 > 0) {
+    const void *prev[1] = {opt->mu_prev_dev};
+    if (ctof_status s = enqueue_resume(E, mm, prev, beta_at(k0 - 1)); s != CTOF_OK) return s;
+  } else {
+    if (ctof_status s = enqueue_start(E, mm, opt->warm_start != 0); s != CTOF_OK) return s;
+  }
   // optional stage timing: events around the contraction and FFT groups of
   // every `timing`-th iteration (0, n, 2n, ...) and one at the loop's end
   const int tstride = opt->timing;
@@ -751,7 +842,13 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
     return (tstride > 0 && it % tstride == 0) ? hipEventRecord(ev[(size_t)(it / tstride) * 5 + j], st)
                                               : hipSuccess;
   };
+  // iterations after which the loop may stop: there mu_{k-1} is kept for a
+  // later resumption
   int done = 0;
+  int base = 0;  // first iteration of the kept run (1 after a zero-start fallback)
+  auto may_stop = [&](int it) {
+    return it == K - 1 || (opt->rel_tol > 0 && (it + 1 - base) % opt->check_every == 0);
+  };
   for (int it = 0; it < K; ++it) {
     double *pk = E.part() + (size_t)it * E.L.part_stride;
     HIP_TRY(mark(it, 0));
@@ -775,11 +872,15 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
     b.sp_in[0] = E.y(0);
     b.sp_out[0] = E.y(0);
     b.sp_aux[0] = mu;
+    if (opt->mu_prev_dev && may_stop(it)) b.sp_prev[0] = opt->mu_prev_dev;
     b.partials = pk + 2 * (size_t)E.L.nblk_t;
     b.tau = tau;
     b.lambda = lam;
-    b.beta = beta[it];
+    b.beta = beta_at(k0 + it - base);
+    if (fused_g0 && it == 0) b.gmap0_at = 0;
     HIP_TRY(E.run_row(b));
+    if (fused_g0 && it == 0)
+      HIP_TRY(ctof::launch_reduce_volumes(pk + 2 * (size_t)E.L.nblk_t + 1, E.L.nblk_z, 1, E.g0sq(), st));
     HIP_TRY(E.col_z(false));
     HIP_TRY(mark(it, 4));
     done = it + 1;
@@ -790,11 +891,14 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
       HIP_TRY(hipMemcpyAsync(h1, scal + 5, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
       HIP_TRY(hipStreamSynchronize(st));
       if (!(h1[1] <= 1.0)) {
+        // a fresh zero start: the next step is the first of its sequence
         rep->fell_back = 1;
+        base = 1;
         if (ctof_status s = restart_from_zero(E, mm, std::vector<int>{1}); s != CTOF_OK) return s;
       }
     }
-    if (opt->rel_tol > 0 && (done % opt->check_every == 0) && done < K) {
+    // checks follow the kept run's count (a restarted scan stops where a zero start would)
+    if (opt->rel_tol > 0 && done > base && ((done - base) % opt->check_every == 0) && done < K) {
       HIP_TRY(ctof::launch_history(E.part() + (size_t)it * E.L.part_stride, 1, 1, E.L.nblk_t, E.L.nblk_z,
                                    E.L.part_stride, tau, E.g0sq(), scal + 5, st));
       double h2[2];
@@ -805,18 +909,21 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
     }
   }
   if (tstride > 0) HIP_TRY(hipEventRecord(ev[(size_t)nsamp * 5], st));  // end of the loop
-  HIP_TRY(ctof::launch_history(E.part(), done, 1, E.L.nblk_t, E.L.nblk_z, E.L.part_stride, tau, E.g0sq(),
-                               E.hist(), st));
-  if (opt->history_dev)
-    HIP_TRY(hipMemcpyAsync(opt->history_dev, E.hist(), (size_t)done * 2 * sizeof(double),
+  const int kept = done - base;
+  HIP_TRY(ctof::launch_history(E.part() + (size_t)base * E.L.part_stride, kept, 1, E.L.nblk_t, E.L.nblk_z,
+                               E.L.part_stride, tau, E.g0sq(), E.hist(), st));
+  if (opt->history_dev && kept > 0)
+    HIP_TRY(hipMemcpyAsync(opt->history_dev, E.hist(), (size_t)kept * 2 * sizeof(double),
                            hipMemcpyDeviceToDevice, st));
   if (ctof_status s = enqueue_final_fit(E, dd, mm, E.part() + (size_t)K * E.L.part_stride, scal + 3);
       s != CTOF_OK)
     return s;
-  double hs[4], h0[2], hl[2], g0;
+  double hs[4], h0[2] = {0, 0}, hl[2] = {0, 0}, g0;
   HIP_TRY(hipMemcpyAsync(hs, scal, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(h0, E.hist(), 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIP_TRY(hipMemcpyAsync(hl, E.hist() + 2 * (size_t)(done - 1), 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  if (kept > 0) {
+    HIP_TRY(hipMemcpyAsync(h0, E.hist(), 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hl, E.hist() + 2 * (size_t)(kept - 1), 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  }
   HIP_TRY(hipMemcpyAsync(&g0, E.g0sq(), sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   if (tstride > 0 && done > 0) {
@@ -841,16 +948,23 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
     rep->timed_iters = ntimed;
   }
   rep->iters = done;
+  rep->fista_k = k0 + kept;
   rep->datafit0 = h0[0];
   rep->datafit = hs[3];
   rep->gmap_ratio = hl[1];
+  if (kept == 0) {
+    // a one-iteration call that fell back returns the zero start itself,
+    // whose ratio is 1 by the definition of the denominator
+    rep->datafit0 = hs[3];
+    rep->gmap_ratio = 1.0;
+  }
   rep->gmap0 = std::sqrt(g0);
   rep->status = CTOF_OK;
-  (void)dm;
+  (void)vol;
   if (!std::isfinite(rep->datafit) || !std::isfinite(rep->datafit0) || !std::isfinite(rep->gmap_ratio) ||
       !std::isfinite(rep->gmap0)) {
     rep->status = CTOF_ENONFINITE;
-    return set_error(CTOF_ENONFINITE, "non-finite FP64 norm during the solve");
+    return set_error(CTOF_ENONFINITE, "non-finite FP64 norm during the solve (stopped after %d iterations)", done);
   }
   return CTOF_OK;
 }
@@ -920,7 +1034,10 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
   char *base = reinterpret_cast<char *>(ws);
   std::vector<Engine<T>> E;
   std::vector<std::vector<const void *>> dv(cls.size());
-  std::vector<std::vector<void *>> mv(cls.size());
+  std::vector<std::vector<void *>> mv(cls.size()), pv(cls.size());
+  const int k0 = opt->k0;
+  // a zero start accumulates ||max(0, A^T d)|| inside its first step (see run_reconstruct)
+  const bool fused_g0 = opt->warm_start == 0 && k0 == 0;
   std::vector<ctof::MuxArgs> muxes(cls.size());  // sized once: the engines keep pointers into it
   for (size_t c = 0; c < cls.size(); ++c) {
     E.push_back(Engine<T>{cls[c].k, (int)cls[c].scans.size(), base + cls[c].off, cls[c].L, st});
@@ -936,12 +1053,16 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
     for (int i : cls[c].scans) {
       dv[c].push_back(d[i]);
       mv[c].push_back(mu[i]);
+      pv[c].push_back(opt->mu_prev_scans ? opt->mu_prev_scans[i] : nullptr);
     }
   }
+  auto prev_of = [&](size_t c) -> void *const * { return opt->mu_prev_scans ? pv[c].data() : nullptr; };
   // set-up: ||G(0)|| per volume and L_A per class (one vector per class)
   for (size_t c = 0; c < cls.size(); ++c) {
     HIP_TRY(ctof::launch_fill_zero(E[c].scal(), 64 * 8, st));
-    if (E[c].mux) {
+    if (fused_g0) {
+      // nothing here: the first step fills g0sq
+    } else if (E[c].mux) {
       std::vector<const void *> sty;
       if (ctof_status s = enqueue_mux_adjoint_data(E[c], dv[c].data(), sty); s != CTOF_OK) return s;
       if (ctof_status s = enqueue_gmap0(E[c], sty.data()); s != CTOF_OK) return s;
@@ -980,11 +1101,28 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
     cls[c].lip = lip;
     cls[c].lip_a = la;
     cls[c].tau = 1.0 / lip;
-    if (ctof_status s = enqueue_start(E[c], mv[c].data(), opt->warm_start != 0); s != CTOF_OK) return s;
-    HIP_TRY(ctof::launch_beta_table(E[c].beta(), K, st));
+    if (k0 > 0) {
+      std::vector<const void *> prev(pv[c].begin(), pv[c].end());
+      if (ctof_status s = enqueue_resume(E[c], mv[c].data(), prev.data(), fista_betas(k0 - 1, 1)[0]); s != CTOF_OK)
+        return s;
+    } else {
+      if (ctof_status s = enqueue_start(E[c], mv[c].data(), opt->warm_start != 0); s != CTOF_OK) return s;
+    }
+    HIP_TRY(ctof::launch_beta_table(E[c].beta(), k0, K, st));
     HIP_TRY(ctof::launch_fill_int(E[c].ctr(), 1, 0, st));
     HIP_TRY(ctof::launch_fill_int(E[c].active(), E[c].nvol, 1, st));
+    HIP_TRY(ctof::launch_fill_int(E[c].boff(), E[c].nvol, 0, st));
   }
+  // ||max(0, A^T d_v)||^2 from the partials of the first step of a zero start
+  bool g0_pending = fused_g0;
+  auto reduce_g0 = [&]() -> ctof_status {
+    if (!g0_pending) return CTOF_OK;
+    for (size_t c = 0; c < cls.size(); ++c)
+      HIP_TRY(ctof::launch_reduce_volumes(E[c].part() + 2 * (size_t)cls[c].L.nblk_t + 1, cls[c].L.nblk_z,
+                                          E[c].nvol, E[c].g0sq(), st));
+    g0_pending = false;
+    return CTOF_OK;
+  };
   // iterations: chunks of `chunk` iterations of every live class, captured once
   // as a graph on an internal stream and replayed on the caller's stream
   const int chunk = std::max(1, std::min(opt->rel_tol > 0 ? opt->check_every : K, 50));
@@ -1009,7 +1147,8 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
     for (size_t c = 0; c < cls.size(); ++c) {
       Engine<T> Ec = E[c];
       Ec.live = E[c].active();
-      if (ctof_status s = enqueue_iteration(Ec, dv[c].data(), mv[c].data(), cls[c].tau, cls[c].lam, true, 0, 0.0);
+      if (ctof_status s = enqueue_iteration(Ec, dv[c].data(), mv[c].data(), cls[c].tau, cls[c].lam, true, 0, 0.0,
+                                            prev_of(c));
           s != CTOF_OK)
         return s;
       const ClassWs &L = cls[c].L;
@@ -1023,7 +1162,10 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
     for (size_t c = 0; c < cls.size(); ++c) {
       for (int v = 0; v < E[c].nvol; ++v) fell[c][v] = (first[c][2 * v + 1] <= 1.0) ? 0 : 1;
       if (ctof_status s = restart_from_zero(E[c], mv[c].data(), fell[c]); s != CTOF_OK) return s;
+      // a restarted volume begins its own step sequence: beta index = counter - 1
+      HIP_TRY(hipMemcpyAsync(E[c].boff(), fell[c].data(), fell[c].size() * sizeof(int), hipMemcpyHostToDevice, st));
     }
+    HIP_TRY(hipStreamSynchronize(st));  // the host flags above are copied before they go out of scope
     done = 1;
   }
   while (done < K) {
@@ -1063,7 +1205,8 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
               Engine<T> Ec = E[c];
               Ec.st = sg.br[b];
               Ec.live = E[c].active();
-              cap = enqueue_iteration(Ec, dv[c].data(), mv[c].data(), cls[c].tau, cls[c].lam, true, 0, 0.0);
+              cap = enqueue_iteration(Ec, dv[c].data(), mv[c].data(), cls[c].tau, cls[c].lam, true, 0, 0.0,
+                                      prev_of(c), fused_g0);
               if (cap != CTOF_OK) break;
             }
         for (int b = 0; b < nb && ce == hipSuccess; ++b) {
@@ -1087,11 +1230,12 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
             Engine<T> Ec = E[c];
             Ec.live = E[c].active();
             if (ctof_status s = enqueue_iteration(Ec, dv[c].data(), mv[c].data(), cls[c].tau, cls[c].lam,
-                                                  true, 0, 0.0);
+                                                  true, 0, 0.0, prev_of(c), fused_g0);
                 s != CTOF_OK)
               return s;
           }
     }
+    if (ctof_status s = reduce_g0(); s != CTOF_OK) return s;
     done += n_this;
     if (opt->rel_tol > 0 && done < K) {
       std::vector<std::vector<double>> last(cls.size());
@@ -1124,6 +1268,7 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
       }
     }
   }
+  if (ctof_status s = reduce_g0(); s != CTOF_OK) return s;
   // reports: full history, final data fit per volume
   std::vector<std::vector<double>> hist(cls.size()), fit(cls.size()), g0(cls.size());
   for (size_t c = 0; c < cls.size(); ++c) {
@@ -1151,7 +1296,9 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
       std::memset(&r, 0, sizeof(r));
       const int its = conv[c][v] > 0 ? conv[c][v] : std::max(1, done);
       r.iters = its;
-      r.datafit0 = hist[c][(size_t)v * 2];
+      r.fista_k = k0 + its - fell[c][v];
+      // the kept run of a restarted volume begins at its second row
+      r.datafit0 = hist[c][((size_t)fell[c][v] * nv + v) * 2];
       r.gmap_ratio = hist[c][((size_t)(its - 1) * nv + v) * 2 + 1];
       r.datafit = fit[c][v];
       r.lipschitz = cls[c].lip;
@@ -1566,8 +1713,12 @@ ctof_status ctof_reconstruct(ctof_kernel k, const void *d_dev, void *mu_inout_de
   if (opts->rel_tol > 0 && opts->check_every < 1) return set_error(CTOF_EINVAL, "check_every must be >= 1");
   if (opts->warm_start < 0 || opts->warm_start > 2) return set_error(CTOF_EINVAL, "warm_start must be 0, 1 or 2");
   if (opts->timing < 0) return set_error(CTOF_EINVAL, "timing must be >= 0");
-  if (opts->lipschitz_scans || opts->lambda_scans)
-    return set_error(CTOF_EINVAL, "lipschitz_scans / lambda_scans are batched options");
+  if (opts->lipschitz_scans || opts->lambda_scans || opts->mu_prev_scans)
+    return set_error(CTOF_EINVAL, "lipschitz_scans / lambda_scans / mu_prev_scans are batched options");
+  if (ctof_status e = check_resume(opts, opts->mu_prev_dev != nullptr); e != CTOF_OK) return e;
+  if (opts->mu_prev_dev &&
+      overlaps(opts->mu_prev_dev, mu_inout_dev, (size_t)k->dims.nz * k->dims.ny * k->dims.nx * elem_size(k->prec)))
+    return set_error(CTOF_EINVAL, "mu_prev_dev overlaps mu_inout_dev");
   if (opts->lambda_l1_z)
     for (int z = 0; z < k->dims.nz; ++z)
       if (!(std::isfinite(opts->lambda_l1_z[z]) && opts->lambda_l1_z[z] >= 0))
@@ -1581,6 +1732,46 @@ ctof_status ctof_reconstruct(ctof_kernel k, const void *d_dev, void *mu_inout_de
   std::memset(report, 0, sizeof(*report));
   if (k->prec == CTOF_FP64) return run_reconstruct<double>(k, d_dev, mu_inout_dev, opts, report, ws_dev, stream);
   return run_reconstruct<float>(k, d_dev, mu_inout_dev, opts, report, ws_dev, stream);
+}
+
+ctof_status ctof_layer_energy_ws_bytes(ctof_kernel k, size_t *ws_bytes) {
+  if (ctof_status s = check_kernel(k); s != CTOF_OK) return s;
+  if (!ws_bytes) return set_error(CTOF_EINVAL, "ws_bytes is NULL");
+  *ws_bytes = class_ws(k, 1, k->dims.nz).solve_total;
+  return CTOF_OK;
+}
+
+ctof_status ctof_l1_depth_weights(ctof_kernel k, double lambda1, double *energy, double *weights, void *ws_dev,
+                                  size_t ws_bytes, hipStream_t stream) {
+  if (ctof_status s = check_kernel(k); s != CTOF_OK) return s;
+  if (!(std::isfinite(lambda1) && lambda1 >= 0)) return set_error(CTOF_EINVAL, "lambda1 must be finite and >= 0");
+  if (!ws_dev) return set_error(CTOF_EINVAL, "workspace is NULL");
+  const ClassWs o = class_ws(k, 1, k->dims.nz);
+  if (ws_bytes < o.solve_total) return set_error(CTOF_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, o.solve_total);
+  const int nz = k->dims.nz;
+  std::vector<double> e((size_t)nz);
+  if (k->prec == CTOF_FP64) {
+    const Engine<double> E = engine<double>(k, 1, ws_dev, nz, stream);
+    if (ctof_status s = enqueue_layer_energy(E, E.hist()); s != CTOF_OK) return s;
+    HIP_TRY(hipMemcpyAsync(e.data(), E.hist(), (size_t)nz * sizeof(double), hipMemcpyDeviceToHost, stream));
+  } else {
+    const Engine<float> E = engine<float>(k, 1, ws_dev, nz, stream);
+    if (ctof_status s = enqueue_layer_energy(E, E.hist()); s != CTOF_OK) return s;
+    HIP_TRY(hipMemcpyAsync(e.data(), E.hist(), (size_t)nz * sizeof(double), hipMemcpyDeviceToHost, stream));
+  }
+  HIP_TRY(hipStreamSynchronize(stream));
+  double emax = 0.0;
+  for (int z = 0; z < nz; ++z) {
+    e[z] *= 2.0;  // the row pass sums 1/2 x^2
+    if (!std::isfinite(e[z])) return set_error(CTOF_ENONFINITE, "non-finite layer energy at layer %d", z);
+    emax = std::max(emax, e[z]);
+  }
+  if (!(emax > 0)) return set_error(CTOF_ENONFINITE, "every layer energy is zero");
+  for (int z = 0; z < nz; ++z) {
+    if (energy) energy[z] = e[z];
+    if (weights) weights[z] = lambda1 * e[z] / emax;
+  }
+  return CTOF_OK;
 }
 
 ctof_status ctof_workspace_bytes_batched(int32_t nscan, const ctof_kernel *k, int32_t max_iter,
@@ -1620,8 +1811,20 @@ ctof_status ctof_reconstruct_batched(int32_t nscan, const ctof_kernel *k, const 
   if (!(std::isfinite(opts->rel_tol) && opts->rel_tol >= 0)) return set_error(CTOF_EINVAL, "rel_tol must be >= 0");
   if (opts->rel_tol > 0 && opts->check_every < 1) return set_error(CTOF_EINVAL, "check_every must be >= 1");
   if (opts->warm_start < 0 || opts->warm_start > 2) return set_error(CTOF_EINVAL, "warm_start must be 0, 1 or 2");
-  if (opts->history_dev || opts->timing)
-    return set_error(CTOF_EINVAL, "history_dev and timing are single-scan options");
+  if (opts->history_dev || opts->timing || opts->mu_prev_dev)
+    return set_error(CTOF_EINVAL, "history_dev, timing and mu_prev_dev are single-scan options");
+  {
+    bool all_prev = opts->mu_prev_scans != nullptr;
+    if (opts->mu_prev_scans)
+      for (int i = 0; i < nscan; ++i) {
+        const size_t vb = (size_t)k[i]->dims.nz * k[i]->dims.ny * k[i]->dims.nx * elem_size(prec);
+        if (!opts->mu_prev_scans[i]) all_prev = false;
+        else if (overlaps(opts->mu_prev_scans[i], mu_inout_dev[i], vb))
+          return set_error(CTOF_EINVAL, "mu_prev_scans[%d] overlaps mu_inout_dev[%d]", i, i);
+      }
+    if (opts->mu_prev_scans && !all_prev) return set_error(CTOF_EINVAL, "mu_prev_scans has a NULL entry");
+    if (ctof_status e = check_resume(opts, all_prev); e != CTOF_OK) return e;
+  }
   if ((opts->lipschitz_scans == nullptr) != (opts->lambda_scans == nullptr))
     return set_error(CTOF_EINVAL, "lipschitz_scans and lambda_scans go together");
   if (opts->lambda_l1_z) {

@@ -131,7 +131,8 @@ enum RowOp : int {
   ROW_FISTA = 4,             // c2r -> prox/FISTA update -> r2c of y_{k+1}
   ROW_POWER_W = 5,           // c2r -> store w, partials |w|^2 and <v, w>
   ROW_GMAP0 = 6,             // c2r -> partial |max(0, x)|^2
-  ROW_SCALE_TO_SPEC = 7      // spatial w * (1/sqrt(scalar)) -> store v -> r2c
+  ROW_SCALE_TO_SPEC = 7,     // spatial w * (1/sqrt(scalar)) -> store v -> r2c
+  ROW_EXTRAPOLATE = 8        // y = mu + beta (mu - mu_prev) -> store y -> r2c (resumed FISTA)
 };
 
 struct RowArgs {
@@ -154,6 +155,11 @@ struct RowArgs {
   const double *scalar;  // device scalar (ROW_SCALE_TO_SPEC: |w|^2)
   const double *l1;      // device per-layer L1 weights (ROW_FISTA, ROW_GMAP0), or NULL
   double tau, lambda, beta;
+  void *sp_prev[kMaxVol];  // ROW_FISTA: per volume, receives mu_{k-1} (the iterate being replaced), or NULL
+  const int *beta_off;     // per volume: subtracted from the counter for the beta index (NULL: 0)
+  int gmap0_at;            // ROW_FISTA: at this iteration (the counter's value, 0 without one) partial 1
+                           // also receives |max(0, -x - l1)|^2, the gradient mapping at zero when y = 0
+                           // (x = A^T (A 0 - d) = -A^T d); -1: never
 };
 
 template <typename T>
@@ -224,7 +230,8 @@ hipError_t launch_history(const double *partials, int iters, int nvol, int nblk_
 // out[v] = sum of partial 0 over the v-th of nvol equal block ranges
 hipError_t launch_reduce_volumes(const double *partials, int nblk, int nvol, double *out, hipStream_t st);
 hipError_t launch_increment(int *ctr, hipStream_t st);
-hipError_t launch_beta_table(double *beta, int iters, hipStream_t st);
+// beta[j] = beta_{first + j} of FISTA's step sequence, j < count
+hipError_t launch_beta_table(double *beta, int first, int count, hipStream_t st);
 hipError_t launch_fill_int(int *p, int n, int v, hipStream_t st);
 hipError_t launch_fill_value(float *p, size_t n, float v, hipStream_t st);
 hipError_t launch_fill_value_f64(double *p, size_t n, double v, hipStream_t st);

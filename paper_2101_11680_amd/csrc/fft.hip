@@ -461,6 +461,15 @@ col_pass_2048_kernel(int ny, int B, const T *__restrict__ in, T *__restrict__ ou
   }
 }
 
+// FISTA's extrapolation y = mu + beta (mu - mu_prev), one rounding of the
+// product-sum (the same expression wherever a step is taken or resumed, so a
+// resumed solve reproduces an uninterrupted one bit for bit).
+template <typename T>
+__device__ __forceinline__ T fista_extrapolate(T mu, T mprev, T beta) {
+  if constexpr (sizeof(T) == 8) return __builtin_fma(beta, mu - mprev, mu);
+  else return __builtin_fmaf(beta, mu - mprev, mu);
+}
+
 // ---- row pass --------------------------------------------------------------------
 // One block per (scan row i, BB planes): c2r along ky, crop, pointwise step,
 // pad, r2c.  A real DFT of length P is a complex DFT of length H = P/2 on
@@ -486,9 +495,12 @@ row_pass_kernel(int ny, int nx, RowArgs a) {
   const bool vol_on = vol < a.nvol;
   if (a.active != nullptr && vol_on && a.active[vol] == 0) return;  // frozen volume
   const int it = a.iter_ctr ? *a.iter_ctr : 0;
-  const bool spec_in = (op != ROW_SPATIAL_TO_SPEC) && (op != ROW_SCALE_TO_SPEC);
+  const bool spec_in = (op != ROW_SPATIAL_TO_SPEC) && (op != ROW_SCALE_TO_SPEC) && (op != ROW_EXTRAPOLATE);
   const bool spec_out = (op == ROW_SPATIAL_TO_SPEC) || (op == ROW_SCALE_TO_SPEC) ||
-                        (op == ROW_RESIDUAL) || (op == ROW_PASS) || (op == ROW_FISTA);
+                        (op == ROW_RESIDUAL) || (op == ROW_PASS) || (op == ROW_FISTA) ||
+                        (op == ROW_EXTRAPOLATE);
+  // the gradient mapping at zero rides along the first step of a zero start
+  const bool g0acc = op == ROW_FISTA && a.gmap0_at >= 0 && it == a.gmap0_at;
   const int nh = (nx + 1) / 2;
   build_twiddles<T, P>(twc, tws);
   __syncthreads();
@@ -551,19 +563,21 @@ row_pass_kernel(int ny, int nx, RowArgs a) {
   // x[j] lives in the slot that receives r[j])
   double acc0 = 0.0, acc1 = 0.0;
   const T tau = (T)a.tau, lam = (T)a.lambda;
-  const T beta = a.beta_tab ? (T)a.beta_tab[it] : (T)a.beta;
+  const int boff = (a.beta_off != nullptr && vol_on) ? a.beta_off[vol] : 0;
+  const T beta = a.beta_tab ? (T)a.beta_tab[it - boff] : (T)a.beta;
   T scale = (T)1;
   if (op == ROW_SCALE_TO_SPEC) scale = (T)(1.0 / sqrt(*a.scalar));
   const T *sp_in = vol_on ? reinterpret_cast<const T *>(a.sp_in[vol]) : nullptr;
   T *sp_out = vol_on ? reinterpret_cast<T *>(a.sp_out[vol]) : nullptr;
   T *sp_aux = vol_on ? reinterpret_cast<T *>(a.sp_aux[vol]) : nullptr;
+  T *sp_prev = vol_on ? reinterpret_cast<T *>(a.sp_prev[vol]) : nullptr;
   // the spatial inputs of four rounds are loaded before any is used (the
   // same units in the same order per thread as one round at a time); each
   // element is read and written by one thread, so outputs that alias an
   // input (FISTA's y) stay correct
   const bool rd_in = op == ROW_SPATIAL_TO_SPEC || op == ROW_SCALE_TO_SPEC || op == ROW_RESIDUAL ||
-                     op == ROW_FISTA || op == ROW_POWER_W;
-  const bool rd_aux = op == ROW_FISTA;
+                     op == ROW_FISTA || op == ROW_POWER_W || op == ROW_EXTRAPOLATE;
+  const bool rd_aux = op == ROW_FISTA || op == ROW_EXTRAPOLATE;
   constexpr int NQ = 4;
   const int NP = nx * BB;
   for (int u0 = tid; u0 < NP; u0 += NQ * NT) {
@@ -621,11 +635,25 @@ row_pass_kernel(int ny, int nx, RowArgs a) {
             T mu = yk - tau * (x + lam * yk);
             if (a.l1) mu -= tau * (T)a.l1[pl];  // prox of the per-layer L1 term
             mu = mu > (T)0 ? mu : (T)0;
-            const T ynew = mu + beta * (mu - mprev);
+            const T ynew = fista_extrapolate(mu, mprev, beta);
+            if (sp_prev) sp_prev[idx] = mprev;
             sp_aux[idx] = mu;
             sp_out[idx] = ynew;
             const double dd = (double)yk - (double)mu;
             acc0 += dd * dd;
+            if (g0acc) {
+              // y = 0 here, so x = -A^T d exactly (negation is exact in every step)
+              const double v = -(double)x - (a.l1 ? a.l1[pl] : 0.0);
+              const double gz = v > 0.0 ? v : 0.0;
+              acc1 += gz * gz;
+            }
+            r = ynew;
+          }
+          break;
+        case ROW_EXTRAPOLATE:
+          if (valid) {
+            const T ynew = fista_extrapolate(yin[q], yaux[q], beta);
+            sp_out[idx] = ynew;
             r = ynew;
           }
           break;

@@ -71,13 +71,14 @@ __global__ void increment_kernel(int *ctr) {
   if (threadIdx.x == 0) *ctr += 1;
 }
 
-// beta_k = (t_k - 1) / t_{k+1}, t_1 = 1, t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2
-__global__ void beta_table_kernel(double *beta, int iters) {
+// beta_k = (t_k - 1) / t_{k+1}, t_1 = 1, t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2;
+// entries first .. first + count - 1 go to beta[0 ..)
+__global__ void beta_table_kernel(double *beta, int first, int count) {
   if (threadIdx.x != 0) return;
   double t = 1.0;
-  for (int k = 0; k < iters; ++k) {
+  for (int k = 0; k < first + count; ++k) {
     const double tn = (1.0 + sqrt(1.0 + 4.0 * t * t)) / 2.0;
-    beta[k] = (t - 1.0) / tn;
+    if (k >= first) beta[k - first] = (t - 1.0) / tn;
     t = tn;
   }
 }
@@ -126,8 +127,8 @@ hipError_t launch_increment(int *ctr, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_beta_table(double *beta, int iters, hipStream_t st) {
-  hipLaunchKernelGGL(beta_table_kernel, dim3(1), dim3(64), 0, st, beta, iters);
+hipError_t launch_beta_table(double *beta, int first, int count, hipStream_t st) {
+  hipLaunchKernelGGL(beta_table_kernel, dim3(1), dim3(64), 0, st, beta, first, count);
   return hipGetLastError();
 }
 

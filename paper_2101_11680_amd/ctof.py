@@ -37,7 +37,7 @@ EXPORTS = ("ctof_kernel_bytes", "ctof_kernel_tabulate", "ctof_kernel_tabulate_qu
            "ctof_warmstart_loss", "ctof_absmax_ws_bytes", "ctof_absmax", "ctof_depth_resample",
            "ctof_sumsq_ws_bytes", "ctof_sumsq", "ctof_layer_threshold_ws_bytes", "ctof_layer_threshold",
            "ctof_mux_forward", "ctof_mux_adjoint", "ctof_mux_normal_ws_bytes", "ctof_mux_normal",
-           "ctof_noisy_counts")
+           "ctof_noisy_counts", "ctof_layer_energy_ws_bytes", "ctof_l1_depth_weights")
 
 
 class CtofError(RuntimeError):
@@ -71,7 +71,8 @@ class _SolverOpts(ctypes.Structure):
                 ("timing", ctypes.c_int32), ("lipschitz_scans", ctypes.POINTER(ctypes.c_double)),
                 ("lambda_scans", ctypes.POINTER(ctypes.c_double)),
                 ("lambda_l1_z", ctypes.POINTER(ctypes.c_double)),
-                ("mux", ctypes.POINTER(_Mux))]
+                ("mux", ctypes.POINTER(_Mux)), ("mu_prev_dev", ctypes.c_void_p),
+                ("k0", ctypes.c_int32), ("mu_prev_scans", ctypes.POINTER(ctypes.c_void_p))]
 
 
 class _SolverReport(ctypes.Structure):
@@ -82,7 +83,8 @@ class _SolverReport(ctypes.Structure):
                 ("gmap0", ctypes.c_double), ("ms_contract_fwd", ctypes.c_double),
                 ("ms_fft_t", ctypes.c_double), ("ms_contract_adj", ctypes.c_double),
                 ("ms_fft_z", ctypes.c_double), ("ms_loop", ctypes.c_double),
-                ("fell_back", ctypes.c_int32), ("timed_iters", ctypes.c_int32)]
+                ("fell_back", ctypes.c_int32), ("timed_iters", ctypes.c_int32),
+                ("fista_k", ctypes.c_int32)]
 
 
 class _ConvDesc(ctypes.Structure):
@@ -164,6 +166,9 @@ def lib() -> ctypes.CDLL:
         L.ctof_sumsq.argtypes = [i32, i64, vp, vp, vp, sz, vp]
         L.ctof_layer_threshold_ws_bytes.argtypes = [i32, ctypes.POINTER(sz)]
         L.ctof_layer_threshold.argtypes = [i32, i64, vp, f32, vp, sz, vp]
+        L.ctof_layer_energy_ws_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+        L.ctof_l1_depth_weights.argtypes = [vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                            ctypes.POINTER(ctypes.c_double), vp, sz, vp]
         mp = ctypes.POINTER(_Mux)
         L.ctof_mux_forward.argtypes = [vp, mp, vp, vp, vp]
         L.ctof_mux_adjoint.argtypes = [vp, mp, vp, vp, vp]
@@ -365,6 +370,7 @@ class Report:
     ms_loop: float = 0.0
     fell_back: int = 0
     timed_iters: int = 0
+    fista_k: int = 0
 
 
 def _l1_array(l1, nz):
@@ -467,13 +473,18 @@ def noisy_counts(m, scale: float, background: float, seed: int, stream_id: int =
 def reconstruct(k: Kernel, d, mu=None, max_iter: int = 200, lam: float = -1.0,
                 lipschitz: float = 0.0, power_iters: int = 50, rel_tol: float = 0.0,
                 check_every: int = 10, warm_start: bool = False, history: bool = False,
-                timing: int = 0, l1=None, mux: Optional[Mux] = None, stream=None):
+                timing: int = 0, l1=None, mux: Optional[Mux] = None, mu_prev=None, k0: int = 0,
+                stream=None):
     """FISTA reconstruction; returns (mu, Report, history or None).  warm_start:
     0/False zero start, 1/True start from ``mu``, 2 start from ``mu`` with the
     zero-start fallback.  l1: per-layer L1 weights (nz numbers) or None.
     mux: a Mux when d holds multiplexed measurements y [nt][rows][ntiles].
     timing: 0 no stage events; n >= 1 (True = 1) events around the stages of
-    every n-th iteration, summed in the report's ms_* over timed_iters."""
+    every n-th iteration, summed in the report's ms_* over timed_iters.
+    mu_prev, k0: resumption (a device tensor shaped like mu, in/out): with
+    k0 >= 1 (and warm_start = 1) mu holds mu_k0 and mu_prev mu_{k0-1}; on
+    return mu_prev holds the iterate before the final one, and the report's
+    fista_k is the k0 that resumes the run."""
     torch = _torch()
     i = k.info
     if mux is None:
@@ -484,13 +495,16 @@ def reconstruct(k: Kernel, d, mu=None, max_iter: int = 200, lam: float = -1.0,
         mu = torch.empty((i.nz, i.ny, i.nx), dtype=d.dtype, device=d.device)
         warm_start = False
     mu = _contig(mu, d.dtype, (i.nz, i.ny, i.nx))
+    if mu_prev is not None:
+        mu_prev = _contig(mu_prev, d.dtype, (i.nz, i.ny, i.nx))
     hist = torch.zeros((max_iter, 2), dtype=torch.float64, device=d.device) if history else None
     l1a = _l1_array(l1, i.nz)
     mdesc = mux.desc(k) if mux is not None else None
     opts = _SolverOpts(int(max_iter), float(lam), float(lipschitz), int(power_iters),
                        float(rel_tol), int(check_every), int(warm_start),
                        hist.data_ptr() if hist is not None else None, int(timing), None, None, l1a,
-                       ctypes.pointer(mdesc) if mdesc is not None else None)
+                       ctypes.pointer(mdesc) if mdesc is not None else None,
+                       mu_prev.data_ptr() if mu_prev is not None else None, int(k0), None)
     rep = _SolverReport()
     _, nb = k.workspace_bytes(max_iter)
     ws = k.workspace(nb, d.device)
@@ -498,7 +512,7 @@ def reconstruct(k: Kernel, d, mu=None, max_iter: int = 200, lam: float = -1.0,
                                   ctypes.byref(rep), ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
     report = _report(rep)
     if hist is not None:
-        hist = hist[: rep.iters]
+        hist = hist[: rep.iters - rep.fell_back]
     return mu, report, hist
 
 
@@ -506,17 +520,20 @@ def _report(rep) -> Report:
     return Report(rep.iters, rep.status, rep.datafit0, rep.datafit, rep.gmap_ratio,
                   rep.lipschitz, rep.lambda_, rep.lipschitz_a, rep.gmap0, rep.ms_contract_fwd,
                   rep.ms_fft_t, rep.ms_contract_adj, rep.ms_fft_z, rep.ms_loop, rep.fell_back,
-                  rep.timed_iters)
+                  rep.timed_iters, rep.fista_k)
 
 
 def reconstruct_batched(kernels, ds, mus=None, max_iter: int = 200, lam=-1.0, lipschitz=0.0,
                         power_iters: int = 50, rel_tol: float = 0.0, check_every: int = 10,
-                        warm_start: bool = False, l1=None, mux: Optional[Mux] = None, stream=None):
+                        warm_start: bool = False, l1=None, mux: Optional[Mux] = None, mu_prevs=None,
+                        k0: int = 0, stream=None):
     """FISTA for many scans at once; scans sharing a Kernel object form one
     shape class.  lam / lipschitz: one value for all scans or one per scan
     (both sequences, then every scan's pair is used as given).  warm_start as
     in reconstruct.  mux: one Mux for every scan, each ds[i] then holding
-    scan i's multiplexed measurements.  Returns (list of mu, list of Report)."""
+    scan i's multiplexed measurements.  mu_prevs, k0: resumption as in
+    reconstruct, one mu_prev tensor per scan.  Returns (list of mu, list of
+    Report)."""
     torch = _torch()
     n = len(ds)
     if len(kernels) != n:
@@ -534,6 +551,13 @@ def reconstruct_batched(kernels, ds, mus=None, max_iter: int = 200, lam=-1.0, li
         if mu is None:
             mu = torch.empty((i.nz, i.ny, i.nx), dtype=d.dtype, device=d.device)
         outs.append(_contig(mu, d.dtype, (i.nz, i.ny, i.nx)))
+    prev_arr = None
+    if mu_prevs is not None:
+        if len(mu_prevs) != n:
+            raise ValueError("one mu_prev per scan")
+        prev_arr = (ctypes.c_void_p * n)(*[
+            _contig(p, _dtype(k.precision), (k.info.nz, k.info.ny, k.info.nx)).data_ptr()
+            for k, p in zip(kernels, mu_prevs)])
     handles = (ctypes.c_void_p * n)(*[k.handle.value for k in kernels])
     dptr = (ctypes.c_void_p * n)(*[d.data_ptr() for d in ds])
     mptr = (ctypes.c_void_p * n)(*[m.data_ptr() for m in outs])
@@ -548,11 +572,11 @@ def reconstruct_batched(kernels, ds, mus=None, max_iter: int = 200, lam=-1.0, li
         la = (ctypes.c_double * n)(*[float(x) for x in lipschitz])
         lb = (ctypes.c_double * n)(*[float(x) for x in lam])
         opts = _SolverOpts(int(max_iter), 0.0, 0.0, int(power_iters), float(rel_tol), int(check_every),
-                           int(warm_start), None, 0, la, lb, l1a, mptr_desc)
+                           int(warm_start), None, 0, la, lb, l1a, mptr_desc, None, int(k0), prev_arr)
     else:
         opts = _SolverOpts(int(max_iter), float(lam), float(lipschitz), int(power_iters),
                            float(rel_tol), int(check_every), int(warm_start), None, 0, None, None, l1a,
-                           mptr_desc)
+                           mptr_desc, None, int(k0), prev_arr)
     reps = (_SolverReport * n)()
     _check(lib().ctof_reconstruct_batched(n, handles, dptr, mptr, ctypes.byref(opts), reps,
                                           ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
@@ -652,36 +676,32 @@ def tune(k: Kernel, nvol: int = 1, iters: int = 5, cache: Optional[str] = None, 
     return bt.value, bz.value, times
 
 
+def _depth_rule(k: Kernel, lam1: float, stream=None):
+    import numpy as np
+    torch = _torch()
+    nz = k.info.nz
+    nb = ctypes.c_size_t()
+    _check(lib().ctof_layer_energy_ws_bytes(k.handle, ctypes.byref(nb)))
+    ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device="cuda")
+    e = (ctypes.c_double * nz)()
+    w = (ctypes.c_double * nz)()
+    _check(lib().ctof_l1_depth_weights(k.handle, float(lam1), e, w, ws.data_ptr(), ws.numel(),
+                                       _stream_ptr(stream)))
+    return np.array(e[:], dtype=np.float64), [float(v) for v in w]
+
+
 def layer_energy(k: Kernel, stream=None):
     """Per-layer sensitivity ||A e_z||^2 (host float64 [nz]): the forward
     model's response to a unit absorber at the window centre of each layer,
     squared and summed on the GPU (FP64)."""
-    torch = _torch()
-    i = k.info
-    dt = _dtype(k.precision)
-    if dt != torch.float32:
-        raise ValueError("layer_energy takes a float handle")
-    out = torch.zeros(i.nz, dtype=torch.float64, device="cuda")
-    nb = ctypes.c_size_t()
-    _check(lib().ctof_sumsq_ws_bytes(1, ctypes.byref(nb)))
-    ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device="cuda")
-    mu = torch.zeros((i.nz, i.ny, i.nx), dtype=dt, device="cuda")
-    for z in range(i.nz):
-        mu.zero_()
-        mu[z, i.ny // 2, i.nx // 2] = 1.0
-        m = forward(k, mu, stream=stream)
-        _check(lib().ctof_sumsq(1, int(m.numel()), m.data_ptr(), out[z:].data_ptr(), ws.data_ptr(), ws.numel(),
-                                _stream_ptr(stream)))
-    return out.cpu().numpy()
+    return _depth_rule(k, 0.0, stream)[0]
 
 
 def l1_depth_weights(k: Kernel, lam1: float, stream=None):
-    """Per-layer L1 weights lam1 * e(z) / max e(z), e(z) = ||A e_z||^2: a
-    voxel's soft threshold in absorption units, lambda(z) / e(z), is then the
-    same at every depth (the layer-wise weights of Eq. 10 counter the loss of
-    sensitivity with depth)."""
-    e = layer_energy(k, stream=stream)
-    return [float(lam1 * v / e.max()) for v in e]
+    """Per-layer L1 weights lam1 * e(z) / max e(z), e(z) = ||A e_z||^2, from
+    the library (Eq. 10's layer-wise weights: a voxel's soft threshold in
+    absorption units, lambda(z) / e(z), is then the same at every depth)."""
+    return _depth_rule(k, lam1, stream)[1]
 
 
 def layer_threshold(mu, frac: float, stream=None):

@@ -78,3 +78,61 @@ def sampled_adjoint(g, r, sources, samples):
         curves = kernel_curves(g, z, keys)
         out[n] = sum(float(curves[q] @ r[:, i, j]) for q, (i, j) in enumerate(sources))
     return out
+
+
+class BinRunOperator:
+    """The oracle's FFT-tier operator evaluated over runs of time bins.
+
+    Eq. 11 gives every time bin of m as a sum over layers of that bin's
+    kernel only, so the forward model is the concatenation of the forwards
+    of runs of bins and the adjoint the sum of the runs' adjoints (added in
+    run order).  Each run is an ``oracle.operator.FFTOperator`` of its own
+    slice of the kernel; runs are built and evaluated in parallel threads
+    (numpy's einsum and scipy's FFTs release the interpreter lock), which
+    keeps the full-size kernel spectrum in bounded pieces and uses every
+    host core.  Same interface as the oracle's operators.
+    """
+
+    def __init__(self, Kq, run: int = 32, threads=None):
+        import os
+        from concurrent.futures import ThreadPoolExecutor
+
+        from oracle import operator as oop
+        nz, n_y, n_x, nt = Kq.shape
+        self.shape = Kq.shape
+        self.bounds = [(t, min(nt, t + run)) for t in range(0, nt, run)]
+        self.threads = int(threads or os.cpu_count() or 1)
+        self._pool = ThreadPoolExecutor(self.threads)
+        self.ops = list(self._pool.map(
+            lambda b: oop.FFTOperator(np.ascontiguousarray(Kq[..., b[0]:b[1]]), workers=1), self.bounds))
+
+    def forward(self, mu):
+        parts = list(self._pool.map(lambda op: op.forward(mu), self.ops))
+        return np.concatenate(parts, axis=0)
+
+    def adjoint(self, r):
+        parts = list(self._pool.map(lambda ob: ob[0].adjoint(np.ascontiguousarray(r[ob[1][0]:ob[1][1]])),
+                                    zip(self.ops, self.bounds)))
+        out = parts[0]
+        for p in parts[1:]:
+            out = out + p
+        return out
+
+    def close(self):
+        self._pool.shutdown()
+        self.ops = []
+
+
+def tabulate_layers_parallel(g, threads=None):
+    """``oracle.kernel.tabulate(g)`` evaluated one layer per task in parallel
+    threads (each layer's kernel depends only on its own depth; the voxel
+    thickness is the geometry's, shared by the single-layer geometries)."""
+    import dataclasses
+    import os
+    from concurrent.futures import ThreadPoolExecutor
+
+    from oracle import kernel as okernel
+    subs = [dataclasses.replace(g, z_mm=(float(z),)) for z in g.z_mm]
+    with ThreadPoolExecutor(int(threads or os.cpu_count() or 1)) as ex:
+        parts = list(ex.map(okernel.tabulate, subs))
+    return np.concatenate(parts, axis=0)

@@ -42,3 +42,37 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode != 0
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_bin_run_driver_equals_the_oracle_operator():
+    # the bin-run evaluation that the full-size parity test and the CPU
+    # baseline drive is the oracle's operator: per-bin forward identical,
+    # adjoint equal up to the order of the bin sum, and the adjoint
+    # identity holds
+    import numpy as np
+
+    from oracle import operator as oop
+    from tests.gpu_common import BinRunOperator
+    rng = np.random.default_rng(5)
+    Kq = rng.random((4, 11, 7, 37))
+    A = oop.FFTOperator(Kq)
+    B = BinRunOperator(Kq, run=8, threads=3)
+    mu = rng.random((4, 11, 7))
+    r = rng.standard_normal((37, 11, 7))
+    np.testing.assert_array_equal(B.forward(mu), A.forward(mu))
+    ga, gb = A.adjoint(r), B.adjoint(r)
+    assert np.linalg.norm(ga - gb) <= 1e-14 * np.linalg.norm(ga)
+    lhs, rhs = float(np.vdot(B.forward(mu), r)), float(np.vdot(mu, gb))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+    B.close()
+
+
+def test_layer_parallel_tabulation_equals_the_oracle():
+    import numpy as np
+
+    from oracle import kernel as okernel
+    from synth.workloads import Geometry, even_layers
+    from tests.gpu_common import tabulate_layers_parallel
+    z, dz = even_layers(1.0, 9.0, 5)
+    g = Geometry(nx=7, ny=5, pitch_mm=0.5, z_mm=z, dz_mm=dz, nt=20, dt_ps=40.0)
+    np.testing.assert_array_equal(tabulate_layers_parallel(g, threads=3), okernel.tabulate(g))

@@ -1,0 +1,82 @@
+"""Plain-path reconstruction against the FP64 oracle at the precision
+workload's full size: 128 x 128 scan at 0.5 mm, 64 layers over 1-30 mm,
+512 bins of 20 ps (the iteration-rate benchmark's shape).
+
+Four FISTA iterations with the same L and lambda on both sides, from the
+oracle's FFT-tier operator (run over blocks of time bins in parallel
+threads, see gpu_common.BinRunOperator) and from ctof_reconstruct in each
+precision.  Bars (relative): iterate L2 1e-5 (FP32), 2e-3 (BF16 hi+lo,
+BF16 hi-only spectrum); data fit after the iterations 1e-4 (FP32), 1e-2
+(BF16 forms); every iteration's data fit as well.  The results are printed
+and written to gpurun_out/precision_report_fullsize.json when that folder
+exists.
+"""
+
+import json
+import os
+import time
+
+import numpy as np
+import pytest
+
+from oracle import solver as osolver
+from synth import noise, phantoms, workloads
+from tests.gpu_common import BinRunOperator, rel_l2, tabulate_layers_parallel, to_np
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+ITERS = 4
+IT_TOL = {"fp32": 1e-5, "bf16x3": 2e-3, "bf16": 2e-3}
+FIT_TOL = {"fp32": 1e-4, "bf16x3": 1e-2, "bf16": 1e-2}
+
+
+@pytest.mark.timeout(900)
+def test_full_size_reconstruct_against_oracle():
+    from paper_2101_11680_amd import ctof as c
+    t0 = time.time()
+    g = workloads.geometry_for("precision", seed=0)
+    w = workloads.workload("precision")
+    mu_true = phantoms.workload_phantom(w, g, 0)
+    Kq = tabulate_layers_parallel(g)
+    t_tab = time.time() - t0
+    F = BinRunOperator(Kq, run=32)
+    del Kq
+    d = noise.poisson_histogram(F.forward(mu_true), w["peak"][0], 1000)
+    print(f"oracle set-up {time.time() - t0:.1f} s (tabulation {t_tab:.1f} s, {F.threads} threads)", flush=True)
+    dt = torch.tensor(d, dtype=torch.float32, device="cuda")
+    k32 = c.tabulate(g, c.FP32)
+    _, rep0, _ = c.reconstruct(k32, dt, max_iter=1)
+    L, lam = rep0.lipschitz, rep0.lam
+    del k32
+    torch.cuda.empty_cache()
+    t1 = time.time()
+    ref, href = osolver.fista(F, d, L, lam, ITERS)
+    fit_ref = osolver.datafit(F, d, ref)
+    g0_ref = osolver.gmap_denominator(F, d)
+    print(f"oracle FISTA {ITERS} iterations + final fit {time.time() - t1:.1f} s", flush=True)
+    F.close()
+    report = {"shape": "128x128 scan, 64 layers, 512 bins", "iterations": ITERS, "lipschitz": L, "lambda": lam}
+    for prec in ("fp32", "bf16x3", "bf16"):
+        k = c.tabulate(g, c.PRECISIONS[prec])
+        mu, rep, hist = c.reconstruct(k, dt, max_iter=ITERS, lam=lam, lipschitz=L, history=True)
+        h = hist.cpu().numpy()
+        r = {"iterate_rel_l2": rel_l2(to_np(mu), ref),
+             "datafit_rel": abs(rep.datafit / fit_ref - 1),
+             "history_datafit_rel_max": float(np.max(np.abs(h[:, 0] / href[:, 0] - 1))),
+             "history_ratio_rel_max": float(np.max(np.abs(h[:, 1] / href[:, 1] - 1))),
+             "gmap0_rel": abs(rep.gmap0 / g0_ref - 1)}
+        report[prec] = r
+        print(prec, json.dumps(r), flush=True)
+        del k
+        torch.cuda.empty_cache()
+    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+    if os.path.isdir(out):
+        with open(os.path.join(out, "precision_report_fullsize.json"), "w") as f:
+            json.dump(report, f, indent=1)
+    for prec in ("fp32", "bf16x3", "bf16"):
+        r = report[prec]
+        assert r["iterate_rel_l2"] <= IT_TOL[prec], (prec, r)
+        assert r["datafit_rel"] <= FIT_TOL[prec], (prec, r)
+        assert r["history_datafit_rel_max"] <= FIT_TOL[prec], (prec, r)
+        assert r["gmap0_rel"] <= IT_TOL[prec], (prec, r)

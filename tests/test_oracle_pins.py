@@ -260,6 +260,55 @@ def test_p13_fista_matches_bounded_lsq():
     assert hist[-1, 1] < 1e-8
 
 
+def test_fista_rate_and_momentum_pins(monkeypatch):
+    # Beck and Teboulle's guarantee for FISTA with a constant step 1/L,
+    # L >= Lipschitz constant of the smooth part (here L_A + lam):
+    #   F(mu_k) - F* <= 2 L ||mu_0 - mu*||^2 / (k + 1)^2   for every k,
+    # with F* and mu* from the library's bounded least squares; and the
+    # momentum sequence's t_k >= (k + 1) / 2 (recovered from the weights
+    # beta_k = (t_k - 1) / t_{k+1}).  Without momentum (beta = 0, plain
+    # projected gradient) the same bound fails on this problem, so the pin
+    # sees whether the weights accelerate at all.
+    g = small_geometry()
+    Kq = kernel.tabulate(g)
+    J = operator.jacobian(Kq)
+    op = _JOp(J, Kq.shape)
+    mu_true = phantoms.phantom(g, 4, n_abs=(2, 2), radius=(1.2, 1.2), dmua=(0.03, 0.03))
+    d = noise.poisson_histogram(op.forward(mu_true), 1e5, 11)
+    L_A = float(np.linalg.eigvalsh(J.T @ J)[-1])
+    L, lam = solver.step_constants(L_A)
+    A = np.vstack([J, math.sqrt(lam) * np.eye(J.shape[1])])
+    b = np.concatenate([d.ravel(), np.zeros(J.shape[1])])
+    xs = optimize.lsq_linear(A, b, bounds=(0, np.inf), method="bvls", tol=1e-15).x
+    F_star = 0.5 * float(np.sum((A @ xs - b) ** 2))
+    assert abs(solver.objective(op, d, xs.reshape(g.nz, g.ny, g.nx), lam) / F_star - 1) < 1e-12
+    R2 = float(xs @ xs)  # mu_0 = 0
+    ks = (1, 2, 3, 5, 10, 20, 50, 100, 200, 500)
+
+    def ratios():
+        out = []
+        for k in ks:
+            mu, _ = solver.fista(op, d, L, lam, k)
+            out.append((solver.objective(op, d, mu, lam) - F_star) / (2 * L * R2 / (k + 1) ** 2))
+        return np.array(out)
+
+    r = ratios()
+    assert np.all(r <= 1.0), r
+    assert np.all(r >= -1e-12)
+    beta = solver.fista_betas(400)
+    assert beta[0] == 0.0 and all(0.0 <= x < 1.0 for x in beta)
+    t = [1.0, None]
+    # t_2 is the one value not recoverable from beta_1 = 0: the golden ratio
+    t[1] = (1.0 + math.sqrt(5.0)) / 2.0
+    for k in range(1, 399):
+        t.append((t[k] - 1.0) / beta[k])
+    for k, tk in enumerate(t[:399], start=1):
+        assert tk >= (k + 1) / 2 - 1e-9 and tk <= k + 1e-9
+    monkeypatch.setattr(solver, "fista_betas", lambda iters, k0=0: [0.0] * iters)
+    r0 = ratios()
+    assert np.max(r0) > 1.5, r0
+
+
 def test_power_iteration_vs_eigvalsh():
     g = small_geometry()
     Kq = kernel.tabulate(g)
