@@ -634,7 +634,7 @@ row_pass_kernel(int ny, int nx, RowArgs a) {
             const T mprev = yaux[q];
             T mu = yk - tau * (x + lam * yk);
             if (a.l1) mu -= tau * (T)a.l1[pl];  // prox of the per-layer L1 term
-            mu = mu > (T)0 ? mu : (T)0;
+            mu = mu < (T)0 ? (T)0 : mu;  // a NaN stays NaN (the solve's checks then stop it)
             const T ynew = fista_extrapolate(mu, mprev, beta);
             if (sp_prev) sp_prev[idx] = mprev;
             sp_aux[idx] = mu;

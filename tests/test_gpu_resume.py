@@ -67,10 +67,15 @@ def test_resume_is_bitwise_uninterrupted(prec):
     assert torch.equal(mu3, full), float((mu3 - full).abs().max())
     assert r3.datafit == rf.datafit
     # data-fit rows are the same sums of the same partials; the ratios share
-    # their numerator, the denominator is computed by the same passes
+    # their numerator, while the denominator ||max(0, A^T d)|| of the resumed
+    # (warm) calls comes from the separate adjoint pass instead of the zero
+    # start's first step: equal in FP32 and FP64, within the last bits of a
+    # few entries with the BF16 split (whose matrix-core sums are not
+    # exactly odd in their inputs)
     hs = torch.cat([h1, h2, h3]).cpu().numpy()
     np.testing.assert_array_equal(hs[:, 0], hf.cpu().numpy()[:, 0])
-    np.testing.assert_allclose(hs[:, 1], hf.cpu().numpy()[:, 1], rtol=1e-12, atol=0)
+    np.testing.assert_allclose(hs[:, 1], hf.cpu().numpy()[:, 1], rtol=1e-12 if prec != "bf16x3" else 1e-6,
+                               atol=0)
 
 
 def test_resume_batched_is_bitwise_uninterrupted():
@@ -107,8 +112,10 @@ def test_fallback_equals_fresh_zero_start():
     _, rep0, _ = c.reconstruct(k, d, max_iter=1)
     L, lam = rep0.lipschitz, rep0.lam
     zero, rz, hz = c.reconstruct(k, d, max_iter=40, lam=lam, lipschitz=L, history=True)
-    bad = torch.full_like(zero, 50.0)
-    mu, rb, hb = c.reconstruct(k, d, mu=bad, warm_start=2, max_iter=41, lam=lam, lipschitz=L, history=True)
+    def bad():
+        return torch.full_like(zero, 50.0)  # (mu is in/out: a fresh start per call)
+
+    mu, rb, hb = c.reconstruct(k, d, mu=bad(), warm_start=2, max_iter=41, lam=lam, lipschitz=L, history=True)
     assert rb.fell_back == 1 and rb.iters == 41 and rb.fista_k == 40
     assert torch.equal(mu, zero)
     assert rb.datafit0 == rz.datafit0 and rb.datafit == rz.datafit
@@ -116,14 +123,14 @@ def test_fallback_equals_fresh_zero_start():
     np.testing.assert_allclose(hb.cpu().numpy(), hz.cpu().numpy(), rtol=1e-12, atol=0)
     # with a tolerance the restarted scan stops where the zero start stops
     zt, rzt, _ = c.reconstruct(k, d, max_iter=3000, lam=lam, lipschitz=L, rel_tol=1e-3, check_every=10)
-    bt, rbt, _ = c.reconstruct(k, d, mu=bad.clone(), warm_start=2, max_iter=3000, lam=lam, lipschitz=L,
+    bt, rbt, _ = c.reconstruct(k, d, mu=bad(), warm_start=2, max_iter=3000, lam=lam, lipschitz=L,
                                rel_tol=1e-3, check_every=10)
     assert rbt.fell_back == 1 and rbt.iters == rzt.iters + 1
     assert torch.equal(bt, zt)
     # batched: one scan falls back, one keeps its start
     ks = [k, k]
     good = zero.clone()
-    mus, reps = c.reconstruct_batched(ks, [d, d], mus=[bad.clone(), good], warm_start=2, max_iter=41, lam=lam,
+    mus, reps = c.reconstruct_batched(ks, [d, d], mus=[bad(), good], warm_start=2, max_iter=41, lam=lam,
                                       lipschitz=L)
     assert reps[0].fell_back == 1 and reps[1].fell_back == 0
     assert reps[0].fista_k == 40 and reps[1].fista_k == 41
