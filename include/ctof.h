@@ -192,6 +192,26 @@ ctof_status ctof_forward(ctof_kernel k, const void *mu_dev, void *m_dev, void *w
                          size_t ws_bytes, hipStream_t stream);
 
 /*
+ * The forward model of ctof_forward for callers that cannot allocate device
+ * memory or supply a workspace: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation.  Same arguments (without the
+ * workspace), same kernels and results bit for bit; the workspace is a fixed
+ * device array of CTOF_NOALLOC_SCRATCH_BYTES bytes inside the library, one
+ * per GPU, held from the first call on that GPU until the process ends.
+ * Nothing is allocated.  CTOF_ENOMEM (before any launch) when the handle's
+ * forward needs more workspace than that (op_ws of ctof_workspace_bytes; a
+ * 64 x 64 scan with 32 layers and 256 bins needs about 30 MB, the
+ * 128 x 128 x 64 layers x 512 bins benchmark shape about 230 MB and is
+ * rejected).  Every call on one GPU shares the array and its contents
+ * persist between calls (the forward writes every scratch byte it reads
+ * before reading it): calls that overlap in time on one GPU, from several
+ * streams or threads, race and must be serialised by the caller.
+ * Asynchronous.
+ */
+#define CTOF_NOALLOC_SCRATCH_BYTES (64u << 20)
+ctof_status ctof_forward_noalloc(ctof_kernel k, const void *mu_dev, void *m_dev, hipStream_t stream);
+
+/*
  * Adjoint (the transpose of A; the kernel is real): g = A^T r.
  * r_dev [nt][ny][nx], g_dev [nz][ny][nx].  Asynchronous.
  */

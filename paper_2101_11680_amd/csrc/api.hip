@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstring>
 #include <limits>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -377,6 +378,34 @@ ctof_status check_kernel(ctof_kernel k) {
 template <typename T>
 Engine<T> engine(const ctof_kernel_s *k, int nvol, void *ws, int max_iter, hipStream_t st) {
   return Engine<T>{k, nvol, reinterpret_cast<char *>(ws), class_ws(k, nvol, max_iter), st};
+}
+
+// ---- fixed device scratch for the allocation-free forward entry point ----------
+// One array per GPU (each device holds its own copy of a __device__ variable),
+// kept until the process ends.  Host code must not pass the array's name to
+// a kernel: on the host it is only a stand-in for the symbol, so its device
+// address is looked up once per device and used everywhere instead.
+static __device__ __align__(256) unsigned char scratch[CTOF_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the first
+// call per device, with that device current).
+ctof_status scratch_address(void **out) {
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return set_error(CTOF_EUNSUPPORTED, "device index %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return set_error(CTOF_EHIP, "hipGetSymbolAddress gave no address for the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return CTOF_OK;
 }
 
 template <typename T>
@@ -1623,6 +1652,20 @@ ctof_status ctof_forward(ctof_kernel k, const void *mu_dev, void *m_dev, void *w
   if (ws_bytes < o.op_total) return set_error(CTOF_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, o.op_total);
   if (k->prec == CTOF_FP64) return run_forward<double>(k, mu_dev, m_dev, ws_dev, stream);
   return run_forward<float>(k, mu_dev, m_dev, ws_dev, stream);
+}
+
+ctof_status ctof_forward_noalloc(ctof_kernel k, const void *mu_dev, void *m_dev, hipStream_t stream) {
+  ctof_status s = check_kernel(k);
+  if (s != CTOF_OK) return s;
+  if (!mu_dev || !m_dev) return set_error(CTOF_EINVAL, "device pointer is NULL");
+  const ClassWs o = class_ws(k, 1, 1);
+  if (o.op_total > (size_t)CTOF_NOALLOC_SCRATCH_BYTES)
+    return set_error(CTOF_ENOMEM, "the forward model needs %zu bytes of workspace, the fixed scratch holds %zu",
+                     o.op_total, (size_t)CTOF_NOALLOC_SCRATCH_BYTES);
+  void *ws = nullptr;
+  if (ctof_status e = scratch_address(&ws); e != CTOF_OK) return e;
+  if (k->prec == CTOF_FP64) return run_forward<double>(k, mu_dev, m_dev, ws, stream);
+  return run_forward<float>(k, mu_dev, m_dev, ws, stream);
 }
 
 ctof_status ctof_adjoint(ctof_kernel k, const void *r_dev, void *g_dev, void *ws_dev, size_t ws_bytes,

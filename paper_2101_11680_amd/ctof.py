@@ -37,7 +37,8 @@ EXPORTS = ("ctof_kernel_bytes", "ctof_kernel_tabulate", "ctof_kernel_tabulate_qu
            "ctof_warmstart_loss", "ctof_absmax_ws_bytes", "ctof_absmax", "ctof_depth_resample",
            "ctof_sumsq_ws_bytes", "ctof_sumsq", "ctof_layer_threshold_ws_bytes", "ctof_layer_threshold",
            "ctof_mux_forward", "ctof_mux_adjoint", "ctof_mux_normal_ws_bytes", "ctof_mux_normal",
-           "ctof_noisy_counts", "ctof_layer_energy_ws_bytes", "ctof_l1_depth_weights")
+           "ctof_noisy_counts", "ctof_layer_energy_ws_bytes", "ctof_l1_depth_weights",
+           "ctof_forward_noalloc")
 
 
 class CtofError(RuntimeError):
@@ -167,6 +168,7 @@ def lib() -> ctypes.CDLL:
         L.ctof_layer_threshold_ws_bytes.argtypes = [i32, ctypes.POINTER(sz)]
         L.ctof_layer_threshold.argtypes = [i32, i64, vp, f32, vp, sz, vp]
         L.ctof_layer_energy_ws_bytes.argtypes = [vp, ctypes.POINTER(sz)]
+        L.ctof_forward_noalloc.argtypes = [vp, vp, vp, vp]
         L.ctof_l1_depth_weights.argtypes = [vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
                                             ctypes.POINTER(ctypes.c_double), vp, sz, vp]
         mp = ctypes.POINTER(_Mux)
@@ -335,6 +337,20 @@ def forward(k: Kernel, mu, out=None, stream=None):
     ws = k.workspace(nb, mu.device)
     _check(lib().ctof_forward(k.handle, mu.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(),
                               _stream_ptr(stream)))
+    return out
+
+
+def forward_noalloc(k: Kernel, mu, out=None, stream=None):
+    """The forward model through ctof_forward_noalloc: the library's fixed
+    per-GPU scratch replaces the workspace (raises CtofError with
+    CTOF_ENOMEM when the handle's forward needs more than it holds)."""
+    torch = _torch()
+    i = k.info
+    mu = _contig(mu, _dtype(k.precision), (i.nz, i.ny, i.nx))
+    if out is None:
+        out = torch.empty((i.nt, i.ny, i.nx), dtype=mu.dtype, device=mu.device)
+    out = _contig(out, mu.dtype, (i.nt, i.ny, i.nx))
+    _check(lib().ctof_forward_noalloc(k.handle, mu.data_ptr(), out.data_ptr(), _stream_ptr(stream)))
     return out
 
 
