@@ -165,6 +165,129 @@ def cpu_baseline(g, n_iter: int = 3, run: int = 32):
     }
 
 
+def composite_target(ctof, torch, dev, rel_tol: float = 1e-3, n_scans: int = 64, seed: int = 0,
+                     max_iter: int = 3000) -> dict:
+    """The composite target on the batching workload (64 uneven scans, N in
+    {32..128}, Nz in {16, 32, 64}, 256 bins of 25 ps), each scan solved to
+    gradient-mapping ratio <= rel_tol.
+
+    plain:        FP32, zero start, one ctof_reconstruct per scan
+    batched:      FP32, zero start, one ctof_reconstruct_batched call (shape
+                  classes share the kernel spectrum; graph replay)
+    accelerated:  BF16 hi+lo contraction, the same batched call, learned
+                  warm start with the zero-start fallback; back-projection
+                  and network time included
+    L and lambda come from one power iteration per shape class (set-up, the
+    same values on every side); tabulation and launch tuning are set-up
+    too.  Tuning: per class for its volume count (batched sides), for one
+    volume (plain side).  Per class: scans, time share, mean iterations and
+    the tuner's choice.  The final objectives (data fit + lambda/2 ||mu||^2)
+    of the accelerated side are compared per scan with the plain side's.
+    """
+    from paper_2101_11680_amd import unet
+    from synth import noise, phantoms, workloads
+    scans = workloads.batching_scans(n_scans, seed=seed)
+    rec = dict(n_abs=(1, 4), radius=(0.5, 2.0), dmua=(0.01, 0.05), kinds=("sphere", "bar"))
+    geoms = []
+    for g, _, _ in scans:
+        if g not in geoms:
+            geoms.append(g)
+    counts = {g: sum(1 for q, _, _ in scans if q == g) for g in geoms}
+    plain_k = {g: ctof.tabulate(g, ctof.FP32) for g in geoms}
+    batch_k = {g: ctof.tabulate(g, ctof.FP32) for g in geoms}
+    acc_k = {g: ctof.tabulate(g, ctof.BF16X3) for g in geoms}
+    tuning = {}
+    for g in geoms:
+        ctof.tune(plain_k[g], nvol=1, iters=3)
+        tb = ctof.tune(batch_k[g], nvol=counts[g], iters=3)
+        ta = ctof.tune(acc_k[g], nvol=counts[g], iters=3)
+        tuning[f"{g.nx}x{g.nz}"] = {"fp32": {"bb": tb["bb"], "parts": tb["parts"]},
+                                    "bf16x3": {"bb": ta["bb"], "parts": ta["parts"]}}
+    ds = []
+    for g, sd, peak in scans:
+        mu = phantoms.phantom(g, sd, **rec)
+        m = ctof.forward(plain_k[g], torch.tensor(mu, dtype=torch.float32, device=dev))
+        ds.append(torch.tensor(noise.poisson_histogram(m.double().cpu().numpy(), peak, sd + 7),
+                               dtype=torch.float32, device=dev))
+    first = {}
+    for i, (g, _, _) in enumerate(scans):
+        first.setdefault(g, i)
+    lip = {}
+    for g, i in first.items():
+        _, rep, _ = ctof.reconstruct(plain_k[g], ds[i], max_iter=1)
+        lip[g] = (rep.lipschitz, rep.lam)
+    Ls = [lip[g][0] for g, _, _ in scans]
+    lams = [lip[g][1] for g, _, _ in scans]
+    net = unet.load_all(device=dev)
+    # warm-up of every path (graph capture, kernels, network) on one scan per class
+    for g, i in first.items():
+        ctof.reconstruct(plain_k[g], ds[i], max_iter=3, lam=lip[g][1], lipschitz=lip[g][0])
+    torch.cuda.synchronize()
+
+    def objective(mu, rep):
+        return rep.datafit + 0.5 * rep.lam * float((mu.double() ** 2).sum())
+
+    t0 = time.perf_counter()
+    plain = []
+    for (g, _, _), d, L, lam in zip(scans, ds, Ls, lams):
+        mu, rep, _ = ctof.reconstruct(plain_k[g], d, max_iter=max_iter, rel_tol=rel_tol, check_every=10, lam=lam,
+                                      lipschitz=L)
+        plain.append((mu, rep))
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    per_scan_plain = []
+    for (g, _, _), (mu, rep) in zip(scans, plain):
+        per_scan_plain.append(rep.iters)
+    t0 = time.perf_counter()
+    _, reps_b = ctof.reconstruct_batched([batch_k[g] for g, _, _ in scans], ds, max_iter=max_iter, rel_tol=rel_tol,
+                                         check_every=10, lipschitz=Ls, lam=lams)
+    torch.cuda.synchronize()
+    t_batched = time.perf_counter() - t0
+    ks = [acc_k[g] for g, _, _ in scans]
+    t0 = time.perf_counter()
+    starts = unet.warm_start_volumes(net, ks, ds, [1.0 / L for L in Ls])
+    torch.cuda.synchronize()
+    t_cnn = time.perf_counter() - t0
+    mus_a, reps_a = ctof.reconstruct_batched(ks, ds, mus=starts, max_iter=max_iter, rel_tol=rel_tol,
+                                             check_every=10, warm_start=2, lipschitz=Ls, lam=lams)
+    torch.cuda.synchronize()
+    t_acc = time.perf_counter() - t0
+    gaps = []
+    for (mu_p, rp), mu_a, ra in zip(plain, mus_a, reps_a):
+        fp, fa = objective(mu_p, rp), objective(mu_a, ra)
+        gaps.append((fa - fp) / fp)
+    per = {}
+    for (g, _, _), (_, rp), rb, ra in zip(scans, plain, reps_b, reps_a):
+        key = f"{g.nx}x{g.nz}"
+        c = per.setdefault(key, dict(scans=0, iters_plain=0, iters_batched=0, iters_accelerated=0, fell_back=0))
+        c["scans"] += 1
+        c["iters_plain"] += rp.iters
+        c["iters_batched"] += rb.iters
+        c["iters_accelerated"] += ra.iters
+        c["fell_back"] += ra.fell_back
+    for key, c in per.items():
+        for f in ("iters_plain", "iters_batched", "iters_accelerated"):
+            c[f] = c[f] / c["scans"]
+        c["tuning"] = tuning[key]
+    return {
+        "workload": (f"batching: {len(scans)} scans in {len(geoms)} shape classes (N in {{32,48,64,96,128}}, "
+                     f"Nz in {{16,32,64}} over 1-20 mm, 256 bins of 25 ps), each to gradient-mapping ratio "
+                     f"<= {rel_tol:g}; L and lambda once per class on every side"),
+        "plain_fp32_s": t_plain,
+        "batched_fp32_s": t_batched,
+        "accelerated_bf16x3_s": t_acc,
+        "accelerated_network_s": t_cnn,
+        "speedup_batched_fp32": t_plain / t_batched,
+        "speedup_accelerated": t_plain / t_acc,
+        "target": 3.0,
+        "fell_back": int(sum(r.fell_back for r in reps_a)),
+        "not_converged": int(sum(r.gmap_ratio > rel_tol for r in reps_a)),
+        "objective_gap_vs_plain": {"mean": float(np.mean(gaps)), "max": float(np.max(gaps)),
+                                   "min": float(np.min(gaps))},
+        "per_class": dict(sorted(per.items())),
+    }
+
+
 def run_batching(args, ctof, torch, dev) -> int:
     """64 uneven scans (N in {32..128}, Nz in {16,32,64}, 256 bins of 25 ps)
     solved to gradient-mapping ratio <= rel_tol: plain FP32 one scan at a
@@ -564,6 +687,8 @@ def main() -> int:
                          ">= BAND * max |entry| (an approximation of the operator; 0 = full operator, the default)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-composite", dest="composite", action="store_false",
+                    help="skip the composite target measurement (batching workload) of the default run")
     ap.add_argument("--no-variants", dest="variants", action="store_false",
                     help="skip the BF16 contraction variants of the default run")
     ap.add_argument("--no-tune", dest="tune", action="store_false",
@@ -646,9 +771,12 @@ def main() -> int:
     if args.tune:
         # FFT planes per block for this shape and one volume (set-up, untimed,
         # like tabulation)
-        bt, bz, times = ctof.tune(k, nvol=1, iters=5)
-        tuning = {"bb_t": bt, "bb_z": bz, "ms_per_iter_candidates": times}
-        log(f"tuned FFT planes per block: bins {bt}, layers {bz} (candidates {times})")
+        t = ctof.tune(k, nvol=1, iters=5)
+        tuning = {"bb_t": t["bb"][0], "bb_z": t["bb"][1], "fwd_parts": t["parts"][0], "adj_parts": t["parts"][1],
+                  "ms_per_iter_bb": t["ms_bb"], "ms_per_iter_fwd_parts": t["ms_fwd"],
+                  "ms_per_iter_adj_parts": t["ms_adj"]}
+        log(f"tuned launch shape: FFT planes per block {t['bb']}, contraction blocks per matrix {t['parts']} "
+            f"(ms per iteration: planes {t['ms_bb']}, forward {t['ms_fwd']}, adjoint {t['ms_adj']})")
 
     mu_true = phantoms.workload_phantom(w, g, args.seed)
     m_true = ctof.forward(k, torch.tensor(mu_true, dtype=dtype, device=dev))
@@ -798,6 +926,14 @@ def main() -> int:
             del kv
             torch.cuda.empty_cache()
         out["precision_variants"] = variants
+    if args.composite:
+        log("composite target on the batching workload (plain FP32 vs batched BF16 hi+lo with the learned start)")
+        torch.cuda.empty_cache()
+        out["composite_3x"] = composite_target(ctof, torch, dev, rel_tol=args.rel_tol)
+        c = out["composite_3x"]
+        log(f"composite: plain {c['plain_fp32_s']:.2f}s, batched FP32 {c['batched_fp32_s']:.2f}s "
+            f"({c['speedup_batched_fp32']:.2f}x), accelerated {c['accelerated_bf16x3_s']:.2f}s "
+            f"({c['speedup_accelerated']:.2f}x)")
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host (bounded sample)")
         out["cpu_baseline"] = cpu_baseline(g)

@@ -448,17 +448,52 @@ ctof_status ctof_reconstruct_batched(int32_t nscan, const ctof_kernel *k, const 
  * Tuning of a handle's FFT passes: planes per block on the bin side (bb_t)
  * and on the layer side (bb_z), each 16 or 32 (0 = built-in rule: 32 when
  * the pass still has >= 1024 blocks).  The value changes launch shapes and
- * workspace sizes, not results.  ctof_tune times the operator passes of a
- * class of nvol volumes for every legal pair (ms[4] receives the average
- * milliseconds per iteration for (16,16), (32,16), (16,32), (32,32); -1 when
- * not legal), keeps the fastest in the handle and returns it.  Synchronises
- * `stream`.  Handles under tuning must not be in use on other streams.
+ * workspace sizes, not results.
  */
 ctof_status ctof_kernel_set_tuning(ctof_kernel k, int32_t bb_t, int32_t bb_z);
 ctof_status ctof_kernel_get_tuning(ctof_kernel k, int32_t *bb_t, int32_t *bb_z);
+
+/*
+ * Launch shape of a handle's contractions (the per-frequency products of
+ * Eq. 11 and their transpose): blocks per spectrum matrix (and pair of
+ * volumes), each 0 (built-in rule), 1, 2, 4 or 8.  The forward splits a
+ * matrix's bins into runs, one block each; the adjoint splits its sum over
+ * bins into runs whose partial results are added, in run order, by the
+ * following inverse column pass (the workspace then holds one volume-side
+ * spectrum per run: query ctof_workspace_bytes after setting).  Shorter
+ * blocks shorten the tail of a launch.  The effective values (get) are
+ * clamped: 1 with a spectrum band or a BF16 precision, an adjoint of FFT
+ * size above 256 keeps 1, and a run has at least one 16-bin tile.  Results
+ * change only by the order of the adjoint's sum.  The handle must not be in
+ * use on other streams meanwhile.
+ */
+ctof_status ctof_kernel_set_contract_parts(ctof_kernel k, int32_t fwd_parts, int32_t adj_parts);
+ctof_status ctof_kernel_get_contract_parts(ctof_kernel k, int32_t *fwd_parts, int32_t *adj_parts);
+/*
+ * Launch-shape tuner for a class of nvol volumes sharing the handle (the
+ * batching form's per-class choice): times `iters` operator passes (the
+ * eight launches of an iteration) for each legal FFT planes-per-block pair
+ * with the contractions at their rule, then, with the fastest pair, the
+ * forward contraction's blocks per matrix 1, 2, 4, 8, then the adjoint's,
+ * keeps the fastest of each in the handle (ctof_kernel_set_tuning,
+ * ctof_kernel_set_contract_parts) and reports every timing.  The FFT size
+ * is not a choice: the radix-2 passes take the power of two >= 2n - 1 (a
+ * smaller non-power-of-two size would need other radices).  Choices change
+ * launch shapes and workspace sizes; results change only by the order of
+ * the adjoint's sum.  Synchronises `stream`; the handle must not be in use
+ * on other streams meanwhile.
+ *   ms_bb   per iteration for (bb_t, bb_z) = (16,16), (32,16), (16,32),
+ *           (32,32); -1 where the block rule does not allow the pair
+ *   ms_fwd, ms_adj   for 1, 2, 4, 8 blocks per matrix; -1 where the value
+ *           clamps to one timed before
+ */
+typedef struct {
+  int32_t bb_t, bb_z, fwd_parts, adj_parts;
+  float ms_bb[4], ms_fwd[4], ms_adj[4];
+} ctof_tuning;
 ctof_status ctof_tune_workspace_bytes(ctof_kernel k, int32_t nvol, size_t *ws_bytes);
 ctof_status ctof_tune(ctof_kernel k, int32_t nvol, int32_t iters, void *ws_dev, size_t ws_bytes,
-                      hipStream_t stream, float *ms, int32_t *bb_t, int32_t *bb_z);
+                      hipStream_t stream, ctof_tuning *out);
 
 /*
  * Band of a handle's kernel spectrum (optional; an approximation of the

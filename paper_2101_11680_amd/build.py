@@ -39,8 +39,9 @@ FLAGS = [
 HOT_SOURCES = ("fft.hip", "contract.hip", "solver.hip", "api.hip", "tabulate.hip")
 # kernels allowed to use scratch, by a substring of the mangled name, with the reason
 SCRATCH_ALLOWED = {
-    # FP64 adjoint for more than 64 layers (16 z tiles of FP64 accumulators):
-    # a parity configuration, not on the FP32/BF16 hot path
+    # FP64 adjoints for 129-256 layers (12 or 16 z tiles of FP64
+    # accumulators): parity configurations, not on the FP32/BF16 hot path
+    "contract_adj_kernelIdLi12E": "FP64 adjoint with 12 layer tiles",
     "contract_adj_kernelIdLi16E": "FP64 adjoint with 16 layer tiles",
 }
 

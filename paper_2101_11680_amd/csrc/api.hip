@@ -200,7 +200,9 @@ TabWs tab_ws(const ctof::Dims &d) {
 // intermediates carry every volume's planes, solver state is per volume.
 struct ClassWs {
   size_t yhat, mhat, xt, xz, op_total;
-  size_t y, v, w, hist, scal, g0sq, part, beta, ctr, active, boff, l1, solve_total;
+  size_t yhat_elems;  // elements of one volume-side spectrum set (the adjoint's parts follow each other)
+  int adj_parts;
+  size_t y, v, w, hist, scal, g0sq, part, beta, ctr, active, boff, conv, l1, solve_total;
   int nblk_t, nblk_z;
   size_t part_stride;  // doubles per iteration
 };
@@ -216,7 +218,10 @@ ClassWs class_ws(const ctof_kernel_s *k, int nvol, int max_iter) {
     off += ctof::round_up(bytes, 256);
     return at;
   };
-  o.yhat = take((size_t)(d.h + 1) * d.p * 2 * nvol * d.nzp * es);
+  // the adjoint contraction split along t writes one spectrum set per part
+  o.adj_parts = ctof::contract_parts(k, true);
+  o.yhat_elems = (size_t)(d.h + 1) * d.p * 2 * nvol * d.nzp;
+  o.yhat = take(o.yhat_elems * es * o.adj_parts);
   o.mhat = take((size_t)(d.h + 1) * d.p * 2 * nvol * d.ntp * es);
   o.xt = take((size_t)(d.h + 1) * d.ny * 2 * nvol * d.ntp * es);
   o.xz = take((size_t)(d.h + 1) * d.ny * 2 * nvol * d.nzp * es);
@@ -237,6 +242,7 @@ ClassWs class_ws(const ctof_kernel_s *k, int nvol, int max_iter) {
   o.ctr = take(64);
   o.active = take((size_t)nvol * 4);
   o.boff = take((size_t)nvol * 4);
+  o.conv = take((size_t)nvol * 4);
   o.l1 = take((size_t)d.nz * 8);
   o.solve_total = off;
   return o;
@@ -270,6 +276,7 @@ struct Engine {
   int *ctr() const { return reinterpret_cast<int *>(ws + L.ctr); }
   int *active() const { return reinterpret_cast<int *>(ws + L.active); }
   int *boff() const { return reinterpret_cast<int *>(ws + L.boff); }
+  int *conv() const { return reinterpret_cast<int *>(ws + L.conv); }
   double *l1() const { return reinterpret_cast<double *>(ws + L.l1); }
   int Bt() const { return nvol * dm().ntp; }
   int Bz() const { return nvol * dm().nzp; }
@@ -296,11 +303,13 @@ struct Engine {
                    : ctof::launch_col_pass<T>(dm(), Bt(), false, xt(), mhat(), st, dm().ntp, k->bb_t, live);
   }
   hipError_t col_z(bool inverse) const {
-    return inverse ? ctof::launch_col_pass<T>(dm(), Bz(), true, yhat(), xz(), st, dm().nzp, k->bb_z, live)
+    // (the inverse pass follows an adjoint contraction and adds its parts)
+    return inverse ? ctof::launch_col_pass<T>(dm(), Bz(), true, yhat(), xz(), st, dm().nzp, k->bb_z, live,
+                                              L.adj_parts, L.yhat_elems)
                    : ctof::launch_col_pass<T>(dm(), Bz(), false, xz(), yhat(), st, dm().nzp, k->bb_z, live);
   }
   hipError_t contract(bool adjoint) const {
-    return adjoint ? ctof::launch_contract(k, true, mhat(), yhat(), st, nvol, live)
+    return adjoint ? ctof::launch_contract(k, true, mhat(), yhat(), st, nvol, live, L.yhat_elems)
                    : ctof::launch_contract(k, false, yhat(), mhat(), st, nvol, live);
   }
   // spatial volume(s) -> yhat
@@ -719,7 +728,7 @@ ctof_status enqueue_start(const Engine<T> &E, void *const *mu, bool warm) {
       HIP_TRY(ctof::launch_fill_zero(mu[v], vol * sizeof(T), E.st));
       HIP_TRY(ctof::launch_fill_zero(E.y(v), vol * sizeof(T), E.st));
     }
-    HIP_TRY(ctof::launch_fill_zero(E.yhat(), E.L.mhat - E.L.yhat, E.st));
+    HIP_TRY(ctof::launch_fill_zero(E.yhat(), E.L.yhat_elems * sizeof(T), E.st));
     return CTOF_OK;
   }
   for (int v = 0; v < E.nvol; ++v)
@@ -1036,16 +1045,24 @@ struct StreamGuard {
   hipStream_t s = nullptr;
   hipStream_t br[kBranches] = {};
   hipEvent_t fork = nullptr, join[kBranches] = {};
+  hipEvent_t chunk_end[2] = {};
   hipGraph_t g = nullptr;
   hipGraphExec_t x = nullptr;
+  // graphs replaced while a launch of theirs may still run: destroyed at the end
+  std::vector<hipGraphExec_t> old_x;
+  std::vector<hipGraph_t> old_g;
   void reset_graph() {
-    if (x) (void)hipGraphExecDestroy(x);
-    if (g) (void)hipGraphDestroy(g);
+    if (x) old_x.push_back(x);
+    if (g) old_g.push_back(g);
     x = nullptr;
     g = nullptr;
   }
   ~StreamGuard() {
     reset_graph();
+    for (hipGraphExec_t e : old_x) (void)hipGraphExecDestroy(e);
+    for (hipGraph_t e : old_g) (void)hipGraphDestroy(e);
+    for (hipEvent_t e : chunk_end)
+      if (e) (void)hipEventDestroy(e);
     for (int b = 0; b < kBranches; ++b) {
       if (join[b]) (void)hipEventDestroy(join[b]);
       if (br[b]) (void)hipStreamDestroy(br[b]);
@@ -1141,6 +1158,7 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
     HIP_TRY(ctof::launch_fill_int(E[c].ctr(), 1, 0, st));
     HIP_TRY(ctof::launch_fill_int(E[c].active(), E[c].nvol, 1, st));
     HIP_TRY(ctof::launch_fill_int(E[c].boff(), E[c].nvol, 0, st));
+    HIP_TRY(ctof::launch_fill_int(E[c].conv(), E[c].nvol, 0, st));
   }
   // ||max(0, A^T d_v)||^2 from the partials of the first step of a zero start
   bool g0_pending = fused_g0;
@@ -1162,6 +1180,7 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
     HIP_TRY(hipEventCreateWithFlags(&sg.join[b], hipEventDisableTiming));
   }
   HIP_TRY(hipEventCreateWithFlags(&sg.fork, hipEventDisableTiming));
+  for (hipEvent_t &e : sg.chunk_end) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   bool recapture = true;
   std::vector<std::vector<int>> conv(cls.size()), fell(cls.size());
   for (size_t c = 0; c < cls.size(); ++c) {
@@ -1197,6 +1216,44 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
     HIP_TRY(hipStreamSynchronize(st));  // the host flags above are copied before they go out of scope
     done = 1;
   }
+  // With a tolerance every chunk ends with a device-side freeze check of each
+  // live class (freeze_kernel: the same ratio launch_history reports).  The
+  // host launches chunk j + 1 before it reads back the flags that chunk j
+  // left, so the device never waits for the host; a class the host finds
+  // all frozen leaves the graph from the next capture on (a chunk launched
+  // meanwhile skips its frozen volumes).
+  const bool freeze = opt->rel_tol > 0;
+  std::vector<std::vector<int>> host_active(cls.size());
+  auto enqueue_freeze = [&](size_t c, hipStream_t s) -> ctof_status {
+    const ClassWs &L = cls[c].L;
+    HIP_TRY(ctof::launch_freeze(E[c].part(), L.part_stride, E[c].ctr(), E[c].nvol, L.nblk_t, L.nblk_z, cls[c].tau,
+                                E[c].g0sq(), fused_g0 ? E[c].part() + 2 * (size_t)L.nblk_t + 1 : nullptr,
+                                opt->rel_tol, E[c].active(), E[c].conv(), s));
+    return CTOF_OK;
+  };
+  // read back the flags of the chunk that ended at event `ev` (blocks the
+  // host until that chunk is done, not the later ones)
+  auto read_flags = [&](hipEvent_t ev) -> ctof_status {
+    HIP_TRY(hipStreamWaitEvent(sg.s, ev, 0));
+    for (size_t c = 0; c < cls.size(); ++c) {
+      if (!cls[c].active) continue;
+      host_active[c].resize(E[c].nvol);
+      HIP_TRY(hipMemcpyAsync(host_active[c].data(), E[c].active(), (size_t)E[c].nvol * sizeof(int),
+                             hipMemcpyDeviceToHost, sg.s));
+    }
+    HIP_TRY(hipStreamSynchronize(sg.s));
+    for (size_t c = 0; c < cls.size(); ++c) {
+      if (!cls[c].active) continue;
+      int live = 0;
+      for (int v = 0; v < E[c].nvol; ++v) live += host_active[c][v] != 0;
+      if (live == 0) {
+        cls[c].active = false;
+        recapture = true;
+      }
+    }
+    return CTOF_OK;
+  };
+  int nchunk = 0;
   while (done < K) {
     bool any = false;
     for (auto &c : cls) any = any || c.active;
@@ -1228,7 +1285,7 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
         ctof_status cap = CTOF_OK;
         hipError_t ce = hipEventRecord(sg.fork, sg.s);
         for (int b = 0; b < nb && ce == hipSuccess; ++b) ce = hipStreamWaitEvent(sg.br[b], sg.fork, 0);
-        for (int b = 0; b < nb && ce == hipSuccess && cap == CTOF_OK; ++b)
+        for (int b = 0; b < nb && ce == hipSuccess && cap == CTOF_OK; ++b) {
           for (int i = 0; i < chunk && cap == CTOF_OK; ++i)
             for (int c : branch[b]) {
               Engine<T> Ec = E[c];
@@ -1238,6 +1295,10 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
                                       prev_of(c), fused_g0);
               if (cap != CTOF_OK) break;
             }
+          if (freeze)
+            for (int c : branch[b])
+              if (cap == CTOF_OK) cap = enqueue_freeze((size_t)c, sg.br[b]);
+        }
         for (int b = 0; b < nb && ce == hipSuccess; ++b) {
           ce = hipEventRecord(sg.join[b], sg.br[b]);
           if (ce == hipSuccess) ce = hipStreamWaitEvent(sg.s, sg.join[b], 0);
@@ -1253,6 +1314,7 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
       }
       HIP_TRY(hipGraphLaunch(sg.x, st));
     } else {
+      // the last, shorter chunk ends at max_iter: no check follows it
       for (int i = 0; i < n_this; ++i)
         for (size_t c = 0; c < cls.size(); ++c)
           if (cls[c].active) {
@@ -1266,37 +1328,21 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
     }
     if (ctof_status s = reduce_g0(); s != CTOF_OK) return s;
     done += n_this;
-    if (opt->rel_tol > 0 && done < K) {
-      std::vector<std::vector<double>> last(cls.size());
-      for (size_t c = 0; c < cls.size(); ++c) {
-        if (!cls[c].active) continue;
-        const ClassWs &L = cls[c].L;
-        double *row = E[c].hist() + (size_t)(done - 1) * E[c].nvol * 2;
-        HIP_TRY(ctof::launch_history(E[c].part() + (size_t)(done - 1) * L.part_stride, 1, E[c].nvol, L.nblk_t,
-                                     L.nblk_z, L.part_stride, cls[c].tau, E[c].g0sq(), row, st));
-        last[c].resize((size_t)E[c].nvol * 2);
-        HIP_TRY(hipMemcpyAsync(last[c].data(), row, last[c].size() * sizeof(double), hipMemcpyDeviceToHost, st));
-      }
-      HIP_TRY(hipStreamSynchronize(st));
-      for (size_t c = 0; c < cls.size(); ++c) {
-        if (!cls[c].active) continue;
-        std::vector<int> act((size_t)E[c].nvol, 1);
-        int live = 0;
-        for (int v = 0; v < E[c].nvol; ++v) {
-          if (conv[c][v] == 0 && std::isfinite(last[c][2 * v + 1]) && last[c][2 * v + 1] <= opt->rel_tol)
-            conv[c][v] = done;
-          act[v] = conv[c][v] == 0 ? 1 : 0;
-          live += act[v];
-        }
-        HIP_TRY(hipMemcpyAsync(E[c].active(), act.data(), act.size() * sizeof(int), hipMemcpyHostToDevice, st));
-        HIP_TRY(hipStreamSynchronize(st));
-        if (live == 0) {
-          cls[c].active = false;
-          recapture = true;
-        }
-      }
+    if (freeze && n_this == chunk) {
+      HIP_TRY(hipEventRecord(sg.chunk_end[nchunk & 1], st));
+      // the previous chunk's flags, read while this one runs
+      if (nchunk > 0)
+        if (ctof_status s = read_flags(sg.chunk_end[(nchunk - 1) & 1]); s != CTOF_OK) return s;
+      ++nchunk;
     }
   }
+  // conv per volume (device): iterations until frozen, 0 for volumes still live
+  for (size_t c = 0; c < cls.size(); ++c) {
+    if (!freeze) break;
+    HIP_TRY(hipMemcpyAsync(conv[c].data(), E[c].conv(), (size_t)E[c].nvol * sizeof(int), hipMemcpyDeviceToHost,
+                           st));
+  }
+  HIP_TRY(hipStreamSynchronize(st));
   if (ctof_status s = reduce_g0(); s != CTOF_OK) return s;
   // reports: full history, final data fit per volume
   std::vector<std::vector<double>> hist(cls.size()), fit(cls.size()), g0(cls.size());
@@ -1346,65 +1392,110 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
   return CTOF_OK;
 }
 
-// Times the operator passes of one class for each legal FFT planes-per-block
-// choice and keeps the fastest in the handle.
+// Launch-shape tuner: times the operator passes of one class (the eight
+// launches of an iteration) for the FFT planes-per-block pairs, then, with
+// the fastest pair, for the forward and the adjoint contraction's blocks per
+// matrix in turn, and keeps the fastest of each in the handle.
 template <typename T>
-ctof_status run_tune(ctof_kernel_s *k, int nvol, int iters, void *ws, hipStream_t st, float *ms,
-                     int32_t *bt, int32_t *bz) {
+ctof_status run_tune(ctof_kernel_s *k, int nvol, int iters, void *ws, hipStream_t st, ctof_tuning *out) {
   const int cand[4][2] = {{16, 16}, {32, 16}, {16, 32}, {32, 32}};
-  float best = 1e30f;
-  int bi = 0;
+  const int parts[4] = {1, 2, 4, 8};
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIP_TRY(hipEventCreate(&e0));
+  struct Ev {
+    hipEvent_t *a, *b;
+    ~Ev() {
+      if (*a) (void)hipEventDestroy(*a);
+      if (*b) (void)hipEventDestroy(*b);
+    }
+  } ev_guard{&e0, &e1};
   HIP_TRY(hipEventCreate(&e1));
-  ctof_status status = CTOF_OK;
-  for (int c = 0; c < 4 && status == CTOF_OK; ++c) {
+  // milliseconds per iteration of the handle's current launch shape (< 0: error)
+  auto time_shape = [&](float *ms) -> ctof_status {
+    const Engine<T> E = engine<T>(k, nvol, ws, 1, st);
+    HIP_TRY(ctof::launch_fill_zero(E.ws, E.L.op_total, st));
+    float t = 0.f;
+    for (int rep = 0; rep < 2; ++rep) {  // the first pass warms up
+      HIP_TRY(hipEventRecord(e0, st));
+      for (int i = 0; i < iters; ++i) {
+        const ctof::RowArgs a = E.row(ctof::ROW_PASS, true);
+        const ctof::RowArgs b = E.row(ctof::ROW_PASS, false);
+        HIP_TRY(E.contract(false));
+        HIP_TRY(E.col_t(true));
+        HIP_TRY(E.run_row(a));
+        HIP_TRY(E.col_t(false));
+        HIP_TRY(E.contract(true));
+        HIP_TRY(E.col_z(true));
+        HIP_TRY(E.run_row(b));
+        HIP_TRY(E.col_z(false));
+      }
+      HIP_TRY(hipEventRecord(e1, st));
+      HIP_TRY(hipEventSynchronize(e1));
+      HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+    }
+    *ms = t / std::max(iters, 1);
+    return CTOF_OK;
+  };
+  std::memset(out, 0, sizeof(*out));
+  // 1. FFT planes per block, contractions at the built-in rule
+  k->fwd_parts = 0;
+  k->adj_parts = 0;
+  float best = 1e30f;
+  int bi = 0;
+  const bool f64 = k->prec == CTOF_FP64;
+  for (int c = 0; c < 4; ++c) {
     k->bb_t = cand[c][0];
     k->bb_z = cand[c][1];
     const Engine<T> E = engine<T>(k, nvol, ws, 1, st);
     // skip choices the block rule would not honour (it falls back to 16)
-    const bool f64 = k->prec == CTOF_FP64;
     if (ctof::batch_block(E.dm(), E.Bt(), E.dm().ntp, f64, cand[c][0]) != cand[c][0] ||
         ctof::batch_block(E.dm(), E.Bz(), E.dm().nzp, f64, cand[c][1]) != cand[c][1]) {
-      if (ms) ms[c] = -1.f;
+      out->ms_bb[c] = -1.f;
       continue;
     }
-    if (hipError_t e = ctof::launch_fill_zero(E.ws, E.L.op_total, st); e != hipSuccess) {
-      status = set_error(CTOF_EHIP, "fill failed: %s", hipGetErrorString(e));
-      break;
-    }
-    float t = 0.f;
-    for (int rep = 0; rep < 2 && status == CTOF_OK; ++rep) {  // first pass warms up
-      if (hipEventRecord(e0, st) != hipSuccess) status = CTOF_EHIP;
-      for (int i = 0; i < iters && status == CTOF_OK; ++i) {
-        ctof::RowArgs a = E.row(ctof::ROW_PASS, true);
-        ctof::RowArgs b = E.row(ctof::ROW_PASS, false);
-        hipError_t e = E.contract(false);
-        if (e == hipSuccess) e = E.col_t(true);
-        if (e == hipSuccess) e = E.run_row(a);
-        if (e == hipSuccess) e = E.col_t(false);
-        if (e == hipSuccess) e = E.contract(true);
-        if (e == hipSuccess) e = E.col_z(true);
-        if (e == hipSuccess) e = E.run_row(b);
-        if (e == hipSuccess) e = E.col_z(false);
-        if (e != hipSuccess) status = set_error(CTOF_EHIP, "tuning launch failed: %s", hipGetErrorString(e));
-      }
-      if (status == CTOF_OK && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess)
-        (void)hipEventElapsedTime(&t, e0, e1);
-    }
-    if (ms) ms[c] = t / std::max(iters, 1);
-    if (status == CTOF_OK && t < best) {
-      best = t;
+    float ms = 0.f;
+    if (ctof_status s = time_shape(&ms); s != CTOF_OK) return s;
+    out->ms_bb[c] = ms;
+    if (ms < best) {
+      best = ms;
       bi = c;
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   k->bb_t = cand[bi][0];
   k->bb_z = cand[bi][1];
-  if (bt) *bt = k->bb_t;
-  if (bz) *bz = k->bb_z;
-  return status;
+  // 2. forward, then 3. adjoint blocks per matrix (values that clamp to one
+  // already timed are skipped)
+  for (int dir = 0; dir < 2; ++dir) {
+    float *row = dir == 0 ? out->ms_fwd : out->ms_adj;
+    int chosen = 0, seen[4] = {0, 0, 0, 0};
+    float bestp = 1e30f;
+    for (int q = 0; q < 4; ++q) {
+      if (dir == 0) k->fwd_parts = parts[q];
+      else k->adj_parts = parts[q];
+      const int eff = ctof::contract_parts(k, dir == 1);
+      bool dup = false;
+      for (int r = 0; r < q; ++r) dup = dup || seen[r] == eff;
+      seen[q] = eff;
+      if (dup) {
+        row[q] = -1.f;
+        continue;
+      }
+      float ms = 0.f;
+      if (ctof_status s = time_shape(&ms); s != CTOF_OK) return s;
+      row[q] = ms;
+      if (ms < bestp) {
+        bestp = ms;
+        chosen = parts[q];
+      }
+    }
+    if (dir == 0) k->fwd_parts = chosen;
+    else k->adj_parts = chosen;
+  }
+  out->bb_t = k->bb_t;
+  out->bb_z = k->bb_z;
+  out->fwd_parts = ctof::contract_parts(k, false);
+  out->adj_parts = ctof::contract_parts(k, true);
+  return CTOF_OK;
 }
 
 }  // namespace
@@ -1900,6 +1991,22 @@ ctof_status ctof_kernel_set_tuning(ctof_kernel k, int32_t bb_t, int32_t bb_z) {
   return CTOF_OK;
 }
 
+ctof_status ctof_kernel_set_contract_parts(ctof_kernel k, int32_t fwd_parts, int32_t adj_parts) {
+  if (ctof_status s = check_kernel(k); s != CTOF_OK) return s;
+  auto ok = [](int32_t v) { return v == 0 || v == 1 || v == 2 || v == 4 || v == 8; };
+  if (!ok(fwd_parts) || !ok(adj_parts)) return set_error(CTOF_EINVAL, "parts must be 0, 1, 2, 4 or 8");
+  k->fwd_parts = fwd_parts;
+  k->adj_parts = adj_parts;
+  return CTOF_OK;
+}
+
+ctof_status ctof_kernel_get_contract_parts(ctof_kernel k, int32_t *fwd_parts, int32_t *adj_parts) {
+  if (ctof_status s = check_kernel(k); s != CTOF_OK) return s;
+  if (fwd_parts) *fwd_parts = ctof::contract_parts(k, false);
+  if (adj_parts) *adj_parts = ctof::contract_parts(k, true);
+  return CTOF_OK;
+}
+
 ctof_status ctof_kernel_get_tuning(ctof_kernel k, int32_t *bb_t, int32_t *bb_z) {
   if (ctof_status s = check_kernel(k); s != CTOF_OK) return s;
   if (bb_t) *bb_t = k->bb_t;
@@ -1907,41 +2014,40 @@ ctof_status ctof_kernel_get_tuning(ctof_kernel k, int32_t *bb_t, int32_t *bb_z) 
   return CTOF_OK;
 }
 
+// largest workspace over the launch shapes the tuner tries
+static size_t tune_ws_bytes(ctof_kernel_s *k, int nvol) {
+  const int32_t save_t = k->bb_t, save_z = k->bb_z, save_a = k->adj_parts;
+  size_t need = 0;
+  for (int bt : {16, 32})
+    for (int bz : {16, 32})
+      for (int ap : {1, 2, 4, 8}) {
+        k->bb_t = bt;
+        k->bb_z = bz;
+        k->adj_parts = ap;
+        need = std::max(need, class_ws(k, nvol, 1).solve_total);
+      }
+  k->bb_t = save_t;
+  k->bb_z = save_z;
+  k->adj_parts = save_a;
+  return need;
+}
+
 ctof_status ctof_tune(ctof_kernel k, int32_t nvol, int32_t iters, void *ws_dev, size_t ws_bytes,
-                      hipStream_t stream, float *ms, int32_t *bb_t, int32_t *bb_z) {
+                      hipStream_t stream, ctof_tuning *out) {
   if (ctof_status s = check_kernel(k); s != CTOF_OK) return s;
   if (nvol < 1 || nvol > ctof::kMaxVol) return set_error(CTOF_EINVAL, "nvol must be in [1, %d]", ctof::kMaxVol);
   if (iters < 1) return set_error(CTOF_EINVAL, "iters must be >= 1");
-  if (!ws_dev) return set_error(CTOF_EINVAL, "workspace is NULL");
-  const int32_t save_t = k->bb_t, save_z = k->bb_z;
-  size_t need = 0;
-  for (int bt : {16, 32})
-    for (int bz : {16, 32}) {
-      k->bb_t = bt;
-      k->bb_z = bz;
-      need = std::max(need, class_ws(k, nvol, 1).solve_total);
-    }
-  k->bb_t = save_t;
-  k->bb_z = save_z;
+  if (!ws_dev || !out) return set_error(CTOF_EINVAL, "workspace or result is NULL");
+  const size_t need = tune_ws_bytes(k, nvol);
   if (ws_bytes < need) return set_error(CTOF_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);
-  if (k->prec == CTOF_FP64) return run_tune<double>(k, nvol, iters, ws_dev, stream, ms, bb_t, bb_z);
-  return run_tune<float>(k, nvol, iters, ws_dev, stream, ms, bb_t, bb_z);
+  if (k->prec == CTOF_FP64) return run_tune<double>(k, nvol, iters, ws_dev, stream, out);
+  return run_tune<float>(k, nvol, iters, ws_dev, stream, out);
 }
 
 ctof_status ctof_tune_workspace_bytes(ctof_kernel k, int32_t nvol, size_t *ws_bytes) {
   if (ctof_status s = check_kernel(k); s != CTOF_OK) return s;
   if (nvol < 1 || nvol > ctof::kMaxVol) return set_error(CTOF_EINVAL, "nvol must be in [1, %d]", ctof::kMaxVol);
-  const int32_t save_t = k->bb_t, save_z = k->bb_z;
-  size_t need = 0;
-  for (int bt : {16, 32})
-    for (int bz : {16, 32}) {
-      k->bb_t = bt;
-      k->bb_z = bz;
-      need = std::max(need, class_ws(k, nvol, 1).solve_total);
-    }
-  k->bb_t = save_t;
-  k->bb_z = save_z;
-  if (ws_bytes) *ws_bytes = need;
+  if (ws_bytes) *ws_bytes = tune_ws_bytes(k, nvol);
   return CTOF_OK;
 }
 

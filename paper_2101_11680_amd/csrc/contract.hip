@@ -32,6 +32,8 @@
 //   mu side    [ky][kx][re/im][nzp]  t side [ky][kx][re/im][ntp]
 #include "ctof_internal.h"
 
+#include <algorithm>
+
 namespace ctof {
 
 namespace {
@@ -152,7 +154,9 @@ struct CArgs {
   void *vout;
   int h, p, nzp, ntp, nmat;
   int nvol, npairs;
-  int parts;          // forward: blocks per (matrix, pair), each a contiguous run of t tiles; adjoint: 1
+  int parts;          // blocks per (matrix, pair): forward, each a contiguous run of t tiles; adjoint,
+                      // each a contiguous run of bin chunks writing its partial sums to output part `part`
+  size_t pstride;     // adjoint: elements between the output spectra of consecutive parts
   const int *active;  // per volume, 0 = frozen (no loads, no stores); NULL = all live
   const int *band;    // per matrix {lo, hi, zend, 0}: 16-bin tiles [lo, hi) and layers [0, zend)
                       // holding its significant entries; NULL = all
@@ -296,6 +300,105 @@ contract_fwd_kernel(CArgs a) {
   }
 }
 
+// ---- FP32 / FP64 adjoint without a band: software-pipelined form ---------------
+// The steady state of each wave's loop is straight-line code: every load of
+// the next chunk is issued unconditionally (columns without a frequency read
+// a valid address and multiply zeros), so the compiler's wait before a
+// chunk's products covers exactly that chunk's loads and the next chunk's
+// loads stay in flight during the products (conditional loads made it wait
+// for the prefetched chunk as well).  The sums are taken in the same order
+// as in contract_adj_kernel.  (The same form of the forward was slower: its
+// output stores, interleaved with the kernel-spectrum reads, dominate.)
+
+// FP32 / FP64 adjoint: wave w takes bin chunks c0 + w, c0 + w + 4, ... of
+// the block's run; partial products of the four waves are summed in a fixed
+// order through LDS.
+template <typename T, int ZT, bool NT>
+__global__ void __launch_bounds__(256)
+contract_adj_pipe_kernel(CArgs a) {
+  using M = Mfma<T>;
+  extern __shared__ unsigned char smem_raw[];
+  T *red = reinterpret_cast<T *>(smem_raw);  // [4 waves][ZT][64 lanes][4]
+  int s, pair, part;
+  if (!map_block(a, s, pair, part) || pair_idle(a, pair)) return;
+  const int w = threadIdx.x >> 6;
+  const int l = threadIdx.x & 63;
+  const int c = l & 15, g = l >> 4;
+  const Col k = column_of(a, s, pair, c);
+  const int nzp = a.nzp, ntp = a.ntp;
+  const T *vcol = k.on ? reinterpret_cast<const T *>(a.vin) + ((size_t)k.f * 2 + k.reim) * a.nvol * ntp +
+                             (size_t)k.vol * ntp + 4 * g
+                       : reinterpret_cast<const T *>(a.vin);
+  const int vstep = k.on ? 16 : 0;
+  const T *khat = reinterpret_cast<const T *>(a.khat);
+  typename M::acc_t acc[ZT];
+#pragma unroll
+  for (int zt = 0; zt < ZT; ++zt) acc[zt] = {0, 0, 0, 0};
+  const int nch = ntp / 16;
+  const int c0 = part * nch / a.parts, c1 = (part + 1) * nch / a.parts;
+  const int ch0 = c0 + w;
+  const int n = ch0 < c1 ? (c1 - ch0 + 3) / 4 : 0;
+  auto load_chunk = [&](int ch, T (&av)[ZT][4], T (&bv)[4]) {
+    load_run<T, 4>(vcol + ch * vstep, bv);
+#pragma unroll
+    for (int zt = 0; zt < ZT; ++zt) load_frag<T, 4, NT>(khat + (((size_t)s * nch + ch) * ZT + zt) * 256, l, av[zt]);
+  };
+  auto mul_chunk = [&](const T (&av)[ZT][4], const T (&bv)[4]) {
+    T b[4];
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) b[kk] = k.on ? bv[kk] : (T)0;
+#pragma unroll
+    for (int zt = 0; zt < ZT; ++zt)
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) acc[zt] = M::step(av[zt][kk], b[kk], acc[zt]);
+  };
+  if (n > 0) {
+    T a0[ZT][4], a1[ZT][4], b0[4], b1[4];
+    load_chunk(ch0, a0, b0);
+    int i = 0;
+    for (; i + 2 < n; i += 2) {
+      load_chunk(ch0 + 4 * (i + 1), a1, b1);
+      __builtin_amdgcn_sched_barrier(0);
+      mul_chunk(a0, b0);
+      __builtin_amdgcn_sched_barrier(0);
+      load_chunk(ch0 + 4 * (i + 2), a0, b0);
+      __builtin_amdgcn_sched_barrier(0);
+      mul_chunk(a1, b1);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (i + 1 < n) {
+      load_chunk(ch0 + 4 * (i + 1), a1, b1);
+      __builtin_amdgcn_sched_barrier(0);
+      mul_chunk(a0, b0);
+      mul_chunk(a1, b1);
+    } else {
+      mul_chunk(a0, b0);
+    }
+  }
+#pragma unroll
+  for (int zt = 0; zt < ZT; ++zt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) red[((w * ZT + zt) * 64 + l) * 4 + r] = acc[zt][r];
+  __syncthreads();
+  if (w == 0 && k.on) {
+    T *ocol = reinterpret_cast<T *>(a.vout) + (size_t)part * a.pstride +
+              ((size_t)k.f * 2 + k.reim) * a.nvol * nzp + (size_t)k.vol * nzp;
+#pragma unroll
+    for (int zt = 0; zt < ZT; ++zt) {
+      typename M::acc_t o;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        T v = red[((0 * ZT + zt) * 64 + l) * 4 + r];
+        v += red[((1 * ZT + zt) * 64 + l) * 4 + r];
+        v += red[((2 * ZT + zt) * 64 + l) * 4 + r];
+        v += red[((3 * ZT + zt) * 64 + l) * 4 + r];
+        o[r] = v;
+      }
+      store4<T>(ocol + zt * 16 + 4 * g, o);
+    }
+  }
+}
+
 // ---- FP32 / FP64, adjoint: M = z (tiles of 16), K = t (chunks of 16) -----------
 template <typename T, int ZT, bool NT, bool BAND>
 __global__ void __launch_bounds__(256)
@@ -320,9 +423,12 @@ contract_adj_kernel(CArgs a) {
   // chunk's products (one chunk of loads in flight per wave)
   const int nch = ntp / 16;
   // chunks of 16 bins and z tiles inside the matrix's band (the rest of the
-  // sum is below the band's threshold; z tiles past it stay zero)
+  // sum is below the band's threshold; z tiles past it stay zero), and of
+  // this block's run of chunks
   int c0, c1, zend;
   band_of<BAND>(a, s, nch, c0, c1, zend);
+  c0 = max(c0, part * nch / a.parts);
+  c1 = min(c1, (part + 1) * nch / a.parts);
   auto load_chunk = [&](int ch, T (&av)[ZT][4], T (&bv)[4]) {
     if (k.on) {
       load_run<T, 4>(vcol + ch * 16 + 4 * g, bv);
@@ -358,8 +464,8 @@ contract_adj_kernel(CArgs a) {
     for (int r = 0; r < 4; ++r) red[((w * ZT + zt) * 64 + l) * 4 + r] = acc[zt][r];
   __syncthreads();
   if (w == 0 && k.on) {
-    T *ocol = reinterpret_cast<T *>(a.vout) + ((size_t)k.f * 2 + k.reim) * a.nvol * nzp +
-              (size_t)k.vol * nzp;
+    T *ocol = reinterpret_cast<T *>(a.vout) + (size_t)part * a.pstride +
+              ((size_t)k.f * 2 + k.reim) * a.nvol * nzp + (size_t)k.vol * nzp;
 #pragma unroll
     for (int zt = 0; zt < ZT; ++zt) {
       typename M::acc_t o;
@@ -536,6 +642,19 @@ template <typename T, bool NT, bool BAND>
 hipError_t launch_plain(const ctof_kernel_s *k, bool adjoint, const CArgs &a, hipStream_t st) {
   const Dims &d = k->dims;
   const dim3 grid((unsigned)(8 * ((d.nmat + 7) / 8) * a.npairs * a.parts)), block(256);
+  if constexpr (!BAND) {
+    if (adjoint && (d.nzp / 16) <= 4) {
+      const size_t shm = (size_t)4 * (d.nzp / 16) * 64 * 4 * sizeof(T);
+      switch (d.nzp / 16) {
+        case 1: hipLaunchKernelGGL((contract_adj_pipe_kernel<T, 1, NT>), grid, block, shm, st, a); break;
+        case 2: hipLaunchKernelGGL((contract_adj_pipe_kernel<T, 2, NT>), grid, block, shm, st, a); break;
+        case 3: hipLaunchKernelGGL((contract_adj_pipe_kernel<T, 3, NT>), grid, block, shm, st, a); break;
+        case 4: hipLaunchKernelGGL((contract_adj_pipe_kernel<T, 4, NT>), grid, block, shm, st, a); break;
+        default: return hipErrorInvalidValue;
+      }
+      return hipGetLastError();
+    }
+  }
   if (!adjoint) {
     const int kz = (d.nzp >= 64 ? 64 : d.nzp) / 4;
     switch (kz) {
@@ -611,8 +730,23 @@ hipError_t dispatch(const ctof_kernel_s *k, bool adjoint, const CArgs &a, hipStr
 
 }  // namespace
 
+int contract_parts(const ctof_kernel_s *k, bool adjoint) {
+  const Dims &d = k->dims;
+  const bool bf = k->prec == CTOF_BF16X3 || k->prec == CTOF_BF16;
+  if (k->band || bf) return 1;  // (the BF16 kernels keep one block per matrix)
+  if (!adjoint) {
+    // up to four blocks per matrix, at least 8 t tiles (2 per wave) each:
+    // shorter blocks shorten the tail of the launch
+    const int rule = std::max(1, std::min(4, d.ntp / 128));
+    return k->fwd_parts > 0 ? std::max(1, std::min(k->fwd_parts, d.ntp / 16)) : rule;
+  }
+  // the partial sums are added by the inverse column pass (FFT sizes <= 256)
+  if (d.p > 256) return 1;
+  return k->adj_parts > 0 ? std::max(1, std::min(k->adj_parts, d.ntp / 16)) : 1;
+}
+
 hipError_t launch_contract(const ctof_kernel_s *k, bool adjoint, const void *in, void *out,
-                           hipStream_t st, int nvol, const int *active) {
+                           hipStream_t st, int nvol, const int *active, size_t pstride) {
   const Dims &d = k->dims;
   const char *kh = reinterpret_cast<const char *>(k->khat);
   CArgs a;
@@ -629,11 +763,11 @@ hipError_t launch_contract(const ctof_kernel_s *k, bool adjoint, const void *in,
   a.nvol = nvol;
   a.npairs = (nvol + 1) / 2;
   a.band = k->band;
-  // forward: up to four blocks per matrix, at least 8 t tiles (2 per wave)
-  // each; shorter blocks shorten the tail of the launch.  With a band most
-  // tiles are skipped, and one block per matrix avoids blocks that only
-  // write zeros (measured 83 against 170 us at the benchmark shape)
-  a.parts = (adjoint || k->band) ? 1 : std::max(1, std::min(4, d.ntp / 128));
+  // (with a band most tiles are skipped, and one block per matrix avoids
+  // blocks that only write zeros: 83 against 170 us at the benchmark shape)
+  a.parts = contract_parts(k, adjoint);
+  a.pstride = pstride;
+  if (adjoint && a.parts > 1 && pstride == 0) return hipErrorInvalidValue;
   a.active = active;
   if (a.npairs == 1) return dispatch<true>(k, adjoint, a, st);
   return dispatch<false>(k, adjoint, a, st);

@@ -97,6 +97,7 @@ struct ctof_kernel_s {
   int bb_t, bb_z;             // FFT planes per block on the bin / layer side (0 = rule)
   const int *band = nullptr;  // caller-owned device table: per matrix {lo, hi, zend, 0} (NULL = all)
   double band_rel = 0.0;      // threshold the table was made with (0 = none)
+  int fwd_parts = 0, adj_parts = 0;  // contraction blocks per matrix (0 = rule), see contract_parts
 };
 
 namespace ctof {
@@ -119,9 +120,13 @@ hipError_t launch_pack(const Dims &d, ctof_precision prec, const double *k64, vo
 //   forward: in [h+1][ny][2][B] (rows >= ny are zero) -> out [h+1][p][2][B]
 // ppv: planes per volume; active: per-volume flags, blocks of frozen (0)
 // volumes do nothing (NULL: all live)
+// nsum > 1 (inverse passes of FFT size <= 256 only): the input is the sum of
+// nsum spectra `sstride` elements apart, added in order (the partial sums of
+// an adjoint contraction split along t).
 template <typename T>
 hipError_t launch_col_pass(const Dims &d, int B, bool inverse, const T *in, T *out,
-                           hipStream_t st, int ppv = 0, int bb = 0, const int *active = nullptr);
+                           hipStream_t st, int ppv = 0, int bb = 0, const int *active = nullptr, int nsum = 1,
+                           size_t sstride = 0);
 
 enum RowOp : int {
   ROW_SPEC_TO_SPATIAL = 0,   // c2r -> crop -> store spatial (forward/adjoint output)
@@ -183,8 +188,13 @@ int batch_block(const Dims &d, int B, int ppv, bool fp64, int bb = 0);
 hipError_t launch_band(const ctof_kernel_s *k, double rel, int *band, unsigned int *scratch, hipStream_t st);
 int band_max_tiles();
 
+// Blocks per (matrix, pair of volumes) of a contraction launch: the forward
+// splits a matrix into runs of 16-bin tiles, the adjoint into runs of bin
+// chunks whose partial sums go to `parts` consecutive output spectra of
+// `pstride` elements each (summed by the following inverse column pass).
+int contract_parts(const ctof_kernel_s *k, bool adjoint);
 hipError_t launch_contract(const ctof_kernel_s *k, bool adjoint, const void *in, void *out,
-                           hipStream_t st, int nvol = 1, const int *active = nullptr);
+                           hipStream_t st, int nvol = 1, const int *active = nullptr, size_t pstride = 0);
 
 // ---- source multiplexing (mux.hip) --------------------------------------------
 // Tiles of tx x ty scan positions (P = tx ty) combined per time bin by S
@@ -227,6 +237,14 @@ hipError_t launch_fill_zero(void *p, size_t bytes, hipStream_t st);
 // blocks of volume v are the v-th of nvol equal contiguous ranges.
 hipError_t launch_history(const double *partials, int iters, int nvol, int nblk_t, int nblk_z,
                           size_t stride, double tau, const double *g0sq, double *hist, hipStream_t st);
+// Freeze check of a batched class after its iteration *ctr - 1: a live volume
+// whose gradient-mapping ratio (as launch_history computes it) is finite and
+// <= rel_tol gets active[v] = 0 and conv[v] = its iteration count.  g0_part
+// (or NULL): the partials of ||max(0, A^T d)||^2 from a zero start's first
+// step, summed into g0sq first (as launch_reduce_volumes does).
+hipError_t launch_freeze(const double *partials, size_t stride, const int *ctr, int nvol, int nblk_t, int nblk_z,
+                         double tau, double *g0sq, const double *g0_part, double rel_tol, int *active, int *conv,
+                         hipStream_t st);
 // out[v] = sum of partial 0 over the v-th of nvol equal block ranges
 hipError_t launch_reduce_volumes(const double *partials, int nblk, int nvol, double *out, hipStream_t st);
 hipError_t launch_increment(int *ctr, hipStream_t st);

@@ -207,7 +207,7 @@ struct Fac {
 template <typename T, int P, int BB, bool INV>
 __global__ void __launch_bounds__(512)
 col_pass_kernel(int ny, int B, const T *__restrict__ in, T *__restrict__ out, int ppv,
-                const int *__restrict__ active) {
+                const int *__restrict__ active, int nsum, size_t sstride) {
   constexpr int R1 = Fac<P>::R1, R2 = Fac<P>::R2;
   constexpr int DIR = INV ? 1 : -1;
   constexpr int ld = BB + 1;
@@ -232,6 +232,11 @@ col_pass_kernel(int ny, int B, const T *__restrict__ in, T *__restrict__ out, in
       if (row < rows_in) {
         yr[n1] = src[((size_t)row * 2) * B + b1];
         yi[n1] = src[((size_t)row * 2 + 1) * B + b1];
+        // partial spectra of a split adjoint, added in part order
+        for (int q = 1; q < nsum; ++q) {
+          yr[n1] += src[(size_t)q * sstride + ((size_t)row * 2) * B + b1];
+          yi[n1] += src[(size_t)q * sstride + ((size_t)row * 2 + 1) * B + b1];
+        }
       } else {
         yr[n1] = (T)0;
         yi[n1] = (T)0;
@@ -748,26 +753,30 @@ row_pass_kernel(int ny, int nx, RowArgs a) {
 
 template <typename T, int P, int BB>
 hipError_t col_dispatch_bb(const Dims &d, int B, bool inverse, const T *in, T *out,
-                           hipStream_t st, int ppv, const int *active) {
+                           hipStream_t st, int ppv, const int *active, int nsum, size_t sstride) {
   dim3 grid((unsigned)(d.h + 1), (unsigned)(B / BB));
   if constexpr (P > 256) {
+    if (nsum != 1) return hipErrorInvalidValue;
     if (inverse)
       hipLaunchKernelGGL((col_pass_lds_kernel<T, P, BB, true>), grid, dim3(512), 0, st, d.ny, B, in, out, ppv, active);
     else
       hipLaunchKernelGGL((col_pass_lds_kernel<T, P, BB, false>), grid, dim3(512), 0, st, d.ny, B, in, out, ppv, active);
   } else {
     if (inverse)
-      hipLaunchKernelGGL((col_pass_kernel<T, P, BB, true>), grid, dim3(512), 0, st, d.ny, B, in, out, ppv, active);
+      hipLaunchKernelGGL((col_pass_kernel<T, P, BB, true>), grid, dim3(512), 0, st, d.ny, B, in, out, ppv, active,
+                         nsum, sstride);
     else
-      hipLaunchKernelGGL((col_pass_kernel<T, P, BB, false>), grid, dim3(512), 0, st, d.ny, B, in, out, ppv, active);
+      hipLaunchKernelGGL((col_pass_kernel<T, P, BB, false>), grid, dim3(512), 0, st, d.ny, B, in, out, ppv, active,
+                         nsum, sstride);
   }
   return hipGetLastError();
 }
 
 template <typename T, int P>
 hipError_t col_dispatch(const Dims &d, int B, bool inverse, const T *in, T *out, hipStream_t st,
-                        int ppv, int bb, const int *active) {
+                        int ppv, int bb, const int *active, int nsum, size_t sstride) {
   ppv = ppv ? ppv : B;
+  if (nsum < 1 || (nsum > 1 && (!inverse || P > 256))) return hipErrorInvalidValue;
   if constexpr (P == 2048) {
     // three-stage column DFT, the whole block in LDS: 4 FP32 or 2 FP64 planes
     constexpr int BB = sizeof(T) == 8 ? 2 : 4;
@@ -779,16 +788,16 @@ hipError_t col_dispatch(const Dims &d, int B, bool inverse, const T *in, T *out,
     return hipGetLastError();
   } else if constexpr (P > 512) {
     // the whole column block lives in LDS: 16 FP32 or 4 FP64 planes fit
-    if constexpr (sizeof(T) == 8) return col_dispatch_bb<T, P, 4>(d, B, inverse, in, out, st, ppv, active);
-    else return col_dispatch_bb<T, P, 16>(d, B, inverse, in, out, st, ppv, active);
+    if constexpr (sizeof(T) == 8) return col_dispatch_bb<T, P, 4>(d, B, inverse, in, out, st, ppv, active, nsum, sstride);
+    else return col_dispatch_bb<T, P, 16>(d, B, inverse, in, out, st, ppv, active, nsum, sstride);
   }
   else {
     // 32 planes per block only where every thread still holds one DFT unit
     if constexpr (Fac<P>::R1 * 32 <= 512 && Fac<P>::R2 * 32 <= 512) {
       if (batch_block(d, B, ppv, sizeof(T) == 8, bb) == 32)
-        return col_dispatch_bb<T, P, 32>(d, B, inverse, in, out, st, ppv, active);
+        return col_dispatch_bb<T, P, 32>(d, B, inverse, in, out, st, ppv, active, nsum, sstride);
     }
-    return col_dispatch_bb<T, P, 16>(d, B, inverse, in, out, st, ppv, active);
+    return col_dispatch_bb<T, P, 16>(d, B, inverse, in, out, st, ppv, active, nsum, sstride);
   }
 }
 
@@ -817,16 +826,16 @@ hipError_t row_dispatch(const Dims &d, const RowArgs &a, hipStream_t st) {
 
 template <typename T>
 hipError_t launch_col_pass(const Dims &d, int B, bool inverse, const T *in, T *out,
-                           hipStream_t st, int ppv, int bb, const int *active) {
+                           hipStream_t st, int ppv, int bb, const int *active, int nsum, size_t sstride) {
   switch (d.p) {
-    case 16: return col_dispatch<T, 16>(d, B, inverse, in, out, st, ppv, bb, active);
-    case 32: return col_dispatch<T, 32>(d, B, inverse, in, out, st, ppv, bb, active);
-    case 64: return col_dispatch<T, 64>(d, B, inverse, in, out, st, ppv, bb, active);
-    case 128: return col_dispatch<T, 128>(d, B, inverse, in, out, st, ppv, bb, active);
-    case 256: return col_dispatch<T, 256>(d, B, inverse, in, out, st, ppv, bb, active);
-    case 512: return col_dispatch<T, 512>(d, B, inverse, in, out, st, ppv, bb, active);
-    case 1024: return col_dispatch<T, 1024>(d, B, inverse, in, out, st, ppv, bb, active);
-    case 2048: return col_dispatch<T, 2048>(d, B, inverse, in, out, st, ppv, bb, active);
+    case 16: return col_dispatch<T, 16>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
+    case 32: return col_dispatch<T, 32>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
+    case 64: return col_dispatch<T, 64>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
+    case 128: return col_dispatch<T, 128>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
+    case 256: return col_dispatch<T, 256>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
+    case 512: return col_dispatch<T, 512>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
+    case 1024: return col_dispatch<T, 1024>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
+    case 2048: return col_dispatch<T, 2048>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
     default: return hipErrorInvalidValue;
   }
 }
@@ -863,9 +872,9 @@ int row_pass_blocks(const Dims &d, int B, int ppv, bool fp64, int bb) {
 }
 
 template hipError_t launch_col_pass<float>(const Dims &, int, bool, const float *, float *, hipStream_t, int, int,
-                                           const int *);
+                                           const int *, int, size_t);
 template hipError_t launch_col_pass<double>(const Dims &, int, bool, const double *, double *, hipStream_t, int,
-                                            int, const int *);
+                                            int, const int *, int, size_t);
 template hipError_t launch_row_pass<float>(const Dims &, const RowArgs &, hipStream_t);
 template hipError_t launch_row_pass<double>(const Dims &, const RowArgs &, hipStream_t);
 

@@ -56,6 +56,42 @@ history_kernel(const double *__restrict__ partials, int nvol, int nblk_t, int nb
   }
 }
 
+// Block v: the gradient-mapping ratio of volume v at the last completed
+// iteration (*ctr - 1), summed exactly as history_kernel does; a live volume
+// whose ratio is finite and <= rel_tol is frozen (active = 0) and its
+// iteration count recorded.
+// g0_part (or NULL): the first step's partials of ||max(0, A^T d)||^2 (a zero
+// start), summed into g0sq[v] first exactly as reduce_volumes_kernel does.
+__global__ void __launch_bounds__(256)
+freeze_kernel(const double *__restrict__ partials, size_t stride, const int *__restrict__ ctr, int nvol,
+              int nblk_t, int nblk_z, double tau, double *__restrict__ g0sq, const double *__restrict__ g0_part,
+              double rel_tol, int *__restrict__ active, int *__restrict__ conv) {
+  __shared__ double red[256];
+  const int v = blockIdx.x;
+  if (active[v] == 0) return;  // (the same value for every thread of the block)
+  const int bz = nblk_z / nvol;
+  double g0s = 0.0;
+  if (g0_part != nullptr) {
+    double a = 0.0;
+    for (int i = threadIdx.x; i < bz; i += blockDim.x) a += g0_part[2 * ((size_t)v * bz + i)];
+    g0s = block_sum(a, red);
+  }
+  const int it = *ctr - 1;
+  const double *pz = partials + (size_t)it * stride + 2 * (size_t)nblk_t;
+  double b = 0.0;
+  for (int i = threadIdx.x; i < bz; i += blockDim.x) b += pz[2 * ((size_t)v * bz + i)];
+  const double gm = block_sum(b, red);
+  if (threadIdx.x == 0) {
+    if (g0_part != nullptr) g0sq[v] = g0s;
+    const double g0 = sqrt(g0_part != nullptr ? g0s : g0sq[v]);
+    const double ratio = g0 > 0.0 ? sqrt(gm) / (tau * g0) : 0.0;
+    if (isfinite(ratio) && ratio <= rel_tol) {
+      active[v] = 0;
+      conv[v] = it + 1;
+    }
+  }
+}
+
 __global__ void __launch_bounds__(256)
 reduce_volumes_kernel(const double *__restrict__ partials, int nblk, int nvol, double *__restrict__ out) {
   __shared__ double red[256];
@@ -114,6 +150,14 @@ hipError_t launch_history(const double *partials, int iters, int nvol, int nblk_
   if (iters <= 0) return hipSuccess;
   hipLaunchKernelGGL(history_kernel, dim3((unsigned)iters, (unsigned)nvol), dim3(256), 0, st, partials,
                      nvol, nblk_t, nblk_z, stride, tau, g0sq, hist);
+  return hipGetLastError();
+}
+
+hipError_t launch_freeze(const double *partials, size_t stride, const int *ctr, int nvol, int nblk_t, int nblk_z,
+                         double tau, double *g0sq, const double *g0_part, double rel_tol, int *active, int *conv,
+                         hipStream_t st) {
+  hipLaunchKernelGGL(freeze_kernel, dim3((unsigned)nvol), dim3(256), 0, st, partials, stride, ctr, nvol, nblk_t,
+                     nblk_z, tau, g0sq, g0_part, rel_tol, active, conv);
   return hipGetLastError();
 }
 

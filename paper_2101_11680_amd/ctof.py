@@ -38,7 +38,7 @@ EXPORTS = ("ctof_kernel_bytes", "ctof_kernel_tabulate", "ctof_kernel_tabulate_qu
            "ctof_sumsq_ws_bytes", "ctof_sumsq", "ctof_layer_threshold_ws_bytes", "ctof_layer_threshold",
            "ctof_mux_forward", "ctof_mux_adjoint", "ctof_mux_normal_ws_bytes", "ctof_mux_normal",
            "ctof_noisy_counts", "ctof_layer_energy_ws_bytes", "ctof_l1_depth_weights",
-           "ctof_forward_noalloc")
+           "ctof_forward_noalloc", "ctof_kernel_set_contract_parts", "ctof_kernel_get_contract_parts")
 
 
 class CtofError(RuntimeError):
@@ -74,6 +74,12 @@ class _SolverOpts(ctypes.Structure):
                 ("lambda_l1_z", ctypes.POINTER(ctypes.c_double)),
                 ("mux", ctypes.POINTER(_Mux)), ("mu_prev_dev", ctypes.c_void_p),
                 ("k0", ctypes.c_int32), ("mu_prev_scans", ctypes.POINTER(ctypes.c_void_p))]
+
+
+class _Tuning(ctypes.Structure):
+    _fields_ = [("bb_t", ctypes.c_int32), ("bb_z", ctypes.c_int32), ("fwd_parts", ctypes.c_int32),
+                ("adj_parts", ctypes.c_int32), ("ms_bb", ctypes.c_float * 4), ("ms_fwd", ctypes.c_float * 4),
+                ("ms_adj", ctypes.c_float * 4)]
 
 
 class _SolverReport(ctypes.Structure):
@@ -135,8 +141,7 @@ def lib() -> ctypes.CDLL:
         L.ctof_kernel_set_tuning.argtypes = [vp, i32, i32]
         L.ctof_kernel_get_tuning.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.ctof_tune_workspace_bytes.argtypes = [vp, i32, ctypes.POINTER(sz)]
-        L.ctof_tune.argtypes = [vp, i32, i32, vp, sz, vp, ctypes.POINTER(ctypes.c_float),
-                                ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.ctof_tune.argtypes = [vp, i32, i32, vp, sz, vp, ctypes.POINTER(_Tuning)]
         dp = ctypes.POINTER(_ConvDesc)
         tp = ctypes.POINTER(_Tensor)
         i64, u64, u32, f32 = ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_float
@@ -169,6 +174,8 @@ def lib() -> ctypes.CDLL:
         L.ctof_layer_threshold.argtypes = [i32, i64, vp, f32, vp, sz, vp]
         L.ctof_layer_energy_ws_bytes.argtypes = [vp, ctypes.POINTER(sz)]
         L.ctof_forward_noalloc.argtypes = [vp, vp, vp, vp]
+        L.ctof_kernel_set_contract_parts.argtypes = [vp, i32, i32]
+        L.ctof_kernel_get_contract_parts.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.ctof_l1_depth_weights.argtypes = [vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
                                             ctypes.POINTER(ctypes.c_double), vp, sz, vp]
         mp = ctypes.POINTER(_Mux)
@@ -646,18 +653,34 @@ def set_tuning(k: Kernel, bb_t: int, bb_z: int) -> None:
     k._ws = {}
 
 
+def set_contract_parts(k: Kernel, fwd_parts: int, adj_parts: int) -> None:
+    """Blocks per spectrum matrix of the forward / adjoint contraction (0 = rule)."""
+    _check(lib().ctof_kernel_set_contract_parts(k.handle, int(fwd_parts), int(adj_parts)))
+    k._ws = {}
+
+
+def get_contract_parts(k: Kernel) -> tuple:
+    """The effective (forward, adjoint) blocks per spectrum matrix."""
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().ctof_kernel_get_contract_parts(k.handle, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
 def get_tuning(k: Kernel) -> tuple:
     a, b = ctypes.c_int32(), ctypes.c_int32()
     _check(lib().ctof_kernel_get_tuning(k.handle, ctypes.byref(a), ctypes.byref(b)))
     return a.value, b.value
 
 
-def tune(k: Kernel, nvol: int = 1, iters: int = 5, cache: Optional[str] = None, stream=None):
-    """Pick the FFT planes-per-block of a handle by timing, with a JSON cache.
+def tune(k: Kernel, nvol: int = 1, iters: int = 5, cache: Optional[str] = None, stream=None) -> dict:
+    """Pick a handle's launch shape for a class of `nvol` volumes by timing
+    (ctof_tune: FFT planes per block, then the contractions' blocks per
+    matrix), with a JSON cache.
 
     The cache (default: $CTOF_TUNE_CACHE, else no cache) maps
-    "arch|n|nz|nt|precision|nvol" to the chosen (bb_t, bb_z) and the timings.
-    Returns (bb_t, bb_z, timings_ms or None when taken from the cache).
+    "arch|grid|nz|nt|precision|nvol" to the choice and its timings.  Returns
+    {"bb": (bb_t, bb_z), "parts": (fwd, adj), "ms_bb": [4], "ms_fwd": [4],
+    "ms_adj": [4], "cached": bool} (timings None when taken from the cache).
     """
     import json
     torch = _torch()
@@ -670,26 +693,31 @@ def tune(k: Kernel, nvol: int = 1, iters: int = 5, cache: Optional[str] = None, 
     if cache and os.path.exists(cache):
         with open(cache) as f:
             table = json.load(f)
-        if key in table:
+        if key in table and "parts" in table[key]:
             bt, bz = table[key]["bb"]
+            fp, ap = table[key]["parts"]
             set_tuning(k, bt, bz)
-            return bt, bz, None
+            set_contract_parts(k, fp, ap)
+            return {"bb": (bt, bz), "parts": (fp, ap), "ms_bb": None, "ms_fwd": None, "ms_adj": None,
+                    "cached": True}
     nb = ctypes.c_size_t()
     _check(lib().ctof_tune_workspace_bytes(k.handle, int(nvol), ctypes.byref(nb)))
     ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=dev)
-    ms = (ctypes.c_float * 4)()
-    bt, bz = ctypes.c_int32(), ctypes.c_int32()
-    _check(lib().ctof_tune(k.handle, int(nvol), int(iters), ws.data_ptr(), ws.numel(),
-                           _stream_ptr(stream), ms, ctypes.byref(bt), ctypes.byref(bz)))
+    t = _Tuning()
+    _check(lib().ctof_tune(k.handle, int(nvol), int(iters), ws.data_ptr(), ws.numel(), _stream_ptr(stream),
+                           ctypes.byref(t)))
     k._ws = {}
-    times = [float(v) for v in ms]
+    out = {"bb": (t.bb_t, t.bb_z), "parts": (t.fwd_parts, t.adj_parts),
+           "ms_bb": [float(v) for v in t.ms_bb], "ms_fwd": [float(v) for v in t.ms_fwd],
+           "ms_adj": [float(v) for v in t.ms_adj], "cached": False}
     if cache:
-        table[key] = {"bb": [bt.value, bz.value], "ms": times}
+        table[key] = {"bb": list(out["bb"]), "parts": list(out["parts"]), "ms_bb": out["ms_bb"],
+                      "ms_fwd": out["ms_fwd"], "ms_adj": out["ms_adj"]}
         tmp = cache + ".tmp"
         with open(tmp, "w") as f:
             json.dump(table, f, indent=1, sort_keys=True)
         os.replace(tmp, cache)
-    return bt.value, bz.value, times
+    return out
 
 
 def _depth_rule(k: Kernel, lam1: float, stream=None):

@@ -124,15 +124,28 @@ def test_tuner_choices_keep_results_and_cache(tmp_path):
     _, rep0, _ = c.reconstruct(k, d, max_iter=1)
     base, _, _ = c.reconstruct(k, d, max_iter=30, lam=rep0.lam, lipschitz=rep0.lipschitz)
     cache = str(tmp_path / "tune.json")
-    bt, bz, times = c.tune(k, nvol=4, iters=3, cache=cache)
-    assert (bt, bz) in [(16, 16), (32, 16), (16, 32), (32, 32)] and times is not None
-    assert c.get_tuning(k) == (bt, bz)
-    bt2, bz2, times2 = c.tune(k, nvol=4, cache=cache)
-    assert (bt2, bz2) == (bt, bz) and times2 is None
-    for bb in [(16, 16), (32, 32), (0, 0)]:
+    t = c.tune(k, nvol=4, iters=3, cache=cache)
+    bt, bz = t["bb"]
+    assert (bt, bz) in [(16, 16), (32, 16), (16, 32), (32, 32)] and not t["cached"]
+    assert c.get_tuning(k) == (bt, bz) and c.get_contract_parts(k) == t["parts"]
+    assert all(x > 0 or x == -1 for x in t["ms_bb"] + t["ms_fwd"] + t["ms_adj"])
+    # the choice is the fastest timed value of each stage
+    assert min(x for x in t["ms_fwd"] if x > 0) > 0
+    t2 = c.tune(k, nvol=4, cache=cache)
+    assert t2["bb"] == t["bb"] and t2["parts"] == t["parts"] and t2["cached"]
+    # the cache round trip restores the choice on a fresh handle
+    k2 = c.tabulate(GC, c.FP32)
+    t3 = c.tune(k2, nvol=4, cache=cache)
+    assert t3["cached"] and c.get_tuning(k2) == t["bb"] and c.get_contract_parts(k2) == t["parts"]
+    dn, F = _data(GC, 7)
+    ref = osolver.fista(F, dn, rep0.lipschitz, rep0.lam, 30)[0]
+    for bb, parts in [((16, 16), (1, 1)), ((32, 32), (4, 2)), ((0, 0), (0, 0)), (t["bb"], t["parts"])]:
         c.set_tuning(k, *bb)
+        c.set_contract_parts(k, *parts)
         mu, _, _ = c.reconstruct(k, d, max_iter=30, lam=rep0.lam, lipschitz=rep0.lipschitz)
         assert rel_l2(to_np(mu), to_np(base)) <= 1e-6
+        # each choice against the oracle as well
+        assert rel_l2(to_np(mu), ref) <= 1e-5
 
 
 @pytest.mark.parametrize("nt", [512, 384, 320])

@@ -343,3 +343,52 @@ def test_full_size_reconstruct_properties_fp32():
     assert rep.gmap_ratio < 0.05
     assert h[-1, 0] < h[0, 0]
     assert np.all(np.isfinite(h))
+
+
+# -- contraction launch shapes: blocks per spectrum matrix ------------------------
+@pytest.mark.parametrize("g", [SMALL, WIDE, P256], ids=["small", "wide", "p256"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_contraction_parts_parity(g, prec):
+    # the forward split into runs of bins and the adjoint split into partial
+    # sums (added by the inverse column pass) give the same operator
+    c = ct()
+    p = c.PRECISIONS[prec]
+    dt = torch.float64 if p == c.FP64 else torch.float32
+    tol = 1e-12 if p == c.FP64 else 1e-5
+    F = oracle_fft(g)
+    rng = np.random.default_rng(41)
+    mu = rng.random((g.nz, g.ny, g.nx))
+    r = rng.standard_normal((g.nt, g.ny, g.nx))
+    m_ref, g_ref = F.forward(mu), F.adjoint(r)
+    k = c.tabulate(g, p)
+    d = torch.tensor(m_ref, dtype=dt, device="cuda")
+    _, rep0, _ = c.reconstruct(k, d, max_iter=1)
+    base = None
+    for fp, ap in [(1, 1), (2, 2), (4, 4), (8, 8), (0, 0)]:
+        c.set_contract_parts(k, fp, ap)
+        efp, eap = c.get_contract_parts(k)
+        assert 1 <= efp <= 8 and 1 <= eap <= 8
+        m = to_np(c.forward(k, torch.tensor(mu, dtype=dt, device="cuda")))
+        gg = to_np(c.adjoint(k, torch.tensor(r, dtype=dt, device="cuda")))
+        assert rel_l2(m, m_ref) <= tol, (fp, ap)
+        assert rel_l2(gg, g_ref) <= tol, (fp, ap)
+        # a short solve: same iterates up to the order of the adjoint's sum
+        mu_s, rep, _ = c.reconstruct(k, d, max_iter=12, lam=rep0.lam, lipschitz=rep0.lipschitz)
+        if base is None:
+            base = to_np(mu_s)
+        else:
+            assert rel_l2(to_np(mu_s), base) <= (1e-13 if p == c.FP64 else 1e-6)
+    c.set_contract_parts(k, 0, 0)
+
+
+def test_contraction_parts_rules():
+    c = ct()
+    k = c.tabulate(SMALL, c.FP32)
+    with pytest.raises(c.CtofError):
+        c.set_contract_parts(k, 3, 1)
+    c.set_contract_parts(k, 8, 8)
+    # 48 bins pad to 64: four 16-bin tiles and four chunks at most
+    assert c.get_contract_parts(k) == (4, 4)
+    kb = c.tabulate(SMALL, c.BF16X3)
+    c.set_contract_parts(kb, 4, 4)
+    assert c.get_contract_parts(kb) == (1, 1)  # the BF16 kernels keep one block per matrix
