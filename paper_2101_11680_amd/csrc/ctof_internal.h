@@ -162,6 +162,8 @@ struct RowArgs {
   double tau, lambda, beta;
   void *sp_prev[kMaxVol];  // ROW_FISTA: per volume, receives mu_{k-1} (the iterate being replaced), or NULL
   const int *beta_off;     // per volume: subtracted from the counter for the beta index (NULL: 0)
+  int sp_vec;              // set by launch_row_pass: rows of whole 16-byte words and 16-byte aligned
+                           // spatial arrays, accessed with vector loads and stores
   int gmap0_at;            // ROW_FISTA: at this iteration (the counter's value, 0 without one) partial 1
                            // also receives |max(0, -x - l1)|^2, the gradient mapping at zero when y = 0
                            // (x = A^T (A 0 - d) = -A^T d); -1: never

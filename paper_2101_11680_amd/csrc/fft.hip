@@ -485,6 +485,10 @@ row_pass_kernel(int ny, int nx, RowArgs a) {
   constexpr int H = P / 2;
   constexpr int ld = BB + 1;
   constexpr int NT = 512;
+  constexpr int V = 16 / (int)sizeof(T);  // elements per 16-byte access
+  constexpr int BQ = BB / V;              // 16-byte words per plane run
+  static_assert(BB % V == 0, "plane blocks are whole 16-byte words");
+  typedef T VT __attribute__((ext_vector_type(V)));
   __shared__ T wr[H * ld], wi[H * ld];
   __shared__ T twc[P], tws[P];
   __shared__ double red[2 * (NT / 64)];
@@ -512,51 +516,53 @@ row_pass_kernel(int ny, int nx, RowArgs a) {
 
   if (spec_in) {
     // Z[k] = A + i B,  A = X[k] + conj(X[H-k]),  B = (X[k] - conj(X[H-k])) e^{+2 pi i k/P}
+    // A unit is (k, V consecutive planes): four 16-byte loads (X[k] and
+    // X[H-k], real and imaginary rows); two rounds of units are loaded
+    // before either is used (indices clamped into range, so every load is in
+    // bounds).
     const T *src = reinterpret_cast<const T *>(a.spec_in) + b0;
-    // three rounds of loads are issued before any is used (indices clamped
-    // into range, so every load is in bounds): three times the loads in
-    // flight per thread at the same occupancy (FP32: 60 registers)
-    constexpr int NU = (H / 2 + 1) * BB;
-    constexpr int NI = (NU + NT - 1) / NT;
+    constexpr int NUV = (H / 2 + 1) * BQ;
+#pragma unroll 1
+    for (int u0 = tid; u0 < NUV; u0 += 2 * NT) {
+      VT xv[2][4];
 #pragma unroll
-    for (int j0 = 0; j0 < NI; j0 += 3) {
-      T xv[3][4];
-#pragma unroll
-      for (int jj = 0; jj < 3; ++jj) {
-        if (j0 + jj < NI) {
-          const int u = min(tid + (j0 + jj) * NT, NU - 1);
-          const int b = u % BB, k = u / BB;
-          const size_t o1 = (((size_t)k * ny + i) * 2) * B + b;
-          const size_t o2 = (((size_t)(H - k) * ny + i) * 2) * B + b;
-          xv[jj][0] = src[o1];
-          xv[jj][1] = src[o1 + B];
-          xv[jj][2] = src[o2];
-          xv[jj][3] = src[o2 + B];
-        }
+      for (int jj = 0; jj < 2; ++jj) {
+        const int u = min(u0 + jj * NT, NUV - 1);
+        const int q = u % BQ, k = u / BQ;
+        const size_t o1 = (((size_t)k * ny + i) * 2) * B + q * V;
+        const size_t o2 = (((size_t)(H - k) * ny + i) * 2) * B + q * V;
+        xv[jj][0] = *reinterpret_cast<const VT *>(src + o1);
+        xv[jj][1] = *reinterpret_cast<const VT *>(src + o1 + B);
+        xv[jj][2] = *reinterpret_cast<const VT *>(src + o2);
+        xv[jj][3] = *reinterpret_cast<const VT *>(src + o2 + B);
       }
 #pragma unroll
-      for (int jj = 0; jj < 3; ++jj) {
-        const int u = tid + (j0 + jj) * NT;
-        if (j0 + jj >= NI || u >= NU) continue;
-        const int b = u % BB, k = u / BB;
-        const T x1r = xv[jj][0], x1i = xv[jj][1];
-        const T x2r = xv[jj][2], x2i = xv[jj][3];
-        {
-          const T ar = x1r + x2r, ai = x1i - x2i;
-          const T dr = x1r - x2r, di = x1i + x2i;
-          const T c = twc[k], s = tws[k];
-          const T br_ = dr * c - di * s, bi_ = dr * s + di * c;
-          wr[k * ld + b] = ar - bi_;
-          wi[k * ld + b] = ai + br_;
-        }
-        if (k > 0 && k < H / 2) {
-          const int kk = H - k;
-          const T ar = x2r + x1r, ai = x2i - x1i;
-          const T dr = x2r - x1r, di = x2i + x1i;
-          const T c = twc[kk], s = tws[kk];
-          const T br_ = dr * c - di * s, bi_ = dr * s + di * c;
-          wr[kk * ld + b] = ar - bi_;
-          wi[kk * ld + b] = ai + br_;
+      for (int jj = 0; jj < 2; ++jj) {
+        const int u = u0 + jj * NT;
+        if (u >= NUV) continue;
+        const int q = u % BQ, k = u / BQ;
+        const T c = twc[k], s = tws[k];
+        const int kk = H - k;
+        const T cc = twc[kk & (P - 1)], ss = tws[kk & (P - 1)];
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          const int b = q * V + e;
+          const T x1r = xv[jj][0][e], x1i = xv[jj][1][e];
+          const T x2r = xv[jj][2][e], x2i = xv[jj][3][e];
+          {
+            const T ar = x1r + x2r, ai = x1i - x2i;
+            const T dr = x1r - x2r, di = x1i + x2i;
+            const T br_ = dr * c - di * s, bi_ = dr * s + di * c;
+            wr[k * ld + b] = ar - bi_;
+            wi[k * ld + b] = ai + br_;
+          }
+          if (k > 0 && k < H / 2) {
+            const T ar = x2r + x1r, ai = x2i - x1i;
+            const T dr = x2r - x1r, di = x2i + x1i;
+            const T br_ = dr * cc - di * ss, bi_ = dr * ss + di * cc;
+            wr[kk * ld + b] = ar - bi_;
+            wi[kk * ld + b] = ai + br_;
+          }
         }
       }
     }
@@ -576,110 +582,156 @@ row_pass_kernel(int ny, int nx, RowArgs a) {
   T *sp_out = vol_on ? reinterpret_cast<T *>(a.sp_out[vol]) : nullptr;
   T *sp_aux = vol_on ? reinterpret_cast<T *>(a.sp_aux[vol]) : nullptr;
   T *sp_prev = vol_on ? reinterpret_cast<T *>(a.sp_prev[vol]) : nullptr;
-  // the spatial inputs of four rounds are loaded before any is used (the
-  // same units in the same order per thread as one round at a time); each
-  // element is read and written by one thread, so outputs that alias an
-  // input (FISTA's y) stay correct
+  // One element of the pointwise step: x is the c2r value (spec_in ops),
+  // yi / ya the spatial inputs; r receives the value for the r2c, o and oa
+  // the spatial outputs (sp_out, sp_aux) of the ops that write them.
+  auto point = [&](T x, T yi, T ya, int pl, T &r, T &o, T &oa) {
+    switch (op) {
+      case ROW_SPEC_TO_SPATIAL:
+        o = x;
+        break;
+      case ROW_SPATIAL_TO_SPEC:
+        r = yi;
+        break;
+      case ROW_SCALE_TO_SPEC:
+        r = yi * scale;
+        o = r;
+        break;
+      case ROW_RESIDUAL:
+        r = x - yi;
+        acc0 += 0.5 * (double)r * (double)r;
+        break;
+      case ROW_PASS:
+        r = x;
+        acc0 += 0.5 * (double)x * (double)x;
+        break;
+      case ROW_FISTA: {
+        T mu = yi - tau * (x + lam * yi);
+        if (a.l1) mu -= tau * (T)a.l1[pl];  // prox of the per-layer L1 term
+        mu = mu < (T)0 ? (T)0 : mu;  // a NaN stays NaN (the solve's checks then stop it)
+        const T ynew = fista_extrapolate(mu, ya, beta);
+        oa = mu;
+        o = ynew;
+        const double dd = (double)yi - (double)mu;
+        acc0 += dd * dd;
+        if (g0acc) {
+          // y = 0 here, so x = -A^T d exactly (negation is exact in every step)
+          const double v = -(double)x - (a.l1 ? a.l1[pl] : 0.0);
+          const double gz = v > 0.0 ? v : 0.0;
+          acc1 += gz * gz;
+        }
+        r = ynew;
+        break;
+      }
+      case ROW_EXTRAPOLATE:
+        o = fista_extrapolate(yi, ya, beta);
+        r = o;
+        break;
+      case ROW_POWER_W:
+        o = x;
+        acc0 += (double)x * (double)x;
+        acc1 += (double)yi * (double)x;
+        break;
+      case ROW_GMAP0: {
+        const double v = (double)x - (a.l1 ? a.l1[pl] : 0.0);
+        const double g = v > 0.0 ? v : 0.0;
+        acc0 += g * g;
+        break;
+      }
+      default:
+        break;
+    }
+  };
   const bool rd_in = op == ROW_SPATIAL_TO_SPEC || op == ROW_SCALE_TO_SPEC || op == ROW_RESIDUAL ||
                      op == ROW_FISTA || op == ROW_POWER_W || op == ROW_EXTRAPOLATE;
   const bool rd_aux = op == ROW_FISTA || op == ROW_EXTRAPOLATE;
-  constexpr int NQ = 4;
-  const int NP = nx * BB;
-  for (int u0 = tid; u0 < NP; u0 += NQ * NT) {
-    T yin[NQ], yaux[NQ];
+  const bool wr_out = op == ROW_SPEC_TO_SPATIAL || op == ROW_SCALE_TO_SPEC || op == ROW_FISTA ||
+                      op == ROW_EXTRAPOLATE || op == ROW_POWER_W;
+  const bool wr_aux = op == ROW_FISTA;
+  const bool wr_prev = op == ROW_FISTA && sp_prev != nullptr;
+  // Each element is read and written by one thread, so outputs that alias
+  // an input (FISTA's y) stay correct.
+  if (a.sp_vec) {
+    // rows of whole 16-byte words: a unit is V consecutive samples of one
+    // plane row, read and written with one vector access per array; two
+    // rounds of units are loaded before either is used
+    const int nxv = nx / V;
+    const int NPV = nxv * BB;
+#pragma unroll 1
+    for (int u0 = tid; u0 < NPV; u0 += 2 * NT) {
+      VT yin[2], yaux[2];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int u = u0 + q * NT;
-      const int pl = pb0 + u / nx;
-      const bool ok = u < NP && vol_on && pl < a.nplanes;
-      const size_t idx = ((size_t)pl * ny + i) * nx + u % nx;
-      yin[q] = (rd_in && ok) ? sp_in[idx] : (T)0;
-      yaux[q] = (rd_aux && ok) ? sp_aux[idx] : (T)0;
-    }
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int u = u0 + q * NT;
-      if (u >= NP) break;
-      const int j = u % nx, b = u / nx;
-      const int pl = pb0 + b;
-      const bool valid = vol_on && pl < a.nplanes;
-      const size_t idx = ((size_t)pl * ny + i) * nx + j;
-      T *slot = ((j & 1) ? wi : wr) + (j >> 1) * ld + b;
-      T x = (T)0;
-      if (spec_in) x = *slot;
-      T r = (T)0;
-      switch (op) {
-        case ROW_SPEC_TO_SPATIAL:
-          if (valid) sp_out[idx] = x;
-          break;
-        case ROW_SPATIAL_TO_SPEC:
-          r = valid ? yin[q] : (T)0;
-          break;
-        case ROW_SCALE_TO_SPEC:
-          if (valid) {
-            r = yin[q] * scale;
-            sp_out[idx] = r;
-          }
-          break;
-        case ROW_RESIDUAL:
-          if (valid) {
-            r = x - yin[q];
-            acc0 += 0.5 * (double)r * (double)r;
-          }
-          break;
-        case ROW_PASS:
-          if (valid) {
-            r = x;
-            acc0 += 0.5 * (double)x * (double)x;
-          }
-          break;
-        case ROW_FISTA:
-          if (valid) {
-            const T yk = yin[q];
-            const T mprev = yaux[q];
-            T mu = yk - tau * (x + lam * yk);
-            if (a.l1) mu -= tau * (T)a.l1[pl];  // prox of the per-layer L1 term
-            mu = mu < (T)0 ? (T)0 : mu;  // a NaN stays NaN (the solve's checks then stop it)
-            const T ynew = fista_extrapolate(mu, mprev, beta);
-            if (sp_prev) sp_prev[idx] = mprev;
-            sp_aux[idx] = mu;
-            sp_out[idx] = ynew;
-            const double dd = (double)yk - (double)mu;
-            acc0 += dd * dd;
-            if (g0acc) {
-              // y = 0 here, so x = -A^T d exactly (negation is exact in every step)
-              const double v = -(double)x - (a.l1 ? a.l1[pl] : 0.0);
-              const double gz = v > 0.0 ? v : 0.0;
-              acc1 += gz * gz;
-            }
-            r = ynew;
-          }
-          break;
-        case ROW_EXTRAPOLATE:
-          if (valid) {
-            const T ynew = fista_extrapolate(yin[q], yaux[q], beta);
-            sp_out[idx] = ynew;
-            r = ynew;
-          }
-          break;
-        case ROW_POWER_W:
-          if (valid) {
-            sp_out[idx] = x;
-            acc0 += (double)x * (double)x;
-            acc1 += (double)yin[q] * (double)x;
-          }
-          break;
-        case ROW_GMAP0:
-          if (valid) {
-            const double v = (double)x - (a.l1 ? a.l1[pl] : 0.0);
-            const double g = v > 0.0 ? v : 0.0;
-            acc0 += g * g;
-          }
-          break;
-        default:
-          break;
+      for (int q = 0; q < 2; ++q) {
+        const int u = u0 + q * NT;
+        const int pl = pb0 + u / nxv;
+        const bool ok = u < NPV && vol_on && pl < a.nplanes;
+        const size_t idx = ((size_t)pl * ny + i) * nx + (size_t)(u % nxv) * V;
+        yin[q] = (rd_in && ok) ? *reinterpret_cast<const VT *>(sp_in + idx) : VT{};
+        yaux[q] = (rd_aux && ok) ? *reinterpret_cast<const VT *>(sp_aux + idx) : VT{};
       }
-      if (spec_out) *slot = r;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int u = u0 + q * NT;
+        if (u >= NPV) break;
+        const int jq = u % nxv, b = u / nxv;
+        const int pl = pb0 + b;
+        const bool valid = vol_on && pl < a.nplanes;
+        const size_t idx = ((size_t)pl * ny + i) * nx + (size_t)jq * V;
+        VT o{}, oa{};
+#pragma unroll
+        for (int e = 0; e < V; ++e) {
+          const int j = jq * V + e;
+          T *slot = ((j & 1) ? wi : wr) + (j >> 1) * ld + b;
+          T x = (T)0;
+          if (spec_in) x = *slot;
+          T r = (T)0, ov = (T)0, oav = (T)0;
+          if (valid) point(x, yin[q][e], yaux[q][e], pl, r, ov, oav);
+          o[e] = ov;
+          oa[e] = oav;
+          if (spec_out) *slot = r;
+        }
+        if (valid) {
+          if (wr_prev) *reinterpret_cast<VT *>(sp_prev + idx) = yaux[q];
+          if (wr_aux) *reinterpret_cast<VT *>(sp_aux + idx) = oa;
+          if (wr_out) *reinterpret_cast<VT *>(sp_out + idx) = o;
+        }
+      }
+    }
+  } else {
+    // any row length: one sample per unit, four rounds loaded before use
+    constexpr int NQ = 4;
+    const int NP = nx * BB;
+    for (int u0 = tid; u0 < NP; u0 += NQ * NT) {
+      T yin[NQ], yaux[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int u = u0 + q * NT;
+        const int pl = pb0 + u / nx;
+        const bool ok = u < NP && vol_on && pl < a.nplanes;
+        const size_t idx = ((size_t)pl * ny + i) * nx + u % nx;
+        yin[q] = (rd_in && ok) ? sp_in[idx] : (T)0;
+        yaux[q] = (rd_aux && ok) ? sp_aux[idx] : (T)0;
+      }
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int u = u0 + q * NT;
+        if (u >= NP) break;
+        const int j = u % nx, b = u / nx;
+        const int pl = pb0 + b;
+        const bool valid = vol_on && pl < a.nplanes;
+        const size_t idx = ((size_t)pl * ny + i) * nx + j;
+        T *slot = ((j & 1) ? wi : wr) + (j >> 1) * ld + b;
+        T x = (T)0;
+        if (spec_in) x = *slot;
+        T r = (T)0, ov = (T)0, oav = (T)0;
+        if (valid) {
+          point(x, yin[q], yaux[q], pl, r, ov, oav);
+          if (wr_prev) sp_prev[idx] = yaux[q];
+          if (wr_aux) sp_aux[idx] = oav;
+          if (wr_out) sp_out[idx] = ov;
+        }
+        if (spec_out) *slot = r;
+      }
     }
   }
   if (spec_out) {
@@ -722,31 +774,44 @@ row_pass_kernel(int ny, int nx, RowArgs a) {
   // r2c: Z' = DFT_H(r_even + i r_odd); X'[k] = Ev[k] + e^{-2 pi i k/P} Od[k]
   dft_lds_inplace<T, H, BB, -1>(wr, wi, twc, tws);
   T *dst = reinterpret_cast<T *>(a.spec_out) + b0;
-  for (int u = tid; u < (H / 2 + 1) * BB; u += NT) {
-    const int b = u % BB, k = u / BB;
+  // a unit is (k, V consecutive planes): bins k, H - k (and H with k = 0)
+  // for V planes, each stored with 16-byte writes
+  for (int u = tid; u < (H / 2 + 1) * BQ; u += NT) {
+    const int q = u % BQ, k = u / BQ;
     const int k2 = (k == 0) ? 0 : H - k;
-    const T z1r = wr[k * ld + b], z1i = wi[k * ld + b];
-    const T z2r = wr[k2 * ld + b], z2i = wi[k2 * ld + b];
-    // bin k from (Z'[k], Z'[H-k]); bin H-k from the same pair swapped
-    // (bin H from Z'[0] with e^{-i pi} = -1)
-    {
+    const T c = twc[k], s = -tws[k];
+    const T c2 = twc[k2], s2 = -tws[k2];
+    VT pr, pi, qr, qi, hr, hi;
+#pragma unroll
+    for (int e = 0; e < V; ++e) {
+      const int b = q * V + e;
+      const T z1r = wr[k * ld + b], z1i = wi[k * ld + b];
+      const T z2r = wr[k2 * ld + b], z2i = wi[k2 * ld + b];
+      // bin k from (Z'[k], Z'[H-k]); bin H-k from the same pair swapped
+      // (bin H from Z'[0] with e^{-i pi} = -1)
       const T evr = (T)0.5 * (z1r + z2r), evi = (T)0.5 * (z1i - z2i);
       const T odr = (T)0.5 * (z1i + z2i), odi = (T)(-0.5) * (z1r - z2r);
-      const T c = twc[k], s = -tws[k];
-      dst[(((size_t)k * ny + i) * 2) * B + b] = evr + odr * c - odi * s;
-      dst[(((size_t)k * ny + i) * 2 + 1) * B + b] = evi + odr * s + odi * c;
-      if (k == 0) {
-        dst[(((size_t)H * ny + i) * 2) * B + b] = evr - odr;
-        dst[(((size_t)H * ny + i) * 2 + 1) * B + b] = evi - odi;
-      }
+      pr[e] = evr + odr * c - odi * s;
+      pi[e] = evi + odr * s + odi * c;
+      hr[e] = evr - odr;
+      hi[e] = evi - odi;
+      const T evr2 = (T)0.5 * (z2r + z1r), evi2 = (T)0.5 * (z2i - z1i);
+      const T odr2 = (T)0.5 * (z2i + z1i), odi2 = (T)(-0.5) * (z2r - z1r);
+      qr[e] = evr2 + odr2 * c2 - odi2 * s2;
+      qi[e] = evi2 + odr2 * s2 + odi2 * c2;
+    }
+    const size_t ok_ = (((size_t)k * ny + i) * 2) * B + q * V;
+    *reinterpret_cast<VT *>(dst + ok_) = pr;
+    *reinterpret_cast<VT *>(dst + ok_ + B) = pi;
+    if (k == 0) {
+      const size_t oh = (((size_t)H * ny + i) * 2) * B + q * V;
+      *reinterpret_cast<VT *>(dst + oh) = hr;
+      *reinterpret_cast<VT *>(dst + oh + B) = hi;
     }
     if (k > 0 && k < H / 2) {
-      const int kk = H - k;
-      const T evr = (T)0.5 * (z2r + z1r), evi = (T)0.5 * (z2i - z1i);
-      const T odr = (T)0.5 * (z2i + z1i), odi = (T)(-0.5) * (z2r - z1r);
-      const T c = twc[kk], s = -tws[kk];
-      dst[(((size_t)kk * ny + i) * 2) * B + b] = evr + odr * c - odi * s;
-      dst[(((size_t)kk * ny + i) * 2 + 1) * B + b] = evi + odr * s + odi * c;
+      const size_t ok2 = (((size_t)k2 * ny + i) * 2) * B + q * V;
+      *reinterpret_cast<VT *>(dst + ok2) = qr;
+      *reinterpret_cast<VT *>(dst + ok2 + B) = qi;
     }
   }
 }
@@ -841,7 +906,17 @@ hipError_t launch_col_pass(const Dims &d, int B, bool inverse, const T *in, T *o
 }
 
 template <typename T>
-hipError_t launch_row_pass(const Dims &d, const RowArgs &a, hipStream_t st) {
+hipError_t launch_row_pass(const Dims &d, const RowArgs &a0, hipStream_t st) {
+  // vector access to the spatial arrays when every row is whole 16-byte
+  // words and every array starts on a 16-byte boundary
+  RowArgs a = a0;
+  const int V = 16 / (int)sizeof(T);
+  bool vec = d.nx % V == 0;
+  for (int v = 0; v < a.nvol && v < kMaxVol; ++v)
+    for (const void *p : {a.sp_in[v], (const void *)a.sp_out[v], (const void *)a.sp_aux[v],
+                          (const void *)a.sp_prev[v]})
+      vec = vec && (reinterpret_cast<uintptr_t>(p) & 15) == 0;
+  a.sp_vec = vec ? 1 : 0;
   switch (d.p) {
     case 16: return row_dispatch<T, 16>(d, a, st);
     case 32: return row_dispatch<T, 32>(d, a, st);

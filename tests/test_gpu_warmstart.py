@@ -86,5 +86,10 @@ def test_learned_warm_start_gain():
     assert res["not_converged_zero"] == 0 and res["not_converged_warm"] == 0
     assert res["iters_ratio"] >= 2.0
     assert res["fell_back"] <= 2
-    # both stop at the same relative residual; their objectives agree on average
+    # both stop at the same gradient-mapping ratio (the configured criterion:
+    # the data misfit plateaus at the noise level and cannot be one); their
+    # objectives agree on average, and on every scan within the spread seen
+    # over 512 held-out scans (the ratio weights the slowly converging deep
+    # components weakly, so two starts can stop at different points of them)
     assert res["objective_rel_diff_mean"] <= 1e-2
+    assert res["objective_rel_diff_max"] <= 0.15
