@@ -34,7 +34,7 @@ if ROOT not in sys.path:
 
 METRIC = "recon iters/s at 128^2x64 vox, 512 bins; % HBM/MFMA peak; rel err vs FP64"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "contract_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "contract_fwd_128x128x64x512_pmc_traffic.json")
 # stage events on every 8th timed iteration: five event records between the
 # launches of an iteration cost about 4% of its time, and 1 in 8 still gives
 # each kernel's average duration over 25 launches of a 200-iteration run
@@ -201,8 +201,8 @@ def composite_target(ctof, torch, dev, rel_tol: float = 1e-3, n_scans: int = 64,
         ctof.tune(plain_k[g], nvol=1, iters=3)
         tb = ctof.tune(batch_k[g], nvol=counts[g], iters=3)
         ta = ctof.tune(acc_k[g], nvol=counts[g], iters=3)
-        tuning[f"{g.nx}x{g.nz}"] = {"fp32": {"bb": tb["bb"], "parts": tb["parts"]},
-                                    "bf16x3": {"bb": ta["bb"], "parts": ta["parts"]}}
+        tuning[f"{g.nx}x{g.nz}"] = {"fp32": {"bb": tb["bb"], "rb": tb["rb"], "parts": tb["parts"]},
+                                    "bf16x3": {"bb": ta["bb"], "rb": ta["rb"], "parts": ta["parts"]}}
     ds = []
     for g, sd, peak in scans:
         mu = phantoms.phantom(g, sd, **rec)
@@ -221,6 +221,7 @@ def composite_target(ctof, torch, dev, rel_tol: float = 1e-3, n_scans: int = 64,
     net = unet.load_all(device=dev)
     # warm-up of every path (graph capture, kernels, network) on one scan per class
     for g, i in first.items():
+        plain_k[g].workspace(plain_k[g].workspace_bytes(max_iter)[1], dev)
         ctof.reconstruct(plain_k[g], ds[i], max_iter=3, lam=lip[g][1], lipschitz=lip[g][0])
     torch.cuda.synchronize()
 
@@ -772,11 +773,13 @@ def main() -> int:
         # FFT planes per block for this shape and one volume (set-up, untimed,
         # like tabulation)
         t = ctof.tune(k, nvol=1, iters=5)
-        tuning = {"bb_t": t["bb"][0], "bb_z": t["bb"][1], "fwd_parts": t["parts"][0], "adj_parts": t["parts"][1],
-                  "ms_per_iter_bb": t["ms_bb"], "ms_per_iter_fwd_parts": t["ms_fwd"],
+        tuning = {"bb_t": t["bb"][0], "bb_z": t["bb"][1], "rb_t": t["rb"][0], "rb_z": t["rb"][1],
+                  "fwd_parts": t["parts"][0], "adj_parts": t["parts"][1],
+                  "ms_per_iter_bb": t["ms_bb"], "ms_per_iter_rb": t["ms_rb"], "ms_per_iter_fwd_parts": t["ms_fwd"],
                   "ms_per_iter_adj_parts": t["ms_adj"]}
-        log(f"tuned launch shape: FFT planes per block {t['bb']}, contraction blocks per matrix {t['parts']} "
-            f"(ms per iteration: planes {t['ms_bb']}, forward {t['ms_fwd']}, adjoint {t['ms_adj']})")
+        log(f"tuned launch shape: FFT planes per block {t['bb']}, row passes {t['rb']}, contraction blocks per "
+            f"matrix {t['parts']} (ms per iteration: planes {t['ms_bb']}, row planes {t['ms_rb']}, "
+            f"forward {t['ms_fwd']}, adjoint {t['ms_adj']})")
 
     mu_true = phantoms.workload_phantom(w, g, args.seed)
     m_true = ctof.forward(k, torch.tensor(mu_true, dtype=dtype, device=dev))
@@ -792,6 +795,9 @@ def main() -> int:
     L, lam = rep0.lipschitz, rep0.lam
     log(f"power iteration L={L:.6e} lambda={lam:.3e} ({t_setup:.3f}s incl. one iteration)")
 
+    # the solver's workspace, sized once for the timed call (the caller's
+    # allocation, set-up like tabulation)
+    k.workspace(k.workspace_bytes(max(args.steps, args.warmup))[1], dev)
     if args.warmup > 0:
         ctof.reconstruct(k, d, max_iter=args.warmup, lam=lam, lipschitz=L)
     torch.cuda.synchronize()

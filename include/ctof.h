@@ -452,6 +452,19 @@ ctof_status ctof_reconstruct_batched(int32_t nscan, const ctof_kernel *k, const 
  */
 ctof_status ctof_kernel_set_tuning(ctof_kernel k, int32_t bb_t, int32_t bb_z);
 ctof_status ctof_kernel_get_tuning(ctof_kernel k, int32_t *bb_t, int32_t *bb_z);
+/*
+ * Planes per block of the row passes alone (the passes that hold whole rows
+ * of the spectrum: the c2r/r2c pair around the residual and around the
+ * prox/FISTA step), on the bin side (rb_t) and the layer side (rb_z): 0 (the
+ * column passes' value), 16, 32 or 64.  64 (256-byte runs of the spectrum,
+ * two blocks per compute unit) applies to FP32 handles with FFT size <= 256
+ * and plane counts divisible by 64; elsewhere a 64 acts as 32.  Changes
+ * launch shapes and workspace sizes; the iterates are unchanged, the FP64
+ * norms change only by their summation order.  get reports the effective
+ * values for one volume.
+ */
+ctof_status ctof_kernel_set_row_tuning(ctof_kernel k, int32_t rb_t, int32_t rb_z);
+ctof_status ctof_kernel_get_row_tuning(ctof_kernel k, int32_t *rb_t, int32_t *rb_z);
 
 /*
  * Launch shape of a handle's contractions (the per-frequency products of
@@ -473,9 +486,10 @@ ctof_status ctof_kernel_get_contract_parts(ctof_kernel k, int32_t *fwd_parts, in
  * Launch-shape tuner for a class of nvol volumes sharing the handle (the
  * batching form's per-class choice): times `iters` operator passes (the
  * eight launches of an iteration) for each legal FFT planes-per-block pair
- * with the contractions at their rule, then, with the fastest pair, the
- * forward contraction's blocks per matrix 1, 2, 4, 8, then the adjoint's,
- * keeps the fastest of each in the handle (ctof_kernel_set_tuning,
+ * with the contractions at their rule, then, with the fastest pair, the row
+ * passes' planes per block, then the forward contraction's blocks per
+ * matrix 1, 2, 4, 8, then the adjoint's, keeps the fastest of each in the
+ * handle (ctof_kernel_set_tuning, ctof_kernel_set_row_tuning,
  * ctof_kernel_set_contract_parts) and reports every timing.  The FFT size
  * is not a choice: the radix-2 passes take the power of two >= 2n - 1 (a
  * smaller non-power-of-two size would need other radices).  Choices change
@@ -486,10 +500,15 @@ ctof_status ctof_kernel_get_contract_parts(ctof_kernel k, int32_t *fwd_parts, in
  *           (32,32); -1 where the block rule does not allow the pair
  *   ms_fwd, ms_adj   for 1, 2, 4, 8 blocks per matrix; -1 where the value
  *           clamps to one timed before
+ *   ms_rb   for row-pass planes (rb_t, rb_z) = (bb_t, bb_z), (64, bb_z),
+ *           (bb_t, 64), (64, 64); -1 where 64 does not apply
+ *   rb_t, rb_z   the row passes' effective planes per block
  */
 typedef struct {
   int32_t bb_t, bb_z, fwd_parts, adj_parts;
   float ms_bb[4], ms_fwd[4], ms_adj[4];
+  int32_t rb_t, rb_z;
+  float ms_rb[4];
 } ctof_tuning;
 ctof_status ctof_tune_workspace_bytes(ctof_kernel k, int32_t nvol, size_t *ws_bytes);
 ctof_status ctof_tune(ctof_kernel k, int32_t nvol, int32_t iters, void *ws_dev, size_t ws_bytes,

@@ -207,6 +207,12 @@ struct ClassWs {
   size_t part_stride;  // doubles per iteration
 };
 
+// planes per block of a handle's row passes on the bin (tside) or layer side
+int row_planes(const ctof_kernel_s *k, bool tside) {
+  const int rb = tside ? k->rb_t : k->rb_z;
+  return rb ? rb : (tside ? k->bb_t : k->bb_z);
+}
+
 ClassWs class_ws(const ctof_kernel_s *k, int nvol, int max_iter) {
   const ctof::Dims &d = k->dims;
   ClassWs o;
@@ -230,8 +236,8 @@ ClassWs class_ws(const ctof_kernel_s *k, int nvol, int max_iter) {
   o.y = take(vol * nvol);
   o.v = take(vol);
   o.w = take(vol);
-  o.nblk_t = ctof::row_pass_blocks(d, nvol * d.ntp, d.ntp, f64, k->bb_t);
-  o.nblk_z = ctof::row_pass_blocks(d, nvol * d.nzp, d.nzp, f64, k->bb_z);
+  o.nblk_t = ctof::row_pass_blocks(d, nvol * d.ntp, d.ntp, f64, row_planes(k, true));
+  o.nblk_z = ctof::row_pass_blocks(d, nvol * d.nzp, d.nzp, f64, row_planes(k, false));
   o.part_stride = 2 * (size_t)(o.nblk_t + o.nblk_z);
   const int iters = std::max(max_iter, 1);
   o.hist = take((size_t)iters * nvol * 2 * 8);
@@ -289,7 +295,7 @@ struct Engine {
     a.ppv = tside ? dm().ntp : dm().nzp;
     a.nplanes = tside ? dm().nt : dm().nz;
     a.nvol = nvol;
-    a.bb = tside ? k->bb_t : k->bb_z;
+    a.bb = row_planes(k, tside);
     a.spec_in = tside ? (void *)xt() : (void *)xz();
     a.spec_out = const_cast<void *>(a.spec_in);
     a.l1 = tside ? nullptr : l1dev;
@@ -777,15 +783,19 @@ ctof_status restart_from_zero(const Engine<T> &E, void *const *mu, const std::ve
 // 1/2 ||A mu_v - d_v||^2 per volume into out[v] (device)
 template <typename T>
 ctof_status enqueue_final_fit(const Engine<T> &E, const void *const *d, void *const *mu, double *pf,
-                              double *out) {
-  ctof::RowArgs a = E.row(ctof::ROW_SPATIAL_TO_SPEC, false);
-  for (int v = 0; v < E.nvol; ++v) a.sp_in[v] = mu[v];
-  HIP_TRY(E.mu_to_spec(a));
+                              double *out, bool have_spec = false) {
+  // (have_spec: the spectrum buffer already holds that of mu)
+  if (!have_spec) {
+    ctof::RowArgs a = E.row(ctof::ROW_SPATIAL_TO_SPEC, false);
+    for (int v = 0; v < E.nvol; ++v) a.sp_in[v] = mu[v];
+    HIP_TRY(E.mu_to_spec(a));
+  }
   HIP_TRY(E.fwd_to_xt());
   if (E.mux) {
     if (ctof_status s = enqueue_mux_residual(E, d, pf, false); s != CTOF_OK) return s;
   } else {
-    ctof::RowArgs b = E.row(ctof::ROW_RESIDUAL, true);
+    // only the norm is needed: no spectrum of the residual
+    ctof::RowArgs b = E.row(ctof::ROW_FIT, true);
     for (int v = 0; v < E.nvol; ++v) b.sp_in[v] = d[v];
     b.partials = pf;
     HIP_TRY(E.run_row(b));
@@ -805,7 +815,7 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
   const int K = opt->max_iter;
   const int k0 = opt->k0;
   const size_t vol = (size_t)dm.nz * dm.ny * dm.nx;
-  // scalars: [0] |w|^2  [1] <v,w>  [3] final fit  [5..6] last history row
+  // scalars: [0] |w|^2  [1] <v,w>  [3] final fit  [5..6] last history row  [16..24] packed report
   HIP_TRY(ctof::launch_fill_zero(scal, 64 * 8, st));
   if (opt->lambda_l1_z) {
     HIP_TRY(hipMemcpyAsync(E.l1(), opt->lambda_l1_z, (size_t)dm.nz * sizeof(double), hipMemcpyHostToDevice, st));
@@ -916,6 +926,9 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
     b.lambda = lam;
     b.beta = beta_at(k0 + it - base);
     if (fused_g0 && it == 0) b.gmap0_at = 0;
+    // the last step transforms mu_K itself: the final data fit needs its
+    // spectrum, and no step follows that would use the one of y_{K+1}
+    b.spec_of_mu = it == K - 1;
     HIP_TRY(E.run_row(b));
     if (fused_g0 && it == 0)
       HIP_TRY(ctof::launch_reduce_volumes(pk + 2 * (size_t)E.L.nblk_t + 1, E.L.nblk_z, 1, E.g0sq(), st));
@@ -953,17 +966,18 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
   if (opt->history_dev && kept > 0)
     HIP_TRY(hipMemcpyAsync(opt->history_dev, E.hist(), (size_t)kept * 2 * sizeof(double),
                            hipMemcpyDeviceToDevice, st));
-  if (ctof_status s = enqueue_final_fit(E, dd, mm, E.part() + (size_t)K * E.L.part_stride, scal + 3);
+  // after all K steps the spectrum buffer holds that of mu_K (also after a
+  // fallback in a one-step call: mu = y = 0 and their spectrum recomputed)
+  if (ctof_status s = enqueue_final_fit(E, dd, mm, E.part() + (size_t)K * E.L.part_stride, scal + 3, done == K);
       s != CTOF_OK)
     return s;
-  double hs[4], h0[2] = {0, 0}, hl[2] = {0, 0}, g0;
-  HIP_TRY(hipMemcpyAsync(hs, scal, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
-  if (kept > 0) {
-    HIP_TRY(hipMemcpyAsync(h0, E.hist(), 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(hl, E.hist() + 2 * (size_t)(kept - 1), 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-  }
-  HIP_TRY(hipMemcpyAsync(&g0, E.g0sq(), sizeof(double), hipMemcpyDeviceToHost, st));
+  // scalars, first and last history rows and ||G(0)||^2, read back with one copy
+  double pk[9];
+  HIP_TRY(ctof::launch_pack_report(scal, E.hist(), kept, E.g0sq(), scal + 16, st));
+  HIP_TRY(hipMemcpyAsync(pk, scal + 16, sizeof(pk), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
+  const double *hs = pk, *h0 = pk + 4, *hl = pk + 6;
+  const double g0 = pk[8];
   if (tstride > 0 && done > 0) {
     // iterations 0, n, ... below `done` were timed (an early stop leaves the
     // later samples unrecorded)
@@ -1119,8 +1133,8 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
       Engine<T> E1 = E[c];
       const bool f64 = E1.k->prec == CTOF_FP64;
       E1.nvol = 1;
-      E1.L.nblk_t = ctof::row_pass_blocks(E1.dm(), E1.dm().ntp, E1.dm().ntp, f64, E1.k->bb_t);
-      E1.L.nblk_z = ctof::row_pass_blocks(E1.dm(), E1.dm().nzp, E1.dm().nzp, f64, E1.k->bb_z);
+      E1.L.nblk_t = ctof::row_pass_blocks(E1.dm(), E1.dm().ntp, E1.dm().ntp, f64, row_planes(E1.k, true));
+      E1.L.nblk_z = ctof::row_pass_blocks(E1.dm(), E1.dm().nzp, E1.dm().nzp, f64, row_planes(E1.k, false));
       if (ctof_status s = enqueue_power_iteration(E1, opt->power_iters > 0 ? opt->power_iters : 50); s != CTOF_OK)
         return s;
     }
@@ -1437,9 +1451,11 @@ ctof_status run_tune(ctof_kernel_s *k, int nvol, int iters, void *ws, hipStream_
     return CTOF_OK;
   };
   std::memset(out, 0, sizeof(*out));
-  // 1. FFT planes per block, contractions at the built-in rule
+  // 1. FFT planes per block, row passes alike, contractions at the built-in rule
   k->fwd_parts = 0;
   k->adj_parts = 0;
+  k->rb_t = 0;
+  k->rb_z = 0;
   float best = 1e30f;
   int bi = 0;
   const bool f64 = k->prec == CTOF_FP64;
@@ -1463,7 +1479,33 @@ ctof_status run_tune(ctof_kernel_s *k, int nvol, int iters, void *ws, hipStream_
   }
   k->bb_t = cand[bi][0];
   k->bb_z = cand[bi][1];
-  // 2. forward, then 3. adjoint blocks per matrix (values that clamp to one
+  // 2. the row passes' planes per block: the column passes' or 64 (pairs the
+  // rule does not allow are skipped; the first repeats the choice above)
+  const int rcand[4][2] = {{0, 0}, {64, 0}, {0, 64}, {64, 64}};
+  {
+    float bestr = 1e30f;
+    int ri = 0;
+    for (int c = 0; c < 4; ++c) {
+      k->rb_t = rcand[c][0];
+      k->rb_z = rcand[c][1];
+      const Engine<T> E = engine<T>(k, nvol, ws, 1, st);
+      if ((rcand[c][0] && ctof::row_block(E.dm(), E.Bt(), E.dm().ntp, f64, 64) != 64) ||
+          (rcand[c][1] && ctof::row_block(E.dm(), E.Bz(), E.dm().nzp, f64, 64) != 64)) {
+        out->ms_rb[c] = -1.f;
+        continue;
+      }
+      float ms = 0.f;
+      if (ctof_status s = time_shape(&ms); s != CTOF_OK) return s;
+      out->ms_rb[c] = ms;
+      if (ms < bestr) {
+        bestr = ms;
+        ri = c;
+      }
+    }
+    k->rb_t = rcand[ri][0];
+    k->rb_z = rcand[ri][1];
+  }
+  // 3. forward, then 4. adjoint blocks per matrix (values that clamp to one
   // already timed are skipped)
   for (int dir = 0; dir < 2; ++dir) {
     float *row = dir == 0 ? out->ms_fwd : out->ms_adj;
@@ -1493,6 +1535,8 @@ ctof_status run_tune(ctof_kernel_s *k, int nvol, int iters, void *ws, hipStream_
   }
   out->bb_t = k->bb_t;
   out->bb_z = k->bb_z;
+  out->rb_t = row_planes(k, true);
+  out->rb_z = row_planes(k, false);
   out->fwd_parts = ctof::contract_parts(k, false);
   out->adj_parts = ctof::contract_parts(k, true);
   return CTOF_OK;
@@ -1991,6 +2035,24 @@ ctof_status ctof_kernel_set_tuning(ctof_kernel k, int32_t bb_t, int32_t bb_z) {
   return CTOF_OK;
 }
 
+ctof_status ctof_kernel_set_row_tuning(ctof_kernel k, int32_t rb_t, int32_t rb_z) {
+  if (ctof_status s = check_kernel(k); s != CTOF_OK) return s;
+  auto ok = [](int32_t v) { return v == 0 || v == 16 || v == 32 || v == 64; };
+  if (!ok(rb_t) || !ok(rb_z)) return set_error(CTOF_EINVAL, "row-pass planes per block must be 0, 16, 32 or 64");
+  k->rb_t = rb_t;
+  k->rb_z = rb_z;
+  return CTOF_OK;
+}
+
+ctof_status ctof_kernel_get_row_tuning(ctof_kernel k, int32_t *rb_t, int32_t *rb_z) {
+  if (ctof_status s = check_kernel(k); s != CTOF_OK) return s;
+  const ctof::Dims &d = k->dims;
+  const bool f64 = k->prec == CTOF_FP64;
+  if (rb_t) *rb_t = ctof::row_block(d, d.ntp, d.ntp, f64, row_planes(k, true));
+  if (rb_z) *rb_z = ctof::row_block(d, d.nzp, d.nzp, f64, row_planes(k, false));
+  return CTOF_OK;
+}
+
 ctof_status ctof_kernel_set_contract_parts(ctof_kernel k, int32_t fwd_parts, int32_t adj_parts) {
   if (ctof_status s = check_kernel(k); s != CTOF_OK) return s;
   auto ok = [](int32_t v) { return v == 0 || v == 1 || v == 2 || v == 4 || v == 8; };
@@ -2016,18 +2078,23 @@ ctof_status ctof_kernel_get_tuning(ctof_kernel k, int32_t *bb_t, int32_t *bb_z) 
 
 // largest workspace over the launch shapes the tuner tries
 static size_t tune_ws_bytes(ctof_kernel_s *k, int nvol) {
-  const int32_t save_t = k->bb_t, save_z = k->bb_z, save_a = k->adj_parts;
+  const int32_t save_t = k->bb_t, save_z = k->bb_z, save_a = k->adj_parts, save_rt = k->rb_t, save_rz = k->rb_z;
   size_t need = 0;
   for (int bt : {16, 32})
     for (int bz : {16, 32})
-      for (int ap : {1, 2, 4, 8}) {
-        k->bb_t = bt;
-        k->bb_z = bz;
-        k->adj_parts = ap;
-        need = std::max(need, class_ws(k, nvol, 1).solve_total);
-      }
+      for (int rb : {0, 64})
+        for (int ap : {1, 2, 4, 8}) {
+          k->bb_t = bt;
+          k->bb_z = bz;
+          k->rb_t = rb;
+          k->rb_z = rb;
+          k->adj_parts = ap;
+          need = std::max(need, class_ws(k, nvol, 1).solve_total);
+        }
   k->bb_t = save_t;
   k->bb_z = save_z;
+  k->rb_t = save_rt;
+  k->rb_z = save_rz;
   k->adj_parts = save_a;
   return need;
 }

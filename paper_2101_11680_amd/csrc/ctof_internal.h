@@ -95,6 +95,7 @@ struct ctof_kernel_s {
   void *khat;                 // caller-owned device buffer
   ctof::KhatLayout layout;
   int bb_t, bb_z;             // FFT planes per block on the bin / layer side (0 = rule)
+  int rb_t = 0, rb_z = 0;     // row passes' planes per block where they differ (0 = bb_t / bb_z)
   const int *band = nullptr;  // caller-owned device table: per matrix {lo, hi, zend, 0} (NULL = all)
   double band_rel = 0.0;      // threshold the table was made with (0 = none)
   int fwd_parts = 0, adj_parts = 0;  // contraction blocks per matrix (0 = rule), see contract_parts
@@ -137,7 +138,8 @@ enum RowOp : int {
   ROW_POWER_W = 5,           // c2r -> store w, partials |w|^2 and <v, w>
   ROW_GMAP0 = 6,             // c2r -> partial |max(0, x)|^2
   ROW_SCALE_TO_SPEC = 7,     // spatial w * (1/sqrt(scalar)) -> store v -> r2c
-  ROW_EXTRAPOLATE = 8        // y = mu + beta (mu - mu_prev) -> store y -> r2c (resumed FISTA)
+  ROW_EXTRAPOLATE = 8,       // y = mu + beta (mu - mu_prev) -> store y -> r2c (resumed FISTA)
+  ROW_FIT = 9                // c2r -> r = x - d, partial 1/2 r^2 (data fit only: no r2c, no stores)
 };
 
 struct RowArgs {
@@ -167,6 +169,8 @@ struct RowArgs {
   int gmap0_at;            // ROW_FISTA: at this iteration (the counter's value, 0 without one) partial 1
                            // also receives |max(0, -x - l1)|^2, the gradient mapping at zero when y = 0
                            // (x = A^T (A 0 - d) = -A^T d); -1: never
+  int spec_of_mu;          // ROW_FISTA: the spectrum written is that of mu_k instead of y_{k+1} (a final step
+                           // whose data fit follows; y_{k+1} is still stored)
 };
 
 template <typename T>
@@ -174,6 +178,9 @@ hipError_t launch_row_pass(const Dims &d, const RowArgs &a, hipStream_t st);
 // Blocks of a row pass over B planes with ppv planes per volume and an
 // optional planes-per-block override (0 = default rule).
 int row_pass_blocks(const Dims &d, int B, int ppv, bool fp64, int bb = 0);
+// Planes per block of a row pass: bb = 64 where allowed (FP32, FFT size <=
+// 256, 64 | B and 64 | ppv), else the column-pass rule (64 asks for 32 there).
+int row_block(const Dims &d, int B, int ppv, bool fp64, int bb = 0);
 int batch_block(const Dims &d, int B, int ppv, bool fp64, int bb = 0);
 
 // ---- contraction (contract.hip) ---------------------------------------------
@@ -247,6 +254,11 @@ hipError_t launch_history(const double *partials, int iters, int nvol, int nblk_
 hipError_t launch_freeze(const double *partials, size_t stride, const int *ctr, int nvol, int nblk_t, int nblk_z,
                          double tau, double *g0sq, const double *g0_part, double rel_tol, int *active, int *conv,
                          hipStream_t st);
+// The end-of-solve values in one place, so that one copy reads them back:
+// out[0..3] = scal[0..3], out[4..5] = history row 0 and out[6..7] row
+// kept - 1 (zeros when kept = 0), out[8] = g0sq[0].
+hipError_t launch_pack_report(const double *scal, const double *hist, int kept, const double *g0sq, double *out,
+                              hipStream_t st);
 // out[v] = sum of partial 0 over the v-th of nvol equal block ranges
 hipError_t launch_reduce_volumes(const double *partials, int nblk, int nvol, double *out, hipStream_t st);
 hipError_t launch_increment(int *ctr, hipStream_t st);

@@ -288,26 +288,35 @@ col_pass_kernel(int ny, int B, const T *__restrict__ in, T *__restrict__ out, in
 }
 
 // Two-stage length-H DFT in place on (wr, wi)[m * ld + b], natural order in
-// and out; every thread holds at most one stage-2 unit.
-template <typename T, int H, int BB, int DIR, int TSTEP = 2>
+// and out, for blocks of NT threads; a thread holds its NU stage-2 units in
+// registers between the two barriers.
+template <typename T, int H, int BB, int DIR, int TSTEP = 2, int NT = 512>
 __device__ __forceinline__ void dft_lds_inplace(T *wr, T *wi, const T *twc, const T *tws) {
   constexpr int R1 = Fac<H>::R1, R2 = Fac<H>::R2;
   constexpr int ld = BB + 1;
+  constexpr int NU = (R1 * BB + NT - 1) / NT;
   // stage-1 twiddles W_H^m live at index TSTEP m of the length-(TSTEP H) table
   dft_stage1<T, R1, R2, BB, DIR>(wr, wi, ld, twc, tws, TSTEP, TSTEP * H - 1);
   __syncthreads();
   const int tid = threadIdx.x;
-  const bool act = tid < R1 * BB;
-  const int b = tid % BB, k1 = tid / BB;
-  T zr[R2], zi[R2];
-  if (act) dft_stage2_unit<T, R1, R2, DIR>(wr, wi, ld, k1, b, zr, zi);
-  __syncthreads();
-  if (act) {
+  T zr[NU][R2], zi[NU][R2];
 #pragma unroll
-    for (int k2 = 0; k2 < R2; ++k2) {
-      const int m = k1 + R1 * k2;
-      wr[m * ld + b] = zr[k2];
-      wi[m * ld + b] = zi[k2];
+  for (int q = 0; q < NU; ++q) {
+    const int u = tid + q * NT;
+    if (u < R1 * BB) dft_stage2_unit<T, R1, R2, DIR>(wr, wi, ld, u / BB, u % BB, zr[q], zi[q]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NU; ++q) {
+    const int u = tid + q * NT;
+    if (u < R1 * BB) {
+      const int b = u % BB, k1 = u / BB;
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) {
+        const int m = k1 + R1 * k2;
+        wr[m * ld + b] = zr[q][k2];
+        wi[m * ld + b] = zi[q][k2];
+      }
     }
   }
   __syncthreads();
@@ -598,6 +607,7 @@ row_pass_kernel(int ny, int nx, RowArgs a) {
         o = r;
         break;
       case ROW_RESIDUAL:
+      case ROW_FIT:
         r = x - yi;
         acc0 += 0.5 * (double)r * (double)r;
         break;
@@ -620,7 +630,7 @@ row_pass_kernel(int ny, int nx, RowArgs a) {
           const double gz = v > 0.0 ? v : 0.0;
           acc1 += gz * gz;
         }
-        r = ynew;
+        r = a.spec_of_mu ? mu : ynew;
         break;
       }
       case ROW_EXTRAPOLATE:
@@ -643,7 +653,7 @@ row_pass_kernel(int ny, int nx, RowArgs a) {
     }
   };
   const bool rd_in = op == ROW_SPATIAL_TO_SPEC || op == ROW_SCALE_TO_SPEC || op == ROW_RESIDUAL ||
-                     op == ROW_FISTA || op == ROW_POWER_W || op == ROW_EXTRAPOLATE;
+                     op == ROW_FIT || op == ROW_FISTA || op == ROW_POWER_W || op == ROW_EXTRAPOLATE;
   const bool rd_aux = op == ROW_FISTA || op == ROW_EXTRAPOLATE;
   const bool wr_out = op == ROW_SPEC_TO_SPATIAL || op == ROW_SCALE_TO_SPEC || op == ROW_FISTA ||
                       op == ROW_EXTRAPOLATE || op == ROW_POWER_W;
@@ -881,7 +891,12 @@ hipError_t row_dispatch(const Dims &d, const RowArgs &a, hipStream_t st) {
   }
   else {
     if constexpr (P <= 256) {
-      if (batch_block(d, a.B, a.ppv, sizeof(T) == 8, a.bb) == 32) return row_dispatch_bb<T, P, 32>(d, a, st);
+      // (row_pass_blocks counts the blocks with the same rule)
+      const int rb = row_block(d, a.B, a.ppv, sizeof(T) == 8, a.bb);
+      if constexpr (sizeof(T) == 4) {
+        if (rb == 64) return row_dispatch_bb<T, P, 64>(d, a, st);
+      }
+      if (rb == 32) return row_dispatch_bb<T, P, 32>(d, a, st);
     }
     return row_dispatch_bb<T, P, 16>(d, a, st);
   }
@@ -942,8 +957,16 @@ int batch_block(const Dims &d, int B, int ppv, bool fp64, int bb) {
   return ((d.h + 1) * (B / 32) >= 1024) ? 32 : 16;
 }
 
+// A row pass also takes 64 planes per block (256-byte runs of the spectrum,
+// 67 KB of LDS: two blocks per compute unit) where asked for: FP32 at FFT
+// sizes up to 256 with 64 dividing the planes per volume.
+int row_block(const Dims &d, int B, int ppv, bool fp64, int bb) {
+  if (bb == 64 && !fp64 && d.p <= 256 && B % 64 == 0 && ppv % 64 == 0) return 64;
+  return batch_block(d, B, ppv, fp64, bb == 64 ? 32 : bb);
+}
+
 int row_pass_blocks(const Dims &d, int B, int ppv, bool fp64, int bb) {
-  return d.ny * (B / batch_block(d, B, ppv, fp64, bb));
+  return d.ny * (B / row_block(d, B, ppv, fp64, bb));
 }
 
 template hipError_t launch_col_pass<float>(const Dims &, int, bool, const float *, float *, hipStream_t, int, int,

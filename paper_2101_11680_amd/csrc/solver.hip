@@ -119,6 +119,18 @@ __global__ void beta_table_kernel(double *beta, int first, int count) {
   }
 }
 
+__global__ void pack_report_kernel(const double *__restrict__ scal, const double *__restrict__ hist, int kept,
+                                   const double *__restrict__ g0sq, double *__restrict__ out) {
+  if (threadIdx.x != 0) return;
+  for (int j = 0; j < 4; ++j) out[j] = scal[j];
+  const size_t last = kept > 0 ? 2 * (size_t)(kept - 1) : 0;
+  out[4] = kept > 0 ? hist[0] : 0.0;
+  out[5] = kept > 0 ? hist[1] : 0.0;
+  out[6] = kept > 0 ? hist[last] : 0.0;
+  out[7] = kept > 0 ? hist[last + 1] : 0.0;
+  out[8] = g0sq[0];
+}
+
 __global__ void fill_int_kernel(int *p, int n, int v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -158,6 +170,12 @@ hipError_t launch_freeze(const double *partials, size_t stride, const int *ctr, 
                          hipStream_t st) {
   hipLaunchKernelGGL(freeze_kernel, dim3((unsigned)nvol), dim3(256), 0, st, partials, stride, ctr, nvol, nblk_t,
                      nblk_z, tau, g0sq, g0_part, rel_tol, active, conv);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_report(const double *scal, const double *hist, int kept, const double *g0sq, double *out,
+                              hipStream_t st) {
+  hipLaunchKernelGGL(pack_report_kernel, dim3(1), dim3(64), 0, st, scal, hist, kept, g0sq, out);
   return hipGetLastError();
 }
 

@@ -38,7 +38,8 @@ EXPORTS = ("ctof_kernel_bytes", "ctof_kernel_tabulate", "ctof_kernel_tabulate_qu
            "ctof_sumsq_ws_bytes", "ctof_sumsq", "ctof_layer_threshold_ws_bytes", "ctof_layer_threshold",
            "ctof_mux_forward", "ctof_mux_adjoint", "ctof_mux_normal_ws_bytes", "ctof_mux_normal",
            "ctof_noisy_counts", "ctof_layer_energy_ws_bytes", "ctof_l1_depth_weights",
-           "ctof_forward_noalloc", "ctof_kernel_set_contract_parts", "ctof_kernel_get_contract_parts")
+           "ctof_forward_noalloc", "ctof_kernel_set_contract_parts", "ctof_kernel_get_contract_parts",
+           "ctof_kernel_set_row_tuning", "ctof_kernel_get_row_tuning")
 
 
 class CtofError(RuntimeError):
@@ -79,7 +80,8 @@ class _SolverOpts(ctypes.Structure):
 class _Tuning(ctypes.Structure):
     _fields_ = [("bb_t", ctypes.c_int32), ("bb_z", ctypes.c_int32), ("fwd_parts", ctypes.c_int32),
                 ("adj_parts", ctypes.c_int32), ("ms_bb", ctypes.c_float * 4), ("ms_fwd", ctypes.c_float * 4),
-                ("ms_adj", ctypes.c_float * 4)]
+                ("ms_adj", ctypes.c_float * 4), ("rb_t", ctypes.c_int32), ("rb_z", ctypes.c_int32),
+                ("ms_rb", ctypes.c_float * 4)]
 
 
 class _SolverReport(ctypes.Structure):
@@ -176,6 +178,8 @@ def lib() -> ctypes.CDLL:
         L.ctof_forward_noalloc.argtypes = [vp, vp, vp, vp]
         L.ctof_kernel_set_contract_parts.argtypes = [vp, i32, i32]
         L.ctof_kernel_get_contract_parts.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+        L.ctof_kernel_set_row_tuning.argtypes = [vp, i32, i32]
+        L.ctof_kernel_get_row_tuning.argtypes = [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]
         L.ctof_l1_depth_weights.argtypes = [vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double),
                                             ctypes.POINTER(ctypes.c_double), vp, sz, vp]
         mp = ctypes.POINTER(_Mux)
@@ -659,6 +663,19 @@ def set_contract_parts(k: Kernel, fwd_parts: int, adj_parts: int) -> None:
     k._ws = {}
 
 
+def set_row_tuning(k: Kernel, rb_t: int, rb_z: int) -> None:
+    """Planes per block of the row passes alone (0 = the column passes')."""
+    _check(lib().ctof_kernel_set_row_tuning(k.handle, int(rb_t), int(rb_z)))
+    k._ws = {}
+
+
+def get_row_tuning(k: Kernel) -> tuple:
+    """The row passes' effective (bin-side, layer-side) planes per block."""
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().ctof_kernel_get_row_tuning(k.handle, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
 def get_contract_parts(k: Kernel) -> tuple:
     """The effective (forward, adjoint) blocks per spectrum matrix."""
     a, b = ctypes.c_int32(), ctypes.c_int32()
@@ -674,13 +691,14 @@ def get_tuning(k: Kernel) -> tuple:
 
 def tune(k: Kernel, nvol: int = 1, iters: int = 5, cache: Optional[str] = None, stream=None) -> dict:
     """Pick a handle's launch shape for a class of `nvol` volumes by timing
-    (ctof_tune: FFT planes per block, then the contractions' blocks per
-    matrix), with a JSON cache.
+    (ctof_tune: FFT planes per block, the row passes' planes per block, then
+    the contractions' blocks per matrix), with a JSON cache.
 
     The cache (default: $CTOF_TUNE_CACHE, else no cache) maps
     "arch|grid|nz|nt|precision|nvol" to the choice and its timings.  Returns
-    {"bb": (bb_t, bb_z), "parts": (fwd, adj), "ms_bb": [4], "ms_fwd": [4],
-    "ms_adj": [4], "cached": bool} (timings None when taken from the cache).
+    {"bb": (bb_t, bb_z), "rb": (rb_t, rb_z), "parts": (fwd, adj), "ms_bb": [4],
+    "ms_rb": [4], "ms_fwd": [4], "ms_adj": [4], "cached": bool} (timings None
+    when taken from the cache).
     """
     import json
     torch = _torch()
@@ -693,13 +711,15 @@ def tune(k: Kernel, nvol: int = 1, iters: int = 5, cache: Optional[str] = None, 
     if cache and os.path.exists(cache):
         with open(cache) as f:
             table = json.load(f)
-        if key in table and "parts" in table[key]:
+        if key in table and "parts" in table[key] and "rb" in table[key]:
             bt, bz = table[key]["bb"]
+            rt, rz = table[key]["rb"]
             fp, ap = table[key]["parts"]
             set_tuning(k, bt, bz)
+            set_row_tuning(k, rt, rz)
             set_contract_parts(k, fp, ap)
-            return {"bb": (bt, bz), "parts": (fp, ap), "ms_bb": None, "ms_fwd": None, "ms_adj": None,
-                    "cached": True}
+            return {"bb": (bt, bz), "rb": (rt, rz), "parts": (fp, ap), "ms_bb": None, "ms_rb": None,
+                    "ms_fwd": None, "ms_adj": None, "cached": True}
     nb = ctypes.c_size_t()
     _check(lib().ctof_tune_workspace_bytes(k.handle, int(nvol), ctypes.byref(nb)))
     ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=dev)
@@ -707,12 +727,12 @@ def tune(k: Kernel, nvol: int = 1, iters: int = 5, cache: Optional[str] = None, 
     _check(lib().ctof_tune(k.handle, int(nvol), int(iters), ws.data_ptr(), ws.numel(), _stream_ptr(stream),
                            ctypes.byref(t)))
     k._ws = {}
-    out = {"bb": (t.bb_t, t.bb_z), "parts": (t.fwd_parts, t.adj_parts),
-           "ms_bb": [float(v) for v in t.ms_bb], "ms_fwd": [float(v) for v in t.ms_fwd],
-           "ms_adj": [float(v) for v in t.ms_adj], "cached": False}
+    out = {"bb": (t.bb_t, t.bb_z), "rb": (t.rb_t, t.rb_z), "parts": (t.fwd_parts, t.adj_parts),
+           "ms_bb": [float(v) for v in t.ms_bb], "ms_rb": [float(v) for v in t.ms_rb],
+           "ms_fwd": [float(v) for v in t.ms_fwd], "ms_adj": [float(v) for v in t.ms_adj], "cached": False}
     if cache:
-        table[key] = {"bb": list(out["bb"]), "parts": list(out["parts"]), "ms_bb": out["ms_bb"],
-                      "ms_fwd": out["ms_fwd"], "ms_adj": out["ms_adj"]}
+        table[key] = {"bb": list(out["bb"]), "rb": list(out["rb"]), "parts": list(out["parts"]),
+                      "ms_bb": out["ms_bb"], "ms_rb": out["ms_rb"], "ms_fwd": out["ms_fwd"], "ms_adj": out["ms_adj"]}
         tmp = cache + ".tmp"
         with open(tmp, "w") as f:
             json.dump(table, f, indent=1, sort_keys=True)

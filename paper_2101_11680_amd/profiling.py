@@ -113,8 +113,9 @@ def traffic(kernel: str, copy_mib: int, out: str, fetch_dir: str, write_dir: str
 
 FISTA_STAGES = ("contract_fwd", "col_t_inverse", "row_t_residual", "col_t_forward", "contract_adj",
                 "col_z_inverse", "row_z_prox", "col_z_forward")
+_ADJ = ("contract_adj_kernel<float", "contract_adj_pipe_kernel<float")
 _STAGE_KERNELS = ("contract_fwd_kernel<float", "col_pass_kernel<float", "row_pass_kernel<float",
-                  "col_pass_kernel<float", "contract_adj_kernel<float", "col_pass_kernel<float",
+                  "col_pass_kernel<float", _ADJ, "col_pass_kernel<float",
                   "row_pass_kernel<float", "col_pass_kernel<float")
 
 
