@@ -16,6 +16,11 @@
       that maps the copy's reading to its known size (bytes read = written =
       COPY_MIB MiB), and the result is tied to the source file's digest so
       that a changed kernel is not credited with old counters.
+  python -m paper_2101_11680_amd.profiling mfma PMC_DIR STEPS MS_PER_STEP PEAK_TFLOPS OUT.txt TITLE COMMAND...
+      one --pmc run holding SQ_INSTS_VALU_MFMA_MOPS_<type> and
+      SQ_VALU_MFMA_BUSY_CYCLES over STEPS repetitions of a step that takes
+      MS_PER_STEP unprofiled -> executed MFMA TFLOP/s per step against
+      PEAK_TFLOPS and the matrix cores' busy share, per kernel and in total
 """
 
 from __future__ import annotations
@@ -196,6 +201,47 @@ def iteration_table(trace_dir, fetch_dir, write_dir, cfetch_dir, cwrite_dir, cop
     return text
 
 
+def mfma_table(pmc_dir: str, steps: int, ms_per_step: float, peak_tflops: float, out: str, title: str,
+               command: str, clock_hz: float = 2.4e9, simds: int = 1024) -> str:
+    """Executed MFMA work per step from one counter run: MOPS x 512 flops and
+    the busy cycles of the SIMDs' matrix cores, per kernel name and in total,
+    over an unprofiled step time."""
+    rows = list(csv.DictReader(open(os.path.join(pmc_dir, "run_counter_collection.csv"))))
+    mops = collections.defaultdict(float)
+    busy = collections.defaultdict(float)
+    mops_name = ""
+    for r in rows:
+        name, cname, val = _short(r["Kernel_Name"]), r["Counter_Name"], float(r["Counter_Value"])
+        if cname.startswith("SQ_INSTS_VALU_MFMA_MOPS"):
+            mops[name] += val
+            mops_name = cname
+        elif cname == "SQ_VALU_MFMA_BUSY_CYCLES":
+            busy[name] += val
+    t = ms_per_step * 1e-3
+    lines = [f"# {title}", "", "command (run from /tmp with TMPDIR=/tmp; R = repository root):", f"  {command}", "",
+             f"{mops_name} x 512 = executed MFMA flops; SQ_VALU_MFMA_BUSY_CYCLES over {simds} SIMDs at "
+             f"{clock_hz / 1e9:.1f} GHz; per step = counter sums / {steps} steps, over the unprofiled step time "
+             f"{ms_per_step:.3f} ms; peak {peak_tflops:g} TFLOP/s", "",
+             f"{'kernel':44s} {'GFLOP/step':>11s} {'TFLOP/s':>8s} {'% peak':>7s} {'busy %':>7s}"]
+    names = sorted(set(mops) | set(busy), key=lambda n: -mops.get(n, 0.0))
+    tot_f = tot_b = 0.0
+    for n in names:
+        f = mops.get(n, 0.0) * 512.0 / steps
+        b = busy.get(n, 0.0) / steps
+        if f == 0.0 and b == 0.0:
+            continue
+        tot_f += f
+        tot_b += b
+        lines.append(f"{n[:44]:44s} {f / 1e9:11.2f} {f / t / 1e12:8.1f} {100 * f / t / 1e12 / peak_tflops:6.2f}% "
+                     f"{100 * b / (simds * clock_hz * t):6.2f}%")
+    lines.append(f"{'step total':44s} {tot_f / 1e9:11.2f} {tot_f / t / 1e12:8.1f} "
+                 f"{100 * tot_f / t / 1e12 / peak_tflops:6.2f}% {100 * tot_b / (simds * clock_hz * t):6.2f}%")
+    text = "\n".join(lines) + "\n"
+    with open(out, "w") as fo:
+        fo.write(text)
+    return text
+
+
 def main(argv) -> int:
     if len(argv) >= 5 and argv[0] == "trace":
         print(summarize_trace(argv[1], argv[2], argv[3], " ".join(argv[4:])))
@@ -208,6 +254,10 @@ def main(argv) -> int:
     if len(argv) >= 11 and argv[0] == "iteration":
         print(iteration_table(argv[1], argv[2], argv[3], argv[4], argv[5], int(argv[6]), argv[7], argv[8], argv[9],
                               " ".join(argv[10:])))
+        return 0
+    if len(argv) >= 8 and argv[0] == "mfma":
+        print(mfma_table(argv[1], int(argv[2]), float(argv[3]), float(argv[4]), argv[5], argv[6],
+                         " ".join(argv[7:])))
         return 0
     print(__doc__)
     return 2
