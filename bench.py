@@ -703,6 +703,9 @@ def main() -> int:
                          "scans solved to gradient-mapping ratio 1e-3, plain vs batched vs batched with "
                          "the learned start; warmstart: held-out scans of the learned geometry, zero vs "
                          "learned start (--scans, default 64; 512 for the full evaluation)")
+    ap.add_argument("--config", default="precision", choices=["precision", "mid", "tiny"],
+                    help="precision workload: the scan configuration (precision: 128x128, 64 layers, 512 bins, the "
+                         "metric's; mid: 64x64, 32 layers, 256 bins; tiny: 16x16, 8 layers, 64 bins)")
     ap.add_argument("--scans", type=int, default=64)
     ap.add_argument("--rel-tol", type=float, default=1e-3)
     ap.add_argument("--integration-ms", type=float, default=10.0,
@@ -752,8 +755,8 @@ def main() -> int:
     prec = ctof.PRECISIONS[args.precision]
     dtype = torch.float64 if prec == ctof.FP64 else torch.float32
 
-    w = workloads.workload("precision")
-    g = workloads.geometry_for("precision", seed=args.seed)
+    w = workloads.workload(args.config)
+    g = workloads.geometry_for(args.config, seed=args.seed)
     log(f"geometry n={g.nx} nz={g.nz} nt={g.nt} dt={g.dt_ps}ps mus'={g.mus_prime_per_mm:.4f}")
 
     torch.cuda.synchronize()
@@ -857,8 +860,9 @@ def main() -> int:
         "dtype": {"fp32": "f32", "fp64": "f64", "bf16x3": "bf16x3+f32", "bf16": "bf16+f32"}[args.precision],
         "data": "synthetic",
         "config": {
-            "workload": ("precision config: 128x128 confocal scan at 0.5 mm, 64 layers 1-30 mm, "
-                         "512 bins of 20 ps, one volume, FISTA non-negative Tikhonov"),
+            "workload": (f"{args.config} config: {g.ny}x{g.nx} confocal scan at {g.pitch_mm:g} mm, {g.nz} layers "
+                         f"{float(g.z_mm[0]):g}-{float(g.z_mm[-1]):g} mm, {g.nt} bins of {g.dt_ps:g} ps, one volume, "
+                         "FISTA non-negative Tikhonov"),
             "n": g.nx, "nz": g.nz, "nt": g.nt, "fft_size": i.p, "matrices": i.nmat,
             "precision": args.precision, "mus_prime_per_mm": g.mus_prime_per_mm,
             "operator": "full" if args.band == 0 else (f"spectrum band {args.band:g} ({kept:.3f} of the kernel-spectrum "
@@ -913,6 +917,7 @@ def main() -> int:
                 kept = ctof.set_band(kv, 1e-9)
             if args.tune:
                 ctof.tune(kv, nvol=1, iters=5)
+            kv.workspace(kv.workspace_bytes(max(args.steps, args.warmup))[1], dev)
             ctof.reconstruct(kv, d, max_iter=args.warmup, lam=lam, lipschitz=L)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
