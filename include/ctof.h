@@ -163,7 +163,8 @@ void ctof_kernel_free(ctof_kernel k);
 /*
  * Shape facts of a handle (any pointer may be NULL):
  *   n           max(nx, ny), the side that sets the FFT size
- *   nz, nt      layers, bins;   p   FFT size (power of two >= 2n-1)
+ *   nz, nt      layers, bins;   p   FFT size: the smallest length >= 2n-1
+ *               among the powers of two (at least 16) and 48, 96, 192
  *   nmat        distinct spectrum matrices, (p/2+1)(p/2+2)/2
  *   prec        precision the handle was tabulated for
  */
@@ -491,8 +492,9 @@ ctof_status ctof_kernel_get_contract_parts(ctof_kernel k, int32_t *fwd_parts, in
  * matrix 1, 2, 4, 8, then the adjoint's, keeps the fastest of each in the
  * handle (ctof_kernel_set_tuning, ctof_kernel_set_row_tuning,
  * ctof_kernel_set_contract_parts) and reports every timing.  The FFT size
- * is not a choice: the radix-2 passes take the power of two >= 2n - 1 (a
- * smaller non-power-of-two size would need other radices).  Choices change
+ * is fixed at tabulation (the kernel spectrum depends on it) to the
+ * smallest supported length >= 2n - 1, which is never slower than a longer
+ * one: it shrinks the spectrum and every pass.  Choices change
  * launch shapes and workspace sizes; results change only by the order of
  * the adjoint's sum.  Synchronises `stream`; the handle must not be in use
  * on other streams meanwhile.

@@ -52,6 +52,19 @@ int next_pow2(int v) {
   return p;
 }
 
+// FFT size of an n-point scan side: the smallest length >= 2n - 1 (the
+// circular convolution then equals the linear one on the scan) among the
+// powers of two and 48, 96, 192 (radix-3 first stages), at least kMinP.
+// 3 * 2^k sizes cut the kernel spectrum by up to 44% (n = 96: 4,753 instead
+// of 8,385 matrices) and every FFT pass by up to a quarter.
+int fft_size(int n) {
+  const int need = 2 * n - 1;
+  int p = std::max(ctof::kMinP, next_pow2(need));
+  for (int q : {48, 96, 192})
+    if (q >= need && q < p) p = q;
+  return p;
+}
+
 bool finite(double v) { return std::isfinite(v); }
 
 // Legendre-Gauss nodes and weights on [-1, 1] by Newton's method on P_16.
@@ -1554,7 +1567,7 @@ Dims make_dims(int nx, int ny, int nz, int nt, ctof_precision prec) {
   d.nx = nx;
   d.nz = nz;
   d.nt = nt;
-  d.p = std::max(kMinP, next_pow2(2 * n - 1));
+  d.p = fft_size(n);
   d.h = d.p / 2;
   d.nmat = (d.h + 1) * (d.h + 2) / 2;
   const bool bf = prec == CTOF_BF16X3 || prec == CTOF_BF16;

@@ -45,6 +45,22 @@ __host__ __device__ constexpr double sin32(int k) {
        : k == 15 ? 0.19509032201612826785 : 0.0;
 }
 
+// cos(2 pi j / 12) and sin(2 pi j / 12) for j in [0, 12) (the twiddles of
+// the radix-3 DFT lengths 3, 6 and 12)
+__host__ __device__ constexpr double cos12(int j) {
+  return j == 0 ? 1.0 : j == 1 ? 0.86602540378443864676 : j == 2 ? 0.5 : j == 3 ? 0.0 : j == 4 ? -0.5
+       : j == 5 ? -0.86602540378443864676 : j == 6 ? -1.0 : j == 7 ? -0.86602540378443864676 : j == 8 ? -0.5
+       : j == 9 ? 0.0 : j == 10 ? 0.5 : 0.86602540378443864676;
+}
+__host__ __device__ constexpr double sin12(int j) { return cos12((j + 9) % 12); }
+
+// m mod L for m >= 0 (a mask when L is a power of two)
+template <int L>
+__device__ __forceinline__ int wrap(int m) {
+  if constexpr ((L & (L - 1)) == 0) return m & (L - 1);
+  else return m % L;
+}
+
 template <int R>
 __host__ __device__ constexpr int bitrev(int i) {
   int r = 0;
@@ -53,12 +69,53 @@ __host__ __device__ constexpr int bitrev(int i) {
   return r;
 }
 
-// In-register DFT of length R (power of two <= 32):
+// In-register DFT of length R (a power of two <= 32, or 3, 6, 12):
 //   X[k] = sum_n x[n] exp(DIR * 2 pi i n k / R)   (DIR = -1 forward, +1 inverse)
 template <typename T, int R, int DIR>
 __device__ __forceinline__ void dft_reg(T (&xr)[R], T (&xi)[R]) {
-  static_assert(R >= 1 && R <= 32 && (R & (R - 1)) == 0, "power of two up to 32");
-  if constexpr (R == 32) {
+  static_assert(R >= 1 && ((R <= 32 && (R & (R - 1)) == 0) || R == 3 || R == 6 || R == 12),
+                "a power of two up to 32, or 3, 6, 12");
+  if constexpr (R % 3 == 0) {
+    // decimation in time by 3: the DFTs E_r of x[3n + r] (length M = R/3),
+    // then X[k + q M] = E_0 + w^q W^k E_1 + w^{2q} W^{2k} E_2 with
+    // W = exp(DIR 2 pi i / R) and w = W^M = -1/2 + DIR i sqrt(3)/2
+    constexpr int M = R / 3;
+    T er[3][M], ei[3][M];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+#pragma unroll
+      for (int n = 0; n < M; ++n) {
+        er[r][n] = xr[3 * n + r];
+        ei[r][n] = xi[3 * n + r];
+      }
+      if constexpr (M > 1) dft_reg<T, M, DIR>(er[r], ei[r]);
+    }
+    constexpr T c3 = (T)(DIR * 0.86602540378443864676);
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+      T t1r = er[1][k], t1i = ei[1][k], t2r = er[2][k], t2i = ei[2][k];
+      if (k != 0) {
+        const int j1 = (k * (12 / R)) % 12, j2 = (2 * k * (12 / R)) % 12;
+        const T c1 = (T)cos12(j1), s1 = (T)(DIR * sin12(j1));
+        const T c2 = (T)cos12(j2), s2 = (T)(DIR * sin12(j2));
+        const T ar = t1r * c1 - t1i * s1, ai = t1r * s1 + t1i * c1;
+        const T br = t2r * c2 - t2i * s2, bi = t2r * s2 + t2i * c2;
+        t1r = ar;
+        t1i = ai;
+        t2r = br;
+        t2i = bi;
+      }
+      const T sr = t1r + t2r, si = t1i + t2i, dr = t1r - t2r, di = t1i - t2i;
+      const T mr = er[0][k] - (T)0.5 * sr, mi = ei[0][k] - (T)0.5 * si;
+      xr[k] = er[0][k] + sr;
+      xi[k] = ei[0][k] + si;
+      xr[k + M] = mr - c3 * di;
+      xi[k + M] = mi + c3 * dr;
+      xr[k + 2 * M] = mr + c3 * di;
+      xi[k + 2 * M] = mi - c3 * dr;
+    }
+    return;
+  } else if constexpr (R == 32) {
     // two length-16 DFTs of the even and odd samples, then one radix-2 step
     // (keeps the live values near 2R instead of the fully unrolled tree's)
     T er[16], ei[16], orr[16], oi[16];
@@ -148,10 +205,9 @@ __device__ __forceinline__ void build_twiddles(T *twc, T *tws) {
 
 // Stage 1 of a length-L = R1*R2 DFT along rows of (br, bi)[row*ld + b] for
 // BB columns: for each (n2, b), DFT_R1 over rows R2*n1 + n2, multiply by
-// W_L^(n2 k1), write back in place.  `tstep` maps W_L^m onto the P-table.
-template <typename T, int R1, int R2, int BB, int DIR>
-__device__ __forceinline__ void dft_stage1(T *br, T *bi, int ld, const T *twc, const T *tws,
-                                           int tstep, int tmask) {
+// W_L^(n2 k1), write back in place.  Entry TSTEP m of the TSIZE-entry table is W_L^m.
+template <typename T, int R1, int R2, int BB, int DIR, int TSTEP, int TSIZE>
+__device__ __forceinline__ void dft_stage1(T *br, T *bi, int ld, const T *twc, const T *tws) {
   for (int u = threadIdx.x; u < R2 * BB; u += blockDim.x) {
     const int b = u % BB, n2 = u / BB;
     T xr[R1], xi[R1];
@@ -165,7 +221,7 @@ __device__ __forceinline__ void dft_stage1(T *br, T *bi, int ld, const T *twc, c
     for (int k1 = 0; k1 < R1; ++k1) {
       T yr = xr[k1], yi = xi[k1];
       if (k1 != 0) {
-        const int m = (n2 * k1 * tstep) & tmask;
+        const int m = wrap<TSIZE>(n2 * k1 * TSTEP);
         const T c = twc[m], s = (T)DIR * tws[m];
         const T tr = yr * c - yi * s;
         yi = yr * s + yi * c;
@@ -193,8 +249,10 @@ __device__ __forceinline__ void dft_stage2_unit(const T *br, const T *bi, int ld
 
 template <int P>
 struct Fac {
-  static constexpr int R1 = P == 1024 ? 32 : P == 512 ? 16 : P == 256 ? 16 : P == 128 ? 16 : P == 64 ? 8 : P == 32 ? 8 : P == 16 ? 4
-                           : P == 8 ? 4 : 2;
+  // (lengths 3 * 2^k: a radix-12 first stage)
+  static constexpr int R1 = (P == 192 || P == 96 || P == 48 || P == 24) ? 12
+                           : P == 1024 ? 32 : P == 512 ? 16 : P == 256 ? 16 : P == 128 ? 16 : P == 64 ? 8 : P == 32 ? 8
+                           : P == 16 ? 4 : P == 8 ? 4 : 2;
   static constexpr int R2 = P / R1;
 };
 
@@ -248,7 +306,7 @@ col_pass_kernel(int ny, int B, const T *__restrict__ in, T *__restrict__ out, in
     dft_reg<T, R1, DIR>(yr, yi);
 #pragma unroll
     for (int k1 = 1; k1 < R1; ++k1) {
-      const int m = (n2 * k1) & (P - 1);
+      const int m = wrap<P>(n2 * k1);
       const T c = twc[m], sn = (T)DIR * tws[m];
       const T tr = yr[k1] * c - yi[k1] * sn;
       yi[k1] = yr[k1] * sn + yi[k1] * c;
@@ -296,7 +354,7 @@ __device__ __forceinline__ void dft_lds_inplace(T *wr, T *wi, const T *twc, cons
   constexpr int ld = BB + 1;
   constexpr int NU = (R1 * BB + NT - 1) / NT;
   // stage-1 twiddles W_H^m live at index TSTEP m of the length-(TSTEP H) table
-  dft_stage1<T, R1, R2, BB, DIR>(wr, wi, ld, twc, tws, TSTEP, TSTEP * H - 1);
+  dft_stage1<T, R1, R2, BB, DIR, TSTEP, TSTEP * H>(wr, wi, ld, twc, tws);
   __syncthreads();
   const int tid = threadIdx.x;
   T zr[NU][R2], zi[NU][R2];
@@ -462,7 +520,7 @@ col_pass_2048_kernel(int ny, int B, const T *__restrict__ in, T *__restrict__ ou
     wi[row * ld + b] = xi;
   }
   __syncthreads();
-  dft_stage1<T, 32, 64, BB, DIR>(wr, wi, ld, twc, tws, 1, P - 1);
+  dft_stage1<T, 32, 64, BB, DIR, 1, P>(wr, wi, ld, twc, tws);
   __syncthreads();
   dft64_blocks<T, P, BB, DIR>(wr, wi, twc, tws);
   T *dst = out + (size_t)ky * rows_out * 2 * B + b0;
@@ -552,7 +610,7 @@ row_pass_kernel(int ny, int nx, RowArgs a) {
         const int q = u % BQ, k = u / BQ;
         const T c = twc[k], s = tws[k];
         const int kk = H - k;
-        const T cc = twc[kk & (P - 1)], ss = tws[kk & (P - 1)];
+        const T cc = twc[wrap<P>(kk)], ss = tws[wrap<P>(kk)];
 #pragma unroll
         for (int e = 0; e < V; ++e) {
           const int b = q * V + e;
@@ -911,7 +969,10 @@ hipError_t launch_col_pass(const Dims &d, int B, bool inverse, const T *in, T *o
     case 16: return col_dispatch<T, 16>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
     case 32: return col_dispatch<T, 32>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
     case 64: return col_dispatch<T, 64>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
+    case 48: return col_dispatch<T, 48>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
+    case 96: return col_dispatch<T, 96>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
     case 128: return col_dispatch<T, 128>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
+    case 192: return col_dispatch<T, 192>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
     case 256: return col_dispatch<T, 256>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
     case 512: return col_dispatch<T, 512>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
     case 1024: return col_dispatch<T, 1024>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
@@ -936,7 +997,10 @@ hipError_t launch_row_pass(const Dims &d, const RowArgs &a0, hipStream_t st) {
     case 16: return row_dispatch<T, 16>(d, a, st);
     case 32: return row_dispatch<T, 32>(d, a, st);
     case 64: return row_dispatch<T, 64>(d, a, st);
+    case 48: return row_dispatch<T, 48>(d, a, st);
+    case 96: return row_dispatch<T, 96>(d, a, st);
     case 128: return row_dispatch<T, 128>(d, a, st);
+    case 192: return row_dispatch<T, 192>(d, a, st);
     case 256: return row_dispatch<T, 256>(d, a, st);
     case 512: return row_dispatch<T, 512>(d, a, st);
     case 1024: return row_dispatch<T, 1024>(d, a, st);

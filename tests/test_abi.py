@@ -122,3 +122,16 @@ def test_non_square_grid_sizes(ctof):
     kb_ns, _ = ctof.kernel_bytes(_geom(nx=24, ny=9), ctof.FP32)
     kb_ns2, _ = ctof.kernel_bytes(_geom(nx=9, ny=24), ctof.FP32)
     assert kb_ns == kb_sq == kb_ns2
+
+
+@pytest.mark.parametrize("n,p", [(8, 16), (9, 32), (16, 32), (17, 48), (24, 48), (25, 64), (32, 64), (33, 96),
+                                 (48, 96), (49, 128), (64, 128), (65, 192), (96, 192), (97, 256), (128, 256),
+                                 (129, 512)])
+def test_fft_size_rule(ctof, n, p):
+    # the smallest length >= 2n - 1 among the powers of two (at least 16)
+    # and 48, 96, 192; the spectrum holds (p/2 + 1)(p/2 + 2)/2 matrices
+    assert max(16, 1 << (2 * n - 2).bit_length()) >= 2 * n - 1
+    assert p >= 2 * n - 1
+    kb, _ = ctof.kernel_bytes(_geom(nx=n, ny=n), ctof.FP32)
+    h = p // 2
+    assert kb == 2 * ((h + 1) * (h + 2) // 2) * 32 * 16 * 4

@@ -64,7 +64,10 @@ def test_fallback_batched_mixed():
     starts = [refs[0].clone(), (mus[1] * 100.0).contiguous(), torch.zeros_like(refs[2])]
     out, rw = ctof.reconstruct_batched([k] * 3, ds, mus=starts, max_iter=3000, lam=lam, lipschitz=L, rel_tol=1e-4,
                                        check_every=10, warm_start=2)
-    assert [r.fell_back for r in rw] == [0, 1, 0]
+    # a converged start is kept, one 100x too large is discarded; a zero
+    # start's first ratio is 1 up to the rounding of its two FP64 norms (R31:
+    # ratio > 1 falls back), so either outcome is a zero-start solve
+    assert rw[0].fell_back == 0 and rw[1].fell_back == 1 and rw[2].fell_back in (0, 1)
     for r in rw:
         assert r.gmap_ratio <= 1e-4
     assert rw[0].iters < rz[0].iters // 4
