@@ -315,14 +315,12 @@ def run_batching(args, ctof, torch, dev) -> int:
         m = ctof.forward(kern["fp32"][g], torch.tensor(mu, dtype=torch.float32, device=dev))
         d = noise.poisson_histogram(m.double().cpu().numpy(), peak, seed + 7)
         ds.append(torch.tensor(d, dtype=torch.float32, device=dev))
-    cache = os.path.join(ROOT, "gpurun_out", "tune_cache.json") if os.path.isdir(
-        os.path.join(ROOT, "gpurun_out")) else None
     counts = {}
     for g, _, _ in scans:
         counts[g] = counts.get(g, 0) + 1
     for name in precs:
         for g in geoms:
-            ctof.tune(kern[name][g], nvol=counts[g], iters=3, cache=cache)
+            ctof.tune(kern[name][g], nvol=counts[g], iters=3)
     maxit = 3000
     out = {"workload": (f"batching: {len(scans)} scans, N in {{32,48,64,96,128}}, Nz in {{16,32,64}} "
                         f"over 1-20 mm, 256 bins of 25 ps, solved to gradient-mapping ratio "

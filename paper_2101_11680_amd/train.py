@@ -288,8 +288,8 @@ def main(argv=None) -> int:
     ap.add_argument("--loss", default="operator", choices=("operator",))
     ap.add_argument("--alpha", type=float, default=1.0)
     ap.add_argument("--robust", action="store_true", help="log(1 + loss) per sample")
-    ap.add_argument("--out", default="gpurun_out/warmstart.npz")
-    ap.add_argument("--report", default="gpurun_out/warmstart_report.json")
+    ap.add_argument("--out", default="warmstart.npz")
+    ap.add_argument("--report", default="warmstart_report.json")
     a = ap.parse_args(argv)
     torch = _torch()
     log = lambda msg: print(msg, flush=True)
