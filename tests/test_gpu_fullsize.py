@@ -8,8 +8,8 @@ threads, see gpu_common.BinRunOperator) and from ctof_reconstruct in each
 precision.  Bars (relative): iterate L2 1e-5 (FP32), 2e-3 (BF16 hi+lo,
 BF16 hi-only spectrum); data fit after the iterations 1e-4 (FP32), 1e-2
 (BF16 forms); every iteration's data fit as well.  The results are printed
-and written to gpurun_out/precision_report_fullsize.json when that folder
-exists.
+and written to $CTOF_REPORT_DIR/precision_report_fullsize.json when that
+variable names a folder.
 """
 
 import json
@@ -70,8 +70,8 @@ def test_full_size_reconstruct_against_oracle():
         print(prec, json.dumps(r), flush=True)
         del k
         torch.cuda.empty_cache()
-    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
-    if os.path.isdir(out):
+    out = os.environ.get("CTOF_REPORT_DIR", "")
+    if out and os.path.isdir(out):
         with open(os.path.join(out, "precision_report_fullsize.json"), "w") as f:
             json.dump(report, f, indent=1)
     for prec in ("fp32", "bf16x3", "bf16"):

@@ -6,7 +6,7 @@ and lambda at a 32x32 scan, 16 layers, 128 bins, where the oracle's FP64
 FISTA runs in seconds.  Bars: forward/adjoint relative L2 1e-5 (FP32),
 2e-3 (BF16X3, BF16 hi-only spectrum); reconstruction data fit 1e-4 (FP32),
 1e-2 (BF16 forms).  Each result is printed and written to
-gpurun_out/precision_report.json when that folder exists.
+$CTOF_REPORT_DIR/precision_report.json when that variable names a folder.
 """
 
 import json
@@ -83,8 +83,8 @@ def test_precision_report():
         report[prec]["recon_datafit_rel"] = abs(rep.datafit / fit_ref - 1)
         report[prec]["recon_iterate_rel_l2"] = rel_l2(to_np(mu_g), mu_ref)
     print(json.dumps(report, indent=1))
-    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
-    if os.path.isdir(out):
+    out = os.environ.get("CTOF_REPORT_DIR", "")
+    if out and os.path.isdir(out):
         with open(os.path.join(out, "precision_report.json"), "w") as f:
             json.dump(report, f, indent=1)
     for prec, rr in report.items():
