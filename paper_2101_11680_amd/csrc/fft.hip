@@ -250,7 +250,7 @@ __device__ __forceinline__ void dft_stage2_unit(const T *br, const T *bi, int ld
 template <int P>
 struct Fac {
   // (lengths 3 * 2^k: a radix-12 first stage)
-  static constexpr int R1 = (P == 192 || P == 96 || P == 48 || P == 24) ? 12
+  static constexpr int R1 = (P == 384 || P == 192 || P == 96 || P == 48 || P == 24) ? 12
                            : P == 1024 ? 32 : P == 512 ? 16 : P == 256 ? 16 : P == 128 ? 16 : P == 64 ? 8 : P == 32 ? 8
                            : P == 16 ? 4 : P == 8 ? 4 : 2;
   static constexpr int R2 = P / R1;
@@ -973,6 +973,7 @@ hipError_t launch_col_pass(const Dims &d, int B, bool inverse, const T *in, T *o
     case 96: return col_dispatch<T, 96>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
     case 128: return col_dispatch<T, 128>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
     case 192: return col_dispatch<T, 192>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
+    case 384: return col_dispatch<T, 384>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
     case 256: return col_dispatch<T, 256>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
     case 512: return col_dispatch<T, 512>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
     case 1024: return col_dispatch<T, 1024>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
@@ -1001,6 +1002,7 @@ hipError_t launch_row_pass(const Dims &d, const RowArgs &a0, hipStream_t st) {
     case 96: return row_dispatch<T, 96>(d, a, st);
     case 128: return row_dispatch<T, 128>(d, a, st);
     case 192: return row_dispatch<T, 192>(d, a, st);
+    case 384: return row_dispatch<T, 384>(d, a, st);
     case 256: return row_dispatch<T, 256>(d, a, st);
     case 512: return row_dispatch<T, 512>(d, a, st);
     case 1024: return row_dispatch<T, 1024>(d, a, st);

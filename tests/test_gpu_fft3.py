@@ -1,5 +1,6 @@
-"""FFT sizes 48, 96 and 192 (a radix-12 first stage built from a radix-3
-step over power-of-two DFTs): scan sides 17-24, 33-48 and 65-96 take the
+"""FFT sizes 48, 96, 192 and 384 (a radix-12 first stage built from a
+radix-3 step over power-of-two DFTs; at 384 the column block is held in
+LDS whole): scan sides 17-24, 33-48, 65-96 and 129-192 take the
 smallest length >= 2n - 1 among the powers of two and these.  Any such
 length gives the same cropped linear convolution (Eq. 11), so the FP64
 oracle (which picks its own transform length) is the reference: forward
@@ -27,7 +28,8 @@ def _geom(ny, nx, nz=5, nt=40):
 
 @pytest.mark.parametrize("ny,nx,p", [(17, 17, 48), (24, 24, 48), (20, 9, 48), (33, 33, 96), (48, 48, 96),
                                     (40, 23, 96), (65, 65, 192), (96, 96, 192), (70, 96, 192),
-                                    (16, 16, 32), (25, 25, 64), (49, 49, 128), (97, 97, 256)])
+                                    (129, 129, 384), (192, 150, 384), (16, 16, 32), (25, 25, 64), (49, 49, 128),
+                                    (97, 97, 256), (193, 193, 512)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_forward_adjoint_match_oracle(ny, nx, p, prec):
     from paper_2101_11680_amd import ctof as c
@@ -47,7 +49,7 @@ def test_forward_adjoint_match_oracle(ny, nx, p, prec):
     assert em <= tol and ea <= tol
 
 
-@pytest.mark.parametrize("ny,nx", [(24, 24), (48, 40), (96, 96)])
+@pytest.mark.parametrize("ny,nx", [(24, 24), (48, 40), (96, 96), (150, 130)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_fista_matches_oracle(ny, nx, prec):
     from paper_2101_11680_amd import ctof as c
