@@ -164,7 +164,7 @@ void ctof_kernel_free(ctof_kernel k);
  * Shape facts of a handle (any pointer may be NULL):
  *   n           max(nx, ny), the side that sets the FFT size
  *   nz, nt      layers, bins;   p   FFT size: the smallest length >= 2n-1
- *               among the powers of two (at least 16) and 48, 96, 192, 384
+ *               among the powers of two (at least 16) and 48, 96, 192, 384, 768
  *   nmat        distinct spectrum matrices, (p/2+1)(p/2+2)/2
  *   prec        precision the handle was tabulated for
  */

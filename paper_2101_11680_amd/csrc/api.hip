@@ -54,13 +54,13 @@ int next_pow2(int v) {
 
 // FFT size of an n-point scan side: the smallest length >= 2n - 1 (the
 // circular convolution then equals the linear one on the scan) among the
-// powers of two and 48, 96, 192, 384 (radix-3 first stages), at least
+// powers of two and 48, 96, 192, 384, 768 (radix-3 first stages), at least
 // kMinP.  3 * 2^k sizes cut the kernel spectrum by up to 44% (n = 96: 4,753
 // instead of 8,385 matrices) and every FFT pass by up to a quarter.
 int fft_size(int n) {
   const int need = 2 * n - 1;
   int p = std::max(ctof::kMinP, next_pow2(need));
-  for (int q : {48, 96, 192, 384})
+  for (int q : {48, 96, 192, 384, 768})
     if (q >= need && q < p) p = q;
   return p;
 }

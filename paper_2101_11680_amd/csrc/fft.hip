@@ -45,14 +45,16 @@ __host__ __device__ constexpr double sin32(int k) {
        : k == 15 ? 0.19509032201612826785 : 0.0;
 }
 
-// cos(2 pi j / 12) and sin(2 pi j / 12) for j in [0, 12) (the twiddles of
-// the radix-3 DFT lengths 3, 6 and 12)
-__host__ __device__ constexpr double cos12(int j) {
-  return j == 0 ? 1.0 : j == 1 ? 0.86602540378443864676 : j == 2 ? 0.5 : j == 3 ? 0.0 : j == 4 ? -0.5
-       : j == 5 ? -0.86602540378443864676 : j == 6 ? -1.0 : j == 7 ? -0.86602540378443864676 : j == 8 ? -0.5
-       : j == 9 ? 0.0 : j == 10 ? 0.5 : 0.86602540378443864676;
+// cos(2 pi j / 24) and sin(2 pi j / 24) for j in [0, 24) (the twiddles of
+// the radix-3 DFT lengths 3, 6, 12 and 24)
+__host__ __device__ constexpr double cos24_half(int j) {  // j in [0, 12]
+  return j == 0 ? 1.0 : j == 1 ? 0.96592582628906828675 : j == 2 ? 0.86602540378443864676
+       : j == 3 ? 0.70710678118654752440 : j == 4 ? 0.5 : j == 5 ? 0.25881904510252076235 : j == 6 ? 0.0
+       : j == 7 ? -0.25881904510252076235 : j == 8 ? -0.5 : j == 9 ? -0.70710678118654752440
+       : j == 10 ? -0.86602540378443864676 : j == 11 ? -0.96592582628906828675 : -1.0;
 }
-__host__ __device__ constexpr double sin12(int j) { return cos12((j + 9) % 12); }
+__host__ __device__ constexpr double cos24(int j) { return j <= 12 ? cos24_half(j) : cos24_half(24 - j); }
+__host__ __device__ constexpr double sin24(int j) { return cos24((j + 18) % 24); }
 
 // m mod L for m >= 0 (a mask when L is a power of two)
 template <int L>
@@ -69,12 +71,12 @@ __host__ __device__ constexpr int bitrev(int i) {
   return r;
 }
 
-// In-register DFT of length R (a power of two <= 32, or 3, 6, 12):
+// In-register DFT of length R (a power of two <= 32, or 3, 6, 12, 24):
 //   X[k] = sum_n x[n] exp(DIR * 2 pi i n k / R)   (DIR = -1 forward, +1 inverse)
 template <typename T, int R, int DIR>
 __device__ __forceinline__ void dft_reg(T (&xr)[R], T (&xi)[R]) {
-  static_assert(R >= 1 && ((R <= 32 && (R & (R - 1)) == 0) || R == 3 || R == 6 || R == 12),
-                "a power of two up to 32, or 3, 6, 12");
+  static_assert(R >= 1 && ((R <= 32 && (R & (R - 1)) == 0) || R == 3 || R == 6 || R == 12 || R == 24),
+                "a power of two up to 32, or 3, 6, 12, 24");
   if constexpr (R % 3 == 0) {
     // decimation in time by 3: the DFTs E_r of x[3n + r] (length M = R/3),
     // then X[k + q M] = E_0 + w^q W^k E_1 + w^{2q} W^{2k} E_2 with
@@ -95,9 +97,9 @@ __device__ __forceinline__ void dft_reg(T (&xr)[R], T (&xi)[R]) {
     for (int k = 0; k < M; ++k) {
       T t1r = er[1][k], t1i = ei[1][k], t2r = er[2][k], t2i = ei[2][k];
       if (k != 0) {
-        const int j1 = (k * (12 / R)) % 12, j2 = (2 * k * (12 / R)) % 12;
-        const T c1 = (T)cos12(j1), s1 = (T)(DIR * sin12(j1));
-        const T c2 = (T)cos12(j2), s2 = (T)(DIR * sin12(j2));
+        const int j1 = (k * (24 / R)) % 24, j2 = (2 * k * (24 / R)) % 24;
+        const T c1 = (T)cos24(j1), s1 = (T)(DIR * sin24(j1));
+        const T c2 = (T)cos24(j2), s2 = (T)(DIR * sin24(j2));
         const T ar = t1r * c1 - t1i * s1, ai = t1r * s1 + t1i * c1;
         const T br = t2r * c2 - t2i * s2, bi = t2r * s2 + t2i * c2;
         t1r = ar;
@@ -249,8 +251,8 @@ __device__ __forceinline__ void dft_stage2_unit(const T *br, const T *bi, int ld
 
 template <int P>
 struct Fac {
-  // (lengths 3 * 2^k: a radix-12 first stage)
-  static constexpr int R1 = (P == 384 || P == 192 || P == 96 || P == 48 || P == 24) ? 12
+  // (lengths 3 * 2^k: a radix-12 or, at 768, radix-24 first stage)
+  static constexpr int R1 = P == 768 ? 24 : (P == 384 || P == 192 || P == 96 || P == 48 || P == 24) ? 12
                            : P == 1024 ? 32 : P == 512 ? 16 : P == 256 ? 16 : P == 128 ? 16 : P == 64 ? 8 : P == 32 ? 8
                            : P == 16 ? 4 : P == 8 ? 4 : 2;
   static constexpr int R2 = P / R1;
@@ -974,6 +976,7 @@ hipError_t launch_col_pass(const Dims &d, int B, bool inverse, const T *in, T *o
     case 128: return col_dispatch<T, 128>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
     case 192: return col_dispatch<T, 192>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
     case 384: return col_dispatch<T, 384>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
+    case 768: return col_dispatch<T, 768>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
     case 256: return col_dispatch<T, 256>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
     case 512: return col_dispatch<T, 512>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
     case 1024: return col_dispatch<T, 1024>(d, B, inverse, in, out, st, ppv, bb, active, nsum, sstride);
@@ -1003,6 +1006,7 @@ hipError_t launch_row_pass(const Dims &d, const RowArgs &a0, hipStream_t st) {
     case 128: return row_dispatch<T, 128>(d, a, st);
     case 192: return row_dispatch<T, 192>(d, a, st);
     case 384: return row_dispatch<T, 384>(d, a, st);
+    case 768: return row_dispatch<T, 768>(d, a, st);
     case 256: return row_dispatch<T, 256>(d, a, st);
     case 512: return row_dispatch<T, 512>(d, a, st);
     case 1024: return row_dispatch<T, 1024>(d, a, st);

@@ -126,10 +126,11 @@ def test_non_square_grid_sizes(ctof):
 
 @pytest.mark.parametrize("n,p", [(8, 16), (9, 32), (16, 32), (17, 48), (24, 48), (25, 64), (32, 64), (33, 96),
                                  (48, 96), (49, 128), (64, 128), (65, 192), (96, 192), (97, 256), (128, 256),
-                                 (129, 384), (192, 384), (193, 512), (256, 512), (257, 1024)])
+                                 (129, 384), (192, 384), (193, 512), (256, 512), (257, 768),
+                                 (384, 768), (385, 1024), (512, 1024), (513, 2048)])
 def test_fft_size_rule(ctof, n, p):
     # the smallest length >= 2n - 1 among the powers of two (at least 16)
-    # and 48, 96, 192, 384; the spectrum holds (p/2 + 1)(p/2 + 2)/2 matrices
+    # and 48, 96, 192, 384, 768; the spectrum holds (p/2 + 1)(p/2 + 2)/2 matrices
     assert max(16, 1 << (2 * n - 2).bit_length()) >= 2 * n - 1
     assert p >= 2 * n - 1
     kb, _ = ctof.kernel_bytes(_geom(nx=n, ny=n), ctof.FP32)

@@ -1,7 +1,8 @@
-"""FFT sizes 48, 96, 192 and 384 (a radix-12 first stage built from a
-radix-3 step over power-of-two DFTs; at 384 the column block is held in
-LDS whole): scan sides 17-24, 33-48, 65-96 and 129-192 take the
-smallest length >= 2n - 1 among the powers of two and these.  Any such
+"""FFT sizes 48, 96, 192, 384 and 768 (a radix-12 or radix-24 first stage
+built from a radix-3 step over power-of-two DFTs; from 384 on the column
+block is held in LDS whole): scan sides 17-24, 33-48, 65-96, 129-192 and
+257-384 take the smallest length >= 2n - 1 among the powers of two and
+these.  Any such
 length gives the same cropped linear convolution (Eq. 11), so the FP64
 oracle (which picks its own transform length) is the reference: forward
 and adjoint in FP64, FP32 and BF16 hi+lo, FISTA in FP64 and FP32, square
@@ -29,7 +30,8 @@ def _geom(ny, nx, nz=5, nt=40):
 @pytest.mark.parametrize("ny,nx,p", [(17, 17, 48), (24, 24, 48), (20, 9, 48), (33, 33, 96), (48, 48, 96),
                                     (40, 23, 96), (65, 65, 192), (96, 96, 192), (70, 96, 192),
                                     (129, 129, 384), (192, 150, 384), (16, 16, 32), (25, 25, 64), (49, 49, 128),
-                                    (97, 97, 256), (193, 193, 512)])
+                                    (97, 97, 256), (193, 193, 512), (257, 257, 768), (384, 300, 768),
+                                    (385, 385, 1024)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
 def test_forward_adjoint_match_oracle(ny, nx, p, prec):
     from paper_2101_11680_amd import ctof as c
@@ -79,3 +81,19 @@ def test_fista_matches_oracle(ny, nx, prec):
                                    max_iter=25, lam=lam, lipschitz=L)
     assert rel_l2(to_np(mus[0]), ref) <= (1e-10 if prec == "fp64" else 1e-5)
     assert rel_l2(to_np(mus[1]), ref2) <= (1e-10 if prec == "fp64" else 1e-5)
+
+
+def test_fista_fp64_at_768():
+    # a short FP64 solve at side 300 (P = 768: radix-24 first stages)
+    from paper_2101_11680_amd import ctof as c
+    g = _geom(300, 300, nz=2, nt=8)
+    F = oop.FFTOperator(okernel.tabulate(g))
+    rng = np.random.default_rng(3)
+    d = F.forward(rng.uniform(0.0, 0.05, (g.nz, 300, 300)))
+    LA = osolver.power_iteration(F, 20)
+    L, lam = osolver.step_constants(LA)
+    ref, _ = osolver.fista(F, d, L, lam, 8)
+    k = c.tabulate(g, c.FP64)
+    assert k.info.p == 768
+    got, _, _ = c.reconstruct(k, torch.tensor(d, device="cuda"), max_iter=8, lam=lam, lipschitz=L)
+    assert rel_l2(to_np(got), ref) <= 1e-10

@@ -3,7 +3,7 @@ stages with the column DFT held in LDS, three stages at 2048) against the
 FP64 oracle: forward and adjoint in FP64, FP32 and BF16 hi+lo, short FISTA
 runs in FP64, FP64 kernel values before the transform, and batched solves.
 Sides 193 (the smallest with P = 512),
-200, 256, 300 (P = 1024), 512, 600 (P = 2048), 1024 (the largest
+200, 256, 400 (P = 1024), 512, 600 (P = 2048), 1024 (the largest
 supported) and the rectangles 512 x 96 and 40 x 1024 are covered; 1025 is
 refused.
 """
@@ -102,7 +102,7 @@ def test_batched_equals_single_at_200():
         assert rel_l2(to_np(mub), to_np(mu1)) <= 1e-6
 
 
-@pytest.mark.parametrize("ny,nx,p", [(300, 300, 1024), (512, 512, 1024), (512, 96, 1024), (600, 600, 2048),
+@pytest.mark.parametrize("ny,nx,p", [(400, 400, 1024), (512, 512, 1024), (512, 96, 1024), (600, 600, 2048),
                                     (1024, 1024, 2048), (40, 1024, 2048)])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_fft_sizes_1024_2048_match_oracle(ny, nx, p, prec):
@@ -121,7 +121,7 @@ def test_fft_sizes_1024_2048_match_oracle(ny, nx, p, prec):
     em, ea = rel_l2(m, F.forward(mu)), rel_l2(a, F.adjoint(r))
     print(f"{ny}x{nx} {prec}: forward {em:.2e} adjoint {ea:.2e}")
     assert em <= tol and ea <= tol
-    if prec == "fp64" and nx == ny and nx in (300, 600):
+    if prec == "fp64" and nx == ny and nx in (400, 600):
         d = F.forward(mu)
         LA = osolver.power_iteration(F, 20)
         L, lam = osolver.step_constants(LA)
