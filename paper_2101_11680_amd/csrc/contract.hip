@@ -681,6 +681,110 @@ hipError_t launch_plain(const ctof_kernel_s *k, bool adjoint, const CArgs &a, hi
   return hipGetLastError();
 }
 
+// BF16 split adjoint without a band, software-pipelined as
+// contract_adj_pipe_kernel: every load of a wave's next 32-bin chunk (its
+// residual values and the chunk's hi / lo fragments) is issued before the
+// current chunk's products, unconditionally (columns without a frequency
+// read a valid address and multiply zeros).  The products are taken in the
+// order of contract_adj_bf16_kernel, so the results are bitwise the same.
+template <int KIND, int ZT, bool NT>
+__global__ void __launch_bounds__(256)
+contract_adj_bf16_pipe_kernel(CArgs a) {
+  extern __shared__ unsigned char smem_raw[];
+  float *red = reinterpret_cast<float *>(smem_raw);
+  int s, pair, part;
+  if (!map_block(a, s, pair, part) || pair_idle(a, pair)) return;
+  const int w = threadIdx.x >> 6;
+  const int l = threadIdx.x & 63;
+  const int c = l & 15, g = l >> 4;
+  const Col k = column_of(a, s, pair, c);
+  const int nzp = a.nzp, ntp = a.ntp;
+  const float *vcol = k.on ? reinterpret_cast<const float *>(a.vin) + ((size_t)k.f * 2 + k.reim) * a.nvol * ntp +
+                                 (size_t)k.vol * ntp + 8 * g
+                           : reinterpret_cast<const float *>(a.vin);
+  const int vstep = k.on ? 32 : 0;
+  const __bf16 *khi = reinterpret_cast<const __bf16 *>(a.khat);
+  const __bf16 *klo = reinterpret_cast<const __bf16 *>(a.khat_lo);
+  constexpr int NF = KIND == 2 ? 2 : 1;  // fragments per z tile: hi (and lo)
+  v4f acc[ZT];
+#pragma unroll
+  for (int zt = 0; zt < ZT; ++zt) acc[zt] = {0, 0, 0, 0};
+  const int nch = ntp / 32;
+  const int ch0 = w;
+  const int n = ch0 < nch ? (nch - ch0 + 3) / 4 : 0;
+  auto load_chunk = [&](int ch, v8bf (&af)[ZT][NF], float (&bv)[8]) {
+    load_run<float, 8>(vcol + ch * vstep, bv);
+#pragma unroll
+    for (int zt = 0; zt < ZT; ++zt) {
+      const size_t off = (((size_t)s * nch + ch) * ZT + zt) * 512 + (size_t)l * 8;
+      af[zt][0] = load_bf8<NT>(khi + off);
+      if constexpr (KIND == 2) af[zt][1] = load_bf8<NT>(klo + off);
+    }
+  };
+  auto mul_chunk = [&](const v8bf (&af)[ZT][NF], const float (&bv)[8]) {
+    v8bf bh, bl;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      __bf16 hi, lo;
+      split_bf16(k.on ? bv[u] : 0.0f, hi, lo);
+      bh[u] = hi;
+      bl[u] = lo;
+    }
+#pragma unroll
+    for (int zt = 0; zt < ZT; ++zt) {
+      acc[zt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[zt][0], bh, acc[zt], 0, 0, 0);
+      acc[zt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[zt][0], bl, acc[zt], 0, 0, 0);
+      if constexpr (KIND == 2) acc[zt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[zt][1], bh, acc[zt], 0, 0, 0);
+    }
+  };
+  if (n > 0) {
+    v8bf a0[ZT][NF], a1[ZT][NF];
+    float b0[8], b1[8];
+    load_chunk(ch0, a0, b0);
+    int i = 0;
+    for (; i + 2 < n; i += 2) {
+      load_chunk(ch0 + 4 * (i + 1), a1, b1);
+      __builtin_amdgcn_sched_barrier(0);
+      mul_chunk(a0, b0);
+      __builtin_amdgcn_sched_barrier(0);
+      load_chunk(ch0 + 4 * (i + 2), a0, b0);
+      __builtin_amdgcn_sched_barrier(0);
+      mul_chunk(a1, b1);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (i + 1 < n) {
+      load_chunk(ch0 + 4 * (i + 1), a1, b1);
+      __builtin_amdgcn_sched_barrier(0);
+      mul_chunk(a0, b0);
+      mul_chunk(a1, b1);
+    } else {
+      mul_chunk(a0, b0);
+    }
+  }
+#pragma unroll
+  for (int zt = 0; zt < ZT; ++zt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) red[((w * ZT + zt) * 64 + l) * 4 + r] = acc[zt][r];
+  __syncthreads();
+  if (w == 0 && k.on) {
+    float *ocol = reinterpret_cast<float *>(a.vout) + ((size_t)k.f * 2 + k.reim) * a.nvol * nzp +
+                  (size_t)k.vol * nzp;
+#pragma unroll
+    for (int zt = 0; zt < ZT; ++zt) {
+      float o[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        float v = red[((0 * ZT + zt) * 64 + l) * 4 + r];
+        v += red[((1 * ZT + zt) * 64 + l) * 4 + r];
+        v += red[((2 * ZT + zt) * 64 + l) * 4 + r];
+        v += red[((3 * ZT + zt) * 64 + l) * 4 + r];
+        o[r] = v;
+      }
+      *reinterpret_cast<float4 *>(ocol + zt * 16 + 4 * g) = make_float4(o[0], o[1], o[2], o[3]);
+    }
+  }
+}
+
 template <int KIND, bool NT, bool BAND>
 hipError_t launch_bf16(const ctof_kernel_s *k, bool adjoint, const CArgs &a0, hipStream_t st) {
   const Dims &d = k->dims;
@@ -699,6 +803,14 @@ hipError_t launch_bf16(const ctof_kernel_s *k, bool adjoint, const CArgs &a0, hi
   } else {
     const int zt = d.nzp / 16;
     const size_t shm = (size_t)4 * zt * 64 * 4 * sizeof(float);
+    if constexpr (!BAND) {
+      if (zt <= 4) {
+        if (zt == 2) hipLaunchKernelGGL((contract_adj_bf16_pipe_kernel<KIND, 2, NT>), grid, block, shm, st, a);
+        else if (zt == 4) hipLaunchKernelGGL((contract_adj_bf16_pipe_kernel<KIND, 4, NT>), grid, block, shm, st, a);
+        else return hipErrorInvalidValue;
+        return hipGetLastError();
+      }
+    }
     switch (zt) {
       case 2: hipLaunchKernelGGL((contract_adj_bf16_kernel<KIND, 2, NT, BAND>), grid, block, shm, st, a); break;
       case 4: hipLaunchKernelGGL((contract_adj_bf16_kernel<KIND, 4, NT, BAND>), grid, block, shm, st, a); break;

@@ -208,3 +208,24 @@ def test_band_table_is_the_box_of_the_oracle_spectrum():
         print(f"rel {rel:g}: matrices with a shorter t range {shrunk_t}, with fewer layers {shrunk_z}")
         assert shrunk_z > 0
     c.set_band(k, 0.0)
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16"])
+@pytest.mark.parametrize("nz", [20, 64])
+def test_pipelined_bf16_adjoint_equals_band_form(prec, nz):
+    # without a band the BF16 adjoints at up to 64 layers run the
+    # software-pipelined kernel; a band holding every nonzero entry runs the
+    # banded kernel over the same products in the same order (the tiles and
+    # layer groups it skips hold only zeros): bitwise the same adjoint
+    from paper_2101_11680_amd import ctof as c
+    g = _geom(n=24, nz=nz, nt=96)
+    k = c.tabulate(g, c.PRECISIONS[prec])
+    rng = np.random.default_rng(nz)
+    r = torch.tensor(rng.standard_normal((g.nt, 24, 24)), dtype=torch.float32, device="cuda")
+    full = c.adjoint(k, r)
+    c.set_band(k, 1e-300)
+    banded = c.adjoint(k, r)
+    c.set_band(k, 0.0)
+    assert torch.equal(full, banded)
+    F = oop.FFTOperator(okernel.tabulate(g))
+    assert rel_l2(to_np(full), F.adjoint(r.double().cpu().numpy())) <= 2e-3
