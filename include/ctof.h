@@ -476,8 +476,9 @@ ctof_status ctof_kernel_get_row_tuning(ctof_kernel k, int32_t *rb_t, int32_t *rb
  * following inverse column pass (the workspace then holds one volume-side
  * spectrum per run: query ctof_workspace_bytes after setting).  Shorter
  * blocks shorten the tail of a launch.  The effective values (get) are
- * clamped: 1 with a spectrum band or a BF16 precision, an adjoint of FFT
- * size above 256 keeps 1, and a run has at least one 16-bin tile.  Results
+ * clamped: 1 with a spectrum band and for the BF16 adjoints (the BF16
+ * forwards' rule is 1, other values as asked), an adjoint of FFT size above
+ * 256 keeps 1, and a run has at least one 16-bin tile.  Results
  * change only by the order of the adjoint's sum.  The handle must not be in
  * use on other streams meanwhile.
  */
@@ -486,7 +487,8 @@ ctof_status ctof_kernel_get_contract_parts(ctof_kernel k, int32_t *fwd_parts, in
 /*
  * Launch-shape tuner for a class of nvol volumes sharing the handle (the
  * batching form's per-class choice): times `iters` operator passes (the
- * eight launches of an iteration) for each legal FFT planes-per-block pair
+ * eight launches of an iteration; the fastest of three timings after a
+ * warm-up) for each legal FFT planes-per-block pair
  * with the contractions at their rule, then, with the fastest pair, the row
  * passes' planes per block, then the forward contraction's blocks per
  * matrix 1, 2, 4, 8, then the adjoint's, keeps the fastest of each in the

@@ -1437,12 +1437,13 @@ ctof_status run_tune(ctof_kernel_s *k, int nvol, int iters, void *ws, hipStream_
     }
   } ev_guard{&e0, &e1};
   HIP_TRY(hipEventCreate(&e1));
-  // milliseconds per iteration of the handle's current launch shape (< 0: error)
+  // milliseconds per iteration of the handle's current launch shape: the
+  // fastest of three timed passes after a warm-up pass (< 0: error)
   auto time_shape = [&](float *ms) -> ctof_status {
     const Engine<T> E = engine<T>(k, nvol, ws, 1, st);
     HIP_TRY(ctof::launch_fill_zero(E.ws, E.L.op_total, st));
-    float t = 0.f;
-    for (int rep = 0; rep < 2; ++rep) {  // the first pass warms up
+    float best = 1e30f;
+    for (int rep = 0; rep < 4; ++rep) {
       HIP_TRY(hipEventRecord(e0, st));
       for (int i = 0; i < iters; ++i) {
         const ctof::RowArgs a = E.row(ctof::ROW_PASS, true);
@@ -1458,9 +1459,11 @@ ctof_status run_tune(ctof_kernel_s *k, int nvol, int iters, void *ws, hipStream_
       }
       HIP_TRY(hipEventRecord(e1, st));
       HIP_TRY(hipEventSynchronize(e1));
+      float t = 0.f;
       HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+      if (rep > 0) best = std::min(best, t);
     }
-    *ms = t / std::max(iters, 1);
+    *ms = best / std::max(iters, 1);
     return CTOF_OK;
   };
   std::memset(out, 0, sizeof(*out));

@@ -788,11 +788,11 @@ contract_adj_bf16_pipe_kernel(CArgs a) {
 template <int KIND, bool NT, bool BAND>
 hipError_t launch_bf16(const ctof_kernel_s *k, bool adjoint, const CArgs &a0, hipStream_t st) {
   const Dims &d = k->dims;
-  // one block per matrix: split into t runs, the BF16 forward measured slower
-  // (each block splits its data columns into hi and lo parts again)
+  // the adjoints keep one block per matrix; the forwards split a matrix
+  // into the handle's runs of bins (contract_parts)
   CArgs a = a0;
-  a.parts = 1;
-  const dim3 grid((unsigned)(8 * ((d.nmat + 7) / 8) * a.npairs)), block(256);
+  if (adjoint) a.parts = 1;
+  const dim3 grid((unsigned)(8 * ((d.nmat + 7) / 8) * a.npairs * a.parts)), block(256);
   if (!adjoint) {
     const int kz = (d.nzp >= 64 ? 64 : d.nzp) / 4;
     switch (kz) {
@@ -845,7 +845,13 @@ hipError_t dispatch(const ctof_kernel_s *k, bool adjoint, const CArgs &a, hipStr
 int contract_parts(const ctof_kernel_s *k, bool adjoint) {
   const Dims &d = k->dims;
   const bool bf = k->prec == CTOF_BF16X3 || k->prec == CTOF_BF16;
-  if (k->band || bf) return 1;  // (the BF16 kernels keep one block per matrix)
+  if (k->band || (bf && adjoint)) return 1;  // (the BF16 adjoints keep one block per matrix)
+  if (bf) {
+    // the BF16 forwards split a matrix only when asked for (each block splits
+    // its data columns into hi and lo parts again: the hi-only form measured
+    // slower split, so the rule keeps one block)
+    return k->fwd_parts > 0 ? std::max(1, std::min(k->fwd_parts, d.ntp / 16)) : 1;
+  }
   if (!adjoint) {
     // up to four blocks per matrix, at least 8 t tiles (2 per wave) each:
     // shorter blocks shorten the tail of the launch

@@ -390,5 +390,22 @@ def test_contraction_parts_rules():
     # 48 bins pad to 64: four 16-bin tiles and four chunks at most
     assert c.get_contract_parts(k) == (4, 4)
     kb = c.tabulate(SMALL, c.BF16X3)
+    assert c.get_contract_parts(kb) == (1, 1)  # the BF16 rule: one block per matrix
     c.set_contract_parts(kb, 4, 4)
-    assert c.get_contract_parts(kb) == (1, 1)  # the BF16 kernels keep one block per matrix
+    assert c.get_contract_parts(kb) == (4, 1)  # the BF16 adjoints keep one block per matrix
+
+
+@pytest.mark.parametrize("prec", ["bf16x3", "bf16"])
+def test_bf16_forward_split_is_bitwise_the_same(prec):
+    # a BF16 forward split into runs of bins takes every tile's products in
+    # the same order as one block per matrix: the same output bit for bit
+    c = ct()
+    k = c.tabulate(SMALL, c.PRECISIONS[prec])
+    rng = np.random.default_rng(5)
+    mu = torch.tensor(rng.random((SMALL.nz, SMALL.ny, SMALL.nx)), dtype=torch.float32, device="cuda")
+    base = c.forward(k, mu)
+    for fp in (2, 4, 8):
+        c.set_contract_parts(k, fp, 0)
+        assert torch.equal(c.forward(k, mu), base), fp
+    c.set_contract_parts(k, 0, 0)
+    assert rel_l2(to_np(base), oracle_fft(SMALL).forward(mu.double().cpu().numpy())) <= 2e-3
