@@ -340,8 +340,16 @@ col_pass_kernel(int ny, int B, const T *__restrict__ in, T *__restrict__ out, in
     for (int k2 = 0; k2 < R2; ++k2) {
       const int row = k1 + R1 * k2;
       if (row < rows_out) {
-        dst[((size_t)row * 2) * B + b2] = zr[k2];
-        dst[((size_t)row * 2 + 1) * B + b2] = zi[k2];
+        if constexpr (!INV) {
+          // the forward pass's spectrum goes to memory at once (non-temporal):
+          // the contraction that reads it next then starts without this
+          // pass's dirty lines draining from the L2 under its reads
+          __builtin_nontemporal_store(zr[k2], &dst[((size_t)row * 2) * B + b2]);
+          __builtin_nontemporal_store(zi[k2], &dst[((size_t)row * 2 + 1) * B + b2]);
+        } else {
+          dst[((size_t)row * 2) * B + b2] = zr[k2];
+          dst[((size_t)row * 2 + 1) * B + b2] = zi[k2];
+        }
       }
     }
   }
