@@ -505,14 +505,15 @@ ctof_status ctof_kernel_get_contract_parts(ctof_kernel k, int32_t *fwd_parts, in
  *   ms_fwd, ms_adj   for 1, 2, 4, 8 blocks per matrix; -1 where the value
  *           clamps to one timed before
  *   ms_rb   for row-pass planes (rb_t, rb_z) = (bb_t, bb_z), (64, bb_z),
- *           (bb_t, 64), (64, 64); -1 where 64 does not apply
+ *           (bb_t, 16), (64, 16), (bb_t, 64), (64, 64); -1 where the
+ *           effective values repeat an earlier pair's
  *   rb_t, rb_z   the row passes' effective planes per block
  */
 typedef struct {
   int32_t bb_t, bb_z, fwd_parts, adj_parts;
   float ms_bb[4], ms_fwd[4], ms_adj[4];
   int32_t rb_t, rb_z;
-  float ms_rb[4];
+  float ms_rb[6];
 } ctof_tuning;
 ctof_status ctof_tune_workspace_bytes(ctof_kernel k, int32_t nvol, size_t *ws_bytes);
 ctof_status ctof_tune(ctof_kernel k, int32_t nvol, int32_t iters, void *ws_dev, size_t ws_bytes,

@@ -1495,18 +1495,24 @@ ctof_status run_tune(ctof_kernel_s *k, int nvol, int iters, void *ws, hipStream_
   }
   k->bb_t = cand[bi][0];
   k->bb_z = cand[bi][1];
-  // 2. the row passes' planes per block: the column passes' or 64 (pairs the
-  // rule does not allow are skipped; the first repeats the choice above)
-  const int rcand[4][2] = {{0, 0}, {64, 0}, {0, 64}, {64, 64}};
+  // 2. the row passes' planes per block: the column passes' or 64 on the
+  // bin side, the column passes', 16 or 64 on the layer side (pairs whose
+  // effective values repeat an earlier pair's are skipped; the first repeats
+  // the choice above)
+  const int rcand[6][2] = {{0, 0}, {64, 0}, {0, 16}, {64, 16}, {0, 64}, {64, 64}};
   {
     float bestr = 1e30f;
     int ri = 0;
-    for (int c = 0; c < 4; ++c) {
+    int seen[6][2];
+    for (int c = 0; c < 6; ++c) {
       k->rb_t = rcand[c][0];
       k->rb_z = rcand[c][1];
       const Engine<T> E = engine<T>(k, nvol, ws, 1, st);
-      if ((rcand[c][0] && ctof::row_block(E.dm(), E.Bt(), E.dm().ntp, f64, 64) != 64) ||
-          (rcand[c][1] && ctof::row_block(E.dm(), E.Bz(), E.dm().nzp, f64, 64) != 64)) {
+      seen[c][0] = ctof::row_block(E.dm(), E.Bt(), E.dm().ntp, f64, row_planes(k, true));
+      seen[c][1] = ctof::row_block(E.dm(), E.Bz(), E.dm().nzp, f64, row_planes(k, false));
+      bool dup = false;
+      for (int r = 0; r < c; ++r) dup = dup || (seen[r][0] == seen[c][0] && seen[r][1] == seen[c][1]);
+      if (dup) {
         out->ms_rb[c] = -1.f;
         continue;
       }
@@ -2098,7 +2104,7 @@ static size_t tune_ws_bytes(ctof_kernel_s *k, int nvol) {
   size_t need = 0;
   for (int bt : {16, 32})
     for (int bz : {16, 32})
-      for (int rb : {0, 64})
+      for (int rb : {0, 16, 64})
         for (int ap : {1, 2, 4, 8}) {
           k->bb_t = bt;
           k->bb_z = bz;

@@ -81,7 +81,7 @@ class _Tuning(ctypes.Structure):
     _fields_ = [("bb_t", ctypes.c_int32), ("bb_z", ctypes.c_int32), ("fwd_parts", ctypes.c_int32),
                 ("adj_parts", ctypes.c_int32), ("ms_bb", ctypes.c_float * 4), ("ms_fwd", ctypes.c_float * 4),
                 ("ms_adj", ctypes.c_float * 4), ("rb_t", ctypes.c_int32), ("rb_z", ctypes.c_int32),
-                ("ms_rb", ctypes.c_float * 4)]
+                ("ms_rb", ctypes.c_float * 6)]
 
 
 class _SolverReport(ctypes.Structure):

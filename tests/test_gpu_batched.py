@@ -130,8 +130,9 @@ def test_tuner_choices_keep_results_and_cache(tmp_path):
     assert c.get_tuning(k) == (bt, bz) and c.get_contract_parts(k) == t["parts"]
     assert c.get_row_tuning(k) == t["rb"] and t["rb"][0] in (16, 32, 64)
     assert all(x > 0 or x == -1 for x in t["ms_bb"] + t["ms_rb"] + t["ms_fwd"] + t["ms_adj"])
-    # 64-plane row blocks apply only where 64 divides the planes (16 layers here)
-    assert t["ms_rb"][2] == -1 and t["ms_rb"][3] == -1
+    # 64-plane row blocks apply only where 64 divides the planes (16 layers
+    # here: a 64 on the layer side acts as the rule's value, a repeat)
+    assert len(t["ms_rb"]) == 6 and t["ms_rb"][4] == -1 and t["ms_rb"][5] == -1
     # the choice is the fastest timed value of each stage
     assert min(x for x in t["ms_fwd"] if x > 0) > 0
     t2 = c.tune(k, nvol=4, cache=cache)
