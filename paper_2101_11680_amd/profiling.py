@@ -16,6 +16,10 @@
       that maps the copy's reading to its known size (bytes read = written =
       COPY_MIB MiB), and the result is tied to the source file's digest so
       that a changed kernel is not credited with old counters.
+  python -m paper_2101_11680_amd.profiling stats STATS_CSV OUT.txt TITLE COMMAND...
+      a kernel-stats CSV (rocprofv3 --kernel-trace --stats) -> per-kernel
+      totals (calls, total and average duration, share), for runs whose full
+      trace is too long to keep
   python -m paper_2101_11680_amd.profiling mfma PMC_DIR STEPS MS_PER_STEP PEAK_TFLOPS OUT.txt TITLE COMMAND...
       one --pmc run holding SQ_INSTS_VALU_MFMA_MOPS_<type> and
       SQ_VALU_MFMA_BUSY_CYCLES over STEPS repetitions of a step that takes
@@ -201,6 +205,22 @@ def iteration_table(trace_dir, fetch_dir, write_dir, cfetch_dir, cwrite_dir, cop
     return text
 
 
+def summarize_stats(stats_csv: str, out: str, title: str, command: str, top: int = 40) -> str:
+    rows = list(csv.DictReader(open(stats_csv)))
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    lines = [f"# {title}", "", "command (run from /tmp with TMPDIR=/tmp; R = repository root):", f"  {command}", "",
+             f"rocprofv3 kernel statistics, {len(rows)} kernels, {tot / 1e9:.3f} s of kernel time in all "
+             f"(durations in microseconds; the {top} largest totals)", "",
+             f"{'kernel':70s} {'calls':>8s} {'total_ms':>10s} {'avg_us':>9s} {'share':>6s}"]
+    for r in sorted(rows, key=lambda r: -float(r["TotalDurationNs"]))[:top]:
+        lines.append(f"{_short(r['Name'])[:70]:70s} {int(r['Calls']):8d} {float(r['TotalDurationNs']) / 1e6:10.1f} "
+                     f"{float(r['AverageNs']) / 1e3:9.1f} {100 * float(r['TotalDurationNs']) / tot:5.1f}%")
+    text = "\n".join(lines) + "\n"
+    with open(out, "w") as f:
+        f.write(text)
+    return text
+
+
 def mfma_table(pmc_dir: str, steps: int, ms_per_step: float, peak_tflops: float, out: str, title: str,
                command: str, clock_hz: float = 2.4e9, simds: int = 1024) -> str:
     """Executed MFMA work per step from one counter run: MOPS x 512 flops and
@@ -254,6 +274,9 @@ def main(argv) -> int:
     if len(argv) >= 11 and argv[0] == "iteration":
         print(iteration_table(argv[1], argv[2], argv[3], argv[4], argv[5], int(argv[6]), argv[7], argv[8], argv[9],
                               " ".join(argv[10:])))
+        return 0
+    if len(argv) >= 5 and argv[0] == "stats":
+        print(summarize_stats(argv[1], argv[2], argv[3], " ".join(argv[4:])))
         return 0
     if len(argv) >= 8 and argv[0] == "mfma":
         print(mfma_table(argv[1], int(argv[2]), float(argv[3]), float(argv[4]), argv[5], argv[6],
