@@ -710,6 +710,12 @@ ctof_status ctof_layer_threshold(int32_t nz, int64_t plane, float *mu_dev, float
 ctof_status ctof_adam_step(int64_t n, float *w_dev, const float *g_dev, float *m_dev, float *v_dev,
                            void *w_bf16_dev, float lr, float beta1, float beta2, float eps, int32_t step,
                            hipStream_t stream);
+/* The same step on the gradient scaled by grad_scale (finite, >= 0): the
+ * caller's gradient-norm clipping (scale = min(1, c / ||g||)) for callers
+ * that tame rare large gradients without a host-side pass over g. */
+ctof_status ctof_adam_step_scaled(int64_t n, float *w_dev, const float *g_dev, float *m_dev, float *v_dev,
+                                  void *w_bf16_dev, float lr, float beta1, float beta2, float eps, int32_t step,
+                                  float grad_scale, hipStream_t stream);
 
 /* Dense float [n] -> BF16 channel out.c0 of n rows (v = x * scale rounded
  * to BF16); with split, channel out.c0 + 1 receives BF16(v - BF16(v)), so the

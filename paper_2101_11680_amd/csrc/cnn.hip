@@ -650,10 +650,10 @@ mse_total_kernel(const double *__restrict__ part, int nblk, long long n, double 
 // Adam with bias correction on FP32 master weights; optional BF16 copy.
 __global__ void adam_kernel(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m,
                             float *__restrict__ v, __bf16 *__restrict__ wb, long long n, float lr, float b1,
-                            float b2, float eps, float c1, float c2) {
+                            float b2, float eps, float c1, float c2, float gs) {
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const float gi = g[i];
+  const float gi = g[i] * gs;
   const float mi = b1 * m[i] + (1.0f - b1) * gi;
   const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
   m[i] = mi;
@@ -1130,12 +1130,12 @@ hipError_t launch_mse(const float *y, int yld, int yc0, float ys, const float *t
 }
 
 hipError_t launch_adam(float *w, const float *g, float *m, float *v, __bf16 *wb, long long n, float lr, float b1,
-                       float b2, float eps, int step, hipStream_t st) {
+                       float b2, float eps, int step, float gscale, hipStream_t st) {
   if (n == 0) return hipSuccess;
   const float c1 = (float)(1.0 - pow((double)b1, (double)step));
   const float c2 = (float)(1.0 - pow((double)b2, (double)step));
   hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(n)), dim3(256), 0, st, w, g, m, v, wb, n, lr, b1, b2, eps, c1,
-                     c2);
+                     c2, gscale);
   return hipGetLastError();
 }
 

@@ -204,7 +204,22 @@ ctof_status ctof_adam_step(int64_t n, float *w_dev, const float *g_dev, float *m
   if (step < 1) return set_error(CTOF_EINVAL, "step counts from 1");
   if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f && lr >= 0.0f))
     return set_error(CTOF_EINVAL, "need 0 <= beta < 1, eps > 0, lr >= 0");
-  HIP_TRY(ctof::launch_adam(w_dev, g_dev, m_dev, v_dev, bfw(w_bf16_dev), n, lr, beta1, beta2, eps, step, stream));
+  HIP_TRY(ctof::launch_adam(w_dev, g_dev, m_dev, v_dev, bfw(w_bf16_dev), n, lr, beta1, beta2, eps, step, 1.0f,
+                            stream));
+  return CTOF_OK;
+}
+
+ctof_status ctof_adam_step_scaled(int64_t n, float *w_dev, const float *g_dev, float *m_dev, float *v_dev,
+                                  void *w_bf16_dev, float lr, float beta1, float beta2, float eps, int32_t step,
+                                  float grad_scale, hipStream_t stream) {
+  if (!(grad_scale >= 0.0f && grad_scale <= 1e30f)) return set_error(CTOF_EINVAL, "grad_scale must be finite, >= 0");
+  if (n < 0 || n > kMaxRows) return set_error(CTOF_EINVAL, "bad n");
+  if (!w_dev || !g_dev || !m_dev || !v_dev) return set_error(CTOF_EINVAL, "w, g, m or v is NULL");
+  if (step < 1) return set_error(CTOF_EINVAL, "step counts from 1");
+  if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f && lr >= 0.0f))
+    return set_error(CTOF_EINVAL, "need 0 <= beta < 1, eps > 0, lr >= 0");
+  HIP_TRY(ctof::launch_adam(w_dev, g_dev, m_dev, v_dev, bfw(w_bf16_dev), n, lr, beta1, beta2, eps, step, grad_scale,
+                            stream));
   return CTOF_OK;
 }
 

@@ -323,7 +323,7 @@ size_t mse_ws_bytes(long long n);
 hipError_t launch_mse(const float *y, int yld, int yc0, float ys, const float *t, long long n, __bf16 *g, int gld,
                       int gc0, int relu_mask, double *part, double *loss, hipStream_t st);
 hipError_t launch_adam(float *w, const float *g, float *m, float *v, __bf16 *wb, long long n, float lr, float b1,
-                       float b2, float eps, int step, hipStream_t st);
+                       float b2, float eps, int step, float gscale, hipStream_t st);
 hipError_t launch_to_channels_last(const float *x, long long n, float scale, __bf16 *out, int ld, int c0,
                                    int zero_rest, int split, hipStream_t st);
 hipError_t launch_from_channels_last(const float *y, int ld, int c0, long long n, float scale, float *out,

@@ -39,7 +39,7 @@ EXPORTS = ("ctof_kernel_bytes", "ctof_kernel_tabulate", "ctof_kernel_tabulate_qu
            "ctof_mux_forward", "ctof_mux_adjoint", "ctof_mux_normal_ws_bytes", "ctof_mux_normal",
            "ctof_noisy_counts", "ctof_layer_energy_ws_bytes", "ctof_l1_depth_weights",
            "ctof_forward_noalloc", "ctof_kernel_set_contract_parts", "ctof_kernel_get_contract_parts",
-           "ctof_kernel_set_row_tuning", "ctof_kernel_get_row_tuning")
+           "ctof_kernel_set_row_tuning", "ctof_kernel_get_row_tuning", "ctof_adam_step_scaled")
 
 
 class CtofError(RuntimeError):
@@ -157,6 +157,7 @@ def lib() -> ctypes.CDLL:
         L.ctof_mse_ws_bytes.argtypes = [i64, ctypes.POINTER(sz)]
         L.ctof_mse.argtypes = [i64, tp, f32, vp, tp, i32, vp, vp, sz, vp]
         L.ctof_adam_step.argtypes = [i64, vp, vp, vp, vp, vp, f32, f32, f32, f32, i32, vp]
+        L.ctof_adam_step_scaled.argtypes = [i64, vp, vp, vp, vp, vp, f32, f32, f32, f32, i32, f32, vp]
         L.ctof_to_channels_last.argtypes = [i64, vp, f32, tp, i32, i32, vp]
         L.ctof_from_channels_last.argtypes = [i64, tp, f32, vp, vp]
         L.ctof_philox4x32.argtypes = [u64, u32, i64, i64, vp, vp]
@@ -282,9 +283,12 @@ class Kernel:
         _check(lib().ctof_workspace_bytes(self._h, int(max_iter), ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
 
-    def workspace(self, nbytes: int, device):
+    def workspace(self, nbytes: int, device, stream=None):
+        """The handle's cached workspace of at least nbytes on device, one per
+        stream (calls on one stream run in order and may share it; calls on
+        different streams may overlap and must not)."""
         torch = _torch()
-        key = str(device)
+        key = f"{device}|{_stream_ptr(stream)}"
         ws = self._ws.get(key)
         if ws is None or ws.numel() < nbytes:
             ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
@@ -345,7 +349,7 @@ def forward(k: Kernel, mu, out=None, stream=None):
         out = torch.empty((i.nt, i.ny, i.nx), dtype=mu.dtype, device=mu.device)
     out = _contig(out, mu.dtype, (i.nt, i.ny, i.nx))
     nb, _ = k.workspace_bytes(1)
-    ws = k.workspace(nb, mu.device)
+    ws = k.workspace(nb, mu.device, stream)
     _check(lib().ctof_forward(k.handle, mu.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(),
                               _stream_ptr(stream)))
     return out
@@ -373,7 +377,7 @@ def adjoint(k: Kernel, r, out=None, stream=None):
         out = torch.empty((i.nz, i.ny, i.nx), dtype=r.dtype, device=r.device)
     out = _contig(out, r.dtype, (i.nz, i.ny, i.nx))
     nb, _ = k.workspace_bytes(1)
-    ws = k.workspace(nb, r.device)
+    ws = k.workspace(nb, r.device, stream)
     _check(lib().ctof_adjoint(k.handle, r.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(),
                               _stream_ptr(stream)))
     return out
@@ -476,7 +480,7 @@ def mux_normal(k: Kernel, mux: Mux, m, y=None, out=None, fit: bool = False, stre
     f = torch.zeros((), dtype=torch.float64, device=m.device) if fit else None
     nb = ctypes.c_size_t()
     _check(lib().ctof_mux_normal_ws_bytes(k.handle, ctypes.byref(desc), ctypes.byref(nb)))
-    ws = k.workspace(nb.value, m.device) if fit else None
+    ws = k.workspace(nb.value, m.device, stream) if fit else None
     _check(lib().ctof_mux_normal(k.handle, ctypes.byref(desc), m.data_ptr(),
                                  y.data_ptr() if y is not None else None, out.data_ptr(),
                                  f.data_ptr() if f is not None else None,
@@ -534,7 +538,7 @@ def reconstruct(k: Kernel, d, mu=None, max_iter: int = 200, lam: float = -1.0,
                        mu_prev.data_ptr() if mu_prev is not None else None, int(k0), None)
     rep = _SolverReport()
     _, nb = k.workspace_bytes(max_iter)
-    ws = k.workspace(nb, d.device)
+    ws = k.workspace(nb, d.device, stream)
     _check(lib().ctof_reconstruct(k.handle, d.data_ptr(), mu.data_ptr(), ctypes.byref(opts),
                                   ctypes.byref(rep), ws.data_ptr(), ws.numel(), _stream_ptr(stream)))
     report = _report(rep)

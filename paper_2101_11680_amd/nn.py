@@ -176,10 +176,27 @@ def mse(n: int, y: Slice, target, grad: Slice, loss, relu_mask=True, y_scale=1.0
                           _stream_ptr(stream)))
 
 
-def adam_step(w, g, m, v, w_bf16, lr, step, b1=0.9, b2=0.999, eps=1e-8, stream=None):
-    _check(lib().ctof_adam_step(int(w.numel()), w.data_ptr(), g.data_ptr(), m.data_ptr(), v.data_ptr(),
-                                w_bf16.data_ptr() if w_bf16 is not None else None, float(lr), float(b1),
-                                float(b2), float(eps), int(step), _stream_ptr(stream)))
+def adam_step(w, g, m, v, w_bf16, lr, step, b1=0.9, b2=0.999, eps=1e-8, grad_scale=1.0, stream=None):
+    wb = w_bf16.data_ptr() if w_bf16 is not None else None
+    if grad_scale == 1.0:
+        _check(lib().ctof_adam_step(int(w.numel()), w.data_ptr(), g.data_ptr(), m.data_ptr(), v.data_ptr(), wb,
+                                    float(lr), float(b1), float(b2), float(eps), int(step), _stream_ptr(stream)))
+    else:
+        _check(lib().ctof_adam_step_scaled(int(w.numel()), w.data_ptr(), g.data_ptr(), m.data_ptr(), v.data_ptr(),
+                                           wb, float(lr), float(b1), float(b2), float(eps), int(step),
+                                           float(grad_scale), _stream_ptr(stream)))
+
+
+def sumsq(x, stream=None):
+    """FP64 sum of squares of a float tensor (one device double)."""
+    torch = _torch()
+    nb = ctypes.c_size_t()
+    _check(lib().ctof_sumsq_ws_bytes(1, ctypes.byref(nb)))
+    ws = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=x.device)
+    out = torch.empty(1, dtype=torch.float64, device=x.device)
+    _check(lib().ctof_sumsq(1, int(x.numel()), x.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(),
+                            _stream_ptr(stream)))
+    return out
 
 
 def to_channels_last(x, scale: float, out: Slice, zero_rest=False, split=False, stream=None):

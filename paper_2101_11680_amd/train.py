@@ -138,7 +138,7 @@ def target_norms(P: Problem, targets, chunk: int = 32):
 def train(net: "unet.UNet", P: Problem, xs, targets, steps: int, batch: int = 8, lr: float = 3e-4,
           lr_min: float = 1e-5, warmup: int = 300, seed: int = 0, log_every: int = 100, log=print,
           loss: str = "operator", alpha: float = 1.0, norms=None, maxima=None,
-          floor_pct: float = 10.0, robust: bool = False) -> List[float]:
+          floor_pct: float = 10.0, robust: bool = False, clip: float = 0.0) -> List[float]:
     """Adam with cosine learning-rate decay on random minibatches.
 
     loss = "operator": mean over the batch of ||H e||^2 / ||H mu*||^2 +
@@ -152,7 +152,10 @@ def train(net: "unet.UNet", P: Problem, xs, targets, steps: int, batch: int = 8,
     log(1 + loss_b) (its gradient divided by 1 + loss_b, found by a first
     evaluation of the terms), which bounds the pull of a sample the network
     overshoots.  The learning rate rises linearly over `warmup` steps, then
-    follows a cosine to lr_min."""
+    follows a cosine to lr_min.  With clip > 0 the gradient is scaled to at
+    most clip times the running mean of its norm (an exponential average
+    over about 50 steps, of the clipped norms), so a rare minibatch that
+    would throw the weights far is taken at a bounded step."""
     torch = _torch()
     g = torch.Generator(device="cpu").manual_seed(seed)
     N = xs.shape[0]
@@ -164,6 +167,7 @@ def train(net: "unet.UNet", P: Problem, xs, targets, steps: int, batch: int = 8,
         floors = np.percentile(norms, floor_pct, axis=0)
         norms = np.maximum(norms, floors[None, :])
     losses = []
+    gnorm_avg, n_clipped = None, 0
     t0 = time.time()
     for step in range(steps):
         idx_h = torch.randint(0, N, (batch,), generator=g)
@@ -190,7 +194,17 @@ def train(net: "unet.UNet", P: Problem, xs, targets, steps: int, batch: int = 8,
         else:
             ph = (step - warmup) / max(steps - warmup, 1)
             cur = lr_min + 0.5 * (lr - lr_min) * (1.0 + math.cos(math.pi * ph))
-        net.adam(cur)
+        gscale = 1.0
+        if clip > 0.0:
+            gn = math.sqrt(float(nn.sumsq(net.grad).item()))
+            if gnorm_avg is None:
+                gnorm_avg = gn
+            limit = clip * gnorm_avg
+            if gn > limit > 0.0:
+                gscale = limit / gn
+                n_clipped += 1
+            gnorm_avg = 0.98 * gnorm_avg + 0.02 * gn * gscale
+        net.adam(cur, grad_scale=gscale)
         if (step + 1) % log_every == 0 or step == steps - 1:
             if loss == "operator":
                 t = terms.cpu().numpy()
@@ -200,7 +214,8 @@ def train(net: "unet.UNet", P: Problem, xs, targets, steps: int, batch: int = 8,
                 val = float(terms.item())
                 extra = ""
             losses.append(val)
-            log(f"train step {step + 1}/{steps} loss {val:.4e}{extra} lr {cur:.2e} "
+            clipped = f" clipped {n_clipped}" if clip > 0.0 else ""
+            log(f"train step {step + 1}/{steps} loss {val:.4e}{extra} lr {cur:.2e}{clipped} "
                 f"{(time.time() - t0) / (step + 1) * 1e3:.1f} ms/step")
     return losses
 
@@ -288,6 +303,8 @@ def main(argv=None) -> int:
     ap.add_argument("--loss", default="operator", choices=("operator",))
     ap.add_argument("--alpha", type=float, default=1.0)
     ap.add_argument("--robust", action="store_true", help="log(1 + loss) per sample")
+    ap.add_argument("--clip", type=float, default=0.0,
+                    help="scale the gradient to at most CLIP times its running mean norm (0: off)")
     ap.add_argument("--out", default="warmstart.npz")
     ap.add_argument("--report", default="warmstart_report.json")
     a = ap.parse_args(argv)
@@ -306,14 +323,14 @@ def main(argv=None) -> int:
     log(f"scales: in {net.in_scale:.4e} out {net.out_scale:.4e}")
     t0 = time.time()
     losses = train(net, P, xs, ts, a.steps, batch=a.batch, lr=a.lr, log=log, loss=a.loss, alpha=a.alpha,
-                   maxima=mx, robust=a.robust)
+                   maxima=mx, robust=a.robust, clip=a.clip)
     torch.cuda.synchronize()
     t_train = time.time() - t0
     del xs, ts
     os.makedirs(os.path.dirname(a.out) or ".", exist_ok=True)
     net.save(a.out, extra=dict(workload=a.workload, nz=geom.nz, n_train=a.n_train, steps=a.steps, batch=a.batch,
                                tol=a.tol, lipschitz=P.lipschitz, lam=P.lam, loss=a.loss, alpha=a.alpha, lr=a.lr,
-                               robust=a.robust))
+                               robust=a.robust, clip=a.clip))
     ds = simulate(P, w, eval_seeds, peak_seed=eval_seeds[0])
     res = evaluate(net, P, ds, tol=a.tol, max_iter=a.max_iter)
     res.update(train_seconds=t_train, train_steps=a.steps, batch=a.batch, n_train=a.n_train,

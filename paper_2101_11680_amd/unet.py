@@ -342,9 +342,10 @@ class UNet:
         self.backward_from_output_grad(stream=stream)
         return self._terms[:n]
 
-    def adam(self, lr: float, stream=None) -> None:
+    def adam(self, lr: float, grad_scale: float = 1.0, stream=None) -> None:
         self.step_count += 1
-        nn.adam_step(self.master, self.grad, self.m, self.v, self.work, lr, self.step_count, stream=stream)
+        nn.adam_step(self.master, self.grad, self.m, self.v, self.work, lr, self.step_count, grad_scale=grad_scale,
+                     stream=stream)
 
     # ---- inference ----------------------------------------------------------------
     def predict(self, x, tau=1.0, stream=None):

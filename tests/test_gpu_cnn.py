@@ -488,3 +488,24 @@ def test_depth_resample():
     np.testing.assert_array_equal(pooled, x[:, 0::2] + x[:, 1::2])
     rep = nn.depth_resample(xt, 1).cpu().numpy()
     np.testing.assert_array_equal(rep, np.repeat(x, 2, axis=1))
+
+
+def test_adam_scaled_gradient_and_sumsq():
+    # ctof_adam_step_scaled is Adam on grad_scale * g (the oracle step on the
+    # scaled FP64 gradient); ctof_sumsq is the FP64 sum of squares
+    nn = _nn()
+    r = np.random.default_rng(21)
+    w0 = r.standard_normal(777)
+    w = torch.tensor(w0, dtype=torch.float32, device="cuda")
+    m, v = torch.zeros_like(w), torch.zeros_like(w)
+    wr, mr, vr = w0.astype(np.float32).astype(np.float64), np.zeros(777), np.zeros(777)
+    for step, gs in ((1, 0.25), (2, 1.0), (3, 0.5)):
+        gr = r.standard_normal(777).astype(np.float32)
+        gt = torch.tensor(gr, device="cuda")
+        assert nn.sumsq(gt).item() == pytest.approx(float(np.sum(gr.astype(np.float64) ** 2)), rel=1e-12)
+        nn.adam_step(w, gt, m, v, None, 1e-2, step, grad_scale=gs)
+        wr, mr, vr = ocnn.adam_step(wr, gs * gr.astype(np.float64), mr, vr, step, lr=1e-2)
+    np.testing.assert_allclose(w.cpu().numpy(), wr, rtol=1e-5, atol=1e-6)
+    from paper_2101_11680_amd import ctof as c
+    with pytest.raises(c.CtofError):
+        nn.adam_step(w, gt, m, v, None, 1e-2, 4, grad_scale=float("nan"))
