@@ -509,3 +509,41 @@ def test_adam_scaled_gradient_and_sumsq():
     from paper_2101_11680_amd import ctof as c
     with pytest.raises(c.CtofError):
         nn.adam_step(w, gt, m, v, None, 1e-2, 4, grad_scale=float("nan"))
+
+
+# every layer of the shipped network (channels 16/32/64/64, split input) at
+# its real grid, batch 1: the forward, input-gradient and weight-gradient
+# kernels each against the oracle
+_LEVEL_GRID = [(32, 64, 64), (16, 32, 32), (8, 16, 16), (4, 8, 8)]
+_LEVEL_IN = {"e1a": 0, "e1b": 0, "d1": 0, "e2a": 1, "e2b": 1, "d2": 1, "e3a": 2, "e3b": 2, "d3": 2, "m4a": 3,
+             "m4b": 3, "u3": 3, "c3a": 2, "c3b": 2, "u2": 2, "c2a": 1, "c2b": 1, "u1": 1, "c1a": 0, "c1b": 0,
+             "head": 0}
+REAL_LAYERS = [(name, kind, co, ci) for name, kind, co, ci in ocnn.unet_layers((16, 32, 64, 64), c_in=2)]
+
+
+@pytest.mark.parametrize("name,kind,co,ci", REAL_LAYERS, ids=[L[0] for L in REAL_LAYERS])
+def test_network_layers_at_real_shapes(name, kind, co, ci):
+    nn = _nn()
+    grid = (1,) + _LEVEL_GRID[_LEVEL_IN[name]]
+    x, W, b = _setup(kind, grid, ci, co, 30)
+    ref = ocnn.conv(kind, x, W, b)
+    cv = _conv(nn, kind, grid, ci, co)
+    xb = _buffer(x, nn.cip(ci))
+    wb = _dev_bf16(nn.pack_weights(cv.kind, W))
+    y = torch.zeros((cv.out_rows(), co), dtype=torch.float32, device="cuda")
+    nn.conv_fwd(cv, nn.Slice(xb, 0, ci), wb, torch.tensor(b, dtype=torch.float32, device="cuda"),
+                nn.Slice(y, 0, co), relu=False)
+    assert np.max(np.abs(_host(y).reshape(ref.shape) - ref)) / np.max(np.abs(ref)) <= 1e-5
+    dy = _bf(np.random.default_rng(31).standard_normal(ref.shape))
+    dxr, dWr, dbr = ocnn.conv_backward(kind, x, W, dy)
+    dyb = _buffer(dy, nn.cip(co))
+    dx = torch.zeros((int(np.prod(grid)), ci), dtype=torch.bfloat16, device="cuda")
+    nn.conv_bwd_data(cv, nn.Slice(dyb, 0, co), wb, nn.Slice(dx, 0, ci))
+    got = _host(dx).reshape(dxr.shape)
+    assert np.all(np.abs(got - dxr) <= 2.0 ** -8 * np.abs(dxr) + 1e-6 * np.max(np.abs(dxr)))
+    dw = torch.full((nn.weight_elems(cv.kind, co, ci),), float("nan"), device="cuda")
+    dbias = torch.zeros(co, device="cuda")
+    nn.conv_bwd_weight(cv, nn.Slice(xb, 0, ci), nn.Slice(dyb, 0, co), dw, dbias)
+    gw = nn.unpack_weights(cv.kind, dw.cpu().numpy(), co, ci)
+    assert np.max(np.abs(gw - dWr)) / np.max(np.abs(dWr)) <= 1e-5
+    np.testing.assert_allclose(dbias.cpu().numpy(), dbr, rtol=1e-5, atol=1e-5 * np.max(np.abs(dbr)))
