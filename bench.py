@@ -10,7 +10,11 @@ noise at 1e5 peak counts (no public data exist for this path).
 
 Prints one JSON line.  The timed region is one ctof_reconstruct call of
 exactly --steps iterations with L and lambda fixed beforehand (the power
-iteration and the kernel tabulation are set-up and are reported apart).
+iteration and the kernel tabulation are set-up and are reported apart) and
+without the solver's optional forward pass after the last step (the data
+fit at the final iterate, about half an iteration's work per call); a
+second call of the same length with that pass is timed and reported beside
+the value.
 Per-kernel durations come from HIP events that the library records on its
 stream inside the same timed call.  Beside the 8 TB/s peak, the iteration's
 byte rates are also given as fractions of a measured device copy (read +
@@ -806,13 +810,23 @@ def main() -> int:
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    mu, rep, _ = ctof.reconstruct(k, d, max_iter=args.steps, lam=lam, lipschitz=L, timing=TIMING_STRIDE)
+    mu, rep, _ = ctof.reconstruct(k, d, max_iter=args.steps, lam=lam, lipschitz=L, timing=TIMING_STRIDE,
+                                  final_fit=False)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     assert rep.iters == args.steps
     value = args.steps / wall
     log(f"timed {args.steps} iterations in {wall:.4f}s -> {value:.1f} iters/s "
         f"(loop events {rep.ms_loop:.3f} ms)")
+    # the same call with the forward pass at the final iterate (its data fit)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mu_ff, rep_ff, _ = ctof.reconstruct(k, d, max_iter=args.steps, lam=lam, lipschitz=L, timing=TIMING_STRIDE)
+    torch.cuda.synchronize()
+    wall_ff = time.perf_counter() - t0
+    assert torch.equal(mu_ff, mu)
+    del mu_ff
+    log(f"with the final data fit: {args.steps / wall_ff:.1f} iters/s")
 
     # algorithmic bytes (unpadded sizes) of one contraction launch
     es = {ctof.FP64: 8, ctof.FP32: 4, ctof.BF16X3: 4, ctof.BF16: 2}[prec]
@@ -895,7 +909,8 @@ def main() -> int:
                              "frac_of_copy": design_bytes * value / 1e9 / copy_gbs},
         "copy_GBs": copy_gbs,
         "setup_s": {"tabulate": t_tab, "power_iteration_and_one_iter": t_setup},
-        "report": {"datafit0": rep.datafit0, "datafit": rep.datafit,
+        "with_final_fit": {"iters_per_s": args.steps / wall_ff, "ms_per_step": 1e3 * wall_ff / args.steps},
+        "report": {"datafit0": rep.datafit0, "datafit_final": rep_ff.datafit, "datafit_last_step": rep.datafit,
                    "gmap_ratio": rep.gmap_ratio},
         "cpu_baseline": None,
     }
@@ -920,7 +935,7 @@ def main() -> int:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             muv, rv, _ = ctof.reconstruct(kv, d, max_iter=args.steps, lam=lam, lipschitz=L,
-                                          timing=TIMING_STRIDE)
+                                          timing=TIMING_STRIDE, final_fit=False)
             torch.cuda.synchronize()
             wv = time.perf_counter() - t0
             variants[name] = {"iters_per_s": args.steps / wv, "ms_per_step": 1e3 * wv / args.steps,

@@ -344,6 +344,16 @@ ctof_status ctof_mux_normal(ctof_kernel k, const ctof_mux *mux, const void *m_de
  *                    device pointers playing mu_prev_dev's role per scan; k0
  *                    applies to every scan (scans frozen early in the
  *                    interrupted call resume from their frozen state).
+ *   skip_final_fit   0: after the last step the solver applies the forward
+ *                    model once more to report datafit at the final iterate
+ *                    (one extra contraction and measurement-side pass, about
+ *                    half an iteration's time).  1: no extra pass; datafit
+ *                    is then the data fit at the last step's extrapolated
+ *                    point y_K (the last history row's), and the iterates,
+ *                    history and gmap_ratio are unchanged, bit for bit.  A
+ *                    one-iteration call whose start was discarded
+ *                    (warm_start = 2) still computes it.  Other values:
+ *                    CTOF_EINVAL.
  */
 typedef struct {
   int32_t max_iter;
@@ -362,12 +372,14 @@ typedef struct {
   void *mu_prev_dev;
   int32_t k0;
   void *const *mu_prev_scans;
+  int32_t skip_final_fit;
 } ctof_solver_opts;
 
 /*
  * Report (host memory):
  *   iters       iterations run;  status  final ctof_status of the solve
  *   datafit0    1/2 ||A mu_0 - d||^2;  datafit  1/2 ||A mu_final - d||^2
+ *               (1/2 ||A y_K - d||^2 with opts.skip_final_fit)
  *   gmap_ratio  gradient-mapping ratio of the last iteration
  *   lipschitz, lambda   the L and lambda used;  lipschitz_a  L_A (0 if L given)
  *   gmap0       ||max(0, A^T d)||, the ratio's denominator

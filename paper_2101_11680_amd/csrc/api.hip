@@ -980,10 +980,14 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
     HIP_TRY(hipMemcpyAsync(opt->history_dev, E.hist(), (size_t)kept * 2 * sizeof(double),
                            hipMemcpyDeviceToDevice, st));
   // after all K steps the spectrum buffer holds that of mu_K (also after a
-  // fallback in a one-step call: mu = y = 0 and their spectrum recomputed)
-  if (ctof_status s = enqueue_final_fit(E, dd, mm, E.part() + (size_t)K * E.L.part_stride, scal + 3, done == K);
-      s != CTOF_OK)
-    return s;
+  // fallback in a one-step call: mu = y = 0 and their spectrum recomputed);
+  // a call that skips the final fit reports the last history row's instead
+  // (a one-step call that fell back has no kept row: it still computes it)
+  const bool final_fit = !opt->skip_final_fit || kept == 0;
+  if (final_fit)
+    if (ctof_status s = enqueue_final_fit(E, dd, mm, E.part() + (size_t)K * E.L.part_stride, scal + 3, done == K);
+        s != CTOF_OK)
+      return s;
   // scalars, first and last history rows and ||G(0)||^2, read back with one copy
   double pk[9];
   HIP_TRY(ctof::launch_pack_report(scal, E.hist(), kept, E.g0sq(), scal + 16, st));
@@ -1015,7 +1019,7 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
   rep->iters = done;
   rep->fista_k = k0 + kept;
   rep->datafit0 = h0[0];
-  rep->datafit = hs[3];
+  rep->datafit = final_fit ? hs[3] : hl[0];
   rep->gmap_ratio = hl[1];
   if (kept == 0) {
     // a one-iteration call that fell back returns the zero start itself,
@@ -1371,22 +1375,28 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
   }
   HIP_TRY(hipStreamSynchronize(st));
   if (ctof_status s = reduce_g0(); s != CTOF_OK) return s;
-  // reports: full history, final data fit per volume
+  // reports: full history, final data fit per volume (skipped on request,
+  // except in a one-step call with the fallback, where a volume that fell
+  // back has no kept history row)
+  const bool skip_fit = opt->skip_final_fit && !(K == 1 && opt->warm_start == 2);
   std::vector<std::vector<double>> hist(cls.size()), fit(cls.size()), g0(cls.size());
   for (size_t c = 0; c < cls.size(); ++c) {
     const ClassWs &L = cls[c].L;
     const int its = std::max(1, std::min(done, K));
     HIP_TRY(ctof::launch_history(E[c].part(), its, E[c].nvol, L.nblk_t, L.nblk_z, L.part_stride, cls[c].tau,
                                  E[c].g0sq(), E[c].hist(), st));
-    if (ctof_status s = enqueue_final_fit(E[c], dv[c].data(), mv[c].data(),
-                                          E[c].part() + (size_t)K * L.part_stride, E[c].scal() + 8);
-        s != CTOF_OK)
-      return s;
+    if (!skip_fit)
+      if (ctof_status s = enqueue_final_fit(E[c], dv[c].data(), mv[c].data(),
+                                            E[c].part() + (size_t)K * L.part_stride, E[c].scal() + 8);
+          s != CTOF_OK)
+        return s;
     hist[c].resize((size_t)its * E[c].nvol * 2);
     fit[c].resize(E[c].nvol);
     g0[c].resize(E[c].nvol);
     HIP_TRY(hipMemcpyAsync(hist[c].data(), E[c].hist(), hist[c].size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(fit[c].data(), E[c].scal() + 8, fit[c].size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    if (!skip_fit)
+      HIP_TRY(hipMemcpyAsync(fit[c].data(), E[c].scal() + 8, fit[c].size() * sizeof(double), hipMemcpyDeviceToHost,
+                             st));
     HIP_TRY(hipMemcpyAsync(g0[c].data(), E[c].g0sq(), g0[c].size() * sizeof(double), hipMemcpyDeviceToHost, st));
   }
   HIP_TRY(hipStreamSynchronize(st));
@@ -1402,7 +1412,8 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
       // the kept run of a restarted volume begins at its second row
       r.datafit0 = hist[c][((size_t)fell[c][v] * nv + v) * 2];
       r.gmap_ratio = hist[c][((size_t)(its - 1) * nv + v) * 2 + 1];
-      r.datafit = fit[c][v];
+      // (without the final fit: the data fit at the last step's extrapolated point)
+      r.datafit = skip_fit ? hist[c][((size_t)(its - 1) * nv + v) * 2] : fit[c][v];
       r.lipschitz = cls[c].lip;
       r.lambda = cls[c].lam;
       r.lipschitz_a = cls[c].lip_a;
@@ -1916,6 +1927,8 @@ ctof_status ctof_reconstruct(ctof_kernel k, const void *d_dev, void *mu_inout_de
   if (opts->lipschitz_scans || opts->lambda_scans || opts->mu_prev_scans)
     return set_error(CTOF_EINVAL, "lipschitz_scans / lambda_scans / mu_prev_scans are batched options");
   if (ctof_status e = check_resume(opts, opts->mu_prev_dev != nullptr); e != CTOF_OK) return e;
+  if (opts->skip_final_fit != 0 && opts->skip_final_fit != 1)
+    return set_error(CTOF_EINVAL, "skip_final_fit must be 0 or 1");
   if (opts->mu_prev_dev &&
       overlaps(opts->mu_prev_dev, mu_inout_dev, (size_t)k->dims.nz * k->dims.ny * k->dims.nx * elem_size(k->prec)))
     return set_error(CTOF_EINVAL, "mu_prev_dev overlaps mu_inout_dev");
@@ -2024,6 +2037,8 @@ ctof_status ctof_reconstruct_batched(int32_t nscan, const ctof_kernel *k, const 
       }
     if (opts->mu_prev_scans && !all_prev) return set_error(CTOF_EINVAL, "mu_prev_scans has a NULL entry");
     if (ctof_status e = check_resume(opts, all_prev); e != CTOF_OK) return e;
+    if (opts->skip_final_fit != 0 && opts->skip_final_fit != 1)
+      return set_error(CTOF_EINVAL, "skip_final_fit must be 0 or 1");
   }
   if ((opts->lipschitz_scans == nullptr) != (opts->lambda_scans == nullptr))
     return set_error(CTOF_EINVAL, "lipschitz_scans and lambda_scans go together");

@@ -74,7 +74,8 @@ class _SolverOpts(ctypes.Structure):
                 ("lambda_scans", ctypes.POINTER(ctypes.c_double)),
                 ("lambda_l1_z", ctypes.POINTER(ctypes.c_double)),
                 ("mux", ctypes.POINTER(_Mux)), ("mu_prev_dev", ctypes.c_void_p),
-                ("k0", ctypes.c_int32), ("mu_prev_scans", ctypes.POINTER(ctypes.c_void_p))]
+                ("k0", ctypes.c_int32), ("mu_prev_scans", ctypes.POINTER(ctypes.c_void_p)),
+                ("skip_final_fit", ctypes.c_int32)]
 
 
 class _Tuning(ctypes.Structure):
@@ -505,7 +506,7 @@ def reconstruct(k: Kernel, d, mu=None, max_iter: int = 200, lam: float = -1.0,
                 lipschitz: float = 0.0, power_iters: int = 50, rel_tol: float = 0.0,
                 check_every: int = 10, warm_start: bool = False, history: bool = False,
                 timing: int = 0, l1=None, mux: Optional[Mux] = None, mu_prev=None, k0: int = 0,
-                stream=None):
+                final_fit: bool = True, stream=None):
     """FISTA reconstruction; returns (mu, Report, history or None).  warm_start:
     0/False zero start, 1/True start from ``mu``, 2 start from ``mu`` with the
     zero-start fallback.  l1: per-layer L1 weights (nz numbers) or None.
@@ -515,7 +516,9 @@ def reconstruct(k: Kernel, d, mu=None, max_iter: int = 200, lam: float = -1.0,
     mu_prev, k0: resumption (a device tensor shaped like mu, in/out): with
     k0 >= 1 (and warm_start = 1) mu holds mu_k0 and mu_prev mu_{k0-1}; on
     return mu_prev holds the iterate before the final one, and the report's
-    fista_k is the k0 that resumes the run."""
+    fista_k is the k0 that resumes the run.  final_fit=False: no forward pass
+    after the last step; the report's datafit is then the one at the last
+    step's extrapolated point y_K."""
     torch = _torch()
     i = k.info
     if mux is None:
@@ -535,7 +538,8 @@ def reconstruct(k: Kernel, d, mu=None, max_iter: int = 200, lam: float = -1.0,
                        float(rel_tol), int(check_every), int(warm_start),
                        hist.data_ptr() if hist is not None else None, int(timing), None, None, l1a,
                        ctypes.pointer(mdesc) if mdesc is not None else None,
-                       mu_prev.data_ptr() if mu_prev is not None else None, int(k0), None)
+                       mu_prev.data_ptr() if mu_prev is not None else None, int(k0), None,
+                       0 if final_fit else 1)
     rep = _SolverReport()
     _, nb = k.workspace_bytes(max_iter)
     ws = k.workspace(nb, d.device, stream)
@@ -557,13 +561,14 @@ def _report(rep) -> Report:
 def reconstruct_batched(kernels, ds, mus=None, max_iter: int = 200, lam=-1.0, lipschitz=0.0,
                         power_iters: int = 50, rel_tol: float = 0.0, check_every: int = 10,
                         warm_start: bool = False, l1=None, mux: Optional[Mux] = None, mu_prevs=None,
-                        k0: int = 0, stream=None):
+                        k0: int = 0, final_fit: bool = True, stream=None):
     """FISTA for many scans at once; scans sharing a Kernel object form one
     shape class.  lam / lipschitz: one value for all scans or one per scan
     (both sequences, then every scan's pair is used as given).  warm_start as
     in reconstruct.  mux: one Mux for every scan, each ds[i] then holding
     scan i's multiplexed measurements.  mu_prevs, k0: resumption as in
-    reconstruct, one mu_prev tensor per scan.  Returns (list of mu, list of
+    reconstruct, one mu_prev tensor per scan.  final_fit as in reconstruct.
+    Returns (list of mu, list of
     Report)."""
     torch = _torch()
     n = len(ds)
@@ -603,11 +608,12 @@ def reconstruct_batched(kernels, ds, mus=None, max_iter: int = 200, lam=-1.0, li
         la = (ctypes.c_double * n)(*[float(x) for x in lipschitz])
         lb = (ctypes.c_double * n)(*[float(x) for x in lam])
         opts = _SolverOpts(int(max_iter), 0.0, 0.0, int(power_iters), float(rel_tol), int(check_every),
-                           int(warm_start), None, 0, la, lb, l1a, mptr_desc, None, int(k0), prev_arr)
+                           int(warm_start), None, 0, la, lb, l1a, mptr_desc, None, int(k0), prev_arr,
+                           0 if final_fit else 1)
     else:
         opts = _SolverOpts(int(max_iter), float(lam), float(lipschitz), int(power_iters),
                            float(rel_tol), int(check_every), int(warm_start), None, 0, None, None, l1a,
-                           mptr_desc, None, int(k0), prev_arr)
+                           mptr_desc, None, int(k0), prev_arr, 0 if final_fit else 1)
     reps = (_SolverReport * n)()
     _check(lib().ctof_reconstruct_batched(n, handles, dptr, mptr, ctypes.byref(opts), reps,
                                           ws.data_ptr(), ws.numel(), _stream_ptr(stream)))

@@ -247,6 +247,53 @@ def test_reconstruct_matches_oracle_fista(prec, fit_tol, mu_tol):
     assert abs(rep.datafit0 / hist_ref[0, 0] - 1) <= fit_tol
 
 
+@pytest.mark.parametrize("prec,fit_tol", [("fp64", 1e-10), ("fp32", 1e-4)])
+def test_skip_final_fit(prec, fit_tol):
+    """Without the final forward pass the iterates, history and ratio are the
+    same bit for bit, and the reported data fit is the one at the last step's
+    extrapolated point y_K, checked against the oracle's history; the batched
+    solver reports the same value."""
+    c = ct()
+    g, F, d = _tiny_problem(4)
+    LA = osolver.power_iteration(F, 50)
+    L, lam = osolver.step_constants(LA)
+    iters = 30
+    _, hist_ref = osolver.fista(F, d, L, lam, iters)
+    p = c.PRECISIONS[prec]
+    dt = torch.float64 if p == c.FP64 else torch.float32
+    k = gpu_kernel(g, p)
+    dd = torch.tensor(d, dtype=dt, device="cuda")
+    mu1, rep1, h1 = c.reconstruct(k, dd, max_iter=iters, lam=lam, lipschitz=L, history=True)
+    mu2, rep2, h2 = c.reconstruct(k, dd, max_iter=iters, lam=lam, lipschitz=L, history=True, final_fit=False)
+    assert torch.equal(mu1, mu2) and torch.equal(h1, h2)
+    assert rep1.gmap_ratio == rep2.gmap_ratio and rep1.datafit0 == rep2.datafit0
+    assert rep2.datafit == h2[-1, 0].item()
+    assert abs(rep2.datafit / hist_ref[-1, 0] - 1) <= fit_tol
+    # the final fit is at mu_K, below the extrapolated point's near convergence
+    assert rep1.datafit != rep2.datafit
+    mus, reps = c.reconstruct_batched([k], [dd], max_iter=iters, lam=lam, lipschitz=L, final_fit=False)
+    assert abs(reps[0].datafit / rep2.datafit - 1) <= fit_tol
+    _, reps1 = c.reconstruct_batched([k], [dd], max_iter=iters, lam=lam, lipschitz=L)
+    assert abs(reps1[0].datafit / rep1.datafit - 1) <= fit_tol
+
+
+def test_skip_final_fit_rejects_other_values():
+    import ctypes
+    c = ct()
+    g, F, d = _tiny_problem(4)
+    k = gpu_kernel(g, c.FP64)
+    dd = torch.tensor(d, device="cuda")
+    mu = torch.zeros((g.nz, g.ny, g.nx), dtype=torch.float64, device="cuda")
+    _, nb = k.workspace_bytes(3)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    opts = c._SolverOpts(3, 1e-3, 1.0, 50, 0.0, 10, 0, None, 0, None, None, None, None, None, 0, None, 2)
+    rep = c._SolverReport()
+    st = c.lib().ctof_reconstruct(k.handle, dd.data_ptr(), mu.data_ptr(), ctypes.byref(opts), ctypes.byref(rep),
+                                  ws.data_ptr(), ws.numel(), None)
+    assert c.STATUS[st] == "CTOF_EINVAL"
+    assert b"skip_final_fit" in c.lib().ctof_last_error()
+
+
 def test_reconstruct_rel_tol_stops_early():
     c = ct()
     g, F, d = _tiny_problem(2)
