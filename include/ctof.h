@@ -130,6 +130,14 @@ ctof_status ctof_kernel_tabulate_quadrant(const ctof_geometry *geom, double *qua
                                           size_t quad_bytes, hipStream_t stream);
 
 /*
+ * The same test hook without a size argument: quad_dev must hold
+ * nz * nt * n * n doubles (n = max(nx, ny)), the size the geometry fixes;
+ * the caller guarantees it (no other check is possible).  Errors as
+ * ctof_kernel_tabulate_quadrant.
+ */
+ctof_status ctof_kernel_tabulate_fp64_quadrant(const ctof_geometry *geom, double *quad_dev, hipStream_t stream);
+
+/*
  * Fluorescence mode (section "Materials and Methods": the optical
  * properties of the excitation and the emission wavelength, and the
  * fluorescence lifetime).  The kernel becomes the sensitivity of the

@@ -1729,6 +1729,14 @@ ctof_status ctof_kernel_tabulate_quadrant(const ctof_geometry *geom, double *qua
   return ctof_kernel_tabulate_quadrant_ex(geom, nullptr, quad_dev, quad_bytes, stream);
 }
 
+ctof_status ctof_kernel_tabulate_fp64_quadrant(const ctof_geometry *geom, double *quad_dev, hipStream_t stream) {
+  if (!geom) return set_error(CTOF_EINVAL, "geometry is NULL");
+  // the buffer size the geometry fixes (geometry errors are reported below)
+  const size_t n = (size_t)std::max(std::max(geom->nx, geom->ny), 0);
+  const size_t need = (size_t)std::max(geom->nz, 0) * (size_t)std::max(geom->nt, 0) * n * n * sizeof(double);
+  return ctof_kernel_tabulate_quadrant_ex(geom, nullptr, quad_dev, need, stream);
+}
+
 ctof_status ctof_kernel_tabulate_quadrant_ex(const ctof_geometry *geom, const ctof_fluorescence *fl, double *quad_dev,
                                              size_t quad_bytes, hipStream_t stream) {
   ctof::TabGeom tg;

@@ -23,6 +23,7 @@ STATUS = {0: "CTOF_OK", -1: "CTOF_EINVAL", -2: "CTOF_ENOMEM", -3: "CTOF_EHIP",
           -4: "CTOF_ENONFINITE", -5: "CTOF_EUNSUPPORTED"}
 
 EXPORTS = ("ctof_kernel_bytes", "ctof_kernel_tabulate", "ctof_kernel_tabulate_quadrant",
+           "ctof_kernel_tabulate_fp64_quadrant",
            "ctof_kernel_tabulate_ex", "ctof_kernel_tabulate_quadrant_ex",
            "ctof_kernel_free", "ctof_kernel_info", "ctof_kernel_grid", "ctof_kernel_band_bytes",
            "ctof_kernel_set_band", "ctof_workspace_bytes", "ctof_forward",
@@ -123,6 +124,7 @@ def lib() -> ctypes.CDLL:
         L.ctof_kernel_bytes.argtypes = [gp, ctypes.c_int, ctypes.POINTER(sz), ctypes.POINTER(sz)]
         L.ctof_kernel_tabulate.argtypes = [gp, ctypes.c_int, vp, sz, vp, sz, vp, ctypes.POINTER(vp)]
         L.ctof_kernel_tabulate_quadrant.argtypes = [gp, vp, sz, vp]
+        L.ctof_kernel_tabulate_fp64_quadrant.argtypes = [gp, vp, vp]
         fp = ctypes.POINTER(_Fluorescence)
         L.ctof_kernel_tabulate_ex.argtypes = [gp, fp, ctypes.c_int, vp, sz, vp, sz, vp, ctypes.POINTER(vp)]
         L.ctof_kernel_tabulate_quadrant_ex.argtypes = [gp, fp, vp, sz, vp]

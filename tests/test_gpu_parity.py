@@ -78,6 +78,23 @@ def test_quadrant_fp64_matches_oracle(g):
     assert np.array_equal(q, np.swapaxes(q, 2, 3))   # exact dy <-> dx symmetry
 
 
+def test_fp64_quadrant_entry_equals_sized_one():
+    """The unsized entry point (the buffer size fixed by the geometry) gives
+    the sized one's values bit for bit, here on a non-square grid."""
+    import ctypes
+    c = ct()
+    g = geom(13, 5, 40, pitch=0.7, zr=(1.5, 9.0), dt=30.0, mus=0.9)
+    ref = c.tabulate_quadrant(g)
+    gs, _z = c._geometry(g)
+    out = torch.full_like(ref, float("nan"))
+    st = c.lib().ctof_kernel_tabulate_fp64_quadrant(ctypes.byref(gs), out.data_ptr(), None)
+    assert c.STATUS[st] == "CTOF_OK"
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    st = c.lib().ctof_kernel_tabulate_fp64_quadrant(ctypes.byref(gs), None, None)
+    assert c.STATUS[st] == "CTOF_EINVAL"
+
+
 def test_quadrant_mid_near_source_floor():
     g = workloads.geometry_for("mid")
     q = to_np(ct().tabulate_quadrant(g))
