@@ -506,14 +506,20 @@ ctof_status ctof_kernel_set_contract_parts(ctof_kernel k, int32_t fwd_parts, int
 ctof_status ctof_kernel_get_contract_parts(ctof_kernel k, int32_t *fwd_parts, int32_t *adj_parts);
 /*
  * Launch-shape tuner for a class of nvol volumes sharing the handle (the
- * batching form's per-class choice): times `iters` operator passes (the
- * eight launches of an iteration; the fastest of three timings after a
- * warm-up) for each legal FFT planes-per-block pair
- * with the contractions at their rule, then, with the fastest pair, the row
- * passes' planes per block, then the forward contraction's blocks per
- * matrix 1, 2, 4, 8, then the adjoint's, keeps the fastest of each in the
- * handle (ctof_kernel_set_tuning, ctof_kernel_set_row_tuning,
- * ctof_kernel_set_contract_parts) and reports every timing.  The FFT size
+ * batching form's per-class choice): times `iters` operator passes (1 to
+ * 1000; the eight launches of an iteration) with events around their four
+ * stages (forward contraction, bin-side passes, adjoint contraction,
+ * layer-side passes; each the fastest of three timings after a warm-up)
+ * for each legal FFT planes-per-block pair with the contractions at their
+ * rule, and keeps the bin side's value that gave the fastest bin-side
+ * passes and the layer side's that gave the fastest layer-side ones; then
+ * the row passes' planes per block alike; then the forward contraction's
+ * blocks per matrix 1, 2, 4, 8 by the time of that contraction and the
+ * bin-side passes, then the adjoint's by the time of the adjoint and the
+ * layer-side passes (which add its partial spectra).  The choices go into
+ * the handle (ctof_kernel_set_tuning, ctof_kernel_set_row_tuning,
+ * ctof_kernel_set_contract_parts); every timing is reported as the whole
+ * iteration (the sum of its stages).  The FFT size
  * is fixed at tabulation (the kernel spectrum depends on it) to the
  * smallest supported length >= 2n - 1, which is never slower than a longer
  * one: it shrinks the spectrum and every pass.  Choices change

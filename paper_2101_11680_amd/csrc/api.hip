@@ -1438,53 +1438,69 @@ template <typename T>
 ctof_status run_tune(ctof_kernel_s *k, int nvol, int iters, void *ws, hipStream_t st, ctof_tuning *out) {
   const int cand[4][2] = {{16, 16}, {32, 16}, {16, 32}, {32, 32}};
   const int parts[4] = {1, 2, 4, 8};
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  HIP_TRY(hipEventCreate(&e0));
+  // events at the stage boundaries of every timed iteration: before the
+  // forward contraction, the bin-side passes, the adjoint contraction and the
+  // layer-side passes, and one at the end
+  std::vector<hipEvent_t> evs((size_t)4 * iters + 1, nullptr);
   struct Ev {
-    hipEvent_t *a, *b;
+    std::vector<hipEvent_t> *v;
     ~Ev() {
-      if (*a) (void)hipEventDestroy(*a);
-      if (*b) (void)hipEventDestroy(*b);
+      for (hipEvent_t e : *v)
+        if (e) (void)hipEventDestroy(e);
     }
-  } ev_guard{&e0, &e1};
-  HIP_TRY(hipEventCreate(&e1));
-  // milliseconds per iteration of the handle's current launch shape: the
-  // fastest of three timed passes after a warm-up pass (< 0: error)
-  auto time_shape = [&](float *ms) -> ctof_status {
+  } ev_guard{&evs};
+  for (auto &e : evs) HIP_TRY(hipEventCreate(&e));
+  // milliseconds per iteration of each stage of the handle's current launch
+  // shape, [0] forward contraction, [1] bin-side passes, [2] adjoint
+  // contraction, [3] layer-side passes: each the fastest of three timed
+  // passes after a warm-up pass.  A choice is judged by the stages it
+  // changes, whose times are far less noisy than the whole iteration's.
+  auto time_stages = [&](float (&ms)[4]) -> ctof_status {
     const Engine<T> E = engine<T>(k, nvol, ws, 1, st);
     HIP_TRY(ctof::launch_fill_zero(E.ws, E.L.op_total, st));
-    float best = 1e30f;
+    float best[4] = {1e30f, 1e30f, 1e30f, 1e30f};
     for (int rep = 0; rep < 4; ++rep) {
-      HIP_TRY(hipEventRecord(e0, st));
       for (int i = 0; i < iters; ++i) {
         const ctof::RowArgs a = E.row(ctof::ROW_PASS, true);
         const ctof::RowArgs b = E.row(ctof::ROW_PASS, false);
+        HIP_TRY(hipEventRecord(evs[(size_t)4 * i], st));
         HIP_TRY(E.contract(false));
+        HIP_TRY(hipEventRecord(evs[(size_t)4 * i + 1], st));
         HIP_TRY(E.col_t(true));
         HIP_TRY(E.run_row(a));
         HIP_TRY(E.col_t(false));
+        HIP_TRY(hipEventRecord(evs[(size_t)4 * i + 2], st));
         HIP_TRY(E.contract(true));
+        HIP_TRY(hipEventRecord(evs[(size_t)4 * i + 3], st));
         HIP_TRY(E.col_z(true));
         HIP_TRY(E.run_row(b));
         HIP_TRY(E.col_z(false));
       }
-      HIP_TRY(hipEventRecord(e1, st));
-      HIP_TRY(hipEventSynchronize(e1));
-      float t = 0.f;
-      HIP_TRY(hipEventElapsedTime(&t, e0, e1));
-      if (rep > 0) best = std::min(best, t);
+      HIP_TRY(hipEventRecord(evs[(size_t)4 * iters], st));
+      HIP_TRY(hipEventSynchronize(evs[(size_t)4 * iters]));
+      float acc[4] = {0.f, 0.f, 0.f, 0.f};
+      for (int i = 0; i < iters; ++i)
+        for (int j = 0; j < 4; ++j) {
+          float t = 0.f;
+          HIP_TRY(hipEventElapsedTime(&t, evs[(size_t)4 * i + j], evs[(size_t)4 * i + j + 1]));
+          acc[j] += t;
+        }
+      if (rep > 0)
+        for (int j = 0; j < 4; ++j) best[j] = std::min(best[j], acc[j]);
     }
-    *ms = best / std::max(iters, 1);
+    for (int j = 0; j < 4; ++j) ms[j] = best[j] / std::max(iters, 1);
     return CTOF_OK;
   };
+  auto total = [](const float (&ms)[4]) { return ms[0] + ms[1] + ms[2] + ms[3]; };
   std::memset(out, 0, sizeof(*out));
-  // 1. FFT planes per block, row passes alike, contractions at the built-in rule
+  // 1. FFT planes per block, row passes alike, contractions at the built-in
+  // rule: the bin side's value by the bin-side passes' time, the layer
+  // side's by theirs
   k->fwd_parts = 0;
   k->adj_parts = 0;
   k->rb_t = 0;
   k->rb_z = 0;
-  float best = 1e30f;
-  int bi = 0;
+  float bt[2] = {1e30f, 1e30f}, bz[2] = {1e30f, 1e30f};  // [0]: 16 planes, [1]: 32
   const bool f64 = k->prec == CTOF_FP64;
   for (int c = 0; c < 4; ++c) {
     k->bb_t = cand[c][0];
@@ -1496,24 +1512,23 @@ ctof_status run_tune(ctof_kernel_s *k, int nvol, int iters, void *ws, hipStream_
       out->ms_bb[c] = -1.f;
       continue;
     }
-    float ms = 0.f;
-    if (ctof_status s = time_shape(&ms); s != CTOF_OK) return s;
-    out->ms_bb[c] = ms;
-    if (ms < best) {
-      best = ms;
-      bi = c;
-    }
+    float ms[4];
+    if (ctof_status s = time_stages(ms); s != CTOF_OK) return s;
+    out->ms_bb[c] = total(ms);
+    float &t = bt[cand[c][0] == 32], &z = bz[cand[c][1] == 32];
+    t = std::min(t, ms[1]);
+    z = std::min(z, ms[3]);
   }
-  k->bb_t = cand[bi][0];
-  k->bb_z = cand[bi][1];
+  k->bb_t = bt[1] < bt[0] ? 32 : 16;
+  k->bb_z = bz[1] < bz[0] ? 32 : 16;
   // 2. the row passes' planes per block: the column passes' or 64 on the
   // bin side, the column passes', 16 or 64 on the layer side (pairs whose
   // effective values repeat an earlier pair's are skipped; the first repeats
-  // the choice above)
+  // the choice above), each side by its own passes' time
   const int rcand[6][2] = {{0, 0}, {64, 0}, {0, 16}, {64, 16}, {0, 64}, {64, 64}};
   {
-    float bestr = 1e30f;
-    int ri = 0;
+    int rt = 0, rz = 0;
+    float bestt = 1e30f, bestz = 1e30f;
     int seen[6][2];
     for (int c = 0; c < 6; ++c) {
       k->rb_t = rcand[c][0];
@@ -1527,19 +1542,25 @@ ctof_status run_tune(ctof_kernel_s *k, int nvol, int iters, void *ws, hipStream_
         out->ms_rb[c] = -1.f;
         continue;
       }
-      float ms = 0.f;
-      if (ctof_status s = time_shape(&ms); s != CTOF_OK) return s;
-      out->ms_rb[c] = ms;
-      if (ms < bestr) {
-        bestr = ms;
-        ri = c;
+      float ms[4];
+      if (ctof_status s = time_stages(ms); s != CTOF_OK) return s;
+      out->ms_rb[c] = total(ms);
+      if (ms[1] < bestt) {
+        bestt = ms[1];
+        rt = rcand[c][0];
+      }
+      if (ms[3] < bestz) {
+        bestz = ms[3];
+        rz = rcand[c][1];
       }
     }
-    k->rb_t = rcand[ri][0];
-    k->rb_z = rcand[ri][1];
+    k->rb_t = rt;
+    k->rb_z = rz;
   }
-  // 3. forward, then 4. adjoint blocks per matrix (values that clamp to one
-  // already timed are skipped)
+  // 3. forward, then 4. adjoint blocks per matrix, each by the time of its
+  // contraction and the passes after it (the adjoint's partial spectra are
+  // added by the layer-side inverse column pass); values that clamp to one
+  // already timed are skipped
   for (int dir = 0; dir < 2; ++dir) {
     float *row = dir == 0 ? out->ms_fwd : out->ms_adj;
     int chosen = 0, seen[4] = {0, 0, 0, 0};
@@ -1555,11 +1576,12 @@ ctof_status run_tune(ctof_kernel_s *k, int nvol, int iters, void *ws, hipStream_
         row[q] = -1.f;
         continue;
       }
-      float ms = 0.f;
-      if (ctof_status s = time_shape(&ms); s != CTOF_OK) return s;
-      row[q] = ms;
-      if (ms < bestp) {
-        bestp = ms;
+      float ms[4];
+      if (ctof_status s = time_stages(ms); s != CTOF_OK) return s;
+      row[q] = total(ms);
+      const float judged = dir == 0 ? ms[0] + ms[1] : ms[2] + ms[3];
+      if (judged < bestp) {
+        bestp = judged;
         chosen = parts[q];
       }
     }
@@ -2148,7 +2170,7 @@ ctof_status ctof_tune(ctof_kernel k, int32_t nvol, int32_t iters, void *ws_dev, 
                       hipStream_t stream, ctof_tuning *out) {
   if (ctof_status s = check_kernel(k); s != CTOF_OK) return s;
   if (nvol < 1 || nvol > ctof::kMaxVol) return set_error(CTOF_EINVAL, "nvol must be in [1, %d]", ctof::kMaxVol);
-  if (iters < 1) return set_error(CTOF_EINVAL, "iters must be >= 1");
+  if (iters < 1 || iters > 1000) return set_error(CTOF_EINVAL, "iters must be in [1, 1000]");
   if (!ws_dev || !out) return set_error(CTOF_EINVAL, "workspace or result is NULL");
   const size_t need = tune_ws_bytes(k, nvol);
   if (ws_bytes < need) return set_error(CTOF_ENOMEM, "workspace %zu < %zu bytes", ws_bytes, need);

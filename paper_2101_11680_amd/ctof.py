@@ -704,13 +704,14 @@ def get_tuning(k: Kernel) -> tuple:
 def tune(k: Kernel, nvol: int = 1, iters: int = 5, cache: Optional[str] = None, stream=None) -> dict:
     """Pick a handle's launch shape for a class of `nvol` volumes by timing
     (ctof_tune: FFT planes per block, the row passes' planes per block, then
-    the contractions' blocks per matrix), with a JSON cache.
+    the contractions' blocks per matrix, each judged by the stages it
+    changes), with a JSON cache.
 
     The cache (default: $CTOF_TUNE_CACHE, else no cache) maps
     "arch|grid|nz|nt|precision|nvol" to the choice and its timings.  Returns
     {"bb": (bb_t, bb_z), "rb": (rb_t, rb_z), "parts": (fwd, adj), "ms_bb": [4],
-    "ms_rb": [4], "ms_fwd": [4], "ms_adj": [4], "cached": bool} (timings None
-    when taken from the cache).
+    "ms_rb": [6], "ms_fwd": [4], "ms_adj": [4], "cached": bool} (timings per
+    whole iteration; None when taken from the cache).
     """
     import json
     torch = _torch()
