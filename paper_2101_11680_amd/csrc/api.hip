@@ -201,7 +201,7 @@ TabWs tab_ws(const ctof::Dims &d) {
   const size_t per = (size_t)d.nt * d.nz;
   const size_t q = std::max((size_t)d.n * d.n, (size_t)(d.h + 1) * (d.h + 1)) * per * 8;
   const size_t t1 = (size_t)d.n * (d.h + 1) * per * 8;
-  const size_t cm = (size_t)(d.h + 1) * d.n * 8;
+  const size_t cm = ctof::cosine_matrix_elems(d.n, d.p) * 8;
   w.q = 0;
   w.t1 = ctof::round_up(q, 256);
   w.cm = w.t1 + ctof::round_up(t1, 256);
@@ -1725,12 +1725,11 @@ ctof_status ctof_kernel_tabulate_ex(const ctof_geometry *geom, const ctof_fluore
   HIP_TRY(ctof::launch_tab_values(tg, zs, gl, Q, (size_t)d.n * per, per, 1, (size_t)d.nz, stream));
   HIP_TRY(ctof::launch_cosine_matrix(d.n, d.p, C, stream));
   // T1[dy][b][k][z] = sum_dx C[b][dx] Q[dy][dx][k][z]
-  HIP_TRY(ctof::launch_gemm_f64(d.h + 1, (long long)per, d.n, C, d.n, 0, Q, (long long)per, (long long)(d.n * per),
-                                T1, (long long)per, (long long)((d.h + 1) * per), d.n, stream));
+  HIP_TRY(ctof::launch_gemm_f64(d.h + 1, (long long)per, d.n, C, Q, (long long)per, (long long)(d.n * per), T1,
+                                (long long)per, (long long)((d.h + 1) * per), d.n, stream));
   // K64[a][b][k][z] = sum_dy C[a][dy] T1[dy][b][k][z]   (written over Q)
   const long long N2 = (long long)(d.h + 1) * (long long)per;
-  HIP_TRY(ctof::launch_gemm_f64(d.h + 1, N2, d.n, C, d.n, 0, T1, N2, 0, Q,
-                                N2, 0, 1, stream));
+  HIP_TRY(ctof::launch_gemm_f64(d.h + 1, N2, d.n, C, T1, N2, 0, Q, N2, 0, 1, stream));
   HIP_TRY(ctof::launch_pack(d, prec, Q, khat_dev, lay, 1.0 / ((double)d.p * (double)d.p), stream));
   HIP_TRY(hipStreamSynchronize(stream));
   ctof_kernel_s *k = new (std::nothrow) ctof_kernel_s;

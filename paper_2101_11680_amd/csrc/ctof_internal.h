@@ -107,11 +107,14 @@ namespace ctof {
 hipError_t launch_tab_values(const TabGeom &g, const LayerDepths &z, const GaussLegendre16 &gl,
                              double *out, size_t s_dy, size_t s_dx, size_t s_z, size_t s_t,
                              hipStream_t st);
+// The (p/2 + 1) x n cosine matrix of the kernel spectrum in the operand
+// order of launch_gemm_f64 (cosine_matrix_elems doubles).
+size_t cosine_matrix_elems(int n, int p);
 hipError_t launch_cosine_matrix(int n, int p, double *C, hipStream_t st);
-// C[M][N] = A[M][K] * B[K][N] (row-major, FP64), batched with strides.
-hipError_t launch_gemm_f64(int M, long long N, int K, const double *A, int lda, long long sA,
-                           const double *B, long long ldb, long long sB, double *C, long long ldc,
-                           long long sC, int batch, hipStream_t st);
+// C[M][N] = A[M][K] * B[K][N] (FP64 on the matrix cores; A in the operand
+// order of launch_cosine_matrix, B and C row-major), batched with strides.
+hipError_t launch_gemm_f64(int M, long long N, int K, const double *Af, const double *B, long long ldb,
+                           long long sB, double *C, long long ldc, long long sC, int batch, hipStream_t st);
 hipError_t launch_pack(const Dims &d, ctof_precision prec, const double *k64, void *khat,
                        const KhatLayout &lay, double scale, hipStream_t st);
 

@@ -160,68 +160,87 @@ tab_values_kernel(TabGeom g, LayerDepths zs, GaussLegendre16 gl, double *__restr
   }
 }
 
-// C[a][d] = w_d cos(2 pi a d / p), a in [0, h], d in [0, n).
+// The cosine matrix C[a][d] = w_d cos(2 pi a d / p), a in [0, h], d in
+// [0, n) (w_0 = 1, else 2), written in the GEMM's operand order: entry
+// (t ks + s) 64 + lane holds C[16 t + lane % 16][4 s + lane / 16], ks =
+// ceil(n / 4) steps of depth 4 per tile of 16 rows, zero past h and n.
 __global__ void cosine_kernel(int n, int p, double *__restrict__ C) {
   const int h = p / 2;
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (h + 1) * n) return;
-  const int a = idx / n;
-  const int d = idx % n;
-  const long long m = (2LL * a * d) % (2LL * p);
-  const double w = (d == 0) ? 1.0 : 2.0;
-  C[idx] = w * cospi((double)m / (double)p);
+  const int ks = (n + 3) / 4;
+  const long long total = (long long)((h + 1 + 15) / 16) * ks * 64;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  const int lane = (int)(idx & 63);
+  const long long ts = idx >> 6;
+  const int t = (int)(ts / ks), st = (int)(ts % ks);
+  const int a = 16 * t + (lane & 15);
+  const int d = 4 * st + (lane >> 4);
+  double v = 0.0;
+  if (a <= h && d < n) {
+    const long long m = (2LL * a * d) % (2LL * p);
+    v = ((d == 0) ? 1.0 : 2.0) * cospi((double)m / (double)p);
+  }
+  C[idx] = v;
 }
 
-// Tiled FP64 GEMM, C = A * B, 32 x 64 output tile per block of 256 threads.
-constexpr int GBM = 32, GBN = 64, GBK = 16;
+// FP64 GEMM on the matrix cores, C = A B: A [M][K] in the operand order of
+// cosine_kernel (Af), B [K][N] row-major (row stride ldb), C [M][N]
+// row-major (ldc), batch z offset by sB and sC.  A wave owns 16 columns of
+// C and a group of up to GMT row tiles of 16 (the cosine transform's M =
+// P/2 + 1 rows fit one group up to P = 286): per 4-deep step of K it loads
+// one B fragment (4 rows x 16 columns, the streamed operand, read once per
+// group) and one A fragment per row tile (512 contiguous bytes; A is at most
+// a few MB and stays in the caches), and issues one 16x16x4 FP64 MFMA per
+// row tile; the next step's operands are loaded before the current step's
+// products.  Operand lanes: A row i = lane % 16 and B column j = lane % 16,
+// both at depth lane / 16; the result item r of lane group g is row 4r + g
+// of the tile.
+typedef double gemm_v4d __attribute__((ext_vector_type(4)));
+constexpr int GMT = 9;
 
 __global__ void __launch_bounds__(256)
-gemm_f64_kernel(int M, long long N, int K, const double *__restrict__ A, int lda, long long sA,
-                const double *__restrict__ B, long long ldb, long long sB, double *__restrict__ C,
-                long long ldc, long long sC) {
-  __shared__ double As[GBK][GBM + 1];
-  __shared__ double Bs[GBK][GBN];
-  const int tid = threadIdx.x;
-  const int tx = tid % 16, ty = tid / 16;
-  const long long n0 = (long long)blockIdx.x * GBN;
-  const int m0 = blockIdx.y * GBM;
-  A += sA * blockIdx.z;
+gemm_f64_kernel(int M, long long N, int K, const double *__restrict__ Af, const double *__restrict__ B,
+                long long ldb, long long sB, double *__restrict__ C, long long ldc, long long sC) {
+  const int l = threadIdx.x & 63;
+  const int c = l & 15, g = l >> 4;
+  const long long col = ((long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16 + c;
+  const int mt0 = blockIdx.y * GMT;                     // first row tile of the group
+  const int nmt = min(GMT, (M + 15) / 16 - mt0);        // row tiles in the group
+  const int ks = (K + 3) / 4;
   B += sB * blockIdx.z;
   C += sC * blockIdx.z;
-  double acc[2][4] = {};
-  for (int k0 = 0; k0 < K; k0 += GBK) {
-    for (int e = tid; e < GBM * GBK; e += 256) {
-      const int mm = e / GBK, kk = e % GBK;
-      const int gm = m0 + mm, gk = k0 + kk;
-      As[kk][mm] = (gm < M && gk < K) ? A[(long long)gm * lda + gk] : 0.0;
-    }
-    for (int e = tid; e < GBK * GBN; e += 256) {
-      const int kk = e / GBN, nn = e % GBN;
-      const int gk = k0 + kk;
-      const long long gn = n0 + nn;
-      Bs[kk][nn] = (gk < K && gn < N) ? B[(long long)gk * ldb + gn] : 0.0;
-    }
-    __syncthreads();
+  const bool con = col < N;
+  gemm_v4d acc[GMT];
 #pragma unroll
-    for (int kk = 0; kk < GBK; ++kk) {
-      const double a0 = As[kk][ty * 2], a1 = As[kk][ty * 2 + 1];
+  for (int t = 0; t < GMT; ++t) acc[t] = {0.0, 0.0, 0.0, 0.0};
+  // operands of step k0 + 4 are loaded before the products of step k0
+  auto load = [&](int k0, double &b, double (&a)[GMT]) {
+    const int k = k0 + g;
+    b = (con && k < K) ? B[(long long)k * ldb + col] : 0.0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const double b = Bs[kk][tx + 16 * j];
-        acc[0][j] = fma(a0, b, acc[0][j]);
-        acc[1][j] = fma(a1, b, acc[1][j]);
-      }
-    }
-    __syncthreads();
+    for (int t = 0; t < GMT; ++t)
+      a[t] = t < nmt ? Af[((size_t)(mt0 + t) * ks + k0 / 4) * 64 + l] : 0.0;
+  };
+  double b0, a0[GMT], b1, a1[GMT];
+  load(0, b0, a0);
+  for (int k0 = 0; k0 < K; k0 += 8) {
+    if (k0 + 4 < K) load(k0 + 4, b1, a1);
+#pragma unroll
+    for (int t = 0; t < GMT; ++t)
+      if (t < nmt) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[t], b0, acc[t], 0, 0, 0);
+    if (k0 + 4 >= K) break;
+    if (k0 + 8 < K) load(k0 + 8, b0, a0);
+#pragma unroll
+    for (int t = 0; t < GMT; ++t)
+      if (t < nmt) acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[t], b1, acc[t], 0, 0, 0);
   }
+  if (!con) return;
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const int gm = m0 + ty * 2 + i;
-    if (gm >= M) continue;
+  for (int t = 0; t < GMT; ++t) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const long long gn = n0 + tx + 16 * j;
-      if (gn < N) C[(long long)gm * ldc + gn] = acc[i][j];
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * (mt0 + t) + 4 * r + g;
+      if (t < nmt && row < M) C[(long long)row * ldc + col] = acc[t][r];
     }
   }
 }
@@ -304,18 +323,20 @@ hipError_t launch_tab_values(const TabGeom &g, const LayerDepths &z, const Gauss
   return hipGetLastError();
 }
 
+size_t cosine_matrix_elems(int n, int p) { return (size_t)((p / 2 + 1 + 15) / 16) * ((n + 3) / 4) * 64; }
+
 hipError_t launch_cosine_matrix(int n, int p, double *C, hipStream_t st) {
-  const int total = (p / 2 + 1) * n;
-  hipLaunchKernelGGL(cosine_kernel, dim3((total + 255) / 256), dim3(256), 0, st, n, p, C);
+  const size_t total = cosine_matrix_elems(n, p);
+  hipLaunchKernelGGL(cosine_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, n, p, C);
   return hipGetLastError();
 }
 
-hipError_t launch_gemm_f64(int M, long long N, int K, const double *A, int lda, long long sA,
-                           const double *B, long long ldb, long long sB, double *C, long long ldc,
-                           long long sC, int batch, hipStream_t st) {
-  dim3 grid((unsigned)((N + GBN - 1) / GBN), (unsigned)((M + GBM - 1) / GBM), (unsigned)batch);
-  hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(256), 0, st, M, N, K, A, lda, sA, B, ldb, sB, C,
-                     ldc, sC);
+hipError_t launch_gemm_f64(int M, long long N, int K, const double *Af, const double *B, long long ldb,
+                           long long sB, double *C, long long ldc, long long sC, int batch, hipStream_t st) {
+  // 64 columns (four waves of 16) per block; one block row per group of row tiles
+  const int groups = ((M + 15) / 16 + GMT - 1) / GMT;
+  dim3 grid((unsigned)((N + 63) / 64), (unsigned)groups, (unsigned)batch);
+  hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(256), 0, st, M, N, K, Af, B, ldb, sB, C, ldc, sC);
   return hipGetLastError();
 }
 
