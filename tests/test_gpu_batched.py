@@ -155,6 +155,24 @@ def test_tuner_choices_keep_results_and_cache(tmp_path):
         assert rel_l2(to_np(mu), ref) <= 1e-5
 
 
+def test_tuner_fp64_handle_keeps_oracle_parity():
+    # the tuner on an FP64 handle (its own instantiation): every stage is
+    # timed, the choice is one of the legal shapes, and the solve with it
+    # still matches the oracle to the FP64 bar
+    from paper_2101_11680_amd import ctof as c
+    k = c.tabulate(GB, c.FP64)
+    dn, F = _data(GB, 3)
+    d = torch.tensor(dn, device="cuda")
+    _, rep0, _ = c.reconstruct(k, d, max_iter=1)
+    t = c.tune(k, nvol=2, iters=2)
+    assert t["bb"][0] in (16, 32) and t["bb"][1] in (16, 32)
+    assert all(x > 0 or x == -1 for x in t["ms_bb"] + t["ms_rb"] + t["ms_fwd"] + t["ms_adj"])
+    mu, _, _ = c.reconstruct(k, d, max_iter=25, lam=rep0.lam, lipschitz=rep0.lipschitz)
+    ref = osolver.fista(F, dn, rep0.lipschitz, rep0.lam, 25)[0]
+    assert rel_l2(to_np(mu), ref) <= 1e-10
+    assert c.STATUS[c.lib().ctof_tune(k.handle, 1, 1001, None, 0, None, None)] == "CTOF_EINVAL"
+
+
 @pytest.mark.parametrize("nt", [512, 384, 320])
 def test_split_forward_blocks_single_and_batched(nt):
     # the FP32 forward gives each matrix to up to four blocks of t tiles
