@@ -194,14 +194,23 @@ __device__ __forceinline__ void dft_reg(T (&xr)[R], T (&xi)[R]) {
   }
 }
 
-// twc[m] = cos(2 pi m / P), tws[m] = sin(2 pi m / P), m < P.
+// twc[m] = cos(2 pi m / P), tws[m] = sin(2 pi m / P), m < P.  FP32 tables
+// come from the FP32 sincospi (about one unit in the last place), FP64
+// tables from the FP64 one.
 template <typename T, int P>
 __device__ __forceinline__ void build_twiddles(T *twc, T *tws) {
   for (int m = threadIdx.x; m < P; m += blockDim.x) {
-    double s, c;
-    sincospi(2.0 * (double)m / (double)P, &s, &c);
-    twc[m] = (T)c;
-    tws[m] = (T)s;
+    if constexpr (sizeof(T) == 4) {
+      float s, c;
+      sincospif(2.0f * (float)m / (float)P, &s, &c);
+      twc[m] = c;
+      tws[m] = s;
+    } else {
+      double s, c;
+      sincospi(2.0 * (double)m / (double)P, &s, &c);
+      twc[m] = c;
+      tws[m] = s;
+    }
   }
 }
 
