@@ -56,7 +56,8 @@ typedef enum {
   CTOF_ENOMEM = -2,        /* a caller buffer is smaller than required           */
   CTOF_EHIP = -3,          /* a HIP runtime call failed                          */
   CTOF_ENONFINITE = -4,    /* a NaN/Inf appeared in an FP64 norm                 */
-  CTOF_EUNSUPPORTED = -5   /* valid but outside what this build implements       */
+  CTOF_EUNSUPPORTED = -5,  /* valid but outside what this build implements       */
+  CTOF_EDIVERGED = -6      /* a solve diverged (a step longer than 1/L_A)        */
 } ctof_status;
 
 typedef enum {
@@ -417,6 +418,10 @@ typedef struct {
  * Enqueues on `stream` and synchronises it before returning (the report is
  * filled from device scalars); also synchronises every check_every
  * iterations when rel_tol > 0.  Reaching max_iter is not an error.
+ * CTOF_EDIVERGED (report filled) when the last step's gradient-mapping
+ * ratio exceeds 1e6 times the first step's (or 1e6 when that is below 1):
+ * FISTA with a step of at most 1/L_A does not grow it so, a `lipschitz`
+ * below the operator's (a step beyond 2/L_A) does, geometrically.
  */
 ctof_status ctof_reconstruct(ctof_kernel k, const void *d_dev, void *mu_inout_dev,
                              const ctof_solver_opts *opts, ctof_solver_report *report,

@@ -388,6 +388,14 @@ bool overlaps(const void *a, const void *b, size_t bytes) {
 }
 
 // Resumption fields shared by both solvers (see ctof_solver_opts).
+// Divergence of a FISTA run from its first and last gradient-mapping ratios:
+// with a step of at most 1/L_A the ratio does not grow by orders of
+// magnitude; with a step beyond 2/L_A it grows geometrically.
+constexpr double kDivergence = 1e6;
+bool diverged(double first_ratio, double last_ratio) {
+  return last_ratio > kDivergence * std::max(1.0, first_ratio);
+}
+
 ctof_status check_resume(const ctof_solver_opts *o, bool have_prev) {
   if (o->k0 < 0 || o->k0 > (1 << 30) - o->max_iter)
     return set_error(CTOF_EINVAL, "k0 must be in [0, 2^30 - max_iter]");
@@ -1035,6 +1043,11 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
     rep->status = CTOF_ENONFINITE;
     return set_error(CTOF_ENONFINITE, "non-finite FP64 norm during the solve (stopped after %d iterations)", done);
   }
+  if (kept > 0 && diverged(h0[1], hl[1])) {
+    rep->status = CTOF_EDIVERGED;
+    return set_error(CTOF_EDIVERGED, "the solve diverged: gradient-mapping ratio %g after %d iterations, %g after the "
+                     "first (is lipschitz below the operator's?)", hl[1], kept, h0[1]);
+  }
   return CTOF_OK;
 }
 
@@ -1423,10 +1436,15 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
       if (!std::isfinite(r.datafit) || !std::isfinite(r.datafit0) || !std::isfinite(r.gmap_ratio)) {
         r.status = CTOF_ENONFINITE;
         worst = CTOF_ENONFINITE;
+      } else if (its > fell[c][v] && diverged(hist[c][((size_t)fell[c][v] * nv + v) * 2 + 1], r.gmap_ratio)) {
+        r.status = CTOF_EDIVERGED;
+        if (worst == CTOF_OK) worst = CTOF_EDIVERGED;
       }
     }
   }
-  if (worst != CTOF_OK) return set_error(worst, "non-finite FP64 norm in a batched solve");
+  if (worst == CTOF_ENONFINITE) return set_error(worst, "non-finite FP64 norm in a batched solve");
+  if (worst == CTOF_EDIVERGED)
+    return set_error(worst, "a scan of the batched solve diverged (is its lipschitz below the operator's?)");
   return CTOF_OK;
 }
 

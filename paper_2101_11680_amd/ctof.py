@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(HERE, "libctof.so")
 FP64, FP32, BF16X3, BF16 = 0, 1, 2, 3
 PRECISIONS = {"fp64": FP64, "fp32": FP32, "bf16x3": BF16X3, "bf16": BF16}
 STATUS = {0: "CTOF_OK", -1: "CTOF_EINVAL", -2: "CTOF_ENOMEM", -3: "CTOF_EHIP",
-          -4: "CTOF_ENONFINITE", -5: "CTOF_EUNSUPPORTED"}
+          -4: "CTOF_ENONFINITE", -5: "CTOF_EUNSUPPORTED", -6: "CTOF_EDIVERGED"}
 
 EXPORTS = ("ctof_kernel_bytes", "ctof_kernel_tabulate", "ctof_kernel_tabulate_quadrant",
            "ctof_kernel_tabulate_fp64_quadrant",

@@ -7,6 +7,8 @@
   filled with a canary pattern come back byte for byte unchanged.
 * Two identical calls give bitwise identical iterates and reports (all
   reductions run in a fixed order).
+* A step beyond 2/L_A (an explicit lipschitz below the operator's) makes
+  FISTA diverge: the solve returns CTOF_EDIVERGED with the report filled.
 """
 
 import ctypes
@@ -97,6 +99,33 @@ def test_nonfinite_batched_reports_the_scan():
     with pytest.raises(c.CtofError) as ei:
         c.reconstruct_batched([k, k], [d, bad], max_iter=20, lam=lam, lipschitz=L)
     assert ei.value.status == -4
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_divergence_is_reported(prec):
+    from paper_2101_11680_amd import ctof as c
+    g = geom()
+    p = c.PRECISIONS[prec]
+    k, d, L, lam = _problem(c, g, p)
+    dt = torch.float64 if p == c.FP64 else torch.float32
+    mu = torch.zeros((g.nz, g.ny, g.nx), dtype=dt, device="cuda")
+    # the step 1/L of a lipschitz at a fifth of the operator's is 2.5 times the
+    # largest stable one: the error grows about fourfold per step
+    st, rep = _raw_reconstruct(c, k, d, mu, 60, lam, 0.2 * L)
+    assert st == -6, c.lib().ctof_last_error()
+    assert rep.status == -6 and rep.iters == 60
+    assert np.isfinite(rep.gmap_ratio) and rep.gmap_ratio > 1e6
+    # with a tolerance the scan never meets it and is reported the same way
+    st, rep = _raw_reconstruct(c, k, d, mu, 60, lam, 0.2 * L, rel_tol=1e-3, check_every=10)
+    assert st == -6 and rep.iters == 60
+    # the operator's own L: no divergence over the same iterations
+    st, rep = _raw_reconstruct(c, k, d, mu, 60, lam, L)
+    assert st == 0 and rep.gmap_ratio < 1.0
+    # batched: the diverging scan is flagged, the other one is not
+    k2 = c.tabulate(g, p)  # a second handle: a class of its own, with its own L
+    with pytest.raises(c.CtofError) as ei:
+        c.reconstruct_batched([k, k2], [d, d], max_iter=60, lam=[lam, lam], lipschitz=[0.2 * L, L])
+    assert ei.value.status == -6
 
 
 def _canary_like(t):
