@@ -190,7 +190,20 @@ ctof_status apply_fluorescence(const ctof_geometry *g, const ctof_fluorescence *
 
 size_t elem_size(ctof_precision p) { return p == CTOF_FP64 ? 8 : 4; }
 
-bool valid_prec(int p) { return p >= CTOF_FP64 && p <= CTOF_BF16; }
+// A caller may pass any 32-bit value where a ctof_precision is expected (C
+// and foreign-function callers do); reading an enum object outside its
+// enumerators' range is undefined in C++, so an argument is read through
+// its bytes (its address) until it is known to be valid.
+int32_t prec_value(const ctof_precision *prec) {
+  int32_t p;
+  static_assert(sizeof(p) == sizeof(*prec), "ctof_precision is 32 bits wide");
+  std::memcpy(&p, prec, sizeof p);
+  return p;
+}
+bool valid_prec(const ctof_precision *prec) {
+  const int32_t p = prec_value(prec);
+  return p >= CTOF_FP64 && p <= CTOF_BF16;
+}
 
 struct TabWs {
   size_t q, t1, cm, total;  // offsets
@@ -1703,7 +1716,7 @@ ctof_status ctof_kernel_bytes(const ctof_geometry *geom, ctof_precision prec, si
                               size_t *tab_ws_bytes) {
   ctof_status s = check_geometry(geom, nullptr, nullptr);
   if (s != CTOF_OK) return s;
-  if (!valid_prec(prec)) return set_error(CTOF_EINVAL, "unknown precision %d", (int)prec);
+  if (!valid_prec(&prec)) return set_error(CTOF_EINVAL, "unknown precision %d", (int)prec_value(&prec));
   const ctof::Dims d = ctof::make_dims(geom->nx, geom->ny, geom->nz, geom->nt, prec);
   if (khat_bytes) *khat_bytes = ctof::khat_layout(d, prec).total;
   if (tab_ws_bytes) *tab_ws_bytes = tab_ws(d).total;
@@ -1713,6 +1726,7 @@ ctof_status ctof_kernel_bytes(const ctof_geometry *geom, ctof_precision prec, si
 ctof_status ctof_kernel_tabulate(const ctof_geometry *geom, ctof_precision prec, void *khat_dev,
                                  size_t khat_bytes, void *tab_ws_dev, size_t tab_ws_bytes,
                                  hipStream_t stream, ctof_kernel *out) {
+  if (!valid_prec(&prec)) return set_error(CTOF_EINVAL, "unknown precision %d", (int)prec_value(&prec));
   return ctof_kernel_tabulate_ex(geom, nullptr, prec, khat_dev, khat_bytes, tab_ws_dev, tab_ws_bytes, stream, out);
 }
 
@@ -1724,7 +1738,7 @@ ctof_status ctof_kernel_tabulate_ex(const ctof_geometry *geom, const ctof_fluore
   ctof_status s = check_geometry(geom, &tg, &zs);
   if (s != CTOF_OK) return s;
   if ((s = apply_fluorescence(geom, fl, &tg)) != CTOF_OK) return s;
-  if (!valid_prec(prec)) return set_error(CTOF_EINVAL, "unknown precision %d", (int)prec);
+  if (!valid_prec(&prec)) return set_error(CTOF_EINVAL, "unknown precision %d", (int)prec_value(&prec));
   if (!out) return set_error(CTOF_EINVAL, "out handle pointer is NULL");
   if (!khat_dev || !tab_ws_dev) return set_error(CTOF_EINVAL, "device buffer is NULL");
   const ctof::Dims d = ctof::make_dims(geom->nx, geom->ny, geom->nz, geom->nt, prec);
