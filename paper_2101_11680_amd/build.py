@@ -35,6 +35,11 @@ FLAGS = [
 ]
 
 
+# libraries the link needs beyond HIP's own: roctx (named host ranges for
+# tracers)
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+LINK = [f"-L{os.path.join(ROCM, 'lib')}", "-lrocprofiler-sdk-roctx", f"-Wl,-rpath,{os.path.join(ROCM, 'lib')}"]
+
 # translation units whose kernels form the solver's hot path
 HOT_SOURCES = ("fft.hip", "contract.hip", "solver.hip", "api.hip", "tabulate.hip")
 # kernels allowed to use scratch, by a substring of the mangled name, with the reason
@@ -108,7 +113,7 @@ def build(jobs: int | None = None) -> str:
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = OUT + ".tmp"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, *LINK, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stderr}")

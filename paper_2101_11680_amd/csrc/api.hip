@@ -13,6 +13,8 @@
 // data, so they are computed on the host and passed as launch arguments.
 #include "ctof_internal.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
@@ -204,6 +206,23 @@ bool valid_prec(const ctof_precision *prec) {
   const int32_t p = prec_value(prec);
   return p >= CTOF_FP64 && p <= CTOF_BF16;
 }
+
+// A named host-side range for tracers (rocprofv3 --marker-trace): it spans
+// the enqueueing of a call's GPU work, which runs asynchronously; without a
+// tracer attached a push or pop costs a call through a null hook.
+struct TraceRange {
+  bool open;
+  explicit TraceRange(const char *name) : open(true) { roctxRangePushA(name); }
+  void end() {
+    if (open) {
+      roctxRangePop();
+      open = false;
+    }
+  }
+  ~TraceRange() { end(); }
+  TraceRange(const TraceRange &) = delete;
+  TraceRange &operator=(const TraceRange &) = delete;
+};
 
 struct TabWs {
   size_t q, t1, cm, total;  // offsets
@@ -841,6 +860,7 @@ ctof_status enqueue_final_fit(const Engine<T> &E, const void *const *d, void *co
 template <typename T>
 ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_solver_opts *opt,
                             ctof_solver_report *rep, void *ws, hipStream_t st) {
+  TraceRange trace("ctof_reconstruct");
   const ctof::Dims &dm = k->dims;
   Engine<T> E = engine<T>(k, 1, ws, opt->max_iter, st);
   const void *dd[1] = {d};
@@ -877,6 +897,7 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
 
   double lam = opt->lambda_tikhonov, Lip = opt->lipschitz, LA = 0.0;
   if (Lip == 0.0) {
+    TraceRange tp("power iteration");
     if (ctof_status s = enqueue_power_iteration(E, opt->power_iters > 0 ? opt->power_iters : 50); s != CTOF_OK)
       return s;
     double hs[2];
@@ -931,6 +952,7 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
   auto may_stop = [&](int it) {
     return it == K - 1 || (opt->rel_tol > 0 && (it + 1 - base) % opt->check_every == 0);
   };
+  TraceRange tl("iterations");
   for (int it = 0; it < K; ++it) {
     double *pk = E.part() + (size_t)it * E.L.part_stride;
     HIP_TRY(mark(it, 0));
@@ -993,6 +1015,7 @@ ctof_status run_reconstruct(ctof_kernel k, const void *d, void *mu, const ctof_s
       if (h2[1] <= opt->rel_tol) break;
     }
   }
+  tl.end();
   if (tstride > 0) HIP_TRY(hipEventRecord(ev[(size_t)nsamp * 5], st));  // end of the loop
   const int kept = done - base;
   HIP_TRY(ctof::launch_history(E.part() + (size_t)base * E.L.part_stride, kept, 1, E.L.nblk_t, E.L.nblk_z,
@@ -1132,6 +1155,7 @@ struct StreamGuard {
 template <typename T>
 ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, void *const *mu,
                         const ctof_solver_opts *opt, ctof_solver_report *rep, void *ws, hipStream_t st) {
+  TraceRange trace("ctof_reconstruct_batched");
   const int K = opt->max_iter;
   std::vector<ClassPlan> cls = plan_classes(nscan, ks, K, nullptr);
   char *base = reinterpret_cast<char *>(ws);
@@ -1311,6 +1335,7 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
     return CTOF_OK;
   };
   int nchunk = 0;
+  TraceRange tl("iterations");
   while (done < K) {
     bool any = false;
     for (auto &c : cls) any = any || c.active;
@@ -1393,6 +1418,7 @@ ctof_status run_batched(int nscan, const ctof_kernel *ks, const void *const *d, 
       ++nchunk;
     }
   }
+  tl.end();
   // conv per volume (device): iterations until frozen, 0 for volumes still live
   for (size_t c = 0; c < cls.size(); ++c) {
     if (!freeze) break;
@@ -1733,6 +1759,7 @@ ctof_status ctof_kernel_tabulate(const ctof_geometry *geom, ctof_precision prec,
 ctof_status ctof_kernel_tabulate_ex(const ctof_geometry *geom, const ctof_fluorescence *fl, ctof_precision prec,
                                     void *khat_dev, size_t khat_bytes, void *tab_ws_dev, size_t tab_ws_bytes,
                                     hipStream_t stream, ctof_kernel *out) {
+  TraceRange trace("ctof_kernel_tabulate");
   ctof::TabGeom tg;
   ctof::LayerDepths zs;
   ctof_status s = check_geometry(geom, &tg, &zs);
@@ -1874,6 +1901,7 @@ ctof_status ctof_workspace_bytes(ctof_kernel k, int32_t max_iter, size_t *op_ws_
 
 ctof_status ctof_forward(ctof_kernel k, const void *mu_dev, void *m_dev, void *ws_dev, size_t ws_bytes,
                          hipStream_t stream) {
+  TraceRange trace("ctof_forward");
   ctof_status s = check_kernel(k);
   if (s != CTOF_OK) return s;
   if (!mu_dev || !m_dev || !ws_dev) return set_error(CTOF_EINVAL, "device pointer is NULL");
@@ -1899,6 +1927,7 @@ ctof_status ctof_forward_noalloc(ctof_kernel k, const void *mu_dev, void *m_dev,
 
 ctof_status ctof_adjoint(ctof_kernel k, const void *r_dev, void *g_dev, void *ws_dev, size_t ws_bytes,
                          hipStream_t stream) {
+  TraceRange trace("ctof_adjoint");
   ctof_status s = check_kernel(k);
   if (s != CTOF_OK) return s;
   if (!r_dev || !g_dev || !ws_dev) return set_error(CTOF_EINVAL, "device pointer is NULL");
@@ -2199,6 +2228,7 @@ static size_t tune_ws_bytes(ctof_kernel_s *k, int nvol) {
 
 ctof_status ctof_tune(ctof_kernel k, int32_t nvol, int32_t iters, void *ws_dev, size_t ws_bytes,
                       hipStream_t stream, ctof_tuning *out) {
+  TraceRange trace("ctof_tune");
   if (ctof_status s = check_kernel(k); s != CTOF_OK) return s;
   if (nvol < 1 || nvol > ctof::kMaxVol) return set_error(CTOF_EINVAL, "nvol must be in [1, %d]", ctof::kMaxVol);
   if (iters < 1 || iters > 1000) return set_error(CTOF_EINVAL, "iters must be in [1, 1000]");

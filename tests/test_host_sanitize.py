@@ -41,8 +41,8 @@ def test_host_validation_under_sanitizers(tmp_path):
                           os.path.join(b.CSRC, "api.hip"), "-o", str(api)], capture_output=True, text=True)
     assert res.returncode == 0, res.stderr[-4000:]
     lib = tmp_path / "libctof_san.so"
-    res = subprocess.run([hipcc, f"--offload-arch={b.ARCH}", "-shared", "-fPIC", *SAN, *objs, str(api), "-o", str(lib)],
-                         capture_output=True, text=True)
+    res = subprocess.run([hipcc, f"--offload-arch={b.ARCH}", "-shared", "-fPIC", *SAN, *objs, str(api), *b.LINK,
+                          "-o", str(lib)], capture_output=True, text=True)
     assert res.returncode == 0, res.stderr[-4000:]
     exe = tmp_path / "host_validation"
     res = subprocess.run([hipcc, "-x", "c", "-O1", "-g", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(rocm, "include"),
