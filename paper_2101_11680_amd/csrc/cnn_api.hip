@@ -17,8 +17,12 @@ ctof_status check_desc(const ctof_conv_desc *d) {
   if (!d) return set_error(CTOF_EINVAL, "conv descriptor is NULL");
   if (d->kind < CTOF_CONV_K3 || d->kind > CTOF_CONV_K1) return set_error(CTOF_EINVAL, "unknown conv kind %d", d->kind);
   if (d->n < 1 || d->d < 1 || d->h < 1 || d->w < 1) return set_error(CTOF_EINVAL, "grid sizes must be >= 1");
-  if ((long long)d->n * d->d * d->h * d->w * (d->kind == CTOF_CONV_UP ? 8 : 1) > kMaxRows)
-    return set_error(CTOF_EINVAL, "grid too large");
+  // the row count, built up factor by factor so that no product overflows
+  long long rows = d->kind == CTOF_CONV_UP ? 8 : 1;
+  for (const int f : {d->n, d->d, d->h, d->w}) {
+    if (f > kMaxRows / rows) return set_error(CTOF_EINVAL, "grid too large");
+    rows *= f;
+  }
   if (d->kind == CTOF_CONV_DN && ((d->d | d->h | d->w) & 1))
     return set_error(CTOF_EINVAL, "a stride-2 layer needs even d, h, w");
   if (d->ci < 1 || d->ci > kMaxChannels) return set_error(CTOF_EINVAL, "ci must be in [1, %d]", kMaxChannels);

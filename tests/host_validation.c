@@ -55,6 +55,28 @@ int main(void) {
   const ctof_kernel ks[2] = {NULL, NULL};
   EXPECT(ctof_workspace_bytes_batched(2, ks, 10, &ws) == CTOF_EINVAL);
   EXPECT(ctof_workspace_bytes_batched(0, ks, 10, &ws) == CTOF_EINVAL);
+  /* the network's layers */
+  ctof_conv_desc cd = {CTOF_CONV_K3, 2, 8, 8, 8, 16, 16};
+  size_t el = 0;
+  EXPECT(ctof_conv3d_weight_elems(&cd, &el) == CTOF_OK && el > 0);
+  EXPECT(ctof_conv3d_weight_elems(NULL, &el) == CTOF_EINVAL);
+  ctof_conv_desc cb = cd; cb.kind = 9;                 EXPECT(ctof_conv3d_weight_elems(&cb, &el) == CTOF_EINVAL);
+  cb = cd; cb.n = 0;                                   EXPECT(ctof_conv3d_weight_elems(&cb, &el) == CTOF_EINVAL);
+  cb = cd; cb.ci = 0;                                  EXPECT(ctof_conv3d_weight_elems(&cb, &el) == CTOF_EINVAL);
+  cb = cd; cb.kind = CTOF_CONV_DN; cb.w = 7;           EXPECT(ctof_conv3d_weight_elems(&cb, &el) == CTOF_EINVAL);
+  cb = cd; cb.n = cb.d = cb.h = cb.w = 1 << 30;        EXPECT(ctof_conv3d_weight_elems(&cb, &el) == CTOF_EINVAL);
+  cb = cd; cb.kind = CTOF_CONV_UP; cb.n = cb.d = cb.h = cb.w = 2147483647;
+  EXPECT(ctof_conv3d_weight_elems(&cb, &el) == CTOF_EINVAL);
+  cb = cd; cb.co = 80;                                 EXPECT(ctof_conv3d_weight_elems(&cb, &el) != CTOF_OK);
+  size_t cws = 0;
+  EXPECT(ctof_conv3d_bwd_data_ws_bytes(&cd, &cws) == CTOF_OK);
+  EXPECT(ctof_conv3d_bwd_weight_ws_bytes(&cd, &cws) == CTOF_OK);
+  EXPECT(ctof_conv3d_bwd_weight_ws_bytes(NULL, &cws) == CTOF_EINVAL);
+  ctof_tensor tx = {NULL, 16, 0};
+  EXPECT(ctof_conv3d_fwd(&cd, &tx, NULL, NULL, &tx, 0, 1, 0, NULL) == CTOF_EINVAL);
+  EXPECT(ctof_conv3d_fwd(&cd, NULL, NULL, NULL, NULL, 0, 1, 0, NULL) == CTOF_EINVAL);
+  EXPECT(ctof_relu_bwd(-1, 16, &tx, &tx, NULL) != CTOF_OK);
+  EXPECT(ctof_mse_ws_bytes(-5, &cws) != CTOF_OK);
   ctof_kernel_free(NULL);
   printf("host validation checks: %d failed\n", fails);
   return fails != 0;

@@ -1,12 +1,15 @@
 """The library's host code (argument validation, sizes, errors) under
 AddressSanitizer and UndefinedBehaviorSanitizer, on the CPU.
 
-The boundary's translation unit (api.hip) is compiled with the sanitizers on
-its host side only (device code is built as usual), linked with the other
-translation units into a separate library, and driven by a C program
+The boundary's translation units (api.hip, cnn_api.hip) are compiled with
+the sanitizers on their host side only (device code is built as usual),
+linked with the other translation units into a separate library, and
+driven by a C program
 (tests/host_validation.c) that calls every validation path reachable
 without a GPU: bad geometries, unknown precisions (any 32-bit value a C
-caller may pass), NULL and undersized buffers, NULL handles.  A sanitizer
+caller may pass), NULL and undersized buffers, NULL handles, convolution
+descriptors out of range (grids whose row count overflows 64 bits
+included).  A sanitizer
 report or a wrong status fails the test.
 """
 
@@ -32,16 +35,20 @@ def test_host_validation_under_sanitizers(tmp_path):
         pytest.skip("hipcc not available")
     from paper_2101_11680_amd import build as b
     srcs = sorted(f for f in os.listdir(b.CSRC) if f.endswith(".hip"))
-    objs = [os.path.join(b.OBJ, f + ".o") for f in srcs if f != "api.hip"]
+    sanitized = ("api.hip", "cnn_api.hip")
+    objs = [os.path.join(b.OBJ, f + ".o") for f in srcs if f not in sanitized]
     if not all(os.path.exists(o) for o in objs):
         b.build()
     rocm = os.path.dirname(os.path.dirname(os.path.realpath(hipcc)))
-    api = tmp_path / "api_san.o"
-    res = subprocess.run([hipcc, *b.FLAGS, "-O1", "-g", *SAN, "-Xarch_host", "-fno-omit-frame-pointer", "-c",
-                          os.path.join(b.CSRC, "api.hip"), "-o", str(api)], capture_output=True, text=True)
-    assert res.returncode == 0, res.stderr[-4000:]
+    san_objs = []
+    for f in sanitized:
+        o = tmp_path / (f + ".san.o")
+        res = subprocess.run([hipcc, *b.FLAGS, "-O1", "-g", *SAN, "-Xarch_host", "-fno-omit-frame-pointer", "-c",
+                              os.path.join(b.CSRC, f), "-o", str(o)], capture_output=True, text=True)
+        assert res.returncode == 0, res.stderr[-4000:]
+        san_objs.append(str(o))
     lib = tmp_path / "libctof_san.so"
-    res = subprocess.run([hipcc, f"--offload-arch={b.ARCH}", "-shared", "-fPIC", *SAN, *objs, str(api), *b.LINK,
+    res = subprocess.run([hipcc, f"--offload-arch={b.ARCH}", "-shared", "-fPIC", *SAN, *objs, *san_objs, *b.LINK,
                           "-o", str(lib)], capture_output=True, text=True)
     assert res.returncode == 0, res.stderr[-4000:]
     exe = tmp_path / "host_validation"
