@@ -86,6 +86,8 @@ typedef enum {
  *   mus_prime_per_mm  reduced scattering coefficient (> 0)
  *   mua_per_mm        background absorption (> 0; the closed form needs it)
  *   n_medium          refractive index inside (>= 1; 1 outside)
+ * nz * ny * nx * nt must not exceed 1e15 (every byte count derived from
+ * the shape then fits in 63 bits); CTOF_EINVAL otherwise.
  */
 typedef struct {
   int32_t nx, ny;

@@ -130,8 +130,10 @@ ctof_status check_geometry(const ctof_geometry *g, ctof::TabGeom *tg, ctof::Laye
         return set_error(CTOF_EINVAL, "dz_mm == 0 needs uniformly spaced z_mm");
     dz = step;
   }
+  // every byte count derived from the shape (kernel spectrum, spectra,
+  // workspaces: at most a few dozen bytes per voxel-bin) then fits in 63 bits
   const double total = (double)g->nz * g->nx * g->ny * (double)g->nt;
-  if (total > 9.0e18) return set_error(CTOF_EINVAL, "nz*ny*nx*nt overflows");
+  if (total > 1.0e15) return set_error(CTOF_EINVAL, "nz*ny*nx*nt = %g exceeds 1e15", total);
   if (g->nx > ctof::kMaxN || g->ny > ctof::kMaxN)
     return set_error(CTOF_EUNSUPPORTED, "a scan side above %d needs an FFT size above 2048", ctof::kMaxN);
   if (g->nz > ctof::kMaxLayers) return set_error(CTOF_EUNSUPPORTED, "nz > %d", ctof::kMaxLayers);

@@ -33,6 +33,10 @@ int main(void) {
   b = g; b.z_mm = NULL;                    EXPECT(ctof_kernel_bytes(&b, CTOF_FP32, &kb, &wb) == CTOF_EINVAL);
   b = g; b.nx = 1025;                      EXPECT(ctof_kernel_bytes(&b, CTOF_FP32, &kb, &wb) != CTOF_OK);
   b = g; b.n_medium = 0.5;                 EXPECT(ctof_kernel_bytes(&b, CTOF_FP32, &kb, &wb) == CTOF_EINVAL);
+  b = g; b.nx = b.ny = 1024; b.nt = 2147483647;
+  EXPECT(ctof_kernel_bytes(&b, CTOF_FP32, &kb, &wb) == CTOF_EINVAL);  /* beyond 1e15 voxel-bins */
+  b = g; b.nx = b.ny = 1024; b.nt = 16384;
+  EXPECT(ctof_kernel_bytes(&b, CTOF_FP64, &kb, &wb) == CTOF_OK && kb > ((size_t)1 << 36));
   EXPECT(strlen(ctof_last_error()) > 0);
   ctof_kernel k = NULL;
   EXPECT(ctof_kernel_tabulate(NULL, CTOF_FP32, NULL, 0, NULL, 0, NULL, &k) == CTOF_EINVAL);
