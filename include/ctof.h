@@ -504,8 +504,9 @@ ctof_status ctof_kernel_get_row_tuning(ctof_kernel k, int32_t *rb_t, int32_t *rb
  * spectrum per run: query ctof_workspace_bytes after setting).  Shorter
  * blocks shorten the tail of a launch.  The effective values (get) are
  * clamped: 1 with a spectrum band and for the BF16 adjoints (the BF16
- * forwards' rule is 1, other values as asked), an adjoint of FFT size above
- * 256 keeps 1, and a run has at least one 16-bin tile.  Results
+ * forwards' rule is 2 from 256 bins, else 1; other values as asked), an
+ * adjoint of FFT size above 256 keeps 1, and a run has at least one 16-bin
+ * tile.  Results
  * change only by the order of the adjoint's sum.  The handle must not be in
  * use on other streams meanwhile.
  */

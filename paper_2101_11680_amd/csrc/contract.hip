@@ -521,14 +521,21 @@ contract_fwd_bf16_kernel(CArgs a) {
   for (int ch = 0; ch < nchunk; ++ch) {
     if (BAND && ch > 0 && ch * 4 * KZ >= zend) break;
     const bool zon = !BAND || ch * 4 * KZ + g * KZ < zend;
+    // the lane group's KZ layers of its column, read in 16-byte words
+    float vz[KZ];
+    if (k.on) {
+      load_run<float, KZ>(vcol + ch * 4 * KZ + g * KZ, vz);
+    } else {
+#pragma unroll
+      for (int u = 0; u < KZ; ++u) vz[u] = 0.0f;
+    }
     v8bf bh[KZ / 8], bl[KZ / 8];
 #pragma unroll
     for (int e = 0; e < KZ / 8; ++e) {
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const float v = k.on ? vcol[ch * 4 * KZ + g * KZ + e * 8 + u] : 0.0f;
         __bf16 hi, lo;
-        split_bf16(v, hi, lo);
+        split_bf16(vz[e * 8 + u], hi, lo);
         bh[e][u] = hi;
         bl[e][u] = lo;
       }
@@ -847,10 +854,11 @@ int contract_parts(const ctof_kernel_s *k, bool adjoint) {
   const bool bf = k->prec == CTOF_BF16X3 || k->prec == CTOF_BF16;
   if (k->band || (bf && adjoint)) return 1;  // (the BF16 adjoints keep one block per matrix)
   if (bf) {
-    // the BF16 forwards split a matrix only when asked for (each block splits
-    // its data columns into hi and lo parts again: the hi-only form measured
-    // slower split, so the rule keeps one block)
-    return k->fwd_parts > 0 ? std::max(1, std::min(k->fwd_parts, d.ntp / 16)) : 1;
+    // the BF16 forwards: up to two blocks per matrix, at least 8 t tiles each
+    // (each block splits its data columns into hi and lo parts, from 16-byte
+    // loads; at 512 bins two blocks measured fastest for both forms)
+    const int rule = std::max(1, std::min(2, d.ntp / 128));
+    return k->fwd_parts > 0 ? std::max(1, std::min(k->fwd_parts, d.ntp / 16)) : rule;
   }
   if (!adjoint) {
     // up to four blocks per matrix, at least 8 t tiles (2 per wave) each:

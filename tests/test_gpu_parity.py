@@ -454,7 +454,7 @@ def test_contraction_parts_rules():
     # 48 bins pad to 64: four 16-bin tiles and four chunks at most
     assert c.get_contract_parts(k) == (4, 4)
     kb = c.tabulate(SMALL, c.BF16X3)
-    assert c.get_contract_parts(kb) == (1, 1)  # the BF16 rule: one block per matrix
+    assert c.get_contract_parts(kb) == (1, 1)  # the BF16 rule: two blocks per matrix from 256 bins
     c.set_contract_parts(kb, 4, 4)
     assert c.get_contract_parts(kb) == (4, 1)  # the BF16 adjoints keep one block per matrix
 
