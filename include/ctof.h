@@ -56,7 +56,7 @@ typedef enum {
   CTOF_ENOMEM = -2,        /* a caller buffer is smaller than required           */
   CTOF_EHIP = -3,          /* a HIP runtime call failed                          */
   CTOF_ENONFINITE = -4,    /* a NaN/Inf appeared in an FP64 norm                 */
-  CTOF_EUNSUPPORTED = -5,  /* valid but outside what this build implements       */
+  CTOF_EUNSUPPORTED = -5,  /* valid but outside what the library implements      */
   CTOF_EDIVERGED = -6      /* a solve diverged (a step longer than 1/L_A)        */
 } ctof_status;
 
