@@ -188,6 +188,8 @@ def composite_target(ctof, torch, dev, rel_tol: float = 1e-3, n_scans: int = 64,
     the tuner's choice.  The final objectives (data fit + lambda/2 ||mu||^2)
     of the accelerated side are compared per scan with the plain side's.
     """
+    import numpy as np
+
     from paper_2101_11680_amd import unet
     from synth import noise, phantoms, workloads
     scans = workloads.batching_scans(n_scans, seed=seed)
