@@ -548,9 +548,20 @@ contract_fwd_bf16_kernel(CArgs a) {
         if (zt < blo || zt >= bhi) *reinterpret_cast<float4 *>(ocol + zt * 16 + 4 * g) = make_float4(0, 0, 0, 0);
     }
     const int tend = bhi;
-    for (int tt = blo + w; tt < tend; tt += 4) {
-      const int t0 = tt * 16;
+    constexpr int NF = KIND == 2 ? 2 : 1;  // fragments per layer group: hi (and lo)
+    // the kernel fragments of tile tt (zeros past the band's layers)
+    auto fetch = [&](int tt, v8bf (&af)[KZ / 8][NF]) {
       const size_t blk = (((size_t)s * ntt + tt) * nchunk + ch) * (64 * KZ);
+#pragma unroll
+      for (int e = 0; e < KZ / 8; ++e) {
+        const size_t off = blk + ((size_t)e * 64 + l) * 8;
+        const v8bf zero8 = {};
+        af[e][0] = (!BAND || zon) ? load_bf8<NT>(khi + off) : zero8;
+        if constexpr (KIND == 2) af[e][1] = (!BAND || zon) ? load_bf8<NT>(klo + off) : zero8;
+      }
+    };
+    auto tile = [&](int tt, const v8bf (&af)[KZ / 8][NF]) {
+      const int t0 = tt * 16;
       v4f acc = {0, 0, 0, 0};
       if (ch > 0 && k.on) {
         const float *o = ocol + t0 + 4 * g;
@@ -558,17 +569,23 @@ contract_fwd_bf16_kernel(CArgs a) {
       }
 #pragma unroll
       for (int e = 0; e < KZ / 8; ++e) {
-        const size_t off = blk + ((size_t)e * 64 + l) * 8;
-        const v8bf zero8 = {};
-        const v8bf ah = (!BAND || zon) ? load_bf8<NT>(khi + off) : zero8;
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[e], acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[e], acc, 0, 0, 0);
-        if (KIND == 2) {
-          const v8bf al = (!BAND || zon) ? load_bf8<NT>(klo + off) : zero8;
-          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[e], acc, 0, 0, 0);
-        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[e][0], bh[e], acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[e][0], bl[e], acc, 0, 0, 0);
+        if constexpr (KIND == 2) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[e][1], bh[e], acc, 0, 0, 0);
       }
       if (k.on) *reinterpret_cast<float4 *>(ocol + t0 + 4 * g) = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    };
+    // the next tile's fragments are loaded before the current one's
+    // products, so each wave keeps a tile of loads in flight
+    v8bf a0[KZ / 8][NF], a1[KZ / 8][NF];
+    int tt = blo + w;
+    if (tt < tend) fetch(tt, a0);
+    for (; tt < tend; tt += 8) {
+      if (tt + 4 < tend) fetch(tt + 4, a1);
+      tile(tt, a0);
+      if (tt + 4 >= tend) break;
+      if (tt + 8 < tend) fetch(tt + 8, a0);
+      tile(tt + 4, a1);
     }
   }
 }
